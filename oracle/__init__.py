@@ -1,0 +1,176 @@
+"""CPU oracle for affine-gap local alignment (Smith-Waterman / Gotoh).
+
+TEST INFRASTRUCTURE. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  The product
+library never loads it, and it shares no code with the HIP path: it has its
+own C source (``sw_oracle.c``), its own build step and its own Python loops.
+
+Two implementations of one definition:
+
+* ``sw_oracle.c`` -- scalar int64 Gotoh recurrence, reference-outer /
+  query-inner, strict ``>`` for the lexicographically smallest
+  (ref_end, query_end) end cell; a pthread pool runs many pairs.
+* ``gotoh_py`` -- the same recurrence in pure Python (small cases only), which
+  can also return the per-column Hd / H tables for hand-checked examples.
+
+Both follow the paper's problem statement (Background: local alignment with
+affine gaps; the update order of the inner loop of Algorithm 1; the remark that
+no value may go negative, i.e. the local-alignment floor at zero).  Readings
+adopted where the paper is silent are stated in each docstring:
+
+* gap of length L costs GapOpen + (L-1) * GapExtend (subtracting GapOpen opens
+  a gap, each further residue subtracts GapExtend);
+* the score is the running maximum of H_diag = H(i-1, j-1) + S[q_j][r_i]
+  (the paper's Max is taken before the E/F maxima), floored at 0;
+* S is indexed [query code][reference code];
+* end coordinates are those of the H_diag cell achieving the maximum, smallest
+  ref_end first, then smallest query_end; score 0 gives (-1, -1).
+
+Parity status: pinned (brute-force enumeration of all local alignments on tiny
+inputs, a hand-computed worked example, closed-form special cases and
+invariants; see ``tests/test_oracle_pins.py``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sw_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int64), ("query_end", ctypes.c_int64),
+                ("ref_end", ctypes.c_int64)]
+
+
+def build(force: bool = True) -> str:
+    """Compile sw_oracle.c into liboracle.so with gcc -O2 (plain C, pthreads)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC",
+                               "-pthread", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.oracle_sw.restype = ctypes.c_int
+        lib.oracle_sw.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                  ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(_Result)]
+        lib.oracle_sw_batch.restype = ctypes.c_int
+        lib.oracle_sw_batch.argtypes = [ctypes.c_int64,
+                                        ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_int64, ctypes.c_int64,
+                                        ctypes.c_int32, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _u8(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.uint8))
+
+
+def align(query, ref, matrix, gap_open: int, gap_extend: int) -> Tuple[int, int, int]:
+    """One pair with the C oracle.  Returns (score, query_end, ref_end)."""
+    q = _u8(query)
+    r = _u8(ref)
+    M = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
+    alpha = M.shape[0]
+    assert M.shape == (alpha, alpha)
+    res = _Result()
+    rc = _load().oracle_sw(q.ctypes.data, q.size, r.ctypes.data, r.size, M.ctypes.data,
+                           alpha, int(gap_open), int(gap_extend), ctypes.byref(res))
+    if rc != 0:
+        raise RuntimeError("oracle_sw failed")
+    return int(res.score), int(res.query_end), int(res.ref_end)
+
+
+def align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix,
+                gap_open: int, gap_extend: int, pair_query=None,
+                n_threads: Optional[int] = None) -> np.ndarray:
+    """Many pairs with the C oracle over a thread pool.
+
+    Queries and references are CSR (residue bytes + offsets of length count+1).
+    Returns an (n_pairs, 3) int64 array of (score, query_end, ref_end).
+    """
+    qres = _u8(query_res)
+    rres = _u8(ref_res)
+    qoff = np.ascontiguousarray(np.asarray(query_off, dtype=np.int64))
+    roff = np.ascontiguousarray(np.asarray(ref_off, dtype=np.int64))
+    pr = np.ascontiguousarray(np.asarray(pair_ref, dtype=np.int32))
+    pq = None if pair_query is None else np.ascontiguousarray(np.asarray(pair_query, dtype=np.int32))
+    M = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
+    n_pairs = pr.size
+    out = np.zeros((n_pairs, 3), dtype=np.int64)
+    if n_threads is None:
+        n_threads = os.cpu_count() or 1
+    rc = _load().oracle_sw_batch(n_pairs, qres.ctypes.data, qoff.ctypes.data,
+                                 rres.ctypes.data, roff.ctypes.data,
+                                 None if pq is None else pq.ctypes.data, pr.ctypes.data,
+                                 M.ctypes.data, M.shape[0], int(gap_open), int(gap_extend),
+                                 int(n_threads), out.ctypes.data)
+    if rc != 0:
+        raise RuntimeError("oracle_sw_batch failed")
+    return out
+
+
+def gotoh_py(query: Sequence[int], ref: Sequence[int], matrix, gap_open: int,
+             gap_extend: int, tables: bool = False):
+    """Pure-Python Gotoh recurrence (small inputs only).
+
+    Same definition and tie-break as the C oracle.  With ``tables=True`` also
+    returns the per-column lists of H_diag and H values (column = reference
+    position), for checking a hand-computed example cell by cell.
+    """
+    m, n = len(query), len(ref)
+    NEG = None  # "no gap open yet"
+    Hprev = [0] * m
+    E = [NEG] * m
+    best, bq, br = 0, -1, -1
+    hd_cols, h_cols = [], []
+    for i in range(n):
+        F = NEG
+        Hcur = [0] * m
+        hd_col = []
+        for j in range(m):
+            diag = Hprev[j - 1] if j > 0 else 0
+            hd = diag + int(matrix[query[j]][ref[i]])
+            hd_col.append(hd)
+            if hd > best:
+                best, bq, br = hd, j, i
+            cands = [0, hd]
+            if E[j] is not None:
+                cands.append(E[j])
+            if F is not None:
+                cands.append(F)
+            h = max(cands)
+            Hcur[j] = h
+            e_ext = E[j] - gap_extend if E[j] is not None else None
+            E[j] = h - gap_open if e_ext is None else max(e_ext, h - gap_open)
+            f_ext = F - gap_extend if F is not None else None
+            F = h - gap_open if f_ext is None else max(f_ext, h - gap_open)
+        hd_cols.append(hd_col)
+        h_cols.append(list(Hcur))
+        Hprev = Hcur
+    res = (best, bq, br) if best > 0 else (0, -1, -1)
+    if tables:
+        return res, hd_cols, h_cols
+    return res

@@ -1,0 +1,162 @@
+/*
+ * Scalar CPU oracle for local alignment with affine gaps (Smith-Waterman
+ * with Gotoh's three-state recurrence).  TEST INFRASTRUCTURE ONLY: nothing in
+ * the product path may link, load or call this file.  It shares no code,
+ * header, table or constant with the HIP implementation.
+ *
+ * What it computes (paper: Background section, the local-alignment problem;
+ * Algorithm 1 inner loop for the update order; the note under Algorithm 1 that
+ * no value may go negative):
+ *
+ *   H(i,j)   = max(0, Hd(i,j), E(i,j), F(i,j))
+ *   Hd(i,j)  = H(i-1,j-1) + S[q_j][r_i]          (diagonal, H(-1,*) = H(*,-1) = 0)
+ *   E(i,j)   = max(E(i-1,j) - GapExtend, H(i-1,j) - GapOpen)   (gap along the reference)
+ *   F(i,j)   = max(F(i,j-1) - GapExtend, H(i,j-1) - GapOpen)   (gap along the query)
+ *
+ * i indexes the reference (outer loop, as in both algorithms of the paper),
+ * j the query.  A gap of length L therefore costs GapOpen + (L-1)*GapExtend:
+ * subtracting GapOpen opens it, each further residue subtracts GapExtend.
+ * The score is max over all cells of Hd (the paper keeps the running maximum
+ * of H + profile before the E/F maxima are applied), floored at 0.
+ *
+ * End cell: the paper returns only the score.  This oracle also returns the
+ * (query_end, ref_end) of the Hd cell achieving it; on ties the smallest
+ * ref_end wins, then the smallest query_end.  That is exactly what a strict ">"
+ * gives in a reference-outer, query-inner scan.  Score 0 gives (-1, -1).
+ *
+ * All arithmetic is int64; inputs are validated by the caller.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+#include <stdatomic.h>
+
+typedef struct {
+    int64_t score;
+    int64_t query_end;
+    int64_t ref_end;
+} oracle_result;
+
+static int64_t max2(int64_t a, int64_t b) { return a > b ? a : b; }
+
+/* One pair.  M is row-major alpha x alpha, indexed M[q_code * alpha + r_code].
+ * Returns 0 on success, -1 on allocation failure or bad arguments. */
+int oracle_sw(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
+              const int32_t *M, int32_t alpha, int64_t gap_open,
+              int64_t gap_extend, oracle_result *out)
+{
+    out->score = 0;
+    out->query_end = -1;
+    out->ref_end = -1;
+    if (m < 0 || n < 0 || alpha <= 0) return -1;
+    if (m == 0 || n == 0) return 0;
+
+    int64_t *Hprev = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+    int64_t *Hcur = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+    int64_t *E = (int64_t *)malloc((size_t)m * sizeof(int64_t));
+    if (!Hprev || !Hcur || !E) {
+        free(Hprev); free(Hcur); free(E);
+        return -1;
+    }
+    for (int64_t j = 0; j < m; ++j) {
+        Hprev[j] = 0;
+        /* No gap can be open before the first column.  Any value <= -GapOpen
+         * behaves the same; 0 - GapOpen - GapExtend keeps it in range. */
+        E[j] = -gap_open - gap_extend;
+    }
+
+    int64_t best = 0, bi = -1, bj = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t rc = r[i];
+        int64_t F = -gap_open - gap_extend;   /* no vertical gap above row 0 */
+        for (int64_t j = 0; j < m; ++j) {
+            const int64_t diag = (j > 0) ? Hprev[j - 1] : 0;
+            const int64_t hd = diag + (int64_t)M[(int64_t)q[j] * alpha + rc];
+            if (hd > best) { best = hd; bi = i; bj = j; }
+            /* E(i,j) was formed while processing column i-1 (below);
+             * F(i,j) was formed while processing row j-1 of this column. */
+            int64_t h = max2(max2(0, hd), max2(E[j], F));
+            Hcur[j] = h;
+            E[j] = max2(E[j] - gap_extend, h - gap_open);   /* E(i+1,j) */
+            F = max2(F - gap_extend, h - gap_open);         /* F(i,j+1) */
+        }
+        int64_t *t = Hprev; Hprev = Hcur; Hcur = t;
+    }
+    free(Hprev); free(Hcur); free(E);
+    if (best > 0) {
+        out->score = best;
+        out->query_end = bj;
+        out->ref_end = bi;
+    }
+    return 0;
+}
+
+/* ---- many pairs over a thread pool -------------------------------------- */
+
+typedef struct {
+    int64_t n_pairs;
+    const uint8_t *query_res; const int64_t *query_off;
+    const uint8_t *ref_res;   const int64_t *ref_off;
+    const int32_t *pair_query; const int32_t *pair_ref;
+    const int32_t *M; int32_t alpha; int64_t gap_open; int64_t gap_extend;
+    oracle_result *out;
+    atomic_long next;
+    atomic_int failed;
+} batch_job;
+
+static void *batch_worker(void *arg)
+{
+    batch_job *b = (batch_job *)arg;
+    for (;;) {
+        long k = atomic_fetch_add(&b->next, 1);
+        if (k >= b->n_pairs) break;
+        int32_t qi = b->pair_query ? b->pair_query[k] : 0;
+        int32_t ri = b->pair_ref[k];
+        const uint8_t *q = b->query_res + b->query_off[qi];
+        int64_t m = b->query_off[qi + 1] - b->query_off[qi];
+        const uint8_t *r = b->ref_res + b->ref_off[ri];
+        int64_t n = b->ref_off[ri + 1] - b->ref_off[ri];
+        if (oracle_sw(q, m, r, n, b->M, b->alpha, b->gap_open, b->gap_extend,
+                      &b->out[k]) != 0)
+            atomic_store(&b->failed, 1);
+    }
+    return NULL;
+}
+
+/* Queries and references are CSR (residues + n+1 offsets).  pair_query may
+ * be NULL (every pair uses query 0).  Uses n_threads POSIX threads (>= 1).
+ * Returns 0, or -1 if any pair failed. */
+int oracle_sw_batch(int64_t n_pairs,
+                    const uint8_t *query_res, const int64_t *query_off,
+                    const uint8_t *ref_res, const int64_t *ref_off,
+                    const int32_t *pair_query, const int32_t *pair_ref,
+                    const int32_t *M, int32_t alpha,
+                    int64_t gap_open, int64_t gap_extend,
+                    int32_t n_threads, oracle_result *out)
+{
+    batch_job b;
+    b.n_pairs = n_pairs;
+    b.query_res = query_res; b.query_off = query_off;
+    b.ref_res = ref_res; b.ref_off = ref_off;
+    b.pair_query = pair_query; b.pair_ref = pair_ref;
+    b.M = M; b.alpha = alpha; b.gap_open = gap_open; b.gap_extend = gap_extend;
+    b.out = out;
+    atomic_init(&b.next, 0);
+    atomic_init(&b.failed, 0);
+    if (n_threads < 1) n_threads = 1;
+    if (n_threads == 1) {
+        batch_worker(&b);
+        return atomic_load(&b.failed) ? -1 : 0;
+    }
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
+    if (!th) return -1;
+    int started = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        if (pthread_create(&th[t], NULL, batch_worker, &b) == 0) ++started;
+    }
+    if (started == 0) batch_worker(&b);
+    for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+    free(th);
+    return atomic_load(&b.failed) ? -1 : 0;
+}

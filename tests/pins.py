@@ -1,0 +1,74 @@
+"""Independent pins for the CPU oracle: definitions that do not share its recurrence.
+
+* ``brute_force`` enumerates every local alignment (a non-empty chain of index
+  pairs strictly increasing in both sequences) and scores it directly from the
+  definition: substitution scores minus g(L) = GapOpen + (L-1)*GapExtend for
+  each horizontal and each vertical gap block between consecutive pairs.
+* ``kadane_no_gaps`` is the closed form when gaps can never pay off: the best
+  maximum-subarray sum along any diagonal.
+* ``lcs`` is the textbook longest-common-subsequence DP, the closed form when
+  gaps are free and mismatches never help.
+"""
+from __future__ import annotations
+
+
+def gap_cost(L: int, go: int, ge: int) -> int:
+    return 0 if L == 0 else go + (L - 1) * ge
+
+
+def brute_force(q, r, M, go: int, ge: int):
+    """(score, query_end, ref_end) by enumerating every chain; tiny inputs only.
+
+    Ties on the score go to the smallest ref_end, then the smallest query_end.
+    """
+    m, n = len(q), len(r)
+    best = [0, -1, -1]
+
+    def consider(score, j, i):
+        if score > best[0] or (score == best[0] and score > 0 and (i, j) < (best[2], best[1])):
+            best[0], best[1], best[2] = score, j, i
+
+    def extend(i, j, score):
+        consider(score, j, i)
+        for i2 in range(i + 1, n):
+            for j2 in range(j + 1, m):
+                s2 = score + int(M[q[j2]][r[i2]]) - gap_cost(i2 - i - 1, go, ge) \
+                    - gap_cost(j2 - j - 1, go, ge)
+                extend(i2, j2, s2)
+
+    for i in range(n):
+        for j in range(m):
+            extend(i, j, int(M[q[j]][r[i]]))
+    if best[0] <= 0:
+        return (0, -1, -1)
+    return tuple(best)
+
+
+def kadane_no_gaps(q, r, M):
+    """Best gap-free local alignment: max over diagonals of the max-subarray sum.
+
+    Also returns the end cell (query_end, ref_end) with the smallest ref_end,
+    then the smallest query_end, among cells where a best run ends.
+    """
+    m, n = len(q), len(r)
+    best = (0, -1, -1)
+    ending = {}
+    for i in range(n):
+        for j in range(m):
+            prev = ending.get((i - 1, j - 1), 0)
+            cur = max(prev, 0) + int(M[q[j]][r[i]])
+            ending[(i, j)] = cur
+    cand = [(-v, i, j) for (i, j), v in ending.items() if v > 0]
+    if not cand:
+        return best
+    v, i, j = min(cand)
+    return (-v, j, i)
+
+
+def lcs(a, b) -> int:
+    m, n = len(a), len(b)
+    T = [[0] * (n + 1) for _ in range(m + 1)]
+    for x in range(m):
+        for y in range(n):
+            T[x + 1][y + 1] = T[x][y] + 1 if a[x] == b[y] else max(T[x][y + 1], T[x + 1][y])
+    return T[m][n]

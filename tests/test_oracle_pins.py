@@ -1,0 +1,250 @@
+"""Pins for the CPU oracle (no GPU).  Each check is independent of the oracle's
+own recurrence: brute-force enumeration of all local alignments, a
+hand-computed worked example, closed forms (Kadane, LCS) and invariants.
+A final test plants plausible mistakes into a copy of the Python oracle and
+shows that these pins catch every one of them."""
+import inspect
+import json
+import os
+import textwrap
+
+import numpy as np
+import pytest
+
+import oracle
+from tests import pins
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _build_oracle():
+    oracle.build(force=False)
+
+
+def _both(q, r, M, go, ge):
+    a = oracle.align(q, r, M, go, ge)
+    b = oracle.gotoh_py(list(q), list(r), M, go, ge)
+    assert a == b, (a, b)
+    return a
+
+
+def _case(rng, maxlen=6, alpha=None, symmetric=None):
+    alpha = alpha or int(rng.integers(2, 5))
+    m = int(rng.integers(1, maxlen + 1))
+    n = int(rng.integers(1, maxlen + 1))
+    q = rng.integers(0, alpha, size=m).tolist()
+    r = rng.integers(0, alpha, size=n).tolist()
+    M = rng.integers(-5, 6, size=(alpha, alpha))
+    if symmetric if symmetric is not None else rng.random() < 0.5:
+        M = np.triu(M) + np.triu(M, 1).T
+    go = int(rng.integers(0, 7))
+    ge = int(rng.integers(0, go + 1))
+    return q, r, M.astype(np.int32), go, ge
+
+
+# ---------------------------------------------------------------- worked example
+
+def test_worked_example_golden():
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    code = {c: k for k, c in enumerate(g["alphabet"])}
+    A = len(g["alphabet"])
+    M = np.full((A, A), g["mismatch"], dtype=np.int32)
+    np.fill_diagonal(M, g["match"])
+    q = [code[c] for c in g["query"]]
+    r = [code[c] for c in g["ref"]]
+    go, ge = g["gap_open"], g["gap_extend"]
+    res, hd_cols, h_cols = oracle.gotoh_py(q, r, M, go, ge, tables=True)
+    assert hd_cols == g["hdiag_by_column"]
+    assert h_cols == g["h_by_column"]
+    want = (g["result"]["score"], g["result"]["query_end"], g["result"]["ref_end"])
+    assert res == want
+    assert oracle.align(q, r, M, go, ge) == want
+    assert pins.brute_force(q, r, M, go, ge) == want
+    sw = g["swapped_result"]
+    assert oracle.align(r, q, M, go, ge) == (sw["score"], sw["query_end"], sw["ref_end"])
+    # The other gap convention (open + L*extend) is rejected by this example.
+    assert pins.brute_force(q, r, M, go + ge, ge)[0] == g["open_plus_l_extend_score"]
+
+
+# ---------------------------------------------------------------- brute force
+
+@pytest.mark.parametrize("seed", range(6))
+def test_brute_force_random(seed):
+    rng = np.random.default_rng(1000 + seed)
+    for _ in range(120):
+        q, r, M, go, ge = _case(rng)
+        assert _both(q, r, M, go, ge) == pins.brute_force(q, r, M, go, ge)
+
+
+def test_brute_force_edge_penalties():
+    rng = np.random.default_rng(77)
+    for go, ge in [(0, 0), (1, 0), (3, 3), (5, 1), (50, 50)]:
+        for _ in range(60):
+            q, r, M, _, _ = _case(rng)
+            assert _both(q, r, M, go, ge) == pins.brute_force(q, r, M, go, ge)
+
+
+def test_double_gap_bridge_family():
+    """A horizontal and a vertical gap in one block are strictly optimal here
+    (match +5 / mismatch -4, GapOpen 11, GapExtend 1, q = A^12 X^k B^12,
+    r = A^12 Y^k B^12 with X, Y never matching): checked against the closed form
+    of the two alignments that compete (gap-free vs bridged)."""
+    A_, B_, X_, Y_ = 0, 1, 2, 3
+    M = np.full((4, 4), -4, dtype=np.int32)
+    M[A_, A_] = M[B_, B_] = 5
+    for k in (11, 12, 16):
+        q = [A_] * 12 + [X_] * k + [B_] * 12
+        r = [A_] * 12 + [Y_] * k + [B_] * 12
+        no_gap = 24 * 5 - 4 * k
+        bridged = 24 * 5 - 2 * (11 + (k - 1) * 1)
+        want = max(no_gap, bridged, 60)
+        s, qe, re_ = oracle.align(q, r, M, 11, 1)
+        assert s == want
+        assert (qe, re_) == (len(q) - 1, len(r) - 1)
+        assert bridged > no_gap  # the gap->gap transition is what wins
+
+
+# ---------------------------------------------------------------- closed forms
+
+def test_kadane_no_gaps():
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        q, r, M, _, _ = _case(rng, maxlen=12)
+        big = 10 ** 6
+        assert _both(q, r, M, big, big) == pins.kadane_no_gaps(q, r, M)
+
+
+def test_lcs_free_gaps():
+    rng = np.random.default_rng(6)
+    for _ in range(300):
+        alpha = int(rng.integers(2, 5))
+        q, r, _, _, _ = _case(rng, maxlen=14, alpha=alpha)
+        M = -rng.integers(0, 4, size=(alpha, alpha))
+        np.fill_diagonal(M, 1)
+        assert _both(q, r, M.astype(np.int32), 0, 0)[0] == pins.lcs(q, r)
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_gap_extend_clamp():
+    rng = np.random.default_rng(7)
+    for _ in range(300):
+        q, r, M, go, _ = _case(rng, maxlen=10)
+        ge = go + int(rng.integers(1, 6))
+        assert oracle.align(q, r, M, go, ge) == oracle.align(q, r, M, go, go)
+
+
+def test_symmetry_and_reversal():
+    rng = np.random.default_rng(8)
+    for _ in range(300):
+        q, r, M, go, ge = _case(rng, maxlen=12, symmetric=True)
+        s = oracle.align(q, r, M, go, ge)[0]
+        assert oracle.align(r, q, M, go, ge)[0] == s
+        assert oracle.align(q[::-1], r[::-1], M, go, ge)[0] == s
+
+
+def test_self_alignment():
+    from paper_1909_00899_amd import workloads
+    M = workloads.protein_matrix()
+    d = np.diag(M)
+    # the protein matrix meets the sufficient condition: diagonal > 0 and
+    # every off-diagonal entry below the mean of its two diagonal entries
+    assert (d > 0).all()
+    assert all(M[a, b] < (d[a] + d[b]) / 2 for a in range(20) for b in range(20) if a != b)
+    rng = np.random.default_rng(9)
+    for m in (1, 2, 7, 50, 300):
+        q = rng.integers(0, 20, size=m)
+        assert oracle.align(q, q, M, 11, 1) == (int(d[q].sum()), m - 1, m - 1)
+    # the diagonal condition alone is not sufficient
+    M2 = np.array([[1, 10], [10, 1]], dtype=np.int32)
+    assert oracle.align([0, 1], [0, 1], M2, 5, 1)[0] == 10
+
+
+def test_bounds_and_monotonicity():
+    rng = np.random.default_rng(10)
+    for _ in range(300):
+        q, r, M, go, ge = _case(rng, maxlen=10)
+        s, qe, re_ = oracle.align(q, r, M, go, ge)
+        assert 0 <= s <= min(len(q), len(r)) * max(0, int(M.max()))
+        assert (s == 0) == (qe == -1) == (re_ == -1)
+        if s:
+            assert 0 <= qe < len(q) and 0 <= re_ < len(r)
+        a = int(rng.integers(0, M.shape[0]))
+        assert oracle.align(q + [a], r, M, go, ge)[0] >= s
+        assert oracle.align(q, [a] + r, M, go, ge)[0] >= s
+
+
+def test_empty_inputs():
+    M = np.eye(4, dtype=np.int32)
+    assert oracle.align([], [1, 2], M, 1, 1) == (0, -1, -1)
+    assert oracle.align([1], [], M, 1, 1) == (0, -1, -1)
+    assert oracle.gotoh_py([], [], M, 1, 1) == (0, -1, -1)
+
+
+def test_batch_matches_single():
+    from paper_1909_00899_amd import workloads
+    w = workloads.random_pairs(64, 20, (0, 40), (0, 60), seed=11)
+    out = oracle.align_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref,
+                             w.matrix, w.gap_open, w.gap_extend, pair_query=w.pair_query,
+                             n_threads=4)
+    for k in range(w.n_pairs):
+        q, r = w.pair(k)
+        assert tuple(out[k]) == oracle.align(q, r, w.matrix, w.gap_open, w.gap_extend)
+
+
+# ---------------------------------------------------------------- planted mistakes
+
+MUTANTS = {
+    "open_plus_L_extend": ("E[j] = h - gap_open if e_ext is None else max(e_ext, h - gap_open)",
+                           "E[j] = h - gap_open - gap_extend if e_ext is None else "
+                           "max(e_ext, h - gap_open - gap_extend)"),
+    "no_floor": ("cands = [0, hd]", "cands = [hd]"),
+    "drop_E": ("if E[j] is not None:\n                cands.append(E[j])",
+               "if False:\n                cands.append(E[j])"),
+    "drop_F": ("if F is not None:\n                cands.append(F)",
+               "if False:\n                cands.append(F)"),
+    "transposed_matrix": ("int(matrix[query[j]][ref[i]])", "int(matrix[ref[i]][query[j]])"),
+    "diag_index": ("diag = Hprev[j - 1] if j > 0 else 0", "diag = Hprev[j] if j > 0 else 0"),
+    "extend_sign": ("e_ext = E[j] - gap_extend", "e_ext = E[j] + gap_extend"),
+    "tie_break_ge": ("if hd > best:", "if hd >= best and hd > 0:"),
+    "max_after_gaps": ("            hd_col.append(hd)\n            if hd > best:\n"
+                       "                best, bq, br = hd, j, i\n",
+                       "            hd_col.append(hd)\n"),
+}
+
+
+def _mutant(name):
+    src = textwrap.dedent(inspect.getsource(oracle.gotoh_py))
+    old, new = MUTANTS[name]
+    assert old in src, name
+    src = src.replace(old, new)
+    if name == "max_after_gaps":
+        src = src.replace("            Hprev = Hcur\n",
+                          "            Hprev = Hcur\n"
+                          "            for jj, hv in enumerate(Hcur):\n"
+                          "                if hv > best:\n"
+                          "                    best, bq, br = hv, jj, i\n")
+    ns = dict(vars(oracle))
+    exec(src, ns)
+    return ns["gotoh_py"]
+
+
+def _pins_catch(fn) -> bool:
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    M = np.full((4, 4), g["mismatch"], dtype=np.int32)
+    np.fill_diagonal(M, g["match"])
+    if fn([0, 1, 2, 3], [0, 2, 3], M, 2, 1) != (7, 3, 2):
+        return True
+    rng = np.random.default_rng(4242)
+    for _ in range(400):
+        q, r, M, go, ge = _case(rng)
+        if fn(q, r, M, go, ge) != pins.brute_force(q, r, M, go, ge):
+            return True
+    return False
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_planted_mistakes(name):
+    assert _pins_catch(oracle.gotoh_py) is False
+    assert _pins_catch(_mutant(name)) is True
