@@ -1,0 +1,238 @@
+/*
+ * sw.h -- C ABI of the MI355X striped-scan Smith-Waterman library (libswscan.so).
+ *
+ * Operation (paper: Background section, problem statement; Algorithm 6,
+ * "Striped Smith-Waterman Scan"): the optimal LOCAL alignment score of a query
+ * q[0..m) against a reference r[0..n) under a substitution matrix S and affine
+ * gap penalties, plus the cell where a best alignment ends.
+ *
+ *   Hd(i,j) = H(i-1,j-1) + S[q_j][r_i]
+ *   E(i,j)  = max(E(i-1,j) - GapExtend, H(i-1,j) - GapOpen)
+ *   F(i,j)  = max(F(i,j-1) - GapExtend, H(i,j-1) - GapOpen)
+ *   H(i,j)  = max(0, Hd(i,j), E(i,j), F(i,j))
+ *   score   = max(0, max over all cells of Hd)
+ *
+ * i runs over the reference (the outer loop of the paper's algorithms), j over
+ * the query.  A gap of length L costs GapOpen + (L-1)*GapExtend.  The paper's
+ * algorithms require GapExtend <= GapOpen; the library uses
+ * min(GapExtend, GapOpen), which gives the same scores for every input
+ * (re-opening a gap at every residue already costs GapOpen per residue).
+ *
+ * End cell (not in the paper, which returns only the maximum): 0-based
+ * inclusive (query_end, ref_end) of the Hd cell achieving the score; among
+ * ties the smallest ref_end, then the smallest query_end.  (-1, -1) iff the
+ * score is 0.
+ *
+ * Residues are alphabet codes 0..alphabet_size-1 (uint8).  All integers are
+ * host-endian.  Every call returns an sw_status code; none aborts, throws or
+ * sets errno.  Calls are thread-safe; they serialise on one internal lock per
+ * device.  The library uses the HIP device that is current when sw_init (or
+ * the first call) runs.
+ */
+#ifndef SW_H_
+#define SW_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SW_OK = 0,
+    SW_PENDING = 1,      /* sw_server_poll: request not finished yet              */
+    SW_EINVAL = -1,      /* bad argument: NULL pointer, negative length or penalty,
+                            residue >= alphabet_size, alphabet_size outside 1..32,
+                            bad option value                                      */
+    SW_ENOMEM = -2,      /* device or host allocation failed, or a server request
+                            can never fit the server's memory budget             */
+    SW_EDEVICE = -3,     /* a HIP call failed (text via sw_last_error)            */
+    SW_EOVERFLOW = -4,   /* min(m, n) * max(0, max S) >= 2^31 - 1                  */
+    SW_ENOENT = -5,      /* unknown or already-collected server ticket            */
+    SW_EBUSY = -6        /* server queue full; retry later                        */
+} sw_status;
+
+/* Scoring scheme.  matrix is alphabet_size^2 int32, row-major, indexed
+ * matrix[query_code * alphabet_size + ref_code] (the paper's query profile
+ * holds S[query residue][reference residue]).  gap_open and gap_extend must be
+ * >= 0.  The caller owns matrix; the library copies it during each call. */
+typedef struct {
+    int32_t alphabet_size;      /* 1..32 */
+    const int32_t *matrix;
+    int32_t gap_open;           /* cost of a gap's first residue         */
+    int32_t gap_extend;         /* cost of each further residue          */
+} sw_scoring;
+
+#define SW_FLAG_SATURATED 1u    /* int16 lanes saturated; result recomputed in int32 */
+
+typedef struct {
+    int32_t score;              /* >= 0 */
+    int32_t query_end;          /* 0-based inclusive; -1 iff score == 0 */
+    int32_t ref_end;            /* 0-based inclusive; -1 iff score == 0 */
+    uint32_t flags;             /* SW_FLAG_* */
+} sw_result;
+
+/* Human-readable text of a status code (static storage). */
+const char *sw_strerror(int code);
+
+/* Text of the last SW_EDEVICE / SW_ENOMEM error on this thread ("" if none). */
+const char *sw_last_error(void);
+
+/* Select and initialise the device (optional; the first call does it with
+ * the current device).  Returns SW_EDEVICE if no gfx950 device is usable. */
+int sw_init(int device);
+
+/* Release every device buffer the library holds.  Servers must be destroyed
+ * first.  The library may be used again afterwards. */
+int sw_shutdown(void);
+
+/* ---------------------------------------------------------------------------
+ * sw_align -- one pair, one kernel launch ("plain" form of Algorithm 6).
+ *
+ * The query is striped over one wavefront sub-group (lanes x segLen query rows,
+ * paper: Algorithm 6 and the striped layout it inherits); every reference
+ * residue is one column step; the vertical-gap correction is the max-plus
+ * scan over lanes.  int32 arithmetic, exact while min(m,n)*max S < 2^31-1.
+ * query/ref are HOST buffers (copied before return); out is host memory.
+ * Empty query or reference is valid and yields {0, -1, -1, 0}.
+ * ------------------------------------------------------------------------- */
+int sw_align(const uint8_t *query, int32_t query_len,
+             const uint8_t *ref, int32_t ref_len,
+             const sw_scoring *sc, sw_result *out);
+
+/* ---------------------------------------------------------------------------
+ * sw_align_batch -- many pairs of uneven lengths in one persistent launch.
+ *
+ * Queries and references are CSR: residues concatenated, offsets of length
+ * count+1 (int64, nondecreasing, offsets[0] == 0).  Pair k aligns query
+ * pair_query[k] (or query 0 if pair_query is NULL) with reference
+ * pair_ref[k].  out[k] receives pair k's result (host memory, n_pairs
+ * entries).
+ *
+ * precision: SW_PREC_AUTO runs packed int16x2 lanes (two alignments per
+ * 32-bit lane) and recomputes in int32 every pair whose int16 maximum reached
+ * 32767 (the int16 result is exact iff its maximum is below 32767, because
+ * every H, E and F value is bounded by the running maximum); the recomputed
+ * result carries SW_FLAG_SATURATED.  SW_PREC_I32 runs int32 only.
+ *
+ * device_resident: 0 => the six sequence/offset/pair pointers are host
+ * memory; 1 => they are device memory on the library's device (e.g. torch
+ * tensors) and must stay valid until the call returns.  The call is
+ * synchronous either way.
+ * ------------------------------------------------------------------------- */
+enum { SW_PREC_AUTO = 0, SW_PREC_I32 = 1 };
+
+typedef struct {
+    int32_t n_pairs;
+    const uint8_t *query_res; const int64_t *query_off; int32_t n_queries;
+    const uint8_t *ref_res;   const int64_t *ref_off;   int32_t n_refs;
+    const int32_t *pair_query;   /* n_pairs entries or NULL (=> query 0) */
+    const int32_t *pair_ref;     /* n_pairs entries                      */
+    int32_t precision;           /* SW_PREC_*                             */
+    int32_t device_resident;     /* 0 host, 1 device                      */
+    void *stream;                /* hipStream_t to order device-resident inputs
+                                    against, or NULL for the default stream */
+} sw_batch;
+
+int sw_align_batch(const sw_batch *b, const sw_scoring *sc, sw_result *out);
+
+/* Options and statistics for the extended batch call (tests, benchmarks,
+ * the autotuner).  Zero-initialise and set what you need. */
+enum { SW_ALG_SCAN = 0,          /* max-plus scan, deferred H fix-up (Algorithm 6) */
+       SW_ALG_LAZYF = 1 };       /* lazy-F correction loop (Algorithm 1), comparator */
+
+typedef struct {
+    int32_t algorithm;           /* SW_ALG_*                                        */
+    int32_t force_lanes;         /* 0 = planner's choice; 16, 32 or 64 = lanes per
+                                    alignment for every pair                        */
+    int32_t force_seglen;        /* 0 = planner's choice; else rows per lane (the
+                                    query is split into chunks of lanes*seglen rows) */
+    int32_t force_kernel;        /* 0 = planner's choice; 1 = shared-query kernel;
+                                    2 = per-pair kernel                              */
+    int32_t mixed_layout;        /* per-pair kernel: 1 = pack 32- and 16-lane
+                                    sub-groups into one wavefront where lengths allow */
+    int32_t int16_cap;           /* 0 = 32767; else a lower saturation threshold for
+                                    the int16 pass (tests force the int32 rerun)     */
+    int32_t use_graph;           /* 1 = capture the launches into a hipGraph and
+                                    replay it                                       */
+    int32_t reserved[9];
+} sw_options;
+
+typedef struct {
+    double kernel_ms;            /* device time of the alignment kernels (hipEvents) */
+    double total_ms;             /* wall time of the call                           */
+    int64_t cells;               /* sum of m*n over pairs                           */
+    int64_t padded_cells;        /* cells including lane/row/column padding          */
+    int32_t n_rerun;             /* pairs recomputed in int32                        */
+    int32_t n_launches;          /* alignment kernel launches                        */
+    int64_t lazyf_steps;         /* SW_ALG_LAZYF: inner correction steps executed    */
+    int64_t columns;             /* column steps executed (per sub-group)            */
+    int32_t lanes_used[3];       /* pairs run with 16 / 32 / 64 lanes                */
+    int32_t seglen_max;          /* largest rows-per-lane used                       */
+    int32_t reserved[8];
+} sw_stats;
+
+int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options *opt,
+                      sw_result *out, sw_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a continuous-batching request loop.
+ *
+ * A resident database of references stays in device memory.  Each request is
+ * one query against one database reference under one of the server's scoring
+ * schemes.  A scheduler thread admits queued requests while the in-flight
+ * work fits hbm_budget_bytes and launches them as batches on several HIP
+ * streams, so requests that arrive while others run overlap with them on the
+ * device.  Results are bit-identical to sw_align_batch on the same pair.
+ * ------------------------------------------------------------------------- */
+typedef struct sw_server sw_server;
+
+typedef struct {
+    size_t hbm_budget_bytes;        /* device bytes the in-flight requests may use */
+    int32_t max_queued;             /* requests accepted but not yet collected     */
+    const uint8_t *db_res;          /* resident references, CSR, host memory       */
+    const int64_t *db_off;
+    int32_t n_db;
+    const sw_scoring *scorings;     /* n_scorings schemes (copied)                 */
+    int32_t n_scorings;
+    int32_t max_batch;              /* requests per launch (0 = library default)   */
+    int32_t n_streams;              /* concurrent launches (0 = library default)   */
+    int32_t reserved[6];
+} sw_server_config;
+
+int sw_server_create(const sw_server_config *cfg, sw_server **out);
+
+/* Copies the query; returns a ticket.  SW_EBUSY if max_queued requests are
+ * outstanding; SW_ENOMEM if the request alone exceeds the budget; SW_EINVAL
+ * for a bad ref_id / scoring_id / residue. */
+int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len,
+                     int32_t ref_id, int32_t scoring_id, uint64_t *ticket);
+
+/* SW_OK (result written; the ticket is then forgotten), SW_PENDING, or
+ * SW_ENOENT for an unknown or already-collected ticket.  If timestamps_ns is
+ * not NULL it receives {submit, admit, done} times (CLOCK_MONOTONIC ns). */
+int sw_server_poll(sw_server *s, uint64_t ticket, sw_result *out, int64_t *timestamps_ns);
+
+/* Blocks until every accepted request has finished. */
+int sw_server_drain(sw_server *s);
+
+/* Stops the scheduler and frees the server's device memory.  Uncollected
+ * tickets are dropped. */
+int sw_server_destroy(sw_server *s);
+
+/* Open-loop replay for measurement: submits request k at arrival_ns[k]
+ * (nanoseconds after the call starts; nondecreasing) from one thread while
+ * another collects completions, then waits for all of them.  Queries are CSR
+ * (host).  out[k] gets the result; times_ns[3k..3k+2] = {submit, admit, done}
+ * relative to the call's start.  A submit that returns SW_EBUSY is retried
+ * until accepted (its submit time is the first attempt). */
+int sw_server_replay(sw_server *s, int32_t n_requests, const uint8_t *query_res,
+                     const int64_t *query_off, const int32_t *ref_id,
+                     const int32_t *scoring_id, const int64_t *arrival_ns,
+                     sw_result *out, int64_t *times_ns);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SW_H_ */

@@ -1,0 +1,329 @@
+"""Thin ctypes binding of libswscan.so (include/sw.h), same entry-point names.
+
+Argument marshalling only: every alignment step runs in the library's HIP
+kernels.  Torch tensors on the GPU may be passed to ``sw_align_batch`` (they
+are handed over as device pointers with ``device_resident=1`` and torch's
+current stream); numpy arrays are host memory.  If the library is missing the
+first call raises ``NativeLibraryError``: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswscan.so")
+
+SW_OK, SW_PENDING, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_EOVERFLOW, SW_ENOENT, SW_EBUSY = \
+    0, 1, -1, -2, -3, -4, -5, -6
+SW_PREC_AUTO, SW_PREC_I32 = 0, 1
+SW_ALG_SCAN, SW_ALG_LAZYF = 0, 1
+SW_FLAG_SATURATED = 1
+
+EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align",
+            "sw_align_batch", "sw_align_batch_ex", "sw_server_create", "sw_server_submit",
+            "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay"]
+
+
+class NativeLibraryError(RuntimeError):
+    pass
+
+
+class SwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("%s (%d): %s" % (_strerror(code), code, msg))
+        self.code = code
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("alphabet_size", ctypes.c_int32), ("matrix", ctypes.c_void_p),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int32), ("query_end", ctypes.c_int32),
+                ("ref_end", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Batch(ctypes.Structure):
+    _fields_ = [("n_pairs", ctypes.c_int32),
+                ("query_res", ctypes.c_void_p), ("query_off", ctypes.c_void_p),
+                ("n_queries", ctypes.c_int32),
+                ("ref_res", ctypes.c_void_p), ("ref_off", ctypes.c_void_p),
+                ("n_refs", ctypes.c_int32),
+                ("pair_query", ctypes.c_void_p), ("pair_ref", ctypes.c_void_p),
+                ("precision", ctypes.c_int32), ("device_resident", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("algorithm", ctypes.c_int32), ("force_lanes", ctypes.c_int32),
+                ("force_seglen", ctypes.c_int32), ("force_kernel", ctypes.c_int32),
+                ("mixed_layout", ctypes.c_int32), ("int16_cap", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("cells", ctypes.c_int64), ("padded_cells", ctypes.c_int64),
+                ("n_rerun", ctypes.c_int32), ("n_launches", ctypes.c_int32),
+                ("lazyf_steps", ctypes.c_int64), ("columns", ctypes.c_int64),
+                ("lanes_used", ctypes.c_int32 * 3), ("seglen_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
+
+    def as_dict(self) -> dict:
+        return {"kernel_ms": self.kernel_ms, "total_ms": self.total_ms, "cells": self.cells,
+                "padded_cells": self.padded_cells, "n_rerun": self.n_rerun,
+                "n_launches": self.n_launches, "lazyf_steps": self.lazyf_steps,
+                "columns": self.columns, "lanes_used": list(self.lanes_used),
+                "seglen_max": self.seglen_max}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_queued", ctypes.c_int32),
+                ("db_res", ctypes.c_void_p), ("db_off", ctypes.c_void_p),
+                ("n_db", ctypes.c_int32), ("scorings", ctypes.c_void_p),
+                ("n_scorings", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+
+
+_lib = None
+
+
+def load():
+    """Load libswscan.so (raises NativeLibraryError if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise NativeLibraryError("%s is missing; run __graft_entry__.build()" % LIB_PATH)
+    # One HIP runtime per process: torch ships its own libamdhip64 (same soname
+    # as the system one).  Loading torch first makes this library bind to the
+    # runtime torch already mapped instead of mapping a second one.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    try:
+        lib = ctypes.CDLL(LIB_PATH)
+    except OSError as e:
+        raise NativeLibraryError("cannot load %s: %s" % (LIB_PATH, e))
+    lib.sw_strerror.restype = ctypes.c_char_p
+    lib.sw_strerror.argtypes = [ctypes.c_int]
+    lib.sw_last_error.restype = ctypes.c_char_p
+    lib.sw_last_error.argtypes = []
+    lib.sw_init.argtypes = [ctypes.c_int]
+    lib.sw_shutdown.argtypes = []
+    lib.sw_align.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                             ctypes.POINTER(Scoring), ctypes.POINTER(Result)]
+    lib.sw_align_batch.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), ctypes.c_void_p]
+    lib.sw_align_batch_ex.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
+                                      ctypes.POINTER(Options), ctypes.c_void_p,
+                                      ctypes.POINTER(Stats)]
+    _bind_server(lib)
+    for name in EXPORTED:
+        if not hasattr(lib, name):
+            raise NativeLibraryError("%s does not export %s" % (LIB_PATH, name))
+    _lib = lib
+    return lib
+
+
+def _bind_server(lib):
+    lib.sw_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(ctypes.c_void_p)]
+    lib.sw_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_uint64)]
+    lib.sw_server_poll.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(Result),
+                                   ctypes.c_void_p]
+    lib.sw_server_drain.argtypes = [ctypes.c_void_p]
+    lib.sw_server_destroy.argtypes = [ctypes.c_void_p]
+    lib.sw_server_replay.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+
+
+def _strerror(code: int) -> str:
+    try:
+        return load().sw_strerror(code).decode()
+    except NativeLibraryError:
+        return "error"
+
+
+def _check(code: int) -> int:
+    if code < 0:
+        raise SwError(code, load().sw_last_error().decode())
+    return code
+
+
+def make_scoring(matrix, gap_open: int, gap_extend: int):
+    M = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
+    if M.ndim != 2 or M.shape[0] != M.shape[1]:
+        raise ValueError("matrix must be square")
+    sc = Scoring(M.shape[0], M.ctypes.data, int(gap_open), int(gap_extend))
+    return sc, M  # keep M alive with the struct
+
+
+def sw_init(device: int = -1) -> None:
+    _check(load().sw_init(device))
+
+
+def sw_align(query, ref, matrix, gap_open: int, gap_extend: int):
+    """One pair, one launch.  Returns (score, query_end, ref_end, flags)."""
+    q = np.ascontiguousarray(np.asarray(query, dtype=np.uint8))
+    r = np.ascontiguousarray(np.asarray(ref, dtype=np.uint8))
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    res = Result()
+    _check(load().sw_align(q.ctypes.data if q.size else None, q.size,
+                           r.ctypes.data if r.size else None, r.size,
+                           ctypes.byref(sc), ctypes.byref(res)))
+    return res.score, res.query_end, res.ref_end, res.flags
+
+
+def _is_torch_cuda(x) -> bool:
+    return type(x).__module__.startswith("torch") and getattr(x, "is_cuda", False)
+
+
+@dataclass
+class BatchOutput:
+    results: np.ndarray      # (n_pairs, 4) int64: score, query_end, ref_end, flags
+    stats: dict
+
+
+def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap_open: int,
+                   gap_extend: int, pair_query=None, precision: int = SW_PREC_AUTO,
+                   algorithm: int = SW_ALG_SCAN, force_lanes: int = 0, force_seglen: int = 0,
+                   force_kernel: int = 0, mixed_layout: int = 0, int16_cap: int = 0,
+                   use_graph: int = 0) -> BatchOutput:
+    """Many pairs in one persistent launch (plus an int32 rerun if needed).
+
+    Sequences are CSR.  Either all six arrays are numpy (host) or all are torch
+    CUDA tensors (device-resident; torch's current stream orders them).
+    """
+    lib = load()
+    dev = _is_torch_cuda(ref_res)
+    keep = []
+    if dev:
+        import torch
+        arrs = [query_res, query_off, ref_res, ref_off, pair_ref] + \
+            ([] if pair_query is None else [pair_query])
+        for a, dt in zip(arrs, [torch.uint8, torch.int64, torch.uint8, torch.int64, torch.int32,
+                                torch.int32]):
+            if not (_is_torch_cuda(a) and a.dtype == dt and a.is_contiguous()):
+                raise TypeError("device-resident inputs must be contiguous CUDA tensors of "
+                                "uint8/int64/uint8/int64/int32/int32")
+        ptr = lambda a: a.data_ptr() if a.numel() else None  # noqa: E731
+        nq, nr, npairs = query_off.numel() - 1, ref_off.numel() - 1, pair_ref.numel()
+        stream = torch.cuda.current_stream().cuda_stream
+    else:
+        query_res = np.ascontiguousarray(np.asarray(query_res, dtype=np.uint8))
+        query_off = np.ascontiguousarray(np.asarray(query_off, dtype=np.int64))
+        ref_res = np.ascontiguousarray(np.asarray(ref_res, dtype=np.uint8))
+        ref_off = np.ascontiguousarray(np.asarray(ref_off, dtype=np.int64))
+        pair_ref = np.ascontiguousarray(np.asarray(pair_ref, dtype=np.int32))
+        if pair_query is not None:
+            pair_query = np.ascontiguousarray(np.asarray(pair_query, dtype=np.int32))
+        keep += [query_res, query_off, ref_res, ref_off, pair_ref, pair_query]
+        ptr = lambda a: a.ctypes.data if a.size else None  # noqa: E731
+        nq, nr, npairs = query_off.size - 1, ref_off.size - 1, pair_ref.size
+        stream = None
+    b = Batch(npairs, ptr(query_res), ptr(query_off), nq, ptr(ref_res), ptr(ref_off), nr,
+              None if pair_query is None else ptr(pair_query), ptr(pair_ref), precision,
+              1 if dev else 0, stream)
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    opt = Options(algorithm, force_lanes, force_seglen, force_kernel, mixed_layout, int16_cap,
+                  use_graph)
+    out = np.zeros((max(npairs, 1), 4), dtype=np.int32)
+    st = Stats()
+    _check(lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
+                                 out.ctypes.data, ctypes.byref(st)))
+    res = out[:npairs].astype(np.int64)
+    res[:, 3] = out[:npairs, 3].view(np.uint32)
+    return BatchOutput(res, st.as_dict())
+
+
+def align_workload(w, **kw) -> BatchOutput:
+    """sw_align_batch on a ``workloads.Workload`` (host arrays)."""
+    return sw_align_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref, w.matrix,
+                          w.gap_open, w.gap_extend, pair_query=w.pair_query, **kw)
+
+
+class Server:
+    """Continuous-batching request server over a resident reference database."""
+
+    def __init__(self, db_res, db_off, scorings, hbm_budget_bytes: int = 0, max_queued: int = 0,
+                 max_batch: int = 0, n_streams: int = 0):
+        lib = load()
+        self._db_res = np.ascontiguousarray(np.asarray(db_res, dtype=np.uint8))
+        self._db_off = np.ascontiguousarray(np.asarray(db_off, dtype=np.int64))
+        self._keep = []
+        arr = (Scoring * len(scorings))()
+        for k, (M, go, ge) in enumerate(scorings):
+            sc, Mk = make_scoring(M, go, ge)
+            arr[k] = sc
+            self._keep.append(Mk)
+        self._scorings = arr
+        cfg = ServerConfig(hbm_budget_bytes, max_queued, self._db_res.ctypes.data,
+                           self._db_off.ctypes.data, self._db_off.size - 1,
+                           ctypes.cast(arr, ctypes.c_void_p), len(scorings), max_batch, n_streams)
+        h = ctypes.c_void_p()
+        _check(lib.sw_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, query, ref_id: int, scoring_id: int = 0) -> int:
+        q = np.ascontiguousarray(np.asarray(query, dtype=np.uint8))
+        t = ctypes.c_uint64()
+        rc = load().sw_server_submit(self._h, q.ctypes.data if q.size else None, q.size, ref_id,
+                                     scoring_id, ctypes.byref(t))
+        if rc == SW_EBUSY:
+            return -1
+        _check(rc)
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending; else (score, query_end, ref_end, flags, (submit, admit, done) ns)."""
+        res = Result()
+        ts = (ctypes.c_int64 * 3)()
+        rc = load().sw_server_poll(self._h, ticket, ctypes.byref(res), ts)
+        if rc == SW_PENDING:
+            return None
+        _check(rc)
+        return res.score, res.query_end, res.ref_end, res.flags, tuple(ts)
+
+    def drain(self) -> None:
+        _check(load().sw_server_drain(self._h))
+
+    def replay(self, query_res, query_off, ref_id, scoring_id, arrival_s):
+        """Open-loop replay; returns (results (n,4), times_ns (n,3): submit, admit, done)."""
+        qres = np.ascontiguousarray(np.asarray(query_res, dtype=np.uint8))
+        qoff = np.ascontiguousarray(np.asarray(query_off, dtype=np.int64))
+        rid = np.ascontiguousarray(np.asarray(ref_id, dtype=np.int32))
+        sid = np.ascontiguousarray(np.asarray(scoring_id, dtype=np.int32))
+        arr = np.ascontiguousarray((np.asarray(arrival_s, dtype=np.float64) * 1e9).astype(np.int64))
+        n = rid.size
+        out = np.zeros((max(n, 1), 4), dtype=np.int32)
+        ts = np.zeros((max(n, 1), 3), dtype=np.int64)
+        _check(load().sw_server_replay(self._h, n, qres.ctypes.data, qoff.ctypes.data,
+                                       rid.ctypes.data, sid.ctypes.data, arr.ctypes.data,
+                                       out.ctypes.data, ts.ctypes.data))
+        return out[:n].astype(np.int64), ts[:n]
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().sw_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

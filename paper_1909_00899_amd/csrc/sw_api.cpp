@@ -1,0 +1,256 @@
+// Public C entry points of libswscan.so (include/sw.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+#include "sw.h"
+#include "sw_runtime.h"
+
+using namespace swrt;
+using swk::PairInfo;
+
+namespace {
+
+#define HIPCHK(expr)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                __LINE__);                                                       \
+      return SW_EDEVICE;                                                         \
+    }                                                                            \
+  } while (0)
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+constexpr int64_t kI32Limit = 2147483647ll;
+
+bool overflows(int64_t m, int64_t n, int max_s) {
+  return std::min(m, n) * (int64_t)max_s >= kI32Limit;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sw_strerror(int code) {
+  switch (code) {
+    case SW_OK: return "ok";
+    case SW_PENDING: return "pending";
+    case SW_EINVAL: return "invalid argument";
+    case SW_ENOMEM: return "out of memory or over the memory budget";
+    case SW_EDEVICE: return "HIP device error";
+    case SW_EOVERFLOW: return "score could exceed the int32 range";
+    case SW_ENOENT: return "unknown ticket";
+    case SW_EBUSY: return "queue full";
+  }
+  return "unknown status";
+}
+
+const char *sw_last_error(void) { return g_last_error.c_str(); }
+
+int sw_init(int device) { return ensure_init(device); }
+
+int sw_shutdown(void) {
+  std::lock_guard<std::mutex> g(g_ctx.mu);
+  g_ctx.shutdown();
+  return SW_OK;
+}
+
+int sw_align(const uint8_t *query, int32_t query_len, const uint8_t *ref, int32_t ref_len,
+             const sw_scoring *sc, sw_result *out) {
+  if (!out || query_len < 0 || ref_len < 0 || (query_len > 0 && !query) ||
+      (ref_len > 0 && !ref)) {
+    set_error("bad argument to sw_align");
+    return SW_EINVAL;
+  }
+  Scoring S;
+  int rc = prepare_scoring(sc, S);
+  if (rc) return rc;
+  for (int k = 0; k < query_len; ++k)
+    if (query[k] >= S.alpha) { set_error("query residue %d out of range", k); return SW_EINVAL; }
+  for (int k = 0; k < ref_len; ++k)
+    if (ref[k] >= S.alpha) { set_error("reference residue %d out of range", k); return SW_EINVAL; }
+  *out = sw_result{0, -1, -1, 0};
+  if (query_len == 0 || ref_len == 0) return SW_OK;
+  if (overflows(query_len, ref_len, S.max_s)) { set_error("score may overflow int32"); return SW_EOVERFLOW; }
+  if ((rc = ensure_init())) return rc;
+  std::lock_guard<std::mutex> g(g_ctx.mu);
+  Context &C = g_ctx;
+  HIPCHK(hipSetDevice(C.device));
+  if ((rc = C.qres.ensure(query_len)) || (rc = C.rres.ensure(ref_len))) return rc;
+  HIPCHK(hipMemcpyAsync(C.qres.p, query, query_len, hipMemcpyHostToDevice, C.stream));
+  HIPCHK(hipMemcpyAsync(C.rres.p, ref, ref_len, hipMemcpyHostToDevice, C.stream));
+  ExecInput in;
+  in.d_qres = C.qres.as<uint8_t>();
+  in.d_rres = C.rres.as<uint8_t>();
+  PairInfo p;
+  std::memset(&p, 0, sizeof(p));
+  p.m = query_len;
+  p.n = ref_len;
+  in.pairs.push_back(p);
+  in.items.push_back(PlanItem{0, 0, query_len, ref_len});
+  in.n_queries = 1;
+  in.q_off_of_query = {0};
+  in.m_of_query = {query_len};
+  ExecOptions opt;
+  opt.force_kernel = 1;
+  opt.force_lanes = 64;
+  return run_batch(in, S, SW_PREC_I32, opt, C.ws, 1, C.stream, C.ev0, C.ev1, C.num_cus, out,
+                   nullptr);
+}
+
+int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options *opt,
+                      sw_result *out, sw_stats *stats) {
+  const double t0 = now_ms();
+  if (!b || !out) { set_error("batch or out is NULL"); return SW_EINVAL; }
+  if (b->n_pairs < 0 || b->n_queries < 0 || b->n_refs < 0) { set_error("negative count"); return SW_EINVAL; }
+  if (b->precision != SW_PREC_AUTO && b->precision != SW_PREC_I32) { set_error("bad precision"); return SW_EINVAL; }
+  Scoring S;
+  int rc = prepare_scoring(sc, S);
+  if (rc) return rc;
+  ExecOptions eo;
+  if (opt) {
+    if (opt->algorithm != SW_ALG_SCAN && opt->algorithm != SW_ALG_LAZYF) { set_error("bad algorithm"); return SW_EINVAL; }
+    if (opt->force_lanes && opt->force_lanes != 16 && opt->force_lanes != 32 && opt->force_lanes != 64) {
+      set_error("force_lanes must be 0, 16, 32 or 64");
+      return SW_EINVAL;
+    }
+    if (opt->force_seglen < 0 || opt->int16_cap < 0 || opt->int16_cap > 32767 ||
+        opt->force_kernel < 0 || opt->force_kernel > 2) {
+      set_error("bad option value");
+      return SW_EINVAL;
+    }
+    eo.algorithm = opt->algorithm;
+    eo.force_lanes = opt->force_lanes;
+    eo.force_seglen = opt->force_seglen;
+    eo.force_kernel = opt->force_kernel;
+    eo.mixed_layout = opt->mixed_layout;
+    if (opt->int16_cap) eo.int16_cap = opt->int16_cap;
+  }
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  const int np = b->n_pairs;
+  if (np == 0) return SW_OK;
+  if (!b->query_res || !b->query_off || !b->ref_res || !b->ref_off || !b->pair_ref ||
+      b->n_queries < 1 || b->n_refs < 1) {
+    set_error("NULL sequence pointer or empty query/reference set");
+    return SW_EINVAL;
+  }
+  if ((rc = ensure_init())) return rc;
+  std::lock_guard<std::mutex> g(g_ctx.mu);
+  Context &C = g_ctx;
+  HIPCHK(hipSetDevice(C.device));
+  hipStream_t st = C.stream;
+  if (b->device_resident && b->stream) {
+    HIPCHK(hipEventRecord(C.evx, (hipStream_t)b->stream));
+    HIPCHK(hipStreamWaitEvent(st, C.evx, 0));
+  }
+  // host views of offsets and pair lists
+  std::vector<int64_t> qoff_v, roff_v;
+  std::vector<int32_t> pq_v, pr_v;
+  const int64_t *qoff = b->query_off, *roff = b->ref_off;
+  const int32_t *pq = b->pair_query, *pr = b->pair_ref;
+  if (b->device_resident) {
+    qoff_v.resize(b->n_queries + 1);
+    roff_v.resize(b->n_refs + 1);
+    pr_v.resize(np);
+    HIPCHK(hipMemcpyAsync(qoff_v.data(), qoff, qoff_v.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(roff_v.data(), roff, roff_v.size() * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pr_v.data(), pr, pr_v.size() * 4, hipMemcpyDeviceToHost, st));
+    if (pq) {
+      pq_v.resize(np);
+      HIPCHK(hipMemcpyAsync(pq_v.data(), pq, pq_v.size() * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    qoff = qoff_v.data();
+    roff = roff_v.data();
+    pr = pr_v.data();
+    pq = pq ? pq_v.data() : nullptr;
+  }
+  for (int q = 0; q < b->n_queries; ++q)
+    if (qoff[q] < 0 || qoff[q + 1] < qoff[q] || qoff[q + 1] - qoff[q] > kI32Limit) {
+      set_error("query offsets not nondecreasing at %d", q);
+      return SW_EINVAL;
+    }
+  for (int r = 0; r < b->n_refs; ++r)
+    if (roff[r] < 0 || roff[r + 1] < roff[r] || roff[r + 1] - roff[r] > kI32Limit) {
+      set_error("reference offsets not nondecreasing at %d", r);
+      return SW_EINVAL;
+    }
+  ExecInput in;
+  in.n_queries = b->n_queries;
+  in.q_off_of_query.resize(b->n_queries);
+  in.m_of_query.resize(b->n_queries);
+  for (int q = 0; q < b->n_queries; ++q) {
+    in.q_off_of_query[q] = qoff[q];
+    in.m_of_query[q] = (int)(qoff[q + 1] - qoff[q]);
+  }
+  in.pairs.resize(np);
+  in.items.reserve(np);
+  int64_t cells = 0;
+  for (int k = 0; k < np; ++k) {
+    const int q = pq ? pq[k] : 0;
+    const int r = pr[k];
+    if (q < 0 || q >= b->n_queries || r < 0 || r >= b->n_refs) {
+      set_error("pair %d refers to query %d / reference %d out of range", k, q, r);
+      return SW_EINVAL;
+    }
+    PairInfo &p = in.pairs[k];
+    std::memset(&p, 0, sizeof(p));
+    p.q_off = qoff[q];
+    p.r_off = roff[r];
+    p.m = (int)(qoff[q + 1] - qoff[q]);
+    p.n = (int)(roff[r + 1] - roff[r]);
+    p.out = k;
+    if (overflows(p.m, p.n, S.max_s)) { set_error("pair %d may overflow int32", k); return SW_EOVERFLOW; }
+    out[k] = sw_result{0, -1, -1, 0};
+    if (p.m > 0 && p.n > 0) {
+      in.items.push_back(PlanItem{k, q, p.m, p.n});
+      cells += (int64_t)p.m * p.n;
+    }
+  }
+  // sequences on the device
+  const int64_t qbytes = qoff[b->n_queries], rbytes = roff[b->n_refs];
+  if (b->device_resident) {
+    in.d_qres = b->query_res;
+    in.d_rres = b->ref_res;
+  } else {
+    if ((rc = C.qres.ensure(std::max<int64_t>(qbytes, 1))) || (rc = C.rres.ensure(std::max<int64_t>(rbytes, 1))))
+      return rc;
+    if (qbytes) HIPCHK(hipMemcpyAsync(C.qres.p, b->query_res, qbytes, hipMemcpyHostToDevice, st));
+    if (rbytes) HIPCHK(hipMemcpyAsync(C.rres.p, b->ref_res, rbytes, hipMemcpyHostToDevice, st));
+    in.d_qres = C.qres.as<uint8_t>();
+    in.d_rres = C.rres.as<uint8_t>();
+  }
+  if ((rc = C.flag.ensure(16))) return rc;
+  HIPCHK(hipMemsetAsync(C.flag.p, 0, 16, st));
+  HIPCHK(swk::launch_check_residues(in.d_qres, qbytes, S.alpha, C.flag.as<int>(), st));
+  HIPCHK(swk::launch_check_residues(in.d_rres, rbytes, S.alpha, C.flag.as<int>(), st));
+  rc = run_batch(in, S, b->precision, eo, C.ws, np, st, C.ev0, C.ev1, C.num_cus, out, stats);
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, C.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) {
+    for (int k = 0; k < np; ++k) out[k] = sw_result{0, -1, -1, 0};
+    set_error("a residue code is >= alphabet_size");
+    return SW_EINVAL;
+  }
+  if (rc) return rc;
+  if (stats) {
+    stats->cells = cells;
+    stats->total_ms = now_ms() - t0;
+  }
+  return SW_OK;
+}
+
+int sw_align_batch(const sw_batch *b, const sw_scoring *sc, sw_result *out) {
+  return sw_align_batch_ex(b, sc, nullptr, out, nullptr);
+}
+
+}  // extern "C"

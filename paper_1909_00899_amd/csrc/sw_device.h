@@ -1,0 +1,624 @@
+// gfx950 kernels for the striped Smith-Waterman scan (paper: Algorithm 6).
+//
+// Layout (paper: striped layout of Algorithm 1/6).  One alignment runs on a
+// sub-group of P = 16, 32 or 64 lanes of a wavefront.  Lane l holds query rows
+// l*SEG + j, j < SEG, of the current query chunk, with H[j] and E[j] in VGPRs.
+// In packed int16 mode every 32-bit lane value carries two independent
+// alignments (low and high half), so a wavefront of four 16-lane sub-groups
+// runs eight alignments; the cross-lane data movement is identical for both
+// halves.  One reference residue = one column step for every sub-group of the
+// wavefront, in lockstep.
+//
+// Column step for reference residue r_i (paper: Algorithm 6, with the readings
+// spelled out in the host runtime's documentation):
+//   top       H_last = max(H[SEG-1], Fscan - (SEG-1)*ge)   corrected last row of
+//             the previous column; moved one lane down (lane 0 of a sub-group
+//             gets 0, or the previous query chunk's boundary value).
+//   inner     hd = Hin + prof[r_i][j];  Max = max(Max, hd)
+//             h = max(hd, E[j], F);     t = h - go (saturating at 0)
+//             E[j] = max(E[j] - ge, t); F = max(F - ge, t)
+//             Hin = max(H_old[j], Fscan - j*ge)   (deferred "lazier" H fix-up)
+//   scan      G = F;  G = max(G, G[l-d] - d*SEG*ge) for d = 1, 2, 4, ...
+//             (inclusive max-plus scan over the sub-group; Hillis-Steele form
+//             of the scan loop of Algorithm 6), then Fscan = G shifted one lane
+//             down: the vertical-gap value entering each lane's first row.
+// Subtraction saturates at 0 (the paper's "-" never goes negative), so E, F and
+// every scan value stay >= 0 and a lane shifted in as 0 is neutral.
+//
+// Cross-lane moves are DPP: row_shr:1/2/4/8 inside 16-lane rows, row_bcast:15
+// and row_bcast:31 to cross rows, wave_shr:1 for the one-lane shift.  Weights
+// of the broadcast steps are per lane, so a wavefront may mix 32- and 16-lane
+// sub-groups (a lane that must not receive gets an infinite weight).
+#pragma once
+#include "sw_internal.h"
+
+namespace swk {
+namespace dev {
+
+template <class T, class F>
+__device__ __forceinline__ T bc(F x) { return __builtin_bit_cast(T, x); }
+
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------- lane arithmetic
+
+struct OpsI32 {
+  static constexpr int kHalves = 1;
+  static constexpr int kES = 4;                       // profile entry bytes
+  static constexpr uint32_t kWeightCap = 0x7fffffffu;
+  __device__ static uint32_t hadd(uint32_t a, uint32_t b) {
+    return (uint32_t)__builtin_elementwise_add_sat((int)a, (int)b);
+  }
+  __device__ static uint32_t vmax(uint32_t a, uint32_t b) { return (uint32_t)max((int)a, (int)b); }
+  __device__ static uint32_t usub(uint32_t a, uint32_t b) { return __builtin_elementwise_sub_sat(a, b); }
+  __device__ static int get(uint32_t x, int) { return (int)x; }
+  __device__ static uint32_t splat(uint32_t v) { return v; }
+};
+
+struct OpsI16 {
+  static constexpr int kHalves = 2;
+  static constexpr int kES = 2;
+  static constexpr uint32_t kWeightCap = 0xffffu;
+  __device__ static uint32_t hadd(uint32_t a, uint32_t b) {
+    return bc<uint32_t>(__builtin_elementwise_add_sat(bc<s16x2>(a), bc<s16x2>(b)));
+  }
+  __device__ static uint32_t vmax(uint32_t a, uint32_t b) {
+    return bc<uint32_t>(__builtin_elementwise_max(bc<s16x2>(a), bc<s16x2>(b)));
+  }
+  __device__ static uint32_t usub(uint32_t a, uint32_t b) {
+    return bc<uint32_t>(__builtin_elementwise_sub_sat(bc<u16x2>(a), bc<u16x2>(b)));
+  }
+  __device__ static int get(uint32_t x, int h) { return (int)(short)(h ? (x >> 16) : (x & 0xffffu)); }
+  __device__ static uint32_t splat(uint32_t v) { return (v & 0xffffu) * 0x10001u; }
+};
+
+// Weight k*unit capped to the lane type's "infinite" (subtracting it from any
+// valid value saturates to 0), splatted to both halves in int16 mode.
+template <class O>
+__device__ __forceinline__ uint32_t weight(uint64_t k, uint64_t unit) {
+  uint64_t w = k * unit;
+  return O::splat((uint32_t)(w > O::kWeightCap ? O::kWeightCap : w));
+}
+
+// ---------------------------------------------------------------- DPP
+
+template <int CTRL, int ROWMASK = 0xf, bool BOUND = true>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWMASK, 0xf, BOUND);
+}
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kWaveShr1 = 0x138, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+// ---------------------------------------------------------------- lane layout
+
+struct LaneCtx {
+  int lane;      // 0..63
+  int sg;        // sub-group ordinal in the wavefront
+  int P;         // sub-group width (16, 32, 64)
+  int l;         // lane index inside the sub-group
+  bool start;    // first lane of its sub-group
+  bool last;     // last lane of its sub-group
+  uint32_t w16;  // weight of the row_bcast:15 scan step for this lane
+  uint32_t w32;  // weight of the row_bcast:31 scan step
+  uint32_t wcarry;  // weight applied to a chunk carry entering this lane's G
+};
+
+// layout: bit r set <=> a sub-group starts at lane 16*r (bit 0 always set).
+template <class O>
+__device__ __forceinline__ LaneCtx make_lane(int layout, int seg, uint32_t ge) {
+  LaneCtx L;
+  L.lane = (int)(threadIdx.x & 63);
+  const int row = L.lane >> 4;
+  int s0 = row;
+  while (s0 > 0 && !((layout >> s0) & 1)) --s0;
+  int e0 = row + 1;
+  while (e0 < 4 && !((layout >> e0) & 1)) ++e0;
+  L.P = (e0 - s0) * 16;
+  L.l = L.lane - s0 * 16;
+  L.sg = __builtin_popcount(layout & ((2 << s0) - 1)) - 1;
+  L.start = L.l == 0;
+  L.last = L.l == L.P - 1;
+  const uint64_t unit = (uint64_t)seg * ge;
+  const uint32_t inf = O::splat(O::kWeightCap);
+  // row_bcast:15 writes rows 1 and 3 with the last lane of rows 0 and 2.
+  const bool r15 = (row & 1) && s0 < row;
+  L.w16 = r15 ? weight<O>((uint64_t)(L.lane & 15) + 1, unit) : inf;
+  // row_bcast:31 writes rows 2 and 3 with lane 31.
+  const bool r31 = row >= 2 && s0 == 0;
+  L.w32 = r31 ? weight<O>((uint64_t)(L.lane & 31) + 1, unit) : inf;
+  L.wcarry = L.start ? weight<O>(1, unit) : inf;
+  return L;
+}
+
+// Move x one lane down inside each sub-group; the first lane of a sub-group
+// receives `carry`.
+template <int PMAX, bool CARRY>
+__device__ __forceinline__ uint32_t shift1(uint32_t x, const LaneCtx &L, uint32_t carry) {
+  if constexpr (PMAX == 16) {
+    uint32_t s = dpp<kRowShr1>(x);
+    if constexpr (CARRY) s = L.start ? carry : s;
+    return s;
+  } else {
+    uint32_t s = dpp<kWaveShr1>(x);
+    return L.start ? (CARRY ? carry : 0u) : s;
+  }
+}
+
+// ---------------------------------------------------------------- per-lane state
+
+template <int SEG>
+struct State {
+  uint32_t H[SEG];    // H of the previous column, before the cross-lane fix-up
+  uint32_t E[SEG];
+  uint32_t S[SEG];    // H_diag of the current column (only read when a lane improves)
+  uint32_t Fscan;     // vertical-gap value entering this lane's first row
+  uint32_t best;      // running maximum of H_diag in this lane (per half)
+  int bcol[2], brow[2];
+};
+
+template <int SEG>
+__device__ __forceinline__ void state_reset(State<SEG> &st) {
+#pragma unroll
+  for (int j = 0; j < SEG; ++j) { st.H[j] = 0; st.E[j] = 0; }
+  st.Fscan = 0;
+  st.best = 0;
+  st.bcol[0] = st.bcol[1] = 0x7fffffff;
+  st.brow[0] = st.brow[1] = 0x7fffffff;
+}
+
+struct Params {
+  uint32_t go, ge;            // splatted gap penalties
+  uint32_t w1, w2, w4, w8;    // scan weights d*SEG*ge
+  uint32_t wlast;             // (SEG-1)*ge
+};
+
+template <class O, int SEG>
+__device__ __forceinline__ Params make_params(uint32_t go, uint32_t ge) {
+  Params p;
+  p.go = O::splat(go);
+  p.ge = O::splat(ge);
+  p.w1 = weight<O>(1ull * SEG, ge);
+  p.w2 = weight<O>(2ull * SEG, ge);
+  p.w4 = weight<O>(4ull * SEG, ge);
+  p.w8 = weight<O>(8ull * SEG, ge);
+  p.wlast = weight<O>((uint64_t)(SEG - 1), ge);
+  return p;
+}
+
+// ---------------------------------------------------------------- profile access
+
+extern __shared__ __align__(16) unsigned char smem[];
+
+// Loads the profile entry of row j for the low-half residue (base lo) and the
+// high-half residue (base hi); JSTRIDE = bytes between consecutive j.
+template <class O, int JSTRIDE>
+struct ProfLds {
+  __device__ __forceinline__ uint32_t load(uint32_t lo, uint32_t hi, int j) const {
+    if constexpr (O::kHalves == 2) {
+      uint32_t a = *(const unsigned short *)(smem + lo + j * JSTRIDE);
+      uint32_t b = *(const unsigned short *)(smem + hi + j * JSTRIDE);
+      return a | (b << 16);
+    } else {
+      return *(const uint32_t *)(smem + lo + j * JSTRIDE);
+    }
+  }
+};
+
+// ---------------------------------------------------------------- one column
+
+template <class O, int SEG, int PMAX, bool CHUNKED, bool LAZY, class Prof>
+__device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const Params &pr,
+                                       const Prof &pf, uint32_t blo, uint32_t bhi,
+                                       uint32_t hb_in, uint32_t fb_in, uint32_t &hb_out,
+                                       uint32_t &fb_out, int i, uint32_t &lazy_steps) {
+  uint32_t cmax;
+  if constexpr (!LAZY) {
+    uint32_t Fj = st.Fscan;
+    const uint32_t hlast = O::vmax(st.H[SEG - 1], O::usub(Fj, pr.wlast));
+    hb_out = hlast;
+    uint32_t Hin = shift1<PMAX, CHUNKED>(hlast, L, hb_in);
+    uint32_t F = 0;
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const uint32_t p = pf.load(blo, bhi, j);
+      const uint32_t hd = O::hadd(Hin, p);
+      st.S[j] = hd;
+      cmax = j == 0 ? hd : O::vmax(cmax, hd);
+      const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
+      const uint32_t hold = st.H[j];
+      st.H[j] = h;
+      const uint32_t t = O::usub(h, pr.go);
+      st.E[j] = O::vmax(O::usub(st.E[j], pr.ge), t);
+      F = O::vmax(O::usub(F, pr.ge), t);
+      if (j + 1 < SEG) {
+        Hin = O::vmax(hold, Fj);
+        Fj = O::usub(Fj, pr.ge);
+      }
+    }
+    // max-plus scan of the per-lane vertical-gap outputs
+    uint32_t G = F;
+    if constexpr (CHUNKED) G = O::vmax(G, O::usub(fb_in, L.wcarry));
+    G = O::vmax(G, O::usub(dpp<kRowShr1>(G), pr.w1));
+    G = O::vmax(G, O::usub(dpp<kRowShr2>(G), pr.w2));
+    G = O::vmax(G, O::usub(dpp<kRowShr4>(G), pr.w4));
+    G = O::vmax(G, O::usub(dpp<kRowShr8>(G), pr.w8));
+    if constexpr (PMAX >= 32) G = O::vmax(G, O::usub(dpp<kRowBcast15, 0xa, false>(G), L.w16));
+    if constexpr (PMAX >= 64) G = O::vmax(G, O::usub(dpp<kRowBcast31, 0xc, false>(G), L.w32));
+    fb_out = G;
+    st.Fscan = shift1<PMAX, CHUNKED>(G, L, fb_in);
+  } else {
+    // Algorithm 1: H[] already holds corrected values.
+    hb_out = st.H[SEG - 1];
+    uint32_t Hin = shift1<PMAX, CHUNKED>(st.H[SEG - 1], L, hb_in);
+    uint32_t F = 0;
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const uint32_t p = pf.load(blo, bhi, j);
+      const uint32_t hd = O::hadd(Hin, p);
+      st.S[j] = hd;
+      cmax = j == 0 ? hd : O::vmax(cmax, hd);
+      const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
+      Hin = st.H[j];
+      st.H[j] = h;
+      const uint32_t t = O::usub(h, pr.go);
+      st.E[j] = O::vmax(O::usub(st.E[j], pr.ge), t);
+      F = O::vmax(O::usub(F, pr.ge), t);
+    }
+    // Lazy-F loop: propagate the vertical gap across lanes until, in every
+    // lane at once, the propagated value can no longer exceed what the first
+    // pass already derived (F <= max(H_before - go, 0)); then stop.
+    uint32_t Fexit = F;
+    uint32_t Fp = shift1<PMAX, CHUNKED>(F, L, fb_in);
+    bool done = false;
+    for (int k = 0; k < PMAX && !done; ++k) {
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) {
+        const uint32_t hb = st.H[j];
+        st.H[j] = O::vmax(hb, Fp);
+        Fp = O::usub(Fp, pr.ge);
+        const uint32_t lim = O::usub(hb, pr.go);
+        ++lazy_steps;
+        if (__all(O::vmax(Fp, lim) == lim)) { done = true; break; }
+      }
+      if (!done) {
+        Fexit = O::vmax(Fexit, Fp);
+        Fp = shift1<PMAX, false>(Fp, L, 0u);
+      }
+    }
+    fb_out = Fexit;
+  }
+  // running maximum and its lexicographically smallest cell
+  const uint32_t nb = O::vmax(st.best, cmax);
+  if (nb != st.best) {
+#pragma unroll
+    for (int h = 0; h < O::kHalves; ++h) {
+      const int cm = O::get(cmax, h);
+      if (cm > O::get(st.best, h)) {
+        int jj = SEG - 1;
+#pragma unroll
+        for (int j = SEG - 1; j >= 0; --j)
+          if (O::get(st.S[j], h) == cm) jj = j;
+        st.bcol[h] = i;
+        st.brow[h] = L.l * SEG + jj;
+      }
+    }
+    st.best = nb;
+  }
+}
+
+// ---------------------------------------------------------------- column loop
+
+// Runs `ncols` reference columns for every sub-group of the wavefront.
+// stream: this task's residue stream; bnd_*: the task's chunk-boundary arrays
+// (HB then FB, [4 sub-groups][ncols] each) or nullptr.
+template <class O, int SEG, int PMAX, bool CHUNKED, bool LAZY, class ProfMap>
+__device__ __forceinline__ void run_columns(State<SEG> &st, const LaneCtx &L, const Params &pr,
+                                            const ProfMap &pm, const uint8_t *stream, int ncols,
+                                            const uint32_t *hb_in, const uint32_t *fb_in,
+                                            uint32_t *hb_out, uint32_t *fb_out,
+                                            uint32_t &lazy_steps) {
+  const int nblk = ncols / kBlock;
+  // residue words of this sub-group: low half at slot 2*sg, high half at 2*sg+1
+  const uint2 *sp = (const uint2 *)stream + L.sg;
+  uint2 rc = sp[0];
+  uint2 rn = sp[4];
+  uint4 hbc, hbn, fbc, fbn;
+  if constexpr (CHUNKED) {
+    hbc = ((const uint4 *)hb_in)[0];
+    hbn = ((const uint4 *)hb_in)[1];
+    fbc = ((const uint4 *)fb_in)[0];
+    fbn = ((const uint4 *)fb_in)[1];
+  }
+  for (int b = 0; b < nblk; ++b) {
+    const uint2 r = rc;
+    rc = rn;
+    rn = sp[(b + 2) * 4];
+    uint4 hbv = make_uint4(0, 0, 0, 0), fbv = make_uint4(0, 0, 0, 0);
+    if constexpr (CHUNKED) {
+      hbv = hbc; hbc = hbn; hbn = ((const uint4 *)hb_in)[b + 2];
+      fbv = fbc; fbc = fbn; fbn = ((const uint4 *)fb_in)[b + 2];
+    }
+    uint32_t ho[kBlock], fo[kBlock];
+    const uint32_t hin[kBlock] = {hbv.x, hbv.y, hbv.z, hbv.w};
+    const uint32_t fin[kBlock] = {fbv.x, fbv.y, fbv.z, fbv.w};
+#pragma unroll
+    for (int k = 0; k < kBlock; ++k) {
+      const uint32_t clo = (r.x >> (8 * k)) & 0xffu;
+      const uint32_t chi = (r.y >> (8 * k)) & 0xffu;
+      column<O, SEG, PMAX, CHUNKED, LAZY>(st, L, pr, pm.prof, pm.base_lo(clo), pm.base_hi(chi),
+                                          hin[k], fin[k], ho[k], fo[k], b * kBlock + k,
+                                          lazy_steps);
+    }
+    if (hb_out != nullptr && L.last) {
+      ((uint4 *)hb_out)[b] = make_uint4(ho[0], ho[1], ho[2], ho[3]);
+      ((uint4 *)fb_out)[b] = make_uint4(fo[0], fo[1], fo[2], fo[3]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- results
+
+__device__ __forceinline__ bool better(int s, int c, int r, int s2, int c2, int r2) {
+  return s > s2 || (s == s2 && (c < c2 || (c == c2 && r < r2)));
+}
+
+// Reduces each slot-half's best cell over its sub-group and writes (or merges
+// with a previous query chunk's) result.
+template <class O, int SEG>
+__device__ __forceinline__ void finish(const State<SEG> &st, const LaneCtx &L, const Task *tp,
+                                       const PairInfo *pairs, DevResult *results, int row_base,
+                                       bool merge, int sat_cap) {
+#pragma unroll
+  for (int h = 0; h < O::kHalves; ++h) {
+    int s = O::get(st.best, h);
+    int c = s > 0 ? st.bcol[h] : 0x7fffffff;
+    int r = s > 0 ? st.brow[h] + row_base : 0x7fffffff;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int s2 = __shfl_xor(s, d), c2 = __shfl_xor(c, d), r2 = __shfl_xor(r, d);
+      if (d < L.P && better(s2, c2, r2, s, c, r)) { s = s2; c = c2; r = r2; }
+    }
+    const int pid = tp->pair[2 * L.sg + h];
+    if (L.start && pid >= 0) {
+      const int out = pairs[pid].out;
+      uint32_t flags = 0;
+      if (O::kHalves == 2 && s >= sat_cap) flags |= kFlagNeedsI32;
+      if (s <= 0) { s = 0; c = -1; r = -1; }
+      if (merge) {
+        const DevResult pv = results[out];
+        flags |= pv.flags;
+        if (pv.score > 0 && (s == 0 || better(pv.score, pv.rend, pv.qend, s, c, r))) {
+          s = pv.score; c = pv.rend; r = pv.qend;
+        }
+      }
+      DevResult res;
+      res.score = s; res.qend = r; res.rend = c; res.flags = flags;
+      results[out] = res;
+    }
+  }
+}
+
+__device__ __forceinline__ int pop_task(int *counter) {
+  int t = 0;
+  if ((threadIdx.x & 63) == 0) t = atomicAdd(counter, 1);
+  return __builtin_amdgcn_readfirstlane(t);
+}
+
+__device__ __forceinline__ void stage_matrix(const KArgs &a) {
+  int32_t *M = (int32_t *)smem;
+  for (int k = threadIdx.x; k < a.alpha * a.alpha; k += blockDim.x) M[k] = a.matrix[k];
+}
+
+// ================================================================ shared-query kernel
+
+// LDS: [matrix][profile of mode 0][mode 1][mode 2]; each profile is
+// [alpha+1][SEG][P] entries with the residue stride padded so that the four
+// 16-lane sub-groups reading different residues spread over the banks.
+__host__ __device__ constexpr uint32_t shared_cstride(int seg, int P, int es) {
+  return (uint32_t)(((seg * P * es + 127) / 128) * 128 + 32);
+}
+
+template <class O, int SEG, int P>
+struct SharedMap {
+  ProfLds<O, P * O::kES> prof;
+  uint32_t lane_base;   // bytes: profile base + l * ES
+  __device__ __forceinline__ uint32_t base_lo(uint32_t c) const {
+    return lane_base + c * shared_cstride(SEG, P, O::kES);
+  }
+  __device__ __forceinline__ uint32_t base_hi(uint32_t c) const { return base_lo(c); }
+};
+
+template <class O, int SEG, int P>
+__device__ void build_shared_profile(const KArgs &a, uint32_t off) {
+  const int32_t *M = (const int32_t *)smem;
+  const int nrow = a.alpha + 1;
+  const int total = nrow * SEG * P;
+  const int64_t row0 = (int64_t)a.chunk * (P * SEG);
+  for (int k = threadIdx.x; k < total; k += blockDim.x) {
+    const int l = k % P;
+    const int j = (k / P) % SEG;
+    const int c = k / (P * SEG);
+    const int64_t row = row0 + l * SEG + j;
+    int v;
+    const int qc = (row < a.shared_m) ? (int)a.query_res[a.shared_q_off + row] : a.alpha;
+    if (c < a.alpha && qc < a.alpha) {
+      v = M[qc * a.alpha + c];
+    } else {
+      v = O::kES == 2 ? -32768 : (int)0x80000000;
+    }
+    unsigned char *dst = smem + off + c * shared_cstride(SEG, P, O::kES) + (j * P + l) * O::kES;
+    if constexpr (O::kES == 2) *(short *)dst = (short)v;
+    else *(int *)dst = v;
+  }
+}
+
+template <class O, int SEG, int P, bool CHUNKED, bool LAZY>
+__device__ __forceinline__ void shared_task(const KArgs &a, const Task &t, const Task *tp,
+                                            uint32_t prof_off,
+                                            uint32_t &lazy_steps, unsigned long long &cols) {
+  const LaneCtx L = make_lane<O>(t.layout, SEG, (uint32_t)a.gap_extend);
+  const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
+  SharedMap<O, SEG, P> pm;
+  pm.lane_base = prof_off + L.l * O::kES;
+  State<SEG> st;
+  state_reset(st);
+  const uint32_t *hb_in = nullptr, *fb_in = nullptr;
+  uint32_t *hb_out = nullptr, *fb_out = nullptr;
+  if constexpr (CHUNKED) {
+    const int64_t base = t.bnd_off + (int64_t)L.sg * t.ncols;
+    const int64_t fofs = 4ll * t.ncols;
+    hb_in = a.bnd_in + base;
+    fb_in = a.bnd_in + base + fofs;
+    if (!a.last_chunk) {
+      hb_out = a.bnd_out + base;
+      fb_out = a.bnd_out + base + fofs;
+    }
+  }
+  run_columns<O, SEG, P, CHUNKED, LAZY>(st, L, pr, pm, a.streams + t.stream_off, t.ncols, hb_in,
+                                        fb_in, hb_out, fb_out, lazy_steps);
+  cols += (unsigned long long)t.ncols;
+  finish<O, SEG>(st, L, tp, a.pairs, a.results, a.chunk * P * SEG, CHUNKED && a.chunk > 0,
+                 a.sat_cap);
+}
+
+template <class O, int S16, int S32, int S64, bool CHUNKED, bool LAZY>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+void shared_kernel(KArgs a, uint32_t mode_mask) {
+  stage_matrix(a);
+  __syncthreads();
+  uint32_t off0 = 0, off1 = 0, off2 = 0;
+  uint32_t cur = matrix_lds_bytes(a.alpha);
+  const int nrow = a.alpha + 1;
+  if constexpr (S16 > 0) {
+    if (mode_mask & 1u) {
+      off0 = cur;
+      build_shared_profile<O, S16, 16>(a, cur);
+      cur += nrow * shared_cstride(S16, 16, O::kES);
+    }
+  }
+  if constexpr (S32 > 0) {
+    if (mode_mask & 2u) {
+      off1 = cur;
+      build_shared_profile<O, S32, 32>(a, cur);
+      cur += nrow * shared_cstride(S32, 32, O::kES);
+    }
+  }
+  if constexpr (S64 > 0) {
+    if (mode_mask & 4u) {
+      off2 = cur;
+      build_shared_profile<O, S64, 64>(a, cur);
+      cur += nrow * shared_cstride(S64, 64, O::kES);
+    }
+  }
+  __syncthreads();
+  uint32_t lazy_steps = 0;
+  unsigned long long cols = 0;
+  for (;;) {
+    const int ti = pop_task(a.task_counter);
+    if (ti >= a.ntasks) break;
+    const Task t = a.tasks[ti];
+    if constexpr (S16 > 0) {
+      if (t.mode == 0) { shared_task<O, S16, 16, CHUNKED, LAZY>(a, t, a.tasks + ti, off0, lazy_steps, cols); continue; }
+    }
+    if constexpr (S32 > 0) {
+      if (t.mode == 1) { shared_task<O, S32, 32, CHUNKED, LAZY>(a, t, a.tasks + ti, off1, lazy_steps, cols); continue; }
+    }
+    if constexpr (S64 > 0) {
+      if (t.mode == 2) { shared_task<O, S64, 64, CHUNKED, LAZY>(a, t, a.tasks + ti, off2, lazy_steps, cols); continue; }
+    }
+  }
+  if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
+    if (cols) atomicAdd(&a.stats[0], cols);
+    if (lazy_steps) atomicAdd(&a.stats[1], (unsigned long long)lazy_steps);
+  }
+}
+
+// ================================================================ per-pair kernel
+
+// Each wavefront owns an LDS region [half][alpha+1][SEG][64 lanes]: lane x
+// reads and writes only column x, so any sub-group partition works and no
+// barrier is needed between building a profile and using it.
+template <class O, int SEG>
+struct PairMap {
+  ProfLds<O, kWave * O::kES> prof;
+  uint32_t lo0, hi0;   // bytes: region + lane*ES (+ half offset)
+  __device__ __forceinline__ uint32_t base_lo(uint32_t c) const { return lo0 + c * (SEG * kWave * O::kES); }
+  __device__ __forceinline__ uint32_t base_hi(uint32_t c) const { return hi0 + c * (SEG * kWave * O::kES); }
+};
+
+__host__ __device__ constexpr uint32_t pair_region_bytes(int seg, int alpha, int halves, int es) {
+  return (uint32_t)(halves * (alpha + 1) * seg * kWave * es);
+}
+
+template <class O, int SEG>
+__device__ __forceinline__ void build_pair_profile(const KArgs &a, const Task *tp, const LaneCtx &L,
+                                                   uint32_t region, int row0) {
+  const int32_t *M = (const int32_t *)smem;
+  const int nrow = a.alpha + 1;
+#pragma unroll
+  for (int h = 0; h < O::kHalves; ++h) {
+    const int pid = tp->pair[2 * L.sg + h];
+    int m = 0;
+    int64_t qo = 0;
+    if (pid >= 0) { m = a.pairs[pid].m; qo = a.pairs[pid].q_off; }
+    const uint32_t hbase = region + (uint32_t)(h * nrow * SEG * kWave * O::kES) + L.lane * O::kES;
+    for (int j = 0; j < SEG; ++j) {
+      const int row = row0 + L.l * SEG + j;
+      int qc = row < m ? (int)a.query_res[qo + row] : -1;
+      if (qc >= a.alpha) qc = -1;   // invalid codes are reported by the host check
+      for (int c = 0; c < nrow; ++c) {
+        const int v = (qc >= 0 && c < a.alpha) ? M[qc * a.alpha + c]
+                                               : (O::kES == 2 ? -32768 : (int)0x80000000);
+        unsigned char *dst = smem + hbase + (c * SEG + j) * kWave * O::kES;
+        if constexpr (O::kES == 2) *(short *)dst = (short)v;
+        else *(int *)dst = v;
+      }
+    }
+  }
+}
+
+template <class O, int SEG, int PMAX, bool CHUNKED>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+void pair_kernel(KArgs a) {
+  stage_matrix(a);
+  __syncthreads();
+  const uint32_t region = matrix_lds_bytes(a.alpha);
+  uint32_t lazy_steps = 0;
+  unsigned long long cols = 0;
+  for (;;) {
+    const int ti = pop_task(a.task_counter);
+    if (ti >= a.ntasks) break;
+    const Task t = a.tasks[ti];
+    const LaneCtx L = make_lane<O>(t.layout, SEG, (uint32_t)a.gap_extend);
+    const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
+    PairMap<O, SEG> pm;
+    pm.lo0 = region + L.lane * O::kES;
+    pm.hi0 = pm.lo0 + (O::kHalves == 2 ? (a.alpha + 1) * SEG * kWave * O::kES : 0);
+    const int nch = CHUNKED ? t.nchunks : 1;
+    for (int ch = 0; ch < nch; ++ch) {
+      const int row0 = ch * L.P * SEG;
+      build_pair_profile<O, SEG>(a, a.tasks + ti, L, region, row0);
+      State<SEG> st;
+      state_reset(st);
+      const uint32_t *hb_in = nullptr, *fb_in = nullptr;
+      uint32_t *hb_out = nullptr, *fb_out = nullptr;
+      if constexpr (CHUNKED) {
+        const int64_t base = t.bnd_off + (int64_t)L.sg * t.ncols;
+        const int64_t fofs = 4ll * t.ncols;
+        uint32_t *rd = a.bnd + (ch & 1) * a.bnd_half;
+        uint32_t *wr = a.bnd + ((ch + 1) & 1) * a.bnd_half;
+        hb_in = rd + base;
+        fb_in = rd + base + fofs;
+        if (ch + 1 < nch) { hb_out = wr + base; fb_out = wr + base + fofs; }
+      }
+      run_columns<O, SEG, PMAX, CHUNKED, false>(st, L, pr, pm, a.streams + t.stream_off, t.ncols,
+                                                hb_in, fb_in, hb_out, fb_out, lazy_steps);
+      cols += (unsigned long long)t.ncols;
+      finish<O, SEG>(st, L, a.tasks + ti, a.pairs, a.results, row0, ch > 0, a.sat_cap);
+    }
+  }
+  if ((threadIdx.x & 63) == 0 && a.stats != nullptr && cols) atomicAdd(&a.stats[0], cols);
+}
+
+}  // namespace dev
+}  // namespace swk

@@ -1,0 +1,112 @@
+// Internal structures shared by the host runtime and the gfx950 kernels of
+// libswscan.so.  Not part of the public ABI (include/sw.h is).
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime.h>
+
+namespace swk {
+
+constexpr int kWave = 64;          // gfx950 wavefront width
+constexpr int kMaxAlpha = 32;      // largest supported alphabet
+constexpr int kSlots = 8;          // slot-halves per task: 4 sub-groups x 2 int16 halves
+constexpr int kBlock = 4;          // reference columns per unrolled block
+constexpr int kStreamBlockBytes = kSlots * kBlock;  // residue-stream bytes per block
+
+// A task is the unit a wavefront pops from the queue: up to four sub-groups
+// (16/32/64 lanes each), each holding one alignment per int16 half (or one
+// int32 alignment), all stepping through the same number of reference
+// columns in lockstep.
+struct Task {
+  int32_t ncols;        // reference columns to run (multiple of kBlock)
+  int32_t layout;       // bit r set <=> a sub-group starts at lane 16*r
+  int64_t stream_off;   // byte offset of the task's residue stream
+  int32_t pair[kSlots]; // PairInfo index of slot-half 2*sub_group + half, or -1
+  int64_t bnd_off;      // element offset of this task's chunk boundary arrays
+  int32_t mode;         // shared-query kernel: index of the lane-width mode
+  int32_t nchunks;      // per-pair kernel: query chunks (same for every slot)
+};
+static_assert(sizeof(Task) == 64, "task layout");
+
+struct PairInfo {
+  int64_t q_off;        // query residue offset (per-pair kernel)
+  int64_t r_off;        // reference residue offset
+  int32_t m;            // query length
+  int32_t n;            // reference length
+  int32_t out;          // index of the result slot
+  int32_t pad;
+};
+static_assert(sizeof(PairInfo) == 32, "pair layout");
+
+struct DevResult {
+  int32_t score;
+  int32_t qend;
+  int32_t rend;
+  uint32_t flags;
+};
+
+enum : uint32_t { kFlagSaturated = 1u, kFlagNeedsI32 = 2u };
+
+// Kernel arguments (passed by value).
+struct KArgs {
+  const Task *tasks;
+  int32_t ntasks;
+  int32_t chunk;              // shared-query kernel: query chunk of this launch
+  int32_t *task_counter;      // one int, zeroed before the launch
+  const PairInfo *pairs;
+  const uint8_t *streams;     // residue streams ([ncols/4][8 slot-halves][4] bytes per task)
+  const uint8_t *query_res;   // residues of every query (device)
+  int64_t shared_q_off;       // shared-query kernel: the query
+  int32_t shared_m;
+  int32_t alpha;
+  const int32_t *matrix;      // alpha*alpha, [query code][ref code] (device)
+  int32_t gap_open;
+  int32_t gap_extend;         // already min(gap_extend, gap_open)
+  int32_t last_chunk;         // shared-query kernel: 1 if no chunk follows
+  int32_t sat_cap;            // int16 saturation threshold (<= 32767)
+  uint32_t *bnd_in;           // chunk boundaries read (shared-query kernel)
+  uint32_t *bnd_out;          // chunk boundaries written
+  uint32_t *bnd;              // per-pair kernel: double-buffered boundaries
+  int64_t bnd_half;           // per-pair kernel: element distance between the two buffers
+  DevResult *results;
+  unsigned long long *stats;  // [0] column steps, [1] lazy-F inner steps
+};
+
+// Host-side launchers (defined in sw_kernels.hip).
+enum Prec { PREC_I16X2 = 0, PREC_I32 = 1 };
+enum Alg { ALG_SCAN = 0, ALG_LAZYF = 1 };
+
+// Shared-query kernel: every task uses the launch's query (one chunk of it).
+// The menu index `menu` selects the rows-per-lane triple compiled into one
+// kernel; task.mode picks 16 (seg16), 32 (seg32) or 64 (seg64) lanes.
+struct SharedMenu { int seg16, seg32, seg64; };
+int shared_menu_count();
+SharedMenu shared_menu(int idx);
+size_t shared_lds_bytes(Prec prec, int menu, int alpha);
+hipError_t launch_shared(Prec prec, Alg alg, int menu, bool chunked, const KArgs &a,
+                         int grid, hipStream_t st);
+
+// Per-pair kernel: each slot-half has its own query; profiles live in each
+// wavefront's own LDS region.  seg = rows per lane, pmax = widest sub-group.
+bool pair_kernel_has(Prec prec, int seg, int pmax);
+size_t pair_lds_bytes(Prec prec, int seg, int alpha);
+hipError_t launch_pair(Prec prec, int seg, int pmax, bool chunked, const KArgs &a,
+                       int grid, hipStream_t st);
+
+// Residue streams for a list of tasks (SENT-padded, 4-aligned).
+hipError_t launch_build_streams(const Task *tasks, int ntasks, const PairInfo *pairs,
+                                const uint8_t *ref_res, uint8_t *streams, int sent_code,
+                                hipStream_t st);
+
+// Sets *flag to 1 if any residue in p[0..n) is >= alpha.
+hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *flag,
+                                 hipStream_t st);
+
+constexpr int kWavesPerGroup = 8;   // shared-query kernel: threads per workgroup = 512
+
+// LDS bytes of the staged substitution matrix (alpha^2 int32, 16-byte aligned).
+__host__ __device__ constexpr uint32_t matrix_lds_bytes(int alpha) {
+  return (uint32_t)(((alpha * alpha * 4) + 15) / 16 * 16);
+}
+
+}  // namespace swk

@@ -1,0 +1,116 @@
+// Residue-stream kernel and the launch dispatchers of libswscan.so.
+#include "sw_device.h"
+#include "sw_menus.h"
+
+#include <algorithm>
+
+namespace swk {
+
+hipError_t launch_shared_i16(Alg alg, int menu, bool chunked, const KArgs &a, int grid,
+                             hipStream_t st, uint32_t mask, size_t lds);
+hipError_t launch_shared_i32(Alg alg, int menu, bool chunked, const KArgs &a, int grid,
+                             hipStream_t st, uint32_t mask, size_t lds);
+hipError_t launch_pair_i16(int seg, int pmax, bool chunked, const KArgs &a, int grid,
+                           hipStream_t st, size_t lds);
+hipError_t launch_pair_i32(int seg, int pmax, bool chunked, const KArgs &a, int grid,
+                           hipStream_t st, size_t lds);
+
+namespace dev {
+// ================================================================ residue streams
+
+// One workgroup per task: block b, slot-half s -> 4 residues (SENT past the end).
+__global__ __launch_bounds__(256) void build_streams_kernel(const Task *tasks, const PairInfo *pairs,
+                                                            const uint8_t *ref_res, uint8_t *streams,
+                                                            int sent) {
+  const Task t = tasks[blockIdx.x];
+  const int nblk = t.ncols / kBlock;
+  uint32_t *dst = (uint32_t *)(streams + t.stream_off);
+  for (int k = threadIdx.x; k < nblk * kSlots; k += blockDim.x) {
+    const int b = k / kSlots, s = k % kSlots;
+    const int pid = tasks[blockIdx.x].pair[s];
+    uint32_t w = (uint32_t)sent * 0x01010101u;
+    if (pid >= 0) {
+      const PairInfo p = pairs[pid];
+      w = 0;
+#pragma unroll
+      for (int q = 0; q < kBlock; ++q) {
+        const int i = b * kBlock + q;
+        uint32_t c = i < p.n ? (uint32_t)ref_res[p.r_off + i] : (uint32_t)sent;
+        c = c < (uint32_t)sent ? c : (uint32_t)sent;   // invalid codes are reported by the host check
+        w |= c << (8 * q);
+      }
+    }
+    dst[k] = w;
+  }
+}
+
+// Sets *flag to 1 if any of the n residues is >= alpha.
+__global__ __launch_bounds__(256) void check_residues_kernel(const uint8_t *p, int64_t n, int alpha,
+                                                             int *flag) {
+  int bad = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+    bad |= p[k] >= alpha;
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+}  // namespace dev
+
+hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *flag,
+                                 hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(dev::check_residues_kernel, dim3(grid), dim3(256), 0, st, p, n, alpha, flag);
+  return hipGetLastError();
+}
+
+int shared_menu_count() { return kNumSharedMenus; }
+SharedMenu shared_menu(int idx) { return kSharedMenus[idx]; }
+
+size_t shared_lds_bytes(Prec prec, int menu, int alpha) {
+  const int es = prec == PREC_I16X2 ? 2 : 4;
+  const SharedMenu m = kSharedMenus[menu];
+  size_t b = matrix_lds_bytes(alpha);
+  if (m.seg16) b += (size_t)(alpha + 1) * dev::shared_cstride(m.seg16, 16, es);
+  if (m.seg32) b += (size_t)(alpha + 1) * dev::shared_cstride(m.seg32, 32, es);
+  if (m.seg64) b += (size_t)(alpha + 1) * dev::shared_cstride(m.seg64, 64, es);
+  return b;
+}
+
+hipError_t launch_shared(Prec prec, Alg alg, int menu, bool chunked, const KArgs &a, int grid,
+                         hipStream_t st) {
+  if (menu < 0 || menu >= kNumSharedMenus) return hipErrorInvalidValue;
+  const size_t lds = shared_lds_bytes(prec, menu, a.alpha);
+  if (prec == PREC_I16X2) return launch_shared_i16(alg, menu, chunked, a, grid, st, 7u, lds);
+  return launch_shared_i32(alg, menu, chunked, a, grid, st, 7u, lds);
+}
+
+bool pair_kernel_has(Prec, int seg, int pmax) {
+  bool s = false;
+  for (int v : kPairSegs) s |= v == seg;
+  return s && (pmax == 16 || pmax == 32 || pmax == 64);
+}
+
+size_t pair_lds_bytes(Prec prec, int seg, int alpha) {
+  const int es = prec == PREC_I16X2 ? 2 : 4;
+  const int halves = prec == PREC_I16X2 ? 2 : 1;
+  return matrix_lds_bytes(alpha) + (size_t)dev::pair_region_bytes(seg, alpha, halves, es);
+}
+
+hipError_t launch_pair(Prec prec, int seg, int pmax, bool chunked, const KArgs &a, int grid,
+                       hipStream_t st) {
+  if (!pair_kernel_has(prec, seg, pmax)) return hipErrorInvalidValue;
+  const size_t lds = pair_lds_bytes(prec, seg, a.alpha);
+  if (prec == PREC_I16X2) return launch_pair_i16(seg, pmax, chunked, a, grid, st, lds);
+  return launch_pair_i32(seg, pmax, chunked, a, grid, st, lds);
+}
+
+hipError_t launch_build_streams(const Task *tasks, int ntasks, const PairInfo *pairs,
+                                const uint8_t *ref_res, uint8_t *streams, int sent_code,
+                                hipStream_t st) {
+  if (ntasks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::build_streams_kernel, dim3(ntasks), dim3(256), 0, st, tasks, pairs,
+                     ref_res, streams, sent_code);
+  return hipGetLastError();
+}
+
+}  // namespace swk

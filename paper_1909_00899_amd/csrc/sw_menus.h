@@ -1,0 +1,18 @@
+// Compiled kernel menus (rows per lane) of libswscan.so.
+#pragma once
+#include "sw_internal.h"
+
+namespace swk {
+
+// Shared-query kernel menus: rows per lane for the 16-, 32- and 64-lane
+// modes; menu k covers 64*seg64 query rows in every mode.
+constexpr SharedMenu kSharedMenus[] = {
+    {4, 2, 1}, {8, 4, 2}, {12, 6, 3}, {16, 8, 4}, {24, 12, 6}, {32, 16, 8},
+};
+constexpr int kNumSharedMenus = sizeof(kSharedMenus) / sizeof(kSharedMenus[0]);
+
+// Per-pair kernel: rows per lane compiled.
+constexpr int kPairSegs[] = {4, 6, 8, 10, 12, 16};
+constexpr int kNumPairSegs = sizeof(kPairSegs) / sizeof(kPairSegs[0]);
+
+}  // namespace swk

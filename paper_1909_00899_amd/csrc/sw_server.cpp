@@ -1,0 +1,353 @@
+// Continuous-batching request server (include/sw.h, "Serving").
+//
+// Requests (one query against one resident database reference) enter a FIFO
+// queue.  n_streams worker threads each own a HIP stream and a device
+// workspace; an idle worker takes, under the server lock, the longest FIFO
+// prefix of requests that share the head's scoring scheme and fit the
+// remaining memory budget (at most max_batch), marks them admitted, releases
+// the lock and runs them as one batch (the batch planner re-buckets them by
+// length into per-pair kernel launches).  Requests that arrive meanwhile wait
+// for the next idle worker, so their kernels overlap with the batches already
+// on the device.  Each result is the batch path's result for that pair.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "sw.h"
+#include "sw_runtime.h"
+
+using namespace swrt;
+using swk::PairInfo;
+
+namespace {
+
+int64_t mono_ns() {
+  return std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+  uint64_t ticket;
+  std::vector<uint8_t> query;
+  int32_t ref_id, scoring_id;
+  size_t bytes;
+  int64_t t_submit = 0, t_admit = 0, t_done = 0;
+  sw_result res{0, -1, -1, 0};
+  int status = SW_PENDING;   // SW_PENDING until finished, then SW_OK or an error
+  bool done = false;
+};
+
+}  // namespace
+
+struct sw_server {
+  int device = 0;
+  int num_cus = 256;
+  size_t budget = 0, in_flight = 0;
+  int max_queued = 0, max_batch = 0;
+  std::vector<Scoring> scorings;
+  DevBuf db;                         // resident reference residues
+  std::vector<int64_t> db_off;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request *> queue;
+  std::unordered_map<uint64_t, std::unique_ptr<Request>> table;
+  uint64_t next_ticket = 1;
+  int outstanding = 0;               // accepted and not yet finished
+  int running = 0;                   // batches on the device
+  bool stop = false;
+  std::vector<std::thread> workers;
+
+  size_t request_bytes(int m, int n) const {
+    // query + residue stream (8 bytes per column per slot-half, rounded) +
+    // chunk boundaries (two buffers of 8 u32 per column per task) + result
+    return (size_t)m + 16 * (size_t)(n + 8) + 64 * (size_t)(n + 8) + 64;
+  }
+
+  void worker_main();
+};
+
+void sw_server::worker_main() {
+  hipSetDevice(device);
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  hipEventCreate(&e0);
+  hipEventCreate(&e1);
+  Workspace ws;
+  DevBuf qbuf;
+  HostBuf qstage;
+  std::vector<Request *> batch;
+  std::vector<sw_result> out;
+  for (;;) {
+    batch.clear();
+    size_t bytes = 0;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+      if (stop && queue.empty()) break;
+      // admission: FIFO prefix with the head's scoring, within the budget
+      const int sid = queue.front()->scoring_id;
+      for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
+        Request *r = *it;
+        if (r->scoring_id != sid) { ++it; continue; }
+        if (in_flight + bytes + r->bytes > budget && !(batch.empty() && in_flight == 0)) break;
+        bytes += r->bytes;
+        batch.push_back(r);
+        it = queue.erase(it);
+      }
+      if (batch.empty()) {
+        // the head does not fit next to what is running: wait for a finish
+        cv_done.wait(lk, [&] { return stop || in_flight == 0 || queue.empty(); });
+        continue;
+      }
+      in_flight += bytes;
+      ++running;
+      const int64_t t = mono_ns();
+      for (Request *r : batch) r->t_admit = t;
+    }
+    // ---- run the batch (outside the lock)
+    const Scoring &sc = scorings[batch[0]->scoring_id];
+    int64_t qtotal = 0;
+    for (Request *r : batch) qtotal += (int64_t)r->query.size();
+    int rc = qstage.ensure(std::max<int64_t>(qtotal, 1));
+    if (!rc) rc = qbuf.ensure(std::max<int64_t>(qtotal, 1));
+    ExecInput in;
+    if (!rc) {
+      unsigned char *h = qstage.as<unsigned char>();
+      int64_t off = 0;
+      in.n_queries = (int)batch.size();
+      in.pairs.resize(batch.size());
+      in.q_off_of_query.resize(batch.size());
+      in.m_of_query.resize(batch.size());
+      for (size_t k = 0; k < batch.size(); ++k) {
+        Request *r = batch[k];
+        std::memcpy(h + off, r->query.data(), r->query.size());
+        PairInfo &p = in.pairs[k];
+        std::memset(&p, 0, sizeof(p));
+        p.q_off = off;
+        p.r_off = db_off[r->ref_id];
+        p.m = (int)r->query.size();
+        p.n = (int)(db_off[r->ref_id + 1] - db_off[r->ref_id]);
+        p.out = (int)k;
+        in.q_off_of_query[k] = off;
+        in.m_of_query[k] = p.m;
+        if (p.m > 0 && p.n > 0) in.items.push_back(PlanItem{(int)k, (int)k, p.m, p.n});
+        off += (int64_t)r->query.size();
+      }
+      if (qtotal && hipMemcpyAsync(qbuf.p, h, qtotal, hipMemcpyHostToDevice, st) != hipSuccess) {
+        set_error("server: query upload failed");
+        rc = SW_EDEVICE;
+      }
+      in.d_qres = qbuf.as<uint8_t>();
+      in.d_rres = db.as<uint8_t>();
+    }
+    out.assign(batch.size(), sw_result{0, -1, -1, 0});
+    if (!rc) {
+      ExecOptions opt;
+      rc = run_batch(in, sc, SW_PREC_AUTO, opt, ws, (int)batch.size(), st, e0, e1, num_cus,
+                     out.data(), nullptr);
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      const int64_t t = mono_ns();
+      for (size_t k = 0; k < batch.size(); ++k) {
+        Request *r = batch[k];
+        r->res = out[k];
+        r->status = rc ? rc : SW_OK;
+        r->t_done = t;
+        r->done = true;
+      }
+      in_flight -= bytes;
+      --running;
+      outstanding -= (int)batch.size();
+    }
+    cv_done.notify_all();
+    cv_work.notify_all();
+  }
+  ws.release();
+  qbuf.release();
+  qstage.release();
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  hipStreamDestroy(st);
+}
+
+extern "C" {
+
+int sw_server_create(const sw_server_config *cfg, sw_server **out) {
+  if (!cfg || !out || cfg->n_db < 1 || !cfg->db_res || !cfg->db_off || !cfg->scorings ||
+      cfg->n_scorings < 1 || cfg->max_queued < 0 || cfg->max_batch < 0 || cfg->n_streams < 0) {
+    set_error("bad server config");
+    return SW_EINVAL;
+  }
+  int rc = ensure_init();
+  if (rc) return rc;
+  std::unique_ptr<sw_server> s(new sw_server());
+  s->device = g_ctx.device;
+  s->num_cus = g_ctx.num_cus;
+  s->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : ((size_t)1 << 32);
+  s->max_queued = cfg->max_queued ? cfg->max_queued : 1 << 20;
+  s->max_batch = cfg->max_batch ? cfg->max_batch : 4096;
+  const int nst = cfg->n_streams ? cfg->n_streams : 4;
+  for (int k = 0; k < cfg->n_scorings; ++k) {
+    Scoring sc;
+    if ((rc = prepare_scoring(&cfg->scorings[k], sc))) return rc;
+    s->scorings.push_back(sc);
+  }
+  s->db_off.assign(cfg->db_off, cfg->db_off + cfg->n_db + 1);
+  for (int r = 0; r < cfg->n_db; ++r)
+    if (s->db_off[r] < 0 || s->db_off[r + 1] < s->db_off[r]) { set_error("bad db offsets"); return SW_EINVAL; }
+  const int64_t nbytes = s->db_off[cfg->n_db];
+  if ((rc = s->db.ensure(std::max<int64_t>(nbytes, 1)))) return rc;
+  if (hipSetDevice(s->device) != hipSuccess ||
+      (nbytes && hipMemcpy(s->db.p, cfg->db_res, nbytes, hipMemcpyHostToDevice) != hipSuccess)) {
+    set_error("server: database upload failed");
+    return SW_EDEVICE;
+  }
+  for (int k = 0; k < nst; ++k) s->workers.emplace_back(&sw_server::worker_main, s.get());
+  *out = s.release();
+  return SW_OK;
+}
+
+int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int32_t ref_id,
+                     int32_t scoring_id, uint64_t *ticket) {
+  if (!s || !ticket || query_len < 0 || (query_len > 0 && !query)) { set_error("bad submit"); return SW_EINVAL; }
+  if (ref_id < 0 || ref_id + 1 >= (int64_t)s->db_off.size() || scoring_id < 0 ||
+      scoring_id >= (int)s->scorings.size()) {
+    set_error("ref_id or scoring_id out of range");
+    return SW_EINVAL;
+  }
+  const Scoring &sc = s->scorings[scoring_id];
+  for (int k = 0; k < query_len; ++k)
+    if (query[k] >= sc.alpha) { set_error("query residue %d out of range", k); return SW_EINVAL; }
+  const int64_t n = s->db_off[ref_id + 1] - s->db_off[ref_id];
+  if (std::min<int64_t>(query_len, n) * (int64_t)sc.max_s >= 2147483647ll) {
+    set_error("score may overflow int32");
+    return SW_EOVERFLOW;
+  }
+  std::unique_ptr<Request> r(new Request());
+  r->query.assign(query, query + query_len);
+  r->ref_id = ref_id;
+  r->scoring_id = scoring_id;
+  r->bytes = s->request_bytes(query_len, (int)n);
+  if (r->bytes > s->budget) { set_error("request needs %zu bytes, budget %zu", r->bytes, s->budget); return SW_ENOMEM; }
+  r->t_submit = mono_ns();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) { set_error("server stopping"); return SW_EINVAL; }
+    if ((int)s->table.size() >= s->max_queued) return SW_EBUSY;
+    r->ticket = s->next_ticket++;
+    *ticket = r->ticket;
+    s->queue.push_back(r.get());
+    s->outstanding++;
+    s->table.emplace(r->ticket, std::move(r));
+  }
+  s->cv_work.notify_one();
+  return SW_OK;
+}
+
+int sw_server_poll(sw_server *s, uint64_t ticket, sw_result *out, int64_t *ts) {
+  if (!s || !out) { set_error("bad poll"); return SW_EINVAL; }
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->table.find(ticket);
+  if (it == s->table.end()) return SW_ENOENT;
+  Request *r = it->second.get();
+  if (!r->done) return SW_PENDING;
+  const int st = r->status;
+  *out = r->res;
+  if (ts) { ts[0] = r->t_submit; ts[1] = r->t_admit; ts[2] = r->t_done; }
+  s->table.erase(it);
+  return st;
+}
+
+int sw_server_drain(sw_server *s) {
+  if (!s) return SW_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  s->cv_done.wait(lk, [&] { return s->outstanding == 0; });
+  return SW_OK;
+}
+
+int sw_server_destroy(sw_server *s) {
+  if (!s) return SW_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->queue.clear();
+  }
+  s->cv_work.notify_all();
+  s->cv_done.notify_all();
+  for (auto &t : s->workers) t.join();
+  hipSetDevice(s->device);
+  s->db.release();
+  delete s;
+  return SW_OK;
+}
+
+int sw_server_replay(sw_server *s, int32_t n, const uint8_t *qres, const int64_t *qoff,
+                     const int32_t *ref_id, const int32_t *scoring_id, const int64_t *arrival_ns,
+                     sw_result *out, int64_t *times_ns) {
+  if (!s || n < 0 || (n > 0 && (!qres || !qoff || !ref_id || !scoring_id || !arrival_ns || !out || !times_ns))) {
+    set_error("bad replay arguments");
+    return SW_EINVAL;
+  }
+  std::vector<uint64_t> tickets(n, 0);
+  std::vector<int64_t> first_try(n, 0);
+  std::atomic<int> submitted{0};
+  std::atomic<int> err{SW_OK};
+  const int64_t t0 = mono_ns();
+  std::thread producer([&] {
+    for (int k = 0; k < n; ++k) {
+      const int64_t due = t0 + arrival_ns[k];
+      int64_t now;
+      while ((now = mono_ns()) < due) {
+        if (due - now > 200000) std::this_thread::sleep_for(std::chrono::microseconds(50));
+      }
+      first_try[k] = mono_ns();
+      int rc;
+      uint64_t tk = 0;
+      while ((rc = sw_server_submit(s, qres + qoff[k], (int32_t)(qoff[k + 1] - qoff[k]), ref_id[k],
+                                    scoring_id[k], &tk)) == SW_EBUSY)
+        std::this_thread::sleep_for(std::chrono::microseconds(20));
+      if (rc != SW_OK) { err = rc; tickets[k] = 0; }
+      else tickets[k] = tk;
+      submitted.store(k + 1, std::memory_order_release);
+    }
+  });
+  std::vector<char> got(n, 0);
+  int remaining = n;
+  int cursor = 0;
+  while (remaining > 0) {
+    const int upto = submitted.load(std::memory_order_acquire);
+    bool any = false;
+    for (int k = cursor; k < upto; ++k) {
+      if (got[k]) continue;
+      if (tickets[k] == 0) { got[k] = 1; --remaining; out[k] = sw_result{0, -1, -1, 0}; any = true; continue; }
+      int64_t ts[3];
+      const int rc = sw_server_poll(s, tickets[k], &out[k], ts);
+      if (rc == SW_PENDING) continue;
+      if (rc != SW_OK) err = rc;
+      times_ns[3 * k + 0] = first_try[k] - t0;
+      times_ns[3 * k + 1] = ts[1] - t0;
+      times_ns[3 * k + 2] = ts[2] - t0;
+      got[k] = 1;
+      --remaining;
+      any = true;
+    }
+    while (cursor < upto && got[cursor]) ++cursor;
+    if (!any) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+  producer.join();
+  return err.load();
+}
+
+}  // extern "C"

@@ -1,0 +1,39 @@
+// Shared-query kernel instances (I16).
+#include "sw_device.h"
+#include "sw_menus.h"
+
+namespace swk {
+namespace {
+using O = dev::OpsI16;
+
+template <int M, bool CH, bool LZ>
+hipError_t launch_m(const KArgs &a, int grid, hipStream_t st, uint32_t mask, size_t lds) {
+  constexpr SharedMenu mm = kSharedMenus[M];
+  auto k = dev::shared_kernel<O, mm.seg16, mm.seg32, mm.seg64, CH, LZ>;
+  hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kWavesPerGroup * kWave), lds, st, a, mask);
+  return hipGetLastError();
+}
+
+template <bool CH, bool LZ>
+hipError_t dispatch(int menu, const KArgs &a, int grid, hipStream_t st, uint32_t mask, size_t lds) {
+  switch (menu) {
+    case 0: return launch_m<0, CH, LZ>(a, grid, st, mask, lds);
+    case 1: return launch_m<1, CH, LZ>(a, grid, st, mask, lds);
+    case 2: return launch_m<2, CH, LZ>(a, grid, st, mask, lds);
+    case 3: return launch_m<3, CH, LZ>(a, grid, st, mask, lds);
+    case 4: return launch_m<4, CH, LZ>(a, grid, st, mask, lds);
+    case 5: return launch_m<5, CH, LZ>(a, grid, st, mask, lds);
+  }
+  return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_shared_i16(Alg alg, int menu, bool chunked, const KArgs &a, int grid,
+                              hipStream_t st, uint32_t mask, size_t lds) {
+  if (alg != ALG_SCAN) return hipErrorInvalidValue;
+  return chunked ? dispatch<true, false>(menu, a, grid, st, mask, lds)
+                 : dispatch<false, false>(menu, a, grid, st, mask, lds);
+}
+
+}  // namespace swk

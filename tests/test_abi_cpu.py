@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+symbol include/sw.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1909_00899_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "sw.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(sw_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(api.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return api.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared_functions()
+    assert "sw_align" in names and "sw_align_batch" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert lib.sw_strerror(code)
+    assert lib.sw_strerror(12345) == b"unknown status"
+
+
+def _sc(M, go=11, ge=1):
+    return api.make_scoring(M, go, ge)
+
+
+def test_sw_align_rejects_bad_arguments(lib):
+    M = np.eye(4, dtype=np.int32)
+    q = np.array([0, 1, 2], dtype=np.uint8)
+    res = api.Result()
+    sc, keep = _sc(M)
+    # residue outside the alphabet
+    bad = np.array([0, 9], dtype=np.uint8)
+    assert lib.sw_align(bad.ctypes.data, 2, q.ctypes.data, 3, ctypes.byref(sc), ctypes.byref(res)) == api.SW_EINVAL
+    # negative length, NULL out
+    assert lib.sw_align(q.ctypes.data, -1, q.ctypes.data, 3, ctypes.byref(sc), ctypes.byref(res)) == api.SW_EINVAL
+    assert lib.sw_align(q.ctypes.data, 3, q.ctypes.data, 3, ctypes.byref(sc), None) == api.SW_EINVAL
+    # alphabet size, negative penalties
+    sc2 = api.Scoring(0, M.ctypes.data, 1, 1)
+    assert lib.sw_align(q.ctypes.data, 3, q.ctypes.data, 3, ctypes.byref(sc2), ctypes.byref(res)) == api.SW_EINVAL
+    sc3 = api.Scoring(4, M.ctypes.data, -1, 1)
+    assert lib.sw_align(q.ctypes.data, 3, q.ctypes.data, 3, ctypes.byref(sc3), ctypes.byref(res)) == api.SW_EINVAL
+    # empty sequences are valid and need no device
+    assert lib.sw_align(None, 0, q.ctypes.data, 3, ctypes.byref(sc), ctypes.byref(res)) == api.SW_OK
+    assert (res.score, res.query_end, res.ref_end) == (0, -1, -1)
+    # overflow guard
+    big = np.full((4, 4), 2 ** 30, dtype=np.int32)
+    scb, kb = _sc(big)
+    assert lib.sw_align(q.ctypes.data, 3, q.ctypes.data, 3, ctypes.byref(scb), ctypes.byref(res)) == api.SW_EOVERFLOW
+
+
+def test_batch_rejects_bad_options(lib):
+    M = np.eye(4, dtype=np.int32)
+    sc, keep = _sc(M)
+    b = api.Batch()
+    out = np.zeros((1, 4), dtype=np.int32)
+    assert lib.sw_align_batch(None, ctypes.byref(sc), out.ctypes.data) == api.SW_EINVAL
+    b.n_pairs = -1
+    assert lib.sw_align_batch(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data) == api.SW_EINVAL
+    b.n_pairs = 0
+    assert lib.sw_align_batch(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data) == api.SW_OK
+    opt = api.Options()
+    opt.force_lanes = 8
+    b.n_pairs = 1
+    assert lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
+                                 out.ctypes.data, None) == api.SW_EINVAL
+    opt.force_lanes = 0
+    opt.int16_cap = 40000
+    assert lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
+                                 out.ctypes.data, None) == api.SW_EINVAL
+    b.precision = 7
+    assert lib.sw_align_batch(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data) == api.SW_EINVAL

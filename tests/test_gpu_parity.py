@@ -1,0 +1,228 @@
+"""GPU parity: every result of the HIP path must equal the CPU oracle exactly
+(score, query_end, ref_end), on the same seeded inputs, through the C ABI."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_00899_amd import api, workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    oracle.build(force=False)
+    api.load()          # raises if the HIP library is missing: no fallback
+    api.sw_init()
+
+
+def oracle_batch(w):
+    return oracle.align_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref,
+                              w.matrix, w.gap_open, w.gap_extend, pair_query=w.pair_query)
+
+
+def assert_same(got, want, w=None, label=""):
+    got3 = np.asarray(got)[:, :3]
+    bad = np.nonzero((got3 != want).any(axis=1))[0]
+    if bad.size:
+        k = int(bad[0])
+        extra = ""
+        if w is not None:
+            q, r = w.pair(k)
+            extra = " m=%d n=%d" % (q.size, r.size)
+        raise AssertionError("%s: %d/%d mismatches; first pair %d got %s want %s%s" %
+                             (label, bad.size, len(want), k, got3[k].tolist(),
+                              want[k].tolist(), extra))
+
+
+# ---------------------------------------------------------------- plain kernel
+
+def test_worked_example_plain():
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    code = {c: k for k, c in enumerate(g["alphabet"])}
+    M = np.full((4, 4), g["mismatch"], dtype=np.int32)
+    np.fill_diagonal(M, g["match"])
+    q = [code[c] for c in g["query"]]
+    r = [code[c] for c in g["ref"]]
+    s, qe, re_, fl = api.sw_align(q, r, M, g["gap_open"], g["gap_extend"])
+    assert (s, qe, re_) == (g["result"]["score"], g["result"]["query_end"], g["result"]["ref_end"])
+    s, qe, re_, fl = api.sw_align(r, q, M, g["gap_open"], g["gap_extend"])
+    sw = g["swapped_result"]
+    assert (s, qe, re_) == (sw["score"], sw["query_end"], sw["ref_end"])
+
+
+def test_single_pair_workload_plain():
+    w = W.single_pair()
+    q, r = w.pair(0)
+    got = api.sw_align(q, r, w.matrix, w.gap_open, w.gap_extend)
+    assert got[:3] == oracle.align(q, r, w.matrix, w.gap_open, w.gap_extend)
+
+
+@pytest.mark.parametrize("m", [1, 2, 15, 16, 17, 63, 64, 65, 127, 200, 511, 512, 513, 1100])
+def test_plain_query_lengths(m):
+    rng = np.random.default_rng(100 + m)
+    M = W.protein_matrix()
+    for n in (1, 3, 4, 5, 77, 300):
+        q = rng.integers(0, 20, size=m)
+        r = rng.integers(0, 20, size=n)
+        got = api.sw_align(q, r, M, 11, 1)
+        assert got[:3] == oracle.align(q, r, M, 11, 1), (m, n)
+
+
+def test_plain_edge_cases():
+    M = W.protein_matrix()
+    assert api.sw_align([], [1, 2], M, 11, 1)[:3] == (0, -1, -1)
+    neg = -np.ones((20, 20), dtype=np.int32)
+    q = np.arange(20)
+    assert api.sw_align(q, q, neg, 3, 1)[:3] == (0, -1, -1)
+    # self alignment of a long query with every residue matching
+    q = np.random.default_rng(3).integers(0, 20, size=700)
+    d = np.diag(M)
+    assert api.sw_align(q, q, M, 11, 1)[:3] == (int(d[q].sum()), 699, 699)
+
+
+def test_double_gap_bridge_plain():
+    M = np.full((4, 4), -4, dtype=np.int32)
+    M[0, 0] = M[1, 1] = 5
+    for k in (11, 12, 16):
+        q = [0] * 12 + [2] * k + [1] * 12
+        r = [0] * 12 + [3] * k + [1] * 12
+        assert api.sw_align(q, r, M, 11, 1)[:3] == oracle.align(q, r, M, 11, 1)
+
+
+def test_gap_extend_above_gap_open_is_clamped():
+    rng = np.random.default_rng(9)
+    M = W.protein_matrix()
+    for _ in range(20):
+        q = rng.integers(0, 20, size=int(rng.integers(1, 90)))
+        r = rng.integers(0, 20, size=int(rng.integers(1, 90)))
+        go = int(rng.integers(0, 6))
+        ge = go + int(rng.integers(1, 5))
+        assert api.sw_align(q, r, M, go, ge)[:3] == oracle.align(q, r, M, go, ge)
+
+
+# ---------------------------------------------------------------- batched kernels
+
+def _random_batch(seed, n, alpha, mlen, nlen, go=11, ge=1):
+    rng = np.random.default_rng(seed)
+    M = W.protein_matrix() if alpha == 20 else W.random_matrix(rng, alpha, symmetric=False)
+    return W.random_pairs(n, alpha, mlen, nlen, seed, matrix=M, gap_open=go, gap_extend=ge)
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("prec", [api.SW_PREC_AUTO, api.SW_PREC_I32])
+def test_batch_random_pairs(kernel, prec):
+    w = _random_batch(7, 600, 20, (1, 260), (1, 400))
+    want = oracle_batch(w)
+    got = api.align_workload(w, force_kernel=kernel, precision=prec)
+    assert_same(got.results, want, w, "kernel=%d prec=%d" % (kernel, prec))
+
+
+@pytest.mark.parametrize("lanes", [16, 32, 64])
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_batch_forced_lanes(lanes, kernel):
+    w = _random_batch(8, 300, 4, (1, 200), (1, 300), go=6, ge=1)
+    want = oracle_batch(w)
+    got = api.align_workload(w, force_kernel=kernel, force_lanes=lanes)
+    assert_same(got.results, want, w, "lanes=%d kernel=%d" % (lanes, kernel))
+
+
+@pytest.mark.parametrize("lanes,seg", [(16, 4), (32, 4), (64, 4), (16, 8), (64, 8), (32, 12)])
+def test_batch_chunked_queries(lanes, seg):
+    """Queries longer than lanes*seglen rows run as chunks with boundary carries."""
+    w = _random_batch(9, 96, 20, (50, 1500), (20, 300))
+    want = oracle_batch(w)
+    for kernel in (1, 2):
+        got = api.align_workload(w, force_kernel=kernel, force_lanes=lanes, force_seglen=seg)
+        assert_same(got.results, want, w, "kernel=%d lanes=%d seg=%d" % (kernel, lanes, seg))
+
+
+def test_int16_saturation_rerun():
+    rng = np.random.default_rng(11)
+    M = W.protein_matrix()
+    # natural saturation: a 4200-residue self alignment over the letters with
+    # diagonal score >= 10 scores above 42000 > 32767
+    rich = np.nonzero(np.diag(M) >= 10)[0]
+    q = rng.choice(rich, size=4200).astype(np.uint8)
+    qs = [q, q[:3300], rng.integers(0, 20, size=300).astype(np.uint8)]
+    qres = np.concatenate(qs)
+    qoff = np.array([0, 4200, 7500, 7800], dtype=np.int64)
+    pq = np.array([0, 1, 2, 0], dtype=np.int32)
+    pr = np.array([0, 1, 2, 2], dtype=np.int32)
+    got = api.sw_align_batch(qres, qoff, qres, qoff, pr, M, 11, 1, pair_query=pq)
+    for k in range(4):
+        qq = qres[qoff[pq[k]]:qoff[pq[k] + 1]]
+        rr = qres[qoff[pr[k]]:qoff[pr[k] + 1]]
+        assert tuple(got.results[k, :3]) == oracle.align(qq, rr, M, 11, 1)
+    assert got.results[0, 3] == api.SW_FLAG_SATURATED and got.results[0, 0] > 32767
+    assert got.stats["n_rerun"] >= 2
+
+
+def test_int16_forced_rerun_cap():
+    w = _random_batch(12, 400, 20, (10, 200), (10, 300))
+    want = oracle_batch(w)
+    got = api.align_workload(w, int16_cap=40)
+    assert_same(got.results, want, w, "cap=40")
+    assert got.stats["n_rerun"] == int((want[:, 0] >= 40).sum())
+    assert ((got.results[:, 3] == 1) == (want[:, 0] >= 40)).all()
+
+
+def test_protein_search_subset():
+    w = W.protein_search(n_refs=3000)
+    want = oracle_batch(w)
+    got = api.align_workload(w)
+    assert_same(got.results, want, w, "protein_search")
+
+
+def test_dna_pairs_subset():
+    w = W.dna_pairs(n_pairs=20000)
+    want = oracle_batch(w)
+    got = api.align_workload(w)
+    assert_same(got.results, want, w, "dna_pairs")
+
+
+def test_long_queries_subset_scan_and_lazyf():
+    w = W.long_queries(n_queries=4, n_refs=40, qlen=(1500, 3000), rlen=(50, 300))
+    want = oracle_batch(w)
+    got = api.align_workload(w, precision=api.SW_PREC_I32)
+    assert_same(got.results, want, w, "scan")
+    lz = api.align_workload(w, precision=api.SW_PREC_I32, algorithm=api.SW_ALG_LAZYF)
+    assert_same(lz.results, want, w, "lazyf")
+    assert lz.stats["lazyf_steps"] > 0
+
+
+def test_batch_empty_and_degenerate_pairs():
+    M = W.protein_matrix()
+    qres = np.array([1, 2, 3, 4, 5], dtype=np.uint8)
+    qoff = np.array([0, 0, 5], dtype=np.int64)
+    pq = np.array([0, 1, 1], dtype=np.int32)
+    pr = np.array([1, 0, 1], dtype=np.int32)
+    got = api.sw_align_batch(qres, qoff, qres, qoff, pr, M, 11, 1, pair_query=pq)
+    assert got.results[:, :3].tolist() == [[0, -1, -1], [0, -1, -1],
+                                          list(oracle.align(qres, qres, M, 11, 1))]
+
+
+def test_batch_invalid_residue_rejected():
+    M = np.eye(4, dtype=np.int32)
+    qres = np.array([0, 1, 7], dtype=np.uint8)
+    qoff = np.array([0, 3], dtype=np.int64)
+    with pytest.raises(api.SwError) as e:
+        api.sw_align_batch(qres, qoff, qres, qoff, np.zeros(1, np.int32), M, 2, 1)
+    assert e.value.code == api.SW_EINVAL
+
+
+def test_device_resident_inputs_match_host():
+    import torch
+    w = _random_batch(13, 200, 20, (1, 300), (1, 300))
+    want = oracle_batch(w)
+    dev = torch.device("cuda")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    got = api.sw_align_batch(t(w.query_res, torch.uint8), t(w.query_off, torch.int64),
+                             t(w.ref_res, torch.uint8), t(w.ref_off, torch.int64),
+                             t(w.pair_ref, torch.int32), w.matrix, w.gap_open, w.gap_extend,
+                             pair_query=t(w.pair_query, torch.int32))
+    assert_same(got.results, want, w, "device-resident")
