@@ -170,6 +170,10 @@ typedef struct {
     int64_t columns;             /* column steps executed (per sub-group)            */
     int32_t lanes_used[3];       /* pairs run with 16 / 32 / 64 lanes                */
     int32_t seglen_max;          /* largest rows-per-lane used                       */
+    double prep_ms;              /* host: argument checks, offsets, sequence upload  */
+    double plan_ms;              /* host: work planner                               */
+    double launch_ms;            /* host: staging uploads and kernel launches        */
+    double finish_ms;            /* waiting for the device, results, int32 reruns    */
     int32_t reserved[8];
 } sw_stats;
 

@@ -73,6 +73,8 @@ class Stats(ctypes.Structure):
                 ("n_rerun", ctypes.c_int32), ("n_launches", ctypes.c_int32),
                 ("lazyf_steps", ctypes.c_int64), ("columns", ctypes.c_int64),
                 ("lanes_used", ctypes.c_int32 * 3), ("seglen_max", ctypes.c_int32),
+                ("prep_ms", ctypes.c_double), ("plan_ms", ctypes.c_double),
+                ("launch_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
                 ("reserved", ctypes.c_int32 * 8)]
 
     def as_dict(self) -> dict:
@@ -80,7 +82,8 @@ class Stats(ctypes.Structure):
                 "padded_cells": self.padded_cells, "n_rerun": self.n_rerun,
                 "n_launches": self.n_launches, "lazyf_steps": self.lazyf_steps,
                 "columns": self.columns, "lanes_used": list(self.lanes_used),
-                "seglen_max": self.seglen_max}
+                "seglen_max": self.seglen_max, "prep_ms": self.prep_ms, "plan_ms": self.plan_ms,
+                "launch_ms": self.launch_ms, "finish_ms": self.finish_ms}
 
 
 class ServerConfig(ctypes.Structure):

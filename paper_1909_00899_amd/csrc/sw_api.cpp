@@ -24,11 +24,6 @@ namespace {
     }                                                                            \
   } while (0)
 
-double now_ms() {
-  return std::chrono::duration<double, std::milli>(
-             std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
 constexpr int64_t kI32Limit = 2147483647ll;
 
 bool overflows(int64_t m, int64_t n, int max_s) {
@@ -202,7 +197,7 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
       return SW_EINVAL;
     }
     PairInfo &p = in.pairs[k];
-    std::memset(&p, 0, sizeof(p));
+    p.pad = 0;
     p.q_off = qoff[q];
     p.r_off = roff[r];
     p.m = (int)(qoff[q + 1] - qoff[q]);
@@ -232,6 +227,7 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
   HIPCHK(hipMemsetAsync(C.flag.p, 0, 16, st));
   HIPCHK(swk::launch_check_residues(in.d_qres, qbytes, S.alpha, C.flag.as<int>(), st));
   HIPCHK(swk::launch_check_residues(in.d_rres, rbytes, S.alpha, C.flag.as<int>(), st));
+  const double t_prep = now_ms() - t0;
   rc = run_batch(in, S, b->precision, eo, C.ws, np, st, C.ev0, C.ev1, C.num_cus, out, stats);
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, C.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -244,6 +240,7 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
   if (rc) return rc;
   if (stats) {
     stats->cells = cells;
+    stats->prep_ms = t_prep;
     stats->total_ms = now_ms() - t0;
   }
   return SW_OK;

@@ -53,6 +53,7 @@ struct OpsI32 {
   __device__ static uint32_t vmax(uint32_t a, uint32_t b) { return (uint32_t)max((int)a, (int)b); }
   __device__ static uint32_t usub(uint32_t a, uint32_t b) { return __builtin_elementwise_sub_sat(a, b); }
   __device__ static int get(uint32_t x, int) { return (int)x; }
+  __device__ static uint32_t set(uint32_t, int, int v) { return (uint32_t)v; }
   __device__ static uint32_t splat(uint32_t v) { return v; }
 };
 
@@ -70,6 +71,9 @@ struct OpsI16 {
     return bc<uint32_t>(__builtin_elementwise_sub_sat(bc<u16x2>(a), bc<u16x2>(b)));
   }
   __device__ static int get(uint32_t x, int h) { return (int)(short)(h ? (x >> 16) : (x & 0xffffu)); }
+  __device__ static uint32_t set(uint32_t x, int h, int v) {
+    return h ? ((x & 0xffffu) | ((uint32_t)v << 16)) : ((x & 0xffff0000u) | ((uint32_t)v & 0xffffu));
+  }
   __device__ static uint32_t splat(uint32_t v) { return (v & 0xffffu) * 0x10001u; }
 };
 
@@ -147,24 +151,34 @@ __device__ __forceinline__ uint32_t shift1(uint32_t x, const LaneCtx &L, uint32_
 
 // ---------------------------------------------------------------- per-lane state
 
+// End cell without storing a column of H_diag: G is the sub-group's running
+// maximum over finished columns.  A cell whose H_diag does not exceed G lies
+// in a later column than a cell scoring at least as much, so it is never the
+// lexicographically smallest best cell.  When a lane's column maximum c
+// exceeds G, every E and F value feeding its rows in this column is at most
+// (a value <= G) minus GapOpen, and every in-lane F comes from rows scoring
+// below c; hence the first row whose new H reaches c is the first row whose
+// H_diag equals c.  The lane records (c, column, row); the final reduction
+// over lanes picks the highest score, then the smallest column, then row.
 template <int SEG>
 struct State {
   uint32_t H[SEG];    // H of the previous column, before the cross-lane fix-up
   uint32_t E[SEG];
-  uint32_t S[SEG];    // H_diag of the current column (only read when a lane improves)
   uint32_t Fscan;     // vertical-gap value entering this lane's first row
-  uint32_t best;      // running maximum of H_diag in this lane (per half)
-  int bcol[2], brow[2];
+  uint32_t G;         // sub-group record of H_diag over finished columns (per half)
+  uint32_t rs;        // this lane's recorded score (per half)
+  int rc[2], rr[2];   // recorded column and row (per half)
 };
 
 template <int SEG>
-__device__ __forceinline__ void state_reset(State<SEG> &st) {
+__device__ __forceinline__ void state_reset(State<SEG> &st, uint32_t g0) {
 #pragma unroll
   for (int j = 0; j < SEG; ++j) { st.H[j] = 0; st.E[j] = 0; }
   st.Fscan = 0;
-  st.best = 0;
-  st.bcol[0] = st.bcol[1] = 0x7fffffff;
-  st.brow[0] = st.brow[1] = 0x7fffffff;
+  st.G = g0;
+  st.rs = 0;
+  st.rc[0] = st.rc[1] = 0x7fffffff;
+  st.rr[0] = st.rr[1] = 0x7fffffff;
 }
 
 struct Params {
@@ -205,6 +219,34 @@ struct ProfLds {
   }
 };
 
+// New records of the running maximum (rare): see State.  H[] must hold this
+// column's values before any cross-lane correction.
+template <class O, int SEG>
+__device__ __forceinline__ void record(State<SEG> &st, const LaneCtx &L, uint32_t cmax, int i) {
+  const uint32_t nb = O::vmax(st.G, cmax);
+  if (__any(nb != st.G)) {
+    uint32_t g = nb;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t o = (uint32_t)__shfl_xor((int)g, d);
+      if (d < L.P) g = O::vmax(g, o);
+    }
+#pragma unroll
+    for (int h = 0; h < O::kHalves; ++h) {
+      const int cm = O::get(cmax, h);
+      if (cm > O::get(st.G, h)) {
+        int jj = SEG - 1;
+#pragma unroll
+        for (int j = SEG - 1; j >= 0; --j)
+          if (O::get(st.H[j], h) >= cm) jj = j;
+        st.rc[h] = i;
+        st.rr[h] = L.l * SEG + jj;
+        st.rs = O::set(st.rs, h, cm);
+      }
+    }
+    st.G = g;
+  }
+}
+
 // ---------------------------------------------------------------- one column
 
 template <class O, int SEG, int PMAX, bool CHUNKED, bool LAZY, class Prof>
@@ -223,7 +265,6 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     for (int j = 0; j < SEG; ++j) {
       const uint32_t p = pf.load(blo, bhi, j);
       const uint32_t hd = O::hadd(Hin, p);
-      st.S[j] = hd;
       cmax = j == 0 ? hd : O::vmax(cmax, hd);
       const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
       const uint32_t hold = st.H[j];
@@ -247,6 +288,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     if constexpr (PMAX >= 64) G = O::vmax(G, O::usub(dpp<kRowBcast31, 0xc, false>(G), L.w32));
     fb_out = G;
     st.Fscan = shift1<PMAX, CHUNKED>(G, L, fb_in);
+    record<O, SEG>(st, L, cmax, i);
   } else {
     // Algorithm 1: H[] already holds corrected values.
     hb_out = st.H[SEG - 1];
@@ -256,7 +298,6 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     for (int j = 0; j < SEG; ++j) {
       const uint32_t p = pf.load(blo, bhi, j);
       const uint32_t hd = O::hadd(Hin, p);
-      st.S[j] = hd;
       cmax = j == 0 ? hd : O::vmax(cmax, hd);
       const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
       Hin = st.H[j];
@@ -265,6 +306,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
       st.E[j] = O::vmax(O::usub(st.E[j], pr.ge), t);
       F = O::vmax(O::usub(F, pr.ge), t);
     }
+    record<O, SEG>(st, L, cmax, i);
     // Lazy-F loop: propagate the vertical gap across lanes until, in every
     // lane at once, the propagated value can no longer exceed what the first
     // pass already derived (F <= max(H_before - go, 0)); then stop.
@@ -287,23 +329,6 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
       }
     }
     fb_out = Fexit;
-  }
-  // running maximum and its lexicographically smallest cell
-  const uint32_t nb = O::vmax(st.best, cmax);
-  if (nb != st.best) {
-#pragma unroll
-    for (int h = 0; h < O::kHalves; ++h) {
-      const int cm = O::get(cmax, h);
-      if (cm > O::get(st.best, h)) {
-        int jj = SEG - 1;
-#pragma unroll
-        for (int j = SEG - 1; j >= 0; --j)
-          if (O::get(st.S[j], h) == cm) jj = j;
-        st.bcol[h] = i;
-        st.brow[h] = L.l * SEG + jj;
-      }
-    }
-    st.best = nb;
   }
 }
 
@@ -363,37 +388,74 @@ __device__ __forceinline__ bool better(int s, int c, int r, int s2, int c2, int 
   return s > s2 || (s == s2 && (c < c2 || (c == c2 && r < r2)));
 }
 
-// Reduces each slot-half's best cell over its sub-group and writes (or merges
-// with a previous query chunk's) result.
+// Reduces each slot-half's recorded cells over its sub-group, merges with
+// the result of the previous query chunks (prev_*, identical in every lane of
+// the sub-group, updated in place) and writes the merged result.
+struct Prev {
+  int s[2], c[2], r[2];
+  uint32_t f[2];
+};
+
+__device__ __forceinline__ void prev_reset(Prev &p) {
+  p.s[0] = p.s[1] = 0;
+  p.c[0] = p.c[1] = p.r[0] = p.r[1] = 0x7fffffff;
+  p.f[0] = p.f[1] = 0;
+}
+
+// Loads the previous chunks' merged results of this lane's slot-halves.
+template <class O>
+__device__ __forceinline__ void prev_load(Prev &p, const LaneCtx &L, const Task *tp,
+                                          const PairInfo *pairs, const DevResult *results) {
+  prev_reset(p);
+#pragma unroll
+  for (int h = 0; h < O::kHalves; ++h) {
+    const int pid = tp->pair[2 * L.sg + h];
+    if (pid >= 0) {
+      const DevResult r = results[pairs[pid].out];
+      if (r.score > 0) { p.s[h] = r.score; p.c[h] = r.rend; p.r[h] = r.qend; }
+      p.f[h] = r.flags;
+    }
+  }
+}
+
+// Initial record G: ties with a previous chunk's best must still be seen (a
+// tie in an earlier column wins), so start one below it.
+template <class O>
+__device__ __forceinline__ uint32_t prev_g0(const Prev &p) {
+  uint32_t g = 0;
+#pragma unroll
+  for (int h = 0; h < O::kHalves; ++h) g = O::set(g, h, p.s[h] > 0 ? p.s[h] - 1 : 0);
+  return g;
+}
+
 template <class O, int SEG>
 __device__ __forceinline__ void finish(const State<SEG> &st, const LaneCtx &L, const Task *tp,
                                        const PairInfo *pairs, DevResult *results, int row_base,
-                                       bool merge, int sat_cap) {
+                                       Prev &prev, int sat_cap) {
 #pragma unroll
   for (int h = 0; h < O::kHalves; ++h) {
-    int s = O::get(st.best, h);
-    int c = s > 0 ? st.bcol[h] : 0x7fffffff;
-    int r = s > 0 ? st.brow[h] + row_base : 0x7fffffff;
+    int s = O::get(st.rs, h);
+    int c = s > 0 ? st.rc[h] : 0x7fffffff;
+    int r = s > 0 ? st.rr[h] + row_base : 0x7fffffff;
     for (int d = 1; d < kWave; d <<= 1) {
       const int s2 = __shfl_xor(s, d), c2 = __shfl_xor(c, d), r2 = __shfl_xor(r, d);
       if (d < L.P && better(s2, c2, r2, s, c, r)) { s = s2; c = c2; r = r2; }
     }
+    uint32_t flags = prev.f[h];
+    if (O::kHalves == 2 && s >= sat_cap) flags |= kFlagNeedsI32;
+    if (prev.s[h] > 0 && (s <= 0 || better(prev.s[h], prev.c[h], prev.r[h], s, c, r))) {
+      s = prev.s[h]; c = prev.c[h]; r = prev.r[h];
+    }
+    if (s <= 0) { s = 0; c = 0x7fffffff; r = 0x7fffffff; }
+    prev.s[h] = s; prev.c[h] = c; prev.r[h] = r; prev.f[h] = flags;
     const int pid = tp->pair[2 * L.sg + h];
     if (L.start && pid >= 0) {
-      const int out = pairs[pid].out;
-      uint32_t flags = 0;
-      if (O::kHalves == 2 && s >= sat_cap) flags |= kFlagNeedsI32;
-      if (s <= 0) { s = 0; c = -1; r = -1; }
-      if (merge) {
-        const DevResult pv = results[out];
-        flags |= pv.flags;
-        if (pv.score > 0 && (s == 0 || better(pv.score, pv.rend, pv.qend, s, c, r))) {
-          s = pv.score; c = pv.rend; r = pv.qend;
-        }
-      }
       DevResult res;
-      res.score = s; res.qend = r; res.rend = c; res.flags = flags;
-      results[out] = res;
+      res.score = s;
+      res.qend = s > 0 ? r : -1;
+      res.rend = s > 0 ? c : -1;
+      res.flags = flags;
+      results[pairs[pid].out] = res;
     }
   }
 }
@@ -460,8 +522,11 @@ __device__ __forceinline__ void shared_task(const KArgs &a, const Task &t, const
   const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
   SharedMap<O, SEG, P> pm;
   pm.lane_base = prof_off + L.l * O::kES;
+  Prev prev;
+  prev_reset(prev);
+  if (CHUNKED && a.chunk > 0) prev_load<O>(prev, L, tp, a.pairs, a.results);
   State<SEG> st;
-  state_reset(st);
+  state_reset(st, prev_g0<O>(prev));
   const uint32_t *hb_in = nullptr, *fb_in = nullptr;
   uint32_t *hb_out = nullptr, *fb_out = nullptr;
   if constexpr (CHUNKED) {
@@ -477,8 +542,7 @@ __device__ __forceinline__ void shared_task(const KArgs &a, const Task &t, const
   run_columns<O, SEG, P, CHUNKED, LAZY>(st, L, pr, pm, a.streams + t.stream_off, t.ncols, hb_in,
                                         fb_in, hb_out, fb_out, lazy_steps);
   cols += (unsigned long long)t.ncols;
-  finish<O, SEG>(st, L, tp, a.pairs, a.results, a.chunk * P * SEG, CHUNKED && a.chunk > 0,
-                 a.sat_cap);
+  finish<O, SEG>(st, L, tp, a.pairs, a.results, a.chunk * P * SEG, prev, a.sat_cap);
 }
 
 template <class O, int S16, int S32, int S64, bool CHUNKED, bool LAZY>
@@ -595,11 +659,13 @@ void pair_kernel(KArgs a) {
     pm.lo0 = region + L.lane * O::kES;
     pm.hi0 = pm.lo0 + (O::kHalves == 2 ? (a.alpha + 1) * SEG * kWave * O::kES : 0);
     const int nch = CHUNKED ? t.nchunks : 1;
+    Prev prev;
+    prev_reset(prev);
     for (int ch = 0; ch < nch; ++ch) {
       const int row0 = ch * L.P * SEG;
       build_pair_profile<O, SEG>(a, a.tasks + ti, L, region, row0);
       State<SEG> st;
-      state_reset(st);
+      state_reset(st, prev_g0<O>(prev));
       const uint32_t *hb_in = nullptr, *fb_in = nullptr;
       uint32_t *hb_out = nullptr, *fb_out = nullptr;
       if constexpr (CHUNKED) {
@@ -614,7 +680,7 @@ void pair_kernel(KArgs a) {
       run_columns<O, SEG, PMAX, CHUNKED, false>(st, L, pr, pm, a.streams + t.stream_off, t.ncols,
                                                 hb_in, fb_in, hb_out, fb_out, lazy_steps);
       cols += (unsigned long long)t.ncols;
-      finish<O, SEG>(st, L, a.tasks + ti, a.pairs, a.results, row0, ch > 0, a.sat_cap);
+      finish<O, SEG>(st, L, a.tasks + ti, a.pairs, a.results, row0, prev, a.sat_cap);
     }
   }
   if ((threadIdx.x & 63) == 0 && a.stats != nullptr && cols) atomicAdd(&a.stats[0], cols);

@@ -51,6 +51,11 @@ void set_error(const char *fmt, ...) {
     }                                                                            \
   } while (0)
 
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 // ------------------------------------------------------------------ buffers
 
 int DevBuf::ensure(size_t bytes) {
@@ -182,6 +187,26 @@ int layout_for(int P) { return P == 16 ? 0xF : (P == 32 ? 0x5 : 0x1); }
 
 int round_up(int64_t x, int64_t k) { return (int)(((x + k - 1) / k) * k); }
 
+// Indices of items ordered by reference length, longest first, ties in input
+// order (a stable counting sort: the lengths of one batch span a small range).
+void sort_by_n_desc(const std::vector<PlanItem> &items, std::vector<int> &order) {
+  order.resize(items.size());
+  if (items.empty()) return;
+  int lo = items[0].n, hi = items[0].n;
+  for (const auto &it : items) { lo = std::min(lo, it.n); hi = std::max(hi, it.n); }
+  const int64_t range = (int64_t)hi - lo + 1;
+  if (range > 4 * (int64_t)items.size() + 1024) {
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return items[a].n > items[b].n; });
+    return;
+  }
+  std::vector<int> start(range + 1, 0);
+  for (const auto &it : items) start[hi - it.n + 1]++;
+  for (int64_t k = 0; k < range; ++k) start[k + 1] += start[k];
+  for (size_t k = 0; k < items.size(); ++k) order[start[hi - items[k].n]++] = (int)k;
+}
+
 }  // namespace
 
 // Builds tasks for one shared-query launch group.
@@ -192,10 +217,8 @@ static void plan_shared(const std::vector<PlanItem> &items, Prec prec, int menu,
   const int segs[3] = {mm.seg16, mm.seg32, mm.seg64};
   const int Ps[3] = {16, 32, 64};
   const size_t first = tasks.size();
-  std::vector<int> order(items.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return items[a].n > items[b].n; });
+  std::vector<int> order;
+  sort_by_n_desc(items, order);
   // Mode per pair: the cheapest (narrowest) mode whose task stays short
   // compared with the average load of a wavefront.
   double total = 0;
@@ -322,6 +345,7 @@ struct LaunchDesc {
 int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions &opt,
             Workspace &ws, int n_results, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
             int num_cus, ExecStats &stats, bool reset_results) {
+  const double t_plan0 = now_ms();
   std::vector<Task> tasks;
   std::vector<LaunchDesc> launches;
   const bool lazy = opt.algorithm == SW_ALG_LAZYF;
@@ -429,6 +453,8 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   if (tasks.empty()) return SW_OK;
 
   // ---- device buffers
+  const double t_launch0 = now_ms();
+  stats.plan_ms += t_launch0 - t_plan0;
   int64_t stream_bytes = 0;
   for (auto &t : tasks) { t.stream_off = stream_bytes; stream_bytes += (int64_t)t.ncols / kBlock * kStreamBlockBytes; }
   stream_bytes += 4 * kStreamBlockBytes;
@@ -538,6 +564,8 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
     }
   }
   HIPCHK(hipEventRecord(e1, st));
+  const double t_fin0 = now_ms();
+  stats.launch_ms += t_fin0 - t_launch0;
   unsigned long long hstats[2];
   HIPCHK(hipMemcpyAsync(hstats, d_stats, sizeof(hstats), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -546,6 +574,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   stats.kernel_ms += ms;
   stats.dev_stats[0] += hstats[0];
   stats.dev_stats[1] += hstats[1];
+  stats.finish_ms += now_ms() - t_fin0;
   return SW_OK;
 }
 
@@ -557,6 +586,7 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
   ExecStats es;
   int rc = execute(in, sc, prec, opt, ws, n_pairs, st, e0, e1, num_cus, es, true);
   if (rc) return rc;
+  const double t_res0 = now_ms();
   int rerun = 0;
   if (!in.items.empty()) {
     if ((rc = ws.staging.ensure((size_t)n_pairs * sizeof(DevResult)))) return rc;
@@ -602,8 +632,12 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
       }
     }
   }
+  es.finish_ms += now_ms() - t_res0;
   if (stats) {
     stats->kernel_ms = es.kernel_ms;
+    stats->plan_ms = es.plan_ms;
+    stats->launch_ms = es.launch_ms;
+    stats->finish_ms = es.finish_ms;
     stats->padded_cells = es.padded_cells;
     stats->n_rerun = rerun;
     stats->n_launches = es.launches;

@@ -69,12 +69,15 @@ struct ExecOptions {
 
 struct ExecStats {
   double kernel_ms = 0;
+  double plan_ms = 0, launch_ms = 0, finish_ms = 0;
   int64_t padded_cells = 0;
   int launches = 0;
   int lanes_used[3] = {0, 0, 0};
   int seglen_max = 0;
   unsigned long long dev_stats[2] = {0, 0};
 };
+
+double now_ms();
 
 // Work buffers used by one execution (the batch path owns one; the request
 // server one per in-flight batch).
