@@ -174,6 +174,8 @@ typedef struct {
     double plan_ms;              /* host: work planner                               */
     double launch_ms;            /* host: staging uploads and kernel launches        */
     double finish_ms;            /* waiting for the device, results, int32 reruns    */
+    int64_t record_events;       /* column steps in which some alignment of a
+                                    wavefront set a new running maximum         */
     int32_t reserved[8];
 } sw_stats;
 

@@ -75,7 +75,7 @@ class Stats(ctypes.Structure):
                 ("lanes_used", ctypes.c_int32 * 3), ("seglen_max", ctypes.c_int32),
                 ("prep_ms", ctypes.c_double), ("plan_ms", ctypes.c_double),
                 ("launch_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("record_events", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
 
     def as_dict(self) -> dict:
         return {"kernel_ms": self.kernel_ms, "total_ms": self.total_ms, "cells": self.cells,
@@ -83,7 +83,8 @@ class Stats(ctypes.Structure):
                 "n_launches": self.n_launches, "lazyf_steps": self.lazyf_steps,
                 "columns": self.columns, "lanes_used": list(self.lanes_used),
                 "seglen_max": self.seglen_max, "prep_ms": self.prep_ms, "plan_ms": self.plan_ms,
-                "launch_ms": self.launch_ms, "finish_ms": self.finish_ms}
+                "launch_ms": self.launch_ms, "finish_ms": self.finish_ms,
+                "record_events": self.record_events}
 
 
 class ServerConfig(ctypes.Structure):

@@ -168,6 +168,7 @@ struct State {
   uint32_t G;         // sub-group record of H_diag over finished columns (per half)
   uint32_t rs;        // this lane's recorded score (per half)
   int rc[2], rr[2];   // recorded column and row (per half)
+  uint32_t events;    // record branches taken (statistics)
 };
 
 template <int SEG>
@@ -179,6 +180,7 @@ __device__ __forceinline__ void state_reset(State<SEG> &st, uint32_t g0) {
   st.rs = 0;
   st.rc[0] = st.rc[1] = 0x7fffffff;
   st.rr[0] = st.rr[1] = 0x7fffffff;
+  st.events = 0;
 }
 
 struct Params {
@@ -219,25 +221,60 @@ struct ProfLds {
   }
 };
 
+// Rows of a column are split into groups of kGroup; the column step keeps
+// the maximum of H_diag of each group (the same number of max operations as
+// one running maximum), so finding the end row only scans one group.
+constexpr int kGroup = 8;
+template <int SEG> struct Groups { static constexpr int n = (SEG + kGroup - 1) / kGroup; };
+
+// Maximum over the lanes of each sub-group (all lanes receive it).
+template <class O, int PMAX>
+__device__ __forceinline__ uint32_t subgroup_max(uint32_t x, const LaneCtx &L) {
+  x = O::vmax(x, dpp<0xB1>(x));        // quad_perm [1,0,3,2]
+  x = O::vmax(x, dpp<0x4E>(x));        // quad_perm [2,3,0,1]
+  x = O::vmax(x, dpp<0x124>(x));       // row_ror:4
+  x = O::vmax(x, dpp<0x128>(x));       // row_ror:8
+  if constexpr (PMAX >= 32) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)x, 16);
+    if (L.P >= 32) x = O::vmax(x, o);
+  }
+  if constexpr (PMAX >= 64) {
+    const uint32_t o = (uint32_t)__shfl_xor((int)x, 32);
+    if (L.P >= 64) x = O::vmax(x, o);
+  }
+  return x;
+}
+
 // New records of the running maximum (rare): see State.  H[] must hold this
-// column's values before any cross-lane correction.
-template <class O, int SEG>
-__device__ __forceinline__ void record(State<SEG> &st, const LaneCtx &L, uint32_t cmax, int i) {
+// column's values before any cross-lane correction; gm[] the group maxima of
+// this column's H_diag.
+template <class O, int SEG, int PMAX>
+__device__ __forceinline__ void record(State<SEG> &st, const LaneCtx &L,
+                                       const uint32_t (&gm)[Groups<SEG>::n], uint32_t cmax,
+                                       int i) {
+  constexpr int NG = Groups<SEG>::n;
   const uint32_t nb = O::vmax(st.G, cmax);
   if (__any(nb != st.G)) {
-    uint32_t g = nb;
-    for (int d = 1; d < kWave; d <<= 1) {
-      const uint32_t o = (uint32_t)__shfl_xor((int)g, d);
-      if (d < L.P) g = O::vmax(g, o);
-    }
+    ++st.events;
+    const uint32_t g = subgroup_max<O, PMAX>(nb, L);
 #pragma unroll
     for (int h = 0; h < O::kHalves; ++h) {
       const int cm = O::get(cmax, h);
       if (cm > O::get(st.G, h)) {
+        int gsel = NG - 1;
+#pragma unroll
+        for (int q = NG - 1; q >= 0; --q)
+          if (O::get(gm[q], h) == cm) gsel = q;
         int jj = SEG - 1;
 #pragma unroll
-        for (int j = SEG - 1; j >= 0; --j)
-          if (O::get(st.H[j], h) >= cm) jj = j;
+        for (int q = 0; q < NG; ++q) {
+          if (q == gsel) {
+            const int hi = (q + 1) * kGroup < SEG ? (q + 1) * kGroup : SEG;
+#pragma unroll
+            for (int j = hi - 1; j >= q * kGroup; --j)
+              if (O::get(st.H[j], h) >= cm) jj = j;
+          }
+        }
         st.rc[h] = i;
         st.rr[h] = L.l * SEG + jj;
         st.rs = O::set(st.rs, h, cm);
@@ -254,7 +291,8 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
                                        const Prof &pf, uint32_t blo, uint32_t bhi,
                                        uint32_t hb_in, uint32_t fb_in, uint32_t &hb_out,
                                        uint32_t &fb_out, int i, uint32_t &lazy_steps) {
-  uint32_t cmax;
+  constexpr int NG = Groups<SEG>::n;
+  uint32_t gm[NG];
   if constexpr (!LAZY) {
     uint32_t Fj = st.Fscan;
     const uint32_t hlast = O::vmax(st.H[SEG - 1], O::usub(Fj, pr.wlast));
@@ -265,7 +303,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     for (int j = 0; j < SEG; ++j) {
       const uint32_t p = pf.load(blo, bhi, j);
       const uint32_t hd = O::hadd(Hin, p);
-      cmax = j == 0 ? hd : O::vmax(cmax, hd);
+      gm[j / kGroup] = j % kGroup == 0 ? hd : O::vmax(gm[j / kGroup], hd);
       const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
       const uint32_t hold = st.H[j];
       st.H[j] = h;
@@ -288,7 +326,10 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     if constexpr (PMAX >= 64) G = O::vmax(G, O::usub(dpp<kRowBcast31, 0xc, false>(G), L.w32));
     fb_out = G;
     st.Fscan = shift1<PMAX, CHUNKED>(G, L, fb_in);
-    record<O, SEG>(st, L, cmax, i);
+    uint32_t cmax = gm[0];
+#pragma unroll
+    for (int q = 1; q < NG; ++q) cmax = O::vmax(cmax, gm[q]);
+    record<O, SEG, PMAX>(st, L, gm, cmax, i);
   } else {
     // Algorithm 1: H[] already holds corrected values.
     hb_out = st.H[SEG - 1];
@@ -298,7 +339,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     for (int j = 0; j < SEG; ++j) {
       const uint32_t p = pf.load(blo, bhi, j);
       const uint32_t hd = O::hadd(Hin, p);
-      cmax = j == 0 ? hd : O::vmax(cmax, hd);
+      gm[j / kGroup] = j % kGroup == 0 ? hd : O::vmax(gm[j / kGroup], hd);
       const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
       Hin = st.H[j];
       st.H[j] = h;
@@ -306,7 +347,10 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
       st.E[j] = O::vmax(O::usub(st.E[j], pr.ge), t);
       F = O::vmax(O::usub(F, pr.ge), t);
     }
-    record<O, SEG>(st, L, cmax, i);
+    uint32_t cmax = gm[0];
+#pragma unroll
+    for (int q = 1; q < NG; ++q) cmax = O::vmax(cmax, gm[q]);
+    record<O, SEG, PMAX>(st, L, gm, cmax, i);
     // Lazy-F loop: propagate the vertical gap across lanes until, in every
     // lane at once, the propagated value can no longer exceed what the first
     // pass already derived (F <= max(H_before - go, 0)); then stop.
@@ -517,7 +561,8 @@ __device__ void build_shared_profile(const KArgs &a, uint32_t off) {
 template <class O, int SEG, int P, bool CHUNKED, bool LAZY>
 __device__ __forceinline__ void shared_task(const KArgs &a, const Task &t, const Task *tp,
                                             uint32_t prof_off,
-                                            uint32_t &lazy_steps, unsigned long long &cols) {
+                                            uint32_t &lazy_steps, unsigned long long &cols,
+                                            unsigned long long &events) {
   const LaneCtx L = make_lane<O>(t.layout, SEG, (uint32_t)a.gap_extend);
   const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
   SharedMap<O, SEG, P> pm;
@@ -542,6 +587,7 @@ __device__ __forceinline__ void shared_task(const KArgs &a, const Task &t, const
   run_columns<O, SEG, P, CHUNKED, LAZY>(st, L, pr, pm, a.streams + t.stream_off, t.ncols, hb_in,
                                         fb_in, hb_out, fb_out, lazy_steps);
   cols += (unsigned long long)t.ncols;
+  events += st.events;
   finish<O, SEG>(st, L, tp, a.pairs, a.results, a.chunk * P * SEG, prev, a.sat_cap);
 }
 
@@ -576,24 +622,25 @@ void shared_kernel(KArgs a, uint32_t mode_mask) {
   }
   __syncthreads();
   uint32_t lazy_steps = 0;
-  unsigned long long cols = 0;
+  unsigned long long cols = 0, events = 0;
   for (;;) {
     const int ti = pop_task(a.task_counter);
     if (ti >= a.ntasks) break;
     const Task t = a.tasks[ti];
     if constexpr (S16 > 0) {
-      if (t.mode == 0) { shared_task<O, S16, 16, CHUNKED, LAZY>(a, t, a.tasks + ti, off0, lazy_steps, cols); continue; }
+      if (t.mode == 0) { shared_task<O, S16, 16, CHUNKED, LAZY>(a, t, a.tasks + ti, off0, lazy_steps, cols, events); continue; }
     }
     if constexpr (S32 > 0) {
-      if (t.mode == 1) { shared_task<O, S32, 32, CHUNKED, LAZY>(a, t, a.tasks + ti, off1, lazy_steps, cols); continue; }
+      if (t.mode == 1) { shared_task<O, S32, 32, CHUNKED, LAZY>(a, t, a.tasks + ti, off1, lazy_steps, cols, events); continue; }
     }
     if constexpr (S64 > 0) {
-      if (t.mode == 2) { shared_task<O, S64, 64, CHUNKED, LAZY>(a, t, a.tasks + ti, off2, lazy_steps, cols); continue; }
+      if (t.mode == 2) { shared_task<O, S64, 64, CHUNKED, LAZY>(a, t, a.tasks + ti, off2, lazy_steps, cols, events); continue; }
     }
   }
   if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
     if (cols) atomicAdd(&a.stats[0], cols);
     if (lazy_steps) atomicAdd(&a.stats[1], (unsigned long long)lazy_steps);
+    if (events) atomicAdd(&a.stats[2], events);
   }
 }
 
@@ -648,7 +695,7 @@ void pair_kernel(KArgs a) {
   __syncthreads();
   const uint32_t region = matrix_lds_bytes(a.alpha);
   uint32_t lazy_steps = 0;
-  unsigned long long cols = 0;
+  unsigned long long cols = 0, events = 0;
   for (;;) {
     const int ti = pop_task(a.task_counter);
     if (ti >= a.ntasks) break;
@@ -680,10 +727,14 @@ void pair_kernel(KArgs a) {
       run_columns<O, SEG, PMAX, CHUNKED, false>(st, L, pr, pm, a.streams + t.stream_off, t.ncols,
                                                 hb_in, fb_in, hb_out, fb_out, lazy_steps);
       cols += (unsigned long long)t.ncols;
+      events += st.events;
       finish<O, SEG>(st, L, a.tasks + ti, a.pairs, a.results, row0, prev, a.sat_cap);
     }
   }
-  if ((threadIdx.x & 63) == 0 && a.stats != nullptr && cols) atomicAdd(&a.stats[0], cols);
+  if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
+    if (cols) atomicAdd(&a.stats[0], cols);
+    if (events) atomicAdd(&a.stats[2], events);
+  }
 }
 
 }  // namespace dev

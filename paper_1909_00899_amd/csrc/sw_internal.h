@@ -69,7 +69,7 @@ struct KArgs {
   uint32_t *bnd;              // per-pair kernel: double-buffered boundaries
   int64_t bnd_half;           // per-pair kernel: element distance between the two buffers
   DevResult *results;
-  unsigned long long *stats;  // [0] column steps, [1] lazy-F inner steps
+  unsigned long long *stats;  // [0] column steps, [1] lazy-F inner steps, [2] record branches
 };
 
 // Host-side launchers (defined in sw_kernels.hip).

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -401,16 +402,23 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   if (!per_pair.empty()) {
     struct Key { int seg, P, nch; bool operator<(const Key &o) const {
       return std::tie(seg, P, nch) < std::tie(o.seg, o.P, o.nch); } };
-    std::vector<std::pair<Key, PlanItem>> keyed;
+    // shapes depend on the query length only: decide once per distinct length
+    std::map<int, PairShape> shape_of_m;
+    std::map<Key, std::vector<PlanItem>> groups;
     for (const auto &it : per_pair) {
-      const PairShape ps = choose_pair_shape(prec, it.m, sc.alpha, opt);
-      keyed.push_back({Key{ps.seg, ps.P, ps.nchunks}, it});
+      auto f = shape_of_m.find(it.m);
+      if (f == shape_of_m.end())
+        f = shape_of_m.emplace(it.m, choose_pair_shape(prec, it.m, sc.alpha, opt)).first;
+      const PairShape &ps = f->second;
+      groups[Key{ps.seg, ps.P, ps.nchunks}].push_back(it);
     }
-    std::stable_sort(keyed.begin(), keyed.end(), [](const auto &a, const auto &b) {
-      if (a.first < b.first) return true;
-      if (b.first < a.first) return false;
-      return a.second.n > b.second.n;
-    });
+    std::vector<std::pair<Key, PlanItem>> keyed;
+    keyed.reserve(per_pair.size());
+    std::vector<int> ord;
+    for (auto &g : groups) {
+      sort_by_n_desc(g.second, ord);
+      for (int k : ord) keyed.push_back({g.first, g.second[k]});
+    }
     size_t a = 0;
     while (a < keyed.size()) {
       size_t b = a;
@@ -486,7 +494,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   }
   int rc;
   const size_t n_launch_total = [&] { size_t c = 0; for (auto &L : launches) c += L.shared ? L.nchunks : 1; return c; }();
-  const size_t misc_bytes = 16 + 4 * n_launch_total + 16;   // stats (2 x u64) + counters + residue flag
+  const size_t misc_bytes = 32 + 4 * n_launch_total + 16;   // stats (3 x u64, padded) + counters
   if ((rc = ws.tasks.ensure(tasks.size() * sizeof(Task))) ||
       (rc = ws.pairs.ensure(std::max<size_t>(1, in.pairs.size()) * sizeof(PairInfo))) ||
       (rc = ws.streams.ensure(stream_bytes)) ||
@@ -520,7 +528,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   HIPCHK(launch_build_streams(ws.tasks.as<Task>(), (int)tasks.size(), ws.pairs.as<PairInfo>(),
                               in.d_rres, ws.streams.as<uint8_t>(), sent, st));
   unsigned long long *d_stats = (unsigned long long *)ws.misc.p;
-  int *d_counters = (int *)((char *)ws.misc.p + 16);
+  int *d_counters = (int *)((char *)ws.misc.p + 32);
   uint32_t *bndA = ws.bnd.as<uint32_t>();
   uint32_t *bndB = bndA ? bndA + bnd_half : nullptr;
 
@@ -566,7 +574,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   HIPCHK(hipEventRecord(e1, st));
   const double t_fin0 = now_ms();
   stats.launch_ms += t_fin0 - t_launch0;
-  unsigned long long hstats[2];
+  unsigned long long hstats[3];
   HIPCHK(hipMemcpyAsync(hstats, d_stats, sizeof(hstats), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   float ms = 0;
@@ -574,6 +582,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   stats.kernel_ms += ms;
   stats.dev_stats[0] += hstats[0];
   stats.dev_stats[1] += hstats[1];
+  stats.dev_stats[2] += hstats[2];
   stats.finish_ms += now_ms() - t_fin0;
   return SW_OK;
 }
@@ -643,6 +652,7 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
     stats->n_launches = es.launches;
     stats->lazyf_steps = (int64_t)es.dev_stats[1];
     stats->columns = (int64_t)es.dev_stats[0];
+    stats->record_events = (int64_t)es.dev_stats[2];
     for (int k = 0; k < 3; ++k) stats->lanes_used[k] = es.lanes_used[k];
     stats->seglen_max = es.seglen_max;
   }

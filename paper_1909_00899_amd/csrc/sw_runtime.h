@@ -74,7 +74,7 @@ struct ExecStats {
   int launches = 0;
   int lanes_used[3] = {0, 0, 0};
   int seglen_max = 0;
-  unsigned long long dev_stats[2] = {0, 0};
+  unsigned long long dev_stats[3] = {0, 0, 0};
 };
 
 double now_ms();
