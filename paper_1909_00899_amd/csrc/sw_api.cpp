@@ -186,7 +186,6 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
     in.q_off_of_query[q] = qoff[q];
     in.m_of_query[q] = (int)(qoff[q + 1] - qoff[q]);
   }
-  in.pairs.resize(np);
   in.items.reserve(np);
   int64_t cells = 0;
   for (int k = 0; k < np; ++k) {
@@ -196,19 +195,39 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
       set_error("pair %d refers to query %d / reference %d out of range", k, q, r);
       return SW_EINVAL;
     }
-    PairInfo &p = in.pairs[k];
-    p.pad = 0;
-    p.q_off = qoff[q];
-    p.r_off = roff[r];
-    p.m = (int)(qoff[q + 1] - qoff[q]);
-    p.n = (int)(roff[r + 1] - roff[r]);
-    p.out = k;
-    if (overflows(p.m, p.n, S.max_s)) { set_error("pair %d may overflow int32", k); return SW_EOVERFLOW; }
+    const int m = in.m_of_query[q];
+    const int n = (int)(roff[r + 1] - roff[r]);
+    if (overflows(m, n, S.max_s)) { set_error("pair %d may overflow int32", k); return SW_EOVERFLOW; }
     out[k] = sw_result{0, -1, -1, 0};
-    if (p.m > 0 && p.n > 0) {
-      in.items.push_back(PlanItem{k, q, p.m, p.n});
-      cells += (int64_t)p.m * p.n;
+    if (m > 0 && n > 0) {
+      in.items.push_back(PlanItem{k, q, m, n});
+      cells += (int64_t)m * n;
     }
+  }
+  // PairInfo records are built on the device from the offsets
+  in.n_pairs = np;
+  {
+    const size_t oq = 0, orr = oq + sizeof(int64_t) * (b->n_queries + 1);
+    const size_t opq = orr + sizeof(int64_t) * (b->n_refs + 1);
+    const size_t opr = opq + sizeof(int32_t) * np;
+    const size_t opairs = (opr + sizeof(int32_t) * np + 15) / 16 * 16;
+    const size_t total = opairs + sizeof(PairInfo) * np;
+    if ((rc = C.ws.offs.ensure(total))) return rc;
+    char *base = C.ws.offs.as<char>();
+    const int64_t *d_qoff = b->query_off, *d_roff = b->ref_off;
+    const int32_t *d_pq = b->pair_query, *d_pr = b->pair_ref;
+    if (!b->device_resident) {
+      HIPCHK(hipMemcpyAsync(base + oq, qoff, orr - oq, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(base + orr, roff, opq - orr, hipMemcpyHostToDevice, st));
+      if (pq) HIPCHK(hipMemcpyAsync(base + opq, pq, opr - opq, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync(base + opr, pr, sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
+      d_qoff = (const int64_t *)(base + oq);
+      d_roff = (const int64_t *)(base + orr);
+      d_pq = pq ? (const int32_t *)(base + opq) : nullptr;
+      d_pr = (const int32_t *)(base + opr);
+    }
+    in.d_pairs = (const PairInfo *)(base + opairs);
+    HIPCHK(swk::launch_build_pairs(np, d_qoff, d_roff, d_pq, d_pr, (PairInfo *)(base + opairs), st));
   }
   // sequences on the device
   const int64_t qbytes = qoff[b->n_queries], rbytes = roff[b->n_refs];

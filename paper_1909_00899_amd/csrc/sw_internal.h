@@ -98,6 +98,15 @@ hipError_t launch_build_streams(const Task *tasks, int ntasks, const PairInfo *p
                                 const uint8_t *ref_res, uint8_t *streams, int sent_code,
                                 hipStream_t st);
 
+// Sets every result to {0, -1, -1, 0}.
+hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);
+
+// PairInfo of every pair from device-resident CSR offsets (indices already
+// validated by the host).
+hipError_t launch_build_pairs(int n_pairs, const int64_t *qoff, const int64_t *roff,
+                              const int32_t *pq, const int32_t *pr, PairInfo *out,
+                              hipStream_t st);
+
 // Sets *flag to 1 if any residue in p[0..n) is >= alpha.
 hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *flag,
                                  hipStream_t st);

@@ -53,7 +53,47 @@ __global__ __launch_bounds__(256) void check_residues_kernel(const uint8_t *p, i
     bad |= p[k] >= alpha;
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
+// PairInfo of every pair from CSR offsets already on the device.
+__global__ __launch_bounds__(256) void build_pairs_kernel(int n_pairs, const int64_t *qoff,
+                                                          const int64_t *roff, const int32_t *pq,
+                                                          const int32_t *pr, PairInfo *out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pairs) return;
+  const int q = pq ? pq[k] : 0;
+  const int r = pr[k];
+  PairInfo p;
+  p.q_off = qoff[q];
+  p.r_off = roff[r];
+  p.m = (int)(qoff[q + 1] - qoff[q]);
+  p.n = (int)(roff[r + 1] - roff[r]);
+  p.out = k;
+  p.pad = 0;
+  out[k] = p;
+}
+__global__ __launch_bounds__(256) void init_results_kernel(int n, DevResult *r) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) {
+    DevResult v;
+    v.score = 0; v.qend = -1; v.rend = -1; v.flags = 0;
+    r[k] = v;
+  }
+}
 }  // namespace dev
+
+hipError_t launch_init_results(int n, DevResult *r, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::init_results_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_pairs(int n_pairs, const int64_t *qoff, const int64_t *roff,
+                              const int32_t *pq, const int32_t *pr, PairInfo *out,
+                              hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::build_pairs_kernel, dim3((n_pairs + 255) / 256), dim3(256), 0, st,
+                     n_pairs, qoff, roff, pq, pr, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *flag,
                                  hipStream_t st) {

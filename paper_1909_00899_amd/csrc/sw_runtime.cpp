@@ -211,68 +211,81 @@ void sort_by_n_desc(const std::vector<PlanItem> &items, std::vector<int> &order)
 }  // namespace
 
 // Builds tasks for one shared-query launch group.
-// items: pairs of this query (n > 0, m > 0).
+// items: pairs of this query (n > 0, m > 0).  Pairs are ordered by reference
+// length (longest first); each pair gets the narrowest lane mode whose task
+// stays short next to the average load of a wavefront (long references get
+// more lanes so they finish in time); consecutive pairs of one mode share a
+// task.  Tasks are emitted longest-first (by estimated cost) across modes.
 static void plan_shared(const std::vector<PlanItem> &items, Prec prec, int menu, int num_waves,
-                 int force_lanes, std::vector<Task> &tasks, int mode_counts[3]) {
+                        int force_lanes, std::vector<Task> &tasks, int mode_counts[3]) {
   const SharedMenu mm = shared_menu(menu);
   const int segs[3] = {mm.seg16, mm.seg32, mm.seg64};
   const int Ps[3] = {16, 32, 64};
-  const size_t first = tasks.size();
   std::vector<int> order;
   sort_by_n_desc(items, order);
-  // Mode per pair: the cheapest (narrowest) mode whose task stays short
-  // compared with the average load of a wavefront.
-  double total = 0;
   int narrow = 0;
   for (int k = 0; k < 3; ++k)
     if (segs[k]) { narrow = k; break; }
-  for (const auto &it : items)
-    total += (double)it.n * step_cost(prec, Ps[narrow], segs[narrow]) /
-             slots_per_wave(prec, Ps[narrow]);
+  double total = 0;
+  for (const auto &it : items) total += (double)it.n;
+  total *= step_cost(prec, Ps[narrow], segs[narrow]) / slots_per_wave(prec, Ps[narrow]);
   const double per_wave = total / std::max(1, num_waves);
-  std::vector<int> mode(items.size(), narrow);
-  for (size_t k = 0; k < items.size(); ++k) {
-    if (force_lanes) {
-      mode[k] = force_lanes == 16 ? 0 : (force_lanes == 32 ? 1 : 2);
-      continue;
-    }
+  // mode boundaries in the sorted order: [0, b2) mode 2, [b2, b1) mode 1, rest mode 0
+  auto mode_of = [&](int n) {
+    if (force_lanes) return force_lanes == 16 ? 0 : (force_lanes == 32 ? 1 : 2);
     int md = narrow;
-    while (md < 2 && segs[md + 1] &&
-           (double)items[k].n * step_cost(prec, Ps[md], segs[md]) > 0.35 * per_wave)
+    while (md < 2 && segs[md + 1] && (double)n * step_cost(prec, Ps[md], segs[md]) > 0.35 * per_wave)
       ++md;
-    mode[k] = md;
+    return md;
+  };
+  std::vector<int> begin(4, (int)order.size());
+  {
+    int pos = 0;
+    for (int md = 2; md >= 0; --md) {
+      begin[md] = pos;
+      while (pos < (int)order.size() && mode_of(items[order[pos]].n) == md) ++pos;
+    }
+    begin[3] = pos;
   }
-  for (int md = 0; md < 3; ++md) {
+  const int halves = prec == PREC_I16X2 ? 2 : 1;
+  std::vector<Task> bym[3];
+  for (int md = 2; md >= 0; --md) {
+    const int from = begin[md];
+    const int to = (md == 0) ? begin[3] : begin[md - 1];
+    if (to <= from) continue;
     const int spw = slots_per_wave(prec, Ps[md]);
-    const int halves = prec == PREC_I16X2 ? 2 : 1;
-    std::vector<int> sel;
-    for (int k : order)
-      if (mode[k] == md) sel.push_back(k);
-    mode_counts[md] += (int)sel.size();
-    for (size_t a = 0; a < sel.size(); a += spw) {
+    mode_counts[md] += to - from;
+    bym[md].reserve((to - from + spw - 1) / spw);
+    for (int a = from; a < to; a += spw) {
       Task t;
-      std::memset(&t, 0, sizeof(t));
       t.layout = layout_for(Ps[md]);
       t.mode = md;
       t.nchunks = 1;
       t.bnd_off = -1;
-      for (int s = 0; s < kSlots; ++s) t.pair[s] = -1;
-      int maxn = 0;
-      for (int q = 0; q < spw && a + q < sel.size(); ++q) {
-        const int sg = q / halves, h = q % halves;
-        t.pair[2 * sg + h] = items[sel[a + q]].pair;
-        maxn = std::max(maxn, items[sel[a + q]].n);
+      t.stream_off = 0;
+      for (int s2 = 0; s2 < kSlots; ++s2) t.pair[s2] = -1;
+      int maxn = 1;
+      for (int q = 0; q < spw && a + q < to; ++q) {
+        const PlanItem &it = items[order[a + q]];
+        t.pair[2 * (q / halves) + q % halves] = it.pair;
+        maxn = std::max(maxn, it.n);
       }
-      t.ncols = round_up(std::max(maxn, 1), kBlock);
-      tasks.push_back(t);
+      t.ncols = round_up(maxn, kBlock);
+      bym[md].push_back(t);
     }
   }
-  // Longest first (by estimated cost) so the tail is short tasks; only this
-  // group's tasks (earlier groups belong to other launches).
-  std::stable_sort(tasks.begin() + first, tasks.end(), [&](const Task &a, const Task &b) {
-    return (double)a.ncols * step_cost(prec, Ps[a.mode], segs[a.mode]) >
-           (double)b.ncols * step_cost(prec, Ps[b.mode], segs[b.mode]);
-  });
+  // three lists, each longest-first: merge by estimated cost
+  size_t ix[3] = {0, 0, 0};
+  auto cost = [&](const Task &t) { return (double)t.ncols * step_cost(prec, Ps[t.mode], segs[t.mode]); };
+  tasks.reserve(tasks.size() + bym[0].size() + bym[1].size() + bym[2].size());
+  for (;;) {
+    int pick = -1;
+    double best = -1;
+    for (int md = 0; md < 3; ++md)
+      if (ix[md] < bym[md].size() && cost(bym[md][ix[md]]) > best) { best = cost(bym[md][ix[md]]); pick = md; }
+    if (pick < 0) break;
+    tasks.push_back(bym[pick][ix[pick]++]);
+  }
 }
 
 // Smallest shared menu whose rows per chunk (64*seg64) cover m, or the largest.
@@ -355,17 +368,25 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   for (const auto &it : in.items) count[it.query]++;
   std::vector<std::vector<PlanItem>> by_query(in.n_queries);
   std::vector<PlanItem> per_pair;
-  for (const auto &it : in.items) {
-    const bool shared = lazy || opt.force_kernel == 1 ||
-                        (opt.force_kernel == 0 && count[it.query] >= 32);
-    if (shared) by_query[it.query].push_back(it);
-    else per_pair.push_back(it);
+  auto wants_shared = [&](int q) {
+    return lazy || opt.force_kernel == 1 || (opt.force_kernel == 0 && count[q] >= 32);
+  };
+  int only_query = -1;   // every item uses one query that runs shared: no copy
+  if (!in.items.empty() && count[in.items[0].query] == (int)in.items.size() &&
+      wants_shared(in.items[0].query))
+    only_query = in.items[0].query;
+  if (only_query < 0) {
+    for (const auto &it : in.items) {
+      if (wants_shared(it.query)) by_query[it.query].push_back(it);
+      else per_pair.push_back(it);
+    }
   }
   const int waves_total = num_cus * 16;
   int64_t bnd_elems = 0;
   // ---- shared-query launches
   for (int q = 0; q < in.n_queries; ++q) {
-    if (by_query[q].empty()) continue;
+    if (q != only_query && by_query[q].empty()) continue;
+    const std::vector<PlanItem> &group = q == only_query ? in.items : by_query[q];
     const int m = in.m_of_query[q];
     int fl = opt.force_lanes;
     const int menu = pick_shared_menu(m, fl ? fl : 64, opt.force_seglen);
@@ -381,7 +402,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
     L.query = q;
     L.task_begin = (int)tasks.size();
     int mc[3] = {0, 0, 0};
-    plan_shared(by_query[q], prec, menu, waves_total, fl, tasks, mc);
+    plan_shared(group, prec, menu, waves_total, fl, tasks, mc);
     L.task_end = (int)tasks.size();
     for (int k = 0; k < 3; ++k) stats.lanes_used[k] += mc[k];
     const int segs[3] = {mm.seg16, mm.seg32, mm.seg64};
@@ -467,7 +488,12 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   for (auto &t : tasks) { t.stream_off = stream_bytes; stream_bytes += (int64_t)t.ncols / kBlock * kStreamBlockBytes; }
   stream_bytes += 4 * kStreamBlockBytes;
   // Every access a kernel makes is derived from these fields: refuse to
-  // launch anything the kernels' bounds assumptions do not cover.
+  // launch anything the kernels' bounds assumptions do not cover.  (PairInfo
+  // index == result index for every path of this library.)
+  const int n_pairs_total = in.d_pairs ? in.n_pairs : (int)in.pairs.size();
+  std::vector<int> nlen(std::max(n_pairs_total, 0), -1);
+  for (const auto &it : in.items)
+    if (it.pair >= 0 && it.pair < n_pairs_total) nlen[it.pair] = it.n;
   for (const auto &L : launches) {
     const bool chunked = L.nchunks > 1;
     for (int t = L.task_begin; t < L.task_end; ++t) {
@@ -479,10 +505,9 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
       if (L.shared) ok = ok && tk.mode >= 0 && tk.mode < 3 && tk.layout == layout_for(16 << tk.mode);
       for (int s2 = 0; s2 < kSlots; ++s2) {
         const int pid = tk.pair[s2];
-        ok = ok && pid >= -1 && pid < (int)in.pairs.size();
+        ok = ok && pid >= -1 && pid < n_pairs_total;
         if (pid >= 0) {
-          ok = ok && in.pairs[pid].n <= tk.ncols && in.pairs[pid].out >= 0 &&
-               in.pairs[pid].out < n_results;
+          ok = ok && nlen[pid] >= 0 && nlen[pid] <= tk.ncols && pid < n_results;
           if (prec == PREC_I32) ok = ok && (s2 & 1) == 0;
         }
       }
@@ -522,10 +547,11 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
     HIPCHK(hipMemcpyAsync(ws.pairs.p, hs + o_pairs, o_mat - o_pairs, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ws.matrix.p, hs + o_mat, o_misc - o_mat, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ws.misc.p, hs + o_misc, misc_bytes, hipMemcpyHostToDevice, st));
-  if (reset_results) HIPCHK(hipMemsetAsync(ws.results.p, 0, std::max(1, n_results) * sizeof(DevResult), st));
+  if (reset_results) HIPCHK(launch_init_results(n_results, ws.results.as<DevResult>(), st));
   if (bnd_elems > 0) HIPCHK(hipMemsetAsync(ws.bnd.p, 0, bnd_half * sizeof(uint32_t), st));
   const int sent = sc.alpha;
-  HIPCHK(launch_build_streams(ws.tasks.as<Task>(), (int)tasks.size(), ws.pairs.as<PairInfo>(),
+  HIPCHK(launch_build_streams(ws.tasks.as<Task>(), (int)tasks.size(),
+                              in.d_pairs ? in.d_pairs : ws.pairs.as<PairInfo>(),
                               in.d_rres, ws.streams.as<uint8_t>(), sent, st));
   unsigned long long *d_stats = (unsigned long long *)ws.misc.p;
   int *d_counters = (int *)((char *)ws.misc.p + 32);
@@ -539,7 +565,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
     std::memset(&a, 0, sizeof(a));
     a.tasks = ws.tasks.as<Task>() + L.task_begin;
     a.ntasks = L.task_end - L.task_begin;
-    a.pairs = ws.pairs.as<PairInfo>();
+    a.pairs = in.d_pairs ? in.d_pairs : ws.pairs.as<PairInfo>();
     a.streams = ws.streams.as<uint8_t>();
     a.query_res = in.d_qres;
     a.alpha = sc.alpha;
@@ -597,27 +623,24 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
   if (rc) return rc;
   const double t_res0 = now_ms();
   int rerun = 0;
+  static_assert(sizeof(DevResult) == sizeof(sw_result), "result layout");
   if (!in.items.empty()) {
-    if ((rc = ws.staging.ensure((size_t)n_pairs * sizeof(DevResult)))) return rc;
-    DevResult *hr = ws.staging.as<DevResult>();
-    HIPCHK(hipMemcpyAsync(hr, ws.results.p, (size_t)n_pairs * sizeof(DevResult),
+    // device results have the sw_result layout: copy straight into out
+    HIPCHK(hipMemcpyAsync(out, ws.results.p, (size_t)n_pairs * sizeof(DevResult),
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     std::vector<PlanItem> again;
-    for (const auto &it : in.items) {
-      const DevResult &r = hr[it.pair];
-      if (prec == PREC_I16X2 && (r.flags & kFlagNeedsI32)) { again.push_back(it); continue; }
-      out[it.pair].score = r.score;
-      out[it.pair].query_end = r.qend;
-      out[it.pair].ref_end = r.rend;
-      out[it.pair].flags = 0;
+    if (prec == PREC_I16X2) {
+      for (const auto &it : in.items)
+        if (out[it.pair].flags & kFlagNeedsI32) again.push_back(it);
     }
     if (!again.empty()) {
       rerun = (int)again.size();
       ExecInput in2;
       in2.d_qres = in.d_qres;
       in2.d_rres = in.d_rres;
-      in2.pairs = in.pairs;
+      in2.d_pairs = in.d_pairs ? in.d_pairs : ws.pairs.as<PairInfo>();
+      in2.n_pairs = in.d_pairs ? in.n_pairs : (int)in.pairs.size();
       in2.items = again;
       in2.n_queries = in.n_queries;
       in2.q_off_of_query = in.q_off_of_query;
@@ -628,7 +651,7 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
       rc = execute(in2, sc, PREC_I32, o2, ws, n_pairs, st, e0, e1, num_cus, es, false);
       if (rc) return rc;
       if ((rc = ws.staging.ensure((size_t)n_pairs * sizeof(DevResult)))) return rc;
-      hr = ws.staging.as<DevResult>();
+      DevResult *hr = ws.staging.as<DevResult>();
       HIPCHK(hipMemcpyAsync(hr, ws.results.p, (size_t)n_pairs * sizeof(DevResult),
                             hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));

@@ -54,7 +54,9 @@ struct PlanItem {
 struct ExecInput {
   const uint8_t *d_qres = nullptr;   // device
   const uint8_t *d_rres = nullptr;   // device
-  std::vector<swk::PairInfo> pairs;  // host copy, index = pair id
+  std::vector<swk::PairInfo> pairs;  // host PairInfo (index = pair id), or empty when
+  const swk::PairInfo *d_pairs = nullptr;  // ... they are already on the device
+  int n_pairs = 0;                   // size of the PairInfo array
   std::vector<PlanItem> items;       // pairs with m > 0 and n > 0
   int n_queries = 0;
   std::vector<int64_t> q_off_of_query;  // query start offsets
@@ -82,10 +84,11 @@ double now_ms();
 // Work buffers used by one execution (the batch path owns one; the request
 // server one per in-flight batch).
 struct Workspace {
-  DevBuf tasks, pairs, streams, results, bnd, misc, matrix;
+  DevBuf tasks, pairs, streams, results, bnd, misc, matrix, offs;
   HostBuf staging;
   void release() {
-    for (DevBuf *b : {&tasks, &pairs, &streams, &results, &bnd, &misc, &matrix}) b->release();
+    for (DevBuf *b : {&tasks, &pairs, &streams, &results, &bnd, &misc, &matrix, &offs})
+      b->release();
     staging.release();
   }
 };
