@@ -151,35 +151,39 @@ __device__ __forceinline__ uint32_t shift1(uint32_t x, const LaneCtx &L, uint32_
 
 // ---------------------------------------------------------------- per-lane state
 
-// End cell without storing a column of H_diag: G is the sub-group's running
-// maximum over finished columns.  A cell whose H_diag does not exceed G lies
-// in a later column than a cell scoring at least as much, so it is never the
-// lexicographically smallest best cell.  When a lane's column maximum c
-// exceeds G, every E and F value feeding its rows in this column is at most
-// (a value <= G) minus GapOpen, and every in-lane F comes from rows scoring
-// below c; hence the first row whose new H reaches c is the first row whose
-// H_diag equals c.  The lane records (c, column, row); the final reduction
-// over lanes picks the highest score, then the smallest column, then row.
+// End cell.  Each lane keeps its own running maximum G of H_diag (per half)
+// and, whenever a half improves it, the column index and a copy of that
+// column's new H values (before any cross-lane correction).  At the end the
+// row is the first row of the copy whose H reaches G.
+//
+// Why this is exact for the cell that matters: let X be the lexicographically
+// smallest (column, row) cell holding the overall maximum S, in lane l and
+// column c.  No cell of an earlier column scores S or more (it would precede
+// X), so lane l improves at column c and never again, and its copy is column
+// c.  Every E and F entering lane l's rows in column c comes from cells of
+// earlier columns (all below S) or from rows of lane l above X (all below S)
+// minus a non-negative gap cost, so the first row whose new H reaches S is
+// X's row.  Other lanes' records may point at a wrong row, but they score
+// below S, or equal S in a later column or in a later lane of the same
+// column, so they never win the final (score, column, row) reduction.
 template <int SEG>
 struct State {
   uint32_t H[SEG];    // H of the previous column, before the cross-lane fix-up
   uint32_t E[SEG];
+  uint32_t snap[SEG]; // H of the column where this lane last improved (per half)
   uint32_t Fscan;     // vertical-gap value entering this lane's first row
-  uint32_t G;         // sub-group record of H_diag over finished columns (per half)
-  uint32_t rs;        // this lane's recorded score (per half)
-  int rc[2], rr[2];   // recorded column and row (per half)
-  uint32_t events;    // record branches taken (statistics)
+  uint32_t G;         // this lane's running maximum of H_diag (per half)
+  int rc[2];          // column of the last improvement (per half), or INT_MAX
+  uint32_t events;    // improvement branches taken (statistics)
 };
 
 template <int SEG>
 __device__ __forceinline__ void state_reset(State<SEG> &st, uint32_t g0) {
 #pragma unroll
-  for (int j = 0; j < SEG; ++j) { st.H[j] = 0; st.E[j] = 0; }
+  for (int j = 0; j < SEG; ++j) { st.H[j] = 0; st.E[j] = 0; st.snap[j] = 0; }
   st.Fscan = 0;
   st.G = g0;
-  st.rs = 0;
   st.rc[0] = st.rc[1] = 0x7fffffff;
-  st.rr[0] = st.rr[1] = 0x7fffffff;
   st.events = 0;
 }
 
@@ -221,66 +225,31 @@ struct ProfLds {
   }
 };
 
-// Rows of a column are split into groups of kGroup; the column step keeps
-// the maximum of H_diag of each group (the same number of max operations as
-// one running maximum), so finding the end row only scans one group.
-constexpr int kGroup = 8;
-template <int SEG> struct Groups { static constexpr int n = (SEG + kGroup - 1) / kGroup; };
-
-// Maximum over the lanes of each sub-group (all lanes receive it).
-template <class O, int PMAX>
-__device__ __forceinline__ uint32_t subgroup_max(uint32_t x, const LaneCtx &L) {
-  x = O::vmax(x, dpp<0xB1>(x));        // quad_perm [1,0,3,2]
-  x = O::vmax(x, dpp<0x4E>(x));        // quad_perm [2,3,0,1]
-  x = O::vmax(x, dpp<0x124>(x));       // row_ror:4
-  x = O::vmax(x, dpp<0x128>(x));       // row_ror:8
-  if constexpr (PMAX >= 32) {
-    const uint32_t o = (uint32_t)__shfl_xor((int)x, 16);
-    if (L.P >= 32) x = O::vmax(x, o);
+// Per-half mask: 0xffff in each 16-bit half where a != b (packed), or all
+// ones where a != b (int32).
+template <class O>
+__device__ __forceinline__ uint32_t diff_mask(uint32_t a, uint32_t b) {
+  if constexpr (O::kHalves == 2) {
+    const uint32_t x = a ^ b;
+    const uint32_t one = bc<uint32_t>(__builtin_elementwise_min(bc<u16x2>(x), bc<u16x2>(0x00010001u)));
+    return one * 0xffffu;   // 0x0001 -> 0xffff per half; no carry between halves
+  } else {
+    return a != b ? 0xffffffffu : 0u;
   }
-  if constexpr (PMAX >= 64) {
-    const uint32_t o = (uint32_t)__shfl_xor((int)x, 32);
-    if (L.P >= 64) x = O::vmax(x, o);
-  }
-  return x;
 }
 
-// New records of the running maximum (rare): see State.  H[] must hold this
-// column's values before any cross-lane correction; gm[] the group maxima of
-// this column's H_diag.
-template <class O, int SEG, int PMAX>
-__device__ __forceinline__ void record(State<SEG> &st, const LaneCtx &L,
-                                       const uint32_t (&gm)[Groups<SEG>::n], uint32_t cmax,
-                                       int i) {
-  constexpr int NG = Groups<SEG>::n;
+// Column end: lanes whose running maximum improves copy this column's H.
+template <class O, int SEG>
+__device__ __forceinline__ void record(State<SEG> &st, uint32_t cmax, int i) {
   const uint32_t nb = O::vmax(st.G, cmax);
   if (__any(nb != st.G)) {
     ++st.events;
-    const uint32_t g = subgroup_max<O, PMAX>(nb, L);
+    const uint32_t m = diff_mask<O>(nb, st.G);
 #pragma unroll
-    for (int h = 0; h < O::kHalves; ++h) {
-      const int cm = O::get(cmax, h);
-      if (cm > O::get(st.G, h)) {
-        int gsel = NG - 1;
-#pragma unroll
-        for (int q = NG - 1; q >= 0; --q)
-          if (O::get(gm[q], h) == cm) gsel = q;
-        int jj = SEG - 1;
-#pragma unroll
-        for (int q = 0; q < NG; ++q) {
-          if (q == gsel) {
-            const int hi = (q + 1) * kGroup < SEG ? (q + 1) * kGroup : SEG;
-#pragma unroll
-            for (int j = hi - 1; j >= q * kGroup; --j)
-              if (O::get(st.H[j], h) >= cm) jj = j;
-          }
-        }
-        st.rc[h] = i;
-        st.rr[h] = L.l * SEG + jj;
-        st.rs = O::set(st.rs, h, cm);
-      }
-    }
-    st.G = g;
+    for (int j = 0; j < SEG; ++j) st.snap[j] = (st.H[j] & m) | (st.snap[j] & ~m);
+    if (m & 0xffffu) st.rc[0] = i;
+    if (O::kHalves == 2 && (m >> 16)) st.rc[1] = i;
+    st.G = nb;
   }
 }
 
@@ -291,8 +260,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
                                        const Prof &pf, uint32_t blo, uint32_t bhi,
                                        uint32_t hb_in, uint32_t fb_in, uint32_t &hb_out,
                                        uint32_t &fb_out, int i, uint32_t &lazy_steps) {
-  constexpr int NG = Groups<SEG>::n;
-  uint32_t gm[NG];
+  uint32_t cmax;
   if constexpr (!LAZY) {
     uint32_t Fj = st.Fscan;
     const uint32_t hlast = O::vmax(st.H[SEG - 1], O::usub(Fj, pr.wlast));
@@ -303,7 +271,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     for (int j = 0; j < SEG; ++j) {
       const uint32_t p = pf.load(blo, bhi, j);
       const uint32_t hd = O::hadd(Hin, p);
-      gm[j / kGroup] = j % kGroup == 0 ? hd : O::vmax(gm[j / kGroup], hd);
+      cmax = j == 0 ? hd : O::vmax(cmax, hd);
       const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
       const uint32_t hold = st.H[j];
       st.H[j] = h;
@@ -326,10 +294,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     if constexpr (PMAX >= 64) G = O::vmax(G, O::usub(dpp<kRowBcast31, 0xc, false>(G), L.w32));
     fb_out = G;
     st.Fscan = shift1<PMAX, CHUNKED>(G, L, fb_in);
-    uint32_t cmax = gm[0];
-#pragma unroll
-    for (int q = 1; q < NG; ++q) cmax = O::vmax(cmax, gm[q]);
-    record<O, SEG, PMAX>(st, L, gm, cmax, i);
+    record<O, SEG>(st, cmax, i);
   } else {
     // Algorithm 1: H[] already holds corrected values.
     hb_out = st.H[SEG - 1];
@@ -339,7 +304,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     for (int j = 0; j < SEG; ++j) {
       const uint32_t p = pf.load(blo, bhi, j);
       const uint32_t hd = O::hadd(Hin, p);
-      gm[j / kGroup] = j % kGroup == 0 ? hd : O::vmax(gm[j / kGroup], hd);
+      cmax = j == 0 ? hd : O::vmax(cmax, hd);
       const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
       Hin = st.H[j];
       st.H[j] = h;
@@ -347,10 +312,7 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
       st.E[j] = O::vmax(O::usub(st.E[j], pr.ge), t);
       F = O::vmax(O::usub(F, pr.ge), t);
     }
-    uint32_t cmax = gm[0];
-#pragma unroll
-    for (int q = 1; q < NG; ++q) cmax = O::vmax(cmax, gm[q]);
-    record<O, SEG, PMAX>(st, L, gm, cmax, i);
+    record<O, SEG>(st, cmax, i);
     // Lazy-F loop: propagate the vertical gap across lanes until, in every
     // lane at once, the propagated value can no longer exceed what the first
     // pass already derived (F <= max(H_before - go, 0)); then stop.
@@ -478,9 +440,18 @@ __device__ __forceinline__ void finish(const State<SEG> &st, const LaneCtx &L, c
                                        Prev &prev, int sat_cap) {
 #pragma unroll
   for (int h = 0; h < O::kHalves; ++h) {
-    int s = O::get(st.rs, h);
-    int c = s > 0 ? st.rc[h] : 0x7fffffff;
-    int r = s > 0 ? st.rr[h] + row_base : 0x7fffffff;
+    int s = st.rc[h] != 0x7fffffff ? O::get(st.G, h) : 0;
+    int c = 0x7fffffff, r = 0x7fffffff;
+    if (s > 0) {
+      int jj = SEG - 1;
+#pragma unroll
+      for (int j = SEG - 1; j >= 0; --j)
+        if (O::get(st.snap[j], h) >= s) jj = j;
+      c = st.rc[h];
+      r = L.l * SEG + jj + row_base;
+    } else {
+      s = 0;
+    }
     for (int d = 1; d < kWave; d <<= 1) {
       const int s2 = __shfl_xor(s, d), c2 = __shfl_xor(c, d), r2 = __shfl_xor(r, d);
       if (d < L.P && better(s2, c2, r2, s, c, r)) { s = s2; c = c2; r = r2; }

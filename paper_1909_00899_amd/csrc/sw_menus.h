@@ -5,9 +5,12 @@
 namespace swk {
 
 // Shared-query kernel menus: rows per lane for the 16-, 32- and 64-lane
-// modes; menu k covers 64*seg64 query rows in every mode.
+// modes; menu k covers 64*seg64 query rows in every mode (0 = mode absent).
+// Modes with more than 16 rows per lane are left out (0): they need more than
+// 128 VGPRs with the end-cell copy, and the narrow modes they would give are
+// slower than the 32-lane mode of the same menu.
 constexpr SharedMenu kSharedMenus[] = {
-    {4, 2, 1}, {8, 4, 2}, {12, 6, 3}, {16, 8, 4}, {24, 12, 6}, {32, 16, 8},
+    {4, 2, 1}, {8, 4, 2}, {12, 6, 3}, {16, 8, 4}, {0, 12, 6}, {0, 16, 8},
 };
 constexpr int kNumSharedMenus = sizeof(kSharedMenus) / sizeof(kSharedMenus[0]);
 

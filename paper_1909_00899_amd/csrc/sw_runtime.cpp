@@ -299,9 +299,19 @@ static int pick_shared_menu(int m, int force_lanes, int force_seg) {
     }
     return -1;
   }
-  for (int k = 0; k < n; ++k)
-    if (64 * shared_menu(k).seg64 >= m) return k;
-  return n - 1;
+  // the smallest menu covering m in one chunk that has the forced width, else
+  // the largest one that has it (the query is then chunked)
+  auto has = [&](const SharedMenu &mm) {
+    return force_lanes == 16 ? mm.seg16 > 0 : (force_lanes == 32 ? mm.seg32 > 0 : mm.seg64 > 0);
+  };
+  int last = -1;
+  for (int k = 0; k < n; ++k) {
+    const SharedMenu mm = shared_menu(k);
+    if (!has(mm)) continue;
+    last = k;
+    if (64 * mm.seg64 >= m) return k;
+  }
+  return last;
 }
 
 
