@@ -28,6 +28,28 @@ PEAK_I16X2_TOPS = 2 * PEAK_I32_TOPS
 OPS_PER_CELL = 11   # Algorithm 6 inner loop: 1 add, 6 max, 4 sub
 
 
+def _csrc_sha256() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1909_00899_amd", "csrc", "*"))):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def _measured_traffic():
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_shared_kernel_protein_search.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    return d["hbm_bytes_per_launch"] if d.get("csrc_sha256") == _csrc_sha256() else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,7 +107,8 @@ def main():
                    "pairs": w.n_pairs, "cells": cells, "query_len": 512},
         "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3),
                      "peak": round(PEAK_I16X2_TOPS, 2), "unit": "Tops/s",
-                     "frac": round(achieved_tops / PEAK_I16X2_TOPS, 4), "traffic": None,
+                     "frac": round(achieved_tops / PEAK_I16X2_TOPS, 4),
+                     "traffic": _measured_traffic(),
                      "ops_per_cell": OPS_PER_CELL, "kernel_ms": round(kms, 4),
                      "kernel_gcups": round(cells / (kms / 1e3) / 1e9, 2)},
         "stats": {k: out.stats[k] for k in ("n_rerun", "n_launches", "lanes_used",
