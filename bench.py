@@ -58,11 +58,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--n-refs", type=int, default=100_000)
+    ap.add_argument("--workload", default="protein_search",
+                    choices=["protein_search", "dna_pairs", "long_queries", "serving"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "long_queries":
+        return bench_long_queries(args)
+    if args.workload == "serving":
+        return bench_serving(args)
+    if args.workload == "dna_pairs":
+        return bench_dna(args)
 
     import torch
     from paper_1909_00899_amd import api, workloads as W
@@ -148,6 +156,165 @@ def main():
                                          "scalar int64 C oracle, pthreads" % (n_s, sub.cells())}
         rec["parity_sample"] = bool(np.array_equal(out.results[:n_s, :3], want))
     print(json.dumps(rec))
+
+
+def _device_batch(w):
+    import torch
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    d = [t(w.query_res, torch.uint8), t(w.query_off, torch.int64), t(w.ref_res, torch.uint8),
+         t(w.ref_off, torch.int64), t(w.pair_ref, torch.int32)]
+    pq = None if w.pair_query is None else t(w.pair_query, torch.int32)
+    torch.cuda.synchronize()
+    return d, pq
+
+
+def bench_dna(args):
+    """Batched DNA pairs: mutated 150 bp reads vs their 300-600 bp windows."""
+    import torch
+    from paper_1909_00899_amd import api, workloads as W
+    api.load()
+    api.sw_init(0)
+    n = min(args.n_refs * 10, 1_000_000)
+    w = W.dna_pairs(n_pairs=n)
+    d, pq = _device_batch(w)
+    step = lambda: api.sw_align_batch(*d, w.matrix, w.gap_open, w.gap_extend, pair_query=pq)  # noqa
+    for _ in range(args.warmup):
+        out = step()
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+        kms.append(out.stats["kernel_ms"])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    cells = w.cells()
+    km = float(np.mean(kms))
+    ach = cells * OPS_PER_CELL / (km / 1e3) / 1e12
+    print(json.dumps({"metric": METRIC, "value": round(cells / wall / 1e9, 2), "unit": "GCUPS",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "i16x2", "data": "synthetic",
+                      "config": {"workload": "dna_pairs: %d mutated 150 bp reads vs 300-600 bp "
+                                             "windows, +1/-4, GapOpen 6, GapExtend 1" % n,
+                                 "pairs": n, "cells": cells},
+                      "roofline": {"bound": "alu", "achieved": round(ach, 3),
+                                   "peak": round(PEAK_I16X2_TOPS, 2), "unit": "Tops/s",
+                                   "frac": round(ach / PEAK_I16X2_TOPS, 4), "traffic": None,
+                                   "kernel_ms": round(km, 3),
+                                   "kernel_gcups": round(cells / (km / 1e3) / 1e9, 1)},
+                      "stats": {k: out.stats[k] for k in ("n_rerun", "lanes_used", "seglen_max",
+                                                          "prep_ms", "plan_ms", "total_ms")}}))
+
+
+def bench_long_queries(args):
+    """Scan vs lazy-F (int32) on long i.i.d. and low-complexity queries.
+
+    Per class (query kind x reference kind) two queries of that kind run
+    against the 5k references of that kind (10k pairs); the full workload is
+    64 queries x 10k references (1.3e13 cells).
+    """
+    import torch
+    from paper_1909_00899_amd import api, workloads as W
+    api.load()
+    api.sw_init(0)
+    full = W.long_queries()
+    nq = full.query_off.size - 1
+    nr = full.ref_off.size - 1
+    half = nr // 2
+    rows = {}
+    for qkind, qsel in (("iid", (0, 1)), ("runs", (nq // 2, nq // 2 + 1))):
+        for rkind, (lo, hi) in (("iid", (0, half)), ("runs", (half, nr))):
+            idx = [q * nr + r for q in qsel for r in range(lo, hi)]
+            sub = full.subset(np.array(idx))
+            d, pq = _device_batch(sub)
+            res = {}
+            for alg, name in ((api.SW_ALG_SCAN, "scan"), (api.SW_ALG_LAZYF, "lazyf")):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = api.sw_align_batch(*d, sub.matrix, sub.gap_open, sub.gap_extend,
+                                         pair_query=pq, precision=api.SW_PREC_I32, algorithm=alg)
+                wall = time.perf_counter() - t0
+                st = out.stats
+                res[name] = {"gcups": round(sub.cells() / wall / 1e9, 1),
+                             "kernel_gcups": round(sub.cells() / (st["kernel_ms"] / 1e3) / 1e9, 1),
+                             "columns": st["columns"], "lazyf_steps": st["lazyf_steps"],
+                             "seglen": st["seglen_max"], "results": out.results}
+            lz = res["lazyf"]
+            passes = lz["lazyf_steps"] / max(1, lz["columns"]) / max(1, lz["seglen"])
+            rows["query_%s/ref_%s" % (qkind, rkind)] = {
+                "pairs": sub.n_pairs, "cells": sub.cells(),
+                "query_lens": [int(full.query_off[q + 1] - full.query_off[q]) for q in qsel],
+                "scan_gcups": res["scan"]["gcups"], "lazyf_gcups": lz["gcups"],
+                "scan_kernel_gcups": res["scan"]["kernel_gcups"],
+                "lazyf_kernel_gcups": lz["kernel_gcups"],
+                "lazyf_passes_per_column": round(passes, 3),
+                "scan_equals_lazyf": bool(np.array_equal(res["scan"]["results"], lz["results"]))}
+    tot_scan = sum(r["cells"] for r in rows.values()) / sum(
+        r["cells"] / r["scan_gcups"] for r in rows.values())
+    print(json.dumps({"metric": METRIC, "value": round(tot_scan, 2), "unit": "GCUPS", "n_gpus": 1,
+                      "higher_is_better": True, "dtype": "i32", "data": "synthetic",
+                      "config": {"workload": "long_queries: per class 2 queries (5k-35k, i.i.d. "
+                                             "or poly-residue runs) x 5k refs (200-2000)"},
+                      "by_class": rows}))
+
+
+def bench_serving(args):
+    """Continuous-batching server: Poisson arrivals at a swept rate, p50/p99."""
+    from paper_1909_00899_amd import api, workloads as W
+    api.load()
+    api.sw_init(0)
+    db = W.serving_db()
+    scor = [(W.protein_matrix(), 11, 1), (W.dna_matrix(), 6, 1)]
+    rates = [1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000]
+    out_rows = []
+    with api.Server(db.ref_res, db.ref_off, scor, hbm_budget_bytes=8 << 30, n_streams=4,
+                    max_batch=4096) as srv:
+        for rate in rates:
+            n = int(min(20000, max(2000, rate * 3)))
+            req = W.serving_requests(db, rate, n, seed=rate)
+            sid = req.is_dna.astype(np.int32)
+            t0 = time.perf_counter()
+            res, ts = srv.replay(req.query_res, req.query_off, req.ref_id, sid, req.arrival_s)
+            wall = time.perf_counter() - t0
+            lat = (ts[:, 2] - ts[:, 0]) / 1e6
+            warm = req.arrival_s >= min(1.0, req.arrival_s[-1] / 4)
+            ql = np.diff(req.query_off)
+            rl = np.diff(db.ref_off)[req.ref_id]
+            cells = float(np.sum(ql.astype(np.float64) * rl))
+            out_rows.append({"rate_per_s": rate, "requests": n,
+                             "p50_ms": round(float(np.percentile(lat[warm], 50)), 3),
+                             "p99_ms": round(float(np.percentile(lat[warm], 99)), 3),
+                             "served_gcups": round(cells / wall / 1e9, 2),
+                             "achieved_rate": round(n / wall, 1)})
+    # offline: the same requests of the last rate as two batches (one per scoring)
+    req = W.serving_requests(db, rates[-1], out_rows[-1]["requests"], seed=rates[-1])
+    fam = []
+    for dna in (False, True):
+        sel = np.nonzero(req.is_dna == dna)[0]
+        qs = [req.query_res[req.query_off[k]:req.query_off[k + 1]] for k in sel]
+        qoff = np.zeros(sel.size + 1, dtype=np.int64)
+        np.cumsum([q.size for q in qs], out=qoff[1:])
+        r0 = 0 if not dna else db.n_protein
+        r1 = db.n_protein if not dna else db.n_protein + db.n_dna
+        rres = db.ref_res[db.ref_off[r0]:db.ref_off[r1]]
+        roff = db.ref_off[r0:r1 + 1] - db.ref_off[r0]
+        fam.append((np.concatenate(qs), qoff, rres, roff, (req.ref_id[sel] - r0).astype(np.int32),
+                    np.arange(sel.size, dtype=np.int32), scor[1 if dna else 0]))
+    t0 = time.perf_counter()
+    for qres, qoff, rres, roff, pr, pq, (M, go, ge) in fam:
+        api.sw_align_batch(qres, qoff, rres, roff, pr, M, go, ge, pair_query=pq)
+    off_wall = time.perf_counter() - t0
+    ql = np.diff(req.query_off)
+    rl = np.diff(db.ref_off)[req.ref_id]
+    off_gcups = float(np.sum(ql.astype(np.float64) * rl)) / off_wall / 1e9
+    print(json.dumps({"metric": METRIC, "value": out_rows[-1]["p99_ms"], "unit": "ms p99",
+                      "n_gpus": 1, "higher_is_better": False, "dtype": "i16x2",
+                      "data": "synthetic",
+                      "config": {"workload": "serving: 25k protein + 25k DNA resident refs, "
+                                             "Poisson arrivals, one reference per request"},
+                      "sweep": out_rows, "offline_gcups": round(off_gcups, 2)}))
 
 
 if __name__ == "__main__":

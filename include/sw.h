@@ -116,6 +116,10 @@ int sw_align(const uint8_t *query, int32_t query_len,
  * every H, E and F value is bounded by the running maximum); the recomputed
  * result carries SW_FLAG_SATURATED.  SW_PREC_I32 runs int32 only.
  *
+ * Every residue in query_res[0 .. query_off[n_queries]) and
+ * ref_res[0 .. ref_off[n_refs]) must be below alphabet_size (SW_EINVAL
+ * otherwise), whether or not a pair uses it.
+ *
  * device_resident: 0 => the six sequence/offset/pair pointers are host
  * memory; 1 => they are device memory on the library's device (e.g. torch
  * tensors) and must stay valid until the call returns.  The call is
