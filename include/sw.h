@@ -154,12 +154,20 @@ typedef struct {
                                     query is split into chunks of lanes*seglen rows) */
     int32_t force_kernel;        /* 0 = planner's choice; 1 = shared-query kernel;
                                     2 = per-pair kernel                              */
-    int32_t mixed_layout;        /* per-pair kernel: 1 = pack 32- and 16-lane
-                                    sub-groups into one wavefront where lengths allow */
+    int32_t mixed_layout;        /* per-pair kernel: 0 = planner's choice (mixed
+                                    unless it models over 15% more work, or the
+                                    autotuner's table decides); 1 = mixed: one
+                                    rows-per-lane for the batch and 16-, 32- and
+                                    64-lane sub-groups inside a wavefront, each
+                                    pair on the narrowest that holds its query;
+                                    2 = one sub-group width per launch          */
     int32_t int16_cap;           /* 0 = 32767; else a lower saturation threshold for
                                     the int16 pass (tests force the int32 rerun)     */
-    int32_t use_graph;           /* 1 = capture the launches into a hipGraph and
-                                    replay it                                       */
+    int32_t use_graph;           /* 1 = run the device work of the call (uploads,
+                                    stream building, alignment kernels) as a
+                                    hipGraph: captured on first use, replayed when
+                                    a later call has identical parameters; then
+                                    kernel_ms spans the whole graph             */
     int32_t reserved[9];
 } sw_options;
 
@@ -180,11 +188,60 @@ typedef struct {
     double finish_ms;            /* waiting for the device, results, int32 reruns    */
     int64_t record_events;       /* column steps in which some alignment of a
                                     wavefront set a new running maximum         */
-    int32_t reserved[8];
+    int32_t graph_hits;          /* use_graph: executions replayed from a cached
+                                    graph (no capture)                          */
+    int32_t reserved[7];
 } sw_stats;
 
 int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options *opt,
                       sw_result *out, sw_stats *stats);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner.
+ *
+ * The planner picks, for each group of pairs, the lanes per alignment (16, 32
+ * or 64) and the rows per lane (segLen) from a cost model of the column step
+ * (VALU instructions per cell plus the log2(lanes) scan steps per column,
+ * amortised over the alignments a wavefront carries).  The autotuner replaces
+ * that model by measurement: it runs candidate shapes on the caller's batch
+ * (or a seeded sample of it), times the alignment kernels with HIP events and
+ * installs the fastest shape per (kernel kind, precision, alphabet size,
+ * query-length range) in a process-wide table that every later call consults
+ * when no option forces a shape.  The table can be read out and installed
+ * again (a cache across processes).
+ * ------------------------------------------------------------------------- */
+enum { SW_TUNE_SHARED = 0,       /* one query against many references            */
+       SW_TUNE_PAIR = 1 };       /* a query per pair (per-pair kernel)            */
+
+typedef struct {
+    int32_t kind;                /* SW_TUNE_*                                      */
+    int32_t precision;           /* SW_PREC_AUTO (int16x2 lanes) or SW_PREC_I32    */
+    int32_t alphabet_size;       /* scorings this entry applies to                 */
+    int32_t m_lo, m_hi;          /* query lengths covered, inclusive               */
+    int32_t lanes;               /* 16, 32 or 64; SW_TUNE_SHARED also 0 = the
+                                    planner's per-pair mix of widths              */
+    int32_t seglen;              /* rows per lane (SW_TUNE_SHARED with lanes 0:
+                                    rows per lane of the 64-lane mode)            */
+    int32_t mixed;               /* SW_TUNE_PAIR: 1 = mixed layouts at this seglen
+                                    for every per-pair query in [m_lo, m_hi]      */
+    double gcups;                /* measured kernel GCUPS of the winner            */
+    double model_gcups;          /* measured GCUPS of the cost model's own choice  */
+} sw_tune_entry;
+
+/* Tunes the shapes for the pairs of `b` (same arguments as sw_align_batch) and
+ * installs the winners.  sample_cells > 0 caps the cells timed per group (a
+ * seeded subset of the group's pairs; 0 = 5e10).  Writes up to `cap` entries to
+ * `out` (may be NULL) and their number to *n_out (may be NULL).  Results of
+ * later calls are unchanged by tuning: only their speed. */
+int sw_autotune(const sw_batch *b, const sw_scoring *sc, int64_t sample_cells,
+                sw_tune_entry *out, int32_t cap, int32_t *n_out);
+
+/* Replaces the tuning table (n = 0 clears it, so the cost model decides).
+ * SW_EINVAL for entries with an unknown kind, precision or shape. */
+int sw_tune_set(const sw_tune_entry *entries, int32_t n);
+
+/* Copies up to `cap` entries of the tuning table; *n_out = their total number. */
+int sw_tune_get(sw_tune_entry *out, int32_t cap, int32_t *n_out);
 
 /* ---------------------------------------------------------------------------
  * Serving: a continuous-batching request loop.

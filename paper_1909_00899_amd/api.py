@@ -26,7 +26,8 @@ SW_FLAG_SATURATED = 1
 
 EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align",
             "sw_align_batch", "sw_align_batch_ex", "sw_server_create", "sw_server_submit",
-            "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay"]
+            "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay",
+            "sw_autotune", "sw_tune_set", "sw_tune_get"]
 
 
 class NativeLibraryError(RuntimeError):
@@ -75,7 +76,8 @@ class Stats(ctypes.Structure):
                 ("lanes_used", ctypes.c_int32 * 3), ("seglen_max", ctypes.c_int32),
                 ("prep_ms", ctypes.c_double), ("plan_ms", ctypes.c_double),
                 ("launch_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
-                ("record_events", ctypes.c_int64), ("reserved", ctypes.c_int32 * 8)]
+                ("record_events", ctypes.c_int64), ("graph_hits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 7)]
 
     def as_dict(self) -> dict:
         return {"kernel_ms": self.kernel_ms, "total_ms": self.total_ms, "cells": self.cells,
@@ -84,7 +86,27 @@ class Stats(ctypes.Structure):
                 "columns": self.columns, "lanes_used": list(self.lanes_used),
                 "seglen_max": self.seglen_max, "prep_ms": self.prep_ms, "plan_ms": self.plan_ms,
                 "launch_ms": self.launch_ms, "finish_ms": self.finish_ms,
-                "record_events": self.record_events}
+                "record_events": self.record_events, "graph_hits": self.graph_hits}
+
+
+SW_TUNE_SHARED, SW_TUNE_PAIR = 0, 1
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("alphabet_size", ctypes.c_int32), ("m_lo", ctypes.c_int32),
+                ("m_hi", ctypes.c_int32), ("lanes", ctypes.c_int32), ("seglen", ctypes.c_int32),
+                ("mixed", ctypes.c_int32), ("gcups", ctypes.c_double),
+                ("model_gcups", ctypes.c_double)]
+    KEYS = ("kind", "precision", "alphabet_size", "m_lo", "m_hi", "lanes", "seglen", "mixed",
+            "gcups", "model_gcups")
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k in self.KEYS}
+
+    @classmethod
+    def from_dict(cls, d: dict) -> "TuneEntry":
+        return cls(*[d.get(k, 0) for k in cls.KEYS])
 
 
 class ServerConfig(ctypes.Structure):
@@ -128,6 +150,12 @@ def load():
     lib.sw_align_batch_ex.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                       ctypes.POINTER(Options), ctypes.c_void_p,
                                       ctypes.POINTER(Stats)]
+    lib.sw_autotune.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), ctypes.c_int64,
+                                ctypes.POINTER(TuneEntry), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_int32)]
+    lib.sw_tune_set.argtypes = [ctypes.POINTER(TuneEntry), ctypes.c_int32]
+    lib.sw_tune_get.argtypes = [ctypes.POINTER(TuneEntry), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_int32)]
     _bind_server(lib)
     for name in EXPORTED:
         if not hasattr(lib, name):
@@ -197,17 +225,9 @@ class BatchOutput:
     stats: dict
 
 
-def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap_open: int,
-                   gap_extend: int, pair_query=None, precision: int = SW_PREC_AUTO,
-                   algorithm: int = SW_ALG_SCAN, force_lanes: int = 0, force_seglen: int = 0,
-                   force_kernel: int = 0, mixed_layout: int = 0, int16_cap: int = 0,
-                   use_graph: int = 0) -> BatchOutput:
-    """Many pairs in one persistent launch (plus an int32 rerun if needed).
-
-    Sequences are CSR.  Either all six arrays are numpy (host) or all are torch
-    CUDA tensors (device-resident; torch's current stream orders them).
-    """
-    lib = load()
+def _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query, precision):
+    """sw_batch for numpy (host) or torch CUDA (device-resident) CSR arrays; returns
+    the struct, the arrays it points into (keep them alive) and the pair count."""
     dev = _is_torch_cuda(ref_res)
     keep = []
     if dev:
@@ -237,6 +257,22 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
     b = Batch(npairs, ptr(query_res), ptr(query_off), nq, ptr(ref_res), ptr(ref_off), nr,
               None if pair_query is None else ptr(pair_query), ptr(pair_ref), precision,
               1 if dev else 0, stream)
+    return b, keep, npairs
+
+
+def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap_open: int,
+                   gap_extend: int, pair_query=None, precision: int = SW_PREC_AUTO,
+                   algorithm: int = SW_ALG_SCAN, force_lanes: int = 0, force_seglen: int = 0,
+                   force_kernel: int = 0, mixed_layout: int = 0, int16_cap: int = 0,
+                   use_graph: int = 0) -> BatchOutput:
+    """Many pairs in one persistent launch (plus an int32 rerun if needed).
+
+    Sequences are CSR.  Either all six arrays are numpy (host) or all are torch
+    CUDA tensors (device-resident; torch's current stream orders them).
+    """
+    lib = load()
+    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
+                                  precision)
     sc, M = make_scoring(matrix, gap_open, gap_extend)
     opt = Options(algorithm, force_lanes, force_seglen, force_kernel, mixed_layout, int16_cap,
                   use_graph)
@@ -253,6 +289,57 @@ def align_workload(w, **kw) -> BatchOutput:
     """sw_align_batch on a ``workloads.Workload`` (host arrays)."""
     return sw_align_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref, w.matrix,
                           w.gap_open, w.gap_extend, pair_query=w.pair_query, **kw)
+
+
+def sw_autotune(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap_open: int,
+                gap_extend: int, pair_query=None, precision: int = SW_PREC_AUTO,
+                sample_cells: int = 0) -> list:
+    """Measures kernel shapes on this batch and installs the fastest (the
+    library's process-wide tuning table); returns the new entries."""
+    lib = load()
+    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
+                                  precision)
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    cap = 256
+    out = (TuneEntry * cap)()
+    n = ctypes.c_int32(0)
+    _check(lib.sw_autotune(ctypes.byref(b), ctypes.byref(sc), int(sample_cells), out, cap,
+                           ctypes.byref(n)))
+    return [out[k].as_dict() for k in range(min(n.value, cap))]
+
+
+def autotune_workload(w, **kw) -> list:
+    """sw_autotune on a ``workloads.Workload`` (host arrays)."""
+    return sw_autotune(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref, w.matrix,
+                       w.gap_open, w.gap_extend, pair_query=w.pair_query, **kw)
+
+
+def tune_get() -> list:
+    lib = load()
+    n = ctypes.c_int32(0)
+    _check(lib.sw_tune_get(None, 0, ctypes.byref(n)))
+    out = (TuneEntry * max(n.value, 1))()
+    _check(lib.sw_tune_get(out, n.value, ctypes.byref(n)))
+    return [out[k].as_dict() for k in range(n.value)]
+
+
+def tune_set(entries) -> None:
+    lib = load()
+    arr = (TuneEntry * max(len(entries), 1))(*[TuneEntry.from_dict(e) for e in entries])
+    _check(lib.sw_tune_set(arr, len(entries)))
+
+
+def tune_save(path: str) -> None:
+    """Writes the tuning table as JSON (a cache for later processes)."""
+    import json
+    with open(path, "w") as f:
+        json.dump(tune_get(), f, indent=1)
+
+
+def tune_load(path: str) -> None:
+    import json
+    with open(path) as f:
+        tune_set(json.load(f))
 
 
 class Server:

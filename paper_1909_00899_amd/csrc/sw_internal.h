@@ -98,6 +98,9 @@ hipError_t launch_build_streams(const Task *tasks, int ntasks, const PairInfo *p
                                 const uint8_t *ref_res, uint8_t *streams, int sent_code,
                                 hipStream_t st);
 
+// p[0..n) = v.
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+
 // Sets every result to {0, -1, -1, 0}.
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);
 

@@ -70,6 +70,10 @@ __global__ __launch_bounds__(256) void build_pairs_kernel(int n_pairs, const int
   p.pad = 0;
   out[k] = p;
 }
+__global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
+}
 __global__ __launch_bounds__(256) void init_results_kernel(int n, DevResult *r) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) {
@@ -83,6 +87,13 @@ __global__ __launch_bounds__(256) void init_results_kernel(int n, DevResult *r) 
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(dev::init_results_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(dev::fill_u32_kernel, dim3(grid), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

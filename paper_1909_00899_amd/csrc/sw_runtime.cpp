@@ -13,11 +13,13 @@
 
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <chrono>
 #include <map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -97,6 +99,41 @@ void HostBuf::release() {
   cap = 0;
 }
 
+// ------------------------------------------------------------------ graph cache
+
+hipGraphExec_t GraphCache::find(const std::vector<uint64_t> &sig) {
+  for (auto &e : entries)
+    if (e.sig == sig) { e.stamp = ++clock; return e.exec; }
+  return nullptr;
+}
+
+void GraphCache::put(const std::vector<uint64_t> &sig, hipGraphExec_t exec) {
+  if (entries.size() >= kMaxEntries) {
+    auto old = std::min_element(entries.begin(), entries.end(),
+                                [](const Entry &x, const Entry &y) { return x.stamp < y.stamp; });
+    (void)hipGraphExecDestroy(old->exec);
+    entries.erase(old);
+  }
+  entries.push_back(Entry{sig, exec, ++clock});
+}
+
+void GraphCache::clear() {
+  for (auto &e : entries) (void)hipGraphExecDestroy(e.exec);
+  entries.clear();
+}
+
+int Workspace::ensure_side_streams() {
+  if (side_ready) return SW_OK;
+  for (int k = 0; k < kSideStreams; ++k) {
+    // default priority (no priority streams), non-blocking like the main one
+    HIPCHK(hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&join[k], hipEventDisableTiming));
+  }
+  HIPCHK(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+  side_ready = true;
+  return SW_OK;
+}
+
 // ------------------------------------------------------------------ device context
 
 Context g_ctx;
@@ -171,6 +208,28 @@ int prepare_scoring(const sw_scoring *sc, Scoring &out) {
 
 // ------------------------------------------------------------------ planner
 
+void LengthIndex::reset(int max_m) {
+  for (int m : ms)
+    if (m < (int)dense.size()) dense[m] = 0;
+  ms.clear();
+  sparse.clear();
+  const size_t want = (size_t)std::min(max_m, 1 << 20) + 1;
+  if (dense.size() < want) dense.resize(want, 0);
+}
+
+int LengthIndex::slot(int m) {
+  if (m < (int)dense.size()) {
+    int &d = dense[m];
+    if (!d) { ms.push_back(m); d = (int)ms.size(); }
+    return d - 1;
+  }
+  auto f = sparse.find(m);
+  if (f != sparse.end()) return f->second;
+  ms.push_back(m);
+  sparse.emplace(m, (int)ms.size() - 1);
+  return (int)ms.size() - 1;
+}
+
 namespace {
 
 constexpr int64_t kI32Limit = 2147483647ll;
@@ -190,23 +249,34 @@ int round_up(int64_t x, int64_t k) { return (int)(((x + k - 1) / k) * k); }
 
 // Indices of items ordered by reference length, longest first, ties in input
 // order (a stable counting sort: the lengths of one batch span a small range).
-void sort_by_n_desc(const std::vector<PlanItem> &items, std::vector<int> &order) {
-  order.resize(items.size());
-  if (items.empty()) return;
+void sort_by_n_desc(const PlanItem *items, size_t cnt, std::vector<int> &order,
+                    std::vector<int> &count) {
+  order.resize(cnt);
+  if (cnt == 0) return;
   int lo = items[0].n, hi = items[0].n;
-  for (const auto &it : items) { lo = std::min(lo, it.n); hi = std::max(hi, it.n); }
+  for (size_t k = 0; k < cnt; ++k) { lo = std::min(lo, items[k].n); hi = std::max(hi, items[k].n); }
   const int64_t range = (int64_t)hi - lo + 1;
-  if (range > 4 * (int64_t)items.size() + 1024) {
+  if (range > 4 * (int64_t)cnt + 1024) {
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return items[a].n > items[b].n; });
     return;
   }
-  std::vector<int> start(range + 1, 0);
-  for (const auto &it : items) start[hi - it.n + 1]++;
-  for (int64_t k = 0; k < range; ++k) start[k + 1] += start[k];
-  for (size_t k = 0; k < items.size(); ++k) order[start[hi - items[k].n]++] = (int)k;
+  count.assign(range + 1, 0);
+  for (size_t k = 0; k < cnt; ++k) count[hi - items[k].n + 1]++;
+  for (int64_t k = 0; k < range; ++k) count[k + 1] += count[k];
+  for (size_t k = 0; k < cnt; ++k) order[count[hi - items[k].n]++] = (int)k;
 }
+
+struct LaunchDesc {
+  bool shared;
+  int task_begin, task_end;
+  int menu;          // shared
+  int seg, pmax;     // per-pair
+  int nchunks;       // shared: launches; per-pair: inside the kernel
+  int query;         // shared
+  int grid;
+};
 
 }  // namespace
 
@@ -216,18 +286,19 @@ void sort_by_n_desc(const std::vector<PlanItem> &items, std::vector<int> &order)
 // stays short next to the average load of a wavefront (long references get
 // more lanes so they finish in time); consecutive pairs of one mode share a
 // task.  Tasks are emitted longest-first (by estimated cost) across modes.
-static void plan_shared(const std::vector<PlanItem> &items, Prec prec, int menu, int num_waves,
-                        int force_lanes, std::vector<Task> &tasks, int mode_counts[3]) {
+static void plan_shared(const PlanItem *items, size_t cnt, Prec prec, int menu, int num_waves,
+                        int force_lanes, HostScratch &hs, std::vector<Task> &tasks,
+                        int mode_counts[3]) {
   const SharedMenu mm = shared_menu(menu);
   const int segs[3] = {mm.seg16, mm.seg32, mm.seg64};
   const int Ps[3] = {16, 32, 64};
-  std::vector<int> order;
-  sort_by_n_desc(items, order);
+  std::vector<int> &order = hs.order;
+  sort_by_n_desc(items, cnt, order, hs.count);
   int narrow = 0;
   for (int k = 0; k < 3; ++k)
     if (segs[k]) { narrow = k; break; }
   double total = 0;
-  for (const auto &it : items) total += (double)it.n;
+  for (size_t k = 0; k < cnt; ++k) total += (double)items[k].n;
   total *= step_cost(prec, Ps[narrow], segs[narrow]) / slots_per_wave(prec, Ps[narrow]);
   const double per_wave = total / std::max(1, num_waves);
   // mode boundaries in the sorted order: [0, b2) mode 2, [b2, b1) mode 1, rest mode 0
@@ -323,83 +394,465 @@ struct PairShape {
   int P, seg, nchunks;
 };
 
+constexpr int kPairSegs[] = {4, 6, 8, 10, 12, 16};
+constexpr size_t kPairLdsBudget = 20 * 1024;   // LDS per wavefront (keeps >= 6 waves per CU)
+
 // LDS bytes of one per-pair wavefront region.
 size_t pair_region(Prec prec, int seg, int alpha) {
   return pair_lds_bytes(prec, seg, alpha) - matrix_lds_bytes(alpha);
 }
 
+bool pair_seg_allowed(Prec prec, int seg, int alpha, const ExecOptions &opt) {
+  if (opt.force_seglen) return seg == opt.force_seglen;
+  return seg == 4 || pair_region(prec, seg, alpha) <= kPairLdsBudget;
+}
+
+// Modelled VALU cost per reference column of one alignment on P lanes of a
+// wavefront whose widest sub-group has pmax lanes (the scan depth).
+double pair_cost(Prec prec, int P, int pmax, int seg, int nch) {
+  return nch * step_cost(prec, pmax, seg) * P / (64.0 * (prec == PREC_I16X2 ? 2 : 1));
+}
+
+// One width per launch: the (lanes, rows per lane) of least modelled cost.
 PairShape choose_pair_shape(Prec prec, int m, int alpha, const ExecOptions &opt) {
-  static const int kSegs[] = {4, 6, 8, 10, 12, 16};
-  const size_t budget = 20 * 1024;   // LDS per wavefront (keeps >= 6 waves per CU)
   PairShape best{64, 4, 1 << 30};
   double best_cost = 1e300;
   for (int P : {16, 32, 64}) {
     if (opt.force_lanes && P != opt.force_lanes) continue;
-    for (int seg : kSegs) {
-      if (opt.force_seglen && seg != opt.force_seglen) continue;
-      if (!opt.force_seglen && pair_region(prec, seg, alpha) > budget && seg != 4) continue;
-      const int rows = P * seg;
-      const int nch = (m + rows - 1) / rows;
-      // cost per reference column, normalised per alignment slot
-      const double cost = (double)nch * step_cost(prec, P, seg) / slots_per_wave(prec, P);
+    for (int seg : kPairSegs) {
+      if (!pair_seg_allowed(prec, seg, alpha, opt)) continue;
+      const int nch = (m + P * seg - 1) / (P * seg);
+      const double cost = pair_cost(prec, P, P, seg, nch);
       if (cost < best_cost - 1e-9) { best_cost = cost; best = PairShape{P, seg, nch}; }
     }
   }
   return best;
 }
 
+// Mixed layouts: the narrowest sub-group that holds m rows at `seg` rows per
+// lane, else 64 lanes over several query chunks.
+PairShape mixed_shape(int m, int seg) {
+  for (int P : {16, 32, 64})
+    if (P * seg >= m) return PairShape{P, seg, 1};
+  return PairShape{64, seg, (m + 64 * seg - 1) / (64 * seg)};
+}
+
 }  // namespace
 
-// ------------------------------------------------------------------ executor
+std::vector<std::pair<int, int>> pair_candidates(Prec prec, int alpha, const PlanItem *items,
+                                                 size_t cnt, int max_cands) {
+  ExecOptions none;
+  std::vector<std::pair<double, std::pair<int, int>>> c;
+  for (int P : {16, 32, 64})
+    for (int seg : kPairSegs) {
+      if (!pair_seg_allowed(prec, seg, alpha, none)) continue;
+      double cost = 0;
+      for (size_t k = 0; k < cnt; ++k) {
+        const int nch = (items[k].m + P * seg - 1) / (P * seg);
+        cost += (double)items[k].n * pair_cost(prec, P, P, seg, nch);
+      }
+      c.push_back({cost, {P, seg}});
+    }
+  std::stable_sort(c.begin(), c.end(),
+                   [](const auto &x, const auto &y) { return x.first < y.first; });
+  std::vector<std::pair<int, int>> r;
+  for (size_t k = 0; k < c.size() && (int)k < max_cands; ++k) r.push_back(c[k].second);
+  return r;
+}
+
+std::vector<int> pair_mixed_candidates(Prec prec, int alpha, const PlanItem *items, size_t cnt,
+                                       int max_cands) {
+  ExecOptions none;
+  std::vector<std::pair<double, int>> c;
+  for (int seg : kPairSegs) {
+    if (!pair_seg_allowed(prec, seg, alpha, none)) continue;
+    int pm = 16;
+    for (size_t k = 0; k < cnt; ++k) {
+      const PairShape ps = mixed_shape(items[k].m, seg);
+      if (ps.nchunks == 1) pm = std::max(pm, ps.P);
+    }
+    double cost = 0;
+    for (size_t k = 0; k < cnt; ++k) {
+      const PairShape ps = mixed_shape(items[k].m, seg);
+      cost += (double)items[k].n * pair_cost(prec, ps.P, ps.nchunks == 1 ? pm : 64, seg, ps.nchunks);
+    }
+    c.push_back({cost, seg});
+  }
+  std::stable_sort(c.begin(), c.end(),
+                   [](const auto &x, const auto &y) { return x.first < y.first; });
+  std::vector<int> r;
+  for (size_t k = 0; k < c.size() && (int)k < max_cands; ++k) r.push_back(c[k].second);
+  return r;
+}
+
+// Sub-group widths (in lanes) of a wavefront layout; returns their number.
+int layout_groups(int layout, int widths[4]) {
+  int n = 0;
+  for (int r = 0; r < 4; ++r) {
+    if (!((layout >> r) & 1)) continue;
+    int e = r + 1;
+    while (e < 4 && !((layout >> e) & 1)) ++e;
+    widths[n++] = 16 * (e - r);
+  }
+  return n;
+}
+
+// Layouts the kernels support: bit 0 set, 32-lane groups start at row 0 or 2,
+// no 48-lane groups, no group wider than pmax.
+bool layout_valid(int layout, int pmax) {
+  if (layout < 1 || layout > 15 || !(layout & 1)) return false;
+  int w[4];
+  const int n = layout_groups(layout, w);
+  int row = 0;
+  for (int g = 0; g < n; ++g) {
+    if (w[g] == 48 || w[g] > pmax) return false;
+    if (w[g] == 32 && (row & 1)) return false;
+    row += w[g] / 16;
+  }
+  return true;
+}
 
 namespace {
 
-struct LaunchDesc {
-  bool shared;
-  int task_begin, task_end;
-  int menu;          // shared
-  int seg, pmax;     // per-pair
-  int nchunks;       // shared: launches; per-pair: inside the kernel
-  int query;         // shared
-  int grid;
-};
+// Per-pair launches.  Every pair gets a shape (lanes P, rows per lane, query
+// chunks); pairs of one launch share rows per lane and chunk count.  With
+// mixed layouts one launch also mixes 16-, 32- and 64-lane sub-groups inside
+// a wavefront (its kernel is compiled for the widest).  Inside a launch the
+// pairs are taken longest reference first; in int16x2 mode the two halves of a
+// sub-group hold consecutive pairs of the same width.
+int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const ExecOptions &opt,
+               int num_cus, HostScratch &hs, std::vector<Task> &tasks,
+               std::vector<LaunchDesc> &launches, int64_t &bnd_elems, ExecStats &stats) {
+  if (cnt == 0) return SW_OK;
+  if (opt.force_seglen &&
+      std::find(std::begin(kPairSegs), std::end(kPairSegs), opt.force_seglen) == std::end(kPairSegs)) {
+    set_error("no compiled per-pair kernel with %d rows per lane", opt.force_seglen);
+    return SW_EINVAL;
+  }
+  // mixed_layout: 0 = planner's choice, 1 = mixed, 2 = one width per launch
+  bool mixed = opt.mixed_layout == 1 && !opt.force_lanes;
+  int mixed_seg = opt.force_seglen;
+  // ---- distinct query lengths
+  int max_m = 0, min_m = INT_MAX;
+  for (size_t k = 0; k < cnt; ++k) { max_m = std::max(max_m, items[k].m); min_m = std::min(min_m, items[k].m); }
+  const bool tunable = opt.use_tuning && !opt.force_lanes && !opt.force_seglen && opt.mixed_layout != 1;
+  sw_tune_entry te;
+  if (tunable && opt.mixed_layout == 0 && tune_mixed(prec, alpha, min_m, max_m, te)) {
+    mixed = true;
+    mixed_seg = te.seglen;
+  }
+  LengthIndex &li = hs.lengths;
+  li.reset(max_m);
+  hs.slot.resize(cnt);
+  hs.nsum.clear();
+  hs.nmax.clear();
+  for (size_t k = 0; k < cnt; ++k) {
+    const int s = li.slot(items[k].m);
+    if (s >= (int)hs.nsum.size()) { hs.nsum.resize(s + 1, 0.0); hs.nmax.resize(s + 1, 0); }
+    hs.nsum[s] += items[k].n;
+    hs.nmax[s] = std::max(hs.nmax[s], items[k].n);
+    hs.slot[k] = s;
+  }
+  const int nd = (int)li.ms.size();
+  std::vector<PairShape> shape(nd);
+  int pmax_mixed = 16;
+  double nonmixed_total = 0;
+  if (!mixed) {
+    // Least modelled work per pair, unless that leaves one wavefront with a
+    // chain of column steps longer than the whole batch needs on a full GPU
+    // (small batches of long queries): then the cheapest shape whose chain
+    // fits that bound (more lanes, fewer query chunks).
+    const double slots = (double)num_cus * 4;   // one full-rate wavefront per SIMD
+    double total = 0, lmin = 0;
+    for (int s = 0; s < nd; ++s) {
+      shape[s] = choose_pair_shape(prec, li.ms[s], alpha, opt);
+      total += hs.nsum[s] * pair_cost(prec, shape[s].P, shape[s].P, shape[s].seg, shape[s].nchunks);
+      double best_lat = 1e300;
+      for (int P : {16, 32, 64}) {
+        if (opt.force_lanes && P != opt.force_lanes) continue;
+        for (int seg : kPairSegs) {
+          if (!pair_seg_allowed(prec, seg, alpha, opt)) continue;
+          const int nch = (li.ms[s] + P * seg - 1) / (P * seg);
+          best_lat = std::min(best_lat, (double)hs.nmax[s] * nch * step_cost(prec, P, seg));
+        }
+      }
+      lmin = std::max(lmin, best_lat);
+    }
+    const double bound = std::max(total / slots, lmin);
+    nonmixed_total = total;
+    for (int s = 0; s < nd; ++s) {
+      const int m = li.ms[s];
+      if (tunable && tune_lookup(SW_TUNE_PAIR, prec, alpha, m, te)) {
+        shape[s] = PairShape{te.lanes, te.seglen, (m + te.lanes * te.seglen - 1) / (te.lanes * te.seglen)};
+        continue;
+      }
+      const PairShape &c0 = shape[s];
+      if ((double)hs.nmax[s] * c0.nchunks * step_cost(prec, c0.P, c0.seg) <= bound) continue;
+      double best = 1e300;
+      for (int P : {16, 32, 64}) {
+        if (opt.force_lanes && P != opt.force_lanes) continue;
+        for (int seg : kPairSegs) {
+          if (!pair_seg_allowed(prec, seg, alpha, opt)) continue;
+          const int nch = (m + P * seg - 1) / (P * seg);
+          if ((double)hs.nmax[s] * nch * step_cost(prec, P, seg) > bound) continue;
+          const double c = pair_cost(prec, P, P, seg, nch);
+          if (c < best - 1e-9) { best = c; shape[s] = PairShape{P, seg, nch}; }
+        }
+      }
+    }
+  }
+  // Planner's choice: mixed layouts (one launch for every width, fewer launch
+  // tails) unless they model over 15% more work than one width per launch.
+  bool try_mixed = mixed;
+  if (!mixed && opt.mixed_layout == 0 && !opt.force_lanes && !opt.force_seglen && nd > 0) {
+    bool tuned_any = false;
+    for (int s = 0; s < nd && tunable; ++s) tuned_any |= tune_lookup(SW_TUNE_PAIR, prec, alpha, li.ms[s], te);
+    try_mixed = !tuned_any;
+  }
+  if (try_mixed) {
+    // one rows-per-lane for the whole batch: the tuned or forced one, else the
+    // least modelled total cost
+    int best_seg = -1;
+    double best = 1e300;
+    for (int seg : kPairSegs) {
+      if (mixed_seg ? seg != mixed_seg : !pair_seg_allowed(prec, seg, alpha, opt)) continue;
+      int pm = 16;
+      for (int s = 0; s < nd; ++s) {
+        const PairShape ps = mixed_shape(li.ms[s], seg);
+        if (ps.nchunks == 1) pm = std::max(pm, ps.P);
+      }
+      double c = 0;
+      for (int s = 0; s < nd; ++s) {
+        const PairShape ps = mixed_shape(li.ms[s], seg);
+        c += hs.nsum[s] * pair_cost(prec, ps.P, ps.nchunks == 1 ? pm : 64, seg, ps.nchunks);
+      }
+      if (c < best - 1e-9) { best = c; best_seg = seg; pmax_mixed = pm; }
+    }
+    if (mixed || best <= 1.15 * nonmixed_total) {
+      mixed = true;
+      for (int s = 0; s < nd; ++s) shape[s] = mixed_shape(li.ms[s], best_seg);
+    }
+  }
+  // ---- launch classes (rows per lane, widest sub-group, chunked or not); a
+  // chunked launch holds tasks of any chunk count
+  struct Cls { int seg, pmax; bool chunked; };
+  std::vector<Cls> cls;
+  std::vector<int> cls_of(nd);
+  int max_nch = 1;
+  for (int s = 0; s < nd; ++s) {
+    const PairShape &ps = shape[s];
+    const int pmax = (mixed && ps.nchunks == 1) ? pmax_mixed : ps.P;
+    const bool chunked = ps.nchunks > 1;
+    max_nch = std::max(max_nch, ps.nchunks);
+    int c = 0;
+    while (c < (int)cls.size() && !(cls[c].seg == ps.seg && cls[c].pmax == pmax && cls[c].chunked == chunked)) ++c;
+    if (c == (int)cls.size()) {
+      if (!pair_kernel_has(prec, ps.seg, pmax)) {
+        set_error("no compiled per-pair kernel for %d rows per lane, %d lanes", ps.seg, pmax);
+        return SW_EINVAL;
+      }
+      cls.push_back(Cls{ps.seg, pmax, chunked});
+    }
+    cls_of[s] = c;
+  }
+  // ---- order: by class, then query chunks and reference length (most work
+  // first), stable; one counting sort into compact records so that packing
+  // reads sequentially
+  const int ncls = (int)cls.size();
+  int nlo = items[0].n, nhi = items[0].n;
+  for (size_t k = 0; k < cnt; ++k) { nlo = std::min(nlo, items[k].n); nhi = std::max(nhi, items[k].n); }
+  const int64_t range = (int64_t)nhi - nlo + 1;
+  const int64_t keys = (int64_t)ncls * max_nch * range;
+  std::vector<PackRec> &rec = hs.packed;
+  rec.resize(cnt);
+  hs.bounds.assign(ncls + 1, 0);
+  if (keys <= 4 * (int64_t)cnt + 4096) {
+    hs.count.assign((size_t)keys + 1, 0);
+    hs.order.resize(cnt);   // sort key of each item
+    for (size_t k = 0; k < cnt; ++k) {
+      const int s = hs.slot[k];
+      const int key = ((cls_of[s] * max_nch) + (max_nch - shape[s].nchunks)) * (int)range +
+                      (nhi - items[k].n);
+      hs.order[k] = key;
+      hs.count[key + 1]++;
+    }
+    for (size_t q = 0; q + 1 < hs.count.size(); ++q) hs.count[q + 1] += hs.count[q];
+    for (int c = 0; c <= ncls; ++c) hs.bounds[c] = hs.count[(size_t)c * max_nch * range];
+    for (size_t k = 0; k < cnt; ++k) {
+      const int s = hs.slot[k];
+      rec[hs.count[hs.order[k]]++] = PackRec{items[k].pair, items[k].n, shape[s].P, shape[s].nchunks};
+    }
+  } else {
+    hs.order.resize(cnt);
+    std::iota(hs.order.begin(), hs.order.end(), 0);
+    std::stable_sort(hs.order.begin(), hs.order.end(), [&](int x, int y) {
+      const int sx = hs.slot[x], sy = hs.slot[y];
+      if (cls_of[sx] != cls_of[sy]) return cls_of[sx] < cls_of[sy];
+      if (shape[sx].nchunks != shape[sy].nchunks) return shape[sx].nchunks > shape[sy].nchunks;
+      return items[x].n > items[y].n;
+    });
+    for (size_t x = 0; x < cnt; ++x) {
+      const int k = hs.order[x];
+      const int s = hs.slot[k];
+      rec[x] = PackRec{items[k].pair, items[k].n, shape[s].P, shape[s].nchunks};
+      hs.bounds[cls_of[s] + 1]++;
+    }
+    for (int c = 0; c < ncls; ++c) hs.bounds[c + 1] += hs.bounds[c];
+  }
+  const int halves = prec == PREC_I16X2 ? 2 : 1;
+  for (int c = 0; c < ncls; ++c) {
+    const int a = hs.bounds[c], b = hs.bounds[c + 1];
+    if (a == b) continue;
+    const Cls K = cls[c];
+    LaunchDesc L{};
+    L.shared = false;
+    L.seg = K.seg;
+    L.pmax = K.pmax;
+    L.nchunks = K.chunked ? 2 : 1;   // > 1: the chunked kernel (per-task counts)
+    L.task_begin = (int)tasks.size();
+    int ti = -1, rows = 4, nsg = 0, maxn = 1;
+    int half_task[3] = {-1, -1, -1}, half_slot[3] = {0, 0, 0};
+    auto close = [&]() {
+      if (ti < 0) return;
+      Task &t = tasks[ti];
+      for (int r = rows; r < 4;) {   // unused rows: empty sub-groups
+        t.layout |= 1 << r;
+        r += ((r & 1) == 0 && K.pmax >= 32) ? 2 : 1;
+      }
+      t.ncols = round_up(maxn, kBlock);
+      ti = -1;
+    };
+    for (int x = a; x < b; ++x) {
+      const PackRec &it = rec[x];
+      const int P = it.P;
+      const int pc = P == 16 ? 0 : (P == 32 ? 1 : 2);
+      stats.lanes_used[pc]++;
+      if (halves == 2 && half_task[pc] >= 0) {
+        // the second half of a sub-group opened by an earlier pair of this
+        // width (as many or more chunks), if its columns cover this reference
+        Task &h = tasks[half_task[pc]];
+        if (half_task[pc] == ti || it.n <= h.ncols) {
+          h.pair[half_slot[pc]] = it.pair;
+          if (half_task[pc] == ti) maxn = std::max(maxn, it.n);
+          half_task[pc] = -1;
+          continue;
+        }
+        half_task[pc] = -1;
+      }
+      int pos = P == 16 ? rows : (P == 32 ? (rows + 1) & ~1 : (rows == 0 ? 0 : 4));
+      if (ti < 0 || pos + P / 16 > 4) {
+        close();
+        Task t;
+        std::memset(&t, 0, sizeof(t));
+        t.nchunks = it.nch;   // the most of any pair it will hold (sorted)
+        t.bnd_off = -1;
+        for (int s2 = 0; s2 < kSlots; ++s2) t.pair[s2] = -1;
+        tasks.push_back(t);
+        ti = (int)tasks.size() - 1;
+        rows = 0;
+        nsg = 0;
+        maxn = 1;
+        pos = 0;
+      }
+      Task &t = tasks[ti];
+      for (int r = rows; r < pos; ++r) { t.layout |= 1 << r; ++nsg; }   // skipped row
+      t.layout |= 1 << pos;
+      t.pair[2 * nsg] = it.pair;
+      if (halves == 2) { half_task[pc] = ti; half_slot[pc] = 2 * nsg + 1; }
+      ++nsg;
+      rows = pos + P / 16;
+      maxn = std::max(maxn, it.n);
+    }
+    close();
+    L.task_end = (int)tasks.size();
+    for (int t = L.task_begin; t < L.task_end; ++t) {
+      Task &tk = tasks[t];
+      if (K.chunked) { tk.bnd_off = bnd_elems; bnd_elems += 8ll * tk.ncols; }
+      int w[4];
+      const int ng = layout_groups(tk.layout, w);
+      for (int g = 0; g < ng; ++g)
+        for (int h = 0; h < halves; ++h)
+          if (tk.pair[2 * g + h] >= 0)
+            stats.padded_cells += (int64_t)tk.ncols * w[g] * K.seg * tk.nchunks;
+    }
+    stats.seglen_max = std::max(stats.seglen_max, K.seg);
+    L.grid = std::max(1, std::min(L.task_end - L.task_begin, num_cus * 16));
+    launches.push_back(L);
+  }
+  return SW_OK;
+}
 
 }  // namespace
+
+// ------------------------------------------------------------------ executor
 
 int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions &opt,
             Workspace &ws, int n_results, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
             int num_cus, ExecStats &stats, bool reset_results) {
   const double t_plan0 = now_ms();
-  std::vector<Task> tasks;
+  HostScratch &hs = ws.host;
+  std::vector<Task> &tasks = hs.tasks;
+  tasks.clear();
   std::vector<LaunchDesc> launches;
   const bool lazy = opt.algorithm == SW_ALG_LAZYF;
-  // ---- group by query
-  std::vector<int> count(in.n_queries, 0);
-  for (const auto &it : in.items) count[it.query]++;
-  std::vector<std::vector<PlanItem>> by_query(in.n_queries);
-  std::vector<PlanItem> per_pair;
+  // ---- split: a query with many pairs runs in the shared-query kernel
+  hs.qcount.assign(in.n_queries, 0);
+  for (const auto &it : in.items) hs.qcount[it.query]++;
   auto wants_shared = [&](int q) {
-    return lazy || opt.force_kernel == 1 || (opt.force_kernel == 0 && count[q] >= 32);
+    return lazy || opt.force_kernel == 1 || (opt.force_kernel == 0 && hs.qcount[q] >= 32);
   };
-  int only_query = -1;   // every item uses one query that runs shared: no copy
-  if (!in.items.empty() && count[in.items[0].query] == (int)in.items.size() &&
-      wants_shared(in.items[0].query))
+  size_t n_shared = 0;
+  for (const auto &it : in.items) n_shared += wants_shared(it.query);
+  const PlanItem *pp_items = nullptr;   // per-pair items
+  size_t pp_cnt = 0;
+  const PlanItem *sh_items = nullptr;   // shared items, grouped by query
+  hs.qstart.clear();
+  int only_query = -1;                  // every item is shared and uses one query
+  if (n_shared == 0) {
+    pp_items = in.items.data();
+    pp_cnt = in.items.size();
+  } else if (n_shared == in.items.size() && hs.qcount[in.items[0].query] == (int)in.items.size()) {
     only_query = in.items[0].query;
-  if (only_query < 0) {
+    sh_items = in.items.data();
+  } else {
+    hs.per_pair.clear();
+    hs.shared_items.resize(n_shared);
+    hs.qstart.assign(in.n_queries + 1, 0);
+    for (const auto &it : in.items)
+      if (wants_shared(it.query)) hs.qstart[it.query + 1]++;
+    for (int q = 0; q < in.n_queries; ++q) hs.qstart[q + 1] += hs.qstart[q];
+    std::vector<int> pos(hs.qstart.begin(), hs.qstart.end() - 1);
     for (const auto &it : in.items) {
-      if (wants_shared(it.query)) by_query[it.query].push_back(it);
-      else per_pair.push_back(it);
+      if (wants_shared(it.query)) hs.shared_items[pos[it.query]++] = it;
+      else hs.per_pair.push_back(it);
     }
+    sh_items = hs.shared_items.data();
+    pp_items = hs.per_pair.data();
+    pp_cnt = hs.per_pair.size();
   }
   const int waves_total = num_cus * 16;
   int64_t bnd_elems = 0;
   // ---- shared-query launches
-  for (int q = 0; q < in.n_queries; ++q) {
-    if (q != only_query && by_query[q].empty()) continue;
-    const std::vector<PlanItem> &group = q == only_query ? in.items : by_query[q];
+  for (int q = 0; sh_items && q < in.n_queries; ++q) {
+    const PlanItem *group;
+    size_t gcnt;
+    if (only_query >= 0) {
+      if (q != only_query) continue;
+      group = sh_items;
+      gcnt = in.items.size();
+    } else {
+      if (hs.qstart[q + 1] == hs.qstart[q]) continue;
+      group = sh_items + hs.qstart[q];
+      gcnt = hs.qstart[q + 1] - hs.qstart[q];
+    }
     const int m = in.m_of_query[q];
-    int fl = opt.force_lanes;
-    const int menu = pick_shared_menu(m, fl ? fl : 64, opt.force_seglen);
+    int fl = opt.force_lanes, fseg = opt.force_seglen;
+    sw_tune_entry te;
+    if (opt.use_tuning && !lazy && !fl && !fseg && tune_lookup(SW_TUNE_SHARED, prec, sc.alpha, m, te)) {
+      fl = te.lanes;
+      fseg = te.seglen;
+    }
+    const int menu = pick_shared_menu(m, fl ? fl : 64, fseg);
     if (menu < 0) { set_error("no compiled shared kernel with %d rows per lane", opt.force_seglen); return SW_EINVAL; }
     const SharedMenu mm = shared_menu(menu);
     if (fl == 16 && !mm.seg16) { set_error("menu has no 16-lane mode"); return SW_EINVAL; }
@@ -412,7 +865,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
     L.query = q;
     L.task_begin = (int)tasks.size();
     int mc[3] = {0, 0, 0};
-    plan_shared(group, prec, menu, waves_total, fl, tasks, mc);
+    plan_shared(group, gcnt, prec, menu, waves_total, fl, hs, tasks, mc);
     L.task_end = (int)tasks.size();
     for (int k = 0; k < 3; ++k) stats.lanes_used[k] += mc[k];
     const int segs[3] = {mm.seg16, mm.seg32, mm.seg64};
@@ -429,66 +882,10 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
     L.grid = std::max(1, std::min((ntask + kWavesPerGroup - 1) / kWavesPerGroup, num_cus * 2));
     launches.push_back(L);
   }
-  // ---- per-pair launches, grouped by (seg, P, chunks)
-  if (!per_pair.empty()) {
-    struct Key { int seg, P, nch; bool operator<(const Key &o) const {
-      return std::tie(seg, P, nch) < std::tie(o.seg, o.P, o.nch); } };
-    // shapes depend on the query length only: decide once per distinct length
-    std::map<int, PairShape> shape_of_m;
-    std::map<Key, std::vector<PlanItem>> groups;
-    for (const auto &it : per_pair) {
-      auto f = shape_of_m.find(it.m);
-      if (f == shape_of_m.end())
-        f = shape_of_m.emplace(it.m, choose_pair_shape(prec, it.m, sc.alpha, opt)).first;
-      const PairShape &ps = f->second;
-      groups[Key{ps.seg, ps.P, ps.nchunks}].push_back(it);
-    }
-    std::vector<std::pair<Key, PlanItem>> keyed;
-    keyed.reserve(per_pair.size());
-    std::vector<int> ord;
-    for (auto &g : groups) {
-      sort_by_n_desc(g.second, ord);
-      for (int k : ord) keyed.push_back({g.first, g.second[k]});
-    }
-    size_t a = 0;
-    while (a < keyed.size()) {
-      size_t b = a;
-      while (b < keyed.size() && !(keyed[a].first < keyed[b].first) && !(keyed[b].first < keyed[a].first)) ++b;
-      const Key k = keyed[a].first;
-      LaunchDesc L{};
-      L.shared = false;
-      L.seg = k.seg;
-      L.pmax = k.P;
-      L.nchunks = k.nch;
-      L.task_begin = (int)tasks.size();
-      const int halves = prec == PREC_I16X2 ? 2 : 1;
-      const int spw = slots_per_wave(prec, k.P);
-      for (size_t x = a; x < b; x += spw) {
-        Task t;
-        std::memset(&t, 0, sizeof(t));
-        t.layout = layout_for(k.P);
-        t.nchunks = k.nch;
-        t.bnd_off = -1;
-        for (int s = 0; s < kSlots; ++s) t.pair[s] = -1;
-        int maxn = 1;
-        for (int q = 0; q < spw && x + q < b; ++q) {
-          const int sg = q / halves, h = q % halves;
-          t.pair[2 * sg + h] = keyed[x + q].second.pair;
-          maxn = std::max(maxn, keyed[x + q].second.n);
-        }
-        t.ncols = round_up(maxn, kBlock);
-        if (k.nch > 1) { t.bnd_off = bnd_elems; bnd_elems += 8ll * t.ncols; }
-        stats.padded_cells += (int64_t)std::min<size_t>(spw, b - x) * t.ncols * k.P * k.seg * k.nch;
-        tasks.push_back(t);
-      }
-      L.task_end = (int)tasks.size();
-      stats.lanes_used[k.P == 16 ? 0 : (k.P == 32 ? 1 : 2)] += (int)(b - a);
-      stats.seglen_max = std::max(stats.seglen_max, k.seg);
-      L.grid = std::max(1, std::min(L.task_end - L.task_begin, num_cus * 16));
-      launches.push_back(L);
-      a = b;
-    }
-  }
+  // ---- per-pair launches
+  int rc = plan_pairs(pp_items, pp_cnt, prec, sc.alpha, opt, num_cus, hs, tasks, launches,
+                      bnd_elems, stats);
+  if (rc) return rc;
   if (tasks.empty()) return SW_OK;
 
   // ---- device buffers
@@ -501,23 +898,34 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   // launch anything the kernels' bounds assumptions do not cover.  (PairInfo
   // index == result index for every path of this library.)
   const int n_pairs_total = in.d_pairs ? in.n_pairs : (int)in.pairs.size();
-  std::vector<int> nlen(std::max(n_pairs_total, 0), -1);
+  std::vector<int> &nlen = hs.nlen;
+  std::vector<int> &mlen = hs.mlen;
+  nlen.assign(std::max(n_pairs_total, 0), -1);
+  mlen.assign(std::max(n_pairs_total, 0), 0);
   for (const auto &it : in.items)
-    if (it.pair >= 0 && it.pair < n_pairs_total) nlen[it.pair] = it.n;
+    if (it.pair >= 0 && it.pair < n_pairs_total) { nlen[it.pair] = it.n; mlen[it.pair] = it.m; }
   for (const auto &L : launches) {
     const bool chunked = L.nchunks > 1;
     for (int t = L.task_begin; t < L.task_end; ++t) {
       const Task &tk = tasks[t];
-      bool ok = tk.ncols >= kBlock && tk.ncols % kBlock == 0 && (tk.layout & 1) &&
+      bool ok = tk.ncols >= kBlock && tk.ncols % kBlock == 0 &&
+                layout_valid(tk.layout, L.shared ? 64 : L.pmax) &&
                 tk.stream_off + (int64_t)tk.ncols / kBlock * kStreamBlockBytes <= stream_bytes;
       if (chunked) ok = ok && tk.bnd_off >= 0 && tk.bnd_off % 4 == 0 &&
                         tk.bnd_off + 8ll * tk.ncols <= bnd_elems;
       if (L.shared) ok = ok && tk.mode >= 0 && tk.mode < 3 && tk.layout == layout_for(16 << tk.mode);
+      int widths[4];
+      const int ngroups = layout_groups(tk.layout, widths);
       for (int s2 = 0; s2 < kSlots; ++s2) {
         const int pid = tk.pair[s2];
         ok = ok && pid >= -1 && pid < n_pairs_total;
         if (pid >= 0) {
-          ok = ok && nlen[pid] >= 0 && nlen[pid] <= tk.ncols && pid < n_results;
+          ok = ok && s2 / 2 < ngroups && nlen[pid] >= 0 && nlen[pid] <= tk.ncols &&
+               pid < n_results;
+          // per-pair: the task's chunks of this sub-group cover the query
+          if (ok && !L.shared)
+            ok = tk.nchunks >= 1 && (chunked || tk.nchunks == 1) &&
+                 (int64_t)mlen[pid] <= (int64_t)tk.nchunks * widths[s2 / 2] * L.seg;
           if (prec == PREC_I32) ok = ok && (s2 & 1) == 0;
         }
       }
@@ -527,7 +935,6 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
       }
     }
   }
-  int rc;
   const size_t n_launch_total = [&] { size_t c = 0; for (auto &L : launches) c += L.shared ? L.nchunks : 1; return c; }();
   const size_t misc_bytes = 32 + 4 * n_launch_total + 16;   // stats (3 x u64, padded) + counters
   if ((rc = ws.tasks.ensure(tasks.size() * sizeof(Task))) ||
@@ -547,28 +954,86 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   const size_t o_misc = o_mat + sizeof(int) * sc.M.size();
   const size_t staging_bytes = o_misc + misc_bytes;
   if ((rc = ws.staging.ensure(staging_bytes))) return rc;
-  unsigned char *hs = ws.staging.as<unsigned char>();
-  std::memcpy(hs + o_tasks, tasks.data(), tasks.size() * sizeof(Task));
-  std::memcpy(hs + o_pairs, in.pairs.data(), in.pairs.size() * sizeof(PairInfo));
-  std::memcpy(hs + o_mat, sc.M.data(), sizeof(int) * sc.M.size());
-  std::memset(hs + o_misc, 0, misc_bytes);
-  HIPCHK(hipMemcpyAsync(ws.tasks.p, hs + o_tasks, o_pairs - o_tasks, hipMemcpyHostToDevice, st));
-  if (!in.pairs.empty())
-    HIPCHK(hipMemcpyAsync(ws.pairs.p, hs + o_pairs, o_mat - o_pairs, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(ws.matrix.p, hs + o_mat, o_misc - o_mat, hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(ws.misc.p, hs + o_misc, misc_bytes, hipMemcpyHostToDevice, st));
-  if (reset_results) HIPCHK(launch_init_results(n_results, ws.results.as<DevResult>(), st));
-  if (bnd_elems > 0) HIPCHK(hipMemsetAsync(ws.bnd.p, 0, bnd_half * sizeof(uint32_t), st));
-  const int sent = sc.alpha;
-  HIPCHK(launch_build_streams(ws.tasks.as<Task>(), (int)tasks.size(),
-                              in.d_pairs ? in.d_pairs : ws.pairs.as<PairInfo>(),
-                              in.d_rres, ws.streams.as<uint8_t>(), sent, st));
-  unsigned long long *d_stats = (unsigned long long *)ws.misc.p;
-  int *d_counters = (int *)((char *)ws.misc.p + 32);
+  unsigned char *stg = ws.staging.as<unsigned char>();
+  std::memcpy(stg + o_tasks, tasks.data(), tasks.size() * sizeof(Task));
+  std::memcpy(stg + o_pairs, in.pairs.data(), in.pairs.size() * sizeof(PairInfo));
+  std::memcpy(stg + o_mat, sc.M.data(), sizeof(int) * sc.M.size());
+  std::memset(stg + o_misc, 0, misc_bytes);
+
+  // The device work of this execution as a list of operations, so that it can
+  // run eagerly or be captured once into a hipGraph and replayed.  `sig`
+  // collects every parameter of every operation: equal signatures mean an
+  // identical graph (the staging contents are read when the graph runs).
+  std::vector<std::function<hipError_t()>> ops;
+  std::vector<uint64_t> sig;
+  auto note = [&](const void *p, size_t n) {
+    const size_t w = sig.size();
+    sig.resize(w + (n + 7) / 8, 0);
+    std::memcpy(sig.data() + w, p, n);
+  };
+  auto copy_op = [&](void *dst, const void *src, size_t bytes) {
+    const uint64_t v[4] = {1, (uint64_t)(uintptr_t)dst, (uint64_t)(uintptr_t)src, bytes};
+    note(v, sizeof(v));
+    ops.push_back([=]() { return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st); });
+  };
+  copy_op(ws.tasks.p, stg + o_tasks, o_pairs - o_tasks);
+  if (!in.pairs.empty()) copy_op(ws.pairs.p, stg + o_pairs, o_mat - o_pairs);
+  copy_op(ws.matrix.p, stg + o_mat, o_misc - o_mat);
+  copy_op(ws.misc.p, stg + o_misc, misc_bytes);
+  if (reset_results) {
+    DevResult *r = ws.results.as<DevResult>();
+    const uint64_t v[3] = {2, (uint64_t)(uintptr_t)r, (uint64_t)n_results};
+    note(v, sizeof(v));
+    ops.push_back([=]() { return launch_init_results(n_results, r, st); });
+  }
   uint32_t *bndA = ws.bnd.as<uint32_t>();
   uint32_t *bndB = bndA ? bndA + bnd_half : nullptr;
-
-  HIPCHK(hipEventRecord(e0, st));
+  if (bnd_elems > 0) {
+    // the first query chunk reads zero boundaries (a fill kernel, not a memset
+    // node: the sequence may be captured into a graph)
+    const uint64_t v[3] = {3, (uint64_t)(uintptr_t)bndA, (uint64_t)bnd_half};
+    note(v, sizeof(v));
+    ops.push_back([=]() { return launch_fill_u32(bndA, bnd_half, 0u, st); });
+  }
+  {
+    const Task *dt = ws.tasks.as<Task>();
+    const int nt = (int)tasks.size();
+    const PairInfo *dp = in.d_pairs ? in.d_pairs : ws.pairs.as<PairInfo>();
+    const uint8_t *rr = in.d_rres;
+    uint8_t *ds = ws.streams.as<uint8_t>();
+    const int sent = sc.alpha;
+    const uint64_t v[7] = {4, (uint64_t)(uintptr_t)dt, (uint64_t)nt, (uint64_t)(uintptr_t)dp,
+                           (uint64_t)(uintptr_t)rr, (uint64_t)(uintptr_t)ds, (uint64_t)sent};
+    note(v, sizeof(v));
+    ops.push_back([=]() { return launch_build_streams(dt, nt, dp, rr, ds, sent, st); });
+  }
+  const size_t first_kernel_op = ops.size();
+  unsigned long long *d_stats = (unsigned long long *)ws.misc.p;
+  int *d_counters = (int *)((char *)ws.misc.p + 32);
+  // Per-pair launches are independent of each other and of the shared-query
+  // launches: they run concurrently on the workspace's side streams (fork and
+  // join through events, which a graph capture turns into dependencies).  The
+  // chunk launches of one shared query stay in order on the main stream.
+  bool any_shared = false;
+  int n_pair_launches = 0;
+  for (const auto &L : launches) { any_shared |= L.shared; n_pair_launches += !L.shared; }
+  const int side_wanted = std::min(kSideStreams, any_shared ? n_pair_launches : n_pair_launches - 1);
+  if (side_wanted > 0 && (rc = ws.ensure_side_streams())) return rc;
+  hipStream_t lane_stream[kSideStreams + 1] = {st};
+  for (int k = 0; k < side_wanted; ++k) lane_stream[k + 1] = ws.side[k];
+  if (side_wanted > 0) {
+    hipEvent_t fork = ws.fork;
+    std::vector<hipStream_t> sides(lane_stream + 1, lane_stream + 1 + side_wanted);
+    const uint64_t v[2] = {7, (uint64_t)side_wanted};
+    note(v, sizeof(v));
+    ops.push_back([=]() {
+      hipError_t e = hipEventRecord(fork, st);
+      for (hipStream_t x : sides)
+        if (e == hipSuccess) e = hipStreamWaitEvent(x, fork, 0);
+      return e;
+    });
+  }
+  int pair_ordinal = 0;
   int ci = 0;
   for (const auto &L : launches) {
     KArgs a;
@@ -585,6 +1050,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
     a.sat_cap = opt.int16_cap;
     a.results = ws.results.as<DevResult>();
     a.stats = d_stats;
+    const Alg alg = lazy ? ALG_LAZYF : ALG_SCAN;
     if (L.shared) {
       a.shared_q_off = in.q_off_of_query[L.query];
       a.shared_m = in.m_of_query[L.query];
@@ -594,8 +1060,13 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
         a.task_counter = d_counters + ci++;
         a.bnd_in = (c & 1) ? bndB : bndA;
         a.bnd_out = (c & 1) ? bndA : bndB;
-        HIPCHK(launch_shared(prec, lazy ? ALG_LAZYF : ALG_SCAN, L.menu, L.nchunks > 1, a,
-                             L.grid, st));
+        const int menu = L.menu, grid = L.grid;
+        const bool chunked = L.nchunks > 1;
+        const uint64_t v[6] = {5, (uint64_t)prec, (uint64_t)alg, (uint64_t)menu, (uint64_t)chunked,
+                               (uint64_t)grid};
+        note(v, sizeof(v));
+        note(&a, sizeof(a));
+        ops.push_back([=]() { return launch_shared(prec, alg, menu, chunked, a, grid, st); });
         stats.launches++;
       }
     } else {
@@ -603,11 +1074,79 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
       a.bnd = bndA;
       a.bnd_half = bnd_half;
       a.bnd_in = bndA;
-      HIPCHK(launch_pair(prec, L.seg, L.pmax, L.nchunks > 1, a, L.grid, st));
+      const int seg = L.seg, pmax = L.pmax, grid = L.grid;
+      const bool chunked = L.nchunks > 1;
+      // lane 0 is the main stream when no shared launch occupies it
+      const int lane = side_wanted == 0 ? 0
+                       : (any_shared ? 1 + pair_ordinal % side_wanted
+                                     : pair_ordinal % (side_wanted + 1));
+      ++pair_ordinal;
+      hipStream_t ls = lane_stream[lane];
+      const uint64_t v[7] = {6, (uint64_t)prec, (uint64_t)seg, (uint64_t)pmax, (uint64_t)chunked,
+                             (uint64_t)grid, (uint64_t)lane};
+      note(v, sizeof(v));
+      note(&a, sizeof(a));
+      ops.push_back([=]() { return launch_pair(prec, seg, pmax, chunked, a, grid, ls); });
       stats.launches++;
     }
   }
-  HIPCHK(hipEventRecord(e1, st));
+  if (side_wanted > 0) {
+    std::vector<hipStream_t> sides(lane_stream + 1, lane_stream + 1 + side_wanted);
+    std::vector<hipEvent_t> joins(ws.join, ws.join + side_wanted);
+    ops.push_back([=]() {
+      hipError_t e = hipSuccess;
+      for (size_t k = 0; k < sides.size() && e == hipSuccess; ++k) {
+        e = hipEventRecord(joins[k], sides[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, joins[k], 0);
+      }
+      return e;
+    });
+  }
+  auto run_ops = [&](size_t from, size_t to) -> int {
+    for (size_t k = from; k < to; ++k) {
+      const hipError_t e = ops[k]();
+      if (e != hipSuccess) {
+        set_error("device operation %zu failed: %s", k, hipGetErrorString(e));
+        return SW_EDEVICE;
+      }
+    }
+    return SW_OK;
+  };
+  if (!opt.use_graph) {
+    if ((rc = run_ops(0, first_kernel_op))) return rc;
+    HIPCHK(hipEventRecord(e0, st));
+    if ((rc = run_ops(first_kernel_op, ops.size()))) return rc;
+    HIPCHK(hipEventRecord(e1, st));
+  } else {
+    hipGraphExec_t exec = ws.graphs.find(sig);
+    if (exec) {
+      stats.graph_hits++;
+    } else {
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+      rc = run_ops(0, ops.size());
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &graph);
+      if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+      }
+      if (ec != hipSuccess) {
+        set_error("hipStreamEndCapture failed: %s", hipGetErrorString(ec));
+        return SW_EDEVICE;
+      }
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+        return SW_EDEVICE;
+      }
+      ws.graphs.put(sig, exec);
+    }
+    // with a graph the timed span also covers the uploads and stream building
+    HIPCHK(hipEventRecord(e0, st));
+    HIPCHK(hipGraphLaunch(exec, st));
+    HIPCHK(hipEventRecord(e1, st));
+  }
   const double t_fin0 = now_ms();
   stats.launch_ms += t_fin0 - t_launch0;
   unsigned long long hstats[3];
@@ -686,6 +1225,7 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
     stats->lazyf_steps = (int64_t)es.dev_stats[1];
     stats->columns = (int64_t)es.dev_stats[0];
     stats->record_events = (int64_t)es.dev_stats[2];
+    stats->graph_hits = es.graph_hits;
     for (int k = 0; k < 3; ++k) stats->lanes_used[k] = es.lanes_used[k];
     stats->seglen_max = es.seglen_max;
   }

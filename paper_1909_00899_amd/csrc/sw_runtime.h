@@ -5,6 +5,7 @@
 
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "sw.h"
@@ -64,8 +65,9 @@ struct ExecInput {
 };
 
 struct ExecOptions {
+  bool use_tuning = true;   // consult the autotuner's table for unforced shapes
   int algorithm = SW_ALG_SCAN;
-  int force_lanes = 0, force_seglen = 0, force_kernel = 0, mixed_layout = 0;
+  int force_lanes = 0, force_seglen = 0, force_kernel = 0, mixed_layout = 0, use_graph = 0;
   int int16_cap = 32767;
 };
 
@@ -74,6 +76,7 @@ struct ExecStats {
   double plan_ms = 0, launch_ms = 0, finish_ms = 0;
   int64_t padded_cells = 0;
   int launches = 0;
+  int graph_hits = 0;
   int lanes_used[3] = {0, 0, 0};
   int seglen_max = 0;
   unsigned long long dev_stats[3] = {0, 0, 0};
@@ -81,12 +84,80 @@ struct ExecStats {
 
 double now_ms();
 
+// Dense index of the distinct query lengths of a batch.
+struct LengthIndex {
+  std::vector<int> dense;               // m -> slot + 1 (0: not seen) for small m
+  std::unordered_map<int, int> sparse;  // larger m
+  std::vector<int> ms;                  // distinct lengths in first-seen order
+  void reset(int max_m);
+  int slot(int m);
+};
+
+// A pair as the per-pair packer reads it (sorted, compact).
+struct PackRec {
+  int pair, n, P, nch;
+};
+
+// Planner scratch kept between calls, so that large batches do not pay for
+// fresh allocations (and their page faults) every time.
+struct HostScratch {
+  std::vector<int> order, count, bounds, slot, qstart, qcount, nlen, mlen;
+  std::vector<PackRec> packed;
+  std::vector<double> nsum;
+  std::vector<int> nmax;
+  std::vector<PlanItem> shared_items, per_pair;
+  std::vector<swk::Task> tasks;
+  LengthIndex lengths;
+};
+
+// Sub-group widths (lanes) of a wavefront layout (bit r set <=> a sub-group
+// starts at lane 16*r); returns their number.
+int layout_groups(int layout, int widths[4]);
+// Layouts the kernels run: 32-lane groups start at lane 0 or 32, no 48-lane
+// groups, none wider than pmax.
+bool layout_valid(int layout, int pmax);
+
+// Instantiated graphs of recent executions, keyed by the full parameter
+// signature of their device operations (least recently used evicted).
+struct GraphCache {
+  static constexpr size_t kMaxEntries = 8;
+  struct Entry {
+    std::vector<uint64_t> sig;
+    hipGraphExec_t exec;
+    uint64_t stamp;
+  };
+  std::vector<Entry> entries;
+  uint64_t clock = 0;
+  hipGraphExec_t find(const std::vector<uint64_t> &sig);
+  void put(const std::vector<uint64_t> &sig, hipGraphExec_t exec);
+  void clear();
+};
+
+constexpr int kSideStreams = 3;
+
 // Work buffers used by one execution (the batch path owns one; the request
 // server one per in-flight batch).
 struct Workspace {
   DevBuf tasks, pairs, streams, results, bnd, misc, matrix, offs;
   HostBuf staging;
+  HostScratch host;
+  GraphCache graphs;
+  // side streams for concurrent per-pair launches (created on first use, on
+  // the device current at that time), fork/join events
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t fork = nullptr, join[kSideStreams] = {};
+  bool side_ready = false;
+  int ensure_side_streams();
   void release() {
+    graphs.clear();
+    if (side_ready) {
+      for (int k = 0; k < kSideStreams; ++k) {
+        (void)hipStreamDestroy(side[k]);
+        (void)hipEventDestroy(join[k]);
+      }
+      (void)hipEventDestroy(fork);
+      side_ready = false;
+    }
     for (DevBuf *b : {&tasks, &pairs, &streams, &results, &bnd, &misc, &matrix, &offs})
       b->release();
     staging.release();
@@ -116,6 +187,26 @@ int ensure_init(int dev = -1);
 int execute(const ExecInput &in, const Scoring &sc, swk::Prec prec, const ExecOptions &opt,
             Workspace &ws, int n_results, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
             int num_cus, ExecStats &stats, bool reset_results);
+
+// Checks a public batch description, builds the planner items and puts the
+// PairInfo records, sequences and the residue check on the device.  The
+// caller holds C.mu; `out` receives the empty result of every pair.
+int prepare_batch(const sw_batch *b, const Scoring &S, Context &C, ExecInput &in,
+                  sw_result *out, int64_t &cells);
+// 1 if prepare_batch's residue check found a code >= alphabet_size, 0 if
+// not, -1 on a device error.
+int residue_flag(Context &C);
+
+// Autotuner table (process-wide).  Lookups return false when no entry applies.
+bool tune_lookup(int kind, swk::Prec prec, int alpha, int m, sw_tune_entry &e);
+bool tune_mixed(swk::Prec prec, int alpha, int m_min, int m_max, sw_tune_entry &e);
+int tune_validate(const sw_tune_entry &e);
+// The per-pair (lanes, rows per lane) shapes of least modelled cost for items,
+// best first; and the rows per lane of least modelled cost for mixed layouts.
+std::vector<std::pair<int, int>> pair_candidates(swk::Prec prec, int alpha, const PlanItem *items,
+                                                 size_t cnt, int max_cands);
+std::vector<int> pair_mixed_candidates(swk::Prec prec, int alpha, const PlanItem *items,
+                                       size_t cnt, int max_cands);
 
 // Full batch semantics (int16 pass + int32 rerun) on prepared input.
 int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecOptions &opt,

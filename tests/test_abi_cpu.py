@@ -89,3 +89,45 @@ def test_batch_rejects_bad_options(lib):
                                  out.ctypes.data, None) == api.SW_EINVAL
     b.precision = 7
     assert lib.sw_align_batch(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data) == api.SW_EINVAL
+    opt = api.Options()
+    opt.mixed_layout = 3
+    b.precision = 0
+    assert lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
+                                 out.ctypes.data, None) == api.SW_EINVAL
+
+
+def _entry(**kw):
+    d = dict(kind=api.SW_TUNE_PAIR, precision=api.SW_PREC_AUTO, alphabet_size=4, m_lo=129,
+             m_hi=160, lanes=16, seglen=10, mixed=0, gcups=1.0, model_gcups=1.0)
+    d.update(kw)
+    return d
+
+
+def test_tuning_table_round_trip_and_validation(lib, tmp_path):
+    try:
+        api.tune_set([])
+        assert api.tune_get() == []
+        good = [_entry(), _entry(kind=api.SW_TUNE_SHARED, alphabet_size=20, m_lo=385, m_hi=512,
+                                 lanes=0, seglen=8),
+                _entry(kind=api.SW_TUNE_SHARED, alphabet_size=20, m_lo=1, m_hi=64, lanes=16,
+                       seglen=4),
+                _entry(mixed=1, m_lo=1, m_hi=1000, lanes=64, seglen=16)]
+        api.tune_set(good)
+        assert api.tune_get() == good
+        path = str(tmp_path / "tune.json")
+        api.tune_save(path)
+        api.tune_set([])
+        api.tune_load(path)
+        assert api.tune_get() == good
+        bad = [_entry(kind=5), _entry(precision=3), _entry(alphabet_size=0), _entry(m_lo=0),
+               _entry(m_lo=10, m_hi=9), _entry(lanes=8), _entry(seglen=7), _entry(mixed=2),
+               _entry(kind=api.SW_TUNE_SHARED, lanes=0, seglen=5),
+               _entry(kind=api.SW_TUNE_SHARED, lanes=16, seglen=2),
+               _entry(kind=api.SW_TUNE_SHARED, mixed=1, lanes=0, seglen=8)]
+        for e in bad:
+            with pytest.raises(api.SwError) as ex:
+                api.tune_set([e])
+            assert ex.value.code == api.SW_EINVAL, e
+        assert api.tune_get() == good          # a rejected table leaves the old one
+    finally:
+        api.tune_set([])

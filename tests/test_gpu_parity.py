@@ -113,13 +113,23 @@ def _random_batch(seed, n, alpha, mlen, nlen, go=11, ge=1):
     return W.random_pairs(n, alpha, mlen, nlen, seed, matrix=M, gap_open=go, gap_extend=ge)
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("kernel,layout", [(1, 0), (2, 0), (2, 2)])
 @pytest.mark.parametrize("prec", [api.SW_PREC_AUTO, api.SW_PREC_I32])
-def test_batch_random_pairs(kernel, prec):
+def test_batch_random_pairs(kernel, layout, prec):
     w = _random_batch(7, 600, 20, (1, 260), (1, 400))
     want = oracle_batch(w)
-    got = api.align_workload(w, force_kernel=kernel, precision=prec)
-    assert_same(got.results, want, w, "kernel=%d prec=%d" % (kernel, prec))
+    got = api.align_workload(w, force_kernel=kernel, precision=prec, mixed_layout=layout)
+    assert_same(got.results, want, w, "kernel=%d layout=%d prec=%d" % (kernel, layout, prec))
+
+
+def test_per_pair_long_queries_many_chunk_counts():
+    """One chunked per-pair launch holds tasks of different chunk counts; with
+    one width per launch the launches run concurrently on side streams."""
+    w = _random_batch(14, 160, 4, (100, 4000), (50, 400), go=6, ge=1)
+    want = oracle_batch(w)
+    for layout in (0, 2):
+        got = api.align_workload(w, force_kernel=2, mixed_layout=layout)
+        assert_same(got.results, want, w, "layout=%d" % layout)
 
 
 @pytest.mark.parametrize("lanes", [16, 32, 64])
@@ -226,3 +236,63 @@ def test_device_resident_inputs_match_host():
                              t(w.pair_ref, torch.int32), w.matrix, w.gap_open, w.gap_extend,
                              pair_query=t(w.pair_query, torch.int32))
     assert_same(got.results, want, w, "device-resident")
+
+
+# ---------------------------------------------------------------- mixed layouts, graphs
+
+@pytest.mark.parametrize("prec", [api.SW_PREC_AUTO, api.SW_PREC_I32])
+@pytest.mark.parametrize("seg", [0, 4, 6])
+def test_mixed_layouts(prec, seg):
+    """16-, 32- and 64-lane sub-groups of one wavefront (one rows-per-lane per
+    launch, each pair on the narrowest sub-group holding its query)."""
+    w = _random_batch(21 + seg, 500, 20, (1, 900), (1, 300))
+    want = oracle_batch(w)
+    got = api.align_workload(w, force_kernel=2, mixed_layout=1, precision=prec,
+                             force_seglen=seg)
+    assert_same(got.results, want, w, "mixed prec=%d seg=%d" % (prec, seg))
+    assert sum(1 for v in got.stats["lanes_used"] if v > 0) >= 2
+
+
+def test_mixed_layouts_dna_with_rerun():
+    w = W.dna_pairs(n_pairs=3000)
+    # vary the query lengths: cut every query at a seeded length in [1, 150]
+    rng = np.random.default_rng(22)
+    cut = rng.integers(1, 151, size=w.pair_query.size)
+    qs = [w.query_res[w.query_off[k]:w.query_off[k] + c] for k, c in enumerate(cut)]
+    qoff = np.zeros(len(qs) + 1, dtype=np.int64)
+    np.cumsum([q.size for q in qs], out=qoff[1:])
+    w2 = W.Workload("dna_cut", np.concatenate(qs), qoff, w.ref_res, w.ref_off, w.pair_query,
+                    w.pair_ref, w.matrix, w.gap_open, w.gap_extend)
+    want = oracle_batch(w2)
+    got = api.align_workload(w2, force_kernel=2, mixed_layout=1, int16_cap=60)
+    assert_same(got.results, want, w2, "mixed dna cap=60")
+    assert got.stats["n_rerun"] == int((want[:, 0] >= 60).sum())
+
+
+@pytest.mark.parametrize("case", ["shared", "pair", "chunked", "rerun"])
+def test_graph_replays_match_eager(case):
+    """Captured graphs replayed several times, with eager calls and other
+    device work in between, give the eager result every time."""
+    import torch
+    if case == "shared":
+        w, kw = W.protein_search(n_refs=2000), {}
+    elif case == "pair":
+        w, kw = _random_batch(31, 400, 4, (1, 300), (1, 300), go=6, ge=1), {"force_kernel": 2}
+    elif case == "chunked":
+        w, kw = _random_batch(32, 64, 20, (300, 1500), (20, 300)), {"force_lanes": 32,
+                                                                     "force_seglen": 4}
+    else:
+        w, kw = _random_batch(33, 300, 20, (10, 200), (10, 300)), {"int16_cap": 40}
+    want = oracle_batch(w)
+    eager = api.align_workload(w, **kw)
+    assert_same(eager.results, want, w, case + " eager")
+    hits = 0
+    for rep in range(4):
+        g = api.align_workload(w, use_graph=1, **kw)
+        assert (g.results == eager.results).all(), (case, rep)
+        hits += g.stats["graph_hits"]
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        again = api.align_workload(w, **kw)
+        assert (again.results == eager.results).all(), (case, rep)
+    assert hits >= 3
