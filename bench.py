@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--n-refs", type=int, default=100_000)
     ap.add_argument("--workload", default="protein_search",
                     choices=["protein_search", "dna_pairs", "long_queries", "serving"])
@@ -86,9 +88,16 @@ def main():
              pref=t(w.pair_ref, torch.int32))
     torch.cuda.synchronize()
 
-    def step():
+    # tile shapes (lanes per alignment, rows per lane) from the autotuner,
+    # measured on this batch before the timed region
+    ta = time.perf_counter()
+    tuned = api.sw_autotune(d["qres"], d["qoff"], d["rres"], d["roff"], d["pref"], w.matrix,
+                            w.gap_open, w.gap_extend) if not args.no_tune else []
+    tune_s = time.perf_counter() - ta
+
+    def step(graph=0):
         return api.sw_align_batch(d["qres"], d["qoff"], d["rres"], d["roff"], d["pref"],
-                                  w.matrix, w.gap_open, w.gap_extend)
+                                  w.matrix, w.gap_open, w.gap_extend, use_graph=graph)
 
     for _ in range(args.warmup):
         out = step()
@@ -120,8 +129,24 @@ def main():
                      "ops_per_cell": OPS_PER_CELL, "kernel_ms": round(kms, 4),
                      "kernel_gcups": round(cells / (kms / 1e3) / 1e9, 2)},
         "stats": {k: out.stats[k] for k in ("n_rerun", "n_launches", "lanes_used",
-                                            "seglen_max", "padded_cells", "total_ms")},
+                                            "seglen_max", "padded_cells", "total_ms", "prep_ms",
+                                            "plan_ms", "launch_ms", "finish_ms")},
+        "tuned": {"seconds": round(tune_s, 3),
+                  "entries": [{k: (round(v, 1) if isinstance(v, float) else v)
+                               for k, v in e.items()} for e in tuned]},
     }
+    if not args.no_graph:
+        # the same steps with the call's device work replayed from a hipGraph
+        step(1)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for _ in range(args.steps):
+            og = step(1)
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - tg) / args.steps * 1e3
+        rec["graph"] = {"ms_per_step": round(gms, 3), "gcups": round(cells / gms / 1e6, 2),
+                        "graph_hits": og.stats["graph_hits"],
+                        "same_results": bool(np.array_equal(og.results, out.results))}
 
     if not args.no_plain:
         # plain kernel: one 256 x 1024 pair per launch (sw_align)
@@ -178,6 +203,8 @@ def bench_dna(args):
     n = min(args.n_refs * 10, 1_000_000)
     w = W.dna_pairs(n_pairs=n)
     d, pq = _device_batch(w)
+    tuned = [] if args.no_tune else api.sw_autotune(*d, w.matrix, w.gap_open, w.gap_extend,
+                                                     pair_query=pq)
     step = lambda: api.sw_align_batch(*d, w.matrix, w.gap_open, w.gap_extend, pair_query=pq)  # noqa
     for _ in range(args.warmup):
         out = step()
@@ -205,7 +232,10 @@ def bench_dna(args):
                                    "kernel_ms": round(km, 3),
                                    "kernel_gcups": round(cells / (km / 1e3) / 1e9, 1)},
                       "stats": {k: out.stats[k] for k in ("n_rerun", "lanes_used", "seglen_max",
-                                                          "prep_ms", "plan_ms", "total_ms")}}))
+                                                          "prep_ms", "plan_ms", "launch_ms",
+                                                          "finish_ms", "total_ms")},
+                      "tuned": [{k: (round(v, 1) if isinstance(v, float) else v)
+                                 for k, v in e.items()} for e in tuned]}))
 
 
 def bench_long_queries(args):
