@@ -106,6 +106,9 @@ struct LaneCtx {
   uint32_t w16;  // weight of the row_bcast:15 scan step for this lane
   uint32_t w32;  // weight of the row_bcast:31 scan step
   uint32_t wcarry;  // weight applied to a chunk carry entering this lane's G
+  uint32_t rx16;    // all ones if this lane takes the row_bcast:15 value (same sub-group)
+  uint32_t rx32;    // all ones if this lane takes the row_bcast:31 value
+  int glast;        // wavefront lane index of the last lane of this sub-group
 };
 
 // layout: bit r set <=> a sub-group starts at lane 16*r (bit 0 always set).
@@ -132,6 +135,9 @@ __device__ __forceinline__ LaneCtx make_lane(int layout, int seg, uint32_t ge) {
   const bool r31 = row >= 2 && s0 == 0;
   L.w32 = r31 ? weight<O>((uint64_t)(L.lane & 31) + 1, unit) : inf;
   L.wcarry = L.start ? weight<O>(1, unit) : inf;
+  L.rx16 = r15 ? 0xffffffffu : 0u;
+  L.rx32 = r31 ? 0xffffffffu : 0u;
+  L.glast = s0 * 16 + L.P - 1;
   return L;
 }
 
@@ -151,20 +157,25 @@ __device__ __forceinline__ uint32_t shift1(uint32_t x, const LaneCtx &L, uint32_
 
 // ---------------------------------------------------------------- per-lane state
 
-// End cell.  Each lane keeps its own running maximum G of H_diag (per half)
-// and, whenever a half improves it, the column index and a copy of that
-// column's new H values (before any cross-lane correction).  At the end the
-// row is the first row of the copy whose H reaches G.
+// End cell.  Each lane keeps a record threshold G (per half) and, whenever
+// the column maximum of H_diag in one of its halves exceeds it, the column
+// index, that maximum (S) and a copy of the column's new H values (before
+// any cross-lane correction).  At the end the row is the first row of the copy
+// whose H reaches S.  Every few columns G is raised to the largest threshold
+// among the lanes before it in the sub-group (all thresholds are values of
+// cells in earlier columns), so that only lanes that beat the alignment's
+// best so far record.
 //
 // Why this is exact for the cell that matters: let X be the lexicographically
-// smallest (column, row) cell holding the overall maximum S, in lane l and
-// column c.  No cell of an earlier column scores S or more (it would precede
-// X), so lane l improves at column c and never again, and its copy is column
-// c.  Every E and F entering lane l's rows in column c comes from cells of
-// earlier columns (all below S) or from rows of lane l above X (all below S)
-// minus a non-negative gap cost, so the first row whose new H reaches S is
-// X's row.  Other lanes' records may point at a wrong row, but they score
-// below S, or equal S in a later column or in a later lane of the same
+// smallest (column, row) cell holding the overall maximum, in lane l and
+// column c.  Every cell of an earlier column scores below it (else it would
+// precede X), so lane l's threshold is below it at column c, lane l records
+// column c, and no later column exceeds what it recorded.  Every E and F
+// entering lane l's rows in column c comes from cells of earlier columns (all
+// below the maximum) or from rows of lane l above X (all below it) minus a
+// non-negative gap cost, so the first row whose new H reaches the maximum is
+// X's row.  Other lanes' records may point at a wrong row, but they score below
+// the maximum, or equal it in a later column or in a later lane of the same
 // column, so they never win the final (score, column, row) reduction.
 template <int SEG>
 struct State {
@@ -172,7 +183,8 @@ struct State {
   uint32_t E[SEG];
   uint32_t snap[SEG]; // H of the column where this lane last improved (per half)
   uint32_t Fscan;     // vertical-gap value entering this lane's first row
-  uint32_t G;         // this lane's running maximum of H_diag (per half)
+  uint32_t G;         // record threshold (per half)
+  uint32_t S;         // column maximum of H_diag at the last record (per half)
   int rc[2];          // column of the last improvement (per half), or INT_MAX
   uint32_t events;    // improvement branches taken (statistics)
 };
@@ -183,6 +195,7 @@ __device__ __forceinline__ void state_reset(State<SEG> &st, uint32_t g0) {
   for (int j = 0; j < SEG; ++j) { st.H[j] = 0; st.E[j] = 0; st.snap[j] = 0; }
   st.Fscan = 0;
   st.G = g0;
+  st.S = 0;
   st.rc[0] = st.rc[1] = 0x7fffffff;
   st.events = 0;
 }
@@ -250,7 +263,28 @@ __device__ __forceinline__ void record(State<SEG> &st, uint32_t cmax, int i) {
     if (m & 0xffffu) st.rc[0] = i;
     if (O::kHalves == 2 && (m >> 16)) st.rc[1] = i;
     st.G = nb;
+    st.S = (nb & m) | (st.S & ~m);
   }
+}
+
+// Raises every lane's record threshold to the largest threshold of its
+// sub-group: an inclusive prefix maximum over the sub-group (thresholds are
+// non-negative, so the zeros shifted in are neutral), then the last lane's
+// value read back for every lane of the sub-group.
+template <class O, int SEG, int PMAX>
+__device__ __forceinline__ void share_threshold(State<SEG> &st, const LaneCtx &L) {
+  uint32_t T = st.G;
+  T = O::vmax(T, dpp<kRowShr1>(T));
+  T = O::vmax(T, dpp<kRowShr2>(T));
+  T = O::vmax(T, dpp<kRowShr4>(T));
+  T = O::vmax(T, dpp<kRowShr8>(T));
+  if constexpr (PMAX >= 32) T = O::vmax(T, dpp<kRowBcast15, 0xa, false>(T) & L.rx16);
+  if constexpr (PMAX >= 64) T = O::vmax(T, dpp<kRowBcast31, 0xc, false>(T) & L.rx32);
+  const uint32_t t15 = (uint32_t)__builtin_amdgcn_readlane((int)T, 15);
+  const uint32_t t31 = (uint32_t)__builtin_amdgcn_readlane((int)T, 31);
+  const uint32_t t47 = (uint32_t)__builtin_amdgcn_readlane((int)T, 47);
+  const uint32_t t63 = (uint32_t)__builtin_amdgcn_readlane((int)T, 63);
+  st.G = L.glast == 15 ? t15 : (L.glast == 31 ? t31 : (L.glast == 47 ? t47 : t63));
 }
 
 // ---------------------------------------------------------------- one column
@@ -343,17 +377,56 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
 // Runs `ncols` reference columns for every sub-group of the wavefront.
 // stream: this task's residue stream; bnd_*: the task's chunk-boundary arrays
 // (HB then FB, [4 sub-groups][ncols] each) or nullptr.
-template <class O, int SEG, int PMAX, bool CHUNKED, bool LAZY, class ProfMap>
+// Reference residues, four columns per 32-bit word (column 4b+k in byte k),
+// for the low and the high half of this lane's sub-group.
+//
+// StreamSrc reads a task's residue stream ([ncols/4][8 slot-halves][4]
+// bytes, sentinel-padded by the stream builder; the stream buffer ends with
+// spare blocks, so reading two blocks past the task's end stays inside it).
+struct StreamSrc {
+  const uint2 *sp;   // this sub-group's (low, high) word of block 0
+  __device__ __forceinline__ uint2 get(int b) const { return sp[b * 4]; }
+};
+
+// DirectSrc reads the references themselves: a full word where all four
+// columns lie inside the reference (an unaligned 4-byte load), single bytes
+// in the last partial word, and the sentinel code at and past the end (no
+// memory access there).
+struct DirectSrc {
+  const uint8_t *plo, *phi;   // first residue of the low / high half's reference
+  int nlo, nhi;               // their lengths (0 for an empty slot)
+  uint32_t sentw;             // sentinel code in all four bytes
+  __device__ __forceinline__ static uint32_t word(const uint8_t *p, int n, int b, uint32_t sentw) {
+    const int i = b * kBlock;
+    if (i + kBlock <= n) {
+      uint32_t w;
+      __builtin_memcpy(&w, p + i, 4);
+      return w;
+    }
+    uint32_t w = sentw;
+    if (i < n) {
+#pragma unroll
+      for (int q = 0; q < kBlock - 1; ++q)
+        if (i + q < n) w = (w & ~(0xffu << (8 * q))) | ((uint32_t)p[i + q] << (8 * q));
+    }
+    return w;
+  }
+  __device__ __forceinline__ uint2 get(int b) const {
+    return make_uint2(word(plo, nlo, b, sentw), word(phi, nhi, b, sentw));
+  }
+};
+
+template <class O, int SEG, int PMAX, bool CHUNKED, bool LAZY, class ProfMap, class Src>
 __device__ __forceinline__ void run_columns(State<SEG> &st, const LaneCtx &L, const Params &pr,
-                                            const ProfMap &pm, const uint8_t *stream, int ncols,
+                                            const ProfMap &pm, const Src &src, int ncols,
                                             const uint32_t *hb_in, const uint32_t *fb_in,
                                             uint32_t *hb_out, uint32_t *fb_out,
                                             uint32_t &lazy_steps) {
   const int nblk = ncols / kBlock;
-  // residue words of this sub-group: low half at slot 2*sg, high half at 2*sg+1
-  const uint2 *sp = (const uint2 *)stream + L.sg;
-  uint2 rc = sp[0];
-  uint2 rn = sp[4];
+  uint32_t ev_shared = st.events;
+  // residue words of this sub-group (low half, high half), two blocks ahead
+  uint2 rc = src.get(0);
+  uint2 rn = src.get(1);
   uint4 hbc, hbn, fbc, fbn;
   if constexpr (CHUNKED) {
     hbc = ((const uint4 *)hb_in)[0];
@@ -364,7 +437,7 @@ __device__ __forceinline__ void run_columns(State<SEG> &st, const LaneCtx &L, co
   for (int b = 0; b < nblk; ++b) {
     const uint2 r = rc;
     rc = rn;
-    rn = sp[(b + 2) * 4];
+    rn = src.get(b + 2);
     uint4 hbv = make_uint4(0, 0, 0, 0), fbv = make_uint4(0, 0, 0, 0);
     if constexpr (CHUNKED) {
       hbv = hbc; hbc = hbn; hbn = ((const uint4 *)hb_in)[b + 2];
@@ -384,6 +457,11 @@ __device__ __forceinline__ void run_columns(State<SEG> &st, const LaneCtx &L, co
     if (hb_out != nullptr && L.last) {
       ((uint4 *)hb_out)[b] = make_uint4(ho[0], ho[1], ho[2], ho[3]);
       ((uint4 *)fb_out)[b] = make_uint4(fo[0], fo[1], fo[2], fo[3]);
+    }
+    // share thresholds after blocks in which some lane recorded
+    if (st.events != ev_shared) {
+      share_threshold<O, SEG, PMAX>(st, L);
+      ev_shared = st.events;
     }
   }
 }
@@ -434,13 +512,14 @@ __device__ __forceinline__ uint32_t prev_g0(const Prev &p) {
   return g;
 }
 
+// pid[h]: PairInfo index of this lane's sub-group in half h, or -1.
 template <class O, int SEG>
-__device__ __forceinline__ void finish(const State<SEG> &st, const LaneCtx &L, const Task *tp,
+__device__ __forceinline__ void finish(const State<SEG> &st, const LaneCtx &L, const int pid[2],
                                        const PairInfo *pairs, DevResult *results, int row_base,
                                        Prev &prev, int sat_cap) {
 #pragma unroll
   for (int h = 0; h < O::kHalves; ++h) {
-    int s = st.rc[h] != 0x7fffffff ? O::get(st.G, h) : 0;
+    int s = st.rc[h] != 0x7fffffff ? O::get(st.S, h) : 0;
     int c = 0x7fffffff, r = 0x7fffffff;
     if (s > 0) {
       int jj = SEG - 1;
@@ -463,14 +542,13 @@ __device__ __forceinline__ void finish(const State<SEG> &st, const LaneCtx &L, c
     }
     if (s <= 0) { s = 0; c = 0x7fffffff; r = 0x7fffffff; }
     prev.s[h] = s; prev.c[h] = c; prev.r[h] = r; prev.f[h] = flags;
-    const int pid = tp->pair[2 * L.sg + h];
-    if (L.start && pid >= 0) {
+    if (L.start && pid[h] >= 0) {
       DevResult res;
       res.score = s;
       res.qend = s > 0 ? r : -1;
       res.rend = s > 0 ? c : -1;
       res.flags = flags;
-      results[pairs[pid].out] = res;
+      results[pairs[pid[h]].out] = res;
     }
   }
 }
@@ -555,11 +633,13 @@ __device__ __forceinline__ void shared_task(const KArgs &a, const Task &t, const
       fb_out = a.bnd_out + base + fofs;
     }
   }
-  run_columns<O, SEG, P, CHUNKED, LAZY>(st, L, pr, pm, a.streams + t.stream_off, t.ncols, hb_in,
-                                        fb_in, hb_out, fb_out, lazy_steps);
+  const StreamSrc src{(const uint2 *)(a.streams + t.stream_off) + L.sg};
+  run_columns<O, SEG, P, CHUNKED, LAZY>(st, L, pr, pm, src, t.ncols, hb_in, fb_in, hb_out,
+                                        fb_out, lazy_steps);
   cols += (unsigned long long)t.ncols;
   events += st.events;
-  finish<O, SEG>(st, L, tp, a.pairs, a.results, a.chunk * P * SEG, prev, a.sat_cap);
+  const int pid[2] = {tp->pair[2 * L.sg], tp->pair[2 * L.sg + 1]};
+  finish<O, SEG>(st, L, pid, a.pairs, a.results, a.chunk * P * SEG, prev, a.sat_cap);
 }
 
 template <class O, int S16, int S32, int S64, bool CHUNKED, bool LAZY>
@@ -612,6 +692,72 @@ void shared_kernel(KArgs a, uint32_t mode_mask) {
     if (cols) atomicAdd(&a.stats[0], cols);
     if (lazy_steps) atomicAdd(&a.stats[1], (unsigned long long)lazy_steps);
     if (events) atomicAdd(&a.stats[2], events);
+  }
+}
+
+// ================================================================ device-planned shared-query kernel
+
+// One query (one chunk), one sub-group width.  Task t is entries
+// [t*slots, (t+1)*slots) of the planner's longest-first order, entry
+// t*slots + s going to sub-group s / halves, half s % halves; the task runs
+// as many columns as its longest reference (rounded up to a block).  Residues
+// come from the references themselves.  Nothing runs when the planner or the
+// residue check flagged the batch (the host then reports the error).
+template <class O, int SEG, int P>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+void shared_direct_kernel(KArgs a) {
+  if (a.plan_meta[kMetaErrResidue] | a.plan_meta[kMetaErrPair]) return;
+  stage_matrix(a);
+  __syncthreads();
+  const uint32_t off = matrix_lds_bytes(a.alpha);
+  build_shared_profile<O, SEG, P>(a, off);
+  __syncthreads();
+  constexpr int kSlotsPerTask = (kWave / P) * O::kHalves;
+  const int nvalid = a.plan_meta[kMetaValid];
+  const int ntasks = (nvalid + kSlotsPerTask - 1) / kSlotsPerTask;
+  const LaneCtx L = make_lane<O>(P == 16 ? 0xF : (P == 32 ? 0x5 : 0x1), SEG,
+                                 (uint32_t)a.gap_extend);
+  const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
+  SharedMap<O, SEG, P> pm;
+  pm.lane_base = off + L.l * O::kES;
+  const uint32_t sentw = (uint32_t)a.alpha * 0x01010101u;
+  uint32_t lazy_steps = 0;
+  unsigned long long cols = 0, events = 0, padded = 0;
+  for (;;) {
+    const int ti = pop_task(a.plan_meta + kMetaCounter);
+    if (ti >= ntasks) break;
+    int pid[2] = {-1, -1};
+    int64_t roff[2] = {0, 0};
+    int n[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < O::kHalves; ++h) {
+      const int e = ti * kSlotsPerTask + L.sg * O::kHalves + h;
+      if (e < nvalid) {
+        pid[h] = a.order[e];
+        const PairInfo p = a.pairs[pid[h]];
+        roff[h] = p.r_off;
+        n[h] = p.n;
+      }
+    }
+    int nmax = max(n[0], n[1]);
+    for (int d = 1; d < kWave; d <<= 1) nmax = max(nmax, __shfl_xor(nmax, d));
+    const int ncols = (nmax + kBlock - 1) / kBlock * kBlock;
+    Prev prev;
+    prev_reset(prev);
+    State<SEG> st;
+    state_reset(st, 0u);
+    const DirectSrc src{a.ref_res + roff[0], a.ref_res + roff[1], n[0], n[1], sentw};
+    run_columns<O, SEG, P, false, false>(st, L, pr, pm, src, ncols, nullptr, nullptr, nullptr,
+                                         nullptr, lazy_steps);
+    cols += (unsigned long long)ncols;
+    events += st.events;
+    padded += (unsigned long long)min(kSlotsPerTask, nvalid - ti * kSlotsPerTask) * ncols * P * SEG;
+    finish<O, SEG>(st, L, pid, a.pairs, a.results, 0, prev, a.sat_cap);
+  }
+  if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
+    if (cols) atomicAdd(&a.stats[0], cols);
+    if (events) atomicAdd(&a.stats[2], events);
+    if (padded) atomicAdd(&a.stats[3], padded);
   }
 }
 
@@ -695,11 +841,13 @@ void pair_kernel(KArgs a) {
         fb_in = rd + base + fofs;
         if (ch + 1 < nch) { hb_out = wr + base; fb_out = wr + base + fofs; }
       }
-      run_columns<O, SEG, PMAX, CHUNKED, false>(st, L, pr, pm, a.streams + t.stream_off, t.ncols,
-                                                hb_in, fb_in, hb_out, fb_out, lazy_steps);
+      const StreamSrc src{(const uint2 *)(a.streams + t.stream_off) + L.sg};
+      run_columns<O, SEG, PMAX, CHUNKED, false>(st, L, pr, pm, src, t.ncols, hb_in, fb_in,
+                                                hb_out, fb_out, lazy_steps);
       cols += (unsigned long long)t.ncols;
       events += st.events;
-      finish<O, SEG>(st, L, a.tasks + ti, a.pairs, a.results, row0, prev, a.sat_cap);
+      const int pid[2] = {t.pair[2 * L.sg], t.pair[2 * L.sg + 1]};
+      finish<O, SEG>(st, L, pid, a.pairs, a.results, row0, prev, a.sat_cap);
     }
   }
   if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {

@@ -69,8 +69,26 @@ struct KArgs {
   uint32_t *bnd;              // per-pair kernel: double-buffered boundaries
   int64_t bnd_half;           // per-pair kernel: element distance between the two buffers
   DevResult *results;
-  unsigned long long *stats;  // [0] column steps, [1] lazy-F inner steps, [2] record branches
+  unsigned long long *stats;  // [0] column steps, [1] lazy-F inner steps, [2] record branches,
+                              // [3] padded cells (device-planned launches)
+  // device-planned shared-query launches (tasks are implicit, residues are
+  // read from the references directly)
+  const int32_t *order;       // valid pairs, longest reference first
+  int32_t *plan_meta;         // kMeta* words
+  const uint8_t *ref_res;     // residues of every reference (device)
 };
+
+// Device planner of a single-query batch: words of the plan_meta array.
+enum : int {
+  kMetaValid = 0,       // pairs with m > 0 and n > 0 (entries of `order`)
+  kMetaCounter = 1,     // task counter of the alignment kernel
+  kMetaErrResidue = 2,  // set if a residue code is >= alpha
+  kMetaErrPair = 3,     // set if a pair's reference id or offsets are invalid
+  kMetaWords = 16
+};
+// Length bins of the planner's counting sort: bin = ceil(n / kBlock), the
+// last bin also takes every longer reference.
+constexpr int kPlanBins = 4096;
 
 // Host-side launchers (defined in sw_kernels.hip).
 enum Prec { PREC_I16X2 = 0, PREC_I32 = 1 };
@@ -100,6 +118,29 @@ hipError_t launch_build_streams(const Task *tasks, int ntasks, const PairInfo *p
 
 // p[0..n) = v.
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+
+// Device planner of a single-query batch (query length m at q_off0).
+// plan_count: PairInfo of every pair with its reference checked (0 <= id <
+// n_refs, 0 <= roff[id] <= roff[id+1] <= ref_bytes; otherwise
+// meta[kMetaErrPair] is set and the pair gets n = 0), results set to
+// {0, -1, -1, 0}, and a histogram of ceil(n/4) over the pairs with m, n > 0.
+hipError_t launch_plan_count(int n_pairs, const int64_t *roff, const int32_t *pq,
+                             const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
+                             int64_t q_off0, PairInfo *pairs, DevResult *results, int32_t *hist,
+                             int32_t *meta, hipStream_t st);
+// plan_scan: cursor[bin] = first position of the bin in the longest-first
+// order; meta[kMetaValid] = number of entries; meta[kMetaCounter] = 0.
+hipError_t launch_plan_scan(const int32_t *hist, int32_t *cursor, int32_t *meta, hipStream_t st);
+// plan_scatter: order[...] = every pair with m, n > 0, longest reference first
+// (pairs of one bin in any order).
+hipError_t launch_plan_scatter(int n_pairs, const PairInfo *pairs, int32_t *cursor,
+                               int32_t *order, hipStream_t st);
+// Device-planned shared-query kernel: rows per lane `seg`, `lanes` lanes per
+// alignment; a.order / a.plan_meta / a.ref_res describe the work.
+bool shared_direct_has(Prec prec, int seg, int lanes);
+size_t shared_direct_lds_bytes(Prec prec, int seg, int lanes, int alpha);
+hipError_t launch_shared_direct(Prec prec, int seg, int lanes, const KArgs &a, int grid,
+                                hipStream_t st);
 
 // Sets every result to {0, -1, -1, 0}.
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);

@@ -14,6 +14,8 @@ hipError_t launch_pair_i16(int seg, int pmax, bool chunked, const KArgs &a, int 
                            hipStream_t st, size_t lds);
 hipError_t launch_pair_i32(int seg, int pmax, bool chunked, const KArgs &a, int grid,
                            hipStream_t st, size_t lds);
+hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
+hipError_t launch_direct_i32(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
 
 namespace dev {
 // ================================================================ residue streams
@@ -70,6 +72,91 @@ __global__ __launch_bounds__(256) void build_pairs_kernel(int n_pairs, const int
   p.pad = 0;
   out[k] = p;
 }
+// ================================================================ device planner
+
+// PairInfo, validation, result initialisation and the length histogram.
+__global__ __launch_bounds__(256) void plan_count_kernel(int n_pairs, const int64_t *roff,
+                                                         const int32_t *pq, const int32_t *pr,
+                                                         int n_refs, int64_t ref_bytes, int m,
+                                                         int64_t q_off0, PairInfo *pairs,
+                                                         DevResult *results, int32_t *hist,
+                                                         int32_t *meta) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pairs) return;
+  const int q = pq ? pq[k] : 0;
+  const int r = pr[k];
+  bool ok = q == 0 && r >= 0 && r < n_refs;
+  int64_t ro = 0, re = 0;
+  if (ok) {
+    ro = roff[r];
+    re = roff[r + 1];
+    ok = ro >= 0 && ro <= re && re <= ref_bytes && re - ro <= 0x7fffffffll;
+  }
+  if (!ok) {
+    atomicOr(&meta[kMetaErrPair], 1);
+    ro = re = 0;
+  }
+  PairInfo p;
+  p.q_off = q_off0;
+  p.r_off = ro;
+  p.m = m;
+  p.n = (int)(re - ro);
+  p.out = k;
+  p.pad = 0;
+  pairs[k] = p;
+  DevResult v;
+  v.score = 0; v.qend = -1; v.rend = -1; v.flags = 0;
+  results[k] = v;
+  if (m > 0 && p.n > 0) {
+    const int bin = min((p.n + kBlock - 1) / kBlock, kPlanBins - 1);
+    atomicAdd(&hist[bin], 1);
+  }
+}
+
+// One workgroup: exclusive scan of the histogram from the longest bin down.
+__global__ __launch_bounds__(1024) void plan_scan_kernel(const int32_t *hist, int32_t *cursor,
+                                                         int32_t *meta) {
+  constexpr int kPer = kPlanBins / 1024;
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  // thread t owns positions [t*kPer, (t+1)*kPer) of the descending order
+  int v[kPer], sum = 0;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    v[q] = hist[kPlanBins - 1 - (t * kPer + q)];
+    sum += v[q];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {
+    const int x = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += x;
+    __syncthreads();
+  }
+  int run = part[t] - sum;   // exclusive prefix of this thread's positions
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    cursor[kPlanBins - 1 - (t * kPer + q)] = run;
+    run += v[q];
+  }
+  if (t == 1023) {
+    meta[kMetaValid] = part[1023];
+    meta[kMetaCounter] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void plan_scatter_kernel(int n_pairs, const PairInfo *pairs,
+                                                           int32_t *cursor, int32_t *order) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n_pairs) return;
+  const PairInfo p = pairs[k];
+  if (p.m > 0 && p.n > 0) {
+    const int bin = min((p.n + kBlock - 1) / kBlock, kPlanBins - 1);
+    order[atomicAdd(&cursor[bin], 1)] = k;
+  }
+}
+
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
@@ -112,6 +199,54 @@ hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *fl
   int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(dev::check_residues_kernel, dim3(grid), dim3(256), 0, st, p, n, alpha, flag);
   return hipGetLastError();
+}
+
+hipError_t launch_plan_count(int n_pairs, const int64_t *roff, const int32_t *pq,
+                             const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
+                             int64_t q_off0, PairInfo *pairs, DevResult *results, int32_t *hist,
+                             int32_t *meta, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::plan_count_kernel, dim3((n_pairs + 255) / 256), dim3(256), 0, st,
+                     n_pairs, roff, pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, hist,
+                     meta);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_scan(const int32_t *hist, int32_t *cursor, int32_t *meta, hipStream_t st) {
+  static_assert(kPlanBins % 1024 == 0, "plan bins");
+  hipLaunchKernelGGL(dev::plan_scan_kernel, dim3(1), dim3(1024), 0, st, hist, cursor, meta);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_scatter(int n_pairs, const PairInfo *pairs, int32_t *cursor,
+                               int32_t *order, hipStream_t st) {
+  if (n_pairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::plan_scatter_kernel, dim3((n_pairs + 255) / 256), dim3(256), 0, st,
+                     n_pairs, pairs, cursor, order);
+  return hipGetLastError();
+}
+
+static int direct_shape_index(int seg, int lanes) {
+  for (int k = 0; k < kNumDirectShapes; ++k)
+    if (kDirectShapes[k].seg == seg && kDirectShapes[k].lanes == lanes) return k;
+  return -1;
+}
+
+bool shared_direct_has(Prec, int seg, int lanes) { return direct_shape_index(seg, lanes) >= 0; }
+
+size_t shared_direct_lds_bytes(Prec prec, int seg, int lanes, int alpha) {
+  const int es = prec == PREC_I16X2 ? 2 : 4;
+  return matrix_lds_bytes(alpha) + (size_t)(alpha + 1) * dev::shared_cstride(seg, lanes, es);
+}
+
+hipError_t launch_shared_direct(Prec prec, int seg, int lanes, const KArgs &a, int grid,
+                                hipStream_t st) {
+  const int k = direct_shape_index(seg, lanes);
+  if (k < 0 || a.order == nullptr || a.plan_meta == nullptr || a.ref_res == nullptr)
+    return hipErrorInvalidValue;
+  const size_t lds = shared_direct_lds_bytes(prec, seg, lanes, a.alpha);
+  if (prec == PREC_I16X2) return launch_direct_i16(k, a, grid, st, lds);
+  return launch_direct_i32(k, a, grid, st, lds);
 }
 
 int shared_menu_count() { return kNumSharedMenus; }

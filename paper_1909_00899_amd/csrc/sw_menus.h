@@ -14,6 +14,14 @@ constexpr SharedMenu kSharedMenus[] = {
 };
 constexpr int kNumSharedMenus = sizeof(kSharedMenus) / sizeof(kSharedMenus[0]);
 
+// Device-planned shared-query kernel: (rows per lane, lanes) compiled; the
+// narrowest mode of each shared menu above.
+struct DirectShape { int seg, lanes; };
+constexpr DirectShape kDirectShapes[] = {
+    {4, 16}, {8, 16}, {12, 16}, {16, 16}, {12, 32}, {16, 32},
+};
+constexpr int kNumDirectShapes = sizeof(kDirectShapes) / sizeof(kDirectShapes[0]);
+
 // Per-pair kernel: rows per lane compiled.
 constexpr int kPairSegs[] = {4, 6, 8, 10, 12, 16};
 constexpr int kNumPairSegs = sizeof(kPairSegs) / sizeof(kPairSegs[0]);

@@ -19,8 +19,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <array>
 #include <functional>
 #include <mutex>
+#include <thread>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -512,7 +514,84 @@ bool layout_valid(int layout, int pmax) {
   return true;
 }
 
+int host_threads() {
+  static const int n = std::max(1, std::min(8, (int)std::thread::hardware_concurrency()));
+  return n;
+}
+
+void parallel_ranges(size_t n, int T, const std::function<void(int, size_t, size_t)> &fn) {
+  T = (int)std::max<size_t>(1, std::min<size_t>((size_t)T, n));
+  if (T <= 1) { fn(0, 0, n); return; }
+  std::vector<std::thread> th;
+  th.reserve(T - 1);
+  for (int t = 1; t < T; ++t) th.emplace_back(fn, t, n * t / T, n * (t + 1) / T);
+  fn(0, 0, n / T);
+  for (auto &x : th) x.join();
+}
+
 namespace {
+
+// Packs sorted pair records into wavefront tasks (appended to `out`).
+// A pair takes the next free rows of the open task (32-lane groups start at
+// lane 0 or 32); in int16x2 mode the high half of a sub-group takes the next
+// pair of the same width if its reference fits the task's columns.
+void pack_pairs(const PackRec *rec, int count, int pmax, int halves, std::vector<Task> &out,
+                int lanes_used[3]) {
+  int ti = -1, rows = 4, nsg = 0, maxn = 1;
+  int half_task[3] = {-1, -1, -1}, half_slot[3] = {0, 0, 0};
+  auto close = [&]() {
+    if (ti < 0) return;
+    Task &t = out[ti];
+    for (int r = rows; r < 4;) {   // unused rows: empty sub-groups
+      t.layout |= 1 << r;
+      r += ((r & 1) == 0 && pmax >= 32) ? 2 : 1;
+    }
+    t.ncols = round_up(maxn, kBlock);
+    ti = -1;
+  };
+  for (int x = 0; x < count; ++x) {
+    const PackRec &it = rec[x];
+    const int P = it.P;
+    const int pc = P == 16 ? 0 : (P == 32 ? 1 : 2);
+    lanes_used[pc]++;
+    if (halves == 2 && half_task[pc] >= 0) {
+      // the second half of a sub-group opened by an earlier pair of this
+      // width (as many or more chunks), if its columns cover this reference
+      Task &h = out[half_task[pc]];
+      if (half_task[pc] == ti || it.n <= h.ncols) {
+        h.pair[half_slot[pc]] = it.pair;
+        if (half_task[pc] == ti) maxn = std::max(maxn, it.n);
+        half_task[pc] = -1;
+        continue;
+      }
+      half_task[pc] = -1;
+    }
+    int pos = P == 16 ? rows : (P == 32 ? (rows + 1) & ~1 : (rows == 0 ? 0 : 4));
+    if (ti < 0 || pos + P / 16 > 4) {
+      close();
+      Task t;
+      std::memset(&t, 0, sizeof(t));
+      t.nchunks = it.nch;   // the most of any pair it will hold (sorted)
+      t.bnd_off = -1;
+      for (int s2 = 0; s2 < kSlots; ++s2) t.pair[s2] = -1;
+      out.push_back(t);
+      ti = (int)out.size() - 1;
+      rows = 0;
+      nsg = 0;
+      maxn = 1;
+      pos = 0;
+    }
+    Task &t = out[ti];
+    for (int r = rows; r < pos; ++r) { t.layout |= 1 << r; ++nsg; }   // skipped row
+    t.layout |= 1 << pos;
+    t.pair[2 * nsg] = it.pair;
+    if (halves == 2) { half_task[pc] = ti; half_slot[pc] = 2 * nsg + 1; }
+    ++nsg;
+    rows = pos + P / 16;
+    maxn = std::max(maxn, it.n);
+  }
+  close();
+}
 
 // Per-pair launches.  Every pair gets a shape (lanes P, rows per lane, query
 // chunks); pairs of one launch share rows per lane and chunk count.  With
@@ -657,7 +736,7 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
   }
   // ---- order: by class, then query chunks and reference length (most work
   // first), stable; one counting sort into compact records so that packing
-  // reads sequentially
+  // reads sequentially (per-thread histograms for large batches)
   const int ncls = (int)cls.size();
   int nlo = items[0].n, nhi = items[0].n;
   for (size_t k = 0; k < cnt; ++k) { nlo = std::min(nlo, items[k].n); nhi = std::max(nhi, items[k].n); }
@@ -666,13 +745,40 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
   std::vector<PackRec> &rec = hs.packed;
   rec.resize(cnt);
   hs.bounds.assign(ncls + 1, 0);
-  if (keys <= 4 * (int64_t)cnt + 4096) {
+  auto key_of = [&](size_t k) {
+    const int s = hs.slot[k];
+    return ((cls_of[s] * max_nch) + (max_nch - shape[s].nchunks)) * (int)range + (nhi - items[k].n);
+  };
+  if (keys <= 65536 && cnt >= 50000) {
+    const int T = host_threads();
+    std::vector<std::vector<int>> h(T, std::vector<int>((size_t)keys, 0));
+    hs.order.resize(cnt);
+    parallel_ranges(cnt, T, [&](int t, size_t lo, size_t hi) {
+      int *ht = h[t].data();
+      for (size_t k = lo; k < hi; ++k) {
+        const int key = key_of(k);
+        hs.order[k] = key;
+        ht[key]++;
+      }
+    });
+    int run = 0;
+    for (int64_t key = 0; key < keys; ++key) {
+      if (key % (max_nch * range) == 0) hs.bounds[key / (max_nch * range)] = run;
+      for (int t = 0; t < T; ++t) { const int c = h[t][key]; h[t][key] = run; run += c; }
+    }
+    hs.bounds[ncls] = run;
+    parallel_ranges(cnt, T, [&](int t, size_t lo, size_t hi) {
+      int *ht = h[t].data();
+      for (size_t k = lo; k < hi; ++k) {
+        const int s = hs.slot[k];
+        rec[ht[hs.order[k]]++] = PackRec{items[k].pair, items[k].n, shape[s].P, shape[s].nchunks};
+      }
+    });
+  } else if (keys <= 4 * (int64_t)cnt + 4096) {
     hs.count.assign((size_t)keys + 1, 0);
     hs.order.resize(cnt);   // sort key of each item
     for (size_t k = 0; k < cnt; ++k) {
-      const int s = hs.slot[k];
-      const int key = ((cls_of[s] * max_nch) + (max_nch - shape[s].nchunks)) * (int)range +
-                      (nhi - items[k].n);
+      const int key = key_of(k);
       hs.order[k] = key;
       hs.count[key + 1]++;
     }
@@ -710,60 +816,22 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
     L.pmax = K.pmax;
     L.nchunks = K.chunked ? 2 : 1;   // > 1: the chunked kernel (per-task counts)
     L.task_begin = (int)tasks.size();
-    int ti = -1, rows = 4, nsg = 0, maxn = 1;
-    int half_task[3] = {-1, -1, -1}, half_slot[3] = {0, 0, 0};
-    auto close = [&]() {
-      if (ti < 0) return;
-      Task &t = tasks[ti];
-      for (int r = rows; r < 4;) {   // unused rows: empty sub-groups
-        t.layout |= 1 << r;
-        r += ((r & 1) == 0 && K.pmax >= 32) ? 2 : 1;
+    if (b - a >= 50000) {
+      // large classes: contiguous sub-ranges packed on several threads, then
+      // concatenated in order (each sub-range may end in one partial task)
+      const int T = host_threads();
+      std::vector<std::vector<Task>> part(T);
+      std::vector<std::array<int, 3>> lu(T, std::array<int, 3>{0, 0, 0});
+      parallel_ranges((size_t)(b - a), T, [&](int t, size_t lo, size_t hi) {
+        pack_pairs(rec.data() + a + lo, (int)(hi - lo), K.pmax, halves, part[t], lu[t].data());
+      });
+      for (int t = 0; t < T; ++t) {
+        tasks.insert(tasks.end(), part[t].begin(), part[t].end());
+        for (int q = 0; q < 3; ++q) stats.lanes_used[q] += lu[t][q];
       }
-      t.ncols = round_up(maxn, kBlock);
-      ti = -1;
-    };
-    for (int x = a; x < b; ++x) {
-      const PackRec &it = rec[x];
-      const int P = it.P;
-      const int pc = P == 16 ? 0 : (P == 32 ? 1 : 2);
-      stats.lanes_used[pc]++;
-      if (halves == 2 && half_task[pc] >= 0) {
-        // the second half of a sub-group opened by an earlier pair of this
-        // width (as many or more chunks), if its columns cover this reference
-        Task &h = tasks[half_task[pc]];
-        if (half_task[pc] == ti || it.n <= h.ncols) {
-          h.pair[half_slot[pc]] = it.pair;
-          if (half_task[pc] == ti) maxn = std::max(maxn, it.n);
-          half_task[pc] = -1;
-          continue;
-        }
-        half_task[pc] = -1;
-      }
-      int pos = P == 16 ? rows : (P == 32 ? (rows + 1) & ~1 : (rows == 0 ? 0 : 4));
-      if (ti < 0 || pos + P / 16 > 4) {
-        close();
-        Task t;
-        std::memset(&t, 0, sizeof(t));
-        t.nchunks = it.nch;   // the most of any pair it will hold (sorted)
-        t.bnd_off = -1;
-        for (int s2 = 0; s2 < kSlots; ++s2) t.pair[s2] = -1;
-        tasks.push_back(t);
-        ti = (int)tasks.size() - 1;
-        rows = 0;
-        nsg = 0;
-        maxn = 1;
-        pos = 0;
-      }
-      Task &t = tasks[ti];
-      for (int r = rows; r < pos; ++r) { t.layout |= 1 << r; ++nsg; }   // skipped row
-      t.layout |= 1 << pos;
-      t.pair[2 * nsg] = it.pair;
-      if (halves == 2) { half_task[pc] = ti; half_slot[pc] = 2 * nsg + 1; }
-      ++nsg;
-      rows = pos + P / 16;
-      maxn = std::max(maxn, it.n);
+    } else {
+      pack_pairs(rec.data() + a, b - a, K.pmax, halves, tasks, stats.lanes_used);
     }
-    close();
     L.task_end = (int)tasks.size();
     for (int t = L.task_begin; t < L.task_end; ++t) {
       Task &tk = tasks[t];
@@ -920,8 +988,10 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
         const int pid = tk.pair[s2];
         ok = ok && pid >= -1 && pid < n_pairs_total;
         if (pid >= 0) {
-          ok = ok && s2 / 2 < ngroups && nlen[pid] >= 0 && nlen[pid] <= tk.ncols &&
-               pid < n_results;
+          // each planned pair sits in exactly one slot (nlen = -2 once seen)
+          const int n = nlen[pid];
+          nlen[pid] = -2;
+          ok = ok && s2 / 2 < ngroups && n >= 0 && n <= tk.ncols && pid < n_results;
           // per-pair: the task's chunks of this sub-group cover the query
           if (ok && !L.shared)
             ok = tk.nchunks >= 1 && (chunked || tk.nchunks == 1) &&
@@ -935,6 +1005,11 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
       }
     }
   }
+  for (const auto &it : in.items)
+    if (nlen[it.pair] != -2) {
+      set_error("internal planner error: pair %d is in no task", it.pair);
+      return SW_EINVAL;
+    }
   const size_t n_launch_total = [&] { size_t c = 0; for (auto &L : launches) c += L.shared ? L.nchunks : 1; return c; }();
   const size_t misc_bytes = 32 + 4 * n_launch_total + 16;   // stats (3 x u64, padded) + counters
   if ((rc = ws.tasks.ensure(tasks.size() * sizeof(Task))) ||

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -109,6 +110,11 @@ struct HostScratch {
   std::vector<swk::Task> tasks;
   LengthIndex lengths;
 };
+
+// Host threads for the planner's large passes, and a helper that runs
+// fn(t, begin, end) over T contiguous ranges of [0, n) (the caller runs t = 0).
+int host_threads();
+void parallel_ranges(size_t n, int T, const std::function<void(int, size_t, size_t)> &fn);
 
 // Sub-group widths (lanes) of a wavefront layout (bit r set <=> a sub-group
 // starts at lane 16*r); returns their number.

@@ -27,7 +27,28 @@ hipError_t dispatch(int menu, const KArgs &a, int grid, hipStream_t st, uint32_t
   }
   return hipErrorInvalidValue;
 }
+template <int K>
+hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  constexpr DirectShape ds = kDirectShapes[K];
+  auto k = dev::shared_direct_kernel<O, ds.seg, ds.lanes>;
+  hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kWavesPerGroup * kWave), lds, st, a);
+  return hipGetLastError();
+}
 }  // namespace
+
+hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  static_assert(kNumDirectShapes == 6, "direct shapes");
+  switch (shape) {
+    case 0: return launch_d<0>(a, grid, st, lds);
+    case 1: return launch_d<1>(a, grid, st, lds);
+    case 2: return launch_d<2>(a, grid, st, lds);
+    case 3: return launch_d<3>(a, grid, st, lds);
+    case 4: return launch_d<4>(a, grid, st, lds);
+    case 5: return launch_d<5>(a, grid, st, lds);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_shared_i16(Alg alg, int menu, bool chunked, const KArgs &a, int grid,
                               hipStream_t st, uint32_t mask, size_t lds) {

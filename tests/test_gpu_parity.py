@@ -189,7 +189,8 @@ def test_protein_search_subset():
 
 
 def test_dna_pairs_subset():
-    w = W.dna_pairs(n_pairs=20000)
+    # 60k pairs: large enough for the planner's multi-threaded sort and packing
+    w = W.dna_pairs(n_pairs=60000)
     want = oracle_batch(w)
     got = api.align_workload(w)
     assert_same(got.results, want, w, "dna_pairs")
