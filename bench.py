@@ -2,12 +2,13 @@
 
 One step = one sw_align_batch call over the protein-search workload (one
 512-residue query vs 100k log-normal references, inputs resident in HBM as
-torch tensors): planning, residue streams, the persistent int16x2 scan kernel
-and any int32 reruns, results copied back.  The call's device work is replayed
-from a hipGraph captured during warm-up (identical parameters every step); an
-eager leg of the same steps gives the per-launch kernel time for the roofline.
-The autotuner picks the tile shapes before the timed region.  Prints ONE JSON
-line.
+torch tensors): the device planner (pair checks, length ordering and task
+packing on the GPU), the persistent int16x2 scan kernel and any int32 reruns,
+results copied back.  The call's device work is replayed from a hipGraph
+captured during warm-up (identical parameters every step); an eager leg of the
+same steps gives the per-launch kernel time for the roofline, and a leg with
+the host planner is timed beside it.  The autotuner picks the tile shapes
+before the timed region.  Prints ONE JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
 """
@@ -147,12 +148,28 @@ def main():
         "stats": {k: out.stats[k] for k in ("n_rerun", "n_launches", "lanes_used",
                                             "seglen_max", "padded_cells", "total_ms", "prep_ms",
                                             "plan_ms", "launch_ms", "finish_ms", "columns",
-                                            "record_events")},
+                                            "record_events", "planner_used")},
         "tuned": {"seconds": round(tune_s, 3),
                   "entries": [{k: (round(v, 1) if isinstance(v, float) else v)
                                for k, v in e.items()} for e in tuned]},
     }
     rec["eager"] = {"ms_per_step": round(eager_ms, 3), "gcups": round(cells / eager_ms / 1e6, 2)}
+    # the same calls with the host planner (offsets read back, pairs sorted and
+    # packed on the host, residue streams built on the device)
+    for _ in range(2):
+        oh = api.sw_align_batch(d["qres"], d["qoff"], d["rres"], d["roff"], d["pref"], w.matrix,
+                                w.gap_open, w.gap_extend, planner=1)
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    for _ in range(args.steps):
+        oh = api.sw_align_batch(d["qres"], d["qoff"], d["rres"], d["roff"], d["pref"], w.matrix,
+                                w.gap_open, w.gap_extend, planner=1)
+    torch.cuda.synchronize()
+    host_ms = (time.perf_counter() - th) / args.steps * 1e3
+    rec["host_planner"] = {"ms_per_step": round(host_ms, 3),
+                           "gcups": round(cells / host_ms / 1e6, 2),
+                           "kernel_ms": round(oh.stats["kernel_ms"], 4),
+                           "same_results": bool(np.array_equal(oh.results, out.results))}
     rec["graph"] = {"used": bool(use_graph), "graph_hits": og.stats["graph_hits"],
                     "same_results_as_eager": bool(np.array_equal(og.results, out.results))}
 

@@ -168,7 +168,17 @@ typedef struct {
                                     hipGraph: captured on first use, replayed when
                                     a later call has identical parameters; then
                                     kernel_ms spans the whole graph             */
-    int32_t reserved[9];
+    int32_t planner;             /* 0 = device planner for a batch with one query
+                                    (pair_query NULL or n_queries 1) of at most 512
+                                    residues and at least 4096 pairs, host planner
+                                    otherwise; 1 = host planner; 2 = device planner
+                                    (SW_EINVAL if the batch does not qualify).  The
+                                    device planner validates, orders and packs the
+                                    pairs on the GPU and reads residues straight
+                                    from the references; only the query's offsets
+                                    and the sets' end offsets are read by the host
+                                    before the launch.                             */
+    int32_t reserved[8];
 } sw_options;
 
 typedef struct {
@@ -190,7 +200,8 @@ typedef struct {
                                     wavefront set a new running maximum         */
     int32_t graph_hits;          /* use_graph: executions replayed from a cached
                                     graph (no capture)                          */
-    int32_t reserved[7];
+    int32_t planner_used;        /* 1 = host planner, 2 = device planner        */
+    int32_t reserved[6];
 } sw_stats;
 
 int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options *opt,

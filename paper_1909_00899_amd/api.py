@@ -65,7 +65,8 @@ class Options(ctypes.Structure):
     _fields_ = [("algorithm", ctypes.c_int32), ("force_lanes", ctypes.c_int32),
                 ("force_seglen", ctypes.c_int32), ("force_kernel", ctypes.c_int32),
                 ("mixed_layout", ctypes.c_int32), ("int16_cap", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("use_graph", ctypes.c_int32), ("planner", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 class Stats(ctypes.Structure):
@@ -77,7 +78,8 @@ class Stats(ctypes.Structure):
                 ("prep_ms", ctypes.c_double), ("plan_ms", ctypes.c_double),
                 ("launch_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
                 ("record_events", ctypes.c_int64), ("graph_hits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("planner_used", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
     def as_dict(self) -> dict:
         return {"kernel_ms": self.kernel_ms, "total_ms": self.total_ms, "cells": self.cells,
@@ -86,7 +88,8 @@ class Stats(ctypes.Structure):
                 "columns": self.columns, "lanes_used": list(self.lanes_used),
                 "seglen_max": self.seglen_max, "prep_ms": self.prep_ms, "plan_ms": self.plan_ms,
                 "launch_ms": self.launch_ms, "finish_ms": self.finish_ms,
-                "record_events": self.record_events, "graph_hits": self.graph_hits}
+                "record_events": self.record_events, "graph_hits": self.graph_hits,
+                "planner_used": self.planner_used}
 
 
 SW_TUNE_SHARED, SW_TUNE_PAIR = 0, 1
@@ -264,7 +267,7 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                    gap_extend: int, pair_query=None, precision: int = SW_PREC_AUTO,
                    algorithm: int = SW_ALG_SCAN, force_lanes: int = 0, force_seglen: int = 0,
                    force_kernel: int = 0, mixed_layout: int = 0, int16_cap: int = 0,
-                   use_graph: int = 0) -> BatchOutput:
+                   use_graph: int = 0, planner: int = 0) -> BatchOutput:
     """Many pairs in one persistent launch (plus an int32 rerun if needed).
 
     Sequences are CSR.  Either all six arrays are numpy (host) or all are torch
@@ -275,7 +278,7 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                                   precision)
     sc, M = make_scoring(matrix, gap_open, gap_extend)
     opt = Options(algorithm, force_lanes, force_seglen, force_kernel, mixed_layout, int16_cap,
-                  use_graph)
+                  use_graph, planner)
     out = np.zeros((max(npairs, 1), 4), dtype=np.int32)
     st = Stats()
     _check(lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),

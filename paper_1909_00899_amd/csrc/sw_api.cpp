@@ -251,7 +251,7 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
     }
     if (opt->force_seglen < 0 || opt->int16_cap < 0 || opt->int16_cap > 32767 ||
         opt->mixed_layout < 0 || opt->mixed_layout > 2 || opt->use_graph < 0 || opt->use_graph > 1 ||
-        opt->force_kernel < 0 || opt->force_kernel > 2) {
+        opt->force_kernel < 0 || opt->force_kernel > 2 || opt->planner < 0 || opt->planner > 2) {
       set_error("bad option value");
       return SW_EINVAL;
     }
@@ -272,6 +272,10 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
   std::lock_guard<std::mutex> g(g_ctx.mu);
   Context &C = g_ctx;
   HIPCHK(hipSetDevice(C.device));
+  bool handled = false;
+  rc = run_device_plan(b, S, eo, opt ? opt->planner : 0, C, out, stats, t0, handled);
+  if (handled) return rc;
+  if (rc) return rc;
   ExecInput in;
   int64_t cells = 0;
   if ((rc = prepare_batch(b, S, C, in, out, cells))) return rc;

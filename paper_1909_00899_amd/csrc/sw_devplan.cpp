@@ -1,0 +1,359 @@
+// Device planner for single-query batches (sw_align_batch with one query):
+// the pairs are validated, counted by reference length, ordered longest
+// first and run by the shared-query kernel entirely on the device; the host
+// reads four offsets before the launch and the results after it.
+//
+// Steps on the device (one stream, capturable as one hipGraph):
+//   matrix upload, clearing of the plan words (a fill kernel),
+//   residue checks of the query and reference sets,
+//   plan_count   PairInfo, reference checks, result initialisation, histogram
+//                of ceil(n / 4) and the sum of the reference lengths,
+//   plan_scan    longest-first bin starts, number of runnable pairs,
+//   plan_scatter the longest-first order,
+//   shared_direct_kernel  one persistent launch; task t = entries
+//                [t*slots, (t+1)*slots) of the order, residues read from the
+//                references.
+// The alignment arithmetic is the same column step as every other launch of
+// this library (Algorithm 6 with the max-plus scan).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "sw.h"
+#include "sw_internal.h"
+#include "sw_menus.h"
+#include "sw_runtime.h"
+
+namespace swrt {
+
+using namespace swk;
+
+#define HIPCHK(expr)                                                             \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                __LINE__);                                                       \
+      return SW_EDEVICE;                                                         \
+    }                                                                            \
+  } while (0)
+
+namespace {
+
+constexpr int kDevPlanMinPairs = 4096;   // smaller batches: the host planner
+constexpr int64_t kI32Limit = 2147483647ll;
+
+// Layout of the plan buffer, in int32 words.
+constexpr int kPlanStats = 0;                       // 8 x u64: stats words
+constexpr int kPlanMeta = 16;                       // kMetaWords
+constexpr int kPlanHist = kPlanMeta + kMetaWords;   // kPlanBins
+constexpr int kPlanCursor = kPlanHist + kPlanBins;  // kPlanBins
+constexpr int kPlanOrder = kPlanCursor + kPlanBins; // n_pairs
+constexpr int kPlanCleared = kPlanHist + kPlanBins; // words cleared per call
+
+// The (rows per lane, lanes) shape for query length m: the caller's forced
+// shape, else the autotuner's entry, else the smallest compiled shape that
+// holds the query in one chunk.  False if none applies.
+bool pick_direct_shape(Prec prec, int alpha, int m, const ExecOptions &eo, int &seg, int &lanes) {
+  if (eo.force_lanes || eo.force_seglen) {
+    for (int k = 0; k < kNumDirectShapes; ++k) {
+      const DirectShape d = kDirectShapes[k];
+      if ((eo.force_lanes == 0 || d.lanes == eo.force_lanes) &&
+          (eo.force_seglen == 0 || d.seg == eo.force_seglen) && d.seg * d.lanes >= m) {
+        seg = d.seg;
+        lanes = d.lanes;
+        return true;
+      }
+    }
+    return false;
+  }
+  sw_tune_entry te;
+  if (eo.use_tuning && tune_lookup(SW_TUNE_SHARED, prec, alpha, m, te) && te.lanes > 0 &&
+      shared_direct_has(prec, te.seglen, te.lanes) && te.seglen * te.lanes >= m) {
+    seg = te.seglen;
+    lanes = te.lanes;
+    return true;
+  }
+  for (int k = 0; k < kNumDirectShapes; ++k) {
+    const DirectShape d = kDirectShapes[k];
+    if (d.seg * d.lanes >= m) {
+      seg = d.seg;
+      lanes = d.lanes;
+      return true;
+    }
+  }
+  return false;
+}
+
+}  // namespace
+
+int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, int planner,
+                    Context &C, sw_result *out, sw_stats *stats, double t0, bool &handled) {
+  handled = false;
+  const int np = b->n_pairs;
+  // ---- does the batch qualify (everything here is host-side)
+  if (planner == 1) return SW_OK;
+  auto refuse = [&](const char *why) {
+    if (planner == 2) {
+      handled = true;
+      set_error("device planner: %s", why);
+      return SW_EINVAL;
+    }
+    return SW_OK;
+  };
+  if (eo.algorithm != SW_ALG_SCAN) return refuse("only the scan algorithm is device-planned");
+  if (eo.force_kernel == 2) return refuse("the per-pair kernel is host-planned");
+  if (b->pair_query && b->n_queries != 1) return refuse("more than one query");
+  if (planner == 0 && np < kDevPlanMinPairs) return SW_OK;
+  if (!b->query_res || !b->query_off || !b->ref_res || !b->ref_off || !b->pair_ref ||
+      b->n_queries < 1 || b->n_refs < 1)
+    return SW_OK;   // the host path reports the argument error
+  hipStream_t st = C.stream;
+  Workspace &ws = C.ws;
+  // query 0's offsets, the query set's end and the reference set's end
+  int64_t hv[4];
+  if (b->device_resident) {
+    if (b->stream) {
+      HIPCHK(hipEventRecord(C.evx, (hipStream_t)b->stream));
+      HIPCHK(hipStreamWaitEvent(st, C.evx, 0));
+    }
+    int rc = ws.staging.ensure(64);
+    if (rc) return rc;
+    int64_t *pv = ws.staging.as<int64_t>();
+    HIPCHK(hipMemcpyAsync(pv, b->query_off, 16, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pv + 2, b->query_off + b->n_queries, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pv + 3, b->ref_off + b->n_refs, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(hv, pv, sizeof(hv));
+  } else {
+    hv[0] = b->query_off[0];
+    hv[1] = b->query_off[1];
+    hv[2] = b->query_off[b->n_queries];
+    hv[3] = b->ref_off[b->n_refs];
+  }
+  const int64_t q_off0 = hv[0], qbytes = hv[2], rbytes = hv[3];
+  if (q_off0 < 0 || hv[1] < q_off0 || hv[1] > qbytes || hv[1] - q_off0 > kI32Limit || rbytes < 0)
+    return SW_OK;   // malformed offsets: the host path reports them
+  const int m = (int)(hv[1] - q_off0);
+  if (m == 0) return SW_OK;
+  if ((int64_t)m * S.max_s >= kI32Limit) return refuse("the query may overflow int32");
+  const Prec prec = (b->precision == SW_PREC_AUTO && S.fits_i16) ? PREC_I16X2 : PREC_I32;
+  int seg = 0, lanes = 0;
+  if (!pick_direct_shape(prec, S.alpha, m, eo, seg, lanes))
+    return refuse("no compiled shape holds the query in one chunk");
+  handled = true;
+
+  // ---- buffers
+  int rc;
+  const size_t plan_words = (size_t)kPlanOrder + np;
+  if ((rc = ws.plan.ensure(plan_words * sizeof(int32_t))) ||
+      (rc = ws.offs.ensure((size_t)np * sizeof(PairInfo) + 4096)) ||
+      (rc = ws.results.ensure((size_t)np * sizeof(DevResult))) ||
+      (rc = ws.matrix.ensure(sizeof(int) * S.M.size())) ||
+      (rc = ws.staging.ensure((sizeof(int) * S.M.size() + 63) / 64 * 64 +
+                              sizeof(int32_t) * (kPlanMeta + kMetaWords))))
+    return rc;
+  int32_t *plan = ws.plan.as<int32_t>();
+  unsigned long long *d_stats = (unsigned long long *)(plan + kPlanStats);
+  int32_t *meta = plan + kPlanMeta;
+  PairInfo *d_pairs = ws.offs.as<PairInfo>();
+  DevResult *d_res = ws.results.as<DevResult>();
+  // sequences and offsets on the device
+  const uint8_t *d_qres = b->query_res, *d_rres = b->ref_res;
+  const int64_t *d_roff = b->ref_off;
+  const int32_t *d_pq = b->pair_query, *d_pr = b->pair_ref;
+  if (!b->device_resident) {
+    if ((rc = C.qres.ensure(std::max<int64_t>(qbytes, 1))) ||
+        (rc = C.rres.ensure(std::max<int64_t>(rbytes, 1))) ||
+        (rc = ws.pairs.ensure(sizeof(int64_t) * (b->n_refs + 1) + sizeof(int32_t) * 2 * np + 64)))
+      return rc;
+    char *base = ws.pairs.as<char>();
+    const size_t o_roff = 0, o_pr = o_roff + sizeof(int64_t) * (b->n_refs + 1);
+    const size_t o_pq = o_pr + sizeof(int32_t) * np;
+    HIPCHK(hipMemcpyAsync(base + o_roff, b->ref_off, o_pr - o_roff, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + o_pr, b->pair_ref, sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
+    if (b->pair_query)
+      HIPCHK(hipMemcpyAsync(base + o_pq, b->pair_query, sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
+    if (qbytes) HIPCHK(hipMemcpyAsync(C.qres.p, b->query_res, qbytes, hipMemcpyHostToDevice, st));
+    if (rbytes) HIPCHK(hipMemcpyAsync(C.rres.p, b->ref_res, rbytes, hipMemcpyHostToDevice, st));
+    d_qres = C.qres.as<uint8_t>();
+    d_rres = C.rres.as<uint8_t>();
+    d_roff = (const int64_t *)(base + o_roff);
+    d_pr = (const int32_t *)(base + o_pr);
+    d_pq = b->pair_query ? (const int32_t *)(base + o_pq) : nullptr;
+  }
+  int *stg = ws.staging.as<int>();
+  std::memcpy(stg, S.M.data(), sizeof(int) * S.M.size());
+
+  // ---- the device work as a list of operations (eager or one graph)
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.pairs = d_pairs;
+  a.query_res = d_qres;
+  a.shared_q_off = q_off0;
+  a.shared_m = m;
+  a.alpha = S.alpha;
+  a.matrix = ws.matrix.as<int32_t>();
+  a.gap_open = S.go;
+  a.gap_extend = S.ge;
+  a.last_chunk = 1;
+  a.sat_cap = eo.int16_cap;
+  a.results = d_res;
+  a.stats = d_stats;
+  a.order = plan + kPlanOrder;
+  a.plan_meta = meta;
+  a.ref_res = d_rres;
+  const int slots = (kWave / lanes) * (prec == PREC_I16X2 ? 2 : 1);
+  const int ntasks_max = (np + slots - 1) / slots;
+  const int grid = std::max(1, std::min((ntasks_max + kWavesPerGroup - 1) / kWavesPerGroup,
+                                        C.num_cus * 2));
+  int32_t *cursor = plan + kPlanCursor;
+  int32_t *hist = plan + kPlanHist;
+  int32_t *order = plan + kPlanOrder;
+  const int ni = b->n_refs;
+  const int alpha = S.alpha;
+  const size_t mat_bytes = sizeof(int) * S.M.size();
+  int32_t *d_mat = ws.matrix.as<int32_t>();
+  auto prep = [=]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(d_mat, stg, mat_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)plan, kPlanCleared, 0u, st);
+    if (e == hipSuccess) e = launch_check_residues(d_qres, qbytes, alpha, meta + kMetaErrResidue, st);
+    if (e == hipSuccess) e = launch_check_residues(d_rres, rbytes, alpha, meta + kMetaErrResidue, st);
+    if (e == hipSuccess)
+      e = launch_plan_count(np, d_roff, d_pq, d_pr, ni, rbytes, m, q_off0, d_pairs, d_res, hist,
+                            meta, d_stats + 4, st);
+    if (e == hipSuccess) e = launch_plan_scan(hist, cursor, meta, st);
+    if (e == hipSuccess) e = launch_plan_scatter(np, d_pairs, cursor, order, st);
+    return e;
+  };
+  auto align = [=]() { return launch_shared_direct(prec, seg, lanes, a, grid, st); };
+  const double t_launch0 = now_ms();
+  ExecStats es;
+  es.plan_ms = t_launch0 - t0;
+  if (!eo.use_graph) {
+    hipError_t e = prep();
+    if (e != hipSuccess) { set_error("device planner: %s", hipGetErrorString(e)); return SW_EDEVICE; }
+    HIPCHK(hipEventRecord(C.ev0, st));
+    e = align();
+    if (e != hipSuccess) { set_error("device-planned launch: %s", hipGetErrorString(e)); return SW_EDEVICE; }
+    HIPCHK(hipEventRecord(C.ev1, st));
+  } else {
+    const uint64_t sig[] = {0xD1D1, (uint64_t)prec, (uint64_t)seg, (uint64_t)lanes,
+                            (uint64_t)grid, (uint64_t)np, (uint64_t)(uintptr_t)d_qres,
+                            (uint64_t)(uintptr_t)d_rres, (uint64_t)(uintptr_t)d_roff,
+                            (uint64_t)(uintptr_t)d_pq, (uint64_t)(uintptr_t)d_pr, (uint64_t)ni,
+                            (uint64_t)rbytes, (uint64_t)qbytes, (uint64_t)m, (uint64_t)q_off0,
+                            (uint64_t)alpha, (uint64_t)S.go, (uint64_t)S.ge,
+                            (uint64_t)eo.int16_cap, (uint64_t)(uintptr_t)plan,
+                            (uint64_t)(uintptr_t)d_pairs, (uint64_t)(uintptr_t)d_res,
+                            (uint64_t)(uintptr_t)d_mat, (uint64_t)(uintptr_t)stg};
+    const std::vector<uint64_t> sv(sig, sig + sizeof(sig) / sizeof(sig[0]));
+    hipGraphExec_t exec = ws.graphs.find(sv);
+    if (exec) {
+      es.graph_hits++;
+    } else {
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+      hipError_t e = prep();
+      if (e == hipSuccess) e = align();
+      hipGraph_t graph = nullptr;
+      const hipError_t ec = hipStreamEndCapture(st, &graph);
+      if (e != hipSuccess || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        set_error("device-planned capture: %s", hipGetErrorString(e != hipSuccess ? e : ec));
+        return SW_EDEVICE;
+      }
+      const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ei != hipSuccess) {
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(ei));
+        return SW_EDEVICE;
+      }
+      ws.graphs.put(sv, exec);
+    }
+    HIPCHK(hipEventRecord(C.ev0, st));
+    HIPCHK(hipGraphLaunch(exec, st));
+    HIPCHK(hipEventRecord(C.ev1, st));
+  }
+  const double t_fin0 = now_ms();
+  es.launch_ms = t_fin0 - t_launch0;
+  // ---- results, statistics and the plan's error words
+  // staging: [matrix | plan words read back]
+  unsigned char *tail = (unsigned char *)ws.staging.p + (mat_bytes + 63) / 64 * 64;
+  HIPCHK(hipMemcpyAsync(out, d_res, (size_t)np * sizeof(DevResult), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(tail, plan, (size_t)(kPlanMeta + kMetaWords) * sizeof(int32_t),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  unsigned long long hs[8];
+  int32_t hm[kMetaWords];
+  std::memcpy(hs, tail, sizeof(hs));
+  std::memcpy(hm, tail + kPlanMeta * sizeof(int32_t), sizeof(hm));
+  float kms = 0;
+  HIPCHK(hipEventElapsedTime(&kms, C.ev0, C.ev1));
+  if (hm[kMetaErrResidue] || hm[kMetaErrPair]) {
+    for (int k = 0; k < np; ++k) out[k] = sw_result{0, -1, -1, 0};
+    set_error(hm[kMetaErrResidue] ? "a residue code is >= alphabet_size"
+                                  : "a pair refers to a query other than 0, a reference out of "
+                                    "range, or reference offsets that are not nondecreasing");
+    return SW_EINVAL;
+  }
+  // ---- exact int32 rerun of the pairs whose int16 lanes saturated
+  std::vector<int> again;
+  if (prec == PREC_I16X2)
+    for (int k = 0; k < np; ++k)
+      if (out[k].flags & kFlagNeedsI32) again.push_back(k);
+  if (!again.empty()) {
+    std::vector<PairInfo> hp(np);
+    HIPCHK(hipMemcpyAsync(hp.data(), d_pairs, (size_t)np * sizeof(PairInfo), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    ExecInput in2;
+    in2.d_qres = d_qres;
+    in2.d_rres = d_rres;
+    in2.d_pairs = d_pairs;
+    in2.n_pairs = np;
+    for (int k : again) in2.items.push_back(PlanItem{k, 0, hp[k].m, hp[k].n});
+    in2.n_queries = 1;
+    in2.q_off_of_query = {q_off0};
+    in2.m_of_query = {m};
+    ExecOptions o2 = eo;
+    o2.force_lanes = 0;
+    o2.force_seglen = 0;
+    o2.use_graph = 0;
+    ExecStats es2;
+    if ((rc = execute(in2, S, PREC_I32, o2, ws, np, st, C.ev0, C.ev1, C.num_cus, es2, false)))
+      return rc;
+    std::vector<DevResult> hr(np);
+    HIPCHK(hipMemcpyAsync(hr.data(), d_res, (size_t)np * sizeof(DevResult), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k : again) {
+      out[k].score = hr[k].score;
+      out[k].query_end = hr[k].qend;
+      out[k].ref_end = hr[k].rend;
+      out[k].flags = SW_FLAG_SATURATED;
+    }
+    es.kernel_ms += es2.kernel_ms;
+    es.launches += es2.launches;
+  }
+  if (stats) {
+    stats->kernel_ms = kms + es.kernel_ms;
+    stats->total_ms = now_ms() - t0;
+    stats->cells = (int64_t)m * (int64_t)hs[4];
+    stats->padded_cells = (int64_t)hs[3];
+    stats->n_rerun = (int)again.size();
+    stats->n_launches = 1 + es.launches;
+    stats->columns = (int64_t)hs[0];
+    stats->record_events = (int64_t)hs[2];
+    stats->lanes_used[lanes == 16 ? 0 : (lanes == 32 ? 1 : 2)] = hm[kMetaValid];
+    stats->seglen_max = seg;
+    stats->prep_ms = 0;
+    stats->plan_ms = es.plan_ms;
+    stats->launch_ms = es.launch_ms;
+    stats->finish_ms = now_ms() - t_fin0;
+    stats->graph_hits = es.graph_hits;
+    stats->planner_used = 2;
+  }
+  return SW_OK;
+}
+
+}  // namespace swrt

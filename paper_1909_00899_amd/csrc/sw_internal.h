@@ -123,11 +123,12 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 // plan_count: PairInfo of every pair with its reference checked (0 <= id <
 // n_refs, 0 <= roff[id] <= roff[id+1] <= ref_bytes; otherwise
 // meta[kMetaErrPair] is set and the pair gets n = 0), results set to
-// {0, -1, -1, 0}, and a histogram of ceil(n/4) over the pairs with m, n > 0.
+// {0, -1, -1, 0}, a histogram of ceil(n/4) over the pairs with m, n > 0 and
+// *nsum += the sum of their n.
 hipError_t launch_plan_count(int n_pairs, const int64_t *roff, const int32_t *pq,
                              const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
                              int64_t q_off0, PairInfo *pairs, DevResult *results, int32_t *hist,
-                             int32_t *meta, hipStream_t st);
+                             int32_t *meta, unsigned long long *nsum, hipStream_t st);
 // plan_scan: cursor[bin] = first position of the bin in the longest-first
 // order; meta[kMetaValid] = number of entries; meta[kMetaCounter] = 0.
 hipError_t launch_plan_scan(const int32_t *hist, int32_t *cursor, int32_t *meta, hipStream_t st);

@@ -74,15 +74,13 @@ __global__ __launch_bounds__(256) void build_pairs_kernel(int n_pairs, const int
 }
 // ================================================================ device planner
 
-// PairInfo, validation, result initialisation and the length histogram.
-__global__ __launch_bounds__(256) void plan_count_kernel(int n_pairs, const int64_t *roff,
-                                                         const int32_t *pq, const int32_t *pr,
-                                                         int n_refs, int64_t ref_bytes, int m,
-                                                         int64_t q_off0, PairInfo *pairs,
-                                                         DevResult *results, int32_t *hist,
-                                                         int32_t *meta) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_pairs) return;
+// One pair of plan_count_kernel; returns its n if it will run, else 0.
+__device__ __forceinline__ unsigned long long plan_one(int k, const int64_t *roff,
+                                                       const int32_t *pq, const int32_t *pr,
+                                                       int n_refs, int64_t ref_bytes, int m,
+                                                       int64_t q_off0, PairInfo *pairs,
+                                                       DevResult *results, int32_t *hist,
+                                                       int32_t *meta) {
   const int q = pq ? pq[k] : 0;
   const int r = pr[k];
   bool ok = q == 0 && r >= 0 && r < n_refs;
@@ -110,7 +108,26 @@ __global__ __launch_bounds__(256) void plan_count_kernel(int n_pairs, const int6
   if (m > 0 && p.n > 0) {
     const int bin = min((p.n + kBlock - 1) / kBlock, kPlanBins - 1);
     atomicAdd(&hist[bin], 1);
+    return (unsigned long long)p.n;
   }
+  return 0;
+}
+
+// PairInfo, validation, result initialisation and the length histogram.
+__global__ __launch_bounds__(256) void plan_count_kernel(int n_pairs, const int64_t *roff,
+                                                         const int32_t *pq, const int32_t *pr,
+                                                         int n_refs, int64_t ref_bytes, int m,
+                                                         int64_t q_off0, PairInfo *pairs,
+                                                         DevResult *results, int32_t *hist,
+                                                         int32_t *meta, unsigned long long *nsum) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  // sum of the runnable reference lengths (one atomic per wavefront)
+  unsigned long long ns = 0;
+  if (k < n_pairs) {
+    ns = plan_one(k, roff, pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, hist, meta);
+  }
+  for (int d = 1; d < kWave; d <<= 1) ns += __shfl_xor(ns, d);
+  if ((threadIdx.x & 63) == 0 && ns) atomicAdd(nsum, ns);
 }
 
 // One workgroup: exclusive scan of the histogram from the longest bin down.
@@ -204,11 +221,11 @@ hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *fl
 hipError_t launch_plan_count(int n_pairs, const int64_t *roff, const int32_t *pq,
                              const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
                              int64_t q_off0, PairInfo *pairs, DevResult *results, int32_t *hist,
-                             int32_t *meta, hipStream_t st) {
+                             int32_t *meta, unsigned long long *nsum, hipStream_t st) {
   if (n_pairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(dev::plan_count_kernel, dim3((n_pairs + 255) / 256), dim3(256), 0, st,
                      n_pairs, roff, pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, hist,
-                     meta);
+                     meta, nsum);
   return hipGetLastError();
 }
 

@@ -1301,6 +1301,7 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
     stats->columns = (int64_t)es.dev_stats[0];
     stats->record_events = (int64_t)es.dev_stats[2];
     stats->graph_hits = es.graph_hits;
+    stats->planner_used = 1;
     for (int k = 0; k < 3; ++k) stats->lanes_used[k] = es.lanes_used[k];
     stats->seglen_max = es.seglen_max;
   }

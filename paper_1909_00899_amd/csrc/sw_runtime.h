@@ -144,7 +144,7 @@ constexpr int kSideStreams = 3;
 // Work buffers used by one execution (the batch path owns one; the request
 // server one per in-flight batch).
 struct Workspace {
-  DevBuf tasks, pairs, streams, results, bnd, misc, matrix, offs;
+  DevBuf tasks, pairs, streams, results, bnd, misc, matrix, offs, plan;
   HostBuf staging;
   HostScratch host;
   GraphCache graphs;
@@ -164,7 +164,7 @@ struct Workspace {
       (void)hipEventDestroy(fork);
       side_ready = false;
     }
-    for (DevBuf *b : {&tasks, &pairs, &streams, &results, &bnd, &misc, &matrix, &offs})
+    for (DevBuf *b : {&tasks, &pairs, &streams, &results, &bnd, &misc, &matrix, &offs, &plan})
       b->release();
     staging.release();
   }
@@ -213,6 +213,14 @@ std::vector<std::pair<int, int>> pair_candidates(swk::Prec prec, int alpha, cons
                                                  size_t cnt, int max_cands);
 std::vector<int> pair_mixed_candidates(swk::Prec prec, int alpha, const PlanItem *items,
                                        size_t cnt, int max_cands);
+
+// Device-planned batch (one query, a compiled shape that holds it in one
+// chunk): planner 0 = use it when the batch qualifies and has at least 4096
+// pairs, 1 = never, 2 = always (SW_EINVAL when the batch does not qualify).
+// `handled` is false when the caller must run the host planner instead (then
+// nothing was launched and `out` is untouched).  The caller holds C.mu.
+int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, int planner,
+                    Context &C, sw_result *out, sw_stats *stats, double t0, bool &handled);
 
 // Full batch semantics (int16 pass + int32 rerun) on prepared input.
 int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecOptions &opt,

@@ -1,0 +1,227 @@
+"""Device-planned single-query batches (the planner's validation, length
+ordering and packing run on the GPU; residues are read from the references
+directly): every result equals the CPU oracle exactly, through the C ABI,
+and equals the host-planned path."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_00899_amd import api, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# (rows per lane, lanes) of the compiled device-planned shapes
+SHAPES = [(4, 16), (8, 16), (12, 16), (16, 16), (12, 32), (16, 32)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    oracle.build(force=False)
+    api.load()          # raises if the HIP library is missing: no fallback
+    api.sw_init()
+
+
+def oracle_batch(w):
+    return oracle.align_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref,
+                              w.matrix, w.gap_open, w.gap_extend, pair_query=w.pair_query)
+
+
+def assert_same(got, want, label=""):
+    got3 = np.asarray(got)[:, :3]
+    bad = np.nonzero((got3 != want).any(axis=1))[0]
+    if bad.size:
+        k = int(bad[0])
+        raise AssertionError("%s: %d/%d mismatches; first pair %d got %s want %s" %
+                             (label, bad.size, len(want), k, got3[k].tolist(), want[k].tolist()))
+
+
+def _device(w):
+    import torch
+    dev = torch.device("cuda")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    pq = None if w.pair_query is None else t(w.pair_query, torch.int32)
+    return (t(w.query_res, torch.uint8), t(w.query_off, torch.int64), t(w.ref_res, torch.uint8),
+            t(w.ref_off, torch.int64), t(w.pair_ref, torch.int32)), pq
+
+
+def _run(w, device=True, **kw):
+    if device:
+        args, pq = _device(w)
+    else:
+        args, pq = (w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref), w.pair_query
+    return api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, pair_query=pq, **kw)
+
+
+def _one_query(seed, m, n_refs, nlen, alpha=20, matrix=None, go=11, ge=1, zero_every=0):
+    """One query of length m against n_refs references of lengths U[nlen]
+    (every zero_every-th reference empty), pairs in reference order."""
+    rng = np.random.default_rng(seed)
+    q = rng.integers(0, alpha, size=m).astype(np.uint8)
+    lens = rng.integers(nlen[0], nlen[1] + 1, size=n_refs)
+    if zero_every:
+        lens[::zero_every] = 0
+    refs = [rng.integers(0, alpha, size=int(L)).astype(np.uint8) for L in lens]
+    roff = np.zeros(n_refs + 1, dtype=np.int64)
+    np.cumsum(lens, out=roff[1:])
+    M = matrix if matrix is not None else (W.protein_matrix() if alpha == 20 else
+                                           W.random_matrix(rng, alpha))
+    return W.Workload("one_query", q, np.array([0, m], dtype=np.int64),
+                      np.concatenate(refs) if n_refs else np.zeros(0, np.uint8), roff, None,
+                      np.arange(n_refs, dtype=np.int32), M, go, ge)
+
+
+def test_protein_search_device_planned_matches_oracle_and_host_planner():
+    w = W.protein_search(n_refs=6000)
+    want = oracle_batch(w)
+    got = _run(w, planner=2)
+    assert got.stats["planner_used"] == 2
+    assert_same(got.results, want, "device planner")
+    assert sum(got.stats["lanes_used"]) == w.pair_ref.size
+    host = _run(w, planner=1)
+    assert host.stats["planner_used"] == 1
+    assert (host.results == got.results).all()
+    auto = _run(w)                      # 6000 pairs, one query: the device planner
+    assert auto.stats["planner_used"] == 2
+    assert (auto.results == got.results).all()
+
+
+def test_host_resident_inputs_device_planned():
+    w = W.protein_search(n_refs=1500, seed=7)
+    want = oracle_batch(w)
+    got = _run(w, device=False, planner=2)
+    assert got.stats["planner_used"] == 2
+    assert_same(got.results, want, "host-resident")
+
+
+@pytest.mark.parametrize("m", [1, 63, 64, 65, 128, 129, 192, 193, 256, 257, 384, 385, 511, 512])
+def test_query_lengths_and_empty_references(m):
+    w = _one_query(40 + m, m, 400, (0, 700), zero_every=7)
+    want = oracle_batch(w)
+    got = _run(w, planner=2)
+    assert_same(got.results, want, "m=%d" % m)
+    assert got.stats["cells"] == int(sum(m * (w.ref_off[k + 1] - w.ref_off[k])
+                                         for k in range(w.pair_ref.size)))
+
+
+@pytest.mark.parametrize("seg,lanes", SHAPES)
+@pytest.mark.parametrize("prec", [api.SW_PREC_AUTO, api.SW_PREC_I32])
+def test_forced_shapes(seg, lanes, prec):
+    m = min(seg * lanes, 300)
+    w = _one_query(7 * seg + lanes, m, 300, (1, 400))
+    want = oracle_batch(w)
+    got = _run(w, planner=2, force_lanes=lanes, force_seglen=seg, precision=prec)
+    assert got.stats["seglen_max"] == seg
+    assert_same(got.results, want, "seg=%d lanes=%d prec=%d" % (seg, lanes, prec))
+
+
+def test_references_longer_than_the_last_length_bin():
+    # bins cover n <= 4 * 4095; longer references share the last bin
+    w = _one_query(50, 100, 64, (1, 300))
+    rng = np.random.default_rng(51)
+    lens = np.diff(w.ref_off)
+    lens[[3, 10, 40]] = [16385, 20001, 17002]
+    refs = [rng.integers(0, 20, size=int(L)).astype(np.uint8) for L in lens]
+    roff = np.zeros(lens.size + 1, dtype=np.int64)
+    np.cumsum(lens, out=roff[1:])
+    w = W.Workload("long_refs", w.query_res, w.query_off, np.concatenate(refs), roff, None,
+                   w.pair_ref, w.matrix, w.gap_open, w.gap_extend)
+    want = oracle_batch(w)
+    got = _run(w, planner=2)
+    assert_same(got.results, want, "long references")
+
+
+def test_unaligned_reference_ends():
+    # every reference length mod 4 and start mod 4 occurs; the last reference
+    # ends exactly at the end of the residue buffer
+    w = _one_query(60, 200, 257, (1, 13))
+    want = oracle_batch(w)
+    assert_same(_run(w, planner=2).results, want, "short refs")
+
+
+def test_int16_forced_and_natural_reruns():
+    w = _one_query(70, 300, 800, (10, 400))
+    want = oracle_batch(w)
+    got = _run(w, planner=2, int16_cap=40)
+    assert_same(got.results, want, "cap=40")
+    assert got.stats["n_rerun"] == int((want[:, 0] >= 40).sum())
+    assert ((got.results[:, 3] == api.SW_FLAG_SATURATED) == (want[:, 0] >= 40)).all()
+    # a matrix whose self-alignment scores pass 32767 in 300 residues
+    M = W.protein_matrix().copy()
+    np.fill_diagonal(M, 120)
+    w2 = _one_query(71, 300, 64, (200, 400), matrix=M)
+    refs = [w2.query_res[:250], w2.query_res] + [w2.ref_res[w2.ref_off[k]:w2.ref_off[k + 1]]
+                                                  for k in range(2, 64)]
+    roff = np.zeros(65, dtype=np.int64)
+    np.cumsum([r.size for r in refs], out=roff[1:])
+    w2 = W.Workload("saturating", w2.query_res, w2.query_off, np.concatenate(refs), roff, None,
+                    w2.pair_ref, M, 11, 1)
+    want2 = oracle_batch(w2)
+    got2 = _run(w2, planner=2)
+    assert_same(got2.results, want2, "natural saturation")
+    assert want2[1, 0] > 32767 and got2.results[1, 3] == api.SW_FLAG_SATURATED
+    assert got2.stats["n_rerun"] == int((want2[:, 0] >= 32767).sum())
+
+
+def test_pair_query_and_qualification():
+    w = _one_query(80, 150, 300, (1, 300))
+    want = oracle_batch(w)
+    pq = np.zeros(w.pair_ref.size, dtype=np.int32)
+    w1 = W.Workload("pq", w.query_res, w.query_off, w.ref_res, w.ref_off, pq, w.pair_ref,
+                    w.matrix, w.gap_open, w.gap_extend)
+    assert_same(_run(w1, planner=2).results, want, "pair_query zeros")
+    # two queries: not device-planned (forced -> SW_EINVAL; auto -> host planner)
+    qres = np.concatenate([w.query_res, w.query_res[:20]])
+    qoff = np.array([0, 150, 170], dtype=np.int64)
+    w2 = W.Workload("two", qres, qoff, w.ref_res, w.ref_off, pq, w.pair_ref, w.matrix,
+                    w.gap_open, w.gap_extend)
+    with pytest.raises(api.SwError) as e:
+        _run(w2, planner=2)
+    assert e.value.code == api.SW_EINVAL
+    got = _run(w2)
+    assert got.stats["planner_used"] == 1
+    assert_same(got.results, want, "two queries, all pairs on query 0")
+    # a query longer than every compiled shape: host planner (chunked)
+    w3 = _one_query(81, 700, 50, (1, 200))
+    with pytest.raises(api.SwError):
+        _run(w3, planner=2)
+    assert_same(_run(w3).results, oracle_batch(w3), "m=700 host planner")
+
+
+def test_invalid_inputs_rejected_on_device():
+    w = _one_query(90, 100, 200, (1, 100))
+    bad = w.pair_ref.copy()
+    bad[17] = 200                       # reference id out of range
+    wb = W.Workload("bad_id", w.query_res, w.query_off, w.ref_res, w.ref_off, None, bad,
+                    w.matrix, w.gap_open, w.gap_extend)
+    for device in (True, False):
+        with pytest.raises(api.SwError) as e:
+            _run(wb, device=device, planner=2)
+        assert e.value.code == api.SW_EINVAL
+    rr = w.ref_res.copy()
+    rr[rr.size // 2] = 20               # residue code == alphabet size
+    wr = W.Workload("bad_res", w.query_res, w.query_off, rr, w.ref_off, None, w.pair_ref,
+                    w.matrix, w.gap_open, w.gap_extend)
+    with pytest.raises(api.SwError) as e:
+        _run(wr, planner=2)
+    assert e.value.code == api.SW_EINVAL
+    # the library is still usable afterwards
+    assert_same(_run(w, planner=2).results, oracle_batch(w), "after errors")
+
+
+def test_device_planned_graph_replays_match_eager():
+    import torch
+    w = W.protein_search(n_refs=5000, seed=9)
+    want = oracle_batch(w)
+    args, pq = _device(w)
+    eager = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, planner=2)
+    assert_same(eager.results, want, "eager")
+    hits = 0
+    for rep in range(4):
+        g = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, planner=2, use_graph=1)
+        assert (g.results == eager.results).all(), rep
+        hits += g.stats["graph_hits"]
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+        again = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, planner=2)
+        assert (again.results == eager.results).all(), rep
+    assert hits >= 3
