@@ -143,6 +143,7 @@ int sw_align_batch(const sw_batch *b, const sw_scoring *sc, sw_result *out);
 
 /* Options and statistics for the extended batch call (tests, benchmarks,
  * the autotuner).  Zero-initialise and set what you need. */
+enum { SW_PAIRING_AUTO = 0, SW_PAIRING_ALIGNMENTS = 1, SW_PAIRING_ROWS = 2 };
 enum { SW_ALG_SCAN = 0,          /* max-plus scan, deferred H fix-up (Algorithm 6) */
        SW_ALG_LAZYF = 1 };       /* lazy-F correction loop (Algorithm 1), comparator */
 
@@ -178,7 +179,18 @@ typedef struct {
                                     from the references; only the query's offsets
                                     and the sets' end offsets are read by the host
                                     before the launch.                             */
-    int32_t reserved[8];
+    int32_t lane_pairing;        /* int16x2 lanes of device-planned batches: what
+                                    the two 16-bit halves of a lane carry.
+                                    SW_PAIRING_AUTO = row pairs when no lanes or
+                                    seglen are forced and the profile fits 64 KiB
+                                    of LDS, else alignment pairs;
+                                    SW_PAIRING_ALIGNMENTS = two alignments (one per
+                                    half, 16/32/64 lanes per alignment);
+                                    SW_PAIRING_ROWS = two row segments of one
+                                    alignment (16 lanes, 32 x seglen rows per
+                                    alignment, seglen 4, 8, 12 or 16): one profile
+                                    word per row pair and one more scan step    */
+    int32_t reserved[7];
 } sw_options;
 
 typedef struct {

@@ -22,6 +22,7 @@ SW_OK, SW_PENDING, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_EOVERFLOW, SW_ENOENT, SW
     0, 1, -1, -2, -3, -4, -5, -6
 SW_PREC_AUTO, SW_PREC_I32 = 0, 1
 SW_ALG_SCAN, SW_ALG_LAZYF = 0, 1
+SW_PAIRING_AUTO, SW_PAIRING_ALIGNMENTS, SW_PAIRING_ROWS = 0, 1, 2
 SW_FLAG_SATURATED = 1
 
 EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align",
@@ -66,7 +67,7 @@ class Options(ctypes.Structure):
                 ("force_seglen", ctypes.c_int32), ("force_kernel", ctypes.c_int32),
                 ("mixed_layout", ctypes.c_int32), ("int16_cap", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("planner", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("lane_pairing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class Stats(ctypes.Structure):
@@ -267,7 +268,8 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                    gap_extend: int, pair_query=None, precision: int = SW_PREC_AUTO,
                    algorithm: int = SW_ALG_SCAN, force_lanes: int = 0, force_seglen: int = 0,
                    force_kernel: int = 0, mixed_layout: int = 0, int16_cap: int = 0,
-                   use_graph: int = 0, planner: int = 0) -> BatchOutput:
+                   use_graph: int = 0, planner: int = 0,
+                   lane_pairing: int = 0) -> BatchOutput:
     """Many pairs in one persistent launch (plus an int32 rerun if needed).
 
     Sequences are CSR.  Either all six arrays are numpy (host) or all are torch
@@ -278,7 +280,7 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                                   precision)
     sc, M = make_scoring(matrix, gap_open, gap_extend)
     opt = Options(algorithm, force_lanes, force_seglen, force_kernel, mixed_layout, int16_cap,
-                  use_graph, planner)
+                  use_graph, planner, lane_pairing)
     out = np.zeros((max(npairs, 1), 4), dtype=np.int32)
     st = Stats()
     _check(lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),

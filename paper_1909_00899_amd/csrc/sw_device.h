@@ -238,16 +238,15 @@ struct ProfLds {
   }
 };
 
-// Per-half mask: 0xffff in each 16-bit half where a != b (packed), or all
-// ones where a != b (int32).
+// Per-half mask where nb > g, given nb >= g: 0xffff in each 16-bit half
+// (packed: the sign of g - nb, which cannot overflow for values in
+// [0, 32767], spread over the half), or all ones (int32).
 template <class O>
-__device__ __forceinline__ uint32_t diff_mask(uint32_t a, uint32_t b) {
+__device__ __forceinline__ uint32_t gain_mask(uint32_t nb, uint32_t g) {
   if constexpr (O::kHalves == 2) {
-    const uint32_t x = a ^ b;
-    const uint32_t one = bc<uint32_t>(__builtin_elementwise_min(bc<u16x2>(x), bc<u16x2>(0x00010001u)));
-    return one * 0xffffu;   // 0x0001 -> 0xffff per half; no carry between halves
+    return bc<uint32_t>((bc<s16x2>(g) - bc<s16x2>(nb)) >> (short)15);
   } else {
-    return a != b ? 0xffffffffu : 0u;
+    return nb != g ? 0xffffffffu : 0u;
   }
 }
 
@@ -257,11 +256,21 @@ __device__ __forceinline__ void record(State<SEG> &st, uint32_t cmax, int i) {
   const uint32_t nb = O::vmax(st.G, cmax);
   if (__any(nb != st.G)) {
     ++st.events;
-    const uint32_t m = diff_mask<O>(nb, st.G);
+    uint32_t m = gain_mask<O>(nb, st.G);
+    // keep the copies below as one bit-select per register (an empty asm
+    // hides where the mask came from, so it is not split into per-half selects)
+    asm("" : "+v"(m));
 #pragma unroll
     for (int j = 0; j < SEG; ++j) st.snap[j] = (st.H[j] & m) | (st.snap[j] & ~m);
-    if (m & 0xffffu) st.rc[0] = i;
-    if (O::kHalves == 2 && (m >> 16)) st.rc[1] = i;
+    if constexpr (O::kHalves == 2) {
+      // 32-bit masks of the two halves: sign-extended low half, high half
+      const uint32_t mlo = (uint32_t)((int)(m << 16) >> 16);
+      const uint32_t mhi = (uint32_t)((int)m >> 16);
+      st.rc[0] = (int)(((uint32_t)i & mlo) | ((uint32_t)st.rc[0] & ~mlo));
+      st.rc[1] = (int)(((uint32_t)i & mhi) | ((uint32_t)st.rc[1] & ~mhi));
+    } else {
+      if (m) st.rc[0] = i;
+    }
     st.G = nb;
     st.S = (nb & m) | (st.S & ~m);
   }
@@ -755,6 +764,249 @@ void shared_direct_kernel(KArgs a) {
     finish<O, SEG>(st, L, pid, a.pairs, a.results, 0, prev, a.sat_cap);
   }
   if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
+    if (cols) atomicAdd(&a.stats[0], cols);
+    if (events) atomicAdd(&a.stats[2], events);
+    if (padded) atomicAdd(&a.stats[3], padded);
+  }
+}
+
+// ================================================================ row-pair layout
+
+// int16 lanes may also carry two row segments of ONE alignment instead of two
+// alignments: in a 16-lane sub-group, lane l holds virtual lanes 2l (low half)
+// and 2l+1 (high half), and virtual lane v holds rows v*SEG + j.  Both halves
+// read the same reference residue, so one 32-bit LDS word holds the profile
+// entries of rows (2l)*SEG + j and (2l+1)*SEG + j: a single ds_read_b32 per
+// row pair and no half-merging instruction.  Cross-lane moves gain one step:
+// moving a value one virtual lane down takes the high half of the lane
+// before and the own low half (row_shr:1 and an align of the two words).
+
+// One virtual lane down inside each 16-lane sub-group (a DPP row); virtual
+// lane 0 receives 0.
+__device__ __forceinline__ uint32_t rp_vshift(uint32_t x) {
+  const uint32_t y = dpp<kRowShr1>(x);
+  return __builtin_amdgcn_alignbit(x, y, 16);
+}
+
+// Largest value of both halves, in both halves.
+__device__ __forceinline__ uint32_t rp_both(uint32_t x) {
+  return OpsI16::vmax(x, __builtin_amdgcn_alignbit(x, x, 16));
+}
+
+struct RpParams {
+  uint32_t go, ge;            // splatted gap penalties
+  uint32_t wv;                // SEG*ge: one virtual lane
+  uint32_t w1, w2, w4, w8;    // 2*SEG*ge*d: d lanes (2d virtual lanes)
+  uint32_t wlast;             // (SEG-1)*ge
+};
+
+template <int SEG>
+__device__ __forceinline__ RpParams make_rp_params(uint32_t go, uint32_t ge) {
+  using O = OpsI16;
+  RpParams p;
+  p.go = O::splat(go);
+  p.ge = O::splat(ge);
+  p.wv = weight<O>(1ull * SEG, ge);
+  p.w1 = weight<O>(2ull * SEG, ge);
+  p.w2 = weight<O>(4ull * SEG, ge);
+  p.w4 = weight<O>(8ull * SEG, ge);
+  p.w8 = weight<O>(16ull * SEG, ge);
+  p.wlast = weight<O>((uint64_t)(SEG - 1), ge);
+  return p;
+}
+
+// LDS profile of the row-pair layout: [alpha+1][SEG][16 lanes] words, the
+// residue stride a multiple of 256 bytes.  Two copies, the second shifted by
+// 16 banks: even sub-groups read the first, odd ones the second, so the two
+// sub-groups of a half-wave never share a bank whatever residues they read.
+__host__ __device__ constexpr uint32_t rp_cstride(int seg) {
+  return (uint32_t)((seg * 16 * 4 + 255) / 256 * 256);
+}
+__host__ __device__ constexpr uint32_t rp_copy_bytes(int seg, int alpha) {
+  return (uint32_t)(alpha + 1) * rp_cstride(seg) + 64;
+}
+
+template <int SEG>
+__device__ void build_rowpair_profile(const KArgs &a, uint32_t off) {
+  const int32_t *M = (const int32_t *)smem;
+  const int nrow = a.alpha + 1;
+  const int total = nrow * SEG * 16;
+  for (int k = threadIdx.x; k < total; k += blockDim.x) {
+    const int l = k % 16;
+    const int j = (k / 16) % SEG;
+    const int c = k / (16 * SEG);
+    uint32_t w = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t row = (int64_t)(2 * l + h) * SEG + j;
+      const int qc = row < a.shared_m ? (int)a.query_res[a.shared_q_off + row] : a.alpha;
+      const int v = (c < a.alpha && qc < a.alpha) ? M[qc * a.alpha + c] : -32768;
+      w |= ((uint32_t)v & 0xffffu) << (16 * h);
+    }
+    const uint32_t at = c * rp_cstride(SEG) + (j * 16 + l) * 4;
+    *(uint32_t *)(smem + off + at) = w;
+    *(uint32_t *)(smem + off + rp_copy_bytes(SEG, a.alpha) + at) = w;
+  }
+}
+
+// One column of the row-pair layout (the same column step as column(),
+// with virtual-lane moves).  base: LDS byte address of this lane's word of
+// row 0 for the column's residue.
+template <int SEG>
+__device__ __forceinline__ void rp_column(State<SEG> &st, const RpParams &pr, uint32_t base,
+                                          int i) {
+  using O = OpsI16;
+  uint32_t Fj = st.Fscan;
+  const uint32_t hlast = O::vmax(st.H[SEG - 1], O::usub(Fj, pr.wlast));
+  uint32_t Hin = rp_vshift(hlast);
+  uint32_t F = 0, cmax;
+#pragma unroll
+  for (int j = 0; j < SEG; ++j) {
+    const uint32_t p = *(const uint32_t *)(smem + base + j * 64);
+    const uint32_t hd = O::hadd(Hin, p);
+    cmax = j == 0 ? hd : O::vmax(cmax, hd);
+    const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
+    const uint32_t hold = st.H[j];
+    st.H[j] = h;
+    const uint32_t t = O::usub(h, pr.go);
+    st.E[j] = O::vmax(O::usub(st.E[j], pr.ge), t);
+    F = O::vmax(O::usub(F, pr.ge), t);
+    if (j + 1 < SEG) {
+      Hin = O::vmax(hold, Fj);
+      Fj = O::usub(Fj, pr.ge);
+    }
+  }
+  // inclusive max-plus scan over the 32 virtual lanes, then one virtual lane down
+  uint32_t G = F;
+  G = O::vmax(G, O::usub(rp_vshift(G), pr.wv));
+  G = O::vmax(G, O::usub(dpp<kRowShr1>(G), pr.w1));
+  G = O::vmax(G, O::usub(dpp<kRowShr2>(G), pr.w2));
+  G = O::vmax(G, O::usub(dpp<kRowShr4>(G), pr.w4));
+  G = O::vmax(G, O::usub(dpp<kRowShr8>(G), pr.w8));
+  st.Fscan = rp_vshift(G);
+  record<O, SEG>(st, cmax, i);
+}
+
+// Record thresholds raised to the largest of the sub-group (both halves).
+template <int SEG>
+__device__ __forceinline__ void rp_share_threshold(State<SEG> &st, int lane) {
+  using O = OpsI16;
+  uint32_t T = rp_both(st.G);
+  T = O::vmax(T, dpp<kRowShr1>(T));
+  T = O::vmax(T, dpp<kRowShr2>(T));
+  T = O::vmax(T, dpp<kRowShr4>(T));
+  T = O::vmax(T, dpp<kRowShr8>(T));
+  const uint32_t t15 = (uint32_t)__builtin_amdgcn_readlane((int)T, 15);
+  const uint32_t t31 = (uint32_t)__builtin_amdgcn_readlane((int)T, 31);
+  const uint32_t t47 = (uint32_t)__builtin_amdgcn_readlane((int)T, 47);
+  const uint32_t t63 = (uint32_t)__builtin_amdgcn_readlane((int)T, 63);
+  const int row = lane >> 4;
+  st.G = row == 0 ? t15 : (row == 1 ? t31 : (row == 2 ? t47 : t63));
+}
+
+template <int SEG, class Src>
+__device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const RpParams &pr,
+                                               uint32_t lane_base, const Src &src, int ncols) {
+  const int nblk = ncols / kBlock;
+  uint32_t ev_shared = st.events;
+  uint32_t rc = src.get(0).x;
+  uint32_t rn = src.get(1).x;
+  for (int b = 0; b < nblk; ++b) {
+    const uint32_t r = rc;
+    rc = rn;
+    rn = src.get(b + 2).x;
+#pragma unroll
+    for (int k = 0; k < kBlock; ++k) {
+      const uint32_t c = __builtin_amdgcn_ubfe(r, 8 * k, 8);
+      rp_column<SEG>(st, pr, lane_base + c * rp_cstride(SEG), b * kBlock + k);
+    }
+    if (st.events != ev_shared) {
+      rp_share_threshold<SEG>(st, lane);
+      ev_shared = st.events;
+    }
+  }
+}
+
+// Result of the alignment of this lane's sub-group: the best recorded cell of
+// each half (virtual lane 2l + h), then the best over the 16 lanes.
+template <int SEG>
+__device__ __forceinline__ void rp_finish(const State<SEG> &st, int lane, int pid,
+                                          const PairInfo *pairs, DevResult *results,
+                                          int sat_cap) {
+  using O = OpsI16;
+  const int l = lane & 15;
+  int s = 0, c = 0x7fffffff, r = 0x7fffffff;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int sh = st.rc[h] != 0x7fffffff ? O::get(st.S, h) : 0;
+    if (sh > 0) {
+      int jj = SEG - 1;
+#pragma unroll
+      for (int j = SEG - 1; j >= 0; --j)
+        if (O::get(st.snap[j], h) >= sh) jj = j;
+      const int ch = st.rc[h], rh = (2 * l + h) * SEG + jj;
+      if (s <= 0 || better(sh, ch, rh, s, c, r)) { s = sh; c = ch; r = rh; }
+    }
+  }
+  for (int d = 1; d < 16; d <<= 1) {
+    const int s2 = __shfl_xor(s, d), c2 = __shfl_xor(c, d), r2 = __shfl_xor(r, d);
+    if (s2 > 0 && (s <= 0 || better(s2, c2, r2, s, c, r))) { s = s2; c = c2; r = r2; }
+  }
+  if (l == 0 && pid >= 0) {
+    DevResult res;
+    res.score = s > 0 ? s : 0;
+    res.qend = s > 0 ? r : -1;
+    res.rend = s > 0 ? c : -1;
+    res.flags = s >= sat_cap ? kFlagNeedsI32 : 0u;
+    results[pairs[pid].out] = res;
+  }
+}
+
+// Device-planned shared-query kernel in the row-pair layout: four
+// alignments per wavefront (one per 16-lane sub-group); task t is entries
+// [4t, 4t+4) of the longest-first order.
+template <int SEG>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+void shared_rowpair_kernel(KArgs a) {
+  if (a.plan_meta[kMetaErrResidue] | a.plan_meta[kMetaErrPair]) return;
+  stage_matrix(a);
+  __syncthreads();
+  const uint32_t off = (matrix_lds_bytes(a.alpha) + 255) / 256 * 256;
+  build_rowpair_profile<SEG>(a, off);
+  __syncthreads();
+  const int lane = (int)(threadIdx.x & 63);
+  const int sg = lane >> 4;
+  const int nvalid = a.plan_meta[kMetaValid];
+  const int ntasks = (nvalid + 3) / 4;
+  const RpParams pr = make_rp_params<SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
+  const uint32_t lane_base = off + (sg & 1) * rp_copy_bytes(SEG, a.alpha) + (lane & 15) * 4;
+  const uint32_t sentw = (uint32_t)a.alpha * 0x01010101u;
+  unsigned long long cols = 0, events = 0, padded = 0;
+  for (;;) {
+    const int ti = pop_task(a.plan_meta + kMetaCounter);
+    if (ti >= ntasks) break;
+    const int e = ti * 4 + sg;
+    int pid = -1, n = 0;
+    int64_t roff = 0;
+    if (e < nvalid) {
+      pid = a.order[e];
+      const PairInfo p = a.pairs[pid];
+      roff = p.r_off;
+      n = p.n;
+    }
+    int nmax = n;
+    for (int d = 16; d < kWave; d <<= 1) nmax = max(nmax, __shfl_xor(nmax, d));
+    const int ncols = (nmax + kBlock - 1) / kBlock * kBlock;
+    State<SEG> st;
+    state_reset(st, 0u);
+    const DirectSrc src{a.ref_res + roff, a.ref_res + roff, n, 0, sentw};
+    rp_run_columns<SEG>(st, lane, pr, lane_base, src, ncols);
+    cols += (unsigned long long)ncols;
+    events += st.events;
+    padded += (unsigned long long)min(4, nvalid - ti * 4) * ncols * 32 * SEG;
+    rp_finish<SEG>(st, lane, pid, a.pairs, a.results, a.sat_cap);
+  }
+  if (lane == 0 && a.stats != nullptr) {
     if (cols) atomicAdd(&a.stats[0], cols);
     if (events) atomicAdd(&a.stats[2], events);
     if (padded) atomicAdd(&a.stats[3], padded);

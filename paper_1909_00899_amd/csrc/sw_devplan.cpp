@@ -87,6 +87,20 @@ bool pick_direct_shape(Prec prec, int alpha, int m, const ExecOptions &eo, int &
   return false;
 }
 
+// Rows per virtual lane of the row-pair layout: the forced value, else the
+// smallest compiled one that holds the query (32 virtual lanes), within
+// 64 KiB of LDS per workgroup.
+bool pick_rowpair_seg(int m, int alpha, int force_seg, int &seg) {
+  for (int s : {4, 8, 12, 16}) {
+    if ((force_seg == 0 || s == force_seg) && 32 * s >= m && shared_rowpair_has(s) &&
+        shared_rowpair_lds_bytes(s, alpha) <= 65536) {
+      seg = s;
+      return true;
+    }
+  }
+  return false;
+}
+
 }  // namespace
 
 int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, int planner,
@@ -141,8 +155,22 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   if ((int64_t)m * S.max_s >= kI32Limit) return refuse("the query may overflow int32");
   const Prec prec = (b->precision == SW_PREC_AUTO && S.fits_i16) ? PREC_I16X2 : PREC_I32;
   int seg = 0, lanes = 0;
-  if (!pick_direct_shape(prec, S.alpha, m, eo, seg, lanes))
+  // row pairs: both halves of a lane hold rows of the same alignment
+  bool rows = false;
+  if (eo.lane_pairing == SW_PAIRING_ROWS) {
+    if (prec != PREC_I16X2) return refuse("row pairs need int16 lanes");
+    if (eo.force_lanes && eo.force_lanes != 16) return refuse("row pairs use 16 lanes");
+    rows = pick_rowpair_seg(m, S.alpha, eo.force_seglen, seg);
+    if (!rows) return refuse("no compiled row-pair shape holds the query");
+    lanes = 16;
+  } else if (eo.lane_pairing == SW_PAIRING_AUTO && prec == PREC_I16X2 && !eo.force_lanes &&
+             !eo.force_seglen && pick_rowpair_seg(m, S.alpha, 0, seg)) {
+    // the default for int16 lanes: one profile word per row pair
+    rows = true;
+    lanes = 16;
+  } else if (!pick_direct_shape(prec, S.alpha, m, eo, seg, lanes)) {
     return refuse("no compiled shape holds the query in one chunk");
+  }
   handled = true;
 
   // ---- buffers
@@ -205,7 +233,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   a.order = plan + kPlanOrder;
   a.plan_meta = meta;
   a.ref_res = d_rres;
-  const int slots = (kWave / lanes) * (prec == PREC_I16X2 ? 2 : 1);
+  const int slots = rows ? kWave / 16 : (kWave / lanes) * (prec == PREC_I16X2 ? 2 : 1);
   const int ntasks_max = (np + slots - 1) / slots;
   const int grid = std::max(1, std::min((ntasks_max + kWavesPerGroup - 1) / kWavesPerGroup,
                                         C.num_cus * 2));
@@ -228,7 +256,10 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     if (e == hipSuccess) e = launch_plan_scatter(np, d_pairs, cursor, order, st);
     return e;
   };
-  auto align = [=]() { return launch_shared_direct(prec, seg, lanes, a, grid, st); };
+  auto align = [=]() {
+    return rows ? launch_shared_rowpair(seg, a, grid, st)
+                : launch_shared_direct(prec, seg, lanes, a, grid, st);
+  };
   const double t_launch0 = now_ms();
   ExecStats es;
   es.plan_ms = t_launch0 - t0;
@@ -240,7 +271,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     if (e != hipSuccess) { set_error("device-planned launch: %s", hipGetErrorString(e)); return SW_EDEVICE; }
     HIPCHK(hipEventRecord(C.ev1, st));
   } else {
-    const uint64_t sig[] = {0xD1D1, (uint64_t)prec, (uint64_t)seg, (uint64_t)lanes,
+    const uint64_t sig[] = {0xD1D1, (uint64_t)prec, (uint64_t)seg, (uint64_t)lanes, (uint64_t)rows,
                             (uint64_t)grid, (uint64_t)np, (uint64_t)(uintptr_t)d_qres,
                             (uint64_t)(uintptr_t)d_rres, (uint64_t)(uintptr_t)d_roff,
                             (uint64_t)(uintptr_t)d_pq, (uint64_t)(uintptr_t)d_pr, (uint64_t)ni,

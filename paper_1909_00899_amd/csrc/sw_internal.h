@@ -143,6 +143,13 @@ size_t shared_direct_lds_bytes(Prec prec, int seg, int lanes, int alpha);
 hipError_t launch_shared_direct(Prec prec, int seg, int lanes, const KArgs &a, int grid,
                                 hipStream_t st);
 
+// Device-planned shared-query kernel in the row-pair layout (int16 only):
+// 16 lanes per alignment, each lane's two halves holding two row segments of
+// `seg` rows (32*seg query rows).
+bool shared_rowpair_has(int seg);
+size_t shared_rowpair_lds_bytes(int seg, int alpha);
+hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st);
+
 // Sets every result to {0, -1, -1, 0}.
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);
 

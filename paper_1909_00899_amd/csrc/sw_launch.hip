@@ -16,6 +16,7 @@ hipError_t launch_pair_i32(int seg, int pmax, bool chunked, const KArgs &a, int 
                            hipStream_t st, size_t lds);
 hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_direct_i32(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
+hipError_t launch_rowpair_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
 
 namespace dev {
 // ================================================================ residue streams
@@ -264,6 +265,19 @@ hipError_t launch_shared_direct(Prec prec, int seg, int lanes, const KArgs &a, i
   const size_t lds = shared_direct_lds_bytes(prec, seg, lanes, a.alpha);
   if (prec == PREC_I16X2) return launch_direct_i16(k, a, grid, st, lds);
   return launch_direct_i32(k, a, grid, st, lds);
+}
+
+bool shared_rowpair_has(int seg) { return seg == 4 || seg == 8 || seg == 12 || seg == 16; }
+
+size_t shared_rowpair_lds_bytes(int seg, int alpha) {
+  return (matrix_lds_bytes(alpha) + 255) / 256 * 256 + 2 * (size_t)dev::rp_copy_bytes(seg, alpha);
+}
+
+hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st) {
+  if (!shared_rowpair_has(seg) || a.order == nullptr || a.plan_meta == nullptr ||
+      a.ref_res == nullptr)
+    return hipErrorInvalidValue;
+  return launch_rowpair_i16(seg, a, grid, st, shared_rowpair_lds_bytes(seg, a.alpha));
 }
 
 int shared_menu_count() { return kNumSharedMenus; }

@@ -35,7 +35,24 @@ hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
   hipLaunchKernelGGL(k, dim3(grid), dim3(kWavesPerGroup * kWave), lds, st, a);
   return hipGetLastError();
 }
+template <int SEG>
+hipError_t launch_rp(const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  auto k = dev::shared_rowpair_kernel<SEG>;
+  hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kWavesPerGroup * kWave), lds, st, a);
+  return hipGetLastError();
+}
 }  // namespace
+
+hipError_t launch_rowpair_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  switch (seg) {
+    case 4: return launch_rp<4>(a, grid, st, lds);
+    case 8: return launch_rp<8>(a, grid, st, lds);
+    case 12: return launch_rp<12>(a, grid, st, lds);
+    case 16: return launch_rp<16>(a, grid, st, lds);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds) {
   static_assert(kNumDirectShapes == 6, "direct shapes");

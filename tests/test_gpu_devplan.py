@@ -76,6 +76,9 @@ def test_protein_search_device_planned_matches_oracle_and_host_planner():
     got = _run(w, planner=2)
     assert got.stats["planner_used"] == 2
     assert_same(got.results, want, "device planner")
+    rows = _run(w, planner=2, lane_pairing=api.SW_PAIRING_ROWS)
+    assert_same(rows.results, want, "device planner, row pairs")
+    assert rows.stats["lanes_used"] == [w.pair_ref.size, 0, 0]
     assert sum(got.stats["lanes_used"]) == w.pair_ref.size
     host = _run(w, planner=1)
     assert host.stats["planner_used"] == 1
@@ -93,12 +96,13 @@ def test_host_resident_inputs_device_planned():
     assert_same(got.results, want, "host-resident")
 
 
+@pytest.mark.parametrize("pairing", [api.SW_PAIRING_ALIGNMENTS, api.SW_PAIRING_ROWS])
 @pytest.mark.parametrize("m", [1, 63, 64, 65, 128, 129, 192, 193, 256, 257, 384, 385, 511, 512])
-def test_query_lengths_and_empty_references(m):
+def test_query_lengths_and_empty_references(m, pairing):
     w = _one_query(40 + m, m, 400, (0, 700), zero_every=7)
     want = oracle_batch(w)
-    got = _run(w, planner=2)
-    assert_same(got.results, want, "m=%d" % m)
+    got = _run(w, planner=2, lane_pairing=pairing)
+    assert_same(got.results, want, "m=%d pairing=%d" % (m, pairing))
     assert got.stats["cells"] == int(sum(m * (w.ref_off[k + 1] - w.ref_off[k])
                                          for k in range(w.pair_ref.size)))
 
@@ -114,6 +118,27 @@ def test_forced_shapes(seg, lanes, prec):
     assert_same(got.results, want, "seg=%d lanes=%d prec=%d" % (seg, lanes, prec))
 
 
+@pytest.mark.parametrize("seg", [4, 8, 12, 16])
+def test_row_pair_shapes(seg):
+    """Two row segments of one alignment per lane: every compiled rows-per-lane,
+    queries that fill the 32 virtual lanes exactly, leave the last ones
+    empty, or end inside a lane's high half."""
+    for m in sorted({32 * seg, 32 * seg - 1, 16 * seg + 1, 16 * seg, 3 * seg + 2}):
+        w = _one_query(300 + 7 * seg + m, m, 250, (1, 600), zero_every=11)
+        want = oracle_batch(w)
+        got = _run(w, planner=2, lane_pairing=api.SW_PAIRING_ROWS, force_seglen=seg)
+        assert got.stats["seglen_max"] == seg and got.stats["lanes_used"][0] > 0
+        assert_same(got.results, want, "rows seg=%d m=%d" % (seg, m))
+
+
+def test_row_pairs_refused_where_they_do_not_apply():
+    w = _one_query(310, 200, 100, (1, 200))
+    for kw in ({"precision": api.SW_PREC_I32}, {"force_lanes": 32}, {"force_seglen": 5}):
+        with pytest.raises(api.SwError) as e:
+            _run(w, planner=2, lane_pairing=api.SW_PAIRING_ROWS, **kw)
+        assert e.value.code == api.SW_EINVAL
+
+
 def test_references_longer_than_the_last_length_bin():
     # bins cover n <= 4 * 4095; longer references share the last bin
     w = _one_query(50, 100, 64, (1, 300))
@@ -126,8 +151,9 @@ def test_references_longer_than_the_last_length_bin():
     w = W.Workload("long_refs", w.query_res, w.query_off, np.concatenate(refs), roff, None,
                    w.pair_ref, w.matrix, w.gap_open, w.gap_extend)
     want = oracle_batch(w)
-    got = _run(w, planner=2)
-    assert_same(got.results, want, "long references")
+    for pairing in (api.SW_PAIRING_ALIGNMENTS, api.SW_PAIRING_ROWS):
+        got = _run(w, planner=2, lane_pairing=pairing)
+        assert_same(got.results, want, "long references, pairing %d" % pairing)
 
 
 def test_unaligned_reference_ends():
@@ -135,13 +161,15 @@ def test_unaligned_reference_ends():
     # ends exactly at the end of the residue buffer
     w = _one_query(60, 200, 257, (1, 13))
     want = oracle_batch(w)
-    assert_same(_run(w, planner=2).results, want, "short refs")
+    for pairing in (api.SW_PAIRING_ALIGNMENTS, api.SW_PAIRING_ROWS):
+        assert_same(_run(w, planner=2, lane_pairing=pairing).results, want, "short refs")
 
 
-def test_int16_forced_and_natural_reruns():
+@pytest.mark.parametrize("pairing", [api.SW_PAIRING_ALIGNMENTS, api.SW_PAIRING_ROWS])
+def test_int16_forced_and_natural_reruns(pairing):
     w = _one_query(70, 300, 800, (10, 400))
     want = oracle_batch(w)
-    got = _run(w, planner=2, int16_cap=40)
+    got = _run(w, planner=2, int16_cap=40, lane_pairing=pairing)
     assert_same(got.results, want, "cap=40")
     assert got.stats["n_rerun"] == int((want[:, 0] >= 40).sum())
     assert ((got.results[:, 3] == api.SW_FLAG_SATURATED) == (want[:, 0] >= 40)).all()
@@ -156,7 +184,7 @@ def test_int16_forced_and_natural_reruns():
     w2 = W.Workload("saturating", w2.query_res, w2.query_off, np.concatenate(refs), roff, None,
                     w2.pair_ref, M, 11, 1)
     want2 = oracle_batch(w2)
-    got2 = _run(w2, planner=2)
+    got2 = _run(w2, planner=2, lane_pairing=pairing)
     assert_same(got2.results, want2, "natural saturation")
     assert want2[1, 0] > 32767 and got2.results[1, 3] == api.SW_FLAG_SATURATED
     assert got2.stats["n_rerun"] == int((want2[:, 0] >= 32767).sum())
@@ -208,20 +236,22 @@ def test_invalid_inputs_rejected_on_device():
     assert_same(_run(w, planner=2).results, oracle_batch(w), "after errors")
 
 
-def test_device_planned_graph_replays_match_eager():
+@pytest.mark.parametrize("pairing", [api.SW_PAIRING_ALIGNMENTS, api.SW_PAIRING_ROWS])
+def test_device_planned_graph_replays_match_eager(pairing):
     import torch
     w = W.protein_search(n_refs=5000, seed=9)
     want = oracle_batch(w)
     args, pq = _device(w)
-    eager = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, planner=2)
+    kw = {"planner": 2, "lane_pairing": pairing}
+    eager = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, **kw)
     assert_same(eager.results, want, "eager")
     hits = 0
     for rep in range(4):
-        g = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, planner=2, use_graph=1)
+        g = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, use_graph=1, **kw)
         assert (g.results == eager.results).all(), rep
         hits += g.stats["graph_hits"]
         x = torch.randn(1 << 20, device="cuda")
         (x * 2).sum().item()
-        again = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, planner=2)
+        again = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, **kw)
         assert (again.results == eager.results).all(), rep
     assert hits >= 3
