@@ -6,10 +6,11 @@
 // Steps on the device (one stream, capturable as one hipGraph):
 //   matrix upload, clearing of the plan words (a fill kernel),
 //   residue checks of the query and reference sets,
-//   plan_count   PairInfo, reference checks, result initialisation, histogram
-//                of ceil(n / 4) and the sum of the reference lengths,
-//   plan_scan    longest-first bin starts, number of runnable pairs,
-//   plan_scatter the longest-first order,
+//   plan_count   PairInfo, reference checks, result initialisation, per-
+//                workgroup histograms of ceil(n / 4), sum of the lengths,
+//   plan_total   every workgroup's offset inside every bin, bin totals,
+//   plan_scatter bin starts (a scan of the totals) and the longest-first
+//                order (LDS atomics only), number of runnable pairs,
 //   shared_direct_kernel  one persistent launch; task t = entries
 //                [t*slots, (t+1)*slots) of the order, residues read from the
 //                references.
@@ -48,10 +49,11 @@ constexpr int64_t kI32Limit = 2147483647ll;
 // Layout of the plan buffer, in int32 words.
 constexpr int kPlanStats = 0;                       // 8 x u64: stats words
 constexpr int kPlanMeta = 16;                       // kMetaWords
-constexpr int kPlanHist = kPlanMeta + kMetaWords;   // kPlanBins
-constexpr int kPlanCursor = kPlanHist + kPlanBins;  // kPlanBins
-constexpr int kPlanOrder = kPlanCursor + kPlanBins; // n_pairs
-constexpr int kPlanCleared = kPlanHist + kPlanBins; // words cleared per call
+constexpr int kPlanHist = kPlanMeta + kMetaWords;                // kPlanBlocks x kPlanBins
+constexpr int kPlanOff = kPlanHist + kPlanBlocks * kPlanBins;     // kPlanBlocks x kPlanBins
+constexpr int kPlanTotals = kPlanOff + kPlanBlocks * kPlanBins;   // kPlanBins
+constexpr int kPlanOrder = kPlanTotals + kPlanBins;               // n_pairs
+constexpr int kPlanCleared = kPlanMeta + kMetaWords;              // words cleared per call
 
 // The (rows per lane, lanes) shape for query length m: the caller's forced
 // shape, else the autotuner's entry, else the smallest compiled shape that
@@ -237,7 +239,8 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   const int ntasks_max = (np + slots - 1) / slots;
   const int grid = std::max(1, std::min((ntasks_max + kWavesPerGroup - 1) / kWavesPerGroup,
                                         C.num_cus * 2));
-  int32_t *cursor = plan + kPlanCursor;
+  int32_t *boff = plan + kPlanOff;
+  int32_t *totals = plan + kPlanTotals;
   int32_t *hist = plan + kPlanHist;
   int32_t *order = plan + kPlanOrder;
   const int ni = b->n_refs;
@@ -252,8 +255,8 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     if (e == hipSuccess)
       e = launch_plan_count(np, d_roff, d_pq, d_pr, ni, rbytes, m, q_off0, d_pairs, d_res, hist,
                             meta, d_stats + 4, st);
-    if (e == hipSuccess) e = launch_plan_scan(hist, cursor, meta, st);
-    if (e == hipSuccess) e = launch_plan_scatter(np, d_pairs, cursor, order, st);
+    if (e == hipSuccess) e = launch_plan_total(hist, boff, totals, st);
+    if (e == hipSuccess) e = launch_plan_scatter(np, d_pairs, totals, boff, order, meta, st);
     return e;
   };
   auto align = [=]() {
@@ -310,7 +313,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   const double t_fin0 = now_ms();
   es.launch_ms = t_fin0 - t_launch0;
   // ---- results, statistics and the plan's error words
-  // staging: [matrix | plan words read back]
+  // staging: [matrix | plan words read back]; results go straight to `out`
   unsigned char *tail = (unsigned char *)ws.staging.p + (mat_bytes + 63) / 64 * 64;
   HIPCHK(hipMemcpyAsync(out, d_res, (size_t)np * sizeof(DevResult), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(tail, plan, (size_t)(kPlanMeta + kMetaWords) * sizeof(int32_t),

@@ -89,6 +89,7 @@ enum : int {
 // Length bins of the planner's counting sort: bin = ceil(n / kBlock), the
 // last bin also takes every longer reference.
 constexpr int kPlanBins = 4096;
+constexpr int kPlanBlocks = 32;   // workgroups of the planner's count and place passes
 
 // Host-side launchers (defined in sw_kernels.hip).
 enum Prec { PREC_I16X2 = 0, PREC_I32 = 1 };
@@ -119,23 +120,28 @@ hipError_t launch_build_streams(const Task *tasks, int ntasks, const PairInfo *p
 // p[0..n) = v.
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 
-// Device planner of a single-query batch (query length m at q_off0).
+// Device planner of a single-query batch (query length m at q_off0), run by
+// kPlanBlocks workgroups that each take a contiguous range of the pairs.
 // plan_count: PairInfo of every pair with its reference checked (0 <= id <
 // n_refs, 0 <= roff[id] <= roff[id+1] <= ref_bytes; otherwise
 // meta[kMetaErrPair] is set and the pair gets n = 0), results set to
-// {0, -1, -1, 0}, a histogram of ceil(n/4) over the pairs with m, n > 0 and
-// *nsum += the sum of their n.
+// {0, -1, -1, 0}, block_hist[w][bin] = the workgroup's pairs with m, n > 0 per
+// length bin, and *nsum += the sum of their n.
 hipError_t launch_plan_count(int n_pairs, const int64_t *roff, const int32_t *pq,
                              const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
-                             int64_t q_off0, PairInfo *pairs, DevResult *results, int32_t *hist,
-                             int32_t *meta, unsigned long long *nsum, hipStream_t st);
-// plan_scan: cursor[bin] = first position of the bin in the longest-first
-// order; meta[kMetaValid] = number of entries; meta[kMetaCounter] = 0.
-hipError_t launch_plan_scan(const int32_t *hist, int32_t *cursor, int32_t *meta, hipStream_t st);
+                             int64_t q_off0, PairInfo *pairs, DevResult *results,
+                             int32_t *block_hist, int32_t *meta, unsigned long long *nsum,
+                             hipStream_t st);
+// plan_total: block_off[w][bin] = workgroup w's first position inside the
+// bin, totals[bin] = pairs of the bin.
+hipError_t launch_plan_total(const int32_t *block_hist, int32_t *block_off, int32_t *totals,
+                             hipStream_t st);
 // plan_scatter: order[...] = every pair with m, n > 0, longest reference first
-// (pairs of one bin in any order).
-hipError_t launch_plan_scatter(int n_pairs, const PairInfo *pairs, int32_t *cursor,
-                               int32_t *order, hipStream_t st);
+// (pairs of one bin in any order); meta[kMetaValid] = number of entries,
+// meta[kMetaCounter] = 0.
+hipError_t launch_plan_scatter(int n_pairs, const PairInfo *pairs, const int32_t *totals,
+                               const int32_t *block_off, int32_t *order, int32_t *meta,
+                               hipStream_t st);
 // Device-planned shared-query kernel: rows per lane `seg`, `lanes` lanes per
 // alignment; a.order / a.plan_meta / a.ref_res describe the work.
 bool shared_direct_has(Prec prec, int seg, int lanes);

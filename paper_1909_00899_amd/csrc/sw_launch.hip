@@ -74,14 +74,25 @@ __global__ __launch_bounds__(256) void build_pairs_kernel(int n_pairs, const int
   out[k] = p;
 }
 // ================================================================ device planner
+//
+// kPlanBlocks workgroups each take a contiguous range of pairs.  Counting and
+// placing use LDS atomics only: every workgroup writes its own length
+// histogram, one workgroup turns them into per-workgroup start positions of
+// every bin, and each workgroup then places its pairs from those starts.
+
+__device__ __forceinline__ int plan_bin(int n) { return min((n + kBlock - 1) / kBlock, kPlanBins - 1); }
+
+__device__ __forceinline__ void plan_range(int n_pairs, int &lo, int &hi) {
+  const int chunk = (n_pairs + kPlanBlocks - 1) / kPlanBlocks;
+  lo = min(n_pairs, (int)blockIdx.x * chunk);
+  hi = min(n_pairs, lo + chunk);
+}
 
 // One pair of plan_count_kernel; returns its n if it will run, else 0.
-__device__ __forceinline__ unsigned long long plan_one(int k, const int64_t *roff,
-                                                       const int32_t *pq, const int32_t *pr,
-                                                       int n_refs, int64_t ref_bytes, int m,
-                                                       int64_t q_off0, PairInfo *pairs,
-                                                       DevResult *results, int32_t *hist,
-                                                       int32_t *meta) {
+__device__ __forceinline__ int plan_one(int k, const int64_t *roff, const int32_t *pq,
+                                        const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
+                                        int64_t q_off0, PairInfo *pairs, DevResult *results,
+                                        int32_t *meta) {
   const int q = pq ? pq[k] : 0;
   const int r = pr[k];
   bool ok = q == 0 && r >= 0 && r < n_refs;
@@ -106,42 +117,74 @@ __device__ __forceinline__ unsigned long long plan_one(int k, const int64_t *rof
   DevResult v;
   v.score = 0; v.qend = -1; v.rend = -1; v.flags = 0;
   results[k] = v;
-  if (m > 0 && p.n > 0) {
-    const int bin = min((p.n + kBlock - 1) / kBlock, kPlanBins - 1);
-    atomicAdd(&hist[bin], 1);
-    return (unsigned long long)p.n;
-  }
-  return 0;
+  return m > 0 ? p.n : 0;
 }
 
-// PairInfo, validation, result initialisation and the length histogram.
-__global__ __launch_bounds__(256) void plan_count_kernel(int n_pairs, const int64_t *roff,
-                                                         const int32_t *pq, const int32_t *pr,
-                                                         int n_refs, int64_t ref_bytes, int m,
-                                                         int64_t q_off0, PairInfo *pairs,
-                                                         DevResult *results, int32_t *hist,
-                                                         int32_t *meta, unsigned long long *nsum) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  // sum of the runnable reference lengths (one atomic per wavefront)
+// PairInfo, validation, result initialisation and this workgroup's length
+// histogram (block_hist[blockIdx.x][bin]).
+__global__ __launch_bounds__(1024) void plan_count_kernel(int n_pairs, const int64_t *roff,
+                                                          const int32_t *pq, const int32_t *pr,
+                                                          int n_refs, int64_t ref_bytes, int m,
+                                                          int64_t q_off0, PairInfo *pairs,
+                                                          DevResult *results, int32_t *block_hist,
+                                                          int32_t *meta, unsigned long long *nsum) {
+  __shared__ int32_t hist[kPlanBins];
+  for (int b = threadIdx.x; b < kPlanBins; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
+  int lo, hi;
+  plan_range(n_pairs, lo, hi);
   unsigned long long ns = 0;
-  if (k < n_pairs) {
-    ns = plan_one(k, roff, pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, hist, meta);
+  for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+    const int n = plan_one(k, roff, pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, meta);
+    if (n > 0) {
+      atomicAdd(&hist[plan_bin(n)], 1);
+      ns += (unsigned long long)n;
+    }
   }
+  // sum of the runnable reference lengths (one atomic per wavefront)
   for (int d = 1; d < kWave; d <<= 1) ns += __shfl_xor(ns, d);
   if ((threadIdx.x & 63) == 0 && ns) atomicAdd(nsum, ns);
+  __syncthreads();
+  int32_t *out = block_hist + (size_t)blockIdx.x * kPlanBins;
+  for (int b = threadIdx.x; b < kPlanBins; b += blockDim.x) out[b] = hist[b];
 }
 
-// One workgroup: exclusive scan of the histogram from the longest bin down.
-__global__ __launch_bounds__(1024) void plan_scan_kernel(const int32_t *hist, int32_t *cursor,
-                                                         int32_t *meta) {
+// One thread per bin: every workgroup's first position inside the bin
+// (block_off[w][bin], counted from the bin's start) and the bin's total.
+__global__ __launch_bounds__(256) void plan_total_kernel(const int32_t *block_hist,
+                                                         int32_t *block_off, int32_t *totals) {
+  const int bin = blockIdx.x * blockDim.x + threadIdx.x;
+  if (bin >= kPlanBins) return;
+  int v[kPlanBlocks];
+#pragma unroll
+  for (int w = 0; w < kPlanBlocks; ++w) v[w] = block_hist[(size_t)w * kPlanBins + bin];
+  int run = 0;
+#pragma unroll
+  for (int w = 0; w < kPlanBlocks; ++w) {
+    block_off[(size_t)w * kPlanBins + bin] = run;
+    run += v[w];
+  }
+  totals[bin] = run;
+}
+
+// Places this workgroup's runnable pairs (the same range as plan_count): the
+// bins' starts in the longest-first order (an exclusive scan of the totals
+// from the longest bin down, redone by every workgroup) plus the workgroup's
+// offset inside each bin give LDS cursors.  Workgroup 0 also publishes the
+// number of entries and clears the alignment kernel's task counter.
+__global__ __launch_bounds__(1024) void plan_scatter_kernel(int n_pairs, const PairInfo *pairs,
+                                                            const int32_t *totals,
+                                                            const int32_t *block_off,
+                                                            int32_t *order, int32_t *meta) {
   constexpr int kPer = kPlanBins / 1024;
   __shared__ int32_t part[1024];
+  __shared__ int32_t cursor[kPlanBins];
   const int t = threadIdx.x;
   // thread t owns positions [t*kPer, (t+1)*kPer) of the descending order
   int v[kPer], sum = 0;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    v[q] = hist[kPlanBins - 1 - (t * kPer + q)];
+    v[q] = totals[kPlanBins - 1 - (t * kPer + q)];
     sum += v[q];
   }
   part[t] = sum;
@@ -153,25 +196,23 @@ __global__ __launch_bounds__(1024) void plan_scan_kernel(const int32_t *hist, in
     __syncthreads();
   }
   int run = part[t] - sum;   // exclusive prefix of this thread's positions
+  const int32_t *off = block_off + (size_t)blockIdx.x * kPlanBins;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
-    cursor[kPlanBins - 1 - (t * kPer + q)] = run;
+    const int bin = kPlanBins - 1 - (t * kPer + q);
+    cursor[bin] = run + off[bin];
     run += v[q];
   }
-  if (t == 1023) {
+  if (blockIdx.x == 0 && t == 1023) {
     meta[kMetaValid] = part[1023];
     meta[kMetaCounter] = 0;
   }
-}
-
-__global__ __launch_bounds__(256) void plan_scatter_kernel(int n_pairs, const PairInfo *pairs,
-                                                           int32_t *cursor, int32_t *order) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n_pairs) return;
-  const PairInfo p = pairs[k];
-  if (p.m > 0 && p.n > 0) {
-    const int bin = min((p.n + kBlock - 1) / kBlock, kPlanBins - 1);
-    order[atomicAdd(&cursor[bin], 1)] = k;
+  __syncthreads();
+  int lo, hi;
+  plan_range(n_pairs, lo, hi);
+  for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+    const PairInfo p = pairs[k];
+    if (p.m > 0 && p.n > 0) order[atomicAdd(&cursor[plan_bin(p.n)], 1)] = k;
   }
 }
 
@@ -221,26 +262,27 @@ hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *fl
 
 hipError_t launch_plan_count(int n_pairs, const int64_t *roff, const int32_t *pq,
                              const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
-                             int64_t q_off0, PairInfo *pairs, DevResult *results, int32_t *hist,
-                             int32_t *meta, unsigned long long *nsum, hipStream_t st) {
-  if (n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::plan_count_kernel, dim3((n_pairs + 255) / 256), dim3(256), 0, st,
-                     n_pairs, roff, pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, hist,
-                     meta, nsum);
+                             int64_t q_off0, PairInfo *pairs, DevResult *results,
+                             int32_t *block_hist, int32_t *meta, unsigned long long *nsum,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(dev::plan_count_kernel, dim3(kPlanBlocks), dim3(1024), 0, st, n_pairs, roff,
+                     pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, block_hist, meta, nsum);
   return hipGetLastError();
 }
 
-hipError_t launch_plan_scan(const int32_t *hist, int32_t *cursor, int32_t *meta, hipStream_t st) {
+hipError_t launch_plan_total(const int32_t *block_hist, int32_t *block_off, int32_t *totals,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(dev::plan_total_kernel, dim3((kPlanBins + 255) / 256), dim3(256), 0, st,
+                     block_hist, block_off, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_scatter(int n_pairs, const PairInfo *pairs, const int32_t *totals,
+                               const int32_t *block_off, int32_t *order, int32_t *meta,
+                               hipStream_t st) {
   static_assert(kPlanBins % 1024 == 0, "plan bins");
-  hipLaunchKernelGGL(dev::plan_scan_kernel, dim3(1), dim3(1024), 0, st, hist, cursor, meta);
-  return hipGetLastError();
-}
-
-hipError_t launch_plan_scatter(int n_pairs, const PairInfo *pairs, int32_t *cursor,
-                               int32_t *order, hipStream_t st) {
-  if (n_pairs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::plan_scatter_kernel, dim3((n_pairs + 255) / 256), dim3(256), 0, st,
-                     n_pairs, pairs, cursor, order);
+  hipLaunchKernelGGL(dev::plan_scatter_kernel, dim3(kPlanBlocks), dim3(1024), 0, st, n_pairs,
+                     pairs, totals, block_off, order, meta);
   return hipGetLastError();
 }
 
