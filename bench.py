@@ -31,6 +31,8 @@ METRIC = "GCUPS (bit-exact) batched vs plain kernel on one MI355X; p99 latency s
 PEAK_I32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PEAK_I16X2_TOPS = 2 * PEAK_I32_TOPS
 OPS_PER_CELL = 11   # Algorithm 6 inner loop: 1 add, 6 max, 4 sub
+# the alignment kernel of a device-planned int16 single-query batch
+KERNEL_NAME = "shared_rowpair_kernel<16>"
 
 
 def _csrc_sha256() -> str:
@@ -47,7 +49,7 @@ def _csrc_sha256() -> str:
 def _measured_traffic():
     """HBM bytes per launch from the committed counter summary, or None when
     the kernel sources changed after the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "traffic_shared_kernel_protein_search.json")
+    path = os.path.join(ROOT, "profiles", "traffic_shared_rowpair_kernel_protein_search.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -139,7 +141,7 @@ def main():
         "config": {"workload": "protein_search: 512-residue query vs 100k refs "
                                "(log-normal median 350, clipped 50-5000), int16x2 + int32 rerun",
                    "pairs": w.n_pairs, "cells": cells, "query_len": 512},
-        "roofline": {"bound": "alu", "achieved": round(achieved_tops, 3),
+        "roofline": {"bound": "alu", "kernel": KERNEL_NAME, "achieved": round(achieved_tops, 3),
                      "peak": round(PEAK_I16X2_TOPS, 2), "unit": "Tops/s",
                      "frac": round(achieved_tops / PEAK_I16X2_TOPS, 4),
                      "traffic": _measured_traffic(),
