@@ -232,7 +232,8 @@ def bench_dna(args):
     d, pq = _device_batch(w)
     tuned = [] if args.no_tune else api.sw_autotune(*d, w.matrix, w.gap_open, w.gap_extend,
                                                      pair_query=pq)
-    step = lambda: api.sw_align_batch(*d, w.matrix, w.gap_open, w.gap_extend, pair_query=pq)  # noqa
+    step = lambda **kw: api.sw_align_batch(*d, w.matrix, w.gap_open, w.gap_extend,  # noqa
+                                           pair_query=pq, **kw)
     for _ in range(args.warmup):
         out = step()
     torch.cuda.synchronize()
@@ -243,6 +244,14 @@ def bench_dna(args):
         kms.append(out.stats["kernel_ms"])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
+    # the same calls with the host planner
+    oh = step(planner=1)
+    torch.cuda.synchronize()
+    th = time.perf_counter()
+    for _ in range(max(1, args.steps // 2)):
+        oh = step(planner=1)
+    torch.cuda.synchronize()
+    host_wall = (time.perf_counter() - th) / max(1, args.steps // 2)
     cells = w.cells()
     km = float(np.mean(kms))
     ach = cells * OPS_PER_CELL / (km / 1e3) / 1e12
@@ -260,7 +269,13 @@ def bench_dna(args):
                                    "kernel_gcups": round(cells / (km / 1e3) / 1e9, 1)},
                       "stats": {k: out.stats[k] for k in ("n_rerun", "lanes_used", "seglen_max",
                                                           "prep_ms", "plan_ms", "launch_ms",
-                                                          "finish_ms", "total_ms")},
+                                                          "finish_ms", "total_ms",
+                                                          "planner_used")},
+                      "host_planner": {"ms_per_step": round(host_wall * 1e3, 3),
+                                       "gcups": round(cells / host_wall / 1e9, 2),
+                                       "kernel_ms": round(oh.stats["kernel_ms"], 3),
+                                       "same_results": bool(np.array_equal(oh.results,
+                                                                           out.results))},
                       "tuned": [{k: (round(v, 1) if isinstance(v, float) else v)
                                  for k, v in e.items()} for e in tuned]}))
 

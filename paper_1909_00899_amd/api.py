@@ -225,7 +225,7 @@ def _is_torch_cuda(x) -> bool:
 
 @dataclass
 class BatchOutput:
-    results: np.ndarray      # (n_pairs, 4) int64: score, query_end, ref_end, flags
+    results: np.ndarray      # (n_pairs, 4) int32: score, query_end, ref_end, flags
     stats: dict
 
 
@@ -281,13 +281,13 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
     sc, M = make_scoring(matrix, gap_open, gap_extend)
     opt = Options(algorithm, force_lanes, force_seglen, force_kernel, mixed_layout, int16_cap,
                   use_graph, planner, lane_pairing)
-    out = np.zeros((max(npairs, 1), 4), dtype=np.int32)
+    # the library writes every entry (sw_result layout: four int32; flags are
+    # small bit sets), so the array is returned as it is, without a copy
+    out = np.empty((max(npairs, 1), 4), dtype=np.int32)
     st = Stats()
     _check(lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
                                  out.ctypes.data, ctypes.byref(st)))
-    res = out[:npairs].astype(np.int64)
-    res[:, 3] = out[:npairs, 3].view(np.uint32)
-    return BatchOutput(res, st.as_dict())
+    return BatchOutput(out[:npairs], st.as_dict())
 
 
 def align_workload(w, **kw) -> BatchOutput:

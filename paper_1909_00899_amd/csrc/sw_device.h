@@ -1030,14 +1030,15 @@ __host__ __device__ constexpr uint32_t pair_region_bytes(int seg, int alpha, int
   return (uint32_t)(halves * (alpha + 1) * seg * kWave * es);
 }
 
+// pids[h]: PairInfo index of this lane's sub-group in half h, or -1.
 template <class O, int SEG>
-__device__ __forceinline__ void build_pair_profile(const KArgs &a, const Task *tp, const LaneCtx &L,
-                                                   uint32_t region, int row0) {
+__device__ __forceinline__ void build_pair_profile(const KArgs &a, const int pids[2],
+                                                   const LaneCtx &L, uint32_t region, int row0) {
   const int32_t *M = (const int32_t *)smem;
   const int nrow = a.alpha + 1;
 #pragma unroll
   for (int h = 0; h < O::kHalves; ++h) {
-    const int pid = tp->pair[2 * L.sg + h];
+    const int pid = pids[h];
     int m = 0;
     int64_t qo = 0;
     if (pid >= 0) { m = a.pairs[pid].m; qo = a.pairs[pid].q_off; }
@@ -1079,7 +1080,8 @@ void pair_kernel(KArgs a) {
     prev_reset(prev);
     for (int ch = 0; ch < nch; ++ch) {
       const int row0 = ch * L.P * SEG;
-      build_pair_profile<O, SEG>(a, a.tasks + ti, L, region, row0);
+      const int pids[2] = {t.pair[2 * L.sg], t.pair[2 * L.sg + 1]};
+      build_pair_profile<O, SEG>(a, pids, L, region, row0);
       State<SEG> st;
       state_reset(st, prev_g0<O>(prev));
       const uint32_t *hb_in = nullptr, *fb_in = nullptr;
@@ -1105,6 +1107,70 @@ void pair_kernel(KArgs a) {
   if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
     if (cols) atomicAdd(&a.stats[0], cols);
     if (events) atomicAdd(&a.stats[2], events);
+  }
+}
+
+// Device-planned per-pair kernel: every pair has its own query (one query
+// chunk, 16 rows-per-lane x 16 lanes at most), four 16-lane sub-groups per
+// wavefront, in int16 mode two alignments per lane.  Task t is entries
+// [t*slots, (t+1)*slots) of the planner's longest-first order (entry
+// t*slots + s to sub-group s / halves, half s % halves); profiles are built
+// per task in the wavefront's own LDS region; residues come from the
+// references themselves.
+template <class O, int SEG>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+void pair_direct_kernel(KArgs a) {
+  if (a.plan_meta[kMetaErrResidue] | a.plan_meta[kMetaErrPair]) return;
+  stage_matrix(a);
+  __syncthreads();
+  const uint32_t region = matrix_lds_bytes(a.alpha);
+  constexpr int kSlotsPerTask = 4 * O::kHalves;
+  const int nvalid = a.plan_meta[kMetaValid];
+  const int ntasks = (nvalid + kSlotsPerTask - 1) / kSlotsPerTask;
+  const LaneCtx L = make_lane<O>(0xF, SEG, (uint32_t)a.gap_extend);
+  const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
+  PairMap<O, SEG> pm;
+  pm.lo0 = region + L.lane * O::kES;
+  pm.hi0 = pm.lo0 + (O::kHalves == 2 ? (a.alpha + 1) * SEG * kWave * O::kES : 0);
+  const uint32_t sentw = (uint32_t)a.alpha * 0x01010101u;
+  uint32_t lazy_steps = 0;
+  unsigned long long cols = 0, events = 0, padded = 0;
+  for (;;) {
+    const int ti = pop_task(a.plan_meta + kMetaCounter);
+    if (ti >= ntasks) break;
+    int pid[2] = {-1, -1};
+    int64_t roff[2] = {0, 0};
+    int n[2] = {0, 0};
+#pragma unroll
+    for (int h = 0; h < O::kHalves; ++h) {
+      const int e = ti * kSlotsPerTask + L.sg * O::kHalves + h;
+      if (e < nvalid) {
+        pid[h] = a.order[e];
+        const PairInfo p = a.pairs[pid[h]];
+        roff[h] = p.r_off;
+        n[h] = p.n;
+      }
+    }
+    int nmax = max(n[0], n[1]);
+    for (int d = 1; d < kWave; d <<= 1) nmax = max(nmax, __shfl_xor(nmax, d));
+    const int ncols = (nmax + kBlock - 1) / kBlock * kBlock;
+    build_pair_profile<O, SEG>(a, pid, L, region, 0);
+    Prev prev;
+    prev_reset(prev);
+    State<SEG> st;
+    state_reset(st, 0u);
+    const DirectSrc src{a.ref_res + roff[0], a.ref_res + roff[1], n[0], n[1], sentw};
+    run_columns<O, SEG, 16, false, false>(st, L, pr, pm, src, ncols, nullptr, nullptr, nullptr,
+                                          nullptr, lazy_steps);
+    cols += (unsigned long long)ncols;
+    events += st.events;
+    padded += (unsigned long long)min(kSlotsPerTask, nvalid - ti * kSlotsPerTask) * ncols * 16 * SEG;
+    finish<O, SEG>(st, L, pid, a.pairs, a.results, 0, prev, a.sat_cap);
+  }
+  if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
+    if (cols) atomicAdd(&a.stats[0], cols);
+    if (events) atomicAdd(&a.stats[2], events);
+    if (padded) atomicAdd(&a.stats[3], padded);
   }
 }
 

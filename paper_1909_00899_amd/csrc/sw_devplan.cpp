@@ -1,7 +1,9 @@
-// Device planner for single-query batches (sw_align_batch with one query):
-// the pairs are validated, counted by reference length, ordered longest
-// first and run by the shared-query kernel entirely on the device; the host
-// reads four offsets before the launch and the results after it.
+// Device planner (sw_align_batch): the pairs are validated, counted by
+// reference length, ordered longest first and run entirely on the device,
+// by the shared-query kernel for a batch with one query, by the per-pair
+// kernel when every pair has its own query.  The host reads four offsets
+// before the launch (and, for per-pair queries, the longest query length
+// once the pairs are counted) and the results after it.
 //
 // Steps on the device (one stream, capturable as one hipGraph):
 //   matrix upload, clearing of the plan words (a fill kernel),
@@ -20,6 +22,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <vector>
 
 #include "sw.h"
@@ -44,6 +47,9 @@ using namespace swk;
 namespace {
 
 constexpr int kDevPlanMinPairs = 4096;   // smaller batches: the host planner
+// LDS of one per-pair wavefront (matrix and profiles): keeps several
+// wavefronts per CU
+constexpr size_t kPairDirectLds = 24 * 1024;
 constexpr int64_t kI32Limit = 2147483647ll;
 
 // Layout of the plan buffer, in int32 words.
@@ -103,6 +109,34 @@ bool pick_rowpair_seg(int m, int alpha, int force_seg, int &seg) {
   return false;
 }
 
+// Rows per lane of the device-planned per-pair kernel for queries of up to
+// max_m residues: the forced value, else the autotuner's 16-lane entry, else
+// the smallest compiled one; within the per-wavefront LDS budget.
+bool pick_pair_seg(Prec prec, int alpha, int max_m, const ExecOptions &eo, int &seg) {
+  auto fits = [&](int s) {
+    return pair_direct_has(s) && 16 * s >= max_m &&
+           pair_direct_lds_bytes(prec, s, alpha) <= kPairDirectLds;
+  };
+  if (eo.force_seglen) {
+    if (!fits(eo.force_seglen)) return false;
+    seg = eo.force_seglen;
+    return true;
+  }
+  sw_tune_entry te;
+  if (eo.use_tuning && tune_lookup(SW_TUNE_PAIR, prec, alpha, max_m, te) && te.lanes == 16 &&
+      fits(te.seglen)) {
+    seg = te.seglen;
+    return true;
+  }
+  for (int s : {4, 6, 8, 10, 12, 16}) {
+    if (fits(s)) {
+      seg = s;
+      return true;
+    }
+  }
+  return false;
+}
+
 }  // namespace
 
 int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, int planner,
@@ -120,12 +154,16 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     return SW_OK;
   };
   if (eo.algorithm != SW_ALG_SCAN) return refuse("only the scan algorithm is device-planned");
-  if (eo.force_kernel == 2) return refuse("the per-pair kernel is host-planned");
-  if (b->pair_query && b->n_queries != 1) return refuse("more than one query");
   if (planner == 0 && np < kDevPlanMinPairs) return SW_OK;
   if (!b->query_res || !b->query_off || !b->ref_res || !b->ref_off || !b->pair_ref ||
       b->n_queries < 1 || b->n_refs < 1)
     return SW_OK;   // the host path reports the argument error
+  // one query (the shared-query kernel) or one query per pair (the per-pair kernel)
+  const bool single = b->pair_query == nullptr || b->n_queries == 1;
+  if (single && eo.force_kernel == 2) return refuse("one query runs in the shared-query kernel");
+  if (!single && eo.force_kernel == 1) return refuse("several queries run in the per-pair kernel");
+  if (!single && eo.lane_pairing == SW_PAIRING_ROWS) return refuse("row pairs need one query");
+  if (!single && eo.force_lanes && eo.force_lanes != 16) return refuse("per-pair launches use 16 lanes");
   hipStream_t st = C.stream;
   Workspace &ws = C.ws;
   // query 0's offsets, the query set's end and the reference set's end
@@ -152,38 +190,36 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   const int64_t q_off0 = hv[0], qbytes = hv[2], rbytes = hv[3];
   if (q_off0 < 0 || hv[1] < q_off0 || hv[1] > qbytes || hv[1] - q_off0 > kI32Limit || rbytes < 0)
     return SW_OK;   // malformed offsets: the host path reports them
-  const int m = (int)(hv[1] - q_off0);
-  if (m == 0) return SW_OK;
-  if ((int64_t)m * S.max_s >= kI32Limit) return refuse("the query may overflow int32");
+  const int m = single ? (int)(hv[1] - q_off0) : 0;
+  if (single && m == 0) return SW_OK;
+  if (single && (int64_t)m * S.max_s >= kI32Limit) return refuse("the query may overflow int32");
   const Prec prec = (b->precision == SW_PREC_AUTO && S.fits_i16) ? PREC_I16X2 : PREC_I32;
-  int seg = 0, lanes = 0;
-  // row pairs: both halves of a lane hold rows of the same alignment
-  bool rows = false;
-  if (eo.lane_pairing == SW_PAIRING_ROWS) {
-    if (prec != PREC_I16X2) return refuse("row pairs need int16 lanes");
-    if (eo.force_lanes && eo.force_lanes != 16) return refuse("row pairs use 16 lanes");
-    rows = pick_rowpair_seg(m, S.alpha, eo.force_seglen, seg);
-    if (!rows) return refuse("no compiled row-pair shape holds the query");
-    lanes = 16;
-  } else if (eo.lane_pairing == SW_PAIRING_AUTO && prec == PREC_I16X2 && !eo.force_lanes &&
-             !eo.force_seglen && pick_rowpair_seg(m, S.alpha, 0, seg)) {
-    // the default for int16 lanes: one profile word per row pair
-    rows = true;
-    lanes = 16;
-  } else if (!pick_direct_shape(prec, S.alpha, m, eo, seg, lanes)) {
-    return refuse("no compiled shape holds the query in one chunk");
+  int seg = 0, lanes = 16;
+  bool rows = false;   // row pairs: both halves of a lane hold rows of one alignment
+  if (single) {
+    if (eo.lane_pairing == SW_PAIRING_ROWS) {
+      if (prec != PREC_I16X2) return refuse("row pairs need int16 lanes");
+      if (eo.force_lanes && eo.force_lanes != 16) return refuse("row pairs use 16 lanes");
+      rows = pick_rowpair_seg(m, S.alpha, eo.force_seglen, seg);
+      if (!rows) return refuse("no compiled row-pair shape holds the query");
+    } else if (eo.lane_pairing == SW_PAIRING_AUTO && prec == PREC_I16X2 && !eo.force_lanes &&
+               !eo.force_seglen && pick_rowpair_seg(m, S.alpha, 0, seg)) {
+      rows = true;   // the default for int16 lanes: one profile word per row pair
+    } else if (!pick_direct_shape(prec, S.alpha, m, eo, seg, lanes)) {
+      return refuse("no compiled shape holds the query in one chunk");
+    }
+    handled = true;
   }
-  handled = true;
 
   // ---- buffers
   int rc;
+  const size_t mat_bytes = sizeof(int) * S.M.size();
   const size_t plan_words = (size_t)kPlanOrder + np;
   if ((rc = ws.plan.ensure(plan_words * sizeof(int32_t))) ||
       (rc = ws.offs.ensure((size_t)np * sizeof(PairInfo) + 4096)) ||
       (rc = ws.results.ensure((size_t)np * sizeof(DevResult))) ||
-      (rc = ws.matrix.ensure(sizeof(int) * S.M.size())) ||
-      (rc = ws.staging.ensure((sizeof(int) * S.M.size() + 63) / 64 * 64 +
-                              sizeof(int32_t) * (kPlanMeta + kMetaWords))))
+      (rc = ws.matrix.ensure(mat_bytes)) ||
+      (rc = ws.staging.ensure((mat_bytes + 63) / 64 * 64 + sizeof(int32_t) * (kPlanMeta + kMetaWords))))
     return rc;
   int32_t *plan = ws.plan.as<int32_t>();
   unsigned long long *d_stats = (unsigned long long *)(plan + kPlanStats);
@@ -192,17 +228,19 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   DevResult *d_res = ws.results.as<DevResult>();
   // sequences and offsets on the device
   const uint8_t *d_qres = b->query_res, *d_rres = b->ref_res;
-  const int64_t *d_roff = b->ref_off;
+  const int64_t *d_roff = b->ref_off, *d_qoff = b->query_off;
   const int32_t *d_pq = b->pair_query, *d_pr = b->pair_ref;
   if (!b->device_resident) {
+    const size_t o_roff = 0, o_qoff = o_roff + sizeof(int64_t) * (b->n_refs + 1);
+    const size_t o_pr = o_qoff + sizeof(int64_t) * (b->n_queries + 1);
+    const size_t o_pq = o_pr + sizeof(int32_t) * np;
     if ((rc = C.qres.ensure(std::max<int64_t>(qbytes, 1))) ||
         (rc = C.rres.ensure(std::max<int64_t>(rbytes, 1))) ||
-        (rc = ws.pairs.ensure(sizeof(int64_t) * (b->n_refs + 1) + sizeof(int32_t) * 2 * np + 64)))
+        (rc = ws.pairs.ensure(o_pq + sizeof(int32_t) * np + 64)))
       return rc;
     char *base = ws.pairs.as<char>();
-    const size_t o_roff = 0, o_pr = o_roff + sizeof(int64_t) * (b->n_refs + 1);
-    const size_t o_pq = o_pr + sizeof(int32_t) * np;
-    HIPCHK(hipMemcpyAsync(base + o_roff, b->ref_off, o_pr - o_roff, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + o_roff, b->ref_off, o_qoff - o_roff, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + o_qoff, b->query_off, o_pr - o_qoff, hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(base + o_pr, b->pair_ref, sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
     if (b->pair_query)
       HIPCHK(hipMemcpyAsync(base + o_pq, b->pair_query, sizeof(int32_t) * np, hipMemcpyHostToDevice, st));
@@ -211,86 +249,54 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     d_qres = C.qres.as<uint8_t>();
     d_rres = C.rres.as<uint8_t>();
     d_roff = (const int64_t *)(base + o_roff);
+    d_qoff = (const int64_t *)(base + o_qoff);
     d_pr = (const int32_t *)(base + o_pr);
     d_pq = b->pair_query ? (const int32_t *)(base + o_pq) : nullptr;
   }
   int *stg = ws.staging.as<int>();
-  std::memcpy(stg, S.M.data(), sizeof(int) * S.M.size());
+  std::memcpy(stg, S.M.data(), mat_bytes);
+  unsigned char *tail = (unsigned char *)ws.staging.p + (mat_bytes + 63) / 64 * 64;
 
-  // ---- the device work as a list of operations (eager or one graph)
-  KArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.pairs = d_pairs;
-  a.query_res = d_qres;
-  a.shared_q_off = q_off0;
-  a.shared_m = m;
-  a.alpha = S.alpha;
-  a.matrix = ws.matrix.as<int32_t>();
-  a.gap_open = S.go;
-  a.gap_extend = S.ge;
-  a.last_chunk = 1;
-  a.sat_cap = eo.int16_cap;
-  a.results = d_res;
-  a.stats = d_stats;
-  a.order = plan + kPlanOrder;
-  a.plan_meta = meta;
-  a.ref_res = d_rres;
-  const int slots = rows ? kWave / 16 : (kWave / lanes) * (prec == PREC_I16X2 ? 2 : 1);
-  const int ntasks_max = (np + slots - 1) / slots;
-  const int grid = std::max(1, std::min((ntasks_max + kWavesPerGroup - 1) / kWavesPerGroup,
-                                        C.num_cus * 2));
+  // ---- the device work: eager, or captured once per parameter signature and
+  // replayed (one graph for a single query; for per-pair queries one before
+  // and one after the host reads the longest query length)
   int32_t *boff = plan + kPlanOff;
   int32_t *totals = plan + kPlanTotals;
   int32_t *hist = plan + kPlanHist;
   int32_t *order = plan + kPlanOrder;
-  const int ni = b->n_refs;
+  const int ni = b->n_refs, nq = b->n_queries;
   const int alpha = S.alpha;
-  const size_t mat_bytes = sizeof(int) * S.M.size();
   int32_t *d_mat = ws.matrix.as<int32_t>();
-  auto prep = [=]() -> hipError_t {
-    hipError_t e = hipMemcpyAsync(d_mat, stg, mat_bytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)plan, kPlanCleared, 0u, st);
-    if (e == hipSuccess) e = launch_check_residues(d_qres, qbytes, alpha, meta + kMetaErrResidue, st);
-    if (e == hipSuccess) e = launch_check_residues(d_rres, rbytes, alpha, meta + kMetaErrResidue, st);
-    if (e == hipSuccess)
-      e = launch_plan_count(np, d_roff, d_pq, d_pr, ni, rbytes, m, q_off0, d_pairs, d_res, hist,
-                            meta, d_stats + 4, st);
-    if (e == hipSuccess) e = launch_plan_total(hist, boff, totals, st);
-    if (e == hipSuccess) e = launch_plan_scatter(np, d_pairs, totals, boff, order, meta, st);
-    return e;
-  };
-  auto align = [=]() {
-    return rows ? launch_shared_rowpair(seg, a, grid, st)
-                : launch_shared_direct(prec, seg, lanes, a, grid, st);
-  };
-  const double t_launch0 = now_ms();
   ExecStats es;
-  es.plan_ms = t_launch0 - t0;
-  if (!eo.use_graph) {
-    hipError_t e = prep();
-    if (e != hipSuccess) { set_error("device planner: %s", hipGetErrorString(e)); return SW_EDEVICE; }
-    HIPCHK(hipEventRecord(C.ev0, st));
-    e = align();
-    if (e != hipSuccess) { set_error("device-planned launch: %s", hipGetErrorString(e)); return SW_EDEVICE; }
-    HIPCHK(hipEventRecord(C.ev1, st));
-  } else {
-    const uint64_t sig[] = {0xD1D1, (uint64_t)prec, (uint64_t)seg, (uint64_t)lanes, (uint64_t)rows,
-                            (uint64_t)grid, (uint64_t)np, (uint64_t)(uintptr_t)d_qres,
-                            (uint64_t)(uintptr_t)d_rres, (uint64_t)(uintptr_t)d_roff,
-                            (uint64_t)(uintptr_t)d_pq, (uint64_t)(uintptr_t)d_pr, (uint64_t)ni,
-                            (uint64_t)rbytes, (uint64_t)qbytes, (uint64_t)m, (uint64_t)q_off0,
-                            (uint64_t)alpha, (uint64_t)S.go, (uint64_t)S.ge,
-                            (uint64_t)eo.int16_cap, (uint64_t)(uintptr_t)plan,
-                            (uint64_t)(uintptr_t)d_pairs, (uint64_t)(uintptr_t)d_res,
-                            (uint64_t)(uintptr_t)d_mat, (uint64_t)(uintptr_t)stg};
-    const std::vector<uint64_t> sv(sig, sig + sizeof(sig) / sizeof(sig[0]));
+  const std::vector<uint64_t> base_sig = {
+      (uint64_t)prec, (uint64_t)np, (uint64_t)(uintptr_t)d_qres, (uint64_t)(uintptr_t)d_rres,
+      (uint64_t)(uintptr_t)d_roff, (uint64_t)(uintptr_t)d_qoff, (uint64_t)(uintptr_t)d_pq,
+      (uint64_t)(uintptr_t)d_pr, (uint64_t)ni, (uint64_t)nq, (uint64_t)rbytes, (uint64_t)qbytes,
+      (uint64_t)m, (uint64_t)q_off0, (uint64_t)alpha, (uint64_t)S.go, (uint64_t)S.ge,
+      (uint64_t)eo.int16_cap, (uint64_t)(uintptr_t)plan, (uint64_t)(uintptr_t)d_pairs,
+      (uint64_t)(uintptr_t)d_res, (uint64_t)(uintptr_t)d_mat, (uint64_t)(uintptr_t)stg};
+  // runs fn eagerly, or as a graph keyed by base_sig + extra; `timed` brackets
+  // it with the kernel-time events
+  auto run = [&](const std::vector<uint64_t> &extra, const std::function<hipError_t()> &fn,
+                 bool timed) -> int {
+    if (!eo.use_graph) {
+      if (timed) HIPCHK(hipEventRecord(C.ev0, st));
+      const hipError_t e = fn();
+      if (e != hipSuccess) {
+        set_error("device-planned launch: %s", hipGetErrorString(e));
+        return SW_EDEVICE;
+      }
+      if (timed) HIPCHK(hipEventRecord(C.ev1, st));
+      return SW_OK;
+    }
+    std::vector<uint64_t> sv = base_sig;
+    sv.insert(sv.end(), extra.begin(), extra.end());
     hipGraphExec_t exec = ws.graphs.find(sv);
     if (exec) {
       es.graph_hits++;
     } else {
       HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-      hipError_t e = prep();
-      if (e == hipSuccess) e = align();
+      const hipError_t e = fn();
       hipGraph_t graph = nullptr;
       const hipError_t ec = hipStreamEndCapture(st, &graph);
       if (e != hipSuccess || ec != hipSuccess) {
@@ -306,15 +312,99 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
       }
       ws.graphs.put(sv, exec);
     }
-    HIPCHK(hipEventRecord(C.ev0, st));
+    if (timed) HIPCHK(hipEventRecord(C.ev0, st));
     HIPCHK(hipGraphLaunch(exec, st));
-    HIPCHK(hipEventRecord(C.ev1, st));
+    if (timed) HIPCHK(hipEventRecord(C.ev1, st));
+    return SW_OK;
+  };
+  auto prep = [=]() -> hipError_t {
+    hipError_t e = hipMemcpyAsync(d_mat, stg, mat_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = launch_fill_u32((uint32_t *)plan, kPlanCleared, 0u, st);
+    if (e == hipSuccess) e = launch_check_residues(d_qres, qbytes, alpha, meta + kMetaErrResidue, st);
+    if (e == hipSuccess) e = launch_check_residues(d_rres, rbytes, alpha, meta + kMetaErrResidue, st);
+    if (e == hipSuccess)
+      e = launch_plan_count(np, single ? nullptr : d_qoff, nq, qbytes, d_roff, d_pq, d_pr, ni,
+                            rbytes, m, q_off0, d_pairs, d_res, hist, meta, d_stats, st);
+    return e;
+  };
+  auto place = [=]() -> hipError_t {
+    hipError_t e = launch_plan_total(hist, boff, totals, st);
+    if (e == hipSuccess) e = launch_plan_scatter(np, d_pairs, totals, boff, order, meta, st);
+    return e;
+  };
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.pairs = d_pairs;
+  a.query_res = d_qres;
+  a.shared_q_off = q_off0;
+  a.shared_m = m;
+  a.alpha = S.alpha;
+  a.matrix = d_mat;
+  a.gap_open = S.go;
+  a.gap_extend = S.ge;
+  a.last_chunk = 1;
+  a.sat_cap = eo.int16_cap;
+  a.results = d_res;
+  a.stats = d_stats;
+  a.order = order;
+  a.plan_meta = meta;
+  a.ref_res = d_rres;
+  const double t_launch0 = now_ms();
+  es.plan_ms = t_launch0 - t0;
+  int max_m = m;
+  if (single) {
+    const int slots = rows ? kWave / 16 : (kWave / lanes) * (prec == PREC_I16X2 ? 2 : 1);
+    const int ntasks_max = (np + slots - 1) / slots;
+    const int grid = std::max(1, std::min((ntasks_max + kWavesPerGroup - 1) / kWavesPerGroup,
+                                          C.num_cus * 2));
+    auto all = [=]() -> hipError_t {
+      hipError_t e = prep();
+      if (e == hipSuccess) e = place();
+      if (e == hipSuccess)
+        e = rows ? launch_shared_rowpair(seg, a, grid, st)
+                 : launch_shared_direct(prec, seg, lanes, a, grid, st);
+      return e;
+    };
+    if ((rc = run({0xD1D1, (uint64_t)seg, (uint64_t)lanes, (uint64_t)rows, (uint64_t)grid}, all,
+                  true)))
+      return rc;
+  } else {
+    // the longest query decides the rows per lane
+    if ((rc = run({0xD2D1}, prep, false))) return rc;
+    HIPCHK(hipMemcpyAsync(tail, plan, (size_t)(kPlanMeta + kMetaWords) * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int32_t hm0[kMetaWords];
+    std::memcpy(hm0, tail + kPlanMeta * sizeof(int32_t), sizeof(hm0));
+    max_m = hm0[kMetaMaxM];
+    if (!hm0[kMetaErrResidue] && !hm0[kMetaErrPair] && max_m > 0) {
+      const bool ok = (int64_t)max_m * S.max_s < kI32Limit &&
+                      pick_pair_seg(prec, S.alpha, max_m, eo, seg);
+      if (!ok) {
+        // nothing was written to `out`: the host planner takes the batch
+        if (planner == 2) {
+          handled = true;
+          set_error("device planner: no per-pair shape holds queries of %d residues", max_m);
+          return SW_EINVAL;
+        }
+        return SW_OK;
+      }
+      const int slots = 4 * (prec == PREC_I16X2 ? 2 : 1);
+      const int ntasks_max = (np + slots - 1) / slots;
+      const int grid = std::max(1, std::min(ntasks_max, C.num_cus * 16));
+      auto rest = [=]() -> hipError_t {
+        hipError_t e = place();
+        if (e == hipSuccess) e = launch_pair_direct(prec, seg, a, grid, st);
+        return e;
+      };
+      if ((rc = run({0xD2D2, (uint64_t)seg, (uint64_t)grid}, rest, true))) return rc;
+    }
+    handled = true;
   }
   const double t_fin0 = now_ms();
   es.launch_ms = t_fin0 - t_launch0;
   // ---- results, statistics and the plan's error words
   // staging: [matrix | plan words read back]; results go straight to `out`
-  unsigned char *tail = (unsigned char *)ws.staging.p + (mat_bytes + 63) / 64 * 64;
   HIPCHK(hipMemcpyAsync(out, d_res, (size_t)np * sizeof(DevResult), hipMemcpyDeviceToHost, st));
   HIPCHK(hipMemcpyAsync(tail, plan, (size_t)(kPlanMeta + kMetaWords) * sizeof(int32_t),
                         hipMemcpyDeviceToHost, st));
@@ -324,12 +414,12 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   std::memcpy(hs, tail, sizeof(hs));
   std::memcpy(hm, tail + kPlanMeta * sizeof(int32_t), sizeof(hm));
   float kms = 0;
-  HIPCHK(hipEventElapsedTime(&kms, C.ev0, C.ev1));
+  if (seg > 0) HIPCHK(hipEventElapsedTime(&kms, C.ev0, C.ev1));
   if (hm[kMetaErrResidue] || hm[kMetaErrPair]) {
     for (int k = 0; k < np; ++k) out[k] = sw_result{0, -1, -1, 0};
     set_error(hm[kMetaErrResidue] ? "a residue code is >= alphabet_size"
-                                  : "a pair refers to a query other than 0, a reference out of "
-                                    "range, or reference offsets that are not nondecreasing");
+                                  : "a pair refers to a query or reference out of range, or "
+                                    "offsets that are not nondecreasing");
     return SW_EINVAL;
   }
   // ---- exact int32 rerun of the pairs whose int16 lanes saturated
@@ -346,13 +436,21 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     in2.d_rres = d_rres;
     in2.d_pairs = d_pairs;
     in2.n_pairs = np;
-    for (int k : again) in2.items.push_back(PlanItem{k, 0, hp[k].m, hp[k].n});
-    in2.n_queries = 1;
-    in2.q_off_of_query = {q_off0};
-    in2.m_of_query = {m};
+    // one query: query 0 (many reruns share its profile); per-pair queries:
+    // every rerun pair as its own query (its PairInfo holds the query offset)
+    for (int k : again) {
+      const int q = single ? 0 : (int)in2.q_off_of_query.size();
+      in2.items.push_back(PlanItem{k, q, hp[k].m, hp[k].n});
+      if (!single || in2.q_off_of_query.empty()) {
+        in2.q_off_of_query.push_back(hp[k].q_off);
+        in2.m_of_query.push_back(hp[k].m);
+      }
+    }
+    in2.n_queries = (int)in2.q_off_of_query.size();
     ExecOptions o2 = eo;
     o2.force_lanes = 0;
     o2.force_seglen = 0;
+    o2.force_kernel = 0;
     o2.use_graph = 0;
     ExecStats es2;
     if ((rc = execute(in2, S, PREC_I32, o2, ws, np, st, C.ev0, C.ev1, C.num_cus, es2, false)))
@@ -372,10 +470,10 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   if (stats) {
     stats->kernel_ms = kms + es.kernel_ms;
     stats->total_ms = now_ms() - t0;
-    stats->cells = (int64_t)m * (int64_t)hs[4];
+    stats->cells = (int64_t)hs[5];
     stats->padded_cells = (int64_t)hs[3];
     stats->n_rerun = (int)again.size();
-    stats->n_launches = 1 + es.launches;
+    stats->n_launches = (seg > 0 ? 1 : 0) + es.launches;
     stats->columns = (int64_t)hs[0];
     stats->record_events = (int64_t)hs[2];
     stats->lanes_used[lanes == 16 ? 0 : (lanes == 32 ? 1 : 2)] = hm[kMetaValid];

@@ -83,7 +83,8 @@ enum : int {
   kMetaValid = 0,       // pairs with m > 0 and n > 0 (entries of `order`)
   kMetaCounter = 1,     // task counter of the alignment kernel
   kMetaErrResidue = 2,  // set if a residue code is >= alpha
-  kMetaErrPair = 3,     // set if a pair's reference id or offsets are invalid
+  kMetaErrPair = 3,     // set if a pair's query / reference id or offsets are invalid
+  kMetaMaxM = 4,        // largest query length of the runnable pairs
   kMetaWords = 16
 };
 // Length bins of the planner's counting sort: bin = ceil(n / kBlock), the
@@ -120,18 +121,20 @@ hipError_t launch_build_streams(const Task *tasks, int ntasks, const PairInfo *p
 // p[0..n) = v.
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 
-// Device planner of a single-query batch (query length m at q_off0), run by
-// kPlanBlocks workgroups that each take a contiguous range of the pairs.
-// plan_count: PairInfo of every pair with its reference checked (0 <= id <
-// n_refs, 0 <= roff[id] <= roff[id+1] <= ref_bytes; otherwise
-// meta[kMetaErrPair] is set and the pair gets n = 0), results set to
+// Device planner, run by kPlanBlocks workgroups that each take a contiguous
+// range of the pairs.  qoff == nullptr: one query (id 0) of length m at
+// q_off0; else every pair's own query (pq, query offsets, query bytes).
+// plan_count: PairInfo of every pair with its query and reference checked
+// (ids in range, 0 <= off[id] <= off[id+1] <= bytes; otherwise
+// meta[kMetaErrPair] is set and the pair gets m = n = 0), results set to
 // {0, -1, -1, 0}, block_hist[w][bin] = the workgroup's pairs with m, n > 0 per
-// length bin, and *nsum += the sum of their n.
-hipError_t launch_plan_count(int n_pairs, const int64_t *roff, const int32_t *pq,
-                             const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
-                             int64_t q_off0, PairInfo *pairs, DevResult *results,
-                             int32_t *block_hist, int32_t *meta, unsigned long long *nsum,
-                             hipStream_t st);
+// length bin, stats[4] += sum of their n, stats[5] += sum of m*n,
+// meta[kMetaMaxM] = their largest m.
+hipError_t launch_plan_count(int n_pairs, const int64_t *qoff, int n_queries, int64_t qbytes,
+                             const int64_t *roff, const int32_t *pq, const int32_t *pr, int n_refs,
+                             int64_t ref_bytes, int m, int64_t q_off0, PairInfo *pairs,
+                             DevResult *results, int32_t *block_hist, int32_t *meta,
+                             unsigned long long *stats, hipStream_t st);
 // plan_total: block_off[w][bin] = workgroup w's first position inside the
 // bin, totals[bin] = pairs of the bin.
 hipError_t launch_plan_total(const int32_t *block_hist, int32_t *block_off, int32_t *totals,
@@ -155,6 +158,12 @@ hipError_t launch_shared_direct(Prec prec, int seg, int lanes, const KArgs &a, i
 bool shared_rowpair_has(int seg);
 size_t shared_rowpair_lds_bytes(int seg, int alpha);
 hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st);
+
+// Device-planned per-pair kernel: four 16-lane sub-groups per wavefront,
+// `seg` rows per lane (16*seg query rows at most), profiles per task.
+bool pair_direct_has(int seg);
+size_t pair_direct_lds_bytes(Prec prec, int seg, int alpha);
+hipError_t launch_pair_direct(Prec prec, int seg, const KArgs &a, int grid, hipStream_t st);
 
 // Sets every result to {0, -1, -1, 0}.
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);

@@ -17,6 +17,8 @@ hipError_t launch_pair_i32(int seg, int pmax, bool chunked, const KArgs &a, int 
 hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_direct_i32(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_rowpair_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
+hipError_t launch_pair_direct_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
+hipError_t launch_pair_direct_i32(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
 
 namespace dev {
 // ================================================================ residue streams
@@ -88,15 +90,30 @@ __device__ __forceinline__ void plan_range(int n_pairs, int &lo, int &hi) {
   hi = min(n_pairs, lo + chunk);
 }
 
-// One pair of plan_count_kernel; returns its n if it will run, else 0.
-__device__ __forceinline__ int plan_one(int k, const int64_t *roff, const int32_t *pq,
+// One pair of plan_count_kernel: PairInfo, checks, empty result.  Returns n if
+// the pair will run (m > 0 and n > 0), else 0; *m_out = its query length.
+// qoff == nullptr: one query (id 0, length m, residues at q_off0); else the
+// pair's own query from pq and the query offsets.
+__device__ __forceinline__ int plan_one(int k, const int64_t *qoff, int n_queries, int64_t qbytes,
+                                        const int64_t *roff, const int32_t *pq,
                                         const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
                                         int64_t q_off0, PairInfo *pairs, DevResult *results,
-                                        int32_t *meta) {
+                                        int32_t *meta, int &m_out) {
   const int q = pq ? pq[k] : 0;
   const int r = pr[k];
-  bool ok = q == 0 && r >= 0 && r < n_refs;
-  int64_t ro = 0, re = 0;
+  bool ok = r >= 0 && r < n_refs;
+  int64_t ro = 0, re = 0, qo = q_off0, qm = m;
+  if (qoff == nullptr) {
+    ok = ok && q == 0;
+  } else {
+    ok = ok && q >= 0 && q < n_queries;
+    if (ok) {
+      qo = qoff[q];
+      const int64_t qe = qoff[q + 1];
+      ok = qo >= 0 && qo <= qe && qe <= qbytes && qe - qo <= 0x7fffffffll;
+      qm = qe - qo;
+    }
+  }
   if (ok) {
     ro = roff[r];
     re = roff[r + 1];
@@ -105,11 +122,13 @@ __device__ __forceinline__ int plan_one(int k, const int64_t *roff, const int32_
   if (!ok) {
     atomicOr(&meta[kMetaErrPair], 1);
     ro = re = 0;
+    qo = 0;
+    qm = 0;
   }
   PairInfo p;
-  p.q_off = q_off0;
+  p.q_off = qo;
   p.r_off = ro;
-  p.m = m;
+  p.m = (int)qm;
   p.n = (int)(re - ro);
   p.out = k;
   p.pad = 0;
@@ -117,33 +136,50 @@ __device__ __forceinline__ int plan_one(int k, const int64_t *roff, const int32_
   DevResult v;
   v.score = 0; v.qend = -1; v.rend = -1; v.flags = 0;
   results[k] = v;
-  return m > 0 ? p.n : 0;
+  m_out = p.m;
+  return p.m > 0 ? p.n : 0;
 }
 
 // PairInfo, validation, result initialisation and this workgroup's length
-// histogram (block_hist[blockIdx.x][bin]).
-__global__ __launch_bounds__(1024) void plan_count_kernel(int n_pairs, const int64_t *roff,
-                                                          const int32_t *pq, const int32_t *pr,
-                                                          int n_refs, int64_t ref_bytes, int m,
-                                                          int64_t q_off0, PairInfo *pairs,
-                                                          DevResult *results, int32_t *block_hist,
-                                                          int32_t *meta, unsigned long long *nsum) {
+// histogram (block_hist[blockIdx.x][bin]); stats[4] += sum of n, stats[5] +=
+// sum of m*n, meta[kMetaMaxM] = largest m, over the pairs that will run.
+__global__ __launch_bounds__(1024) void plan_count_kernel(int n_pairs, const int64_t *qoff,
+                                                          int n_queries, int64_t qbytes,
+                                                          const int64_t *roff, const int32_t *pq,
+                                                          const int32_t *pr, int n_refs,
+                                                          int64_t ref_bytes, int m, int64_t q_off0,
+                                                          PairInfo *pairs, DevResult *results,
+                                                          int32_t *block_hist, int32_t *meta,
+                                                          unsigned long long *stats) {
   __shared__ int32_t hist[kPlanBins];
   for (int b = threadIdx.x; b < kPlanBins; b += blockDim.x) hist[b] = 0;
   __syncthreads();
   int lo, hi;
   plan_range(n_pairs, lo, hi);
-  unsigned long long ns = 0;
+  unsigned long long ns = 0, cs = 0;
+  int mmax = 0;
   for (int k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-    const int n = plan_one(k, roff, pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, meta);
+    int mk = 0;
+    const int n = plan_one(k, qoff, n_queries, qbytes, roff, pq, pr, n_refs, ref_bytes, m, q_off0,
+                           pairs, results, meta, mk);
     if (n > 0) {
       atomicAdd(&hist[plan_bin(n)], 1);
       ns += (unsigned long long)n;
+      cs += (unsigned long long)n * (unsigned long long)mk;
+      mmax = max(mmax, mk);
     }
   }
-  // sum of the runnable reference lengths (one atomic per wavefront)
-  for (int d = 1; d < kWave; d <<= 1) ns += __shfl_xor(ns, d);
-  if ((threadIdx.x & 63) == 0 && ns) atomicAdd(nsum, ns);
+  // one atomic per wavefront for each sum and the maximum
+  for (int d = 1; d < kWave; d <<= 1) {
+    ns += __shfl_xor(ns, d);
+    cs += __shfl_xor(cs, d);
+    mmax = max(mmax, __shfl_xor(mmax, d));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    if (ns) atomicAdd(&stats[4], ns);
+    if (cs) atomicAdd(&stats[5], cs);
+    if (mmax) atomicMax(&meta[kMetaMaxM], mmax);
+  }
   __syncthreads();
   int32_t *out = block_hist + (size_t)blockIdx.x * kPlanBins;
   for (int b = threadIdx.x; b < kPlanBins; b += blockDim.x) out[b] = hist[b];
@@ -260,14 +296,31 @@ hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *fl
   return hipGetLastError();
 }
 
-hipError_t launch_plan_count(int n_pairs, const int64_t *roff, const int32_t *pq,
-                             const int32_t *pr, int n_refs, int64_t ref_bytes, int m,
-                             int64_t q_off0, PairInfo *pairs, DevResult *results,
-                             int32_t *block_hist, int32_t *meta, unsigned long long *nsum,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(dev::plan_count_kernel, dim3(kPlanBlocks), dim3(1024), 0, st, n_pairs, roff,
-                     pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results, block_hist, meta, nsum);
+hipError_t launch_plan_count(int n_pairs, const int64_t *qoff, int n_queries, int64_t qbytes,
+                             const int64_t *roff, const int32_t *pq, const int32_t *pr, int n_refs,
+                             int64_t ref_bytes, int m, int64_t q_off0, PairInfo *pairs,
+                             DevResult *results, int32_t *block_hist, int32_t *meta,
+                             unsigned long long *stats, hipStream_t st) {
+  hipLaunchKernelGGL(dev::plan_count_kernel, dim3(kPlanBlocks), dim3(1024), 0, st, n_pairs, qoff,
+                     n_queries, qbytes, roff, pq, pr, n_refs, ref_bytes, m, q_off0, pairs, results,
+                     block_hist, meta, stats);
   return hipGetLastError();
+}
+
+bool pair_direct_has(int seg) {
+  for (int v : kPairSegs)
+    if (v == seg) return true;
+  return false;
+}
+
+size_t pair_direct_lds_bytes(Prec prec, int seg, int alpha) { return pair_lds_bytes(prec, seg, alpha); }
+
+hipError_t launch_pair_direct(Prec prec, int seg, const KArgs &a, int grid, hipStream_t st) {
+  if (!pair_direct_has(seg) || a.order == nullptr || a.plan_meta == nullptr || a.ref_res == nullptr)
+    return hipErrorInvalidValue;
+  const size_t lds = pair_direct_lds_bytes(prec, seg, a.alpha);
+  if (prec == PREC_I16X2) return launch_pair_direct_i16(seg, a, grid, st, lds);
+  return launch_pair_direct_i32(seg, a, grid, st, lds);
 }
 
 hipError_t launch_plan_total(const int32_t *block_hist, int32_t *block_off, int32_t *totals,

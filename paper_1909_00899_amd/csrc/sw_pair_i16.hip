@@ -34,7 +34,26 @@ hipError_t launch_s(int seg, int pmax, const KArgs &a, int grid, hipStream_t st,
   }
   return hipErrorInvalidValue;
 }
+template <int SEG>
+hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  auto k = dev::pair_direct_kernel<O, SEG>;
+  hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3(grid), dim3(kWave), lds, st, a);
+  return hipGetLastError();
+}
 }  // namespace
+
+hipError_t launch_pair_direct_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  switch (seg) {
+    case 4: return launch_d<4>(a, grid, st, lds);
+    case 6: return launch_d<6>(a, grid, st, lds);
+    case 8: return launch_d<8>(a, grid, st, lds);
+    case 10: return launch_d<10>(a, grid, st, lds);
+    case 12: return launch_d<12>(a, grid, st, lds);
+    case 16: return launch_d<16>(a, grid, st, lds);
+  }
+  return hipErrorInvalidValue;
+}
 
 hipError_t launch_pair_i16(int seg, int pmax, bool chunked, const KArgs &a, int grid,
                             hipStream_t st, size_t lds) {

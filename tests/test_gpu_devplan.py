@@ -255,3 +255,117 @@ def test_device_planned_graph_replays_match_eager(pairing):
         again = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, **kw)
         assert (again.results == eager.results).all(), rep
     assert hits >= 3
+
+
+# ---------------------------------------------------------------- one query per pair
+
+def _per_pair(seed, n_pairs, alpha, mlen, nlen, n_queries=None, zero_every=0):
+    """n_pairs pairs, each with a query drawn from n_queries (default: its own)
+    of lengths U[mlen] and its own reference of length U[nlen]."""
+    rng = np.random.default_rng(seed)
+    nq = n_queries or n_pairs
+    qlens = rng.integers(mlen[0], mlen[1] + 1, size=nq)
+    rlens = rng.integers(nlen[0], nlen[1] + 1, size=n_pairs)
+    if zero_every:
+        qlens[::zero_every] = 0
+        rlens[1::zero_every] = 0
+    qoff = np.zeros(nq + 1, dtype=np.int64)
+    np.cumsum(qlens, out=qoff[1:])
+    roff = np.zeros(n_pairs + 1, dtype=np.int64)
+    np.cumsum(rlens, out=roff[1:])
+    qres = rng.integers(0, alpha, size=int(qoff[-1])).astype(np.uint8)
+    rres = rng.integers(0, alpha, size=int(roff[-1])).astype(np.uint8)
+    pq = (np.arange(n_pairs) if n_queries is None else rng.integers(0, nq, size=n_pairs))
+    M = W.dna_matrix() if alpha == 4 else (W.protein_matrix() if alpha == 20 else
+                                           W.random_matrix(rng, alpha))
+    go, ge = (6, 1) if alpha == 4 else (11, 1)
+    return W.Workload("per_pair", qres, qoff, rres, roff, pq.astype(np.int32),
+                      np.arange(n_pairs, dtype=np.int32), M, go, ge)
+
+
+def test_dna_pairs_device_planned():
+    w = W.dna_pairs(n_pairs=60000)
+    want = oracle_batch(w)
+    got = _run(w, planner=2)
+    assert got.stats["planner_used"] == 2 and got.stats["lanes_used"][0] == w.n_pairs
+    assert_same(got.results, want, "dna pairs, device planner")
+    assert got.stats["cells"] == w.cells()
+    auto = _run(w)
+    assert auto.stats["planner_used"] == 2
+    assert (auto.results == got.results).all()
+    host = _run(w, planner=1)
+    assert (host.results == got.results).all()
+    hres = _run(w, device=False, planner=2)
+    assert (hres.results == got.results).all()
+
+
+@pytest.mark.parametrize("alpha,mlen", [(4, (1, 256)), (4, (140, 160)), (20, (1, 64)), (7, (30, 100))])
+@pytest.mark.parametrize("prec", [api.SW_PREC_AUTO, api.SW_PREC_I32])
+def test_per_pair_queries_device_planned(alpha, mlen, prec):
+    w = _per_pair(500 + alpha + mlen[1], 900, alpha, mlen, (0, 700), zero_every=13)
+    want = oracle_batch(w)
+    got = _run(w, planner=2, precision=prec)
+    assert got.stats["planner_used"] == 2
+    assert_same(got.results, want, "per pair alpha=%d m=%s prec=%d" % (alpha, mlen, prec))
+
+
+def test_per_pair_shared_queries_and_forced_seglen():
+    # queries reused by many pairs; every compiled rows-per-lane that holds them
+    w = _per_pair(520, 700, 4, (20, 64), (1, 500), n_queries=37)
+    want = oracle_batch(w)
+    for seg in (4, 6, 8, 10, 12, 16):
+        got = _run(w, planner=2, force_seglen=seg)
+        assert got.stats["seglen_max"] == seg
+        assert_same(got.results, want, "seg=%d" % seg)
+
+
+def test_per_pair_not_device_planned_when_queries_too_long():
+    w = _per_pair(530, 300, 20, (200, 300), (1, 200))
+    with pytest.raises(api.SwError) as e:
+        _run(w, planner=2)
+    assert e.value.code == api.SW_EINVAL
+    got = _run(w)
+    assert got.stats["planner_used"] == 1
+    assert_same(got.results, oracle_batch(w), "host planner fallback")
+
+
+def test_per_pair_reruns_and_errors():
+    w = _per_pair(540, 600, 20, (10, 64), (10, 300))
+    want = oracle_batch(w)
+    got = _run(w, planner=2, int16_cap=30)
+    assert_same(got.results, want, "cap=30")
+    assert got.stats["n_rerun"] == int((want[:, 0] >= 30).sum()) > 0
+    bad = w.pair_query.copy()
+    bad[5] = w.query_off.size - 1          # query id out of range
+    wb = W.Workload("bad_q", w.query_res, w.query_off, w.ref_res, w.ref_off, bad, w.pair_ref,
+                    w.matrix, w.gap_open, w.gap_extend)
+    with pytest.raises(api.SwError) as e:
+        _run(wb, planner=2)
+    assert e.value.code == api.SW_EINVAL
+    qo = w.query_off.copy()
+    qo[3], qo[4] = qo[4], qo[3]            # offsets not nondecreasing
+    wo = W.Workload("bad_off", w.query_res, qo, w.ref_res, w.ref_off, w.pair_query, w.pair_ref,
+                    w.matrix, w.gap_open, w.gap_extend)
+    if qo[3] != qo[4]:
+        with pytest.raises(api.SwError) as e:
+            _run(wo, planner=2)
+        assert e.value.code == api.SW_EINVAL
+    assert_same(_run(w, planner=2).results, want, "after errors")
+
+
+def test_per_pair_graph_replays_match_eager():
+    import torch
+    w = W.dna_pairs(n_pairs=8000, seed=12)
+    want = oracle_batch(w)
+    args, pq = _device(w)
+    eager = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, pair_query=pq, planner=2)
+    assert_same(eager.results, want, "eager")
+    hits = 0
+    for rep in range(4):
+        g = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, pair_query=pq,
+                               planner=2, use_graph=1)
+        assert (g.results == eager.results).all(), rep
+        hits += g.stats["graph_hits"]
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+    assert hits >= 6          # two graphs per call after the first
