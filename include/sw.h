@@ -188,8 +188,13 @@ typedef struct {
                                     half, 16/32/64 lanes per alignment);
                                     SW_PAIRING_ROWS = two row segments of one
                                     alignment (16 lanes, 32 x seglen rows per
-                                    alignment, seglen 4, 8, 12 or 16): one profile
-                                    word per row pair and one more scan step    */
+                                    alignment or query chunk, seglen 4, 8, 12 or
+                                    16): one profile word per row pair and one
+                                    more scan step.  Applies to device-planned
+                                    batches and to the host planner's per-pair
+                                    launches, where AUTO lets the cost model
+                                    choose (row pairs need int16 lanes and an
+                                    alphabet of at most 24 letters)             */
     int32_t reserved[7];
 } sw_options;
 
@@ -213,7 +218,8 @@ typedef struct {
     int32_t graph_hits;          /* use_graph: executions replayed from a cached
                                     graph (no capture)                          */
     int32_t planner_used;        /* 1 = host planner, 2 = device planner        */
-    int32_t reserved[6];
+    int32_t row_pairs;           /* pairs run in the row-pair lane layout       */
+    int32_t reserved[5];
 } sw_stats;
 
 int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options *opt,

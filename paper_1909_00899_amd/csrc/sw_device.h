@@ -788,6 +788,48 @@ __device__ __forceinline__ uint32_t rp_vshift(uint32_t x) {
   return __builtin_amdgcn_alignbit(x, y, 16);
 }
 
+// One virtual lane down inside sub-groups of P lanes; virtual lane 0 of each
+// sub-group receives 0.  P = 16: DPP rows; wider: a wave shift with the
+// sub-group's first lane cleared (`keep` is zero there).
+template <int P>
+__device__ __forceinline__ uint32_t rp_vshift_p(uint32_t x, uint32_t keep) {
+  if constexpr (P == 16) {
+    return rp_vshift(x);
+  } else {
+    uint32_t y = dpp<kWaveShr1>(x);
+    if constexpr (P == 32) y &= keep;
+    return __builtin_amdgcn_alignbit(x, y, 16);
+  }
+}
+
+// Per-lane constants of the row-pair layout with P lanes per alignment.
+struct RpLane {
+  int lane, sg, l;        // wavefront lane, sub-group, lane inside the sub-group
+  uint32_t keep;          // 0 in the first lane of a sub-group, else all ones
+  uint32_t w16, w32;      // weights of the row_bcast:15 / :31 scan steps (inf: no input)
+  uint32_t rx16, rx32;    // all ones where the broadcast value belongs to the sub-group
+};
+
+template <int P, int SEG>
+__device__ __forceinline__ RpLane make_rp_lane(uint32_t ge) {
+  using O = OpsI16;
+  RpLane L;
+  L.lane = (int)(threadIdx.x & 63);
+  L.sg = L.lane / P;
+  L.l = L.lane % P;
+  L.keep = L.l == 0 ? 0u : 0xffffffffu;
+  const int row = L.lane >> 4;
+  const uint64_t unit = 2ull * SEG * ge;   // one lane = two virtual lanes
+  const uint32_t inf = O::splat(O::kWeightCap);
+  const bool r15 = P >= 32 && (row & 1);
+  const bool r31 = P >= 64 && row >= 2;
+  L.w16 = r15 ? weight<O>((uint64_t)(L.lane & 15) + 1, unit) : inf;
+  L.w32 = r31 ? weight<O>((uint64_t)(L.lane & 31) + 1, unit) : inf;
+  L.rx16 = r15 ? 0xffffffffu : 0u;
+  L.rx32 = r31 ? 0xffffffffu : 0u;
+  return L;
+}
+
 // Largest value of both halves, in both halves.
 __device__ __forceinline__ uint32_t rp_both(uint32_t x) {
   return OpsI16::vmax(x, __builtin_amdgcn_alignbit(x, x, 16));
@@ -849,20 +891,52 @@ __device__ void build_rowpair_profile(const KArgs &a, uint32_t off) {
   }
 }
 
-// One column of the row-pair layout (the same column step as column(),
-// with virtual-lane moves).  base: LDS byte address of this lane's word of
-// row 0 for the column's residue.
+// Profile words of one column in the row-pair layout: word j holds the scores
+// of rows (2l)*SEG + j (low half) and (2l+1)*SEG + j (high half) against the
+// column's reference residue.
+// RpShared: the query profile of a shared query, base = this lane's word of row
+// 0 for the residue (rows 64 bytes apart).
+struct RpShared {
+  uint32_t base;
+  __device__ __forceinline__ uint32_t operator()(int j) const {
+    return *(const uint32_t *)(smem + base + j * 64);
+  }
+};
+// RpPairs: the pair-score table (word (qa*(alpha+1) + qb)*(alpha+1) + r holds
+// S(qa, r) and S(qb, r)); qq[j] = byte address of this lane's row pair j,
+// c4 = 4 * the column's residue.
 template <int SEG>
-__device__ __forceinline__ void rp_column(State<SEG> &st, const RpParams &pr, uint32_t base,
-                                          int i) {
+struct RpPairs {
+  const uint32_t (&qq)[SEG];
+  uint32_t c4;
+  __device__ __forceinline__ uint32_t operator()(int j) const {
+    return *(const uint32_t *)(smem + qq[j] + c4);
+  }
+};
+
+// One column of the row-pair layout (the same column step as column(), with
+// virtual-lane moves).  CHUNKED: cin_h / cin_f are the previous query chunk's
+// corrected last-row H and vertical-gap carry at this column, already placed
+// in the low half of the sub-group's first lane (zero elsewhere); hb_out /
+// fb_out receive this chunk's (in the low 16 bits, meaningful in the last lane).
+template <int SEG, bool CHUNKED, class Prof, int P = 16>
+__device__ __forceinline__ void rp_column(State<SEG> &st, const RpParams &pr, const Prof &pf,
+                                          int i, uint32_t cin_h, uint32_t cin_f,
+                                          uint32_t &hb_out, uint32_t &fb_out,
+                                          const RpLane *lp = nullptr) {
   using O = OpsI16;
+  const uint32_t keep = P == 32 ? lp->keep : 0u;
   uint32_t Fj = st.Fscan;
   const uint32_t hlast = O::vmax(st.H[SEG - 1], O::usub(Fj, pr.wlast));
-  uint32_t Hin = rp_vshift(hlast);
+  uint32_t Hin = rp_vshift_p<P>(hlast, keep);
+  if constexpr (CHUNKED) {
+    Hin |= cin_h;
+    hb_out = hlast >> 16;
+  }
   uint32_t F = 0, cmax;
 #pragma unroll
   for (int j = 0; j < SEG; ++j) {
-    const uint32_t p = *(const uint32_t *)(smem + base + j * 64);
+    const uint32_t p = pf(j);
     const uint32_t hd = O::hadd(Hin, p);
     cmax = j == 0 ? hd : O::vmax(cmax, hd);
     const uint32_t h = O::vmax(O::vmax(hd, st.E[j]), F);
@@ -876,14 +950,22 @@ __device__ __forceinline__ void rp_column(State<SEG> &st, const RpParams &pr, ui
       Fj = O::usub(Fj, pr.ge);
     }
   }
-  // inclusive max-plus scan over the 32 virtual lanes, then one virtual lane down
+  // inclusive max-plus scan over the 32 virtual lanes (a carry from the
+  // previous chunk enters as virtual lane -1), then one virtual lane down
   uint32_t G = F;
-  G = O::vmax(G, O::usub(rp_vshift(G), pr.wv));
+  if constexpr (CHUNKED) G = O::vmax(G, O::usub(cin_f, pr.wv));
+  G = O::vmax(G, O::usub(rp_vshift_p<P>(G, keep), pr.wv));
   G = O::vmax(G, O::usub(dpp<kRowShr1>(G), pr.w1));
   G = O::vmax(G, O::usub(dpp<kRowShr2>(G), pr.w2));
   G = O::vmax(G, O::usub(dpp<kRowShr4>(G), pr.w4));
   G = O::vmax(G, O::usub(dpp<kRowShr8>(G), pr.w8));
-  st.Fscan = rp_vshift(G);
+  if constexpr (P >= 32) G = O::vmax(G, O::usub(dpp<kRowBcast15, 0xa, false>(G), lp->w16));
+  if constexpr (P >= 64) G = O::vmax(G, O::usub(dpp<kRowBcast31, 0xc, false>(G), lp->w32));
+  st.Fscan = rp_vshift_p<P>(G, keep);
+  if constexpr (CHUNKED) {
+    st.Fscan |= cin_f;
+    fb_out = G >> 16;
+  }
   record<O, SEG>(st, cmax, i);
 }
 
@@ -904,6 +986,30 @@ __device__ __forceinline__ void rp_share_threshold(State<SEG> &st, int lane) {
   st.G = row == 0 ? t15 : (row == 1 ? t31 : (row == 2 ? t47 : t63));
 }
 
+// Record thresholds raised to the largest of the P-lane sub-group (both halves).
+template <int SEG, int P>
+__device__ __forceinline__ void rp_share_threshold_p(State<SEG> &st, const RpLane &L) {
+  if constexpr (P == 16) {
+    rp_share_threshold<SEG>(st, L.lane);
+  } else {
+    using O = OpsI16;
+    uint32_t T = rp_both(st.G);
+    T = O::vmax(T, dpp<kRowShr1>(T));
+    T = O::vmax(T, dpp<kRowShr2>(T));
+    T = O::vmax(T, dpp<kRowShr4>(T));
+    T = O::vmax(T, dpp<kRowShr8>(T));
+    T = O::vmax(T, dpp<kRowBcast15, 0xa, false>(T) & L.rx16);
+    if constexpr (P >= 64) T = O::vmax(T, dpp<kRowBcast31, 0xc, false>(T) & L.rx32);
+    const uint32_t t63 = (uint32_t)__builtin_amdgcn_readlane((int)T, 63);
+    if constexpr (P == 64) {
+      st.G = t63;
+    } else {
+      const uint32_t t31 = (uint32_t)__builtin_amdgcn_readlane((int)T, 31);
+      st.G = L.sg == 0 ? t31 : t63;
+    }
+  }
+}
+
 template <int SEG, class Src>
 __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const RpParams &pr,
                                                uint32_t lane_base, const Src &src, int ncols) {
@@ -918,7 +1024,9 @@ __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const R
 #pragma unroll
     for (int k = 0; k < kBlock; ++k) {
       const uint32_t c = __builtin_amdgcn_ubfe(r, 8 * k, 8);
-      rp_column<SEG>(st, pr, lane_base + c * rp_cstride(SEG), b * kBlock + k);
+      uint32_t ho, fo;
+      rp_column<SEG, false>(st, pr, RpShared{lane_base + c * rp_cstride(SEG)}, b * kBlock + k,
+                            0u, 0u, ho, fo);
     }
     if (st.events != ev_shared) {
       rp_share_threshold<SEG>(st, lane);
@@ -1171,6 +1279,201 @@ void pair_direct_kernel(KArgs a) {
     if (cols) atomicAdd(&a.stats[0], cols);
     if (events) atomicAdd(&a.stats[2], events);
     if (padded) atomicAdd(&a.stats[3], padded);
+  }
+}
+
+// ================================================================ per-pair row pairs
+
+// Pair-score table: word (qa*A1 + qb)*A1 + r (A1 = alpha+1) holds S(qa, r) in
+// the low half and S(qb, r) in the high half, -32768 where a code is the
+// padding / sentinel code alpha.  Shared by every wavefront of a workgroup; it
+// replaces the per-pair query profile, so a lane's rows can be as many as its
+// registers hold whatever the alphabet.
+__host__ __device__ constexpr uint32_t rp_table_bytes(int alpha) {
+  return (uint32_t)((alpha + 1) * (alpha + 1) * (alpha + 1) * 4);
+}
+
+__device__ void build_pair_table(const KArgs &a, uint32_t off) {
+  const int32_t *M = (const int32_t *)smem;
+  const int A1 = a.alpha + 1;
+  const int total = A1 * A1 * A1;
+  for (int k = threadIdx.x; k < total; k += blockDim.x) {
+    const int r = k % A1;
+    const int qb = (k / A1) % A1;
+    const int qa = k / (A1 * A1);
+    const int va = (qa < a.alpha && r < a.alpha) ? M[qa * a.alpha + r] : -32768;
+    const int vb = (qb < a.alpha && r < a.alpha) ? M[qb * a.alpha + r] : -32768;
+    *(uint32_t *)(smem + off + 4u * k) = ((uint32_t)va & 0xffffu) | ((uint32_t)vb << 16);
+  }
+}
+
+// Best cell of one alignment so far (identical in every lane of its sub-group).
+struct RpBest {
+  int s, c, r;
+  uint32_t f;
+};
+
+// Merges this chunk's records (rows row0 + (2l+h)*SEG + j) into `best`.
+template <int SEG, int P>
+__device__ __forceinline__ void rp_merge(const State<SEG> &st, int l, int row0, RpBest &best,
+                                         int sat_cap) {
+  using O = OpsI16;
+  int s = 0, c = 0x7fffffff, r = 0x7fffffff;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int sh = st.rc[h] != 0x7fffffff ? O::get(st.S, h) : 0;
+    if (sh > 0) {
+      int jj = SEG - 1;
+#pragma unroll
+      for (int j = SEG - 1; j >= 0; --j)
+        if (O::get(st.snap[j], h) >= sh) jj = j;
+      const int ch = st.rc[h], rh = row0 + (2 * l + h) * SEG + jj;
+      if (s <= 0 || better(sh, ch, rh, s, c, r)) { s = sh; c = ch; r = rh; }
+    }
+  }
+  for (int d = 1; d < P; d <<= 1) {
+    const int s2 = __shfl_xor(s, d), c2 = __shfl_xor(c, d), r2 = __shfl_xor(r, d);
+    if (s2 > 0 && (s <= 0 || better(s2, c2, r2, s, c, r))) { s = s2; c = c2; r = r2; }
+  }
+  if (s >= sat_cap) best.f |= kFlagNeedsI32;
+  if (s > 0 && (best.s <= 0 || better(s, c, r, best.s, best.c, best.r))) {
+    best.s = s; best.c = c; best.r = r;
+  }
+}
+
+// Column loop of one query chunk for the per-pair row-pair kernel: residues
+// from the task's stream (the sub-group's low-half word), chunk boundaries as
+// in run_columns (written by the sub-group's last lane, low 16 bits).
+template <int SEG, bool CHUNKED, int P>
+__device__ __forceinline__ void rp_pair_columns(State<SEG> &st, const RpLane &L,
+                                                const RpParams &pr, const uint32_t (&qq)[SEG],
+                                                const StreamSrc &src, int ncols,
+                                                const uint32_t *hb_in, const uint32_t *fb_in,
+                                                uint32_t *hb_out, uint32_t *fb_out) {
+  const int nblk = ncols / kBlock;
+  const bool first = L.l == 0, last = L.l == P - 1;
+  uint32_t ev_shared = st.events;
+  uint32_t rc = src.get(0).x;
+  uint32_t rn = src.get(1).x;
+  uint4 hbc, hbn, fbc, fbn;
+  if constexpr (CHUNKED) {
+    hbc = ((const uint4 *)hb_in)[0];
+    hbn = ((const uint4 *)hb_in)[1];
+    fbc = ((const uint4 *)fb_in)[0];
+    fbn = ((const uint4 *)fb_in)[1];
+  }
+  for (int b = 0; b < nblk; ++b) {
+    const uint32_t r = rc;
+    rc = rn;
+    rn = src.get(b + 2).x;
+    uint4 hbv = make_uint4(0, 0, 0, 0), fbv = make_uint4(0, 0, 0, 0);
+    if constexpr (CHUNKED) {
+      hbv = hbc; hbc = hbn; hbn = ((const uint4 *)hb_in)[b + 2];
+      fbv = fbc; fbc = fbn; fbn = ((const uint4 *)fb_in)[b + 2];
+    }
+    const uint32_t hin[kBlock] = {hbv.x, hbv.y, hbv.z, hbv.w};
+    const uint32_t fin[kBlock] = {fbv.x, fbv.y, fbv.z, fbv.w};
+    uint32_t ho[kBlock], fo[kBlock];
+#pragma unroll
+    for (int k = 0; k < kBlock; ++k) {
+      const uint32_t c4 = __builtin_amdgcn_ubfe(r, 8 * k, 8) * 4u;
+      const uint32_t ch = first ? (hin[k] & 0xffffu) : 0u;
+      const uint32_t cf = first ? (fin[k] & 0xffffu) : 0u;
+      rp_column<SEG, CHUNKED, RpPairs<SEG>, P>(st, pr, RpPairs<SEG>{qq, c4}, b * kBlock + k, ch,
+                                               cf, ho[k], fo[k], &L);
+    }
+    if (CHUNKED && hb_out != nullptr && last) {
+      ((uint4 *)hb_out)[b] = make_uint4(ho[0], ho[1], ho[2], ho[3]);
+      ((uint4 *)fb_out)[b] = make_uint4(fo[0], fo[1], fo[2], fo[3]);
+    }
+    if (st.events != ev_shared) {
+      rp_share_threshold_p<SEG, P>(st, L);
+      ev_shared = st.events;
+    }
+  }
+}
+
+// Per-pair kernel in the row-pair layout (int16): one alignment per P-lane
+// sub-group (task slot 2*sub_group), 2*P*SEG query rows per chunk, the pair-
+// score table in LDS instead of per-pair profiles.  Tasks, residue streams and
+// chunk boundaries are those of the host planner's per-pair launches.
+// Wavefronts per SIMD: 16 rows per lane, or 12 with chunk boundaries, need
+// more than 128 VGPRs.
+__host__ __device__ constexpr int rp_pair_waves_per_eu(int seg, bool chunked) {
+  return (seg >= 16 || (seg >= 12 && chunked)) ? 3 : 4;
+}
+
+template <int SEG, bool CHUNKED, int P>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(rp_pair_waves_per_eu(SEG, CHUNKED))))
+void pair_rowpair_kernel(KArgs a) {
+  stage_matrix(a);
+  __syncthreads();
+  const uint32_t off = matrix_lds_bytes(a.alpha);
+  build_pair_table(a, off);
+  __syncthreads();
+  const RpLane L = make_rp_lane<P, SEG>((uint32_t)a.gap_extend);
+  const int lane = L.lane, sg = L.sg, l = L.l;
+  const int A1 = a.alpha + 1;
+  const RpParams pr = make_rp_params<SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
+  unsigned long long cols = 0, events = 0;
+  for (;;) {
+    const int ti = pop_task(a.task_counter);
+    if (ti >= a.ntasks) break;
+    const Task t = a.tasks[ti];
+    const int pid = t.pair[2 * sg];
+    int m = 0;
+    int64_t qo = 0;
+    if (pid >= 0) {
+      const PairInfo p = a.pairs[pid];
+      m = p.m;
+      qo = p.q_off;
+    }
+    const int nch = CHUNKED ? t.nchunks : 1;
+    RpBest best{0, 0x7fffffff, 0x7fffffff, 0u};
+    for (int ch = 0; ch < nch; ++ch) {
+      const int row0 = ch * 2 * P * SEG;
+      // this lane's row pairs: table rows of (query code of row (2l)*SEG + j,
+      // query code of row (2l+1)*SEG + j), alpha past the query's end
+      uint32_t qq[SEG];
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) {
+        const int ra = row0 + 2 * l * SEG + j, rb = ra + SEG;
+        const int qa = ra < m ? min((int)a.query_res[qo + ra], a.alpha) : a.alpha;
+        const int qb = rb < m ? min((int)a.query_res[qo + rb], a.alpha) : a.alpha;
+        qq[j] = off + (uint32_t)((qa * A1 + qb) * A1) * 4u;
+      }
+      State<SEG> st;
+      const uint32_t g0 = best.s > 0 ? (uint32_t)(best.s - 1) : 0u;
+      state_reset(st, OpsI16::splat(g0));
+      const uint32_t *hb_in = nullptr, *fb_in = nullptr;
+      uint32_t *hb_out = nullptr, *fb_out = nullptr;
+      if constexpr (CHUNKED) {
+        const int64_t base = t.bnd_off + (int64_t)sg * t.ncols;
+        const int64_t fofs = 4ll * t.ncols;
+        uint32_t *rd = a.bnd + (ch & 1) * a.bnd_half;
+        uint32_t *wr = a.bnd + ((ch + 1) & 1) * a.bnd_half;
+        hb_in = rd + base;
+        fb_in = rd + base + fofs;
+        if (ch + 1 < nch) { hb_out = wr + base; fb_out = wr + base + fofs; }
+      }
+      const StreamSrc src{(const uint2 *)(a.streams + t.stream_off) + sg};
+      rp_pair_columns<SEG, CHUNKED, P>(st, L, pr, qq, src, t.ncols, hb_in, fb_in, hb_out, fb_out);
+      cols += (unsigned long long)t.ncols;
+      events += st.events;
+      rp_merge<SEG, P>(st, l, row0, best, a.sat_cap);
+    }
+    if (l == 0 && pid >= 0) {
+      DevResult res;
+      res.score = best.s > 0 ? best.s : 0;
+      res.qend = best.s > 0 ? best.r : -1;
+      res.rend = best.s > 0 ? best.c : -1;
+      res.flags = best.f;
+      a.results[a.pairs[pid].out] = res;
+    }
+  }
+  if (lane == 0 && a.stats != nullptr) {
+    if (cols) atomicAdd(&a.stats[0], cols);
+    if (events) atomicAdd(&a.stats[2], events);
   }
 }
 

@@ -450,6 +450,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     ExecOptions o2 = eo;
     o2.force_lanes = 0;
     o2.force_seglen = 0;
+    o2.lane_pairing = SW_PAIRING_AUTO;   // the int32 rerun has no int16 halves
     o2.force_kernel = 0;
     o2.use_graph = 0;
     ExecStats es2;
@@ -484,6 +485,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     stats->finish_ms = now_ms() - t_fin0;
     stats->graph_hits = es.graph_hits;
     stats->planner_used = 2;
+    stats->row_pairs = rows ? hm[kMetaValid] : 0;
   }
   return SW_OK;
 }

@@ -165,6 +165,16 @@ bool pair_direct_has(int seg);
 size_t pair_direct_lds_bytes(Prec prec, int seg, int alpha);
 hipError_t launch_pair_direct(Prec prec, int seg, const KArgs &a, int grid, hipStream_t st);
 
+// Host-planned per-pair kernel in the row-pair layout (int16 only): one
+// alignment per sub-group of `lanes` (16, 32, 64) lanes (task slot
+// 2*sub_group), `seg` rows per virtual lane (2*lanes*seg query rows per
+// chunk), a pair-score table of (alpha+1)^3 words in LDS instead of per-pair
+// profiles (alphabets up to 24).  grid = wavefronts.
+bool pair_rowpair_has(int seg, int alpha);
+size_t pair_rowpair_lds_bytes(int alpha);
+hipError_t launch_pair_rowpair(int seg, int lanes, bool chunked, const KArgs &a, int grid,
+                               hipStream_t st);
+
 // Sets every result to {0, -1, -1, 0}.
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);
 

@@ -19,6 +19,8 @@ hipError_t launch_direct_i32(int shape, const KArgs &a, int grid, hipStream_t st
 hipError_t launch_rowpair_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_pair_direct_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_pair_direct_i32(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
+hipError_t launch_pair_rowpair_i16(int seg, int lanes, bool chunked, const KArgs &a, int grid,
+                                   hipStream_t st, size_t lds);
 
 namespace dev {
 // ================================================================ residue streams
@@ -373,6 +375,21 @@ hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t 
       a.ref_res == nullptr)
     return hipErrorInvalidValue;
   return launch_rowpair_i16(seg, a, grid, st, shared_rowpair_lds_bytes(seg, a.alpha));
+}
+
+bool pair_rowpair_has(int seg, int alpha) {
+  return (seg == 4 || seg == 8 || seg == 12 || seg == 16) && pair_rowpair_lds_bytes(alpha) <= 65536;
+}
+
+size_t pair_rowpair_lds_bytes(int alpha) {
+  return matrix_lds_bytes(alpha) + dev::rp_table_bytes(alpha);
+}
+
+hipError_t launch_pair_rowpair(int seg, int lanes, bool chunked, const KArgs &a, int grid,
+                               hipStream_t st) {
+  if (!pair_rowpair_has(seg, a.alpha) || (lanes != 16 && lanes != 32 && lanes != 64))
+    return hipErrorInvalidValue;
+  return launch_pair_rowpair_i16(seg, lanes, chunked, a, grid, st, pair_rowpair_lds_bytes(a.alpha));
 }
 
 int shared_menu_count() { return kNumSharedMenus; }

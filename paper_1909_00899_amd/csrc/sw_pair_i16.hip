@@ -41,7 +41,42 @@ hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
   hipLaunchKernelGGL(k, dim3(grid), dim3(kWave), lds, st, a);
   return hipGetLastError();
 }
+// grid: wavefronts wanted; workgroups of 8 wavefronts (4 where the kernel
+// runs three wavefronts per SIMD, so that three workgroups share a CU)
+template <int SEG, bool CH, int P>
+hipError_t launch_rp(const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  auto k = dev::pair_rowpair_kernel<SEG, CH, P>;
+  constexpr int wpg = dev::rp_pair_waves_per_eu(SEG, CH) == 3 ? 4 : kWavesPerGroup;
+  hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, dim3((grid + wpg - 1) / wpg), dim3(wpg * kWave), lds, st, a);
+  return hipGetLastError();
+}
+template <bool CH, int P>
+hipError_t launch_rps(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  switch (seg) {
+    case 4: return launch_rp<4, CH, P>(a, grid, st, lds);
+    case 8: return launch_rp<8, CH, P>(a, grid, st, lds);
+    case 12: return launch_rp<12, CH, P>(a, grid, st, lds);
+    case 16: return launch_rp<16, CH, P>(a, grid, st, lds);
+  }
+  return hipErrorInvalidValue;
+}
+template <bool CH>
+hipError_t launch_rpp(int seg, int lanes, const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  switch (lanes) {
+    case 16: return launch_rps<CH, 16>(seg, a, grid, st, lds);
+    case 32: return launch_rps<CH, 32>(seg, a, grid, st, lds);
+    case 64: return launch_rps<CH, 64>(seg, a, grid, st, lds);
+  }
+  return hipErrorInvalidValue;
+}
 }  // namespace
+
+hipError_t launch_pair_rowpair_i16(int seg, int lanes, bool chunked, const KArgs &a, int grid,
+                                   hipStream_t st, size_t lds) {
+  return chunked ? launch_rpp<true>(seg, lanes, a, grid, st, lds)
+                 : launch_rpp<false>(seg, lanes, a, grid, st, lds);
+}
 
 hipError_t launch_pair_direct_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds) {
   switch (seg) {

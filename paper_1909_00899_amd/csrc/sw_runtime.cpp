@@ -272,6 +272,7 @@ void sort_by_n_desc(const PlanItem *items, size_t cnt, std::vector<int> &order,
 
 struct LaunchDesc {
   bool shared;
+  bool rp;           // per-pair: row pairs (pair_rowpair_kernel)
   int task_begin, task_end;
   int menu;          // shared
   int seg, pmax;     // per-pair
@@ -394,6 +395,7 @@ namespace {
 
 struct PairShape {
   int P, seg, nchunks;
+  bool rp = false;   // row pairs: one alignment per 16-lane sub-group, 32*seg rows per chunk
 };
 
 constexpr int kPairSegs[] = {4, 6, 8, 10, 12, 16};
@@ -415,19 +417,84 @@ double pair_cost(Prec prec, int P, int pmax, int seg, int nch) {
   return nch * step_cost(prec, pmax, seg) * P / (64.0 * (prec == PREC_I16X2 ? 2 : 1));
 }
 
-// One width per launch: the (lanes, rows per lane) of least modelled cost.
+// Row pairs: VALU instructions of one wavefront's column step (the recurrence
+// and the pair-score table address per row pair, 1 + log2(P) scan steps, two
+// virtual-lane moves, records; chunk carries), and per alignment (64/P per
+// wavefront).
+const int kRpSegs[] = {4, 8, 12, 16};
+double rp_step_cost(int P, int seg, int nch) {
+  const int lg = P == 16 ? 4 : (P == 32 ? 5 : 6);
+  return seg * 13.0 + 3.0 * (lg + 1) + 18.0 + (P > 16 ? 2.0 : 0.0) + (nch > 1 ? 8.0 : 0.0);
+}
+double rp_cost(int P, int seg, int nch) { return nch * rp_step_cost(P, seg, nch) * P / 64.0; }
+
+// Which lane pairings the options and the batch allow for per-pair launches.
+bool rp_allowed(Prec prec, int alpha, const ExecOptions &opt) {
+  if (prec != PREC_I16X2 || opt.lane_pairing == SW_PAIRING_ALIGNMENTS) return false;
+  if (!pair_rowpair_has(4, alpha)) return false;
+  if (opt.lane_pairing == SW_PAIRING_ROWS) return true;
+  return !opt.force_lanes && !opt.force_seglen;   // forced shapes keep alignment pairs
+}
+// Row pairs only: when asked for, or (planner's choice) when the alphabet is
+// so large that per-pair profiles would hold just 4 rows per lane: there the
+// alignment-pair kernel runs short lanes over many query chunks, and measured
+// 1.7x slower on uniform 400 x 400 protein pairs and 1.4x on the serving mix.
+bool rows_only(Prec prec, int alpha, const ExecOptions &opt) {
+  if (opt.lane_pairing == SW_PAIRING_ROWS) return true;
+  if (opt.mixed_layout == 1) return false;   // mixed widths are an alignment-pair layout
+  ExecOptions none;
+  return rp_allowed(prec, alpha, opt) && !pair_seg_allowed(prec, 6, alpha, none);
+}
+bool rp_seg_allowed(int seg, int alpha, const ExecOptions &opt) {
+  return pair_rowpair_has(seg, alpha) && (!opt.force_seglen || seg == opt.force_seglen);
+}
+
+// Modelled cost per reference column of one alignment, and the length of one
+// wavefront's chain of column steps per reference column, for a shape.
+double shape_cost(Prec prec, const PairShape &ps, int) {
+  return ps.rp ? rp_cost(ps.P, ps.seg, ps.nchunks) : pair_cost(prec, ps.P, ps.P, ps.seg, ps.nchunks);
+}
+double shape_chain(Prec prec, const PairShape &ps) {
+  return ps.nchunks * (ps.rp ? rp_step_cost(ps.P, ps.seg, ps.nchunks) : step_cost(prec, ps.P, ps.seg));
+}
+
+// Every per-pair shape the options allow for a query of m rows.
+template <class F>
+void for_each_pair_shape(Prec prec, int m, int alpha, const ExecOptions &opt, F &&f) {
+  if (!rows_only(prec, alpha, opt)) {
+    for (int P : {16, 32, 64}) {
+      if (opt.force_lanes && P != opt.force_lanes) continue;
+      for (int seg : kPairSegs) {
+        if (!pair_seg_allowed(prec, seg, alpha, opt)) continue;
+        f(PairShape{P, seg, (m + P * seg - 1) / (P * seg)});
+      }
+    }
+  }
+  if (rp_allowed(prec, alpha, opt)) {
+    // unforced: a short menu (16 lanes at 8 or 16 rows, 64 lanes at 16 rows),
+    // so that a batch of mixed lengths needs few launches
+    const bool forced = opt.force_lanes || opt.force_seglen;
+    for (int P : {16, 32, 64}) {
+      if (opt.force_lanes && P != opt.force_lanes) continue;
+      if (!forced && P == 32) continue;
+      for (int seg : kRpSegs) {
+        if (!forced && (P == 16 ? (seg != 8 && seg != 16) : seg != 16)) continue;
+        if (rp_seg_allowed(seg, alpha, opt))
+          f(PairShape{P, seg, (m + 2 * P * seg - 1) / (2 * P * seg), true});
+      }
+    }
+  }
+}
+
+// One width per launch: the (lanes, rows per lane) of least modelled cost,
+// over alignment pairs and row pairs as the options allow.
 PairShape choose_pair_shape(Prec prec, int m, int alpha, const ExecOptions &opt) {
   PairShape best{64, 4, 1 << 30};
   double best_cost = 1e300;
-  for (int P : {16, 32, 64}) {
-    if (opt.force_lanes && P != opt.force_lanes) continue;
-    for (int seg : kPairSegs) {
-      if (!pair_seg_allowed(prec, seg, alpha, opt)) continue;
-      const int nch = (m + P * seg - 1) / (P * seg);
-      const double cost = pair_cost(prec, P, P, seg, nch);
-      if (cost < best_cost - 1e-9) { best_cost = cost; best = PairShape{P, seg, nch}; }
-    }
-  }
+  for_each_pair_shape(prec, m, alpha, opt, [&](const PairShape &ps) {
+    const double cost = shape_cost(prec, ps, alpha);
+    if (cost < best_cost - 1e-9) { best_cost = cost; best = ps; }
+  });
   return best;
 }
 
@@ -603,9 +670,20 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
                int num_cus, HostScratch &hs, std::vector<Task> &tasks,
                std::vector<LaunchDesc> &launches, int64_t &bnd_elems, ExecStats &stats) {
   if (cnt == 0) return SW_OK;
+  if (opt.lane_pairing == SW_PAIRING_ROWS &&
+      (!rp_allowed(prec, alpha, opt) ||
+       (opt.force_seglen && !rp_seg_allowed(opt.force_seglen, alpha, opt)))) {
+    set_error("row pairs need int16 lanes, an alphabet of at most 24 letters and 4, 8, 12 "
+              "or 16 rows per lane");
+    return SW_EINVAL;
+  }
   if (opt.force_seglen &&
       std::find(std::begin(kPairSegs), std::end(kPairSegs), opt.force_seglen) == std::end(kPairSegs)) {
     set_error("no compiled per-pair kernel with %d rows per lane", opt.force_seglen);
+    return SW_EINVAL;
+  }
+  if (opt.lane_pairing == SW_PAIRING_ROWS && opt.mixed_layout == 1) {
+    set_error("mixed layouts hold alignment pairs, not row pairs");
     return SW_EINVAL;
   }
   // mixed_layout: 0 = planner's choice, 1 = mixed, 2 = one width per launch
@@ -616,7 +694,8 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
   for (size_t k = 0; k < cnt; ++k) { max_m = std::max(max_m, items[k].m); min_m = std::min(min_m, items[k].m); }
   const bool tunable = opt.use_tuning && !opt.force_lanes && !opt.force_seglen && opt.mixed_layout != 1;
   sw_tune_entry te;
-  if (tunable && opt.mixed_layout == 0 && tune_mixed(prec, alpha, min_m, max_m, te)) {
+  if (tunable && opt.mixed_layout == 0 && !rows_only(prec, alpha, opt) &&
+      tune_mixed(prec, alpha, min_m, max_m, te)) {
     mixed = true;
     mixed_seg = te.seglen;
   }
@@ -645,45 +724,39 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
     double total = 0, lmin = 0;
     for (int s = 0; s < nd; ++s) {
       shape[s] = choose_pair_shape(prec, li.ms[s], alpha, opt);
-      total += hs.nsum[s] * pair_cost(prec, shape[s].P, shape[s].P, shape[s].seg, shape[s].nchunks);
+      total += hs.nsum[s] * shape_cost(prec, shape[s], alpha);
       double best_lat = 1e300;
-      for (int P : {16, 32, 64}) {
-        if (opt.force_lanes && P != opt.force_lanes) continue;
-        for (int seg : kPairSegs) {
-          if (!pair_seg_allowed(prec, seg, alpha, opt)) continue;
-          const int nch = (li.ms[s] + P * seg - 1) / (P * seg);
-          best_lat = std::min(best_lat, (double)hs.nmax[s] * nch * step_cost(prec, P, seg));
-        }
-      }
+      for_each_pair_shape(prec, li.ms[s], alpha, opt, [&](const PairShape &ps) {
+        best_lat = std::min(best_lat, (double)hs.nmax[s] * shape_chain(prec, ps));
+      });
       lmin = std::max(lmin, best_lat);
     }
     const double bound = std::max(total / slots, lmin);
     nonmixed_total = total;
     for (int s = 0; s < nd; ++s) {
       const int m = li.ms[s];
-      if (tunable && tune_lookup(SW_TUNE_PAIR, prec, alpha, m, te)) {
-        shape[s] = PairShape{te.lanes, te.seglen, (m + te.lanes * te.seglen - 1) / (te.lanes * te.seglen)};
-        continue;
-      }
-      const PairShape &c0 = shape[s];
-      if ((double)hs.nmax[s] * c0.nchunks * step_cost(prec, c0.P, c0.seg) <= bound) continue;
-      double best = 1e300;
-      for (int P : {16, 32, 64}) {
-        if (opt.force_lanes && P != opt.force_lanes) continue;
-        for (int seg : kPairSegs) {
-          if (!pair_seg_allowed(prec, seg, alpha, opt)) continue;
-          const int nch = (m + P * seg - 1) / (P * seg);
-          if ((double)hs.nmax[s] * nch * step_cost(prec, P, seg) > bound) continue;
-          const double c = pair_cost(prec, P, P, seg, nch);
-          if (c < best - 1e-9) { best = c; shape[s] = PairShape{P, seg, nch}; }
+      if (tunable && !rows_only(prec, alpha, opt) && tune_lookup(SW_TUNE_PAIR, prec, alpha, m, te)) {
+        // the tuned alignment-pair shape, unless row pairs model far less work
+        const PairShape tuned{te.lanes, te.seglen, (m + te.lanes * te.seglen - 1) / (te.lanes * te.seglen)};
+        if (!(shape[s].rp && shape_cost(prec, shape[s], alpha) < 0.7 * shape_cost(prec, tuned, alpha))) {
+          shape[s] = tuned;
+          continue;
         }
       }
+      if ((double)hs.nmax[s] * shape_chain(prec, shape[s]) <= bound) continue;
+      double best = 1e300;
+      for_each_pair_shape(prec, m, alpha, opt, [&](const PairShape &ps) {
+        if ((double)hs.nmax[s] * shape_chain(prec, ps) > bound) return;
+        const double c = shape_cost(prec, ps, alpha);
+        if (c < best - 1e-9) { best = c; shape[s] = ps; }
+      });
     }
   }
   // Planner's choice: mixed layouts (one launch for every width, fewer launch
   // tails) unless they model over 15% more work than one width per launch.
-  bool try_mixed = mixed;
-  if (!mixed && opt.mixed_layout == 0 && !opt.force_lanes && !opt.force_seglen && nd > 0) {
+  const bool ap = !rows_only(prec, alpha, opt);
+  bool try_mixed = mixed && ap;
+  if (!mixed && opt.mixed_layout == 0 && !opt.force_lanes && !opt.force_seglen && nd > 0 && ap) {
     bool tuned_any = false;
     for (int s = 0; s < nd && tunable; ++s) tuned_any |= tune_lookup(SW_TUNE_PAIR, prec, alpha, li.ms[s], te);
     try_mixed = !tuned_any;
@@ -714,7 +787,7 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
   }
   // ---- launch classes (rows per lane, widest sub-group, chunked or not); a
   // chunked launch holds tasks of any chunk count
-  struct Cls { int seg, pmax; bool chunked; };
+  struct Cls { int seg, pmax; bool chunked, rp; };
   std::vector<Cls> cls;
   std::vector<int> cls_of(nd);
   int max_nch = 1;
@@ -724,13 +797,24 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
     const bool chunked = ps.nchunks > 1;
     max_nch = std::max(max_nch, ps.nchunks);
     int c = 0;
-    while (c < (int)cls.size() && !(cls[c].seg == ps.seg && cls[c].pmax == pmax && cls[c].chunked == chunked)) ++c;
+    while (c < (int)cls.size() && !(cls[c].seg == ps.seg && cls[c].pmax == pmax &&
+                                     cls[c].chunked == chunked && cls[c].rp == ps.rp))
+      ++c;
     if (c == (int)cls.size()) {
+      if (ps.rp) {
+        if (!pair_rowpair_has(ps.seg, alpha)) {
+          set_error("no compiled row-pair kernel for %d rows per lane", ps.seg);
+          return SW_EINVAL;
+        }
+        cls.push_back(Cls{ps.seg, ps.P, chunked, true});
+        cls_of[s] = c;
+        continue;
+      }
       if (!pair_kernel_has(prec, ps.seg, pmax)) {
         set_error("no compiled per-pair kernel for %d rows per lane, %d lanes", ps.seg, pmax);
         return SW_EINVAL;
       }
-      cls.push_back(Cls{ps.seg, pmax, chunked});
+      cls.push_back(Cls{ps.seg, pmax, chunked, false});
     }
     cls_of[s] = c;
   }
@@ -805,7 +889,7 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
     }
     for (int c = 0; c < ncls; ++c) hs.bounds[c + 1] += hs.bounds[c];
   }
-  const int halves = prec == PREC_I16X2 ? 2 : 1;
+  const int halves_all = prec == PREC_I16X2 ? 2 : 1;
   for (int c = 0; c < ncls; ++c) {
     const int a = hs.bounds[c], b = hs.bounds[c + 1];
     if (a == b) continue;
@@ -814,8 +898,11 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
     L.shared = false;
     L.seg = K.seg;
     L.pmax = K.pmax;
+    L.rp = K.rp;
     L.nchunks = K.chunked ? 2 : 1;   // > 1: the chunked kernel (per-task counts)
     L.task_begin = (int)tasks.size();
+    // row pairs: one alignment per sub-group (the even slots)
+    const int halves = K.rp ? 1 : halves_all;
     if (b - a >= 50000) {
       // large classes: contiguous sub-ranges packed on several threads, then
       // concatenated in order (each sub-range may end in one partial task)
@@ -833,6 +920,7 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
       pack_pairs(rec.data() + a, b - a, K.pmax, halves, tasks, stats.lanes_used);
     }
     L.task_end = (int)tasks.size();
+    if (K.rp) stats.row_pairs += b - a;
     for (int t = L.task_begin; t < L.task_end; ++t) {
       Task &tk = tasks[t];
       if (K.chunked) { tk.bnd_off = bnd_elems; bnd_elems += 8ll * tk.ncols; }
@@ -841,7 +929,7 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
       for (int g = 0; g < ng; ++g)
         for (int h = 0; h < halves; ++h)
           if (tk.pair[2 * g + h] >= 0)
-            stats.padded_cells += (int64_t)tk.ncols * w[g] * K.seg * tk.nchunks;
+            stats.padded_cells += (int64_t)tk.ncols * w[g] * K.seg * tk.nchunks * (K.rp ? 2 : 1);
     }
     stats.seglen_max = std::max(stats.seglen_max, K.seg);
     L.grid = std::max(1, std::min(L.task_end - L.task_begin, num_cus * 16));
@@ -995,8 +1083,9 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
           // per-pair: the task's chunks of this sub-group cover the query
           if (ok && !L.shared)
             ok = tk.nchunks >= 1 && (chunked || tk.nchunks == 1) &&
-                 (int64_t)mlen[pid] <= (int64_t)tk.nchunks * widths[s2 / 2] * L.seg;
-          if (prec == PREC_I32) ok = ok && (s2 & 1) == 0;
+                 (int64_t)mlen[pid] <= (int64_t)tk.nchunks * widths[s2 / 2] * L.seg * (L.rp ? 2 : 1);
+          if (prec == PREC_I32 || L.rp) ok = ok && (s2 & 1) == 0;
+          if (L.rp) ok = ok && widths[s2 / 2] == L.pmax && prec == PREC_I16X2;
         }
       }
       if (!ok) {
@@ -1150,18 +1239,21 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
       a.bnd_half = bnd_half;
       a.bnd_in = bndA;
       const int seg = L.seg, pmax = L.pmax, grid = L.grid;
-      const bool chunked = L.nchunks > 1;
+      const bool chunked = L.nchunks > 1, rp = L.rp;
       // lane 0 is the main stream when no shared launch occupies it
       const int lane = side_wanted == 0 ? 0
                        : (any_shared ? 1 + pair_ordinal % side_wanted
                                      : pair_ordinal % (side_wanted + 1));
       ++pair_ordinal;
       hipStream_t ls = lane_stream[lane];
-      const uint64_t v[7] = {6, (uint64_t)prec, (uint64_t)seg, (uint64_t)pmax, (uint64_t)chunked,
-                             (uint64_t)grid, (uint64_t)lane};
+      const uint64_t v[8] = {6, (uint64_t)prec, (uint64_t)seg, (uint64_t)pmax, (uint64_t)chunked,
+                             (uint64_t)grid, (uint64_t)lane, (uint64_t)rp};
       note(v, sizeof(v));
       note(&a, sizeof(a));
-      ops.push_back([=]() { return launch_pair(prec, seg, pmax, chunked, a, grid, ls); });
+      ops.push_back([=]() {
+        return rp ? launch_pair_rowpair(seg, pmax, chunked, a, grid, ls)
+                  : launch_pair(prec, seg, pmax, chunked, a, grid, ls);
+      });
       stats.launches++;
     }
   }
@@ -1272,6 +1364,7 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
       ExecOptions o2 = opt;
       o2.force_lanes = 0;
       o2.force_seglen = 0;
+      o2.lane_pairing = SW_PAIRING_AUTO;   // the int32 rerun has no int16 halves
       rc = execute(in2, sc, PREC_I32, o2, ws, n_pairs, st, e0, e1, num_cus, es, false);
       if (rc) return rc;
       if ((rc = ws.staging.ensure((size_t)n_pairs * sizeof(DevResult)))) return rc;
@@ -1302,6 +1395,7 @@ int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecO
     stats->record_events = (int64_t)es.dev_stats[2];
     stats->graph_hits = es.graph_hits;
     stats->planner_used = 1;
+    stats->row_pairs = es.row_pairs;
     for (int k = 0; k < 3; ++k) stats->lanes_used[k] = es.lanes_used[k];
     stats->seglen_max = es.seglen_max;
   }

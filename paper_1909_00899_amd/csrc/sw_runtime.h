@@ -80,6 +80,7 @@ struct ExecStats {
   int launches = 0;
   int graph_hits = 0;
   int lanes_used[3] = {0, 0, 0};
+  int row_pairs = 0;
   int seglen_max = 0;
   unsigned long long dev_stats[3] = {0, 0, 0};
 };
