@@ -85,6 +85,12 @@ __device__ __forceinline__ uint32_t weight(uint64_t k, uint64_t unit) {
   return O::splat((uint32_t)(w > O::kWeightCap ? O::kWeightCap : w));
 }
 
+// Capped per-half weights lo_k*unit (low half) and hi_k*unit (high half).
+__device__ __forceinline__ uint32_t weight2(uint64_t lo_k, uint64_t hi_k, uint64_t unit) {
+  using O = OpsI16;
+  return (weight<O>(lo_k, unit) & 0xffffu) | (weight<O>(hi_k, unit) & 0xffff0000u);
+}
+
 // ---------------------------------------------------------------- DPP
 
 template <int CTRL, int ROWMASK = 0xf, bool BOUND = true>
@@ -271,6 +277,36 @@ __device__ __forceinline__ void record(State<SEG> &st, uint32_t cmax, int i) {
     } else {
       if (m) st.rc[0] = i;
     }
+    st.G = nb;
+    st.S = (nb & m) | (st.S & ~m);
+  }
+}
+
+// record() for int16 lanes with the end-cell copy in LDS instead of VGPRs:
+// a lane whose low (high) half improves stores the low (high) halves of the
+// column's H with 16-bit LDS stores (row j at snap + 256*j), which costs LDS
+// issue slots instead of one VALU select per row.
+template <int SEG>
+__device__ __forceinline__ void record_lds(State<SEG> &st, uint32_t cmax, int i, uint32_t snap) {
+  using O = OpsI16;
+  const uint32_t nb = O::vmax(st.G, cmax);
+  if (__any(nb != st.G)) {
+    ++st.events;
+    uint32_t m = gain_mask<O>(nb, st.G);
+    asm("" : "+v"(m));
+    if (m & 0xffffu) {
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) *(unsigned short *)(smem + snap + 256 * j) = (unsigned short)st.H[j];
+    }
+    if (m >> 16) {
+#pragma unroll
+      for (int j = 0; j < SEG; ++j)
+        *(unsigned short *)(smem + snap + 256 * j + 2) = (unsigned short)(st.H[j] >> 16);
+    }
+    const uint32_t mlo = (uint32_t)((int)(m << 16) >> 16);
+    const uint32_t mhi = (uint32_t)((int)m >> 16);
+    st.rc[0] = (int)(((uint32_t)i & mlo) | ((uint32_t)st.rc[0] & ~mlo));
+    st.rc[1] = (int)(((uint32_t)i & mhi) | ((uint32_t)st.rc[1] & ~mhi));
     st.G = nb;
     st.S = (nb & m) | (st.S & ~m);
   }
@@ -819,12 +855,14 @@ __device__ __forceinline__ RpLane make_rp_lane(uint32_t ge) {
   L.l = L.lane % P;
   L.keep = L.l == 0 ? 0u : 0xffffffffu;
   const int row = L.lane >> 4;
-  const uint64_t unit = 2ull * SEG * ge;   // one lane = two virtual lanes
+  const uint64_t unit = (uint64_t)SEG * ge;   // one virtual lane
   const uint32_t inf = O::splat(O::kWeightCap);
   const bool r15 = P >= 32 && (row & 1);
   const bool r31 = P >= 64 && row >= 2;
-  L.w16 = r15 ? weight<O>((uint64_t)(L.lane & 15) + 1, unit) : inf;
-  L.w32 = r31 ? weight<O>((uint64_t)(L.lane & 31) + 1, unit) : inf;
+  // the broadcast lane's total reaches this lane e lanes further down
+  const uint64_t e15 = (uint64_t)(L.lane & 15) + 1, e31 = (uint64_t)(L.lane & 31) + 1;
+  L.w16 = r15 ? weight2(2 * e15 - 1, 2 * e15, unit) : inf;
+  L.w32 = r31 ? weight2(2 * e31 - 1, 2 * e31, unit) : inf;
   L.rx16 = r15 ? 0xffffffffu : 0u;
   L.rx32 = r31 ? 0xffffffffu : 0u;
   return L;
@@ -838,7 +876,10 @@ __device__ __forceinline__ uint32_t rp_both(uint32_t x) {
 struct RpParams {
   uint32_t go, ge;            // splatted gap penalties
   uint32_t wv;                // SEG*ge: one virtual lane
-  uint32_t w1, w2, w4, w8;    // 2*SEG*ge*d: d lanes (2d virtual lanes)
+  // lane steps of the scan: the total of the lane d lanes up (its high half,
+  // virtual lane 2(l-d)+1) reaches this lane's low half over 2d-1 virtual lanes
+  // and its high half over 2d: weights (2d-1)*SEG*ge | 2d*SEG*ge << 16
+  uint32_t w1, w2, w4, w8;
   uint32_t wlast;             // (SEG-1)*ge
 };
 
@@ -849,12 +890,23 @@ __device__ __forceinline__ RpParams make_rp_params(uint32_t go, uint32_t ge) {
   p.go = O::splat(go);
   p.ge = O::splat(ge);
   p.wv = weight<O>(1ull * SEG, ge);
-  p.w1 = weight<O>(2ull * SEG, ge);
-  p.w2 = weight<O>(4ull * SEG, ge);
-  p.w4 = weight<O>(8ull * SEG, ge);
-  p.w8 = weight<O>(16ull * SEG, ge);
+  p.w1 = weight2(1, 2, (uint64_t)SEG * ge);
+  p.w2 = weight2(3, 4, (uint64_t)SEG * ge);
+  p.w4 = weight2(7, 8, (uint64_t)SEG * ge);
+  p.w8 = weight2(15, 16, (uint64_t)SEG * ge);
   p.wlast = weight<O>((uint64_t)(SEG - 1), ge);
   return p;
+}
+
+// x's high half in both halves (a packed operand select, not an instruction).
+__device__ __forceinline__ uint32_t rp_hi2(uint32_t x) {
+  const u16x2 v = bc<u16x2>(x);
+  return bc<uint32_t>(__builtin_shufflevector(v, v, 1, 1));
+}
+// x's low half in both halves.
+__device__ __forceinline__ uint32_t rp_lo2(uint32_t x) {
+  const u16x2 v = bc<u16x2>(x);
+  return bc<uint32_t>(__builtin_shufflevector(v, v, 0, 0));
 }
 
 // LDS profile of the row-pair layout: [alpha+1][SEG][16 lanes] words, the
@@ -919,11 +971,11 @@ struct RpPairs {
 // corrected last-row H and vertical-gap carry at this column, already placed
 // in the low half of the sub-group's first lane (zero elsewhere); hb_out /
 // fb_out receive this chunk's (in the low 16 bits, meaningful in the last lane).
-template <int SEG, bool CHUNKED, class Prof, int P = 16>
+template <int SEG, bool CHUNKED, class Prof, int P = 16, bool LREC = false>
 __device__ __forceinline__ void rp_column(State<SEG> &st, const RpParams &pr, const Prof &pf,
                                           int i, uint32_t cin_h, uint32_t cin_f,
                                           uint32_t &hb_out, uint32_t &fb_out,
-                                          const RpLane *lp = nullptr) {
+                                          const RpLane *lp = nullptr, uint32_t snap = 0) {
   using O = OpsI16;
   const uint32_t keep = P == 32 ? lp->keep : 0u;
   uint32_t Fj = st.Fscan;
@@ -952,21 +1004,24 @@ __device__ __forceinline__ void rp_column(State<SEG> &st, const RpParams &pr, co
   }
   // inclusive max-plus scan over the 32 virtual lanes (a carry from the
   // previous chunk enters as virtual lane -1), then one virtual lane down
+  // (first inside the lane: high half from low half; then Hillis-Steele over
+  // the lanes on their totals, the high halves, with per-half weights)
   uint32_t G = F;
   if constexpr (CHUNKED) G = O::vmax(G, O::usub(cin_f, pr.wv));
-  G = O::vmax(G, O::usub(rp_vshift_p<P>(G, keep), pr.wv));
-  G = O::vmax(G, O::usub(dpp<kRowShr1>(G), pr.w1));
-  G = O::vmax(G, O::usub(dpp<kRowShr2>(G), pr.w2));
-  G = O::vmax(G, O::usub(dpp<kRowShr4>(G), pr.w4));
-  G = O::vmax(G, O::usub(dpp<kRowShr8>(G), pr.w8));
-  if constexpr (P >= 32) G = O::vmax(G, O::usub(dpp<kRowBcast15, 0xa, false>(G), lp->w16));
-  if constexpr (P >= 64) G = O::vmax(G, O::usub(dpp<kRowBcast31, 0xc, false>(G), lp->w32));
+  G = O::vmax(G, O::usub(rp_lo2(G), pr.wv));
+  G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr1>(G)), pr.w1));
+  G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr2>(G)), pr.w2));
+  G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr4>(G)), pr.w4));
+  G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr8>(G)), pr.w8));
+  if constexpr (P >= 32) G = O::vmax(G, O::usub(rp_hi2(dpp<kRowBcast15, 0xa, false>(G)), lp->w16));
+  if constexpr (P >= 64) G = O::vmax(G, O::usub(rp_hi2(dpp<kRowBcast31, 0xc, false>(G)), lp->w32));
   st.Fscan = rp_vshift_p<P>(G, keep);
   if constexpr (CHUNKED) {
     st.Fscan |= cin_f;
     fb_out = G >> 16;
   }
-  record<O, SEG>(st, cmax, i);
+  if constexpr (LREC) record_lds<SEG>(st, cmax, i, snap);
+  else record<O, SEG>(st, cmax, i);
 }
 
 // Record thresholds raised to the largest of the sub-group (both halves).
@@ -1010,9 +1065,10 @@ __device__ __forceinline__ void rp_share_threshold_p(State<SEG> &st, const RpLan
   }
 }
 
-template <int SEG, class Src>
+template <int SEG, bool LREC, class Src>
 __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const RpParams &pr,
-                                               uint32_t lane_base, const Src &src, int ncols) {
+                                               uint32_t lane_base, const Src &src, int ncols,
+                                               uint32_t snap) {
   const int nblk = ncols / kBlock;
   uint32_t ev_shared = st.events;
   uint32_t rc = src.get(0).x;
@@ -1025,8 +1081,8 @@ __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const R
     for (int k = 0; k < kBlock; ++k) {
       const uint32_t c = __builtin_amdgcn_ubfe(r, 8 * k, 8);
       uint32_t ho, fo;
-      rp_column<SEG, false>(st, pr, RpShared{lane_base + c * rp_cstride(SEG)}, b * kBlock + k,
-                            0u, 0u, ho, fo);
+      rp_column<SEG, false, RpShared, 16, LREC>(st, pr, RpShared{lane_base + c * rp_cstride(SEG)},
+                                               b * kBlock + k, 0u, 0u, ho, fo, nullptr, snap);
     }
     if (st.events != ev_shared) {
       rp_share_threshold<SEG>(st, lane);
@@ -1037,10 +1093,10 @@ __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const R
 
 // Result of the alignment of this lane's sub-group: the best recorded cell of
 // each half (virtual lane 2l + h), then the best over the 16 lanes.
-template <int SEG>
+template <int SEG, bool LREC>
 __device__ __forceinline__ void rp_finish(const State<SEG> &st, int lane, int pid,
                                           const PairInfo *pairs, DevResult *results,
-                                          int sat_cap) {
+                                          int sat_cap, uint32_t snap) {
   using O = OpsI16;
   const int l = lane & 15;
   int s = 0, c = 0x7fffffff, r = 0x7fffffff;
@@ -1050,8 +1106,12 @@ __device__ __forceinline__ void rp_finish(const State<SEG> &st, int lane, int pi
     if (sh > 0) {
       int jj = SEG - 1;
 #pragma unroll
-      for (int j = SEG - 1; j >= 0; --j)
-        if (O::get(st.snap[j], h) >= sh) jj = j;
+      for (int j = SEG - 1; j >= 0; --j) {
+        int v;
+        if constexpr (LREC) v = (int)*(const short *)(smem + snap + 256 * j + 2 * h);
+        else v = O::get(st.snap[j], h);
+        if (v >= sh) jj = j;
+      }
       const int ch = st.rc[h], rh = (2 * l + h) * SEG + jj;
       if (s <= 0 || better(sh, ch, rh, s, c, r)) { s = sh; c = ch; r = rh; }
     }
@@ -1073,7 +1133,9 @@ __device__ __forceinline__ void rp_finish(const State<SEG> &st, int lane, int pi
 // Device-planned shared-query kernel in the row-pair layout: four
 // alignments per wavefront (one per 16-lane sub-group); task t is entries
 // [4t, 4t+4) of the longest-first order.
-template <int SEG>
+// LREC: end-cell copies in LDS ([8 wavefronts][SEG][64 lanes] words after the
+// two profile copies) instead of VGPRs.
+template <int SEG, bool LREC>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 void shared_rowpair_kernel(KArgs a) {
   if (a.plan_meta[kMetaErrResidue] | a.plan_meta[kMetaErrPair]) return;
@@ -1083,6 +1145,8 @@ void shared_rowpair_kernel(KArgs a) {
   build_rowpair_profile<SEG>(a, off);
   __syncthreads();
   const int lane = (int)(threadIdx.x & 63);
+  const uint32_t snap = off + 2 * rp_copy_bytes(SEG, a.alpha) +
+                        (uint32_t)(threadIdx.x >> 6) * (SEG * 256) + (uint32_t)lane * 4;
   const int sg = lane >> 4;
   const int nvalid = a.plan_meta[kMetaValid];
   const int ntasks = (nvalid + 3) / 4;
@@ -1108,11 +1172,11 @@ void shared_rowpair_kernel(KArgs a) {
     State<SEG> st;
     state_reset(st, 0u);
     const DirectSrc src{a.ref_res + roff, a.ref_res + roff, n, 0, sentw};
-    rp_run_columns<SEG>(st, lane, pr, lane_base, src, ncols);
+    rp_run_columns<SEG, LREC>(st, lane, pr, lane_base, src, ncols, snap);
     cols += (unsigned long long)ncols;
     events += st.events;
     padded += (unsigned long long)min(4, nvalid - ti * 4) * ncols * 32 * SEG;
-    rp_finish<SEG>(st, lane, pid, a.pairs, a.results, a.sat_cap);
+    rp_finish<SEG, LREC>(st, lane, pid, a.pairs, a.results, a.sat_cap, snap);
   }
   if (lane == 0 && a.stats != nullptr) {
     if (cols) atomicAdd(&a.stats[0], cols);

@@ -16,7 +16,8 @@ hipError_t launch_pair_i32(int seg, int pmax, bool chunked, const KArgs &a, int 
                            hipStream_t st, size_t lds);
 hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_direct_i32(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
-hipError_t launch_rowpair_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
+hipError_t launch_rowpair_i16(int seg, bool lds_records, const KArgs &a, int grid,
+                              hipStream_t st, size_t lds);
 hipError_t launch_pair_direct_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_pair_direct_i32(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_pair_rowpair_i16(int seg, int lanes, bool chunked, const KArgs &a, int grid,
@@ -370,11 +371,19 @@ size_t shared_rowpair_lds_bytes(int seg, int alpha) {
   return (matrix_lds_bytes(alpha) + 255) / 256 * 256 + 2 * (size_t)dev::rp_copy_bytes(seg, alpha);
 }
 
+// With the end-cell copies in LDS as well, while two workgroups still share a
+// CU (160 KB of LDS).
+static size_t rowpair_lds_records_bytes(int seg, int alpha) {
+  return shared_rowpair_lds_bytes(seg, alpha) + (size_t)kWavesPerGroup * seg * 256;
+}
+
 hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st) {
   if (!shared_rowpair_has(seg) || a.order == nullptr || a.plan_meta == nullptr ||
       a.ref_res == nullptr)
     return hipErrorInvalidValue;
-  return launch_rowpair_i16(seg, a, grid, st, shared_rowpair_lds_bytes(seg, a.alpha));
+  const size_t with = rowpair_lds_records_bytes(seg, a.alpha);
+  if (with <= 80 * 1024) return launch_rowpair_i16(seg, true, a, grid, st, with);
+  return launch_rowpair_i16(seg, false, a, grid, st, shared_rowpair_lds_bytes(seg, a.alpha));
 }
 
 bool pair_rowpair_has(int seg, int alpha) {

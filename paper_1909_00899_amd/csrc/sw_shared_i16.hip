@@ -35,23 +35,30 @@ hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
   hipLaunchKernelGGL(k, dim3(grid), dim3(kWavesPerGroup * kWave), lds, st, a);
   return hipGetLastError();
 }
-template <int SEG>
+template <int SEG, bool LREC>
 hipError_t launch_rp(const KArgs &a, int grid, hipStream_t st, size_t lds) {
-  auto k = dev::shared_rowpair_kernel<SEG>;
+  auto k = dev::shared_rowpair_kernel<SEG, LREC>;
   hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(kWavesPerGroup * kWave), lds, st, a);
   return hipGetLastError();
 }
-}  // namespace
 
-hipError_t launch_rowpair_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds) {
+template <bool LREC>
+hipError_t launch_rps(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds) {
   switch (seg) {
-    case 4: return launch_rp<4>(a, grid, st, lds);
-    case 8: return launch_rp<8>(a, grid, st, lds);
-    case 12: return launch_rp<12>(a, grid, st, lds);
-    case 16: return launch_rp<16>(a, grid, st, lds);
+    case 4: return launch_rp<4, LREC>(a, grid, st, lds);
+    case 8: return launch_rp<8, LREC>(a, grid, st, lds);
+    case 12: return launch_rp<12, LREC>(a, grid, st, lds);
+    case 16: return launch_rp<16, LREC>(a, grid, st, lds);
   }
   return hipErrorInvalidValue;
+}
+}  // namespace
+
+hipError_t launch_rowpair_i16(int seg, bool lds_records, const KArgs &a, int grid,
+                              hipStream_t st, size_t lds) {
+  return lds_records ? launch_rps<true>(seg, a, grid, st, lds)
+                     : launch_rps<false>(seg, a, grid, st, lds);
 }
 
 hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds) {
