@@ -1079,7 +1079,9 @@ __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const R
     rn = src.get(b + 2).x;
 #pragma unroll
     for (int k = 0; k < kBlock; ++k) {
-      const uint32_t c = __builtin_amdgcn_ubfe(r, 8 * k, 8);
+      // byte k of the word alone (a byte permute; written as shifts and masks
+      // the compiler spends two instructions on it), then one shift-add
+      const uint32_t c = __builtin_amdgcn_perm(0u, r, 0x0c0c0c00u | (uint32_t)k);
       uint32_t ho, fo;
       rp_column<SEG, false, RpShared, 16, LREC>(st, pr, RpShared{lane_base + c * rp_cstride(SEG)},
                                                b * kBlock + k, 0u, 0u, ho, fo, nullptr, snap);
