@@ -150,7 +150,11 @@ enum { SW_ALG_SCAN = 0,          /* max-plus scan, deferred H fix-up (Algorithm 
 typedef struct {
     int32_t algorithm;           /* SW_ALG_*                                        */
     int32_t force_lanes;         /* 0 = planner's choice; 16, 32 or 64 = lanes per
-                                    alignment for every pair                        */
+                                    alignment for every pair; 8 only for
+                                    device-planned batches with one query per
+                                    pair (sixteen alignments per wavefront, a
+                                    scoring matrix within int8, queries of at
+                                    most 152 residues)                           */
     int32_t force_seglen;        /* 0 = planner's choice; else rows per lane (the
                                     query is split into chunks of lanes*seglen rows) */
     int32_t force_kernel;        /* 0 = planner's choice; 1 = shared-query kernel;
@@ -219,7 +223,8 @@ typedef struct {
                                     graph (no capture)                          */
     int32_t planner_used;        /* 1 = host planner, 2 = device planner        */
     int32_t row_pairs;           /* pairs run in the row-pair lane layout       */
-    int32_t reserved[5];
+    int32_t lanes8;              /* pairs run with 8 lanes                      */
+    int32_t reserved[4];
 } sw_stats;
 
 int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options *opt,

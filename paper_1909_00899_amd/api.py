@@ -80,7 +80,7 @@ class Stats(ctypes.Structure):
                 ("launch_ms", ctypes.c_double), ("finish_ms", ctypes.c_double),
                 ("record_events", ctypes.c_int64), ("graph_hits", ctypes.c_int32),
                 ("planner_used", ctypes.c_int32), ("row_pairs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("lanes8", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
     def as_dict(self) -> dict:
         return {"kernel_ms": self.kernel_ms, "total_ms": self.total_ms, "cells": self.cells,
@@ -90,7 +90,8 @@ class Stats(ctypes.Structure):
                 "seglen_max": self.seglen_max, "prep_ms": self.prep_ms, "plan_ms": self.plan_ms,
                 "launch_ms": self.launch_ms, "finish_ms": self.finish_ms,
                 "record_events": self.record_events, "graph_hits": self.graph_hits,
-                "planner_used": self.planner_used, "row_pairs": self.row_pairs}
+                "planner_used": self.planner_used, "row_pairs": self.row_pairs,
+                "lanes8": self.lanes8}
 
 
 SW_TUNE_SHARED, SW_TUNE_PAIR = 0, 1

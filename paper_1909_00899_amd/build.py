@@ -18,7 +18,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libswscan.so")
 ARCH = "gfx950"
 
-SOURCES = ["sw_shared_i16.hip", "sw_shared_i32.hip", "sw_pair_i16.hip", "sw_pair_i32.hip",
+SOURCES = ["sw_shared_i16.hip", "sw_shared_i32.hip", "sw_pair_i16.hip", "sw_pair8_i16.hip",
+           "sw_pair_i32.hip",
            "sw_launch.hip", "sw_runtime.cpp", "sw_devplan.cpp", "sw_api.cpp", "sw_server.cpp", "sw_tune.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

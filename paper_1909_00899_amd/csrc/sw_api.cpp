@@ -245,8 +245,9 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
   ExecOptions eo;
   if (opt) {
     if (opt->algorithm != SW_ALG_SCAN && opt->algorithm != SW_ALG_LAZYF) { set_error("bad algorithm"); return SW_EINVAL; }
-    if (opt->force_lanes && opt->force_lanes != 16 && opt->force_lanes != 32 && opt->force_lanes != 64) {
-      set_error("force_lanes must be 0, 16, 32 or 64");
+    if (opt->force_lanes && opt->force_lanes != 8 && opt->force_lanes != 16 &&
+        opt->force_lanes != 32 && opt->force_lanes != 64) {
+      set_error("force_lanes must be 0, 8, 16, 32 or 64");
       return SW_EINVAL;
     }
     if (opt->force_seglen < 0 || opt->int16_cap < 0 || opt->int16_cap > 32767 ||
@@ -278,6 +279,11 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
   rc = run_device_plan(b, S, eo, opt ? opt->planner : 0, C, out, stats, t0, handled);
   if (handled) return rc;
   if (rc) return rc;
+  if (eo.force_lanes == 8) {
+    set_error("8 lanes per alignment only in the device planner's per-pair kernel (one query "
+              "per pair, int16 lanes, scores within int8, queries of at most 152 residues)");
+    return SW_EINVAL;
+  }
   ExecInput in;
   int64_t cells = 0;
   if ((rc = prepare_batch(b, S, C, in, out, cells))) return rc;

@@ -30,6 +30,8 @@
 // of the broadcast steps are per lane, so a wavefront may mix 32- and 16-lane
 // sub-groups (a lane that must not receive gets an infinite weight).
 #pragma once
+#include <type_traits>
+
 #include "sw_internal.h"
 
 namespace swk {
@@ -99,6 +101,9 @@ __device__ __forceinline__ uint32_t dpp(uint32_t x) {
 }
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
 constexpr int kWaveShr1 = 0x138, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+// quad_perm [1,0,3,2] and [2,3,0,1] (lane xor 1, xor 2), and the mirror of
+// each eight-lane half of a row (lane xor 7 inside the half)
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowHalfMirror = 0x141;
 
 // ---------------------------------------------------------------- lane layout
 
@@ -115,6 +120,11 @@ struct LaneCtx {
   uint32_t rx16;    // all ones if this lane takes the row_bcast:15 value (same sub-group)
   uint32_t rx32;    // all ones if this lane takes the row_bcast:31 value
   int glast;        // wavefront lane index of the last lane of this sub-group
+  // eight-lane sub-groups only: scan weights of the row_shr:1/2/4 steps
+  // (infinite where the source lane lies in the previous sub-group) and the
+  // mask that clears what a one-lane move brings across the boundary
+  uint32_t v1, v2, v4;
+  uint32_t keep;
 };
 
 // layout: bit r set <=> a sub-group starts at lane 16*r (bit 0 always set).
@@ -144,6 +154,34 @@ __device__ __forceinline__ LaneCtx make_lane(int layout, int seg, uint32_t ge) {
   L.rx16 = r15 ? 0xffffffffu : 0u;
   L.rx32 = r31 ? 0xffffffffu : 0u;
   L.glast = s0 * 16 + L.P - 1;
+  L.v1 = L.v2 = L.v4 = inf;
+  L.keep = 0xffffffffu;
+  return L;
+}
+
+// Eight sub-groups of eight lanes (per-pair kernels for short queries):
+// sub-group g is wavefront lanes 8g..8g+7.  Two sub-groups share each 16-lane
+// DPP row, so a row shift by d brings lanes of the previous sub-group into the
+// first d lanes of the upper one: their scan weight is infinite and the
+// one-lane moves are masked there.
+template <class O>
+__device__ __forceinline__ LaneCtx make_lane8(int seg, uint32_t ge) {
+  LaneCtx L;
+  L.lane = (int)(threadIdx.x & 63);
+  L.P = 8;
+  L.l = L.lane & 7;
+  L.sg = L.lane >> 3;
+  L.start = L.l == 0;
+  L.last = L.l == 7;
+  const uint64_t unit = (uint64_t)seg * ge;
+  const uint32_t inf = O::splat(O::kWeightCap);
+  L.v1 = L.l >= 1 ? weight<O>(unit, 1) : inf;
+  L.v2 = L.l >= 2 ? weight<O>(2 * unit, 1) : inf;
+  L.v4 = L.l >= 4 ? weight<O>(4 * unit, 1) : inf;
+  L.keep = L.start ? 0u : 0xffffffffu;
+  L.w16 = L.w32 = L.wcarry = inf;
+  L.rx16 = L.rx32 = 0u;
+  L.glast = L.lane | 7;
   return L;
 }
 
@@ -151,7 +189,10 @@ __device__ __forceinline__ LaneCtx make_lane(int layout, int seg, uint32_t ge) {
 // receives `carry`.
 template <int PMAX, bool CARRY>
 __device__ __forceinline__ uint32_t shift1(uint32_t x, const LaneCtx &L, uint32_t carry) {
-  if constexpr (PMAX == 16) {
+  if constexpr (PMAX == 8) {
+    static_assert(!CARRY, "eight-lane sub-groups hold the whole query");
+    return dpp<kRowShr1>(x) & L.keep;
+  } else if constexpr (PMAX == 16) {
     uint32_t s = dpp<kRowShr1>(x);
     if constexpr (CARRY) s = L.start ? carry : s;
     return s;
@@ -244,6 +285,22 @@ struct ProfLds {
   }
 };
 
+// Byte profile entries (matrices whose scores fit in int8), sign-extended to
+// the lane type; otherwise as ProfLds.
+template <class O, int JSTRIDE>
+struct ProfLds8 {
+  __device__ __forceinline__ uint32_t load(uint32_t lo, uint32_t hi, int j) const {
+    const int a = *(const signed char *)(smem + lo + j * JSTRIDE);
+    if constexpr (O::kHalves == 2) {
+      const int b = *(const signed char *)(smem + hi + j * JSTRIDE);
+      // low 16 bits of each sign-extended byte: one byte permute
+      return __builtin_amdgcn_perm((uint32_t)b, (uint32_t)a, 0x05040100u);
+    } else {
+      return (uint32_t)a;
+    }
+  }
+};
+
 // Per-half mask where nb > g, given nb >= g: 0xffff in each 16-bit half
 // (packed: the sign of g - nb, which cannot overflow for values in
 // [0, 32767], spread over the half), or all ones (int32).
@@ -318,6 +375,14 @@ __device__ __forceinline__ void record_lds(State<SEG> &st, uint32_t cmax, int i,
 // value read back for every lane of the sub-group.
 template <class O, int SEG, int PMAX>
 __device__ __forceinline__ void share_threshold(State<SEG> &st, const LaneCtx &L) {
+  if constexpr (PMAX == 8) {
+    // butterfly over the eight lanes: every lane ends with the maximum
+    uint32_t T = st.G;
+    T = O::vmax(T, dpp<kQuadXor1>(T));
+    T = O::vmax(T, dpp<kQuadXor2>(T));
+    st.G = O::vmax(T, dpp<kRowHalfMirror>(T));
+    return;
+  }
   uint32_t T = st.G;
   T = O::vmax(T, dpp<kRowShr1>(T));
   T = O::vmax(T, dpp<kRowShr2>(T));
@@ -365,10 +430,16 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     // max-plus scan of the per-lane vertical-gap outputs
     uint32_t G = F;
     if constexpr (CHUNKED) G = O::vmax(G, O::usub(fb_in, L.wcarry));
-    G = O::vmax(G, O::usub(dpp<kRowShr1>(G), pr.w1));
-    G = O::vmax(G, O::usub(dpp<kRowShr2>(G), pr.w2));
-    G = O::vmax(G, O::usub(dpp<kRowShr4>(G), pr.w4));
-    G = O::vmax(G, O::usub(dpp<kRowShr8>(G), pr.w8));
+    if constexpr (PMAX == 8) {
+      G = O::vmax(G, O::usub(dpp<kRowShr1>(G), L.v1));
+      G = O::vmax(G, O::usub(dpp<kRowShr2>(G), L.v2));
+      G = O::vmax(G, O::usub(dpp<kRowShr4>(G), L.v4));
+    } else {
+      G = O::vmax(G, O::usub(dpp<kRowShr1>(G), pr.w1));
+      G = O::vmax(G, O::usub(dpp<kRowShr2>(G), pr.w2));
+      G = O::vmax(G, O::usub(dpp<kRowShr4>(G), pr.w4));
+      G = O::vmax(G, O::usub(dpp<kRowShr8>(G), pr.w8));
+    }
     if constexpr (PMAX >= 32) G = O::vmax(G, O::usub(dpp<kRowBcast15, 0xa, false>(G), L.w16));
     if constexpr (PMAX >= 64) G = O::vmax(G, O::usub(dpp<kRowBcast31, 0xc, false>(G), L.w32));
     fb_out = G;
@@ -1191,21 +1262,25 @@ void shared_rowpair_kernel(KArgs a) {
 
 // Each wavefront owns an LDS region [half][alpha+1][SEG][64 lanes]: lane x
 // reads and writes only column x, so any sub-group partition works and no
-// barrier is needed between building a profile and using it.
-template <class O, int SEG>
+// barrier is needed between building a profile and using it.  ES: bytes per
+// entry, the lane type's or 1 (int8 entries, half or a quarter of the LDS).
+template <class O, int SEG, int ES = O::kES>
 struct PairMap {
-  ProfLds<O, kWave * O::kES> prof;
+  typename std::conditional<ES == 1, ProfLds8<O, kWave>, ProfLds<O, kWave * O::kES>>::type prof;
   uint32_t lo0, hi0;   // bytes: region + lane*ES (+ half offset)
-  __device__ __forceinline__ uint32_t base_lo(uint32_t c) const { return lo0 + c * (SEG * kWave * O::kES); }
-  __device__ __forceinline__ uint32_t base_hi(uint32_t c) const { return hi0 + c * (SEG * kWave * O::kES); }
+  __device__ __forceinline__ uint32_t base_lo(uint32_t c) const { return lo0 + c * (SEG * kWave * ES); }
+  __device__ __forceinline__ uint32_t base_hi(uint32_t c) const { return hi0 + c * (SEG * kWave * ES); }
 };
 
 __host__ __device__ constexpr uint32_t pair_region_bytes(int seg, int alpha, int halves, int es) {
   return (uint32_t)(halves * (alpha + 1) * seg * kWave * es);
 }
 
-// pids[h]: PairInfo index of this lane's sub-group in half h, or -1.
-template <class O, int SEG>
+// pids[h]: PairInfo index of this lane's sub-group in half h, or -1.  Rows
+// past the query and the sentinel code get the most negative entry: any
+// negative score keeps those cells below the alignment's best, since they
+// follow every real cell in (column, row) order.
+template <class O, int SEG, int ES = O::kES>
 __device__ __forceinline__ void build_pair_profile(const KArgs &a, const int pids[2],
                                                    const LaneCtx &L, uint32_t region, int row0) {
   const int32_t *M = (const int32_t *)smem;
@@ -1216,16 +1291,17 @@ __device__ __forceinline__ void build_pair_profile(const KArgs &a, const int pid
     int m = 0;
     int64_t qo = 0;
     if (pid >= 0) { m = a.pairs[pid].m; qo = a.pairs[pid].q_off; }
-    const uint32_t hbase = region + (uint32_t)(h * nrow * SEG * kWave * O::kES) + L.lane * O::kES;
+    const uint32_t hbase = region + (uint32_t)(h * nrow * SEG * kWave * ES) + L.lane * ES;
     for (int j = 0; j < SEG; ++j) {
       const int row = row0 + L.l * SEG + j;
       int qc = row < m ? (int)a.query_res[qo + row] : -1;
       if (qc >= a.alpha) qc = -1;   // invalid codes are reported by the host check
       for (int c = 0; c < nrow; ++c) {
         const int v = (qc >= 0 && c < a.alpha) ? M[qc * a.alpha + c]
-                                               : (O::kES == 2 ? -32768 : (int)0x80000000);
-        unsigned char *dst = smem + hbase + (c * SEG + j) * kWave * O::kES;
-        if constexpr (O::kES == 2) *(short *)dst = (short)v;
+                                               : (ES == 1 ? -128 : (ES == 2 ? -32768 : (int)0x80000000));
+        unsigned char *dst = smem + hbase + (c * SEG + j) * kWave * ES;
+        if constexpr (ES == 1) *(signed char *)dst = (signed char)v;
+        else if constexpr (ES == 2) *(short *)dst = (short)v;
         else *(int *)dst = v;
       }
     }
@@ -1285,27 +1361,33 @@ void pair_kernel(KArgs a) {
 }
 
 // Device-planned per-pair kernel: every pair has its own query (one query
-// chunk, 16 rows-per-lane x 16 lanes at most), four 16-lane sub-groups per
-// wavefront, in int16 mode two alignments per lane.  Task t is entries
-// [t*slots, (t+1)*slots) of the planner's longest-first order (entry
-// t*slots + s to sub-group s / halves, half s % halves); profiles are built
-// per task in the wavefront's own LDS region; residues come from the
-// references themselves.
-template <class O, int SEG>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+// chunk, SEG rows per lane x P lanes at most), 64/P sub-groups of P = 8 or 16
+// lanes per wavefront, in int16 mode two alignments per lane.  Task t is
+// entries [t*slots, (t+1)*slots) of the planner's longest-first order (entry
+// t*slots + s to sub-group s / halves, half s % halves); profiles (ES bytes
+// per entry) are built per task in the wavefront's own LDS region; residues
+// come from the references themselves.
+__host__ __device__ constexpr int pair_direct_waves_per_eu(int seg, int P) {
+  return (P == 8 && seg >= 16) ? 3 : 4;
+}
+
+template <class O, int SEG, int P, int ES>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(pair_direct_waves_per_eu(SEG, P))))
 void pair_direct_kernel(KArgs a) {
+  static_assert(P == 8 || P == 16, "sub-groups of 8 or 16 lanes");
   if (a.plan_meta[kMetaErrResidue] | a.plan_meta[kMetaErrPair]) return;
   stage_matrix(a);
   __syncthreads();
   const uint32_t region = matrix_lds_bytes(a.alpha);
-  constexpr int kSlotsPerTask = 4 * O::kHalves;
+  constexpr int kSlotsPerTask = (kWave / P) * O::kHalves;
   const int nvalid = a.plan_meta[kMetaValid];
   const int ntasks = (nvalid + kSlotsPerTask - 1) / kSlotsPerTask;
-  const LaneCtx L = make_lane<O>(0xF, SEG, (uint32_t)a.gap_extend);
+  const LaneCtx L = P == 8 ? make_lane8<O>(SEG, (uint32_t)a.gap_extend)
+                           : make_lane<O>(0xF, SEG, (uint32_t)a.gap_extend);
   const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
-  PairMap<O, SEG> pm;
-  pm.lo0 = region + L.lane * O::kES;
-  pm.hi0 = pm.lo0 + (O::kHalves == 2 ? (a.alpha + 1) * SEG * kWave * O::kES : 0);
+  PairMap<O, SEG, ES> pm;
+  pm.lo0 = region + L.lane * ES;
+  pm.hi0 = pm.lo0 + (O::kHalves == 2 ? (a.alpha + 1) * SEG * kWave * ES : 0);
   const uint32_t sentw = (uint32_t)a.alpha * 0x01010101u;
   uint32_t lazy_steps = 0;
   unsigned long long cols = 0, events = 0, padded = 0;
@@ -1328,17 +1410,17 @@ void pair_direct_kernel(KArgs a) {
     int nmax = max(n[0], n[1]);
     for (int d = 1; d < kWave; d <<= 1) nmax = max(nmax, __shfl_xor(nmax, d));
     const int ncols = (nmax + kBlock - 1) / kBlock * kBlock;
-    build_pair_profile<O, SEG>(a, pid, L, region, 0);
+    build_pair_profile<O, SEG, ES>(a, pid, L, region, 0);
     Prev prev;
     prev_reset(prev);
     State<SEG> st;
     state_reset(st, 0u);
     const DirectSrc src{a.ref_res + roff[0], a.ref_res + roff[1], n[0], n[1], sentw};
-    run_columns<O, SEG, 16, false, false>(st, L, pr, pm, src, ncols, nullptr, nullptr, nullptr,
-                                          nullptr, lazy_steps);
+    run_columns<O, SEG, P, false, false>(st, L, pr, pm, src, ncols, nullptr, nullptr, nullptr,
+                                         nullptr, lazy_steps);
     cols += (unsigned long long)ncols;
     events += st.events;
-    padded += (unsigned long long)min(kSlotsPerTask, nvalid - ti * kSlotsPerTask) * ncols * 16 * SEG;
+    padded += (unsigned long long)min(kSlotsPerTask, nvalid - ti * kSlotsPerTask) * ncols * P * SEG;
     finish<O, SEG>(st, L, pid, a.pairs, a.results, 0, prev, a.sat_cap);
   }
   if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {

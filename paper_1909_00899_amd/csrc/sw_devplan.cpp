@@ -109,32 +109,46 @@ bool pick_rowpair_seg(int m, int alpha, int force_seg, int &seg) {
   return false;
 }
 
-// Rows per lane of the device-planned per-pair kernel for queries of up to
-// max_m residues: the forced value, else the autotuner's 16-lane entry, else
-// the smallest compiled one; within the per-wavefront LDS budget.
-bool pick_pair_seg(Prec prec, int alpha, int max_m, const ExecOptions &eo, int &seg) {
-  auto fits = [&](int s) {
-    return pair_direct_has(s) && 16 * s >= max_m &&
-           pair_direct_lds_bytes(prec, s, alpha) <= kPairDirectLds;
+// Shape of the device-planned per-pair kernel for queries of up to max_m
+// residues: profile entry bytes (1 where the matrix fits int8), then rows per
+// lane for 16-lane sub-groups (the forced value, else the autotuner's 16-lane
+// entry, else the smallest compiled one) and for 8-lane sub-groups (int16
+// lanes with byte profiles: the smallest compiled one), within the
+// per-wavefront LDS budget.  Between the two, forced lanes decide, else the
+// smaller modelled VALU work per alignment column: a column costs about 13
+// instructions per row (the recurrence's 11, the profile merge and the
+// end-cell copy) plus ~22 for the scan, the residue and the record test,
+// shared by 8 (16 lanes) or 16 (8 lanes) alignments.
+bool pick_pair_shape(Prec prec, const Scoring &S, int max_m, const ExecOptions &eo, int &seg,
+                     int &lanes, int &es) {
+  es = prec == PREC_I16X2 ? (S.fits_i8 ? 1 : 2) : 4;
+  auto fits = [&](int s, int P) {
+    return pair_direct_has(s, P) && (int64_t)P * s >= max_m &&
+           pair_direct_lds_bytes(prec, s, S.alpha, es) <= kPairDirectLds;
   };
-  if (eo.force_seglen) {
-    if (!fits(eo.force_seglen)) return false;
-    seg = eo.force_seglen;
-    return true;
-  }
-  sw_tune_entry te;
-  if (eo.use_tuning && tune_lookup(SW_TUNE_PAIR, prec, alpha, max_m, te) && te.lanes == 16 &&
-      fits(te.seglen)) {
-    seg = te.seglen;
-    return true;
-  }
-  for (int s : {4, 6, 8, 10, 12, 16}) {
-    if (fits(s)) {
-      seg = s;
-      return true;
+  int s16 = 0, s8 = 0;
+  if (eo.force_lanes != 8) {
+    if (eo.force_seglen) {
+      if (fits(eo.force_seglen, 16)) s16 = eo.force_seglen;
+    } else {
+      sw_tune_entry te;
+      if (eo.use_tuning && tune_lookup(SW_TUNE_PAIR, prec, S.alpha, max_m, te) && te.lanes == 16 &&
+          fits(te.seglen, 16))
+        s16 = te.seglen;
+      for (int s : kPairSegs)
+        if (s16 == 0 && fits(s, 16)) s16 = s;
     }
   }
-  return false;
+  if (eo.force_lanes != 16 && prec == PREC_I16X2 && es == 1) {
+    for (int s : kPair8Segs)
+      if (s8 == 0 && (eo.force_seglen == 0 || s == eo.force_seglen) && fits(s, 8)) s8 = s;
+  }
+  if (s16 == 0 && s8 == 0) return false;
+  bool eight = s16 == 0;
+  if (s16 && s8 && !eo.force_seglen) eight = (13.0 * s8 + 22.0) / 16.0 < (13.0 * s16 + 22.0) / 8.0;
+  seg = eight ? s8 : s16;
+  lanes = eight ? 8 : 16;
+  return true;
 }
 
 }  // namespace
@@ -154,7 +168,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     return SW_OK;
   };
   if (eo.algorithm != SW_ALG_SCAN) return refuse("only the scan algorithm is device-planned");
-  if (planner == 0 && np < kDevPlanMinPairs) return SW_OK;
+  if (planner == 0 && np < kDevPlanMinPairs && eo.force_lanes != 8) return SW_OK;
   if (!b->query_res || !b->query_off || !b->ref_res || !b->ref_off || !b->pair_ref ||
       b->n_queries < 1 || b->n_refs < 1)
     return SW_OK;   // the host path reports the argument error
@@ -163,7 +177,9 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   if (single && eo.force_kernel == 2) return refuse("one query runs in the shared-query kernel");
   if (!single && eo.force_kernel == 1) return refuse("several queries run in the per-pair kernel");
   if (!single && eo.lane_pairing == SW_PAIRING_ROWS) return refuse("row pairs need one query");
-  if (!single && eo.force_lanes && eo.force_lanes != 16) return refuse("per-pair launches use 16 lanes");
+  if (!single && eo.force_lanes && eo.force_lanes != 16 && eo.force_lanes != 8)
+    return refuse("per-pair launches use 8 or 16 lanes");
+  if (single && eo.force_lanes == 8) return refuse("8 lanes only for one query per pair");
   hipStream_t st = C.stream;
   Workspace &ws = C.ws;
   // query 0's offsets, the query set's end and the reference set's end
@@ -194,7 +210,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   if (single && m == 0) return SW_OK;
   if (single && (int64_t)m * S.max_s >= kI32Limit) return refuse("the query may overflow int32");
   const Prec prec = (b->precision == SW_PREC_AUTO && S.fits_i16) ? PREC_I16X2 : PREC_I32;
-  int seg = 0, lanes = 16;
+  int seg = 0, lanes = 16, pes = 0;   // pes: per-pair profile entry bytes
   bool rows = false;   // row pairs: both halves of a lane hold rows of one alignment
   if (single) {
     if (eo.lane_pairing == SW_PAIRING_ROWS) {
@@ -379,7 +395,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     max_m = hm0[kMetaMaxM];
     if (!hm0[kMetaErrResidue] && !hm0[kMetaErrPair] && max_m > 0) {
       const bool ok = (int64_t)max_m * S.max_s < kI32Limit &&
-                      pick_pair_seg(prec, S.alpha, max_m, eo, seg);
+                      pick_pair_shape(prec, S, max_m, eo, seg, lanes, pes);
       if (!ok) {
         // nothing was written to `out`: the host planner takes the batch
         if (planner == 2) {
@@ -389,15 +405,17 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
         }
         return SW_OK;
       }
-      const int slots = 4 * (prec == PREC_I16X2 ? 2 : 1);
+      const int slots = (64 / lanes) * (prec == PREC_I16X2 ? 2 : 1);
       const int ntasks_max = (np + slots - 1) / slots;
       const int grid = std::max(1, std::min(ntasks_max, C.num_cus * 16));
       auto rest = [=]() -> hipError_t {
         hipError_t e = place();
-        if (e == hipSuccess) e = launch_pair_direct(prec, seg, a, grid, st);
+        if (e == hipSuccess) e = launch_pair_direct(prec, seg, lanes, pes, a, grid, st);
         return e;
       };
-      if ((rc = run({0xD2D2, (uint64_t)seg, (uint64_t)grid}, rest, true))) return rc;
+      if ((rc = run({0xD2D2, (uint64_t)seg, (uint64_t)lanes, (uint64_t)pes, (uint64_t)grid}, rest,
+                    true)))
+        return rc;
     }
     handled = true;
   }
@@ -477,7 +495,10 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     stats->n_launches = (seg > 0 ? 1 : 0) + es.launches;
     stats->columns = (int64_t)hs[0];
     stats->record_events = (int64_t)hs[2];
-    stats->lanes_used[lanes == 16 ? 0 : (lanes == 32 ? 1 : 2)] = hm[kMetaValid];
+    if (lanes == 8)
+      stats->lanes8 = hm[kMetaValid];
+    else
+      stats->lanes_used[lanes == 16 ? 0 : (lanes == 32 ? 1 : 2)] = hm[kMetaValid];
     stats->seglen_max = seg;
     stats->prep_ms = 0;
     stats->plan_ms = es.plan_ms;

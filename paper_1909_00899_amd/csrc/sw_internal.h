@@ -161,9 +161,12 @@ hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t 
 
 // Device-planned per-pair kernel: four 16-lane sub-groups per wavefront,
 // `seg` rows per lane (16*seg query rows at most), profiles per task.
-bool pair_direct_has(int seg);
-size_t pair_direct_lds_bytes(Prec prec, int seg, int alpha);
-hipError_t launch_pair_direct(Prec prec, int seg, const KArgs &a, int grid, hipStream_t st);
+// lanes 8: eight sub-groups of eight lanes (int16 lanes and byte profiles
+// only).  es: profile entry bytes, 1 (scores within int8) or the lane type's.
+bool pair_direct_has(int seg, int lanes);
+size_t pair_direct_lds_bytes(Prec prec, int seg, int alpha, int es);
+hipError_t launch_pair_direct(Prec prec, int seg, int lanes, int es, const KArgs &a, int grid,
+                              hipStream_t st);
 
 // Host-planned per-pair kernel in the row-pair layout (int16 only): one
 // alignment per sub-group of `lanes` (16, 32, 64) lanes (task slot

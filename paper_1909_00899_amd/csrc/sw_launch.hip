@@ -18,7 +18,9 @@ hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st
 hipError_t launch_direct_i32(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_rowpair_i16(int seg, bool lds_records, const KArgs &a, int grid,
                               hipStream_t st, size_t lds);
-hipError_t launch_pair_direct_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
+hipError_t launch_pair_direct_i16(int seg, int es, const KArgs &a, int grid, hipStream_t st,
+                                  size_t lds);
+hipError_t launch_pair_direct8_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_pair_direct_i32(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds);
 hipError_t launch_pair_rowpair_i16(int seg, int lanes, bool chunked, const KArgs &a, int grid,
                                    hipStream_t st, size_t lds);
@@ -310,19 +312,34 @@ hipError_t launch_plan_count(int n_pairs, const int64_t *qoff, int n_queries, in
   return hipGetLastError();
 }
 
-bool pair_direct_has(int seg) {
+bool pair_direct_has(int seg, int lanes) {
+  if (lanes == 8) {
+    for (int v : kPair8Segs)
+      if (v == seg) return true;
+    return false;
+  }
+  if (lanes != 16) return false;
   for (int v : kPairSegs)
     if (v == seg) return true;
   return false;
 }
 
-size_t pair_direct_lds_bytes(Prec prec, int seg, int alpha) { return pair_lds_bytes(prec, seg, alpha); }
+size_t pair_direct_lds_bytes(Prec prec, int seg, int alpha, int es) {
+  const int halves = prec == PREC_I16X2 ? 2 : 1;
+  return matrix_lds_bytes(alpha) + (size_t)dev::pair_region_bytes(seg, alpha, halves, es);
+}
 
-hipError_t launch_pair_direct(Prec prec, int seg, const KArgs &a, int grid, hipStream_t st) {
-  if (!pair_direct_has(seg) || a.order == nullptr || a.plan_meta == nullptr || a.ref_res == nullptr)
+hipError_t launch_pair_direct(Prec prec, int seg, int lanes, int es, const KArgs &a, int grid,
+                              hipStream_t st) {
+  if (!pair_direct_has(seg, lanes) || a.order == nullptr || a.plan_meta == nullptr ||
+      a.ref_res == nullptr)
     return hipErrorInvalidValue;
-  const size_t lds = pair_direct_lds_bytes(prec, seg, a.alpha);
-  if (prec == PREC_I16X2) return launch_pair_direct_i16(seg, a, grid, st, lds);
+  const size_t lds = pair_direct_lds_bytes(prec, seg, a.alpha, es);
+  if (prec == PREC_I16X2) {
+    if (lanes == 8) return es == 1 ? launch_pair_direct8_i16(seg, a, grid, st, lds) : hipErrorInvalidValue;
+    return launch_pair_direct_i16(seg, es, a, grid, st, lds);
+  }
+  if (lanes != 16 || es != 4) return hipErrorInvalidValue;
   return launch_pair_direct_i32(seg, a, grid, st, lds);
 }
 

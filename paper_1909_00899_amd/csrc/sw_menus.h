@@ -26,4 +26,11 @@ constexpr int kNumDirectShapes = sizeof(kDirectShapes) / sizeof(kDirectShapes[0]
 constexpr int kPairSegs[] = {4, 6, 8, 10, 12, 16};
 constexpr int kNumPairSegs = sizeof(kPairSegs) / sizeof(kPairSegs[0]);
 
+// Device-planned per-pair kernel with eight-lane sub-groups (int16 lanes, byte
+// profiles): rows per lane compiled, for queries of up to 64, 80, 104, 128
+// and 152 residues (common short-read lengths fit with little padding; more
+// rows per lane would spill registers).
+constexpr int kPair8Segs[] = {8, 10, 13, 16, 19};
+constexpr int kNumPair8Segs = sizeof(kPair8Segs) / sizeof(kPair8Segs[0]);
+
 }  // namespace swk

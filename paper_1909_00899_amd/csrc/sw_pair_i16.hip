@@ -34,9 +34,9 @@ hipError_t launch_s(int seg, int pmax, const KArgs &a, int grid, hipStream_t st,
   }
   return hipErrorInvalidValue;
 }
-template <int SEG>
+template <int SEG, int ES>
 hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
-  auto k = dev::pair_direct_kernel<O, SEG>;
+  auto k = dev::pair_direct_kernel<O, SEG, 16, ES>;
   hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(kWave), lds, st, a);
   return hipGetLastError();
@@ -78,14 +78,26 @@ hipError_t launch_pair_rowpair_i16(int seg, int lanes, bool chunked, const KArgs
                  : launch_rpp<false>(seg, lanes, a, grid, st, lds);
 }
 
-hipError_t launch_pair_direct_i16(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds) {
-  switch (seg) {
-    case 4: return launch_d<4>(a, grid, st, lds);
-    case 6: return launch_d<6>(a, grid, st, lds);
-    case 8: return launch_d<8>(a, grid, st, lds);
-    case 10: return launch_d<10>(a, grid, st, lds);
-    case 12: return launch_d<12>(a, grid, st, lds);
-    case 16: return launch_d<16>(a, grid, st, lds);
+hipError_t launch_pair_direct_i16(int seg, int es, const KArgs &a, int grid, hipStream_t st,
+                                  size_t lds) {
+  if (es == 1) {
+    switch (seg) {
+      case 4: return launch_d<4, 1>(a, grid, st, lds);
+      case 6: return launch_d<6, 1>(a, grid, st, lds);
+      case 8: return launch_d<8, 1>(a, grid, st, lds);
+      case 10: return launch_d<10, 1>(a, grid, st, lds);
+      case 12: return launch_d<12, 1>(a, grid, st, lds);
+      case 16: return launch_d<16, 1>(a, grid, st, lds);
+    }
+  } else if (es == 2) {
+    switch (seg) {
+      case 4: return launch_d<4, 2>(a, grid, st, lds);
+      case 6: return launch_d<6, 2>(a, grid, st, lds);
+      case 8: return launch_d<8, 2>(a, grid, st, lds);
+      case 10: return launch_d<10, 2>(a, grid, st, lds);
+      case 12: return launch_d<12, 2>(a, grid, st, lds);
+      case 16: return launch_d<16, 2>(a, grid, st, lds);
+    }
   }
   return hipErrorInvalidValue;
 }

@@ -36,7 +36,7 @@ hipError_t launch_s(int seg, int pmax, const KArgs &a, int grid, hipStream_t st,
 }
 template <int SEG>
 hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
-  auto k = dev::pair_direct_kernel<O, SEG>;
+  auto k = dev::pair_direct_kernel<O, SEG, 16, 4>;
   hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(kWave), lds, st, a);
   return hipGetLastError();

@@ -198,13 +198,15 @@ int prepare_scoring(const sw_scoring *sc, Scoring &out) {
   out.go = sc->gap_open;
   out.ge = std::min(sc->gap_extend, sc->gap_open);
   int mx = 0;
-  bool fits16 = out.go <= 32767;
+  bool fits16 = out.go <= 32767, fits8 = true;
   for (int v : out.M) {
     mx = std::max(mx, v);
     if (v < -32767 || v > 32767) fits16 = false;
+    if (v < -128 || v > 127) fits8 = false;
   }
   out.max_s = mx;
   out.fits_i16 = fits16;
+  out.fits_i8 = fits8;
   return SW_OK;
 }
 

@@ -41,6 +41,7 @@ struct Scoring {
   int go = 0, ge = 0;   // ge already min(ge, go)
   int max_s = 0;        // max(0, max entry)
   bool fits_i16 = false;
+  bool fits_i8 = false;  // every entry in [-128, 127]: byte profile entries
 };
 int prepare_scoring(const sw_scoring *sc, Scoring &out);
 

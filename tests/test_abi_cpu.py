@@ -79,7 +79,7 @@ def test_batch_rejects_bad_options(lib):
     b.n_pairs = 0
     assert lib.sw_align_batch(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data) == api.SW_OK
     opt = api.Options()
-    opt.force_lanes = 8
+    opt.force_lanes = 12
     b.n_pairs = 1
     assert lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
                                  out.ctypes.data, None) == api.SW_EINVAL

@@ -287,8 +287,13 @@ def test_dna_pairs_device_planned():
     w = W.dna_pairs(n_pairs=60000)
     want = oracle_batch(w)
     got = _run(w, planner=2)
-    assert got.stats["planner_used"] == 2 and got.stats["lanes_used"][0] == w.n_pairs
+    # 150-residue reads: 8-lane sub-groups of 19 rows per lane model less work
+    assert got.stats["planner_used"] == 2 and got.stats["lanes8"] == w.n_pairs
+    assert got.stats["seglen_max"] == 19
     assert_same(got.results, want, "dna pairs, device planner")
+    g16 = _run(w, planner=2, force_lanes=16)
+    assert g16.stats["lanes_used"][0] == w.n_pairs and g16.stats["lanes8"] == 0
+    assert (g16.results == got.results).all()
     assert got.stats["cells"] == w.cells()
     auto = _run(w)
     assert auto.stats["planner_used"] == 2
@@ -369,3 +374,95 @@ def test_per_pair_graph_replays_match_eager():
         x = torch.randn(1 << 20, device="cuda")
         (x * 2).sum().item()
     assert hits >= 6          # two graphs per call after the first
+
+
+# ---------------------------------------------------------------- eight-lane sub-groups
+
+def _nonempty(w):
+    m = np.diff(w.query_off)[w.pair_query]
+    n = np.diff(w.ref_off)[w.pair_ref]
+    return int(((m > 0) & (n > 0)).sum())
+
+
+@pytest.mark.parametrize("seg", [8, 10, 13, 16, 19])
+@pytest.mark.parametrize("alpha", [4, 7])
+def test_eight_lane_sub_groups_every_seglen(seg, alpha):
+    """Sixteen alignments per wavefront, queries up to 8*seg residues (some
+    empty), references of every length mod 4 (some empty)."""
+    w = _per_pair(900 + seg + alpha, 700, alpha, (1, 8 * seg), (0, 400), zero_every=11)
+    want = oracle_batch(w)
+    got = _run(w, planner=2, force_lanes=8, force_seglen=seg)
+    # pairs with an empty side never reach the kernel
+    assert got.stats["lanes8"] == _nonempty(w) and got.stats["seglen_max"] == seg
+    assert_same(got.results, want, "8 lanes seg=%d alpha=%d" % (seg, alpha))
+
+
+def test_eight_lane_sub_groups_protein_and_chosen_shape():
+    # 20 letters: the byte profile of 8 rows per lane fits the LDS budget
+    w = _per_pair(930, 500, 20, (1, 64), (1, 300), zero_every=9)
+    want = oracle_batch(w)
+    got = _run(w, planner=2, force_lanes=8)
+    assert got.stats["lanes8"] == _nonempty(w) and got.stats["seglen_max"] == 8
+    assert_same(got.results, want, "8 lanes protein")
+    # unforced: short DNA queries go to eight-lane sub-groups
+    w4 = _per_pair(931, 900, 4, (100, 150), (100, 600))
+    auto = _run(w4, planner=2)
+    assert auto.stats["lanes8"] == w4.n_pairs
+    assert_same(auto.results, oracle_batch(w4), "auto")
+
+
+def test_byte_and_16_bit_profiles_agree():
+    """Scores within int8 use byte profile entries (16-lane and 8-lane
+    sub-groups); a matrix entry outside int8 keeps 16-bit entries and refuses
+    8 lanes."""
+    w = _per_pair(940, 600, 4, (1, 150), (1, 500), zero_every=7)
+    M2 = w.matrix.copy()
+    M2[0, 0] = 200                        # outside int8
+    w2 = W.Workload("wide", w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_query,
+                    w.pair_ref, M2, w.gap_open, w.gap_extend)
+    for ww in (w, w2):
+        want = oracle_batch(ww)
+        got = _run(ww, planner=2, force_lanes=16)
+        assert_same(got.results, want, "16 lanes M00=%d" % ww.matrix[0, 0])
+    with pytest.raises(api.SwError) as e:
+        _run(w2, planner=2, force_lanes=8)
+    assert e.value.code == api.SW_EINVAL
+    auto2 = _run(w2, planner=2)
+    assert auto2.stats["lanes8"] == 0
+    assert_same(auto2.results, oracle_batch(w2), "auto, wide matrix")
+
+
+def test_eight_lane_reruns_and_refusals():
+    w = _per_pair(950, 600, 4, (20, 150), (10, 500))
+    want = oracle_batch(w)
+    # random DNA pairs score about 6: a cap of 7 sends a good share to int32
+    got = _run(w, planner=2, force_lanes=8, int16_cap=7)
+    assert_same(got.results, want, "cap=7")
+    assert got.stats["n_rerun"] == int((want[:, 0] >= 7).sum()) > 0
+    # int32 lanes, queries longer than 152 residues, one query, host planner
+    with pytest.raises(api.SwError):
+        _run(w, planner=2, force_lanes=8, precision=api.SW_PREC_I32)
+    wl = _per_pair(951, 100, 4, (150, 200), (10, 100))
+    with pytest.raises(api.SwError):
+        _run(wl, planner=2, force_lanes=8)
+    w1 = _one_query(952, 100, 300, (1, 200), alpha=4, matrix=W.dna_matrix(), go=6, ge=1)
+    with pytest.raises(api.SwError):
+        _run(w1, planner=2, force_lanes=8)
+    with pytest.raises(api.SwError):
+        _run(w, planner=1, force_lanes=8)
+
+
+def test_eight_lane_graph_replays_match_eager():
+    import torch
+    w = _per_pair(960, 5000, 4, (140, 152), (300, 600))
+    want = oracle_batch(w)
+    args, pq = _device(w)
+    eager = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, pair_query=pq,
+                               planner=2, force_lanes=8)
+    assert_same(eager.results, want, "eager")
+    for rep in range(3):
+        g = api.sw_align_batch(*args, w.matrix, w.gap_open, w.gap_extend, pair_query=pq,
+                               planner=2, force_lanes=8, use_graph=1)
+        assert (g.results == eager.results).all(), rep
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
