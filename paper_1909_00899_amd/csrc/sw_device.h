@@ -101,9 +101,10 @@ __device__ __forceinline__ uint32_t dpp(uint32_t x) {
 }
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
 constexpr int kWaveShr1 = 0x138, kRowBcast15 = 0x142, kRowBcast31 = 0x143;
-// quad_perm [1,0,3,2] and [2,3,0,1] (lane xor 1, xor 2), and the mirror of
-// each eight-lane half of a row (lane xor 7 inside the half)
-constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowHalfMirror = 0x141;
+// quad_perm [1,0,3,2] and [2,3,0,1] (lane xor 1, xor 2), the mirror of each
+// eight-lane half of a row (lane xor 7 inside the half) and of the whole row
+// (lane xor 15)
+constexpr int kQuadXor1 = 0xB1, kQuadXor2 = 0x4E, kRowHalfMirror = 0x141, kRowMirror = 0x140;
 
 // ---------------------------------------------------------------- lane layout
 
@@ -339,34 +340,44 @@ __device__ __forceinline__ void record(State<SEG> &st, uint32_t cmax, int i) {
   }
 }
 
-// record() for int16 lanes with the end-cell copy in LDS instead of VGPRs:
+// record() for int16 lanes with the end-cell record in LDS instead of VGPRs:
 // a lane whose low (high) half improves stores the low (high) halves of the
-// column's H with 16-bit LDS stores (row j at snap + 256*j), which costs LDS
-// issue slots instead of one VALU select per row.
+// column's H with 16-bit LDS stores (row j at snap + 256*j), the column index
+// (row SEG for the low half, SEG+1 for the high half) and the column maximum
+// (row SEG+2, 16 bits per half).  The stores take LDS issue slots instead of
+// a VALU select per row and the per-half column and maximum selects.
+constexpr int kRecRows = 3;   // rows after the copy: column (low, high), maximum
+
 template <int SEG>
 __device__ __forceinline__ void record_lds(State<SEG> &st, uint32_t cmax, int i, uint32_t snap) {
   using O = OpsI16;
   const uint32_t nb = O::vmax(st.G, cmax);
   if (__any(nb != st.G)) {
     ++st.events;
-    uint32_t m = gain_mask<O>(nb, st.G);
-    asm("" : "+v"(m));
-    if (m & 0xffffu) {
+    const uint32_t g = st.G;
+    st.G = nb;
+    if ((unsigned short)nb != (unsigned short)g) {
 #pragma unroll
       for (int j = 0; j < SEG; ++j) *(unsigned short *)(smem + snap + 256 * j) = (unsigned short)st.H[j];
+      *(int *)(smem + snap + 256 * SEG) = i;
+      *(unsigned short *)(smem + snap + 256 * (SEG + 2)) = (unsigned short)nb;
     }
-    if (m >> 16) {
+    if ((nb >> 16) != (g >> 16)) {
 #pragma unroll
       for (int j = 0; j < SEG; ++j)
         *(unsigned short *)(smem + snap + 256 * j + 2) = (unsigned short)(st.H[j] >> 16);
+      *(int *)(smem + snap + 256 * (SEG + 1)) = i;
+      *(unsigned short *)(smem + snap + 256 * (SEG + 2) + 2) = (unsigned short)(nb >> 16);
     }
-    const uint32_t mlo = (uint32_t)((int)(m << 16) >> 16);
-    const uint32_t mhi = (uint32_t)((int)m >> 16);
-    st.rc[0] = (int)(((uint32_t)i & mlo) | ((uint32_t)st.rc[0] & ~mlo));
-    st.rc[1] = (int)(((uint32_t)i & mhi) | ((uint32_t)st.rc[1] & ~mhi));
-    st.G = nb;
-    st.S = (nb & m) | (st.S & ~m);
   }
+}
+
+// No record yet: columns INT_MAX, maxima 0 (this lane's words only).
+template <int SEG>
+__device__ __forceinline__ void record_lds_reset(uint32_t snap) {
+  *(int *)(smem + snap + 256 * SEG) = 0x7fffffff;
+  *(int *)(smem + snap + 256 * (SEG + 1)) = 0x7fffffff;
+  *(uint32_t *)(smem + snap + 256 * (SEG + 2)) = 0u;
 }
 
 // Raises every lane's record threshold to the largest threshold of its
@@ -375,12 +386,14 @@ __device__ __forceinline__ void record_lds(State<SEG> &st, uint32_t cmax, int i,
 // value read back for every lane of the sub-group.
 template <class O, int SEG, int PMAX>
 __device__ __forceinline__ void share_threshold(State<SEG> &st, const LaneCtx &L) {
-  if constexpr (PMAX == 8) {
-    // butterfly over the eight lanes: every lane ends with the maximum
+  if constexpr (PMAX <= 16) {
+    // butterfly over the eight or sixteen lanes: every lane ends with the maximum
     uint32_t T = st.G;
     T = O::vmax(T, dpp<kQuadXor1>(T));
     T = O::vmax(T, dpp<kQuadXor2>(T));
-    st.G = O::vmax(T, dpp<kRowHalfMirror>(T));
+    T = O::vmax(T, dpp<kRowHalfMirror>(T));
+    if constexpr (PMAX == 16) T = O::vmax(T, dpp<kRowMirror>(T));
+    st.G = T;
     return;
   }
   uint32_t T = st.G;
@@ -1095,21 +1108,16 @@ __device__ __forceinline__ void rp_column(State<SEG> &st, const RpParams &pr, co
   else record<O, SEG>(st, cmax, i);
 }
 
-// Record thresholds raised to the largest of the sub-group (both halves).
+// Record thresholds raised to the largest of the sub-group (both halves):
+// a butterfly over the 16 lanes, every lane ends with the maximum.
 template <int SEG>
-__device__ __forceinline__ void rp_share_threshold(State<SEG> &st, int lane) {
+__device__ __forceinline__ void rp_share_threshold(State<SEG> &st, int) {
   using O = OpsI16;
   uint32_t T = rp_both(st.G);
-  T = O::vmax(T, dpp<kRowShr1>(T));
-  T = O::vmax(T, dpp<kRowShr2>(T));
-  T = O::vmax(T, dpp<kRowShr4>(T));
-  T = O::vmax(T, dpp<kRowShr8>(T));
-  const uint32_t t15 = (uint32_t)__builtin_amdgcn_readlane((int)T, 15);
-  const uint32_t t31 = (uint32_t)__builtin_amdgcn_readlane((int)T, 31);
-  const uint32_t t47 = (uint32_t)__builtin_amdgcn_readlane((int)T, 47);
-  const uint32_t t63 = (uint32_t)__builtin_amdgcn_readlane((int)T, 63);
-  const int row = lane >> 4;
-  st.G = row == 0 ? t15 : (row == 1 ? t31 : (row == 2 ? t47 : t63));
+  T = O::vmax(T, dpp<kQuadXor1>(T));
+  T = O::vmax(T, dpp<kQuadXor2>(T));
+  T = O::vmax(T, dpp<kRowHalfMirror>(T));
+  st.G = O::vmax(T, dpp<kRowMirror>(T));
 }
 
 // Record thresholds raised to the largest of the P-lane sub-group (both halves).
@@ -1175,7 +1183,15 @@ __device__ __forceinline__ void rp_finish(const State<SEG> &st, int lane, int pi
   int s = 0, c = 0x7fffffff, r = 0x7fffffff;
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
-    const int sh = st.rc[h] != 0x7fffffff ? O::get(st.S, h) : 0;
+    int rch, sh;
+    if constexpr (LREC) {
+      rch = *(const int *)(smem + snap + 256 * (SEG + h));
+      sh = (int)*(const short *)(smem + snap + 256 * (SEG + 2) + 2 * h);
+    } else {
+      rch = st.rc[h];
+      sh = O::get(st.S, h);
+    }
+    if (rch == 0x7fffffff) sh = 0;
     if (sh > 0) {
       int jj = SEG - 1;
 #pragma unroll
@@ -1185,7 +1201,7 @@ __device__ __forceinline__ void rp_finish(const State<SEG> &st, int lane, int pi
         else v = O::get(st.snap[j], h);
         if (v >= sh) jj = j;
       }
-      const int ch = st.rc[h], rh = (2 * l + h) * SEG + jj;
+      const int ch = rch, rh = (2 * l + h) * SEG + jj;
       if (s <= 0 || better(sh, ch, rh, s, c, r)) { s = sh; c = ch; r = rh; }
     }
   }
@@ -1206,10 +1222,13 @@ __device__ __forceinline__ void rp_finish(const State<SEG> &st, int lane, int pi
 // Device-planned shared-query kernel in the row-pair layout: four
 // alignments per wavefront (one per 16-lane sub-group); task t is entries
 // [4t, 4t+4) of the longest-first order.
-// LREC: end-cell copies in LDS ([8 wavefronts][SEG][64 lanes] words after the
-// two profile copies) instead of VGPRs.
+// LREC: end-cell records in LDS ([16 wavefronts][SEG + kRecRows][64 lanes]
+// words after the two profile copies) instead of VGPRs, one workgroup of 16
+// wavefronts per CU sharing one profile; else 8 wavefronts per workgroup.
+__host__ __device__ constexpr int rowpair_waves_per_group(bool lrec) { return lrec ? 16 : 8; }
+
 template <int SEG, bool LREC>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(rowpair_waves_per_group(LREC) * 64) __attribute__((amdgpu_waves_per_eu(4)))
 void shared_rowpair_kernel(KArgs a) {
   if (a.plan_meta[kMetaErrResidue] | a.plan_meta[kMetaErrPair]) return;
   stage_matrix(a);
@@ -1219,7 +1238,7 @@ void shared_rowpair_kernel(KArgs a) {
   __syncthreads();
   const int lane = (int)(threadIdx.x & 63);
   const uint32_t snap = off + 2 * rp_copy_bytes(SEG, a.alpha) +
-                        (uint32_t)(threadIdx.x >> 6) * (SEG * 256) + (uint32_t)lane * 4;
+                        (uint32_t)(threadIdx.x >> 6) * ((SEG + kRecRows) * 256) + (uint32_t)lane * 4;
   const int sg = lane >> 4;
   const int nvalid = a.plan_meta[kMetaValid];
   const int ntasks = (nvalid + 3) / 4;
@@ -1244,6 +1263,7 @@ void shared_rowpair_kernel(KArgs a) {
     const int ncols = (nmax + kBlock - 1) / kBlock * kBlock;
     State<SEG> st;
     state_reset(st, 0u);
+    if constexpr (LREC) record_lds_reset<SEG>(snap);
     const DirectSrc src{a.ref_res + roff, a.ref_res + roff, n, 0, sentw};
     rp_run_columns<SEG, LREC>(st, lane, pr, lane_base, src, ncols, snap);
     cols += (unsigned long long)ncols;

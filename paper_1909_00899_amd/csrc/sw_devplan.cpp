@@ -371,8 +371,11 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   if (single) {
     const int slots = rows ? kWave / 16 : (kWave / lanes) * (prec == PREC_I16X2 ? 2 : 1);
     const int ntasks_max = (np + slots - 1) / slots;
-    const int grid = std::max(1, std::min((ntasks_max + kWavesPerGroup - 1) / kWavesPerGroup,
-                                          C.num_cus * 2));
+    // row pairs: wavefronts wanted (the launcher sizes its workgroups);
+    // otherwise workgroups of kWavesPerGroup wavefronts
+    const int grid = rows ? std::max(1, std::min(ntasks_max, C.num_cus * 16))
+                          : std::max(1, std::min((ntasks_max + kWavesPerGroup - 1) / kWavesPerGroup,
+                                                 C.num_cus * 2));
     auto all = [=]() -> hipError_t {
       hipError_t e = prep();
       if (e == hipSuccess) e = place();

@@ -154,7 +154,7 @@ hipError_t launch_shared_direct(Prec prec, int seg, int lanes, const KArgs &a, i
 
 // Device-planned shared-query kernel in the row-pair layout (int16 only):
 // 16 lanes per alignment, each lane's two halves holding two row segments of
-// `seg` rows (32*seg query rows).
+// `seg` rows (32*seg query rows).  grid: wavefronts wanted.
 bool shared_rowpair_has(int seg);
 size_t shared_rowpair_lds_bytes(int seg, int alpha);
 hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st);

@@ -388,10 +388,11 @@ size_t shared_rowpair_lds_bytes(int seg, int alpha) {
   return (matrix_lds_bytes(alpha) + 255) / 256 * 256 + 2 * (size_t)dev::rp_copy_bytes(seg, alpha);
 }
 
-// With the end-cell copies in LDS as well, while two workgroups still share a
-// CU (160 KB of LDS).
+// With the end-cell records in LDS as well: one workgroup of 16 wavefronts
+// per CU (160 KB of LDS).
 static size_t rowpair_lds_records_bytes(int seg, int alpha) {
-  return shared_rowpair_lds_bytes(seg, alpha) + (size_t)kWavesPerGroup * seg * 256;
+  return shared_rowpair_lds_bytes(seg, alpha) +
+         (size_t)dev::rowpair_waves_per_group(true) * (seg + dev::kRecRows) * 256;
 }
 
 hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st) {
@@ -399,7 +400,7 @@ hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t 
       a.ref_res == nullptr)
     return hipErrorInvalidValue;
   const size_t with = rowpair_lds_records_bytes(seg, a.alpha);
-  if (with <= 80 * 1024) return launch_rowpair_i16(seg, true, a, grid, st, with);
+  if (with <= 160 * 1024) return launch_rowpair_i16(seg, true, a, grid, st, with);
   return launch_rowpair_i16(seg, false, a, grid, st, shared_rowpair_lds_bytes(seg, a.alpha));
 }
 

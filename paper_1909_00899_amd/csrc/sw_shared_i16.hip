@@ -37,9 +37,11 @@ hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
 }
 template <int SEG, bool LREC>
 hipError_t launch_rp(const KArgs &a, int grid, hipStream_t st, size_t lds) {
+  // grid: wavefronts wanted
   auto k = dev::shared_rowpair_kernel<SEG, LREC>;
+  constexpr int wpg = dev::rowpair_waves_per_group(LREC);
   hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(k, dim3(grid), dim3(kWavesPerGroup * kWave), lds, st, a);
+  hipLaunchKernelGGL(k, dim3((grid + wpg - 1) / wpg), dim3(wpg * kWave), lds, st, a);
   return hipGetLastError();
 }
 
