@@ -16,6 +16,9 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libswscan.so")
+# the VALU issue-rate probe (a measurement aid) is a library of its own
+PROBE_SRC = "valu_probe.hip"
+PROBE_LIB = os.path.join(HERE, "libswprobe.so")
 ARCH = "gfx950"
 
 SOURCES = ["sw_shared_i16.hip", "sw_shared_i32.hip", "sw_pair_i16.hip", "sw_pair8_i16.hip",
@@ -52,16 +55,22 @@ def build(incremental: bool = False, jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hdr = _headers_mtime()
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    jobs = jobs or min(len(srcs) + 1, max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, incremental, hdr), srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
+        objs = list(ex.map(lambda s: _compile(s, incremental, hdr), srcs + [PROBE_SRC]))
+    _link(objs[-1:], PROBE_LIB, [])
+    objs = objs[:-1]
+    _link(objs, LIB, ["-lpthread"])
+    return LIB
+
+
+def _link(objs, lib, extra):
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + extra
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), res.stderr))
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
 
 
 if __name__ == "__main__":

@@ -33,6 +33,17 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), n
 
 
+def test_valu_probe_library_loads(lib):
+    # the measurement aid is its own library; built beside libswscan.so
+    from paper_1909_00899_amd import valu_probe
+    probe = ctypes.CDLL(os.path.join(os.path.dirname(valu_probe.__file__), "libswprobe.so"))
+    assert hasattr(probe, "swprobe_valu")
+    probe.swprobe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    out = ctypes.c_double(1.0)
+    assert probe.swprobe_valu(0, 1, ctypes.byref(out)) != 0     # bad grid: rejected on the host
+    assert out.value == 1.0
+
+
 def test_strerror(lib):
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert lib.sw_strerror(code)

@@ -1,0 +1,13 @@
+"""The VALU issue-rate probe runs and reports a rate of the right order: at
+most the int16x2 rate derived from unit counts and clock (plus clock slack),
+and not far below it."""
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_valu_probe_rate():
+    from paper_1909_00899_amd import valu_probe
+    derived = 256 * 4 * 16 * 2.4e9 * 2
+    r = valu_probe.measure(grid=2048, trips=2000)
+    assert 0.3 * derived < r < 1.1 * derived, r / derived
