@@ -1038,6 +1038,14 @@ struct RpShared {
     return *(const uint32_t *)(smem + base + j * 64);
   }
 };
+// RpWords: words already read into registers (the next column's profile is
+// read during the current column, before its end-cell record stores, which
+// the compiler cannot move loads across).
+template <int SEG>
+struct RpWords {
+  const uint32_t (&w)[SEG];
+  __device__ __forceinline__ uint32_t operator()(int j) const { return w[j]; }
+};
 // RpPairs: the pair-score table (word (qa*(alpha+1) + qb)*(alpha+1) + r holds
 // S(qa, r) and S(qb, r)); qq[j] = byte address of this lane's row pair j,
 // c4 = 4 * the column's residue.
@@ -1152,18 +1160,39 @@ __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const R
   uint32_t ev_shared = st.events;
   uint32_t rc = src.get(0).x;
   uint32_t rn = src.get(1).x;
+  // byte k of a residue word alone (a byte permute; written as shifts and
+  // masks the compiler spends two instructions on it), then one shift-add
+  auto base = [&](uint32_t r, int k) {
+    return lane_base + __builtin_amdgcn_perm(0u, r, 0x0c0c0c00u | (uint32_t)k) * rp_cstride(SEG);
+  };
+  // profile words of the current column, read one column ahead
+  uint32_t pw[SEG];
+  {
+    const RpShared p0{base(rc, 0)};
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) pw[j] = p0(j);
+  }
   for (int b = 0; b < nblk; ++b) {
     const uint32_t r = rc;
     rc = rn;
     rn = src.get(b + 2).x;
 #pragma unroll
     for (int k = 0; k < kBlock; ++k) {
-      // byte k of the word alone (a byte permute; written as shifts and masks
-      // the compiler spends two instructions on it), then one shift-add
-      const uint32_t c = __builtin_amdgcn_perm(0u, r, 0x0c0c0c00u | (uint32_t)k);
+      // the next column's residue: this word's next byte, or the next word's
+      // first (past the last column: a sentinel or padding code, still a
+      // valid profile row)
+      const RpShared pn{k + 1 < kBlock ? base(r, k + 1) : base(rc, 0)};
+      uint32_t nw[SEG];
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) nw[j] = pn(j);
+      // keep the reads here, a whole column ahead of their use (the
+      // scheduler would otherwise sink them to the end of the column)
+      __builtin_amdgcn_sched_barrier(0);
       uint32_t ho, fo;
-      rp_column<SEG, false, RpShared, 16, LREC>(st, pr, RpShared{lane_base + c * rp_cstride(SEG)},
-                                               b * kBlock + k, 0u, 0u, ho, fo, nullptr, snap);
+      rp_column<SEG, false, RpWords<SEG>, 16, LREC>(st, pr, RpWords<SEG>{pw}, b * kBlock + k, 0u, 0u,
+                                                   ho, fo, nullptr, snap);
+#pragma unroll
+      for (int j = 0; j < SEG; ++j) pw[j] = nw[j];
     }
     if (st.events != ev_shared) {
       rp_share_threshold<SEG>(st, lane);
