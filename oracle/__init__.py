@@ -26,9 +26,13 @@ adopted where the paper is silent are stated in each docstring:
 * end coordinates are those of the H_diag cell achieving the maximum, smallest
   ref_end first, then smallest query_end; score 0 gives (-1, -1).
 
+Start cells (``start_cell``, ``start_batch``): the end cell of the same
+recurrence on the reversed prefixes that end at the reported end cell.
+
 Parity status: pinned (brute-force enumeration of all local alignments on tiny
 inputs, a hand-computed worked example, closed-form special cases and
-invariants; see ``tests/test_oracle_pins.py``).
+invariants; start cells by brute-force enumeration of the optimal alignments
+ending at the end cell; see ``tests/test_oracle_pins.py``).
 """
 from __future__ import annotations
 
@@ -174,3 +178,67 @@ def gotoh_py(query: Sequence[int], ref: Sequence[int], matrix, gap_open: int,
     if tables:
         return res, hd_cols, h_cols
     return res
+
+
+# ---------------------------------------------------------------- start cells
+
+def start_cell(query, ref, matrix, gap_open: int, gap_extend: int,
+               end: Optional[Tuple[int, int, int]] = None) -> Tuple[int, int]:
+    """Start (query_start, ref_start) of the alignment reported by ``align``.
+
+    Reading (the paper returns only Max; start cells are this library's
+    extension): of all optimal local alignments that end at the reported end
+    cell, the one with the largest ref_start, then the largest query_start.
+    Computed as the end cell of the same recurrence on the reversed prefixes
+    q[0..query_end] and r[0..ref_end]: every optimal alignment inside those
+    prefixes ends at the reported end cell (an earlier end would precede it in
+    the (ref_end, query_end) order), and the smallest reversed end is the
+    largest forward start.  (-1, -1) when the score is 0.
+    """
+    q = _u8(query)
+    r = _u8(ref)
+    s, qe, re_ = align(q, r, matrix, gap_open, gap_extend) if end is None else end
+    if s <= 0:
+        return (-1, -1)
+    s2, qe2, re2 = align(q[:qe + 1][::-1], r[:re_ + 1][::-1], matrix, gap_open, gap_extend)
+    if s2 != s:
+        raise ValueError("end cell does not belong to an optimal alignment of this pair")
+    return (qe - qe2, re_ - re2)
+
+
+def start_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap_open: int,
+                gap_extend: int, ends, pair_query=None,
+                n_threads: Optional[int] = None) -> np.ndarray:
+    """``start_cell`` for every pair of a batch, given the batch's (score,
+    query_end, ref_end) rows; returns an (n_pairs, 2) int64 array of
+    (query_start, ref_start).  The reversed prefixes run through
+    ``align_batch``."""
+    qres = _u8(query_res)
+    rres = _u8(ref_res)
+    qoff = np.asarray(query_off, dtype=np.int64)
+    roff = np.asarray(ref_off, dtype=np.int64)
+    pr = np.asarray(pair_ref, dtype=np.int64)
+    pq = np.zeros_like(pr) if pair_query is None else np.asarray(pair_query, dtype=np.int64)
+    ends = np.asarray(ends, dtype=np.int64)
+    out = np.full((pr.size, 2), -1, dtype=np.int64)
+    live = np.nonzero(ends[:, 0] > 0)[0]
+    if live.size == 0:
+        return out
+    qs, rs = [], []
+    for k in live:
+        qe, re_ = int(ends[k, 1]), int(ends[k, 2])
+        q0, r0 = int(qoff[pq[k]]), int(roff[pr[k]])
+        qs.append(qres[q0:q0 + qe + 1][::-1])
+        rs.append(rres[r0:r0 + re_ + 1][::-1])
+    nqoff = np.zeros(live.size + 1, dtype=np.int64)
+    np.cumsum([x.size for x in qs], out=nqoff[1:])
+    nroff = np.zeros(live.size + 1, dtype=np.int64)
+    np.cumsum([x.size for x in rs], out=nroff[1:])
+    idx = np.arange(live.size, dtype=np.int32)
+    rev = align_batch(np.concatenate(qs), nqoff, np.concatenate(rs), nroff, idx, matrix,
+                      gap_open, gap_extend, pair_query=idx, n_threads=n_threads)
+    if (rev[:, 0] != ends[live, 0]).any():
+        raise ValueError("end cells do not belong to optimal alignments of these pairs")
+    out[live, 0] = ends[live, 1] - rev[:, 1]
+    out[live, 1] = ends[live, 2] - rev[:, 2]
+    return out

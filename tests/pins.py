@@ -72,3 +72,31 @@ def lcs(a, b) -> int:
         for y in range(n):
             T[x + 1][y + 1] = T[x][y] + 1 if a[x] == b[y] else max(T[x][y + 1], T[x + 1][y])
     return T[m][n]
+
+
+def brute_force_start(q, r, M, go: int, ge: int):
+    """(query_start, ref_start) by enumeration: among every chain scoring the
+    optimum and ending at the reported end cell (smallest ref_end, then
+    query_end), the largest ref_start, then the largest query_start; (-1, -1)
+    when the optimum is 0.  Tiny inputs only."""
+    s, qe, re_ = brute_force(q, r, M, go, ge)
+    if s <= 0:
+        return (-1, -1)
+    best = None
+    m, n = len(q), len(r)
+
+    def extend(i0, j0, i, j, score):
+        nonlocal best
+        if (i, j) == (re_, qe) and score == s:
+            if best is None or (i0, j0) > best:
+                best = (i0, j0)
+        for i2 in range(i + 1, n):
+            for j2 in range(j + 1, m):
+                s2 = score + int(M[q[j2]][r[i2]]) - gap_cost(i2 - i - 1, go, ge) \
+                    - gap_cost(j2 - j - 1, go, ge)
+                extend(i0, j0, i2, j2, s2)
+
+    for i in range(n):
+        for j in range(m):
+            extend(i, j, i, j, int(M[q[j]][r[i]]))
+    return (best[1], best[0])

@@ -9,6 +9,7 @@ import oracle
 from paper_1909_00899_amd import api, workloads as W
 
 pytestmark = pytest.mark.gpu
+ROWS_PAIRING = api.SW_PAIRING_ROWS
 
 # (rows per lane, lanes) of the compiled device-planned shapes
 SHAPES = [(4, 16), (8, 16), (12, 16), (16, 16), (12, 32), (16, 32)]
@@ -466,3 +467,72 @@ def test_eight_lane_graph_replays_match_eager():
         assert (g.results == eager.results).all(), rep
         x = torch.randn(1 << 20, device="cuda")
         (x * 2).sum().item()
+
+
+# ---------------------------------------------------------------- gap-to-gap regression family
+
+def _bridge_pairs(shifts=range(0, 48, 5)):
+    """q = X^s A^12 X^k B^12, r = Y^s A^12 Y^k B^12 (X, Y never match anything):
+    for k = 11, 12, 16 the best alignment bridges the middle with a gap in
+    each sequence back to back, so a vertical gap followed directly by a
+    horizontal one decides the score; the prefix s moves the bridge across
+    lane and chunk boundaries."""
+    M = np.full((4, 4), -4, dtype=np.int32)
+    M[0, 0] = M[1, 1] = 5
+    qs, rs = [], []
+    for k in (11, 12, 16):
+        for s in shifts:
+            qs.append(np.array([2] * s + [0] * 12 + [2] * k + [1] * 12, dtype=np.uint8))
+            rs.append(np.array([3] * s + [0] * 12 + [3] * k + [1] * 12, dtype=np.uint8))
+    qoff = np.zeros(len(qs) + 1, dtype=np.int64)
+    np.cumsum([q.size for q in qs], out=qoff[1:])
+    roff = np.zeros(len(rs) + 1, dtype=np.int64)
+    np.cumsum([r.size for r in rs], out=roff[1:])
+    idx = np.arange(len(qs), dtype=np.int32)
+    return W.Workload("bridge", np.concatenate(qs), qoff, np.concatenate(rs), roff, idx, idx.copy(),
+                      M, 11, 1)
+
+
+@pytest.mark.parametrize("kw", [
+    dict(planner=1, force_kernel=2, force_lanes=16, force_seglen=4),
+    dict(planner=1, force_kernel=2, force_lanes=32, force_seglen=4),
+    dict(planner=1, force_kernel=2, force_lanes=64, force_seglen=4),
+    dict(planner=1, force_kernel=2, force_lanes=16, force_seglen=8),
+    dict(planner=1, force_kernel=2, force_lanes=64, force_seglen=8, precision=api.SW_PREC_I32),
+    dict(planner=1, force_kernel=2, lane_pairing=ROWS_PAIRING, force_seglen=4),
+    dict(planner=1, force_kernel=2, lane_pairing=ROWS_PAIRING, force_seglen=8),
+    # device-planned per-pair launches hold the longest query (85) in one chunk
+    dict(planner=2, force_lanes=8, force_seglen=13),
+    dict(planner=2, force_lanes=8, force_seglen=16),
+    dict(planner=2, force_lanes=16, force_seglen=6),
+    dict(planner=2, force_lanes=16, force_seglen=8),
+    dict(planner=1, algorithm=api.SW_ALG_LAZYF, force_lanes=16, force_seglen=4),
+], ids=lambda kw: "-".join("%s%s" % (k[:6], v) for k, v in kw.items()))
+def test_gap_to_gap_family_every_layout(kw):
+    w = _bridge_pairs()
+    want = oracle_batch(w)
+    # the bridge beats the ungapped score for every k (78 vs 76, 76 vs 72, 68 vs 60)
+    assert set(np.unique(want[:, 0])) == {78, 76, 68}
+    got = _run(w, **kw)
+    assert_same(got.results, want, "bridge %s" % kw)
+
+
+def test_gap_to_gap_family_shared_query():
+    """One query, the references of the family: row pairs and direct shapes
+    of the device-planned shared-query kernel."""
+    M = np.full((4, 4), -4, dtype=np.int32)
+    M[0, 0] = M[1, 1] = 5
+    for s in (0, 9, 17, 40):
+        q = np.array([2] * s + [0] * 12 + [2] * 12 + [1] * 12, dtype=np.uint8)
+        refs = [np.array([3] * t + [0] * 12 + [3] * k + [1] * 12, dtype=np.uint8)
+                for k in (11, 12, 16) for t in range(0, 30, 3)]
+        roff = np.zeros(len(refs) + 1, dtype=np.int64)
+        np.cumsum([r.size for r in refs], out=roff[1:])
+        w = W.Workload("bridge1", q, np.array([0, q.size], np.int64), np.concatenate(refs), roff,
+                       None, np.arange(len(refs), dtype=np.int32), M, 11, 1)
+        want = oracle_batch(w)
+        for kw in (dict(lane_pairing=ROWS_PAIRING, force_seglen=4),
+                   dict(lane_pairing=api.SW_PAIRING_ALIGNMENTS, force_lanes=16, force_seglen=4),
+                   dict(lane_pairing=api.SW_PAIRING_ALIGNMENTS, force_lanes=32, force_seglen=12)):
+            got = _run(w, planner=2, **kw)
+            assert_same(got.results, want, "bridge shared s=%d %s" % (s, kw))

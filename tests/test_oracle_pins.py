@@ -248,3 +248,90 @@ def _pins_catch(fn) -> bool:
 def test_pins_catch_planted_mistakes(name):
     assert _pins_catch(oracle.gotoh_py) is False
     assert _pins_catch(_mutant(name)) is True
+
+
+# ---------------------------------------------------------------- start cells
+
+def _start_via(fn, q, r, M, go, ge):
+    """Start cell from an end-cell function ``fn`` applied to the reversed
+    prefixes (the construction ``oracle.start_cell`` uses)."""
+    s, qe, re_ = oracle.align(q, r, M, go, ge)
+    if s <= 0:
+        return (-1, -1)
+    s2, qe2, re2 = fn(list(q[:qe + 1])[::-1], list(r[:re_ + 1])[::-1], M, go, ge)
+    return (qe - qe2, re_ - re2)
+
+
+def test_start_cell_worked_example():
+    # A/A, C against a gap, G/G, T/T: the only alignment scoring 7 starts at (0, 0)
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    M = np.full((4, 4), g["mismatch"], dtype=np.int32)
+    np.fill_diagonal(M, g["match"])
+    assert oracle.start_cell([0, 1, 2, 3], [0, 2, 3], M, 2, 1) == (0, 0)
+    assert pins.brute_force_start([0, 1, 2, 3], [0, 2, 3], M, 2, 1) == (0, 0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_start_cell_brute_force_random(seed):
+    rng = np.random.default_rng(3000 + seed)
+    ties = 0
+    for _ in range(150):
+        q, r, M, go, ge = _case(rng)
+        want = pins.brute_force_start(q, r, M, go, ge)
+        assert oracle.start_cell(q, r, M, go, ge) == want
+        # cases where another optimal start exists make the tie rule matter
+        if want != (-1, -1) and _start_via(_min_start_end, q, r, M, go, ge) != want:
+            ties += 1
+    assert ties > 0
+
+
+def _min_start_end(q, r, M, go, ge):
+    """End cell with the tie going to the LAST maximal H_diag in scan order
+    (a plausible mistake: it yields the smallest start instead of the largest)."""
+    m, n = len(q), len(r)
+    Hprev, E = [0] * m, [0] * m
+    best, bq, br = 0, -1, -1
+    for i in range(n):
+        F, Hcur = 0, [0] * m
+        for j in range(m):
+            hd = (Hprev[j - 1] if j > 0 else 0) + int(M[q[j]][r[i]])
+            if hd >= best and hd > 0:
+                best, bq, br = hd, j, i
+            h = max(0, hd, E[j], F)
+            E[j] = max(E[j] - ge, h - go)
+            F = max(F - ge, h - go)
+            Hcur[j] = h
+        Hprev = Hcur
+    return (best, bq, br) if best > 0 else (0, -1, -1)
+
+
+def test_start_cell_pins_catch_planted_mistakes():
+    rng = np.random.default_rng(3100)
+    cases = [_case(rng) for _ in range(300)]
+    want = [pins.brute_force_start(*c) for c in cases]
+    # prefixes one residue too short, forward (unreversed) prefixes, and the
+    # smallest instead of the largest start are each caught
+    short = lambda q, r, M, go, ge: oracle.align(q[1:], r[1:], M, go, ge)  # noqa: E731
+    forward = lambda q, r, M, go, ge: oracle.align(q[::-1], r[::-1], M, go, ge)  # noqa: E731
+    for fn in (short, forward, _min_start_end):
+        got = []
+        for c in cases:
+            try:
+                got.append(_start_via(fn, *c))
+            except (IndexError, ValueError):
+                got.append(None)
+        assert got != want
+
+
+def test_start_batch_matches_single():
+    from paper_1909_00899_amd import workloads
+    w = workloads.random_pairs(80, 4, (0, 30), (0, 40), seed=12)
+    ends = oracle.align_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref,
+                              w.matrix, w.gap_open, w.gap_extend, pair_query=w.pair_query)
+    st = oracle.start_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref, w.matrix,
+                            w.gap_open, w.gap_extend, ends, pair_query=w.pair_query, n_threads=2)
+    for k in range(w.n_pairs):
+        q, r = w.pair(k)
+        assert tuple(st[k]) == oracle.start_cell(q, r, w.matrix, w.gap_open, w.gap_extend)
+        if ends[k, 0] > 0:
+            assert 0 <= st[k, 0] <= ends[k, 1] and 0 <= st[k, 1] <= ends[k, 2]
