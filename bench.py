@@ -192,6 +192,22 @@ def main():
                            "same_results": bool(np.array_equal(oh.results, out.results))}
     rec["graph"] = {"used": bool(use_graph), "graph_hits": og.stats["graph_hits"],
                     "same_results_as_eager": bool(np.array_equal(og.results, out.results))}
+    # start cells of the same alignments: the reversed prefixes ending at every
+    # end cell through the batch path (one query per pair)
+    api.sw_align_batch_starts(d["qres"], d["qoff"], d["rres"], d["roff"], d["pref"], w.matrix,
+                              w.gap_open, w.gap_extend, out.results)
+    n_st = max(1, args.steps // 2)
+    ts = time.perf_counter()
+    for _ in range(n_st):
+        qs, rs = api.sw_align_batch_starts(d["qres"], d["qoff"], d["rres"], d["roff"], d["pref"],
+                                           w.matrix, w.gap_open, w.gap_extend, out.results)
+    st_ms = (time.perf_counter() - ts) / n_st * 1e3
+    live = out.results[:, 0] > 0
+    pcells = int(((out.results[live, 1].astype(np.int64) + 1) *
+                  (out.results[live, 2].astype(np.int64) + 1)).sum())
+    rec["starts"] = {"ms_per_call": round(st_ms, 3), "prefix_cells": pcells,
+                     "gcups_prefix_cells": round(pcells / st_ms / 1e6, 1),
+                     "median_alignment_rows": int(np.median(out.results[live, 1] - qs[live] + 1))}
 
     if not args.no_plain:
         # plain kernel: one 256 x 1024 pair per launch (sw_align)

@@ -141,6 +141,29 @@ typedef struct {
 
 int sw_align_batch(const sw_batch *b, const sw_scoring *sc, sw_result *out);
 
+/* ---------------------------------------------------------------------------
+ * sw_align_batch_starts -- start cells of the alignments a batch call found.
+ *
+ * The paper's method returns only the maximum score (Algorithm 6 keeps Max);
+ * start cells are this library's extension.  For pair k with
+ * ends[k].score > 0 (ends: the n_pairs results sw_align_batch returned for
+ * the same batch and scoring), query_start[k] / ref_start[k] receive the start
+ * of an optimal alignment ending at (ends[k].query_end, ends[k].ref_end): of
+ * all such alignments, the one with the largest ref_start, then the largest
+ * query_start (0-based, inclusive).  Pairs with score 0 get -1, -1.
+ *
+ * Computed by aligning the reversed prefixes q[0 .. query_end] and
+ * r[0 .. ref_end] with the batch path itself (same kernels and precision
+ * rules); their optimum must equal ends[k].score, so an end cell that is
+ * not the pair's optimum gives SW_EINVAL.  Also SW_EINVAL for NULL arrays,
+ * pair ids or offsets out of range, or an end cell outside its sequences.
+ * The batch's arrays follow sw_align_batch's rules (device_resident
+ * included); ends, query_start and ref_start are host arrays of n_pairs
+ * entries owned by the caller.  Synchronous; calls are serialised.
+ * ------------------------------------------------------------------------- */
+int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc, const sw_result *ends,
+                          int32_t *query_start, int32_t *ref_start);
+
 /* Options and statistics for the extended batch call (tests, benchmarks,
  * the autotuner).  Zero-initialise and set what you need. */
 enum { SW_PAIRING_AUTO = 0, SW_PAIRING_ALIGNMENTS = 1, SW_PAIRING_ROWS = 2 };

@@ -28,7 +28,7 @@ SW_FLAG_SATURATED = 1
 EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align",
             "sw_align_batch", "sw_align_batch_ex", "sw_server_create", "sw_server_submit",
             "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay",
-            "sw_autotune", "sw_tune_set", "sw_tune_get"]
+            "sw_autotune", "sw_tune_set", "sw_tune_get", "sw_align_batch_starts"]
 
 
 class NativeLibraryError(RuntimeError):
@@ -155,6 +155,8 @@ def load():
     lib.sw_align_batch_ex.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                       ctypes.POINTER(Options), ctypes.c_void_p,
                                       ctypes.POINTER(Stats)]
+    lib.sw_align_batch_starts.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.sw_autotune.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), ctypes.c_int64,
                                 ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_int32)]
@@ -289,6 +291,27 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
     _check(lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
                                  out.ctypes.data, ctypes.byref(st)))
     return BatchOutput(out[:npairs], st.as_dict())
+
+
+def sw_align_batch_starts(query_res, query_off, ref_res, ref_off, pair_ref, matrix,
+                          gap_open: int, gap_extend: int, results, pair_query=None,
+                          precision: int = SW_PREC_AUTO):
+    """Start cells of the alignments ``sw_align_batch`` returned (``results``:
+    its (n_pairs, 4) int32 array for the same batch and scoring).  Returns
+    (query_start, ref_start), two int32 arrays; -1 where the score is 0."""
+    lib = load()
+    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
+                                  precision)
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    ends = np.ascontiguousarray(np.asarray(results, dtype=np.int32))
+    if ends.shape != (npairs, 4):
+        raise ValueError("results must be the (n_pairs, 4) array of sw_align_batch")
+    qs = np.empty(max(npairs, 1), dtype=np.int32)
+    rs = np.empty(max(npairs, 1), dtype=np.int32)
+    _check(lib.sw_align_batch_starts(ctypes.byref(b), ctypes.byref(sc),
+                                     ends.ctypes.data if npairs else None, qs.ctypes.data,
+                                     rs.ctypes.data))
+    return qs[:npairs], rs[:npairs]
 
 
 def align_workload(w, **kw) -> BatchOutput:

@@ -181,6 +181,11 @@ hipError_t launch_pair_rowpair(int seg, int lanes, bool chunked, const KArgs &a,
 // Sets every result to {0, -1, -1, 0}.
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);
 
+// dst segment t = the dst_off[t+1] - dst_off[t] bytes of src from src_off[t]
+// on, reversed (offsets validated by the host; n segments).
+hipError_t launch_reverse_segments(int n, const uint8_t *src, const int64_t *src_off,
+                                   const int64_t *dst_off, uint8_t *dst, hipStream_t st);
+
 // PairInfo of every pair from device-resident CSR offsets (indices already
 // validated by the host).
 hipError_t launch_build_pairs(int n_pairs, const int64_t *qoff, const int64_t *roff,

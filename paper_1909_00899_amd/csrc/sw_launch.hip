@@ -257,6 +257,19 @@ __global__ __launch_bounds__(1024) void plan_scatter_kernel(int n_pairs, const P
   }
 }
 
+// Segment t of dst (bytes [dst_off[t], dst_off[t+1])) = the same number of
+// bytes of src from src_off[t] on, in reverse order; a workgroup per segment
+// (grid-stride over the segments).
+__global__ __launch_bounds__(256) void reverse_segments_kernel(int n, const uint8_t *src,
+                                                               const int64_t *src_off,
+                                                               const int64_t *dst_off,
+                                                               uint8_t *dst) {
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const int64_t d0 = dst_off[t], len = dst_off[t + 1] - d0, s_last = src_off[t] + len - 1;
+    for (int64_t x = threadIdx.x; x < len; x += blockDim.x) dst[d0 + x] = src[s_last - x];
+  }
+}
+
 __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
@@ -270,6 +283,14 @@ __global__ __launch_bounds__(256) void init_results_kernel(int n, DevResult *r) 
   }
 }
 }  // namespace dev
+
+hipError_t launch_reverse_segments(int n, const uint8_t *src, const int64_t *src_off,
+                                   const int64_t *dst_off, uint8_t *dst, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::reverse_segments_kernel, dim3(std::min(n, 65535)), dim3(256), 0, st, n,
+                     src, src_off, dst_off, dst);
+  return hipGetLastError();
+}
 
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st) {
   if (n <= 0) return hipSuccess;

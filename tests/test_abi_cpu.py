@@ -142,3 +142,22 @@ def test_tuning_table_round_trip_and_validation(lib, tmp_path):
         assert api.tune_get() == good          # a rejected table leaves the old one
     finally:
         api.tune_set([])
+
+
+def test_starts_rejects_bad_arguments(lib):
+    M = np.eye(4, dtype=np.int32)
+    sc, keep = _sc(M)
+    b = api.Batch()
+    qs = np.zeros(2, dtype=np.int32)
+    assert lib.sw_align_batch_starts(None, ctypes.byref(sc), None, qs.ctypes.data,
+                                     qs.ctypes.data) == api.SW_EINVAL
+    b.n_pairs = 0
+    assert lib.sw_align_batch_starts(ctypes.byref(b), ctypes.byref(sc), None, None,
+                                     None) == api.SW_OK
+    b.n_pairs = 1                                   # ends and outputs missing
+    assert lib.sw_align_batch_starts(ctypes.byref(b), ctypes.byref(sc), None, qs.ctypes.data,
+                                     qs.ctypes.data) == api.SW_EINVAL
+    b.n_pairs = -1
+    ends = np.zeros((1, 4), dtype=np.int32)
+    assert lib.sw_align_batch_starts(ctypes.byref(b), ctypes.byref(sc), ends.ctypes.data,
+                                     qs.ctypes.data, qs.ctypes.data) == api.SW_EINVAL

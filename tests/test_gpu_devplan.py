@@ -532,7 +532,7 @@ def test_gap_to_gap_family_shared_query():
                        None, np.arange(len(refs), dtype=np.int32), M, 11, 1)
         want = oracle_batch(w)
         for kw in (dict(lane_pairing=ROWS_PAIRING, force_seglen=4),
-                   dict(lane_pairing=api.SW_PAIRING_ALIGNMENTS, force_lanes=16, force_seglen=4),
+                   dict(lane_pairing=api.SW_PAIRING_ALIGNMENTS, force_lanes=16, force_seglen=8),
                    dict(lane_pairing=api.SW_PAIRING_ALIGNMENTS, force_lanes=32, force_seglen=12)):
             got = _run(w, planner=2, **kw)
             assert_same(got.results, want, "bridge shared s=%d %s" % (s, kw))
