@@ -965,6 +965,10 @@ struct RpParams {
   // and its high half over 2d: weights (2d-1)*SEG*ge | 2d*SEG*ge << 16
   uint32_t w1, w2, w4, w8;
   uint32_t wlast;             // (SEG-1)*ge
+  // 16-lane sub-groups (lane l = threadIdx.x % 16): the 32-bit scan's offset
+  // l*2*SEG*ge, the lane before's max(l-1, 0)*2*SEG*ge, and 0 | SEG*ge << 16
+  int tn;
+  uint32_t tc, w0h;
 };
 
 template <int SEG>
@@ -979,6 +983,11 @@ __device__ __forceinline__ RpParams make_rp_params(uint32_t go, uint32_t ge) {
   p.w4 = weight2(7, 8, (uint64_t)SEG * ge);
   p.w8 = weight2(15, 16, (uint64_t)SEG * ge);
   p.wlast = weight<O>((uint64_t)(SEG - 1), ge);
+  const int l = (int)(threadIdx.x & 15);
+  const uint64_t u2 = 2ull * SEG * ge;   // at most 2*16*32767: fits easily in int32
+  p.tn = (int)(l * u2);
+  p.tc = (uint32_t)((l > 0 ? l - 1 : 0) * u2);
+  p.w0h = weight2(0, 1, (uint64_t)SEG * ge);
   return p;
 }
 
@@ -1101,16 +1110,36 @@ __device__ __forceinline__ void rp_column(State<SEG> &st, const RpParams &pr, co
   uint32_t G = F;
   if constexpr (CHUNKED) G = O::vmax(G, O::usub(cin_f, pr.wv));
   G = O::vmax(G, O::usub(rp_lo2(G), pr.wv));
-  G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr1>(G)), pr.w1));
-  G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr2>(G)), pr.w2));
-  G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr4>(G)), pr.w4));
-  G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr8>(G)), pr.w8));
-  if constexpr (P >= 32) G = O::vmax(G, O::usub(rp_hi2(dpp<kRowBcast15, 0xa, false>(G)), lp->w16));
-  if constexpr (P >= 64) G = O::vmax(G, O::usub(rp_hi2(dpp<kRowBcast31, 0xc, false>(G)), lp->w32));
-  st.Fscan = rp_vshift_p<P>(G, keep);
-  if constexpr (CHUNKED) {
-    st.Fscan |= cin_f;
-    fb_out = G >> 16;
+  if constexpr (P == 16) {
+    // 16 lanes: the lane totals (high halves) as 32-bit values plus l*2*SEG*ge,
+    // so that the scan over the lanes is a plain prefix maximum (one max with
+    // a DPP operand per step; lanes past the row's start read 0, which is
+    // neutral for these non-negative values), then without the offset again.
+    int Tn = (int)(G >> 16) + pr.tn;
+    Tn = max(Tn, (int)dpp<kRowShr1>((uint32_t)Tn));
+    Tn = max(Tn, (int)dpp<kRowShr2>((uint32_t)Tn));
+    Tn = max(Tn, (int)dpp<kRowShr4>((uint32_t)Tn));
+    Tn = max(Tn, (int)dpp<kRowShr8>((uint32_t)Tn));
+    // scan value of virtual lane 2l-1 (the lane before's total; 0 in lane 0)
+    const uint32_t X = dpp<kRowShr1>((uint32_t)Tn) - pr.tc;
+    // entering virtual lane 2l: X; entering 2l+1: max(own low half, X - SEG*ge)
+    st.Fscan = O::vmax(O::usub(rp_lo2(X), pr.w0h), G << 16);
+    if constexpr (CHUNKED) {
+      st.Fscan |= cin_f;
+      fb_out = (uint32_t)(Tn - pr.tn);
+    }
+  } else {
+    G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr1>(G)), pr.w1));
+    G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr2>(G)), pr.w2));
+    G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr4>(G)), pr.w4));
+    G = O::vmax(G, O::usub(rp_hi2(dpp<kRowShr8>(G)), pr.w8));
+    if constexpr (P >= 32) G = O::vmax(G, O::usub(rp_hi2(dpp<kRowBcast15, 0xa, false>(G)), lp->w16));
+    if constexpr (P >= 64) G = O::vmax(G, O::usub(rp_hi2(dpp<kRowBcast31, 0xc, false>(G)), lp->w32));
+    st.Fscan = rp_vshift_p<P>(G, keep);
+    if constexpr (CHUNKED) {
+      st.Fscan |= cin_f;
+      fb_out = G >> 16;
+    }
   }
   if constexpr (LREC) record_lds<SEG>(st, cmax, i, snap);
   else record<O, SEG>(st, cmax, i);
