@@ -272,11 +272,14 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                    algorithm: int = SW_ALG_SCAN, force_lanes: int = 0, force_seglen: int = 0,
                    force_kernel: int = 0, mixed_layout: int = 0, int16_cap: int = 0,
                    use_graph: int = 0, planner: int = 0,
-                   lane_pairing: int = 0) -> BatchOutput:
+                   lane_pairing: int = 0, out=None) -> BatchOutput:
     """Many pairs in one persistent launch (plus an int32 rerun if needed).
 
     Sequences are CSR.  Either all six arrays are numpy (host) or all are torch
     CUDA tensors (device-resident; torch's current stream orders them).
+    ``out``: optional C-contiguous (n_pairs, 4) int32 host array to receive the
+    results (e.g. a view of pinned memory, which the device copies into at
+    full link speed); a new array otherwise.
     """
     lib = load()
     b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
@@ -286,7 +289,11 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                   use_graph, planner, lane_pairing)
     # the library writes every entry (sw_result layout: four int32; flags are
     # small bit sets), so the array is returned as it is, without a copy
-    out = np.empty((max(npairs, 1), 4), dtype=np.int32)
+    if out is None:
+        out = np.empty((max(npairs, 1), 4), dtype=np.int32)
+    elif not (isinstance(out, np.ndarray) and out.dtype == np.int32 and
+              out.shape == (npairs, 4) and out.flags.c_contiguous and npairs > 0):
+        raise ValueError("out must be a C-contiguous (n_pairs, 4) int32 array")
     st = Stats()
     _check(lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
                                  out.ctypes.data, ctypes.byref(st)))

@@ -536,3 +536,22 @@ def test_gap_to_gap_family_shared_query():
                    dict(lane_pairing=api.SW_PAIRING_ALIGNMENTS, force_lanes=32, force_seglen=12)):
             got = _run(w, planner=2, **kw)
             assert_same(got.results, want, "bridge shared s=%d %s" % (s, kw))
+
+
+def test_results_into_caller_buffers():
+    """out= takes a caller's (n_pairs, 4) int32 array, pinned or pageable, and
+    the results are those of a fresh array, graph replays included."""
+    import torch
+    w = W.dna_pairs(n_pairs=5000, seed=31)
+    want = _run(w)
+    pinned = torch.empty((w.n_pairs, 4), dtype=torch.int32, pin_memory=True).numpy()
+    pinned.fill(-7)
+    for graph in (0, 1, 1):
+        got = _run(w, out=pinned, use_graph=graph)
+        assert np.shares_memory(got.results, pinned)
+        assert (pinned == want.results).all()
+        pinned.fill(-7)
+    plain = np.full((w.n_pairs, 4), -7, dtype=np.int32)
+    assert (_run(w, out=plain).results == want.results).all()
+    with pytest.raises(ValueError):
+        _run(w, out=np.zeros((w.n_pairs, 3), dtype=np.int32))
