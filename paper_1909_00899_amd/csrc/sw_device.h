@@ -69,6 +69,9 @@ struct OpsI16 {
   __device__ static uint32_t vmax(uint32_t a, uint32_t b) {
     return bc<uint32_t>(__builtin_elementwise_max(bc<s16x2>(a), bc<s16x2>(b)));
   }
+  __device__ static uint32_t vmin(uint32_t a, uint32_t b) {
+    return bc<uint32_t>(__builtin_elementwise_min(bc<s16x2>(a), bc<s16x2>(b)));
+  }
   __device__ static uint32_t usub(uint32_t a, uint32_t b) {
     return bc<uint32_t>(__builtin_elementwise_sub_sat(bc<u16x2>(a), bc<u16x2>(b)));
   }
@@ -1181,10 +1184,12 @@ __device__ __forceinline__ void rp_share_threshold_p(State<SEG> &st, const RpLan
   }
 }
 
-template <int SEG, bool LREC, class Src>
+// MASKED: cap[j] caps the profile words of row pair j (0 in a half whose row
+// lies before the alignment's first row, 32767 otherwise).
+template <int SEG, bool LREC, bool MASKED, class Src>
 __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const RpParams &pr,
                                                uint32_t lane_base, const Src &src, int ncols,
-                                               uint32_t snap) {
+                                               uint32_t snap, const uint32_t (&cap)[SEG]) {
   const int nblk = ncols / kBlock;
   uint32_t ev_shared = st.events;
   uint32_t rc = src.get(0).x;
@@ -1199,7 +1204,7 @@ __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const R
   {
     const RpShared p0{base(rc, 0)};
 #pragma unroll
-    for (int j = 0; j < SEG; ++j) pw[j] = p0(j);
+    for (int j = 0; j < SEG; ++j) pw[j] = MASKED ? OpsI16::vmin(p0(j), cap[j]) : p0(j);
   }
   for (int b = 0; b < nblk; ++b) {
     const uint32_t r = rc;
@@ -1221,7 +1226,7 @@ __device__ __forceinline__ void rp_run_columns(State<SEG> &st, int lane, const R
       rp_column<SEG, false, RpWords<SEG>, 16, LREC>(st, pr, RpWords<SEG>{pw}, b * kBlock + k, 0u, 0u,
                                                    ho, fo, nullptr, snap);
 #pragma unroll
-      for (int j = 0; j < SEG; ++j) pw[j] = nw[j];
+      for (int j = 0; j < SEG; ++j) pw[j] = MASKED ? OpsI16::vmin(nw[j], cap[j]) : nw[j];
     }
     if (st.events != ev_shared) {
       rp_share_threshold<SEG>(st, lane);
@@ -1283,9 +1288,14 @@ __device__ __forceinline__ void rp_finish(const State<SEG> &st, int lane, int pi
 // LREC: end-cell records in LDS ([16 wavefronts][SEG + kRecRows][64 lanes]
 // words after the two profile copies) instead of VGPRs, one workgroup of 16
 // wavefronts per CU sharing one profile; else 8 wavefronts per workgroup.
+// MASKED (start cells): pair p aligns only the query rows from
+// a.first_row[p] on (the reversed prefix ending at its end cell is a suffix of
+// the reversed query); the rows before get profile scores capped at 0, so their
+// H, E and F stay 0 and the first real row starts as after a zero row, exactly
+// as in the alignment of that suffix alone.  Reported rows count from row 0.
 __host__ __device__ constexpr int rowpair_waves_per_group(bool lrec) { return lrec ? 16 : 8; }
 
-template <int SEG, bool LREC>
+template <int SEG, bool LREC, bool MASKED = false>
 __global__ __launch_bounds__(rowpair_waves_per_group(LREC) * 64) __attribute__((amdgpu_waves_per_eu(4)))
 void shared_rowpair_kernel(KArgs a) {
   if (a.plan_meta[kMetaErrResidue] | a.plan_meta[kMetaErrPair]) return;
@@ -1323,7 +1333,15 @@ void shared_rowpair_kernel(KArgs a) {
     state_reset(st, 0u);
     if constexpr (LREC) record_lds_reset<SEG>(snap);
     const DirectSrc src{a.ref_res + roff, a.ref_res + roff, n, 0, sentw};
-    rp_run_columns<SEG, LREC>(st, lane, pr, lane_base, src, ncols, snap);
+    uint32_t cap[SEG];
+    if constexpr (MASKED) {
+      const int r0 = pid >= 0 ? a.first_row[pid] : 0;
+      const int lo0 = 2 * (lane & 15) * SEG;
+#pragma unroll
+      for (int j = 0; j < SEG; ++j)
+        cap[j] = (lo0 + j < r0 ? 0u : 0x7fffu) | (lo0 + SEG + j < r0 ? 0u : 0x7fff0000u);
+    }
+    rp_run_columns<SEG, LREC, MASKED>(st, lane, pr, lane_base, src, ncols, snap, cap);
     cols += (unsigned long long)ncols;
     events += st.events;
     padded += (unsigned long long)min(4, nvalid - ti * 4) * ncols * 32 * SEG;

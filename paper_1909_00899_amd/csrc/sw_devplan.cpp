@@ -153,8 +153,11 @@ bool pick_pair_shape(Prec prec, const Scoring &S, int max_m, const ExecOptions &
 
 }  // namespace
 
+bool rowpair_shape(int m, int alpha, int &seg) { return pick_rowpair_seg(m, alpha, 0, seg); }
+
 int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, int planner,
-                    Context &C, sw_result *out, sw_stats *stats, double t0, bool &handled) {
+                    Context &C, sw_result *out, sw_stats *stats, double t0, bool &handled,
+                    const int32_t *first_row) {
   handled = false;
   const int np = b->n_pairs;
   // ---- does the batch qualify (everything here is host-side)
@@ -212,7 +215,14 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   const Prec prec = (b->precision == SW_PREC_AUTO && S.fits_i16) ? PREC_I16X2 : PREC_I32;
   int seg = 0, lanes = 16, pes = 0;   // pes: per-pair profile entry bytes
   bool rows = false;   // row pairs: both halves of a lane hold rows of one alignment
-  if (single) {
+  if (first_row) {
+    // start-cell pass: masked row pairs only
+    if (!single) return refuse("masked rows need one query");
+    if (prec != PREC_I16X2) return refuse("masked rows need int16 lanes");
+    if (!pick_rowpair_seg(m, S.alpha, 0, seg)) return refuse("no row-pair shape holds the query");
+    rows = true;
+    handled = true;
+  } else if (single) {
     if (eo.lane_pairing == SW_PAIRING_ROWS) {
       if (prec != PREC_I16X2) return refuse("row pairs need int16 lanes");
       if (eo.force_lanes && eo.force_lanes != 16) return refuse("row pairs use 16 lanes");
@@ -365,6 +375,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   a.order = order;
   a.plan_meta = meta;
   a.ref_res = d_rres;
+  a.first_row = first_row;
   const double t_launch0 = now_ms();
   es.plan_ms = t_launch0 - t0;
   int max_m = m;
@@ -384,7 +395,8 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
                  : launch_shared_direct(prec, seg, lanes, a, grid, st);
       return e;
     };
-    if ((rc = run({0xD1D1, (uint64_t)seg, (uint64_t)lanes, (uint64_t)rows, (uint64_t)grid}, all,
+    if ((rc = run({0xD1D1, (uint64_t)seg, (uint64_t)lanes, (uint64_t)rows, (uint64_t)grid,
+                   (uint64_t)(uintptr_t)first_row}, all,
                   true)))
       return rc;
   } else {
@@ -445,7 +457,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   }
   // ---- exact int32 rerun of the pairs whose int16 lanes saturated
   std::vector<int> again;
-  if (prec == PREC_I16X2)
+  if (prec == PREC_I16X2 && !first_row)
     for (int k = 0; k < np; ++k)
       if (out[k].flags & kFlagNeedsI32) again.push_back(k);
   if (!again.empty()) {

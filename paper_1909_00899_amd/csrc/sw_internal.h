@@ -76,6 +76,10 @@ struct KArgs {
   const int32_t *order;       // valid pairs, longest reference first
   int32_t *plan_meta;         // kMeta* words
   const uint8_t *ref_res;     // residues of every reference (device)
+  // masked shared row-pair launches (start cells): per pair (PairInfo index)
+  // the number of leading rows of the shared query outside its alignment,
+  // whose profile scores are capped at 0; nullptr otherwise
+  const int32_t *first_row;
 };
 
 // Device planner of a single-query batch: words of the plan_meta array.

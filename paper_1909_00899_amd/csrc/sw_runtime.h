@@ -222,8 +222,15 @@ std::vector<int> pair_mixed_candidates(swk::Prec prec, int alpha, const PlanItem
 // pairs, 1 = never, 2 = always (SW_EINVAL when the batch does not qualify).
 // `handled` is false when the caller must run the host planner instead (then
 // nothing was launched and `out` is untouched).  The caller holds C.mu.
+// first_row (start-cell passes; device memory, one int per pair, planner 2):
+// one query, int16 row pairs, each pair aligning the query rows from
+// first_row[k] on; saturated pairs are not rerun but keep kFlagNeedsI32.
 int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, int planner,
-                    Context &C, sw_result *out, sw_stats *stats, double t0, bool &handled);
+                    Context &C, sw_result *out, sw_stats *stats, double t0, bool &handled,
+                    const int32_t *first_row = nullptr);
+// Rows per virtual lane of the device planner's row-pair layout for a query of
+// m residues (false if no compiled shape holds it in one chunk).
+bool rowpair_shape(int m, int alpha, int &seg);
 
 // Full batch semantics (int16 pass + int32 rerun) on prepared input.
 int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecOptions &opt,

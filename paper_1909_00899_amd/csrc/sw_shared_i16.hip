@@ -35,32 +35,37 @@ hipError_t launch_d(const KArgs &a, int grid, hipStream_t st, size_t lds) {
   hipLaunchKernelGGL(k, dim3(grid), dim3(kWavesPerGroup * kWave), lds, st, a);
   return hipGetLastError();
 }
-template <int SEG, bool LREC>
+template <int SEG, bool LREC, bool MASKED>
 hipError_t launch_rp(const KArgs &a, int grid, hipStream_t st, size_t lds) {
   // grid: wavefronts wanted
-  auto k = dev::shared_rowpair_kernel<SEG, LREC>;
+  auto k = dev::shared_rowpair_kernel<SEG, LREC, MASKED>;
   constexpr int wpg = dev::rowpair_waves_per_group(LREC);
   hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3((grid + wpg - 1) / wpg), dim3(wpg * kWave), lds, st, a);
   return hipGetLastError();
 }
 
-template <bool LREC>
+template <bool LREC, bool MASKED>
 hipError_t launch_rps(int seg, const KArgs &a, int grid, hipStream_t st, size_t lds) {
   switch (seg) {
-    case 4: return launch_rp<4, LREC>(a, grid, st, lds);
-    case 8: return launch_rp<8, LREC>(a, grid, st, lds);
-    case 12: return launch_rp<12, LREC>(a, grid, st, lds);
-    case 16: return launch_rp<16, LREC>(a, grid, st, lds);
+    case 4: return launch_rp<4, LREC, MASKED>(a, grid, st, lds);
+    case 8: return launch_rp<8, LREC, MASKED>(a, grid, st, lds);
+    case 12: return launch_rp<12, LREC, MASKED>(a, grid, st, lds);
+    case 16: return launch_rp<16, LREC, MASKED>(a, grid, st, lds);
   }
   return hipErrorInvalidValue;
 }
 }  // namespace
 
+// masked: a.first_row gives each pair's first query row (start-cell passes)
 hipError_t launch_rowpair_i16(int seg, bool lds_records, const KArgs &a, int grid,
                               hipStream_t st, size_t lds) {
-  return lds_records ? launch_rps<true>(seg, a, grid, st, lds)
-                     : launch_rps<false>(seg, a, grid, st, lds);
+  const bool masked = a.first_row != nullptr;
+  if (masked)
+    return lds_records ? launch_rps<true, true>(seg, a, grid, st, lds)
+                       : launch_rps<false, true>(seg, a, grid, st, lds);
+  return lds_records ? launch_rps<true, false>(seg, a, grid, st, lds)
+                     : launch_rps<false, false>(seg, a, grid, st, lds);
 }
 
 hipError_t launch_direct_i16(int shape, const KArgs &a, int grid, hipStream_t st, size_t lds) {

@@ -5,10 +5,17 @@
 // r[0..ref_end]: every optimal alignment inside the prefixes ends at the
 // reported end cell (an alignment ending earlier would precede it in the
 // (ref_end, query_end) order the end cell is chosen by), and the smallest end
-// of the reversed problem is the largest start of the forward one.  So the
-// reversed prefixes are cut out on the device and run through the batch path
-// itself (device or host planner, the same kernels, int32 reruns), one query
-// per pair.
+// of the reversed problem is the largest start of the forward one.  The
+// reversed prefixes are cut out on the device and aligned by the library's own
+// kernels:
+//
+// * one query (the batch's pairs share it): every reversed query prefix is a
+//   suffix of the reversed query, so all pairs run in one device-planned
+//   row-pair launch on the whole reversed query, each pair with the rows
+//   before its suffix masked (profile scores capped at 0); pairs whose int16
+//   lanes saturate, and batches that do not fit that kernel, take the next path;
+// * otherwise each reversed query prefix is a query of its own, through the
+//   batch path (device or host planner, int32 reruns).
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -33,14 +40,13 @@ namespace {
     }                                                                            \
   } while (0)
 
-// Grow-only device buffers and a stream of their own (the batch call takes
-// the library context's lock itself); one call at a time.
+// Grow-only device buffers and a stream of their own; one call at a time.
 struct StartsWork {
   std::mutex mu;
   hipStream_t st = nullptr;
   DevBuf src_q, src_r;   // host-resident residue sets, uploaded
-  DevBuf rev_q, rev_r;   // reversed prefixes
-  DevBuf tab;            // offsets: q src, q dst, r src, r dst (int64), pair ids (int32)
+  DevBuf rev_q, rev_r;   // reversed query / prefixes
+  DevBuf tab;            // offsets (int64), pair ids and first rows (int32)
 };
 StartsWork g_starts;
 
@@ -50,6 +56,167 @@ int read_back(std::vector<T> &dst, const T *src, size_t n, bool device) {
   if (n == 0) return SW_OK;
   if (device) HIPCHK(hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
   else std::memcpy(dst.data(), src, n * sizeof(T));
+  return SW_OK;
+}
+
+// What every path needs: the batch's offsets and ids on the host, its residues
+// on the device.
+struct Batch {
+  const sw_batch *b;
+  const sw_result *ends;
+  std::vector<int64_t> qoff, roff;
+  std::vector<int32_t> pq, pr;
+  const uint8_t *d_q = nullptr, *d_r = nullptr;
+};
+
+int upload(const std::vector<int64_t> *v64[4], size_t L1, const std::vector<int32_t> *v32[2],
+           size_t L, StartsWork &W, int64_t *&d64, int32_t *&d32) {
+  const size_t bytes = 4 * L1 * sizeof(int64_t) + 2 * L * sizeof(int32_t) + 64;
+  int rc = W.tab.ensure(bytes);
+  if (rc) return rc;
+  d64 = W.tab.as<int64_t>();
+  d32 = (int32_t *)(d64 + 4 * L1);
+  for (int k = 0; k < 4; ++k)
+    if (v64[k]) HIPCHK(hipMemcpyAsync(d64 + k * L1, v64[k]->data(), L1 * sizeof(int64_t),
+                                      hipMemcpyHostToDevice, W.st));
+  for (int k = 0; k < 2; ++k)
+    if (v32[k] && L) HIPCHK(hipMemcpyAsync(d32 + k * L, v32[k]->data(), L * sizeof(int32_t),
+                                           hipMemcpyHostToDevice, W.st));
+  return SW_OK;
+}
+
+// One query: the masked row-pair launch on the reversed query.  Pairs it
+// cannot finish (int16 saturation) are appended to `rest`.
+int starts_masked(const Batch &B, const sw_scoring *sc, const Scoring &S,
+                  const std::vector<int> &live, StartsWork &W, int32_t *query_start,
+                  int32_t *ref_start, std::vector<int> &rest) {
+  const int L = (int)live.size();
+  const int q0 = B.pq[live[0]];   // every live pair's query
+  const int64_t m = B.qoff[q0 + 1] - B.qoff[q0];
+  std::vector<int64_t> rsrc, rdst{0};
+  std::vector<int32_t> ids(L), first(L);
+  for (int t = 0; t < L; ++t) {
+    const int k = live[t];
+    ids[t] = t;
+    first[t] = (int32_t)(m - 1 - B.ends[k].query_end);
+    rsrc.push_back(B.roff[B.pr[k]]);
+    rdst.push_back(rdst.back() + B.ends[k].ref_end + 1);
+  }
+  rsrc.push_back(0);
+  int rc;
+  if ((rc = W.rev_q.ensure((size_t)m)) || (rc = W.rev_r.ensure((size_t)rdst.back()))) return rc;
+  const size_t L1 = (size_t)L + 1;
+  // table rows: [0] the query's source offset, [1] its reversed copy's
+  // offsets {0, m}, [2] reference sources, [3] reversed prefix offsets
+  std::vector<int64_t> qsrcL(L1, 0), qdstL(L1, 0);
+  qsrcL[0] = B.qoff[q0];
+  qdstL[1] = m;
+  const std::vector<int64_t> *v64[4] = {&qsrcL, &qdstL, &rsrc, &rdst};
+  const std::vector<int32_t> *v32[2] = {&ids, &first};
+  int64_t *d64;
+  int32_t *d32;
+  if ((rc = upload(v64, L1, v32, (size_t)L, W, d64, d32))) return rc;
+  HIPCHK(swk::launch_reverse_segments(1, B.d_q, d64, d64 + L1, W.rev_q.as<uint8_t>(), W.st));
+  HIPCHK(swk::launch_reverse_segments(L, B.d_r, d64 + 2 * L1, d64 + 3 * L1,
+                                      W.rev_r.as<uint8_t>(), W.st));
+  HIPCHK(hipStreamSynchronize(W.st));
+  sw_batch nb;
+  std::memset(&nb, 0, sizeof(nb));
+  nb.n_pairs = L;
+  nb.query_res = W.rev_q.as<uint8_t>();
+  nb.query_off = d64 + L1;          // {0, m}
+  nb.n_queries = 1;
+  nb.ref_res = W.rev_r.as<uint8_t>();
+  nb.ref_off = d64 + 3 * L1;
+  nb.n_refs = L;
+  nb.pair_ref = d32;
+  nb.precision = SW_PREC_AUTO;
+  nb.device_resident = 1;
+  nb.stream = W.st;
+  std::vector<sw_result> rev(L);
+  {
+    std::lock_guard<std::mutex> g(g_ctx.mu);
+    HIPCHK(hipSetDevice(g_ctx.device));
+    ExecOptions eo;
+    bool handled = false;
+    rc = run_device_plan(&nb, S, eo, 2, g_ctx, rev.data(), nullptr, now_ms(), handled, d32 + L);
+  }
+  if (rc) return rc;
+  (void)sc;
+  for (int t = 0; t < L; ++t) {
+    const int k = live[t];
+    if (rev[t].flags & swk::kFlagNeedsI32) {
+      rest.push_back(k);
+      continue;
+    }
+    if (rev[t].score != B.ends[k].score) {
+      set_error("pair %d: score %d is not this pair's optimum at its end cell (%d found)", k,
+                B.ends[k].score, rev[t].score);
+      return SW_EINVAL;
+    }
+    // reported rows count from the reversed query's first row
+    query_start[k] = B.ends[k].query_end - (rev[t].query_end - first[t]);
+    ref_start[k] = B.ends[k].ref_end - rev[t].ref_end;
+  }
+  return SW_OK;
+}
+
+// Each reversed query prefix as a query of its own, through the batch path.
+int starts_per_pair(const Batch &B, const sw_scoring *sc, const std::vector<int> &live,
+                    StartsWork &W, int32_t *query_start, int32_t *ref_start) {
+  const int L = (int)live.size();
+  std::vector<int64_t> qsrc, qdst{0}, rsrc, rdst{0};
+  std::vector<int32_t> ids(L);
+  for (int t = 0; t < L; ++t) {
+    const int k = live[t];
+    const int q = B.b->pair_query ? B.pq[k] : 0;
+    ids[t] = t;
+    qsrc.push_back(B.qoff[q]);
+    qdst.push_back(qdst.back() + B.ends[k].query_end + 1);
+    rsrc.push_back(B.roff[B.pr[k]]);
+    rdst.push_back(rdst.back() + B.ends[k].ref_end + 1);
+  }
+  qsrc.push_back(0);
+  rsrc.push_back(0);
+  int rc;
+  if ((rc = W.rev_q.ensure((size_t)qdst.back())) || (rc = W.rev_r.ensure((size_t)rdst.back())))
+    return rc;
+  const size_t L1 = (size_t)L + 1;
+  const std::vector<int64_t> *v64[4] = {&qsrc, &qdst, &rsrc, &rdst};
+  const std::vector<int32_t> *v32[2] = {&ids, nullptr};
+  int64_t *d64;
+  int32_t *d32;
+  if ((rc = upload(v64, L1, v32, (size_t)L, W, d64, d32))) return rc;
+  HIPCHK(swk::launch_reverse_segments(L, B.d_q, d64, d64 + L1, W.rev_q.as<uint8_t>(), W.st));
+  HIPCHK(swk::launch_reverse_segments(L, B.d_r, d64 + 2 * L1, d64 + 3 * L1,
+                                      W.rev_r.as<uint8_t>(), W.st));
+  HIPCHK(hipStreamSynchronize(W.st));
+  sw_batch nb;
+  std::memset(&nb, 0, sizeof(nb));
+  nb.n_pairs = L;
+  nb.query_res = W.rev_q.as<uint8_t>();
+  nb.query_off = d64 + L1;
+  nb.n_queries = L;
+  nb.ref_res = W.rev_r.as<uint8_t>();
+  nb.ref_off = d64 + 3 * L1;
+  nb.n_refs = L;
+  nb.pair_query = d32;
+  nb.pair_ref = d32;
+  nb.precision = B.b->precision;
+  nb.device_resident = 1;
+  nb.stream = W.st;
+  std::vector<sw_result> rev(L);
+  if ((rc = sw_align_batch(&nb, sc, rev.data()))) return rc;
+  for (int t = 0; t < L; ++t) {
+    const int k = live[t];
+    if (rev[t].score != B.ends[k].score) {
+      set_error("pair %d: score %d is not this pair's optimum at its end cell (%d found)", k,
+                B.ends[k].score, rev[t].score);
+      return SW_EINVAL;
+    }
+    query_start[k] = B.ends[k].query_end - rev[t].query_end;
+    ref_start[k] = B.ends[k].ref_end - rev[t].ref_end;
+  }
   return SW_OK;
 }
 
@@ -67,8 +234,7 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
   const int np = b->n_pairs;
   if (np == 0) return SW_OK;
   if (!ends || !query_start || !ref_start) { set_error("ends or an output array is NULL"); return SW_EINVAL; }
-  if (!b->query_off || !b->ref_off || !b->pair_ref || b->n_queries < 1 || b->n_refs < 1 ||
-      (!b->pair_query && b->n_queries < 1)) {
+  if (!b->query_off || !b->ref_off || !b->pair_ref || b->n_queries < 1 || b->n_refs < 1) {
     set_error("batch arrays are NULL or empty");
     return SW_EINVAL;
   }
@@ -89,104 +255,68 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
     HIPCHK(e);
   }
   // ---- the batch's offsets and pair ids on the host (validated here)
-  std::vector<int64_t> qoff, roff;
-  std::vector<int32_t> pq, pr;
-  if ((rc = read_back(qoff, b->query_off, (size_t)b->n_queries + 1, dev)) ||
-      (rc = read_back(roff, b->ref_off, (size_t)b->n_refs + 1, dev)) ||
-      (rc = read_back(pr, b->pair_ref, (size_t)np, dev)))
+  Batch B;
+  B.b = b;
+  B.ends = ends;
+  if ((rc = read_back(B.qoff, b->query_off, (size_t)b->n_queries + 1, dev)) ||
+      (rc = read_back(B.roff, b->ref_off, (size_t)b->n_refs + 1, dev)) ||
+      (rc = read_back(B.pr, b->pair_ref, (size_t)np, dev)))
     return rc;
   if (b->pair_query) {
-    if ((rc = read_back(pq, b->pair_query, (size_t)np, dev))) return rc;
+    if ((rc = read_back(B.pq, b->pair_query, (size_t)np, dev))) return rc;
   } else {
-    pq.assign(np, 0);
+    B.pq.assign(np, 0);
   }
   for (int k = 0; k < b->n_queries; ++k)
-    if (qoff[k] < 0 || qoff[k + 1] < qoff[k]) { set_error("query offsets not nondecreasing"); return SW_EINVAL; }
+    if (B.qoff[k] < 0 || B.qoff[k + 1] < B.qoff[k]) { set_error("query offsets not nondecreasing"); return SW_EINVAL; }
   for (int k = 0; k < b->n_refs; ++k)
-    if (roff[k] < 0 || roff[k + 1] < roff[k]) { set_error("reference offsets not nondecreasing"); return SW_EINVAL; }
-  // ---- the reversed prefix of every pair with a positive score
+    if (B.roff[k] < 0 || B.roff[k + 1] < B.roff[k]) { set_error("reference offsets not nondecreasing"); return SW_EINVAL; }
   std::vector<int> live;
-  std::vector<int64_t> tab;   // [4][L+1]: q src, q dst, r src, r dst
-  std::vector<int64_t> qsrc, qdst{0}, rsrc, rdst{0};
+  bool one_query = true;
   for (int k = 0; k < np; ++k) {
     const sw_result &e = ends[k];
     query_start[k] = ref_start[k] = -1;
-    if (pq[k] < 0 || pq[k] >= b->n_queries || pr[k] < 0 || pr[k] >= b->n_refs) {
+    if (B.pq[k] < 0 || B.pq[k] >= b->n_queries || B.pr[k] < 0 || B.pr[k] >= b->n_refs) {
       set_error("pair %d refers to a query or reference out of range", k);
       return SW_EINVAL;
     }
     if (e.score <= 0) continue;
-    const int64_t m = qoff[pq[k] + 1] - qoff[pq[k]], n = roff[pr[k] + 1] - roff[pr[k]];
+    const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
+    const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
     if (e.query_end < 0 || e.query_end >= m || e.ref_end < 0 || e.ref_end >= n) {
       set_error("pair %d: end cell (%d, %d) outside its %lld x %lld sequences", k, e.query_end,
                 e.ref_end, (long long)m, (long long)n);
       return SW_EINVAL;
     }
+    one_query = one_query && B.pq[k] == B.pq[live.empty() ? k : live[0]];
     live.push_back(k);
-    qsrc.push_back(qoff[pq[k]]);
-    qdst.push_back(qdst.back() + e.query_end + 1);
-    rsrc.push_back(roff[pr[k]]);
-    rdst.push_back(rdst.back() + e.ref_end + 1);
   }
-  const int L = (int)live.size();
-  if (L == 0) return SW_OK;
-  qsrc.push_back(0);
-  rsrc.push_back(0);
-  const size_t L1 = (size_t)L + 1;
-  const size_t tab_bytes = 4 * L1 * sizeof(int64_t) + (size_t)L * sizeof(int32_t) + 64;
-  if ((rc = W.tab.ensure(tab_bytes)) || (rc = W.rev_q.ensure((size_t)qdst.back())) ||
-      (rc = W.rev_r.ensure((size_t)rdst.back())))
-    return rc;
-  int64_t *d_tab = W.tab.as<int64_t>();
-  int32_t *d_ids = (int32_t *)(d_tab + 4 * L1);
-  std::vector<int32_t> ids(L);
-  for (int t = 0; t < L; ++t) ids[t] = t;
-  HIPCHK(hipMemcpyAsync(d_tab, qsrc.data(), L1 * sizeof(int64_t), hipMemcpyHostToDevice, W.st));
-  HIPCHK(hipMemcpyAsync(d_tab + L1, qdst.data(), L1 * sizeof(int64_t), hipMemcpyHostToDevice, W.st));
-  HIPCHK(hipMemcpyAsync(d_tab + 2 * L1, rsrc.data(), L1 * sizeof(int64_t), hipMemcpyHostToDevice, W.st));
-  HIPCHK(hipMemcpyAsync(d_tab + 3 * L1, rdst.data(), L1 * sizeof(int64_t), hipMemcpyHostToDevice, W.st));
-  HIPCHK(hipMemcpyAsync(d_ids, ids.data(), (size_t)L * sizeof(int32_t), hipMemcpyHostToDevice, W.st));
-  // residues on the device
-  const uint8_t *d_q = b->query_res, *d_r = b->ref_res;
+  if (live.empty()) return SW_OK;
+  // ---- residues on the device
+  B.d_q = b->query_res;
+  B.d_r = b->ref_res;
   if (!dev) {
-    const size_t qb = (size_t)qoff[b->n_queries], rb = (size_t)roff[b->n_refs];
+    const size_t qb = (size_t)B.qoff[b->n_queries], rb = (size_t)B.roff[b->n_refs];
     if ((rc = W.src_q.ensure(qb + 1)) || (rc = W.src_r.ensure(rb + 1))) return rc;
     if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, qb, hipMemcpyHostToDevice, W.st));
     if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, rb, hipMemcpyHostToDevice, W.st));
-    d_q = W.src_q.as<uint8_t>();
-    d_r = W.src_r.as<uint8_t>();
+    B.d_q = W.src_q.as<uint8_t>();
+    B.d_r = W.src_r.as<uint8_t>();
   }
-  HIPCHK(swk::launch_reverse_segments(L, d_q, d_tab, d_tab + L1, W.rev_q.as<uint8_t>(), W.st));
-  HIPCHK(swk::launch_reverse_segments(L, d_r, d_tab + 2 * L1, d_tab + 3 * L1, W.rev_r.as<uint8_t>(),
-                                      W.st));
-  HIPCHK(hipStreamSynchronize(W.st));
-  // ---- the reversed pairs through the batch path, one query per pair
-  sw_batch nb;
-  std::memset(&nb, 0, sizeof(nb));
-  nb.n_pairs = L;
-  nb.query_res = W.rev_q.as<uint8_t>();
-  nb.query_off = d_tab + L1;
-  nb.n_queries = L;
-  nb.ref_res = W.rev_r.as<uint8_t>();
-  nb.ref_off = d_tab + 3 * L1;
-  nb.n_refs = L;
-  nb.pair_query = d_ids;
-  nb.pair_ref = d_ids;
-  nb.precision = b->precision;
-  nb.device_resident = 1;
-  nb.stream = W.st;
-  std::vector<sw_result> rev(L);
-  if ((rc = sw_align_batch(&nb, sc, rev.data()))) return rc;
-  for (int t = 0; t < L; ++t) {
-    const int k = live[t];
-    if (rev[t].score != ends[k].score) {
-      for (int u = 0; u < np; ++u) query_start[u] = ref_start[u] = -1;
-      set_error("pair %d: score %d is not this pair's optimum at its end cell (%d found)", k,
-                ends[k].score, rev[t].score);
-      return SW_EINVAL;
-    }
-    query_start[k] = ends[k].query_end - rev[t].query_end;
-    ref_start[k] = ends[k].ref_end - rev[t].ref_end;
+  std::vector<int> rest;
+  int seg = 0;
+  const int q0 = B.pq[live[0]];
+  const int64_t m0 = B.qoff[q0 + 1] - B.qoff[q0];
+  if (one_query && b->precision == SW_PREC_AUTO && S.fits_i16 && m0 <= 512 &&
+      rowpair_shape((int)m0, S.alpha, seg)) {
+    rc = starts_masked(B, sc, S, live, W, query_start, ref_start, rest);
+  } else {
+    rest = live;
+  }
+  if (!rc && !rest.empty()) rc = starts_per_pair(B, sc, rest, W, query_start, ref_start);
+  if (rc) {
+    for (int u = 0; u < np; ++u) query_start[u] = ref_start[u] = -1;
+    return rc;
   }
   return SW_OK;
 }

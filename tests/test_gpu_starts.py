@@ -118,3 +118,47 @@ def test_starts_device_resident_and_errors():
     assert e.value.code == api.SW_EINVAL
     qs2, rs2 = api.sw_align_batch_starts(*args, ends, pair_query=w.pair_query)
     assert (np.stack([qs2, rs2], axis=1) == starts).all()
+
+
+def _one_query(seed, m, n_refs, nlen, alpha, matrix, go=11, ge=1):
+    rng = np.random.default_rng(seed)
+    q = rng.integers(0, alpha, size=m).astype(np.uint8)
+    lens = rng.integers(nlen[0], nlen[1] + 1, size=n_refs)
+    refs = [rng.integers(0, alpha, size=int(L)).astype(np.uint8) for L in lens]
+    roff = np.zeros(n_refs + 1, dtype=np.int64)
+    np.cumsum(lens, out=roff[1:])
+    return W.Workload("one_query", q, np.array([0, m], dtype=np.int64), np.concatenate(refs), roff,
+                      None, np.arange(n_refs, dtype=np.int32), matrix, go, ge)
+
+
+@pytest.mark.parametrize("alpha,m", [(2, 200), (4, 512), (20, 97)])
+def test_starts_one_query_masked_rows(alpha, m):
+    """One query: every pair's reversed prefix is a suffix of the reversed
+    query, aligned in one masked row-pair launch (rows before the suffix
+    capped at score 0)."""
+    rng = np.random.default_rng(900 + alpha)
+    M = W.protein_matrix() if alpha == 20 else W.random_matrix(rng, alpha)
+    w = _one_query(901 + alpha, m, 3000, (1, 700), alpha, M)
+    _check(w, "one query alpha=%d m=%d" % (alpha, m))
+
+
+def test_starts_one_query_saturated_pairs_take_int32():
+    # copies of the query inside the references: with a diagonal of 100 the
+    # best score exceeds 32767, so those pairs leave the masked int16 launch
+    M = W.protein_matrix().copy()
+    np.fill_diagonal(M, 100)
+    rng = np.random.default_rng(902)
+    q = rng.integers(0, 20, size=450).astype(np.uint8)
+    refs = []
+    for k in range(400):
+        r = rng.integers(0, 20, size=int(rng.integers(50, 900))).astype(np.uint8)
+        if k % 7 == 0:
+            at = int(rng.integers(0, r.size))
+            r = np.concatenate([r[:at], q[k % 50:], r[at:]])
+        refs.append(r)
+    roff = np.zeros(len(refs) + 1, dtype=np.int64)
+    np.cumsum([r.size for r in refs], out=roff[1:])
+    w = W.Workload("sat1", q, np.array([0, q.size], np.int64), np.concatenate(refs), roff, None,
+                   np.arange(len(refs), dtype=np.int32), M, 11, 1)
+    ends, starts = _check(w, "one query, saturated")
+    assert (ends[:, 3] == api.SW_FLAG_SATURATED).sum() > 10
