@@ -715,8 +715,10 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
   }
   const int nd = (int)li.ms.size();
   std::vector<PairShape> shape(nd);
+  std::vector<char> own(nd, 0);   // mixed batch: a class in a launch of its own shape
   int pmax_mixed = 16;
   double nonmixed_total = 0;
+  double bound = 1e300;   // the batch's modelled time on a full GPU (set below)
   if (!mixed) {
     // Least modelled work per pair, unless that leaves one wavefront with a
     // chain of column steps longer than the whole batch needs on a full GPU
@@ -733,14 +735,15 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
       });
       lmin = std::max(lmin, best_lat);
     }
-    const double bound = std::max(total / slots, lmin);
+    bound = std::max(total / slots, lmin);
     nonmixed_total = total;
     for (int s = 0; s < nd; ++s) {
       const int m = li.ms[s];
       if (tunable && !rows_only(prec, alpha, opt) && tune_lookup(SW_TUNE_PAIR, prec, alpha, m, te)) {
         // the tuned alignment-pair shape, unless row pairs model far less work
         const PairShape tuned{te.lanes, te.seglen, (m + te.lanes * te.seglen - 1) / (te.lanes * te.seglen)};
-        if (!(shape[s].rp && shape_cost(prec, shape[s], alpha) < 0.7 * shape_cost(prec, tuned, alpha))) {
+        if (!(shape[s].rp && shape_cost(prec, shape[s], alpha) < 0.7 * shape_cost(prec, tuned, alpha)) &&
+            (double)hs.nmax[s] * shape_chain(prec, tuned) <= bound) {
           shape[s] = tuned;
           continue;
         }
@@ -783,8 +786,22 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
       if (c < best - 1e-9) { best = c; best_seg = seg; pmax_mixed = pm; }
     }
     if (mixed || best <= 1.15 * nonmixed_total) {
+      const bool chosen = !mixed;   // the planner's choice, not forced or tuned
       mixed = true;
       for (int s = 0; s < nd; ++s) shape[s] = mixed_shape(li.ms[s], best_seg);
+      // ... keeping the latency bound: a length class whose chain of column
+      // steps would outlast the whole batch gets its own launch in the
+      // cheapest shape that fits (long queries in a small batch: row pairs
+      // halve the chain)
+      for (int s = 0; s < nd && chosen; ++s) {
+        if ((double)hs.nmax[s] * shape_chain(prec, shape[s]) <= 1.05 * bound) continue;
+        double bc = 1e300;
+        for_each_pair_shape(prec, li.ms[s], alpha, opt, [&](const PairShape &ps) {
+          if ((double)hs.nmax[s] * shape_chain(prec, ps) > bound) return;
+          const double c = shape_cost(prec, ps, alpha);
+          if (c < bc - 1e-9) { bc = c; shape[s] = ps; own[s] = 1; }
+        });
+      }
     }
   }
   // ---- launch classes (rows per lane, widest sub-group, chunked or not); a
@@ -795,7 +812,9 @@ int plan_pairs(const PlanItem *items, size_t cnt, Prec prec, int alpha, const Ex
   int max_nch = 1;
   for (int s = 0; s < nd; ++s) {
     const PairShape &ps = shape[s];
-    const int pmax = (mixed && ps.nchunks == 1) ? pmax_mixed : ps.P;
+    // mixed alignment-pair launches share one widest width; a latency-bound
+    // class of a mixed batch keeps its own shape and launch
+    const int pmax = (mixed && ps.nchunks == 1 && !own[s]) ? pmax_mixed : ps.P;
     const bool chunked = ps.nchunks > 1;
     max_nch = std::max(max_nch, ps.nchunks);
     int c = 0;
