@@ -242,3 +242,66 @@ def start_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap_op
     out[live, 0] = ends[live, 1] - rev[:, 1]
     out[live, 1] = ends[live, 2] - rev[:, 2]
     return out
+
+
+# ---------------------------------------------------------------- alignment paths
+
+_OPS = "MID"
+
+
+def path(query, ref, matrix, gap_open: int, gap_extend: int, end=None, start=None):
+    """Alignment path (CIGAR runs) of the reported alignment, from its start
+    cell to its end cell: a list of (length, op), op in 'M' (an aligned pair),
+    'I' (query residues skipped), 'D' (reference residues skipped).
+
+    Reading (the paper returns only the score): over the rectangle between the
+    start and the end pair, walking back from the end, each predecessor pair is
+    the largest (ref index, then query index) that lies on an optimal chain from
+    the start; between two pairs the reference gap is written before the query
+    gap.  Computed by ``oracle_path`` in sw_oracle.c as plain maxima over the
+    rectangle (no recurrence shortcuts).  [] when the score is 0.
+    """
+    q = _u8(query)
+    r = _u8(ref)
+    M = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
+    s, qe, re_ = align(q, r, M, gap_open, gap_extend) if end is None else end
+    if s <= 0:
+        return []
+    qs, rs = start_cell(q, r, M, gap_open, gap_extend, end=(s, qe, re_)) if start is None else start
+    cap = (qe - qs + 1) + (re_ - rs + 1) + 1
+    ops = np.zeros(cap, dtype=np.uint32)
+    lib = _load()
+    lib.oracle_path.restype = ctypes.c_int64
+    lib.oracle_path.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                ctypes.c_int64]
+    n = lib.oracle_path(q.ctypes.data, r.ctypes.data, M.ctypes.data, M.shape[0], int(gap_open),
+                        int(gap_extend), int(qs), int(rs), int(qe), int(re_), int(s),
+                        ops.ctypes.data, cap)
+    if n < 0:
+        raise ValueError("oracle_path failed (%d)" % n)
+    return [(int(v >> 4), _OPS[int(v & 15)]) for v in ops[:n]]
+
+
+def path_score(query, ref, matrix, gap_open: int, gap_extend: int, start, runs) -> int:
+    """Score of an alignment given as CIGAR runs from its start cell (a
+    direct evaluation: pairs scored from the matrix, each gap run by its
+    affine cost)."""
+    q, r = _u8(query), _u8(ref)
+    M = np.asarray(matrix)
+    j, i = start
+    total = 0
+    for L, op in runs:
+        if op == "M":
+            for _ in range(L):
+                total += int(M[q[j]][r[i]])
+                i += 1
+                j += 1
+        else:
+            total -= gap_open + (L - 1) * gap_extend
+            if op == "I":
+                j += L
+            else:
+                i += L
+    return total

@@ -160,3 +160,87 @@ int oracle_sw_batch(int64_t n_pairs,
     free(th);
     return atomic_load(&b.failed) ? -1 : 0;
 }
+
+/*
+ * Alignment path between a start pair (qs, rs) and an end pair (qe, re) of
+ * score S (this library's extension: the paper returns only the score).
+ *
+ * Over the rectangle a = i - rs in [0, A), b = j - qs in [0, B):
+ *   M(a,b)  best score of a chain of matched pairs that starts with the start
+ *           pair and ends with pair (a,b): S[q][r] of (a,b) plus, unless (a,b)
+ *           is the start, the best V(a-1, b-1);
+ *   V(x,y)  best over pairs (x',y') <= (x,y) of M(x',y') - g(x-x') - g(y-y'),
+ *           g(0) = 0, g(L) = GapOpen + (L-1)*GapExtend (a reference gap and a
+ *           query gap between consecutive pairs cost independently);
+ * both written out as plain maxima.  The path is read back from the end
+ * pair: each predecessor is the largest (a', b') -- reference index first,
+ * then query index -- with M(a',b') - g(a-1-a') - g(b-1-b') equal to
+ * V(a-1, b-1), i.e. the largest predecessor lying on an optimal chain from
+ * the start.  Between two consecutive pairs the skipped reference residues
+ * are written first (D), then the skipped query residues (I), then the pair
+ * itself (M).
+ *
+ * ops receives run-length entries (len << 4 | op, op 0 = M, 1 = I, 2 = D) in
+ * forward order; returns their count, -1 on bad arguments or allocation
+ * failure, -2 if no chain from the start reaches the end with score S.
+ */
+static int64_t gap_cost(int64_t L, int64_t go, int64_t ge) { return L == 0 ? 0 : go + (L - 1) * ge; }
+
+int64_t oracle_path(const uint8_t *q, const uint8_t *r, const int32_t *Mx, int32_t alpha,
+                    int64_t go, int64_t ge, int64_t qs, int64_t rs, int64_t qe, int64_t re,
+                    int64_t S, uint32_t *ops, int64_t cap)
+{
+    if (qe < qs || re < rs || qs < 0 || rs < 0 || alpha <= 0) return -1;
+    const int64_t A = re - rs + 1, B = qe - qs + 1;
+    const int64_t NEG = INT64_MIN / 4;
+    int64_t *M = (int64_t *)malloc((size_t)(A * B) * sizeof(int64_t));
+    int64_t *V = (int64_t *)malloc((size_t)(A * B) * sizeof(int64_t));
+    char *rev = (char *)malloc((size_t)(A + B + 1));
+    if (!M || !V || !rev) { free(M); free(V); free(rev); return -1; }
+#define SC(a, b) ((int64_t)Mx[(int)q[qs + (b)] * alpha + (int)r[rs + (a)]])
+    for (int64_t a = 0; a < A; ++a) {
+        for (int64_t b = 0; b < B; ++b) {
+            int64_t m = NEG;
+            if (a == 0 && b == 0) m = SC(0, 0);
+            else if (a > 0 && b > 0 && V[(a - 1) * B + (b - 1)] > NEG) m = SC(a, b) + V[(a - 1) * B + (b - 1)];
+            M[a * B + b] = m;
+            int64_t v = NEG;
+            for (int64_t x = 0; x <= a; ++x)
+                for (int64_t y = 0; y <= b; ++y)
+                    if (M[x * B + y] > NEG) v = max2(v, M[x * B + y] - gap_cost(a - x, go, ge) - gap_cost(b - y, go, ge));
+            V[a * B + b] = v;
+        }
+    }
+    int64_t n = 0, a = A - 1, b = B - 1;
+    int64_t rc = 0;
+    if (M[a * B + b] != S) rc = -2;
+    while (rc == 0 && (a > 0 || b > 0)) {
+        rev[n++] = 'M';
+        const int64_t target = M[a * B + b] - SC(a, b);
+        int64_t fx = -1, fy = -1;
+        for (int64_t x = a - 1; x >= 0 && fx < 0; --x)
+            for (int64_t y = b - 1; y >= 0; --y)
+                if (M[x * B + y] > NEG &&
+                    M[x * B + y] - gap_cost(a - 1 - x, go, ge) - gap_cost(b - 1 - y, go, ge) == target) {
+                    fx = x; fy = y;
+                    break;
+                }
+        if (fx < 0) { rc = -2; break; }
+        for (int64_t k = 0; k < b - 1 - fy; ++k) rev[n++] = 'I';
+        for (int64_t k = 0; k < a - 1 - fx; ++k) rev[n++] = 'D';
+        a = fx;
+        b = fy;
+    }
+    if (rc == 0) rev[n++] = 'M';
+#undef SC
+    int64_t cnt = 0;
+    for (int64_t k = n - 1; rc == 0 && k >= 0;) {
+        const char c = rev[k];
+        int64_t len = 0;
+        while (k >= 0 && rev[k] == c) { ++len; --k; }
+        if (cnt >= cap) { rc = -1; break; }
+        ops[cnt++] = (uint32_t)(len << 4) | (c == 'M' ? 0u : (c == 'I' ? 1u : 2u));
+    }
+    free(M); free(V); free(rev);
+    return rc ? rc : cnt;
+}

@@ -100,3 +100,44 @@ def brute_force_start(q, r, M, go: int, ge: int):
         for j in range(m):
             extend(i, j, i, j, int(M[q[j]][r[i]]))
     return (best[1], best[0])
+
+
+def brute_force_path(q, r, M, go: int, ge: int):
+    """CIGAR runs of the reported alignment by enumeration: every chain from
+    the start pair to the end pair scoring the optimum; of those, the one
+    whose pairs, read from the end backwards, are lexicographically largest
+    ((ref, query) per pair); rendered as D (skipped reference residues), then
+    I (skipped query residues), then M per pair.  Tiny inputs only."""
+    s, qe, re_ = brute_force(q, r, M, go, ge)
+    if s <= 0:
+        return []
+    qs, rs = brute_force_start(q, r, M, go, ge)
+    best = None
+
+    def extend(chain, score):
+        nonlocal best
+        i, j = chain[-1]
+        if (i, j) == (re_, qe):
+            if score == s:
+                key = list(reversed(chain))
+                if best is None or key > best:
+                    best = key
+            return
+        for i2 in range(i + 1, re_ + 1):
+            for j2 in range(j + 1, qe + 1):
+                s2 = score + int(M[q[j2]][r[i2]]) - gap_cost(i2 - i - 1, go, ge) \
+                    - gap_cost(j2 - j - 1, go, ge)
+                extend(chain + [(i2, j2)], s2)
+
+    extend([(rs, qs)], int(M[q[qs]][r[rs]]))
+    chain = list(reversed(best))
+    ops = ["M"]
+    for (i, j), (i2, j2) in zip(chain, chain[1:]):
+        ops += ["D"] * (i2 - i - 1) + ["I"] * (j2 - j - 1) + ["M"]
+    runs = []
+    for o in ops:
+        if runs and runs[-1][1] == o:
+            runs[-1] = (runs[-1][0] + 1, o)
+        else:
+            runs.append((1, o))
+    return runs

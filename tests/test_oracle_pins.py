@@ -335,3 +335,130 @@ def test_start_batch_matches_single():
         assert tuple(st[k]) == oracle.start_cell(q, r, w.matrix, w.gap_open, w.gap_extend)
         if ends[k, 0] > 0:
             assert 0 <= st[k, 0] <= ends[k, 1] and 0 <= st[k, 1] <= ends[k, 2]
+
+
+# ---------------------------------------------------------------- alignment paths
+
+def _gappy_case(rng):
+    alpha = int(rng.integers(2, 4))
+    m, n = int(rng.integers(2, 7)), int(rng.integers(2, 7))
+    q = rng.integers(0, alpha, size=m).tolist()
+    r = rng.integers(0, alpha, size=n).tolist()
+    M = rng.integers(-3, 2, size=(alpha, alpha)).astype(np.int32)
+    M[np.arange(alpha), np.arange(alpha)] = rng.integers(2, 6, size=alpha)
+    go = int(rng.integers(0, 3))
+    ge = int(rng.integers(0, go + 1))
+    return q, r, M, go, ge
+
+
+def test_path_double_gap():
+    Mb = np.full((4, 4), -10, dtype=np.int32)
+    Mb[0, 0] = Mb[1, 1] = 5
+    want = [(1, "M"), (1, "D"), (1, "I"), (1, "M")]
+    assert pins.brute_force_path([0, 2, 1], [0, 3, 1], Mb, 1, 1) == want
+    assert oracle.path([0, 2, 1], [0, 3, 1], Mb, 1, 1) == want
+
+
+def test_path_worked_example():
+    # A/A, C against a gap, G/G, T/T
+    g = json.load(open(os.path.join(GOLDEN, "worked_example.json")))
+    M = np.full((4, 4), g["mismatch"], dtype=np.int32)
+    np.fill_diagonal(M, g["match"])
+    want = [(1, "M"), (1, "I"), (2, "M")]
+    assert oracle.path([0, 1, 2, 3], [0, 2, 3], M, 2, 1) == want
+    assert pins.brute_force_path([0, 1, 2, 3], [0, 2, 3], M, 2, 1) == want
+    assert oracle.path_score([0, 1, 2, 3], [0, 2, 3], M, 2, 1, (0, 0), want) == 7
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_path_brute_force_random(seed):
+    rng = np.random.default_rng(4000 + seed)
+    gaps = 0
+    for _ in range(160):
+        q, r, M, go, ge = (_gappy_case if _ % 2 else _case)(rng)
+        want = pins.brute_force_path(q, r, M, go, ge)
+        assert oracle.path(q, r, M, go, ge) == want
+        gaps += any(op != "M" for _, op in want)
+    assert gaps >= 10
+
+
+def test_path_consistency_larger():
+    """Larger pairs (oracle only): the path starts and ends at the reported
+    cells, consumes exactly the rectangle between them and scores the optimum."""
+    rng = np.random.default_rng(4100)
+    for _ in range(40):
+        alpha = int(rng.integers(2, 21))
+        m, n = int(rng.integers(1, 60)), int(rng.integers(1, 60))
+        q = rng.integers(0, alpha, size=m)
+        r = rng.integers(0, alpha, size=n)
+        M = rng.integers(-4, 4, size=(alpha, alpha)).astype(np.int32)
+        M[np.arange(alpha), np.arange(alpha)] = rng.integers(3, 9, size=alpha)
+        go = int(rng.integers(1, 12))
+        ge = int(rng.integers(0, go + 1))
+        s, qe, re_ = oracle.align(q, r, M, go, ge)
+        runs = oracle.path(q, r, M, go, ge)
+        if s == 0:
+            assert runs == []
+            continue
+        qs, rs = oracle.start_cell(q, r, M, go, ge)
+        assert runs[0][1] == "M" and runs[-1][1] == "M"
+        assert sum(L for L, op in runs if op != "D") == qe - qs + 1
+        assert sum(L for L, op in runs if op != "I") == re_ - rs + 1
+        assert oracle.path_score(q, r, M, go, ge, (qs, rs), runs) == s
+
+
+def test_path_pins_tell_other_rules_apart():
+    """The brute-force pin fixes the tie rule: the smallest instead of the
+    largest predecessor, query index before reference index, and the query gap
+    written before the reference gap each give other paths on some cases."""
+    rng = np.random.default_rng(4200)
+
+    def variant(q, r, M, go, ge, key, igap_first):
+        s, qe, re_ = pins.brute_force(q, r, M, go, ge)
+        if s <= 0:
+            return []
+        qs, rs = pins.brute_force_start(q, r, M, go, ge)
+        chains = []
+
+        def extend(chain, score):
+            i, j = chain[-1]
+            if (i, j) == (re_, qe):
+                if score == s:
+                    chains.append(chain)
+                return
+            for i2 in range(i + 1, re_ + 1):
+                for j2 in range(j + 1, qe + 1):
+                    extend(chain + [(i2, j2)], score + int(M[q[j2]][r[i2]]) -
+                           pins.gap_cost(i2 - i - 1, go, ge) - pins.gap_cost(j2 - j - 1, go, ge))
+
+        extend([(rs, qs)], int(M[q[qs]][r[rs]]))
+        chain = max(chains, key=key)
+        ops = ["M"]
+        for (i, j), (i2, j2) in zip(chain, chain[1:]):
+            d, ins = ["D"] * (i2 - i - 1), ["I"] * (j2 - j - 1)
+            ops += (ins + d if igap_first else d + ins) + ["M"]
+        runs = []
+        for o in ops:
+            if runs and runs[-1][1] == o:
+                runs[-1] = (runs[-1][0] + 1, o)
+            else:
+                runs.append((1, o))
+        return runs
+
+    rules = {
+        "smallest predecessor": (lambda c: [(-i, -j) for i, j in reversed(c)], False),
+        "query index first": (lambda c: [(j, i) for i, j in reversed(c)], False),
+        "query gap first": (lambda c: list(reversed(c)), True),
+    }
+    # found by a seeded search: two optimal predecessors where one has the
+    # larger reference index and the other the larger query index
+    crossing = ([1, 2, 0, 1], [1, 0, 2, 1, 1, 2],
+                np.array([[2, -3, -3], [0, 5, 0], [-3, 0, 2]], dtype=np.int32), 1, 0)
+    # a reference gap and a query gap between the same two pairs (X, Y never
+    # match anything): the bridge beats the mismatch
+    Mb = np.full((4, 4), -10, dtype=np.int32)
+    Mb[0, 0] = Mb[1, 1] = 5
+    bridge = ([0, 2, 1], [0, 3, 1], Mb, 1, 1)
+    cases = [crossing, bridge] + [_gappy_case(rng) for _ in range(400)]
+    for name, (key, igf) in rules.items():
+        assert any(variant(*c, key, igf) != pins.brute_force_path(*c) for c in cases), name
