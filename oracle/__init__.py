@@ -259,7 +259,10 @@ def path(query, ref, matrix, gap_open: int, gap_extend: int, end=None, start=Non
     the largest (ref index, then query index) that lies on an optimal chain from
     the start; between two pairs the reference gap is written before the query
     gap.  Computed by ``oracle_path`` in sw_oracle.c as plain maxima over the
-    rectangle (no recurrence shortcuts).  [] when the score is 0.
+    rectangle (no recurrence shortcuts).  A gap run of length L costs
+    gap_open + (L - 1) * min(gap_extend, gap_open): the Gotoh recurrences
+    score an extension above the opening cost as a fresh opening.  [] when
+    the score is 0.
     """
     q = _u8(query)
     r = _u8(ref)
@@ -291,6 +294,7 @@ def path_score(query, ref, matrix, gap_open: int, gap_extend: int, start, runs) 
     q, r = _u8(query), _u8(ref)
     M = np.asarray(matrix)
     j, i = start
+    gap_extend = min(gap_extend, gap_open)     # as the recurrences price runs
     total = 0
     for L, op in runs:
         if op == "M":

@@ -191,6 +191,10 @@ int64_t oracle_path(const uint8_t *q, const uint8_t *r, const int32_t *Mx, int32
                     int64_t S, uint32_t *ops, int64_t cap)
 {
     if (qe < qs || re < rs || qs < 0 || rs < 0 || alpha <= 0) return -1;
+    /* Gotoh's recurrences may close a gap and open the next one at once, so a
+     * run of k gaps never costs more than k * go: the scores are those of the
+     * extension min(ge, go), and the runs of a path are priced with it. */
+    if (ge > go) ge = go;
     const int64_t A = re - rs + 1, B = qe - qs + 1;
     const int64_t NEG = INT64_MIN / 4;
     int64_t *M = (int64_t *)malloc((size_t)(A * B) * sizeof(int64_t));

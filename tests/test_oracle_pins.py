@@ -351,6 +351,22 @@ def _gappy_case(rng):
     return q, r, M, go, ge
 
 
+def test_path_extension_above_opening():
+    # the scores do not change when gap_extend > gap_open is clamped, so
+    # neither may the paths, and a path's runs add up to the score
+    rng = np.random.default_rng(31)
+    for _ in range(200):
+        q, r, M, go, _ = _gappy_case(rng)
+        ge = go + int(rng.integers(1, 4))
+        s, qe, re_ = oracle.align(q, r, M, go, ge)
+        if s <= 0:
+            continue
+        runs = oracle.path(q, r, M, go, ge)
+        assert runs == oracle.path(q, r, M, go, go)
+        start = oracle.start_cell(q, r, M, go, ge)
+        assert oracle.path_score(q, r, M, go, ge, start, runs) == s
+
+
 def test_path_double_gap():
     Mb = np.full((4, 4), -10, dtype=np.int32)
     Mb[0, 0] = Mb[1, 1] = 5
