@@ -164,6 +164,50 @@ int sw_align_batch(const sw_batch *b, const sw_scoring *sc, sw_result *out);
 int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc, const sw_result *ends,
                           int32_t *query_start, int32_t *ref_start);
 
+/* ---------------------------------------------------------------------------
+ * sw_align_batch_cigar -- paths (CIGAR runs) of the alignments a batch call
+ * found.
+ *
+ * The paper returns only the score; paths are this library's extension.  For
+ * pair k with ends[k].score > 0 and its start cell (query_start[k],
+ * ref_start[k]) as sw_align_batch_starts returns it, the path of an
+ * alignment of score ends[k].score from the start to the end cell, as runs
+ * (length << 4 | op; op SW_CIGAR_M: aligned pairs, SW_CIGAR_I: query
+ * residues skipped, SW_CIGAR_D: reference residues skipped; the BAM codes).
+ * Of all such alignments, walking back from the end cell, the aligned pair
+ * before each aligned pair is the largest (ref index, then query index) on
+ * an optimal path; between two aligned pairs the D run comes before the I
+ * run.  A gap run of length L costs gap_open + (L - 1) * min(gap_extend,
+ * gap_open), the cost the scores are computed with.
+ *
+ * Output, packed: pair k's runs are cigar[cigar_off[k] .. cigar_off[k+1])
+ * (none for score 0); cigar_off has n_pairs + 1 entries, cigar_off[0] = 0.
+ * Pair k never needs more than min(A + B - 1, 3 min(A, B) - 2) runs, with
+ * A = ref_end - ref_start + 1 and B = query_end - query_start + 1.  If the
+ * total exceeds cigar_cap, cigar_off is still filled, cigar is not written,
+ * and SW_EINVAL is returned.
+ *
+ * Computed on the device: one wavefront per pair fills the rectangle between
+ * start and end cell, anchored at the start, keeping four decision bits per
+ * cell (in LDS when they fit, else in device scratch of at most 256 MiB per
+ * launch), then walks them back from the end cell.
+ *
+ * SW_EINVAL: NULL arrays, pair ids or offsets out of range, a start cell
+ * after its end cell or an end cell outside its sequences, no alignment of
+ * score ends[k].score from the start to the end cell, a residue not below
+ * alphabet_size inside a rectangle, or too small a cigar_cap.  SW_EOVERFLOW:
+ * a rectangle whose anchored scores could leave the kernel's int32 range
+ * (about 2^29 / (gap_extend + 1) cells along its sides).  SW_ENOMEM: a
+ * rectangle needing more than 2 GiB of decision bits.  The batch's arrays
+ * follow sw_align_batch's rules (device_resident included); ends,
+ * query_start, ref_start, cigar and cigar_off are host arrays owned by the
+ * caller.  Synchronous; calls are serialised with sw_align_batch_starts.
+ * ------------------------------------------------------------------------- */
+enum { SW_CIGAR_M = 0, SW_CIGAR_I = 1, SW_CIGAR_D = 2 };
+int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc, const sw_result *ends,
+                         const int32_t *query_start, const int32_t *ref_start,
+                         uint32_t *cigar, int64_t cigar_cap, int64_t *cigar_off);
+
 /* Options and statistics for the extended batch call (tests, benchmarks,
  * the autotuner).  Zero-initialise and set what you need. */
 enum { SW_PAIRING_AUTO = 0, SW_PAIRING_ALIGNMENTS = 1, SW_PAIRING_ROWS = 2 };

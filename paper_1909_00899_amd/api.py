@@ -28,7 +28,8 @@ SW_FLAG_SATURATED = 1
 EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align",
             "sw_align_batch", "sw_align_batch_ex", "sw_server_create", "sw_server_submit",
             "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay",
-            "sw_autotune", "sw_tune_set", "sw_tune_get", "sw_align_batch_starts"]
+            "sw_autotune", "sw_tune_set", "sw_tune_get", "sw_align_batch_starts",
+            "sw_align_batch_cigar"]
 
 
 class NativeLibraryError(RuntimeError):
@@ -157,6 +158,9 @@ def load():
                                       ctypes.POINTER(Stats)]
     lib.sw_align_batch_starts.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.sw_align_batch_cigar.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     lib.sw_autotune.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), ctypes.c_int64,
                                 ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_int32)]
@@ -319,6 +323,50 @@ def sw_align_batch_starts(query_res, query_off, ref_res, ref_off, pair_ref, matr
                                      ends.ctypes.data if npairs else None, qs.ctypes.data,
                                      rs.ctypes.data))
     return qs[:npairs], rs[:npairs]
+
+
+SW_CIGAR_M, SW_CIGAR_I, SW_CIGAR_D = 0, 1, 2
+CIGAR_OPS = "MID"
+
+
+def sw_align_batch_cigar(query_res, query_off, ref_res, ref_off, pair_ref, matrix,
+                         gap_open: int, gap_extend: int, results, query_start, ref_start,
+                         pair_query=None, cigar_cap=None):
+    """Paths of the alignments ``sw_align_batch`` returned, from the start cells
+    ``sw_align_batch_starts`` returned.  Returns (runs, offsets): pair k's runs
+    are runs[offsets[k]:offsets[k + 1]], each ``length << 4 | op`` (op 0 M,
+    1 I, 2 D); ``decode_cigar`` turns them into (length, op letter) lists.
+    ``cigar_cap`` overrides the run capacity passed (default: the bound the
+    library documents, which always suffices)."""
+    lib = load()
+    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, None
+                                  if pair_query is None else pair_query, SW_PREC_AUTO)
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    ends = np.ascontiguousarray(np.asarray(results, dtype=np.int32))
+    qs = np.ascontiguousarray(np.asarray(query_start, dtype=np.int32))
+    rs = np.ascontiguousarray(np.asarray(ref_start, dtype=np.int32))
+    if ends.shape != (npairs, 4) or qs.shape != (npairs,) or rs.shape != (npairs,):
+        raise ValueError("results must be (n_pairs, 4), query_start and ref_start (n_pairs,)")
+    # capacity: the library's bound on the runs of each rectangle
+    live = ends[:, 0] > 0
+    A = (ends[:, 2] - rs).astype(np.int64) + 1
+    B = (ends[:, 1] - qs).astype(np.int64) + 1
+    bound = np.where(live, np.minimum(A + B - 1, 3 * np.minimum(A, B) - 2), 0)
+    cap = int(np.clip(bound, 0, None).sum()) if cigar_cap is None else int(cigar_cap)
+    runs = np.empty(max(cap, 1), dtype=np.uint32)
+    off = np.empty(npairs + 1, dtype=np.int64)
+    _check(lib.sw_align_batch_cigar(ctypes.byref(b), ctypes.byref(sc),
+                                    ends.ctypes.data if npairs else None,
+                                    qs.ctypes.data if npairs else None,
+                                    rs.ctypes.data if npairs else None, runs.ctypes.data, cap,
+                                    off.ctypes.data))
+    return runs[:off[-1]], off
+
+
+def decode_cigar(runs, offsets, k: int) -> list:
+    """Pair k's runs as [(length, 'M' | 'I' | 'D'), ...]."""
+    seg = runs[offsets[k]:offsets[k + 1]]
+    return [(int(v >> 4), CIGAR_OPS[int(v & 15)]) for v in seg]
 
 
 def align_workload(w, **kw) -> BatchOutput:

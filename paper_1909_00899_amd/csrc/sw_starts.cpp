@@ -1,4 +1,5 @@
-// Start cells of a batch's alignments (include/sw.h, sw_align_batch_starts).
+// Start cells and paths of a batch's alignments (include/sw.h,
+// sw_align_batch_starts and sw_align_batch_cigar).
 //
 // The start of the reported alignment of a pair is the end cell of the same
 // local alignment problem on the reversed prefixes q[0..query_end] and
@@ -18,6 +19,7 @@
 //   batch path (device or host planner, int32 reruns).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -47,6 +49,8 @@ struct StartsWork {
   DevBuf src_q, src_r;   // host-resident residue sets, uploaded
   DevBuf rev_q, rev_r;   // reversed query / prefixes
   DevBuf tab;            // offsets (int64), pair ids and first rows (int32)
+  // paths
+  DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off, tr_bits, tr_carry;
 };
 StartsWork g_starts;
 
@@ -220,27 +224,11 @@ int starts_per_pair(const Batch &B, const sw_scoring *sc, const std::vector<int>
   return SW_OK;
 }
 
-}  // namespace
-
-extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
-                                     const sw_result *ends, int32_t *query_start,
-                                     int32_t *ref_start) {
-  if (!b) { set_error("batch is NULL"); return SW_EINVAL; }
-  if (b->n_pairs < 0 || b->n_queries < 0 || b->n_refs < 0) { set_error("negative count"); return SW_EINVAL; }
-  if (b->precision != SW_PREC_AUTO && b->precision != SW_PREC_I32) { set_error("bad precision"); return SW_EINVAL; }
-  Scoring S;
-  int rc = prepare_scoring(sc, S);
-  if (rc) return rc;
+// The batch's offsets and pair ids on the host (validated), its residues on
+// the device (uploaded when host-resident), in the order of the caller's
+// stream.  Entry checks common to the starts and path calls.
+int load_batch(const sw_batch *b, StartsWork &W, Batch &B) {
   const int np = b->n_pairs;
-  if (np == 0) return SW_OK;
-  if (!ends || !query_start || !ref_start) { set_error("ends or an output array is NULL"); return SW_EINVAL; }
-  if (!b->query_off || !b->ref_off || !b->pair_ref || b->n_queries < 1 || b->n_refs < 1) {
-    set_error("batch arrays are NULL or empty");
-    return SW_EINVAL;
-  }
-  if ((rc = ensure_init())) return rc;
-  std::lock_guard<std::mutex> g(g_starts.mu);
-  StartsWork &W = g_starts;
   HIPCHK(hipSetDevice(g_ctx.device));
   if (!W.st) HIPCHK(hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking));
   const bool dev = b->device_resident != 0;
@@ -254,10 +242,8 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
     (void)hipEventDestroy(ev);
     HIPCHK(e);
   }
-  // ---- the batch's offsets and pair ids on the host (validated here)
-  Batch B;
+  int rc;
   B.b = b;
-  B.ends = ends;
   if ((rc = read_back(B.qoff, b->query_off, (size_t)b->n_queries + 1, dev)) ||
       (rc = read_back(B.roff, b->ref_off, (size_t)b->n_refs + 1, dev)) ||
       (rc = read_back(B.pr, b->pair_ref, (size_t)np, dev)))
@@ -271,15 +257,58 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
     if (B.qoff[k] < 0 || B.qoff[k + 1] < B.qoff[k]) { set_error("query offsets not nondecreasing"); return SW_EINVAL; }
   for (int k = 0; k < b->n_refs; ++k)
     if (B.roff[k] < 0 || B.roff[k + 1] < B.roff[k]) { set_error("reference offsets not nondecreasing"); return SW_EINVAL; }
+  for (int k = 0; k < np; ++k)
+    if (B.pq[k] < 0 || B.pq[k] >= b->n_queries || B.pr[k] < 0 || B.pr[k] >= b->n_refs) {
+      set_error("pair %d refers to a query or reference out of range", k);
+      return SW_EINVAL;
+    }
+  B.d_q = b->query_res;
+  B.d_r = b->ref_res;
+  if (!dev) {
+    const size_t qb = (size_t)B.qoff[b->n_queries], rb = (size_t)B.roff[b->n_refs];
+    if ((rc = W.src_q.ensure(qb + 1)) || (rc = W.src_r.ensure(rb + 1))) return rc;
+    if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, qb, hipMemcpyHostToDevice, W.st));
+    if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, rb, hipMemcpyHostToDevice, W.st));
+    B.d_q = W.src_q.as<uint8_t>();
+    B.d_r = W.src_r.as<uint8_t>();
+  }
+  return SW_OK;
+}
+
+int check_batch_args(const sw_batch *b) {
+  if (!b) { set_error("batch is NULL"); return SW_EINVAL; }
+  if (b->n_pairs < 0 || b->n_queries < 0 || b->n_refs < 0) { set_error("negative count"); return SW_EINVAL; }
+  if (b->precision != SW_PREC_AUTO && b->precision != SW_PREC_I32) { set_error("bad precision"); return SW_EINVAL; }
+  if (b->n_pairs > 0 && (!b->query_off || !b->ref_off || !b->pair_ref || b->n_queries < 1 || b->n_refs < 1)) {
+    set_error("batch arrays are NULL or empty");
+    return SW_EINVAL;
+  }
+  return SW_OK;
+}
+
+}  // namespace
+
+extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
+                                     const sw_result *ends, int32_t *query_start,
+                                     int32_t *ref_start) {
+  int rc = check_batch_args(b);
+  if (rc) return rc;
+  Scoring S;
+  if ((rc = prepare_scoring(sc, S))) return rc;
+  const int np = b->n_pairs;
+  if (np == 0) return SW_OK;
+  if (!ends || !query_start || !ref_start) { set_error("ends or an output array is NULL"); return SW_EINVAL; }
+  if ((rc = ensure_init())) return rc;
+  std::lock_guard<std::mutex> g(g_starts.mu);
+  StartsWork &W = g_starts;
+  Batch B;
+  B.ends = ends;
+  if ((rc = load_batch(b, W, B))) return rc;
   std::vector<int> live;
   bool one_query = true;
   for (int k = 0; k < np; ++k) {
     const sw_result &e = ends[k];
     query_start[k] = ref_start[k] = -1;
-    if (B.pq[k] < 0 || B.pq[k] >= b->n_queries || B.pr[k] < 0 || B.pr[k] >= b->n_refs) {
-      set_error("pair %d refers to a query or reference out of range", k);
-      return SW_EINVAL;
-    }
     if (e.score <= 0) continue;
     const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
     const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
@@ -292,17 +321,6 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
     live.push_back(k);
   }
   if (live.empty()) return SW_OK;
-  // ---- residues on the device
-  B.d_q = b->query_res;
-  B.d_r = b->ref_res;
-  if (!dev) {
-    const size_t qb = (size_t)B.qoff[b->n_queries], rb = (size_t)B.roff[b->n_refs];
-    if ((rc = W.src_q.ensure(qb + 1)) || (rc = W.src_r.ensure(rb + 1))) return rc;
-    if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, qb, hipMemcpyHostToDevice, W.st));
-    if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, rb, hipMemcpyHostToDevice, W.st));
-    B.d_q = W.src_q.as<uint8_t>();
-    B.d_r = W.src_r.as<uint8_t>();
-  }
   std::vector<int> rest;
   int seg = 0;
   const int q0 = B.pq[live[0]];
@@ -320,3 +338,196 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
   }
   return SW_OK;
 }
+
+// ------------------------------------------------------------------ paths
+
+namespace {
+
+constexpr int64_t kTraceScratchBytes = 256ll << 20;   // device-memory decision bits per launch
+constexpr int kTraceMaxWaves = 4096;
+
+// Runs a path can have between start and end: every run but the first is
+// preceded by a change of operation, M runs alternate with one or two gap
+// runs, and a rectangle of A x B cells holds at most min(A, B) pairs.
+int64_t run_bound(int64_t A, int64_t B) {
+  return std::min(A + B - 1, 3 * std::min(A, B) - 2);
+}
+
+}  // namespace
+
+extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
+                                    const sw_result *ends, const int32_t *query_start,
+                                    const int32_t *ref_start, uint32_t *cigar,
+                                    int64_t cigar_cap, int64_t *cigar_off) {
+  int rc = check_batch_args(b);
+  if (rc) return rc;
+  Scoring S;
+  if ((rc = prepare_scoring(sc, S))) return rc;
+  const int np = b->n_pairs;
+  if (!cigar_off) { set_error("cigar_off is NULL"); return SW_EINVAL; }
+  cigar_off[0] = 0;
+  if (np == 0) return SW_OK;
+  if (!ends || !query_start || !ref_start) { set_error("ends or starts are NULL"); return SW_EINVAL; }
+  if (cigar_cap < 0 || (cigar_cap > 0 && !cigar)) { set_error("cigar is NULL or its capacity negative"); return SW_EINVAL; }
+  if ((rc = ensure_init())) return rc;
+  std::lock_guard<std::mutex> g(g_starts.mu);
+  StartsWork &W = g_starts;
+  Batch B;
+  B.ends = ends;
+  if ((rc = load_batch(b, W, B))) return rc;
+  int64_t maxabs = 0;
+  for (int v : S.M) maxabs = std::max<int64_t>(maxabs, v < 0 ? -(int64_t)v : v);
+  // ---- one rectangle per pair with a positive score; LDS-sized ones first
+  std::vector<swk::TracePair> lds, glob;
+  int64_t region = 0;
+  for (int k = 0; k < np; ++k) {
+    const sw_result &e = ends[k];
+    if (e.score <= 0) continue;
+    const int qs = query_start[k], rs = ref_start[k];
+    const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
+    const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
+    if (qs < 0 || qs > e.query_end || e.query_end >= m || rs < 0 || rs > e.ref_end ||
+        e.ref_end >= n) {
+      set_error("pair %d: start (%d, %d) and end (%d, %d) are not a rectangle of its %lld x %lld "
+                "sequences", k, qs, rs, e.query_end, e.ref_end, (long long)m, (long long)n);
+      return SW_EINVAL;
+    }
+    const int64_t A = e.ref_end - rs + 1, Bq = e.query_end - qs + 1;
+    // every reachable value stays above -2^29 and every row term below 2^30
+    const int64_t lo = 2 * (maxabs + S.go) + (A + Bq + 2 * swk::kTraceTileCols) * (S.ge + 1);
+    const int64_t hi = std::min(A, Bq) * (int64_t)S.max_s + (Bq + swk::kTraceTileCols) * S.ge;
+    if (lo >= (1ll << 29) || hi >= (1ll << 30)) {
+      set_error("pair %d: a %lld x %lld rectangle leaves the int32 range of the path kernel", k,
+                (long long)A, (long long)Bq);
+      return SW_EOVERFLOW;
+    }
+    swk::TracePair tp;
+    tp.q = B.qoff[B.pq[k]] + qs;
+    tp.r = B.roff[B.pr[k]] + rs;
+    tp.out = region;
+    tp.A = (int32_t)A;
+    tp.B = (int32_t)Bq;
+    tp.score = e.score;
+    tp.cap = (int32_t)run_bound(A, Bq);
+    tp.id = k;
+    tp.pad = 0;
+    region += tp.cap;
+    const int64_t tiles = (Bq + swk::kTraceTileCols - 1) / swk::kTraceTileCols;
+    (A * tiles <= swk::kTraceLdsRowTiles ? lds : glob).push_back(tp);
+  }
+  // device-memory rectangles: largest first, in groups of similar size
+  std::sort(glob.begin(), glob.end(), [](const swk::TracePair &x, const swk::TracePair &y) {
+    const int64_t nx = (int64_t)x.A * ((x.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols);
+    const int64_t ny = (int64_t)y.A * ((y.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols);
+    return nx > ny;
+  });
+  struct Group { int first, count, waves; int64_t slot_words; int carry_rows; };
+  std::vector<Group> groups;
+  int64_t bits_words = 0, carry_ints = 0;
+  for (int t = 0; t < (int)glob.size();) {
+    const swk::TracePair &P0 = glob[t];
+    const int64_t slot = (int64_t)P0.A * ((P0.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols) * 64;
+    if (slot * 2 > (2ll << 30)) {
+      set_error("pair %d: a %d x %d rectangle needs more than 2 GiB of path scratch", P0.id,
+                P0.A, P0.B);
+      return SW_ENOMEM;
+    }
+    int u = t, carry_rows = 1;
+    while (u < (int)glob.size()) {   // members need at least half the first one's slot
+      const swk::TracePair &P = glob[u];
+      const int64_t need = (int64_t)P.A * ((P.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols) * 64;
+      if (2 * need < slot) break;
+      carry_rows = std::max(carry_rows, P.A);
+      ++u;
+    }
+    const int64_t per_wave = slot * 2 + 6ll * carry_rows * 4;
+    const int waves = (int)std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)(u - t), kTraceScratchBytes / per_wave, kTraceMaxWaves}));
+    groups.push_back({t, u - t, waves, slot, carry_rows});
+    bits_words = std::max<int64_t>(bits_words, slot * waves);
+    carry_ints = std::max<int64_t>(carry_ints, 6ll * carry_rows * waves);
+    t = u;
+  }
+  const int nl = (int)lds.size(), ng = (int)glob.size(), nt = nl + ng;
+  std::vector<int32_t> counts(np, 0);
+  if (nt > 0) {
+    if ((rc = W.tr_pairs.ensure((size_t)nt * sizeof(swk::TracePair))) ||
+        (rc = W.tr_mat.ensure((size_t)S.alpha * S.alpha * sizeof(int32_t))) ||
+        (rc = W.tr_runs.ensure((size_t)std::max<int64_t>(region, 1) * sizeof(uint32_t))) ||
+        (rc = W.tr_nruns.ensure((size_t)np * sizeof(int32_t))) ||
+        (rc = W.tr_off.ensure((size_t)(np + 1) * sizeof(int64_t))) ||
+        (rc = W.tr_bits.ensure((size_t)std::max<int64_t>(bits_words, 1) * sizeof(uint16_t))) ||
+        (rc = W.tr_carry.ensure((size_t)std::max<int64_t>(carry_ints, 1) * sizeof(int32_t))))
+      return rc;
+    swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
+    if (nl) HIPCHK(hipMemcpyAsync(dp, lds.data(), nl * sizeof(swk::TracePair), hipMemcpyHostToDevice, W.st));
+    if (ng) HIPCHK(hipMemcpyAsync(dp + nl, glob.data(), ng * sizeof(swk::TracePair), hipMemcpyHostToDevice, W.st));
+    HIPCHK(hipMemcpyAsync(W.tr_mat.p, S.M.data(), (size_t)S.alpha * S.alpha * sizeof(int32_t),
+                          hipMemcpyHostToDevice, W.st));
+    swk::TraceArgs ta;
+    ta.qres = B.d_q;
+    ta.rres = B.d_r;
+    ta.matrix = W.tr_mat.as<int32_t>();
+    ta.alpha = S.alpha;
+    ta.go = S.go;
+    ta.ge = S.ge;
+    ta.gbits = W.tr_bits.as<uint16_t>();
+    ta.gcarry = W.tr_carry.as<int32_t>();
+    ta.cigar = W.tr_runs.as<uint32_t>();
+    ta.n_runs = W.tr_nruns.as<int32_t>();
+    ta.pairs = dp;
+    ta.n = nl;
+    ta.slot_words = 0;
+    ta.carry_rows = 0;
+    HIPCHK(swk::launch_trace(true, ta, nl, W.st));
+    for (const Group &gr : groups) {
+      ta.pairs = dp + nl + gr.first;
+      ta.n = gr.count;
+      ta.slot_words = gr.slot_words;
+      ta.carry_rows = gr.carry_rows;
+      HIPCHK(swk::launch_trace(false, ta, gr.waves, W.st));
+    }
+    std::vector<int32_t> dev_counts(np);
+    HIPCHK(hipMemcpyAsync(dev_counts.data(), W.tr_nruns.p, (size_t)np * sizeof(int32_t),
+                          hipMemcpyDeviceToHost, W.st));
+    HIPCHK(hipStreamSynchronize(W.st));
+    for (const std::vector<swk::TracePair> *v : {&lds, &glob})
+      for (const swk::TracePair &P : *v) {
+        const int c = dev_counts[P.id];
+        if (c == swk::kTraceBadResidue) {
+          set_error("pair %d: a residue code inside its alignment is not below alphabet_size", P.id);
+          return SW_EINVAL;
+        }
+        if (c == swk::kTraceInconsistent) {
+          set_error("pair %d: no alignment of score %d runs from its start (%d, %d) to its end "
+                    "(%d, %d)", P.id, P.score, query_start[P.id], ref_start[P.id],
+                    ends[P.id].query_end, ends[P.id].ref_end);
+          return SW_EINVAL;
+        }
+        if (c < 1 || c > P.cap) {
+          set_error("pair %d: internal path error (%d runs, bound %d)", P.id, c, P.cap);
+          return SW_EDEVICE;
+        }
+        counts[P.id] = c;
+      }
+  }
+  for (int k = 0; k < np; ++k) cigar_off[k + 1] = cigar_off[k] + counts[k];
+  if (cigar_off[np] > cigar_cap) {
+    set_error("the paths need %lld runs, cigar holds %lld", (long long)cigar_off[np],
+              (long long)cigar_cap);
+    return SW_EINVAL;
+  }
+  if (nt > 0 && cigar_off[np] > 0) {
+    if ((rc = W.tr_packed.ensure((size_t)cigar_off[np] * sizeof(uint32_t)))) return rc;
+    HIPCHK(hipMemcpyAsync(W.tr_off.p, cigar_off, (size_t)(np + 1) * sizeof(int64_t),
+                          hipMemcpyHostToDevice, W.st));
+    HIPCHK(swk::launch_pack_runs(W.tr_pairs.as<swk::TracePair>(), nt, W.tr_nruns.as<int32_t>(),
+                                 W.tr_off.as<int64_t>(), W.tr_runs.as<uint32_t>(),
+                                 W.tr_packed.as<uint32_t>(), W.st));
+    HIPCHK(hipMemcpyAsync(cigar, W.tr_packed.p, (size_t)cigar_off[np] * sizeof(uint32_t),
+                          hipMemcpyDeviceToHost, W.st));
+    HIPCHK(hipStreamSynchronize(W.st));
+  }
+  return SW_OK;
+}
+

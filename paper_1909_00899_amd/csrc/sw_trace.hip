@@ -1,0 +1,262 @@
+// Alignment paths (include/sw.h, sw_align_batch_cigar).
+//
+// The paper's kernels return only the maximum (Algorithm 6 keeps Max); the
+// path of the reported alignment is this library's extension.  With its start
+// and end cell known, the path lies in the rectangle between them and every
+// cell of it is scored relative to the start pair (no zero floor).  Writing
+// a = reference index and b = query index inside the rectangle, s(a, b) the
+// substitution score and g(k) = go + (k - 1) ge the cost of a k-gap run:
+//
+//   M(a, b)  = s(a, b) + V(a-1, b-1)        (M(0, 0) = s(0, 0); other edge pairs unreachable)
+//   Eg(a, b) = max(M(a, b-1) - go, Eg(a, b-1) - ge)      query residues skipped along row a
+//   G(a, b)  = max(M(a, b), Eg(a, b))                    best "pair, then query gap" in row a
+//   Fv(a, b) = max(G(a-1, b) - go, Fv(a-1, b) - ge)      reference residues skipped down column b
+//   V(a, b)  = max(G(a, b), Fv(a, b))
+//
+// V(a, b) is the best score of a chain from the start whose last pair (x, y)
+// satisfies x <= a, y <= b, counting the gaps to (a, b): exactly Gotoh's H
+// anchored at the start, with the two gap states ordered so that a walk back
+// from V meets the reference gap first and the query gap second.  Preferring
+// G over Fv and an opening over an extension therefore picks, before each
+// aligned pair, the predecessor pair with the largest reference index, then
+// the largest query index: the path rule of the library (sw.h).
+//
+// Layout: one wavefront per pair; the query span is cut into tiles of 256
+// columns, four consecutive columns per lane.  A row of a tile costs one
+// four-column pass per lane plus one max-plus scan over the 64 lanes for Eg
+// (Eg(a, b) = max_{y<b} (M(a, y) + y ge) - go - (b - 1) ge, the scan of the
+// paper's Fscan turned along the row) and DPP moves for the diagonal.  Four
+// decision bits per cell are kept -- in LDS when the rectangle fits, in a
+// per-wavefront slot of device memory otherwise -- and the wavefront then
+// walks them back from the end cell, writing CIGAR runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "sw_internal.h"
+
+namespace swk {
+namespace dev {
+namespace {
+
+constexpr int kNeg = -(1 << 30);     // unreachable; every reachable value stays above kNeg / 2
+
+__device__ __forceinline__ int dpp_wave_shr1(int old, int x) {
+  return __builtin_amdgcn_update_dpp(old, x, 0x138, 0xf, 0xf, false);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_move(int x) {
+  return __builtin_amdgcn_update_dpp(kNeg, x, CTRL, ROWMASK, 0xf, false);
+}
+
+// inclusive max over lanes 0..lane
+__device__ __forceinline__ int wave_max_scan(int x) {
+  x = max(x, dpp_move<0x111, 0xf>(x));   // row_shr:1
+  x = max(x, dpp_move<0x112, 0xf>(x));   // row_shr:2
+  x = max(x, dpp_move<0x114, 0xf>(x));   // row_shr:4
+  x = max(x, dpp_move<0x118, 0xf>(x));   // row_shr:8
+  x = max(x, dpp_move<0x142, 0xa>(x));   // row_bcast:15 into rows 1 and 3
+  x = max(x, dpp_move<0x143, 0xc>(x));   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ int readlane(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+
+template <bool LB>
+__global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
+  extern __shared__ int smem[];
+  int *smat = smem;                                            // [query code][ref code]
+  uint16_t *lbits = (uint16_t *)(smem + kMaxAlpha * kMaxAlpha);
+  int *lcarry = (int *)(lbits + kTraceLdsRowTiles * 64);
+  const int L = threadIdx.x;
+  const int alpha = a.alpha, go = a.go, ge = a.ge;
+  for (int k = L; k < alpha * alpha; k += 64) smat[k] = a.matrix[k];
+  __syncthreads();
+
+  for (int p = blockIdx.x; p < a.n; p += gridDim.x) {
+    const TracePair P = a.pairs[p];
+    const int A = P.A, B = P.B, T = (B + kTraceTileCols - 1) / kTraceTileCols;
+    uint16_t *bits = LB ? lbits : a.gbits + (size_t)blockIdx.x * a.slot_words;
+    int *carry = LB ? lcarry : a.gcarry + (size_t)blockIdx.x * 6 * a.carry_rows;
+    const int crow = LB ? kTraceLdsCarryRows : a.carry_rows;
+    bool bad = false, ok = false;
+
+    for (int t = 0; t < T; ++t) {
+      const int base = t * kTraceTileCols, jc0 = base + 4 * L;
+      const int *cr = carry + ((t + 1) & 1) * 3 * crow;   // written by tile t - 1
+      int *cw = carry + (t & 1) * 3 * crow;                // read by tile t + 1
+      int qb[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int code = jc0 + c < B ? (int)a.qres[P.q + jc0 + c] : 0;
+        bad |= code >= alpha;
+        qb[c] = min(code, alpha - 1) * alpha;
+      }
+      int Vp[4], Gp[4], Fp[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) Vp[c] = Gp[c] = Fp[c] = kNeg;
+      int cv_prev = kNeg;                      // V(i-1, base-1)
+      int rreg = 0, crv = kNeg, crm = kNeg, crp = kNeg;
+      for (int i = 0; i < A; ++i) {
+        if ((i & 63) == 0) {                   // 64 rows of residues (and carries) at a time
+          const int row = i + L;
+          rreg = row < A ? (int)a.rres[P.r + row] : 0;
+          if (t == 0) bad |= rreg >= alpha;
+          if (t > 0 && row < A) {
+            crv = cr[3 * row];
+            crm = cr[3 * row + 1];
+            crp = cr[3 * row + 2];
+          }
+        }
+        const int rc = min(readlane(rreg, i & 63), alpha - 1);
+        const int cv_in = t ? readlane(crv, i & 63) : kNeg;   // V(i, base-1)
+        const int cm_in = t ? readlane(crm, i & 63) : kNeg;   // M(i, base-1)
+        const int cp_in = t ? readlane(crp, i & 63) : kNeg;   // max_{y<base} M(i, y) + y ge
+        int Mv[4];
+        Mv[0] = max(smat[qb[0] + rc] + dpp_wave_shr1(cv_prev, Vp[3]), kNeg);
+        Mv[1] = max(smat[qb[1] + rc] + Vp[0], kNeg);
+        Mv[2] = max(smat[qb[2] + rc] + Vp[1], kNeg);
+        Mv[3] = max(smat[qb[3] + rc] + Vp[2], kNeg);
+        if (i == 0 && jc0 == 0) Mv[0] = smat[qb[0] + rc];      // the start pair
+        int w[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w[c] = Mv[c] + (jc0 + c) * ge;
+        int lp[4];
+        lp[0] = kNeg;
+        lp[1] = w[0];
+        lp[2] = max(w[0], w[1]);
+        lp[3] = max(lp[2], w[2]);
+        const int agg = max(lp[3], w[3]);
+        const int exc = max(dpp_wave_shr1(kNeg, wave_max_scan(agg)), cp_in);
+        const int m_left = dpp_wave_shr1(cm_in, Mv[3]);          // M(i, jc0 - 1)
+        uint32_t word = 0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int j = jc0 + c;
+          const int eg = max(max(exc, lp[c]) - go - (j - 1) * ge, kNeg);
+          const int mprev = c ? Mv[c - 1] : m_left;
+          const int g = max(Mv[c], eg);
+          const int fo = Gp[c] - go, fe = Fp[c] - ge;
+          const int f = max(max(fo, fe), kNeg);
+          const int v = max(g, f);
+          const uint32_t nib = (uint32_t)(g >= f) | (uint32_t)(fo >= fe) << 1 |
+                               (uint32_t)(Mv[c] >= eg) << 2 | (uint32_t)(mprev - go == eg) << 3;
+          word |= nib << (4 * c);
+          Vp[c] = v;
+          Gp[c] = g;
+          Fp[c] = f;
+        }
+        bits[((size_t)t * A + i) * 64 + L] = (uint16_t)word;
+        if (t + 1 < T && L == 63) {
+          cw[3 * i] = Vp[3];
+          cw[3 * i + 1] = Mv[3];
+          cw[3 * i + 2] = max(exc, agg);
+        }
+        cv_prev = cv_in;
+        if (t == T - 1 && i == A - 1) {
+          const int jb = B - 1 - jc0;
+          const int mend = jb == 0 ? Mv[0] : jb == 1 ? Mv[1] : jb == 2 ? Mv[2] : Mv[3];
+          ok = __ballot(jb >= 0 && jb < 4 && mend == P.score) != 0;
+        }
+      }
+      __threadfence();                         // carries (and bits) before their readers
+    }
+    bad = __ballot(bad) != 0;
+
+    // ---- walk back from the end pair; runs written backward from the end of
+    // the pair's region (the last run of the path at out + cap - 1)
+    int nrun = 0;
+    bool fail = !ok || bad;
+    const int64_t end = P.out + P.cap;
+    auto emit = [&](uint32_t v) {
+      if (nrun < P.cap && L == 0) a.cigar[end - 1 - nrun] = v;
+      ++nrun;
+    };
+    auto nib_at = [&](int i, int j) -> int {
+      const uint32_t wd = bits[((size_t)(j / kTraceTileCols) * A + i) * 64 + (j % kTraceTileCols) / 4];
+      return (int)(wd >> (4 * (j & 3))) & 15;
+    };
+    if (!fail) {
+      int ra = A - 1, qb_ = B - 1, mrun = 1, guard = A + B + 2;
+      while ((ra | qb_) != 0) {
+        if (ra == 0 || qb_ == 0 || --guard < 0) { fail = true; break; }
+        int i = ra - 1, j = qb_ - 1, nd = 0, ni = 0;
+        int nib = nib_at(i, j);
+        if (!(nib & 1)) {                      // a reference gap ends at (i, j)
+          for (;;) {
+            ++nd;
+            const bool open = nib & 2;
+            if (--i < 0) { fail = true; break; }
+            nib = nib_at(i, j);
+            if (open) break;
+          }
+          if (fail) break;
+        }
+        if (!(nib & 4)) {                      // a query gap ends at (i, j)
+          for (;;) {
+            ++ni;
+            const bool open = nib & 8;
+            if (--j < 0) { fail = true; break; }
+            nib = nib_at(i, j);
+            if (open) break;
+          }
+          if (fail) break;
+        }
+        if (nd | ni) {
+          emit((uint32_t)mrun << 4 | kCigarM);
+          if (ni) emit((uint32_t)ni << 4 | kCigarI);
+          if (nd) emit((uint32_t)nd << 4 | kCigarD);
+          mrun = 0;
+        }
+        ++mrun;
+        ra = i;
+        qb_ = j;
+      }
+      if (!fail) emit((uint32_t)mrun << 4 | kCigarM);
+    }
+    if (L == 0) a.n_runs[P.id] = bad ? kTraceBadResidue : fail ? kTraceInconsistent : nrun;
+  }
+}
+
+// Pair t's runs (the last n_runs[id] entries of its region) to
+// cigar_dst[dst_off[id] ..]; a workgroup per pair, grid-stride.
+__global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, int n,
+                                                        const int32_t *n_runs,
+                                                        const int64_t *dst_off,
+                                                        const uint32_t *src, uint32_t *dst) {
+  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+    const TracePair P = pairs[t];
+    const int cnt = min(n_runs[P.id], P.cap);   // the host checked every count already
+    const int64_t s0 = P.out + P.cap - cnt, d0 = dst_off[P.id];
+    for (int k = threadIdx.x; k < cnt; k += blockDim.x) dst[d0 + k] = src[s0 + k];
+  }
+}
+
+}  // namespace
+}  // namespace dev
+
+size_t trace_lds_bytes(bool lds_bits) {
+  size_t b = (size_t)kMaxAlpha * kMaxAlpha * sizeof(int);
+  if (lds_bits) b += (size_t)kTraceLdsRowTiles * 64 * sizeof(uint16_t) + 6 * kTraceLdsCarryRows * sizeof(int);
+  return b;
+}
+
+hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs,
+                            const int64_t *dst_off, const uint32_t *src, uint32_t *dst,
+                            hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::pack_runs_kernel, dim3(std::min(n, 65535)), dim3(256), 0, st, pairs, n,
+                     n_runs, dst_off, src, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(bool lds_bits, const TraceArgs &a, int grid, hipStream_t st) {
+  if (a.n <= 0 || grid <= 0) return hipSuccess;
+  if (lds_bits)
+    hipLaunchKernelGGL(dev::trace_kernel<true>, dim3(grid), dim3(64), trace_lds_bytes(true), st, a);
+  else
+    hipLaunchKernelGGL(dev::trace_kernel<false>, dim3(grid), dim3(64), trace_lds_bytes(false), st, a);
+  return hipGetLastError();
+}
+
+}  // namespace swk

@@ -161,3 +161,27 @@ def test_starts_rejects_bad_arguments(lib):
     ends = np.zeros((1, 4), dtype=np.int32)
     assert lib.sw_align_batch_starts(ctypes.byref(b), ctypes.byref(sc), ends.ctypes.data,
                                      qs.ctypes.data, qs.ctypes.data) == api.SW_EINVAL
+
+
+def test_cigar_rejects_bad_arguments(lib):
+    M = np.eye(4, dtype=np.int32)
+    sc, keep = _sc(M)
+    b = api.Batch()
+    z = np.zeros(2, dtype=np.int32)
+    off = np.full(3, 7, dtype=np.int64)
+    runs = np.zeros(4, dtype=np.uint32)
+    assert lib.sw_align_batch_cigar(None, ctypes.byref(sc), None, z.ctypes.data, z.ctypes.data,
+                                    runs.ctypes.data, 4, off.ctypes.data) == api.SW_EINVAL
+    b.n_pairs = 0
+    assert lib.sw_align_batch_cigar(ctypes.byref(b), ctypes.byref(sc), None, None, None, None, 0,
+                                    off.ctypes.data) == api.SW_OK
+    assert off[0] == 0
+    assert lib.sw_align_batch_cigar(ctypes.byref(b), ctypes.byref(sc), None, None, None, None, 0,
+                                    None) == api.SW_EINVAL          # no offsets array
+    b.n_pairs = 1                                   # arrays missing
+    assert lib.sw_align_batch_cigar(ctypes.byref(b), ctypes.byref(sc), None, z.ctypes.data,
+                                    z.ctypes.data, runs.ctypes.data, 4,
+                                    off.ctypes.data) == api.SW_EINVAL
+    b.n_pairs = -1
+    assert lib.sw_align_batch_cigar(ctypes.byref(b), ctypes.byref(sc), None, None, None, None, 0,
+                                    off.ctypes.data) == api.SW_EINVAL
