@@ -222,6 +222,8 @@ def main():
     rec["starts"] = {"ms_per_call": round(st_ms, 3), "prefix_cells": pcells,
                      "gcups_prefix_cells": round(pcells / st_ms / 1e6, 1),
                      "median_alignment_rows": int(np.median(out.results[live, 1] - qs[live] + 1))}
+    rec["paths"] = _paths_leg(api, [d[k] for k in ("qres", "qoff", "rres", "roff", "pref")], None,
+                              w, out.results, qs, rs, n_st)
 
     if not args.no_plain:
         # plain kernel: one 256 x 1024 pair per launch (sw_align)
@@ -256,6 +258,30 @@ def main():
                                          "scalar int64 C oracle, pthreads" % (n_s, sub.cells())}
         rec["parity_sample"] = bool(np.array_equal(out.results[:n_s, :3], want))
     print(json.dumps(rec))
+
+
+def _paths_leg(api, d, pq, w, ends, qs, rs, reps):
+    """sw_align_batch_cigar on the batch's alignments (device-resident
+    sequences): whole-call time, rectangle cells per second, run counts."""
+    import torch
+    call = lambda: api.sw_align_batch_cigar(*d, w.matrix, w.gap_open, w.gap_extend, ends,  # noqa
+                                            qs, rs, pair_query=pq)
+    runs, off = call()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        runs, off = call()
+    ms = (time.perf_counter() - t) / reps * 1e3
+    live = ends[:, 0] > 0
+    A = (ends[live, 2] - rs[live]).astype(np.int64) + 1
+    B = (ends[live, 1] - qs[live]).astype(np.int64) + 1
+    cells = int((A * B).sum())
+    nr = np.diff(off)[live]
+    return {"ms_per_call": round(ms, 3), "alignments": int(live.sum()),
+            "rectangle_cells": cells, "gcups_rectangle_cells": round(cells / ms / 1e6, 2),
+            "median_rows": int(np.median(A)), "median_cols": int(np.median(B)),
+            "runs_total": int(off[-1]), "median_runs": int(np.median(nr)),
+            "alignments_per_s": round(live.sum() / ms * 1e3, 1)}
 
 
 def _device_batch(w):
@@ -322,6 +348,15 @@ def bench_dna(args):
     cells = w.cells()
     km = float(np.mean(kms))
     ach = cells * OPS_PER_CELL / (km / 1e3) / 1e12
+    # start cells and paths of the same alignments
+    reps = max(1, args.steps // 4)
+    api.sw_align_batch_starts(*d, w.matrix, w.gap_open, w.gap_extend, out.results, pair_query=pq)
+    ts = time.perf_counter()
+    for _ in range(reps):
+        qs, rs = api.sw_align_batch_starts(*d, w.matrix, w.gap_open, w.gap_extend, out.results,
+                                           pair_query=pq)
+    starts_ms = (time.perf_counter() - ts) / reps * 1e3
+    paths = _paths_leg(api, d, pq, w, out.results, qs, rs, reps)
     print(json.dumps({"metric": METRIC, "value": round(cells / wall / 1e9, 2), "unit": "GCUPS",
                       "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                       "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True,
@@ -352,6 +387,8 @@ def bench_dna(args):
                                        "kernel_ms": round(oh.stats["kernel_ms"], 3),
                                        "same_results": bool(np.array_equal(oh.results,
                                                                            out.results))},
+                      "starts": {"ms_per_call": round(starts_ms, 3)},
+                      "paths": paths,
                       "tuned": [{k: (round(v, 1) if isinstance(v, float) else v)
                                  for k, v in e.items()} for e in tuned]}))
 

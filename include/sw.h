@@ -197,7 +197,7 @@ int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc, const sw_resu
  * score ends[k].score from the start to the end cell, a residue not below
  * alphabet_size inside a rectangle, or too small a cigar_cap.  SW_EOVERFLOW:
  * a rectangle whose anchored scores could leave the kernel's int32 range
- * (about 2^29 / (gap_extend + 1) cells along its sides).  SW_ENOMEM: a
+ * (about 2^27 / (gap_extend + 1) cells along its sides).  SW_ENOMEM: a
  * rectangle needing more than 2 GiB of decision bits.  The batch's arrays
  * follow sw_align_batch's rules (device_resident included); ends,
  * query_start, ref_start, cigar and cigar_off are host arrays owned by the

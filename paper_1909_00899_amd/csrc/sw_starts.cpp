@@ -393,10 +393,11 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
       return SW_EINVAL;
     }
     const int64_t A = e.ref_end - rs + 1, Bq = e.query_end - qs + 1;
-    // every reachable value stays above -2^29 and every row term below 2^30
+    // every reachable value stays above -2^28 and every row term below 2^30,
+    // so unreachable values (near -2^30) never meet reachable ones
     const int64_t lo = 2 * (maxabs + S.go) + (A + Bq + 2 * swk::kTraceTileCols) * (S.ge + 1);
     const int64_t hi = std::min(A, Bq) * (int64_t)S.max_s + (Bq + swk::kTraceTileCols) * S.ge;
-    if (lo >= (1ll << 29) || hi >= (1ll << 30)) {
+    if (lo >= (1ll << 27) || hi >= (1ll << 30)) {
       set_error("pair %d: a %lld x %lld rectangle leaves the int32 range of the path kernel", k,
                 (long long)A, (long long)Bq);
       return SW_EOVERFLOW;

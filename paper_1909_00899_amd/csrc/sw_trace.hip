@@ -39,14 +39,17 @@ namespace swk {
 namespace dev {
 namespace {
 
-constexpr int kNeg = -(1 << 30);     // unreachable; every reachable value stays above kNeg / 2
+constexpr int kNeg = -(1 << 30);     // unreachable edge; every reachable value stays above -2^28
+constexpr int kWalkRows = 64;        // rows of one tile in the walk window (8 KiB)
 
 __device__ __forceinline__ int dpp_wave_shr1(int old, int x) {
   return __builtin_amdgcn_update_dpp(old, x, 0x138, 0xf, 0xf, false);
 }
+// lanes without a source (and rows the mask leaves out) read INT_MIN, the
+// identity of max, so each step fuses into one v_max_i32 with a DPP operand
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ int dpp_move(int x) {
-  return __builtin_amdgcn_update_dpp(kNeg, x, CTRL, ROWMASK, 0xf, false);
+  return __builtin_amdgcn_update_dpp((int)0x80000000, x, CTRL, ROWMASK, 0xf, false);
 }
 
 // inclusive max over lanes 0..lane
@@ -68,6 +71,7 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   int *smat = smem;                                            // [query code][ref code]
   uint16_t *lbits = (uint16_t *)(smem + kMaxAlpha * kMaxAlpha);
   int *lcarry = (int *)(lbits + kTraceLdsRowTiles * 64);
+  uint16_t *lwin = lbits;                                      // walk window (device-memory bits)
   const int L = threadIdx.x;
   const int alpha = a.alpha, go = a.go, ge = a.ge;
   for (int k = L; k < alpha * alpha; k += 64) smat[k] = a.matrix[k];
@@ -92,9 +96,13 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
         bad |= code >= alpha;
         qb[c] = min(code, alpha - 1) * alpha;
       }
-      int Vp[4], Gp[4], Fp[4];
+      int Vp[4], Gp[4], Fp[4], wj[4], ej[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) Vp[c] = Gp[c] = Fp[c] = kNeg;
+      for (int c = 0; c < 4; ++c) {
+        Vp[c] = Gp[c] = Fp[c] = kNeg;
+        wj[c] = (jc0 + c) * ge;              // scan term offset of column j
+        ej[c] = go + (jc0 + c - 1) * ge;     // Eg(., j) = prefix max - go - (j - 1) ge
+      }
       int cv_prev = kNeg;                      // V(i-1, base-1)
       int rreg = 0, crv = kNeg, crm = kNeg, crp = kNeg;
       for (int i = 0; i < A; ++i) {
@@ -113,14 +121,17 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
         const int cm_in = t ? readlane(crm, i & 63) : kNeg;   // M(i, base-1)
         const int cp_in = t ? readlane(crp, i & 63) : kNeg;   // max_{y<base} M(i, y) + y ge
         int Mv[4];
-        Mv[0] = max(smat[qb[0] + rc] + dpp_wave_shr1(cv_prev, Vp[3]), kNeg);
-        Mv[1] = max(smat[qb[1] + rc] + Vp[0], kNeg);
-        Mv[2] = max(smat[qb[2] + rc] + Vp[1], kNeg);
-        Mv[3] = max(smat[qb[3] + rc] + Vp[2], kNeg);
+        // no clamps below: every cell off row 0 and column 0 is reachable
+        // (gaps from the start), so unreachable values only arise next to
+        // the kNeg edges and never drift (the host bounds the rest)
+        Mv[0] = smat[qb[0] + rc] + dpp_wave_shr1(cv_prev, Vp[3]);
+        Mv[1] = smat[qb[1] + rc] + Vp[0];
+        Mv[2] = smat[qb[2] + rc] + Vp[1];
+        Mv[3] = smat[qb[3] + rc] + Vp[2];
         if (i == 0 && jc0 == 0) Mv[0] = smat[qb[0] + rc];      // the start pair
         int w[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) w[c] = Mv[c] + (jc0 + c) * ge;
+        for (int c = 0; c < 4; ++c) w[c] = Mv[c] + wj[c];
         int lp[4];
         lp[0] = kNeg;
         lp[1] = w[0];
@@ -132,12 +143,11 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
         uint32_t word = 0;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          const int j = jc0 + c;
-          const int eg = max(max(exc, lp[c]) - go - (j - 1) * ge, kNeg);
+          const int eg = max(exc, lp[c]) - ej[c];
           const int mprev = c ? Mv[c - 1] : m_left;
           const int g = max(Mv[c], eg);
           const int fo = Gp[c] - go, fe = Fp[c] - ge;
-          const int f = max(max(fo, fe), kNeg);
+          const int f = max(fo, fe);
           const int v = max(g, f);
           const uint32_t nib = (uint32_t)(g >= f) | (uint32_t)(fo >= fe) << 1 |
                                (uint32_t)(Mv[c] >= eg) << 2 | (uint32_t)(mprev - go == eg) << 3;
@@ -159,7 +169,10 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
           ok = __ballot(jb >= 0 && jb < 4 && mend == P.score) != 0;
         }
       }
-      __threadfence();                         // carries (and bits) before their readers
+      // carries and bits are read back by this same wavefront: a workgroup-
+      // scope fence (wait for its own stores) is enough; an agent-scope one
+      // would write back the L2 of the XCD on every tile
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     }
     bad = __ballot(bad) != 0;
 
@@ -172,8 +185,26 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
       if (nrun < P.cap && L == 0) a.cigar[end - 1 - nrun] = v;
       ++nrun;
     };
+    // device-memory bits are read through an LDS window of kWalkRows rows of
+    // one tile (the walk only moves up and left): one coalesced copy per
+    // window instead of a dependent device-memory load per step
+    int w_tile = -1, w_lo = 0;
     auto nib_at = [&](int i, int j) -> int {
-      const uint32_t wd = bits[((size_t)(j / kTraceTileCols) * A + i) * 64 + (j % kTraceTileCols) / 4];
+      const int t = j / kTraceTileCols, col = (j % kTraceTileCols) / 4;
+      uint32_t wd;
+      if (LB) {
+        wd = bits[((size_t)t * A + i) * 64 + col];
+      } else {
+        if (t != w_tile || i < w_lo || i >= w_lo + kWalkRows) {
+          w_tile = t;
+          w_lo = max(0, i - kWalkRows + 1);
+          const int rows = min(kWalkRows, A - w_lo);
+          const uint4 *src = (const uint4 *)(bits + ((size_t)t * A + w_lo) * 64);
+          uint4 *dst = (uint4 *)lwin;
+          for (int k = L; k < rows * 8; k += 64) dst[k] = src[k];
+        }
+        wd = lwin[(i - w_lo) * 64 + col];
+      }
       return (int)(wd >> (4 * (j & 3))) & 15;
     };
     if (!fail) {
@@ -238,6 +269,7 @@ __global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, 
 size_t trace_lds_bytes(bool lds_bits) {
   size_t b = (size_t)kMaxAlpha * kMaxAlpha * sizeof(int);
   if (lds_bits) b += (size_t)kTraceLdsRowTiles * 64 * sizeof(uint16_t) + 6 * kTraceLdsCarryRows * sizeof(int);
+  else b += (size_t)dev::kWalkRows * 64 * sizeof(uint16_t);
   return b;
 }
 
