@@ -189,8 +189,9 @@ int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc, const sw_resu
  *
  * Computed on the device: one wavefront per pair fills the rectangle between
  * start and end cell, anchored at the start, keeping four decision bits per
- * cell (in LDS when they fit, else in device scratch of at most 256 MiB per
- * launch), then walks them back from the end cell.
+ * cell (in LDS when they fit, else in device scratch of at most 1 GiB per
+ * launch, up to three launches at once on streams of the library's own),
+ * then walks them back from the end cell.
  *
  * SW_EINVAL: NULL arrays, pair ids or offsets out of range, a start cell
  * after its end cell or an end cell outside its sequences, no alignment of

@@ -50,7 +50,14 @@ struct StartsWork {
   DevBuf rev_q, rev_r;   // reversed query / prefixes
   DevBuf tab;            // offsets (int64), pair ids and first rows (int32)
   // paths
-  DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off, tr_bits, tr_carry;
+  DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off;
+  // device-memory rectangles: the largest group, the second, the rest each on
+  // a stream of their own, so the long poles of the largest rectangles (one
+  // wavefront each) overlap instead of adding up
+  static constexpr int kTraceStreams = 3;
+  hipStream_t tr_st[kTraceStreams] = {};
+  hipEvent_t tr_ready = nullptr, tr_done[kTraceStreams] = {};
+  DevBuf tr_bits[kTraceStreams], tr_carry[kTraceStreams];
 };
 StartsWork g_starts;
 
@@ -343,7 +350,7 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
 
 namespace {
 
-constexpr int64_t kTraceScratchBytes = 256ll << 20;   // device-memory decision bits per launch
+constexpr int64_t kTraceScratchBytes = 1ll << 30;    // device-memory decision bits per launch
 constexpr int kTraceMaxWaves = 4096;
 
 // Runs a path can have between start and end: every run but the first is
@@ -424,7 +431,8 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
   });
   struct Group { int first, count, waves; int64_t slot_words; int carry_rows; };
   std::vector<Group> groups;
-  int64_t bits_words = 0, carry_ints = 0;
+  constexpr int NS = StartsWork::kTraceStreams;
+  int64_t bits_words[NS] = {}, carry_ints[NS] = {};
   for (int t = 0; t < (int)glob.size();) {
     const swk::TracePair &P0 = glob[t];
     const int64_t slot = (int64_t)P0.A * ((P0.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols) * 64;
@@ -444,9 +452,10 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     const int64_t per_wave = slot * 2 + 6ll * carry_rows * 4;
     const int waves = (int)std::max<int64_t>(
         1, std::min<int64_t>({(int64_t)(u - t), kTraceScratchBytes / per_wave, kTraceMaxWaves}));
+    const int sk = std::min((int)groups.size(), NS - 1);
     groups.push_back({t, u - t, waves, slot, carry_rows});
-    bits_words = std::max<int64_t>(bits_words, slot * waves);
-    carry_ints = std::max<int64_t>(carry_ints, 6ll * carry_rows * waves);
+    bits_words[sk] = std::max<int64_t>(bits_words[sk], slot * waves);
+    carry_ints[sk] = std::max<int64_t>(carry_ints[sk], 6ll * carry_rows * waves);
     t = u;
   }
   const int nl = (int)lds.size(), ng = (int)glob.size(), nt = nl + ng;
@@ -456,10 +465,16 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
         (rc = W.tr_mat.ensure((size_t)S.alpha * S.alpha * sizeof(int32_t))) ||
         (rc = W.tr_runs.ensure((size_t)std::max<int64_t>(region, 1) * sizeof(uint32_t))) ||
         (rc = W.tr_nruns.ensure((size_t)np * sizeof(int32_t))) ||
-        (rc = W.tr_off.ensure((size_t)(np + 1) * sizeof(int64_t))) ||
-        (rc = W.tr_bits.ensure((size_t)std::max<int64_t>(bits_words, 1) * sizeof(uint16_t))) ||
-        (rc = W.tr_carry.ensure((size_t)std::max<int64_t>(carry_ints, 1) * sizeof(int32_t))))
+        (rc = W.tr_off.ensure((size_t)(np + 1) * sizeof(int64_t))))
       return rc;
+    for (int k = 0; k < NS && k < (int)groups.size(); ++k) {
+      if ((rc = W.tr_bits[k].ensure((size_t)std::max<int64_t>(bits_words[k], 1) * sizeof(uint16_t))) ||
+          (rc = W.tr_carry[k].ensure((size_t)std::max<int64_t>(carry_ints[k], 1) * sizeof(int32_t))))
+        return rc;
+      if (!W.tr_st[k]) HIPCHK(hipStreamCreateWithFlags(&W.tr_st[k], hipStreamNonBlocking));
+      if (!W.tr_done[k]) HIPCHK(hipEventCreateWithFlags(&W.tr_done[k], hipEventDisableTiming));
+    }
+    if (!W.tr_ready) HIPCHK(hipEventCreateWithFlags(&W.tr_ready, hipEventDisableTiming));
     swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
     if (nl) HIPCHK(hipMemcpyAsync(dp, lds.data(), nl * sizeof(swk::TracePair), hipMemcpyHostToDevice, W.st));
     if (ng) HIPCHK(hipMemcpyAsync(dp + nl, glob.data(), ng * sizeof(swk::TracePair), hipMemcpyHostToDevice, W.st));
@@ -472,21 +487,32 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     ta.alpha = S.alpha;
     ta.go = S.go;
     ta.ge = S.ge;
-    ta.gbits = W.tr_bits.as<uint16_t>();
-    ta.gcarry = W.tr_carry.as<int32_t>();
     ta.cigar = W.tr_runs.as<uint32_t>();
     ta.n_runs = W.tr_nruns.as<int32_t>();
     ta.pairs = dp;
     ta.n = nl;
     ta.slot_words = 0;
     ta.carry_rows = 0;
+    ta.gbits = nullptr;
+    ta.gcarry = nullptr;
+    const int used = std::min((int)groups.size(), NS);
+    if (used) HIPCHK(hipEventRecord(W.tr_ready, W.st));
+    for (int k = 0; k < used; ++k) HIPCHK(hipStreamWaitEvent(W.tr_st[k], W.tr_ready, 0));
     HIPCHK(swk::launch_trace(true, ta, nl, W.st));
-    for (const Group &gr : groups) {
+    for (int g = 0; g < (int)groups.size(); ++g) {
+      const Group &gr = groups[g];
+      const int k = std::min(g, NS - 1);
       ta.pairs = dp + nl + gr.first;
       ta.n = gr.count;
       ta.slot_words = gr.slot_words;
       ta.carry_rows = gr.carry_rows;
-      HIPCHK(swk::launch_trace(false, ta, gr.waves, W.st));
+      ta.gbits = W.tr_bits[k].as<uint16_t>();
+      ta.gcarry = W.tr_carry[k].as<int32_t>();
+      HIPCHK(swk::launch_trace(false, ta, gr.waves, W.tr_st[k]));
+    }
+    for (int k = 0; k < used; ++k) {
+      HIPCHK(hipEventRecord(W.tr_done[k], W.tr_st[k]));
+      HIPCHK(hipStreamWaitEvent(W.st, W.tr_done[k], 0));
     }
     std::vector<int32_t> dev_counts(np);
     HIPCHK(hipMemcpyAsync(dev_counts.data(), W.tr_nruns.p, (size_t)np * sizeof(int32_t),
