@@ -51,6 +51,7 @@ struct StartsWork {
   DevBuf tab;            // offsets (int64), pair ids and first rows (int32)
   // paths
   DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off;
+  HostBuf tr_host, tr_hcounts;   // pinned: the pair table, the run counts
   // device-memory rectangles: the largest group, the second, the rest each on
   // a stream of their own, so the long poles of the largest rectangles (one
   // wavefront each) overlap instead of adding up
@@ -384,8 +385,14 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
   if ((rc = load_batch(b, W, B))) return rc;
   int64_t maxabs = 0;
   for (int v : S.M) maxabs = std::max<int64_t>(maxabs, v < 0 ? -(int64_t)v : v);
-  // ---- one rectangle per pair with a positive score; LDS-sized ones first
-  std::vector<swk::TracePair> lds, glob;
+  // ---- one rectangle per pair with a positive score; LDS-sized ones first,
+  // built straight into pinned memory (one fast upload)
+  if ((rc = W.tr_host.ensure((size_t)np * sizeof(swk::TracePair))) ||
+      (rc = W.tr_hcounts.ensure((size_t)np * sizeof(int32_t))))
+    return rc;
+  swk::TracePair *htab = W.tr_host.as<swk::TracePair>();
+  int nl = 0;
+  std::vector<swk::TracePair> glob;
   int64_t region = 0;
   for (int k = 0; k < np; ++k) {
     const sw_result &e = ends[k];
@@ -421,7 +428,8 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     tp.pad = 0;
     region += tp.cap;
     const int64_t tiles = (Bq + swk::kTraceTileCols - 1) / swk::kTraceTileCols;
-    (A * tiles <= swk::kTraceLdsRowTiles ? lds : glob).push_back(tp);
+    if (A * tiles <= swk::kTraceLdsRowTiles) htab[nl++] = tp;
+    else glob.push_back(tp);
   }
   // device-memory rectangles: largest first, in groups of similar size
   std::sort(glob.begin(), glob.end(), [](const swk::TracePair &x, const swk::TracePair &y) {
@@ -458,7 +466,8 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     carry_ints[sk] = std::max<int64_t>(carry_ints[sk], 6ll * carry_rows * waves);
     t = u;
   }
-  const int nl = (int)lds.size(), ng = (int)glob.size(), nt = nl + ng;
+  const int ng = (int)glob.size(), nt = nl + ng;
+  if (ng) std::memcpy(htab + nl, glob.data(), (size_t)ng * sizeof(swk::TracePair));
   std::vector<int32_t> counts(np, 0);
   if (nt > 0) {
     if ((rc = W.tr_pairs.ensure((size_t)nt * sizeof(swk::TracePair))) ||
@@ -476,8 +485,8 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     }
     if (!W.tr_ready) HIPCHK(hipEventCreateWithFlags(&W.tr_ready, hipEventDisableTiming));
     swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
-    if (nl) HIPCHK(hipMemcpyAsync(dp, lds.data(), nl * sizeof(swk::TracePair), hipMemcpyHostToDevice, W.st));
-    if (ng) HIPCHK(hipMemcpyAsync(dp + nl, glob.data(), ng * sizeof(swk::TracePair), hipMemcpyHostToDevice, W.st));
+    HIPCHK(hipMemcpyAsync(dp, htab, (size_t)nt * sizeof(swk::TracePair), hipMemcpyHostToDevice,
+                          W.st));
     HIPCHK(hipMemcpyAsync(W.tr_mat.p, S.M.data(), (size_t)S.alpha * S.alpha * sizeof(int32_t),
                           hipMemcpyHostToDevice, W.st));
     swk::TraceArgs ta;
@@ -514,29 +523,29 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
       HIPCHK(hipEventRecord(W.tr_done[k], W.tr_st[k]));
       HIPCHK(hipStreamWaitEvent(W.st, W.tr_done[k], 0));
     }
-    std::vector<int32_t> dev_counts(np);
-    HIPCHK(hipMemcpyAsync(dev_counts.data(), W.tr_nruns.p, (size_t)np * sizeof(int32_t),
+    int32_t *dev_counts = W.tr_hcounts.as<int32_t>();
+    HIPCHK(hipMemcpyAsync(dev_counts, W.tr_nruns.p, (size_t)np * sizeof(int32_t),
                           hipMemcpyDeviceToHost, W.st));
     HIPCHK(hipStreamSynchronize(W.st));
-    for (const std::vector<swk::TracePair> *v : {&lds, &glob})
-      for (const swk::TracePair &P : *v) {
-        const int c = dev_counts[P.id];
-        if (c == swk::kTraceBadResidue) {
-          set_error("pair %d: a residue code inside its alignment is not below alphabet_size", P.id);
-          return SW_EINVAL;
-        }
-        if (c == swk::kTraceInconsistent) {
-          set_error("pair %d: no alignment of score %d runs from its start (%d, %d) to its end "
-                    "(%d, %d)", P.id, P.score, query_start[P.id], ref_start[P.id],
-                    ends[P.id].query_end, ends[P.id].ref_end);
-          return SW_EINVAL;
-        }
-        if (c < 1 || c > P.cap) {
-          set_error("pair %d: internal path error (%d runs, bound %d)", P.id, c, P.cap);
-          return SW_EDEVICE;
-        }
-        counts[P.id] = c;
+    for (int t = 0; t < nt; ++t) {
+      const swk::TracePair &P = htab[t];
+      const int c = dev_counts[P.id];
+      if (c == swk::kTraceBadResidue) {
+        set_error("pair %d: a residue code inside its alignment is not below alphabet_size", P.id);
+        return SW_EINVAL;
       }
+      if (c == swk::kTraceInconsistent) {
+        set_error("pair %d: no alignment of score %d runs from its start (%d, %d) to its end "
+                  "(%d, %d)", P.id, P.score, query_start[P.id], ref_start[P.id],
+                  ends[P.id].query_end, ends[P.id].ref_end);
+        return SW_EINVAL;
+      }
+      if (c < 1 || c > P.cap) {
+        set_error("pair %d: internal path error (%d runs, bound %d)", P.id, c, P.cap);
+        return SW_EDEVICE;
+      }
+      counts[P.id] = c;
+    }
   }
   for (int k = 0; k < np; ++k) cigar_off[k + 1] = cigar_off[k] + counts[k];
   if (cigar_off[np] > cigar_cap) {
