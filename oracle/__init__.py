@@ -28,6 +28,8 @@ adopted where the paper is silent are stated in each docstring:
 
 Start cells (``start_cell``, ``start_batch``): the end cell of the same
 recurrence on the reversed prefixes that end at the reported end cell.
+Paths (``path``) and end-to-end scores (``endtoend``: global and semi-global,
+not in the paper) are plain maxima over chains of aligned pairs.
 
 Parity status: pinned (brute-force enumeration of all local alignments on tiny
 inputs, a hand-computed worked example, closed-form special cases and
@@ -309,3 +311,46 @@ def path_score(query, ref, matrix, gap_open: int, gap_extend: int, start, runs) 
             else:
                 i += L
     return total
+
+
+def endtoend(query, ref, matrix, gap_open: int, gap_extend: int, mode: int) -> Tuple[int, int, int]:
+    """(score, query_end, ref_end) of the best global (mode 0) or semi-global
+    (mode 1: the query end to end, reference ends free) alignment, from
+    ``oracle_endtoend`` in sw_oracle.c (plain maxima over the chains of aligned
+    pairs; gap runs priced with min(gap_extend, gap_open)).  Not in the paper,
+    whose problem is local alignment.  query_end is always m - 1; ref_end is
+    n - 1 in mode 0 and, in mode 1, the smallest reference prefix end holding
+    an optimal alignment (-1: the empty prefix)."""
+    q, r = _u8(query), _u8(ref)
+    M = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
+    lib = _load()
+    lib.oracle_endtoend.restype = ctypes.c_int
+    lib.oracle_endtoend.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                    ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.POINTER(_Result)]
+    res = _Result()
+    rc = lib.oracle_endtoend(q.ctypes.data if q.size else None, q.size,
+                             r.ctypes.data if r.size else None, r.size, M.ctypes.data,
+                             M.shape[0], int(gap_open), int(gap_extend), int(mode),
+                             ctypes.byref(res))
+    if rc != 0:
+        raise ValueError("oracle_endtoend failed (%d)" % rc)
+    return int(res.score), int(res.query_end), int(res.ref_end)
+
+
+def endtoend_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap_open: int,
+                   gap_extend: int, mode: int, pair_query=None, pairs=None) -> np.ndarray:
+    """``endtoend`` for every pair (or the listed ``pairs``) of a CSR batch:
+    an (n, 3) int64 array."""
+    qo, ro = np.asarray(query_off), np.asarray(ref_off)
+    pr = np.asarray(pair_ref)
+    idx = range(pr.size) if pairs is None else pairs
+    out = []
+    for k in idx:
+        qi = 0 if pair_query is None else int(pair_query[k])
+        ri = int(pr[k])
+        out.append(endtoend(query_res[qo[qi]:qo[qi + 1]], ref_res[ro[ri]:ro[ri + 1]], matrix,
+                            gap_open, gap_extend, mode))
+    return np.array(out, dtype=np.int64).reshape(-1, 3)
+

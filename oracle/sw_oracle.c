@@ -248,3 +248,86 @@ int64_t oracle_path(const uint8_t *q, const uint8_t *r, const int32_t *Mx, int32
     free(M); free(V); free(rev);
     return rc ? rc : cnt;
 }
+
+/*
+ * End-to-end alignments (not in the paper, whose problem is local): an
+ * alignment is a chain of aligned pairs (x_1, y_1) < (x_2, y_2) < ... strictly
+ * increasing in both the reference index x and the query index y; its score is
+ * the sum of S[q_y][r_x] over the pairs minus the cost of every gap run, a run
+ * of L skipped residues costing go + (L - 1) * min(ge, go) (Gotoh's
+ * recurrences reopen a gap rather than extend it at a higher cost).  Between
+ * two pairs, before the first and after the last, the skipped reference
+ * residues and the skipped query residues are one run each.
+ *
+ * mode 0, global: every residue of both sequences is aligned or skipped at a
+ *   cost; the chain may be empty (both sequences skipped whole).
+ * mode 1, semi-global (fitting): the query end to end as in mode 0, the
+ *   reference residues before the first pair and after the last pair are
+ *   skipped for free.  End: the smallest reference prefix end a (-1 for the
+ *   empty prefix) such that the best such alignment of the query inside
+ *   r[0..a] -- counting reference residues after its last pair up to a as a
+ *   gap run -- reaches the score.
+ *
+ * Computed as plain maxima over the chains, no affine recurrence:
+ *   W(x, y) = S[q_y][r_x] + best(x - 1, y - 1)    (the best chain ending with pair (x, y))
+ *   best(a, b) = max( lead(a, b),  max over x <= a, y <= b of W(x, y) - g(a - x) - g(b - y) )
+ * with lead(a, b) the chain before any pair -- residues r[0..a] and q[0..b]
+ * skipped: -g(a + 1) - g(b + 1) in mode 0, -g(b + 1) in mode 1 (g(0) = 0) --
+ * and best(-1, -1) = 0, best(a, -1) = lead(a, -1), best(-1, b) = lead(-1, b).
+ * The inner maximum is taken over y first, then x (one pass per row and one
+ * per column), an exact regrouping of the same maximum.  Global score:
+ * best(n - 1, m - 1).  Semi-global score: max over a in -1..n-1 of best(a, m - 1).
+ */
+static int64_t gcost(int64_t L, int64_t go, int64_t ge) { return L <= 0 ? 0 : go + (L - 1) * ge; }
+
+int oracle_endtoend(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
+                    const int32_t *Mx, int32_t alpha, int64_t go, int64_t ge, int32_t mode,
+                    oracle_result *out)
+{
+    if (m < 0 || n < 0 || alpha <= 0 || (mode != 0 && mode != 1)) return -1;
+    if (ge > go) ge = go;
+    const int64_t NEG = INT64_MIN / 4;
+    /* best and W over (a, b) in -1..n-1 x -1..m-1, stored with a +1 offset */
+    const int64_t R = n + 1, C = m + 1;
+    int64_t *best = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
+    int64_t *W = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
+    int64_t *G = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
+    if (!best || !W || !G) { free(best); free(W); free(G); return -1; }
+#define IX(a, b) (((a) + 1) * C + ((b) + 1))
+    for (int64_t a = -1; a < n; ++a) {
+        for (int64_t b = -1; b < m; ++b) {
+            const int64_t lead = mode == 0 ? -gcost(a + 1, go, ge) - gcost(b + 1, go, ge)
+                                           : -gcost(b + 1, go, ge);
+            if (a < 0 || b < 0) {
+                W[IX(a, b)] = NEG;
+                G[IX(a, b)] = NEG;
+                best[IX(a, b)] = lead;
+                continue;
+            }
+            W[IX(a, b)] = (int64_t)Mx[(int)q[b] * alpha + (int)r[a]] + best[IX(a - 1, b - 1)];
+            /* G(x, b) = max over y <= b of W(x, y) - g(b - y), for this row x = a */
+            int64_t g = NEG;
+            for (int64_t y = 0; y <= b; ++y) g = max2(g, W[IX(a, y)] - gcost(b - y, go, ge));
+            G[IX(a, b)] = g;
+            int64_t v = lead;
+            for (int64_t x = 0; x <= a; ++x)
+                if (G[IX(x, b)] > NEG) v = max2(v, G[IX(x, b)] - gcost(a - x, go, ge));
+            best[IX(a, b)] = v;
+        }
+    }
+    if (mode == 0) {
+        out->score = best[IX(n - 1, m - 1)];
+        out->query_end = m - 1;
+        out->ref_end = n - 1;
+    } else {
+        int64_t s = NEG, at = -1;
+        for (int64_t a = -1; a < n; ++a)
+            if (best[IX(a, m - 1)] > s) { s = best[IX(a, m - 1)]; at = a; }
+        out->score = s;
+        out->query_end = m - 1;
+        out->ref_end = at;
+    }
+#undef IX
+    free(best); free(W); free(G);
+    return 0;
+}

@@ -141,3 +141,48 @@ def brute_force_path(q, r, M, go: int, ge: int):
         else:
             runs.append((1, o))
     return runs
+
+
+def brute_force_endtoend(q, r, M, go: int, ge: int, mode: int):
+    """(score, query_end, ref_end) of the best global (mode 0) or semi-global
+    (mode 1: query end to end, reference ends free) alignment by enumerating
+    every chain of index pairs, the empty chain included, and pricing every
+    gap run from the definition (runs cost g(L) with the extension clamped to
+    the opening cost).  Mode 1's ref_end: the smallest prefix end a whose best
+    alignment -- the reference residues after the last pair up to a counted as
+    a gap run -- reaches the score.  Tiny inputs only."""
+    m, n = len(q), len(r)
+    ge = min(ge, go)
+    chains = [[]]
+
+    def grow(chain):
+        i0, j0 = chain[-1] if chain else (-1, -1)
+        for i in range(i0 + 1, n):
+            for j in range(j0 + 1, m):
+                c = chain + [(i, j)]
+                chains.append(c)
+                grow(c)
+
+    grow([])
+    best_at = {}
+    for c in chains:
+        s = sum(int(M[q[j]][r[i]]) for i, j in c)
+        for (i, j), (i2, j2) in zip(c, c[1:]):
+            s -= gap_cost(i2 - i - 1, go, ge) + gap_cost(j2 - j - 1, go, ge)
+        fi, fj = c[0] if c else (n, m)         # first pair (or past the end)
+        li, lj = c[-1] if c else (-1, -1)      # last pair (or before the start)
+        if mode == 0:
+            if c:
+                s -= gap_cost(fi, go, ge) + gap_cost(fj, go, ge)
+                s -= gap_cost(n - 1 - li, go, ge) + gap_cost(m - 1 - lj, go, ge)
+            else:
+                s -= gap_cost(n, go, ge) + gap_cost(m, go, ge)
+            best_at[n - 1] = max(best_at.get(n - 1, s), s)
+        else:
+            s -= (gap_cost(fj, go, ge) + gap_cost(m - 1 - lj, go, ge)) if c else gap_cost(m, go, ge)
+            for a in range(li if c else -1, n):
+                v = s - (gap_cost(a - li, go, ge) if c else 0)
+                best_at[a] = max(best_at.get(a, v), v)
+    score = max(best_at.values())
+    end = min(a for a, v in best_at.items() if v == score)
+    return score, m - 1, end

@@ -478,3 +478,65 @@ def test_path_pins_tell_other_rules_apart():
     cases = [crossing, bridge] + [_gappy_case(rng) for _ in range(400)]
     for name, (key, igf) in rules.items():
         assert any(variant(*c, key, igf) != pins.brute_force_path(*c) for c in cases), name
+
+
+# ---------------------------------------------------------------- end to end
+
+def test_endtoend_brute_force_random():
+    rng = np.random.default_rng(41)
+    for _ in range(500):
+        alpha = int(rng.integers(2, 4))
+        m, n = int(rng.integers(0, 5)), int(rng.integers(0, 6))
+        q = rng.integers(0, alpha, size=m).tolist()
+        r = rng.integers(0, alpha, size=n).tolist()
+        M = rng.integers(-4, 3, size=(alpha, alpha)).astype(np.int32)
+        go = int(rng.integers(0, 4))
+        ge = int(rng.integers(0, go + 3))      # sometimes above the opening cost
+        for mode in (0, 1):
+            want = pins.brute_force_endtoend(q, r, M, go, ge, mode)
+            assert oracle.endtoend(q, r, M, go, ge, mode) == want, (q, r, M.tolist(), go, ge, mode)
+
+
+def test_endtoend_closed_forms():
+    rng = np.random.default_rng(42)
+    M = np.full((4, 4), -4, dtype=np.int32)
+    np.fill_diagonal(M, 5)
+    for _ in range(100):
+        m = int(rng.integers(1, 30))
+        q = rng.integers(0, 4, size=m).tolist()
+        go, ge = int(rng.integers(1, 8)), int(rng.integers(0, 3))
+        # a sequence against itself: every residue paired
+        assert oracle.endtoend(q, q, M, go, ge, 0) == (5 * m, m - 1, m - 1)
+        # against nothing: one gap run
+        assert oracle.endtoend(q, [], M, go, ge, 0)[0] == -(go + (m - 1) * min(ge, go))
+        assert oracle.endtoend([], q, M, go, ge, 0)[0] == -(go + (m - 1) * min(ge, go))
+        assert oracle.endtoend([], q, M, go, ge, 1) == (0, -1, -1)
+        # a query inside a longer reference: free reference ends, the first
+        # occurrence's end
+        pre = rng.integers(0, 4, size=int(rng.integers(0, 20))).tolist()
+        post = rng.integers(0, 4, size=int(rng.integers(0, 20))).tolist()
+        r = pre + q + post
+        s, qe, re_ = oracle.endtoend(q, r, M, go, ge, 1)
+        assert s == 5 * m and qe == m - 1
+        first = min(k for k in range(m - 1, len(r)) if r[k - m + 1:k + 1] == q)
+        assert re_ == first
+    # free gaps and a +1 identity matrix: global = longest common subsequence
+    I1 = np.eye(4, dtype=np.int32)
+    for _ in range(100):
+        q = rng.integers(0, 4, size=int(rng.integers(0, 15))).tolist()
+        r = rng.integers(0, 4, size=int(rng.integers(0, 15))).tolist()
+        assert oracle.endtoend(q, r, I1, 0, 0, 0)[0] == pins.lcs(q, r)
+        assert oracle.endtoend(q, r, I1, 0, 0, 1)[0] == pins.lcs(q, r)
+
+
+def test_endtoend_invariants():
+    rng = np.random.default_rng(43)
+    for _ in range(300):
+        q, r, M, go, ge = _case(rng, maxlen=12)
+        g = oracle.endtoend(q, r, M, go, ge, 0)[0]
+        sg = oracle.endtoend(q, r, M, go, ge, 1)[0]
+        assert sg >= g                                       # fewer gaps are paid
+        assert oracle.align(q, r, M, go, ge)[0] >= sg        # a local alignment too
+        assert oracle.endtoend(q[::-1], r[::-1], M, go, ge, 0)[0] == g
+        assert oracle.endtoend(r, q, np.ascontiguousarray(np.asarray(M).T), go, ge, 0)[0] == g
+
