@@ -209,6 +209,41 @@ int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc, const sw_resul
                          const int32_t *query_start, const int32_t *ref_start,
                          uint32_t *cigar, int64_t cigar_cap, int64_t *cigar_off);
 
+/* ---------------------------------------------------------------------------
+ * sw_align_batch_global -- end-to-end alignment scores of a batch.
+ *
+ * Not in the paper (whose problem is local alignment): the same affine gap
+ * model without the zero floor.  An alignment is a chain of aligned pairs
+ * strictly increasing in both sequences; it scores the substitution scores of
+ * its pairs minus gap_open + (L - 1) * min(gap_extend, gap_open) for every
+ * run of L skipped residues (between two pairs the skipped reference residues
+ * and the skipped query residues are one run each).
+ *
+ * mode SW_MODE_GLOBAL: every residue of both sequences is aligned or skipped
+ *   at a cost, including before the first and after the last pair.
+ *   query_end = m - 1, ref_end = n - 1.
+ * mode SW_MODE_SEMIGLOBAL: the query end to end as above; reference residues
+ *   before the first and after the last pair are free (a read placed inside
+ *   a reference window).  query_end = m - 1; ref_end = the smallest
+ *   reference prefix end a (-1: the empty prefix) such that the best
+ *   alignment of the query inside r[0..a], with the reference residues after
+ *   its last pair up to a counted as a gap run, reaches the score.
+ *
+ * out[k] receives pair k's {score, query_end, ref_end, 0}; scores may be
+ * negative.  An empty side gives the gap run of the other (or 0).  Computed
+ * in int32 by one wavefront per pair (the query in 256-column tiles, a
+ * max-plus scan over the lanes for the query gap); SW_EOVERFLOW for a pair
+ * whose scores could leave that range (about 2^27 / (gap_extend + 1) residues
+ * in m + n).  SW_EINVAL for a bad mode, NULL arrays, ids or offsets out of
+ * range, or a residue not below alphabet_size.  The batch's arrays follow
+ * sw_align_batch's rules (device_resident included; precision is ignored);
+ * out is a host array of n_pairs entries.  Synchronous; calls are serialised
+ * with sw_align_batch_starts and sw_align_batch_cigar.
+ * ------------------------------------------------------------------------- */
+enum { SW_MODE_GLOBAL = 0, SW_MODE_SEMIGLOBAL = 1 };
+int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, int32_t mode,
+                          sw_result *out);
+
 /* Options and statistics for the extended batch call (tests, benchmarks,
  * the autotuner).  Zero-initialise and set what you need. */
 enum { SW_PAIRING_AUTO = 0, SW_PAIRING_ALIGNMENTS = 1, SW_PAIRING_ROWS = 2 };

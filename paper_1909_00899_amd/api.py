@@ -29,7 +29,7 @@ EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align"
             "sw_align_batch", "sw_align_batch_ex", "sw_server_create", "sw_server_submit",
             "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay",
             "sw_autotune", "sw_tune_set", "sw_tune_get", "sw_align_batch_starts",
-            "sw_align_batch_cigar"]
+            "sw_align_batch_cigar", "sw_align_batch_global"]
 
 
 class NativeLibraryError(RuntimeError):
@@ -161,6 +161,8 @@ def load():
     lib.sw_align_batch_cigar.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    lib.sw_align_batch_global.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
+                                          ctypes.c_int32, ctypes.c_void_p]
     lib.sw_autotune.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), ctypes.c_int64,
                                 ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_int32)]
@@ -361,6 +363,25 @@ def sw_align_batch_cigar(query_res, query_off, ref_res, ref_off, pair_ref, matri
                                     rs.ctypes.data if npairs else None, runs.ctypes.data, cap,
                                     off.ctypes.data))
     return runs[:off[-1]], off
+
+
+SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL = 0, 1
+
+
+def sw_align_batch_global(query_res, query_off, ref_res, ref_off, pair_ref, matrix,
+                          gap_open: int, gap_extend: int, mode: int = SW_MODE_GLOBAL,
+                          pair_query=None) -> np.ndarray:
+    """End-to-end scores of every pair: global (``SW_MODE_GLOBAL``) or
+    semi-global with free reference ends (``SW_MODE_SEMIGLOBAL``).  Returns an
+    (n_pairs, 4) int32 array of {score, query_end, ref_end, flags}."""
+    lib = load()
+    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
+                                  SW_PREC_AUTO)
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    out = np.empty((max(npairs, 1), 4), dtype=np.int32)
+    _check(lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), int(mode),
+                                     out.ctypes.data))
+    return out[:npairs]
 
 
 def decode_cigar(runs, offsets, k: int) -> list:

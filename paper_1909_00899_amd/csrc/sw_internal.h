@@ -237,6 +237,22 @@ struct TraceArgs {
 // carries live in LDS, else in gbits / gcarry (grid-stride over the pairs).
 size_t trace_lds_bytes(bool lds_bits);
 hipError_t launch_trace(bool lds_bits, const TraceArgs &a, int grid, hipStream_t st);
+// End-to-end scores (sw_trace.hip): TracePair with A = n, B = m (both >= 1);
+// results to out[id] (flags kFlagBadResidue for a residue >= alphabet size).
+constexpr int kFlagBadResidue = 1 << 20;
+struct EndArgs {
+  const TracePair *pairs;
+  int n;
+  const uint8_t *qres, *rres;
+  const int32_t *matrix;
+  int alpha, go, ge;
+  int32_t *gcarry;         // 4 * carry_rows per workgroup (pairs of two or more tiles)
+  int carry_rows;
+  DevResult *out;
+};
+size_t endtoend_lds_bytes();
+hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st);
+
 // Runs of every pair (n_runs[id] of them, ending at out + cap) to
 // dst[dst_off[id] ..]; every count must be <= its pair's cap.
 hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs,

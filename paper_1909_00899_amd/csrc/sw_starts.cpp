@@ -52,6 +52,8 @@ struct StartsWork {
   // paths
   DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off;
   HostBuf tr_host, tr_hcounts;   // pinned: the pair table, the run counts
+  DevBuf tr_res;                 // end-to-end results
+  HostBuf tr_hres;
   // device-memory rectangles: the largest group, the second, the rest each on
   // a stream of their own, so the long poles of the largest rectangles (one
   // wavefront each) overlap instead of adding up
@@ -567,3 +569,117 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
   return SW_OK;
 }
 
+
+// ------------------------------------------------------------------ end-to-end scores
+
+extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, int32_t mode,
+                                     sw_result *out) {
+  int rc = check_batch_args(b);
+  if (rc) return rc;
+  if (mode != SW_MODE_GLOBAL && mode != SW_MODE_SEMIGLOBAL) { set_error("bad mode %d", mode); return SW_EINVAL; }
+  Scoring S;
+  if ((rc = prepare_scoring(sc, S))) return rc;
+  const int np = b->n_pairs;
+  if (np == 0) return SW_OK;
+  if (!out) { set_error("out is NULL"); return SW_EINVAL; }
+  if ((rc = ensure_init())) return rc;
+  std::lock_guard<std::mutex> g(g_starts.mu);
+  StartsWork &W = g_starts;
+  Batch B;
+  if ((rc = load_batch(b, W, B))) return rc;
+  int64_t maxabs = 0;
+  for (int v : S.M) maxabs = std::max<int64_t>(maxabs, v < 0 ? -(int64_t)v : v);
+  auto gap = [&](int64_t L) -> int64_t { return L <= 0 ? 0 : S.go + (L - 1) * (int64_t)S.ge; };
+  if ((rc = W.tr_host.ensure((size_t)np * sizeof(swk::TracePair)))) return rc;
+  swk::TracePair *htab = W.tr_host.as<swk::TracePair>();
+  int n1 = 0;                        // one-tile pairs first, then the rest
+  std::vector<swk::TracePair> multi;
+  int carry_rows = 0;
+  for (int k = 0; k < np; ++k) {
+    const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
+    const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
+    if (m == 0 || n == 0) {          // a side with nothing to align: one gap run (or none)
+      const int64_t s = mode == SW_MODE_GLOBAL ? -gap(m) - gap(n) : -gap(m);
+      out[k].score = (int32_t)s;
+      out[k].query_end = (int32_t)(m - 1);
+      out[k].ref_end = mode == SW_MODE_GLOBAL ? (int32_t)(n - 1) : -1;
+      out[k].flags = 0;
+      if (s < INT32_MIN) { set_error("pair %d: score below the int32 range", k); return SW_EOVERFLOW; }
+      continue;
+    }
+    const int64_t lo = 2 * (maxabs + S.go) + (m + n + 2 * swk::kTraceTileCols) * (S.ge + 1);
+    const int64_t hi = std::min(m, n) * (int64_t)S.max_s + (m + swk::kTraceTileCols) * S.ge;
+    if (lo >= (1ll << 27) || hi >= (1ll << 30)) {
+      set_error("pair %d: %lld x %lld leaves the int32 range of the end-to-end kernel", k,
+                (long long)m, (long long)n);
+      return SW_EOVERFLOW;
+    }
+    swk::TracePair tp;
+    tp.q = B.qoff[B.pq[k]];
+    tp.r = B.roff[B.pr[k]];
+    tp.out = 0;
+    tp.A = (int32_t)n;
+    tp.B = (int32_t)m;
+    tp.score = 0;
+    tp.cap = 0;
+    tp.id = k;
+    tp.pad = 0;
+    if (m <= swk::kTraceTileCols) {
+      htab[n1++] = tp;
+    } else {
+      multi.push_back(tp);
+      carry_rows = std::max(carry_rows, (int)n);
+    }
+  }
+  const int nm = (int)multi.size(), nt = n1 + nm;
+  if (nt == 0) return SW_OK;
+  if (nm) std::memcpy(htab + n1, multi.data(), (size_t)nm * sizeof(swk::TracePair));
+  const int64_t per_wave = 4ll * carry_rows * (int64_t)sizeof(int32_t);
+  const int waves_m = nm == 0 ? 0 : (int)std::max<int64_t>(
+      1, std::min<int64_t>({(int64_t)nm, kTraceScratchBytes / std::max<int64_t>(per_wave, 1),
+                            kTraceMaxWaves}));
+  if ((rc = W.tr_pairs.ensure((size_t)nt * sizeof(swk::TracePair))) ||
+      (rc = W.tr_mat.ensure((size_t)S.alpha * S.alpha * sizeof(int32_t))) ||
+      (rc = W.tr_carry[0].ensure((size_t)std::max<int64_t>(per_wave * waves_m, 4))) ||
+      (rc = W.tr_res.ensure((size_t)np * sizeof(swk::DevResult))) ||
+      (rc = W.tr_hres.ensure((size_t)np * sizeof(swk::DevResult))))
+    return rc;
+  swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
+  HIPCHK(hipMemcpyAsync(dp, htab, (size_t)nt * sizeof(swk::TracePair), hipMemcpyHostToDevice, W.st));
+  HIPCHK(hipMemcpyAsync(W.tr_mat.p, S.M.data(), (size_t)S.alpha * S.alpha * sizeof(int32_t),
+                        hipMemcpyHostToDevice, W.st));
+  swk::EndArgs ea;
+  ea.qres = B.d_q;
+  ea.rres = B.d_r;
+  ea.matrix = W.tr_mat.as<int32_t>();
+  ea.alpha = S.alpha;
+  ea.go = S.go;
+  ea.ge = S.ge;
+  ea.gcarry = W.tr_carry[0].as<int32_t>();
+  ea.out = W.tr_res.as<swk::DevResult>();
+  ea.pairs = dp;
+  ea.n = n1;
+  ea.carry_rows = 0;
+  HIPCHK(swk::launch_endtoend(mode, ea, n1, W.st));   // a workgroup per one-tile pair
+  ea.pairs = dp + n1;
+  ea.n = nm;
+  ea.carry_rows = carry_rows;
+  HIPCHK(swk::launch_endtoend(mode, ea, waves_m, W.st));
+  swk::DevResult *hres = W.tr_hres.as<swk::DevResult>();
+  HIPCHK(hipMemcpyAsync(hres, W.tr_res.p, (size_t)np * sizeof(swk::DevResult),
+                        hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipStreamSynchronize(W.st));
+  for (int t = 0; t < nt; ++t) {
+    const int k = htab[t].id;
+    const swk::DevResult &r = hres[k];
+    if (r.flags & swk::kFlagBadResidue) {
+      set_error("pair %d: a residue code is not below alphabet_size", k);
+      return SW_EINVAL;
+    }
+    out[k].score = r.score;
+    out[k].query_end = r.qend;
+    out[k].ref_end = r.rend;
+    out[k].flags = 0;
+  }
+  return SW_OK;
+}

@@ -29,6 +29,12 @@
 // decision bits per cell are kept -- in LDS when the rectangle fits, in a
 // per-wavefront slot of device memory otherwise -- and the wavefront then
 // walks them back from the end cell, writing CIGAR runs.
+//
+// End-to-end scores (sw_align_batch_global) reuse the row step without the
+// decision bits: the same recurrences over the whole pair with the boundary of
+// a global alignment (row -1 and column -1 priced as gap runs from a virtual
+// pair at (-1, -1)) or of a semi-global one (column -1 free: a virtual pair at
+// every (a, -1)), and the score read at the last column.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -249,6 +255,109 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   }
 }
 
+// Global (MODE 0) or semi-global (MODE 1: query end to end, reference ends
+// free) score of each pair; one wavefront per pair, the query in tiles of 256
+// columns as in trace_kernel, V and the scan total of each tile's last column
+// carried per row in the wavefront's slot of gcarry.
+template <int MODE>
+__global__ __launch_bounds__(64) void endtoend_kernel(EndArgs a) {
+  extern __shared__ int smem[];
+  int *smat = smem;
+  const int L = threadIdx.x;
+  const int alpha = a.alpha, go = a.go, ge = a.ge;
+  for (int k = L; k < alpha * alpha; k += 64) smat[k] = a.matrix[k];
+  __syncthreads();
+  for (int p = blockIdx.x; p < a.n; p += gridDim.x) {
+    const TracePair P = a.pairs[p];
+    const int A = P.A, B = P.B, T = (B + kTraceTileCols - 1) / kTraceTileCols;
+    int *carry = a.gcarry + (size_t)blockIdx.x * 4 * a.carry_rows;
+    bool bad = false;
+    // semi-global: best V(a, B-1) over a = -1 .. A-1, the first one on ties
+    int best = -(go + (B - 1) * ge), best_row = -1, score = 0;
+    for (int t = 0; t < T; ++t) {
+      const int base = t * kTraceTileCols, jc0 = base + 4 * L;
+      const int *cr = carry + ((t + 1) & 1) * 2 * a.carry_rows;
+      int *cw = carry + (t & 1) * 2 * a.carry_rows;
+      int qb[4], Vp[4], Gp[4], Fp[4], wj[4], ej[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int code = jc0 + c < B ? (int)a.qres[P.q + jc0 + c] : 0;
+        bad |= code >= alpha;
+        qb[c] = min(code, alpha - 1) * alpha;
+        Vp[c] = Gp[c] = -(go + (jc0 + c) * ge);   // row -1: the first j + 1 query residues skipped
+        Fp[c] = kNeg;
+        wj[c] = (jc0 + c) * ge;
+        ej[c] = go + (jc0 + c - 1) * ge;
+      }
+      // V(-1, base - 1): the virtual pair, or the row -1 gap run
+      int cv_prev = base == 0 ? 0 : -(go + (base - 1) * ge);
+      int rreg = 0, crv = kNeg, crp = kNeg;
+      for (int i = 0; i < A; ++i) {
+        if ((i & 63) == 0) {
+          const int row = i + L;
+          rreg = row < A ? (int)a.rres[P.r + row] : 0;
+          if (t == 0) bad |= rreg >= alpha;
+          if (t > 0 && row < A) {
+            crv = cr[2 * row];
+            crp = cr[2 * row + 1];
+          }
+        }
+        const int rc = min(readlane(rreg, i & 63), alpha - 1);
+        // column -1: V(i, -1) and the scan term of M(i, -1)
+        const int cv_in = t ? readlane(crv, i & 63) : (MODE == 0 ? -(go + i * ge) : 0);
+        const int cp_in = t ? readlane(crp, i & 63) : (MODE == 0 ? kNeg : -ge);
+        int Mv[4];
+        Mv[0] = smat[qb[0] + rc] + dpp_wave_shr1(cv_prev, Vp[3]);
+        Mv[1] = smat[qb[1] + rc] + Vp[0];
+        Mv[2] = smat[qb[2] + rc] + Vp[1];
+        Mv[3] = smat[qb[3] + rc] + Vp[2];
+        int w[4], lp[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) w[c] = Mv[c] + wj[c];
+        lp[0] = kNeg;
+        lp[1] = w[0];
+        lp[2] = max(w[0], w[1]);
+        lp[3] = max(lp[2], w[2]);
+        const int agg = max(lp[3], w[3]);
+        const int exc = max(dpp_wave_shr1(kNeg, wave_max_scan(agg)), cp_in);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int g = max(Mv[c], max(exc, lp[c]) - ej[c]);
+          const int f = max(Gp[c] - go, Fp[c] - ge);
+          Vp[c] = max(g, f);
+          Gp[c] = g;
+          Fp[c] = f;
+        }
+        if (t + 1 < T && L == 63) {
+          cw[2 * i] = Vp[3];
+          cw[2 * i + 1] = max(exc, agg);
+        }
+        cv_prev = cv_in;
+        if (t == T - 1) {
+          const int jb = B - 1 - jc0;
+          const int v = jb == 0 ? Vp[0] : jb == 1 ? Vp[1] : jb == 2 ? Vp[2] : Vp[3];
+          if (MODE == 1 && v > best) {
+            best = v;
+            best_row = i;
+          }
+          score = v;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // carries before tile t + 1
+    }
+    bad = __ballot(bad) != 0;
+    const int jb = B - 1 - (T - 1) * kTraceTileCols - 4 * L;
+    if (jb >= 0 && jb < 4) {
+      DevResult r;
+      r.score = MODE == 0 ? score : best;
+      r.qend = B - 1;
+      r.rend = MODE == 0 ? A - 1 : best_row;
+      r.flags = bad ? kFlagBadResidue : 0;
+      a.out[P.id] = r;
+    }
+  }
+}
+
 // Pair t's runs (the last n_runs[id] entries of its region) to
 // cigar_dst[dst_off[id] ..]; a workgroup per pair, grid-stride.
 __global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, int n,
@@ -271,6 +380,17 @@ size_t trace_lds_bytes(bool lds_bits) {
   if (lds_bits) b += (size_t)kTraceLdsRowTiles * 64 * sizeof(uint16_t) + 6 * kTraceLdsCarryRows * sizeof(int);
   else b += (size_t)dev::kWalkRows * 64 * sizeof(uint16_t);
   return b;
+}
+
+size_t endtoend_lds_bytes() { return (size_t)kMaxAlpha * kMaxAlpha * sizeof(int); }
+
+hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st) {
+  if (a.n <= 0 || grid <= 0) return hipSuccess;
+  if (mode == 0)
+    hipLaunchKernelGGL(dev::endtoend_kernel<0>, dim3(grid), dim3(64), endtoend_lds_bytes(), st, a);
+  else
+    hipLaunchKernelGGL(dev::endtoend_kernel<1>, dim3(grid), dim3(64), endtoend_lds_bytes(), st, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs,

@@ -185,3 +185,18 @@ def test_cigar_rejects_bad_arguments(lib):
     b.n_pairs = -1
     assert lib.sw_align_batch_cigar(ctypes.byref(b), ctypes.byref(sc), None, None, None, None, 0,
                                     off.ctypes.data) == api.SW_EINVAL
+
+
+def test_global_rejects_bad_arguments(lib):
+    M = np.eye(4, dtype=np.int32)
+    sc, keep = _sc(M)
+    b = api.Batch()
+    out = np.zeros((2, 4), dtype=np.int32)
+    assert lib.sw_align_batch_global(None, ctypes.byref(sc), 0, out.ctypes.data) == api.SW_EINVAL
+    b.n_pairs = 0
+    assert lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), 0, None) == api.SW_OK
+    assert lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), 2,
+                                     out.ctypes.data) == api.SW_EINVAL        # no such mode
+    b.n_pairs = 1                                   # arrays missing
+    assert lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), 1,
+                                     out.ctypes.data) == api.SW_EINVAL

@@ -1,0 +1,108 @@
+"""End-to-end scores (sw_align_batch_global): global and semi-global (query
+end to end, reference ends free) results equal the CPU oracle's exactly --
+score, query_end and the smallest optimal reference end -- through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_00899_amd import api, workloads as W
+
+pytestmark = pytest.mark.gpu
+MODES = [api.SW_MODE_GLOBAL, api.SW_MODE_SEMIGLOBAL]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    oracle.build(force=False)
+    api.load()          # raises if the HIP library is missing: no fallback
+    api.sw_init()
+
+
+def _run(w, mode, **kw):
+    return api.sw_align_batch_global(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref,
+                                     w.matrix, w.gap_open, w.gap_extend, mode=mode,
+                                     pair_query=w.pair_query, **kw)
+
+
+def _check(w, mode, label, pairs=None):
+    got = _run(w, mode)
+    idx = list(range(w.n_pairs)) if pairs is None else list(pairs)
+    want = oracle.endtoend_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref,
+                                 w.matrix, w.gap_open, w.gap_extend, mode,
+                                 pair_query=w.pair_query, pairs=idx)
+    g = got[idx, :3].astype(np.int64)
+    bad = np.nonzero((g != want).any(axis=1))[0]
+    if bad.size:
+        k = int(bad[0])
+        raise AssertionError("%s mode %d: %d/%d mismatches; first pair %d got %s want %s" %
+                             (label, mode, bad.size, len(idx), idx[k], g[k].tolist(),
+                              want[k].tolist()))
+    assert (got[:, 3] == 0).all()
+    return got
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("alpha,go,ge", [(2, 2, 1), (4, 3, 1), (20, 11, 1), (3, 1, 0),
+                                         (4, 2, 5), (4, 0, 0)])
+def test_small_pairs_equal_the_oracle(mode, alpha, go, ge):
+    # empty sides, one residue, ragged lengths; (2, 5): extension above opening
+    rng = np.random.default_rng(970 + alpha + go + 7 * mode)
+    M = W.protein_matrix() if alpha == 20 else W.random_matrix(rng, alpha)
+    w = W.random_pairs(500, alpha, (0, 60), (0, 70), 971 + alpha + mode, matrix=M,
+                       gap_open=go, gap_extend=ge)
+    _check(w, mode, "small")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_queries_across_tiles(mode):
+    # queries of 257-900 residues: two to four 256-column tiles with carries,
+    # references from 1 to 400
+    rng = np.random.default_rng(980 + mode)
+    w = W.random_pairs(60, 4, (257, 900), (1, 400), 981 + mode, matrix=W.random_matrix(rng, 4),
+                       gap_open=3, gap_extend=1)
+    _check(w, mode, "tiles")
+
+
+def test_dna_pairs_subset():
+    # reads inside their windows: semi-global places each read, global also
+    # pays for the window's overhang; every pair scores at least as well
+    # semi-globally, and locally better still
+    w = W.dna_pairs(n_pairs=2000, seed=25)
+    glob = _check(w, api.SW_MODE_GLOBAL, "dna", pairs=range(0, 2000, 50))
+    semi = _check(w, api.SW_MODE_SEMIGLOBAL, "dna", pairs=range(0, 2000, 50))
+    assert (semi[:, 0] >= glob[:, 0]).all()
+    assert np.median(semi[:, 0]) > 100           # 150 bp reads, 2% substitutions
+    local = api.align_workload(w).results
+    assert (local[:, 0] >= semi[:, 0]).all()
+
+
+def test_protein_search_sample_and_shared_query():
+    w = W.protein_search(n_refs=2000)
+    for mode in MODES:
+        _check(w, mode, "protein", pairs=range(0, 2000, 200))
+
+
+def test_device_resident_inputs_and_errors():
+    import torch
+    w = W.random_pairs(200, 4, (0, 300), (0, 300), 990)
+    host = _run(w, api.SW_MODE_SEMIGLOBAL)
+    dev = torch.device("cuda")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    got = api.sw_align_batch_global(t(w.query_res, torch.uint8), t(w.query_off, torch.int64),
+                                    t(w.ref_res, torch.uint8), t(w.ref_off, torch.int64),
+                                    t(w.pair_ref, torch.int32), w.matrix, w.gap_open,
+                                    w.gap_extend, mode=api.SW_MODE_SEMIGLOBAL,
+                                    pair_query=t(w.pair_query, torch.int32))
+    assert (got == host).all()
+    ref = w.ref_res.copy()
+    ref[len(ref) // 2] = 7                       # beyond the 4-letter alphabet
+    with pytest.raises(api.SwError) as e:
+        api.sw_align_batch_global(w.query_res, w.query_off, ref, w.ref_off, w.pair_ref, w.matrix,
+                                  w.gap_open, w.gap_extend, mode=api.SW_MODE_GLOBAL,
+                                  pair_query=w.pair_query)
+    assert e.value.code == api.SW_EINVAL
+    with pytest.raises(api.SwError) as e:
+        _run(w, 5)
+    assert e.value.code == api.SW_EINVAL
+    again = _run(w, api.SW_MODE_SEMIGLOBAL)
+    assert (again == host).all()
