@@ -288,6 +288,25 @@ def _paths_leg(api, d, pq, w, ends, qs, rs, reps):
             "alignments_per_s": round(live.sum() / ms * 1e3, 1)}
 
 
+def _endtoend_leg(api, d, pq, w, reps):
+    """sw_align_batch_global in both modes on the same pairs (whole calls,
+    device-resident sequences): every cell of every pair is computed."""
+    import torch
+    res = {}
+    cells = w.cells()
+    for name, mode in (("global", api.SW_MODE_GLOBAL), ("semiglobal", api.SW_MODE_SEMIGLOBAL)):
+        api.sw_align_batch_global(*d, w.matrix, w.gap_open, w.gap_extend, mode=mode, pair_query=pq)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = api.sw_align_batch_global(*d, w.matrix, w.gap_open, w.gap_extend, mode=mode,
+                                          pair_query=pq)
+        ms = (time.perf_counter() - t) / reps * 1e3
+        res[name] = {"ms_per_call": round(ms, 3), "gcups": round(cells / ms / 1e6, 1),
+                     "median_score": int(np.median(r[:, 0]))}
+    return res
+
+
 def _device_batch(w):
     import torch
     dev = torch.device("cuda:0")
@@ -361,6 +380,7 @@ def bench_dna(args):
                                            pair_query=pq)
     starts_ms = (time.perf_counter() - ts) / reps * 1e3
     paths = _paths_leg(api, d, pq, w, out.results, qs, rs, reps)
+    endtoend = _endtoend_leg(api, d, pq, w, reps)
     print(json.dumps({"metric": METRIC, "value": round(cells / wall / 1e9, 2), "unit": "GCUPS",
                       "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                       "ms_per_step": round(wall * 1e3, 3), "higher_is_better": True,
@@ -393,6 +413,7 @@ def bench_dna(args):
                                                                            out.results))},
                       "starts": {"ms_per_call": round(starts_ms, 3)},
                       "paths": paths,
+                      "endtoend": endtoend,
                       "tuned": [{k: (round(v, 1) if isinstance(v, float) else v)
                                  for k, v in e.items()} for e in tuned]}))
 
