@@ -32,7 +32,7 @@ PEAK_I32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 PEAK_I16X2_TOPS = 2 * PEAK_I32_TOPS
 OPS_PER_CELL = 11   # Algorithm 6 inner loop: 1 add, 6 max, 4 sub
 # the alignment kernel of a device-planned int16 single-query batch
-KERNEL_NAME = "shared_rowpair_kernel<16, true>"
+KERNEL_NAME = "shared_rowpair_kernel<16, true, false>"
 
 
 # sources that define the protein-search kernel and its launch: the counter
