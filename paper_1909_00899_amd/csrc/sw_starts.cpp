@@ -26,6 +26,7 @@
 
 #include "sw.h"
 #include "sw_internal.h"
+#include "sw_trace.h"
 #include "sw_runtime.h"
 
 using namespace swrt;
@@ -430,8 +431,14 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     tp.pad = 0;
     region += tp.cap;
     const int64_t tiles = (Bq + swk::kTraceTileCols - 1) / swk::kTraceTileCols;
-    if (A * tiles <= swk::kTraceLdsRowTiles) htab[nl++] = tp;
-    else glob.push_back(tp);
+    // columns per lane: the fewest that hold a one-tile query (LDS path only)
+    tp.pad = (int32_t)std::min<int64_t>(4, (Bq + 63) / 64);
+    if (A * tiles <= swk::kTraceLdsRowTiles) {
+      htab[nl++] = tp;
+    } else {
+      tp.pad = 4;
+      glob.push_back(tp);
+    }
   }
   // device-memory rectangles: largest first, in groups of similar size
   std::sort(glob.begin(), glob.end(), [](const swk::TracePair &x, const swk::TracePair &y) {
@@ -623,7 +630,7 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
     tp.score = 0;
     tp.cap = 0;
     tp.id = k;
-    tp.pad = 0;
+    tp.pad = (int32_t)std::min<int64_t>(4, (m + 63) / 64);   // query columns per lane
     if (m <= swk::kTraceTileCols) {
       htab[n1++] = tp;
     } else {

@@ -1,0 +1,70 @@
+// Paths and end-to-end scores (sw_trace.hip): shared between the kernels
+// and the host code that plans their launches (sw_starts.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw_internal.h"
+
+namespace swk {
+
+constexpr int kTraceTileCols = 256;      // query columns per tile at 4 columns per lane
+constexpr int kTraceLdsRowTiles = 160;   // rows x tiles whose decision bits fit in LDS
+constexpr int kTraceLdsCarryRows = 80;   // a rectangle of two or more tiles in LDS has <= 80 rows
+constexpr int kCigarM = 0, kCigarI = 1, kCigarD = 2;
+constexpr int kTraceInconsistent = -2;   // no alignment of the given score from start to end
+constexpr int kTraceBadResidue = -3;     // a residue code >= alphabet size in the rectangle
+
+// One rectangle: query residues qres[q .. q + B), reference residues
+// rres[r .. r + A); its runs are written backward from cigar[out + cap - 1]
+// (first run of the path last); the count goes to n_runs[id], or
+// kTraceInconsistent / kTraceBadResidue.
+// pad: query columns per lane, 1-4 (a tile of 64 * pad columns; the LDS path
+// and end-to-end variants; the device-memory path variant uses 4).
+struct TracePair {
+  int64_t q, r, out;
+  int32_t A, B, score, cap, id, pad;
+};
+
+struct TraceArgs {
+  const TracePair *pairs;
+  int n;
+  const uint8_t *qres, *rres;
+  const int32_t *matrix;   // alpha x alpha, [query code][ref code], device
+  int alpha, go, ge;       // ge <= go
+  uint16_t *gbits;         // device-memory variant: slot_words per workgroup
+  int64_t slot_words;
+  int32_t *gcarry;         // device-memory variant: 6 * carry_rows per workgroup
+  int carry_rows;
+  uint32_t *cigar;         // device
+  int32_t *n_runs;         // device, indexed by TracePair::id
+};
+
+// LDS bytes of a workgroup; with lds_bits the decision bits and tile
+// carries live in LDS, else in gbits / gcarry (grid-stride over the pairs).
+size_t trace_lds_bytes(bool lds_bits);
+hipError_t launch_trace(bool lds_bits, const TraceArgs &a, int grid, hipStream_t st);
+// End-to-end scores (sw_trace.hip): TracePair with A = n, B = m (both >= 1);
+// results to out[id] (flags kFlagBadResidue for a residue >= alphabet size).
+constexpr int kFlagBadResidue = 1 << 20;
+struct EndArgs {
+  const TracePair *pairs;
+  int n;
+  const uint8_t *qres, *rres;
+  const int32_t *matrix;
+  int alpha, go, ge;
+  int32_t *gcarry;         // 4 * carry_rows per workgroup (pairs of two or more tiles)
+  int carry_rows;
+  DevResult *out;
+};
+size_t endtoend_lds_bytes();
+hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st);
+
+// Runs of every pair (n_runs[id] of them, ending at out + cap) to
+// dst[dst_off[id] ..]; every count must be <= its pair's cap.
+hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs,
+                            const int64_t *dst_off, const uint32_t *src, uint32_t *dst,
+                            hipStream_t st);
+
+}  // namespace swk

@@ -40,6 +40,7 @@
 #include <algorithm>
 
 #include "sw_internal.h"
+#include "sw_trace.h"
 
 namespace swk {
 namespace dev {
@@ -71,6 +72,185 @@ __device__ __forceinline__ int wave_max_scan(int x) {
 
 __device__ __forceinline__ int readlane(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
 
+// One pair at C query columns per lane (a tile of 64 C columns).
+template <bool LB, int C>
+__device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P, const int *smat,
+                                          uint16_t *lbits, int *lcarry, uint16_t *lwin) {
+  constexpr int TC = 64 * C;
+  const int L = threadIdx.x;
+  const int alpha = a.alpha, go = a.go, ge = a.ge;
+  const int A = P.A, B = P.B, T = (B + TC - 1) / TC;
+  uint16_t *bits = LB ? lbits : a.gbits + (size_t)blockIdx.x * a.slot_words;
+  int *carry = LB ? lcarry : a.gcarry + (size_t)blockIdx.x * 6 * a.carry_rows;
+  const int crow = LB ? kTraceLdsCarryRows : a.carry_rows;
+  bool bad = false, ok = false;
+
+  for (int t = 0; t < T; ++t) {
+    const int base = t * TC, jc0 = base + C * L;
+    const int *cr = carry + ((t + 1) & 1) * 3 * crow;   // written by tile t - 1
+    int *cw = carry + (t & 1) * 3 * crow;                // read by tile t + 1
+    int qb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int code = jc0 + c < B ? (int)a.qres[P.q + jc0 + c] : 0;
+      bad |= code >= alpha;
+      qb[c] = min(code, alpha - 1) * alpha;
+    }
+    int Vp[C], Gp[C], Fp[C], wj[C], ej[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      Vp[c] = Gp[c] = Fp[c] = kNeg;
+      wj[c] = (jc0 + c) * ge;              // scan term offset of column j
+      ej[c] = go + (jc0 + c - 1) * ge;     // Eg(., j) = prefix max - go - (j - 1) ge
+    }
+    int cv_prev = kNeg;                      // V(i-1, base-1)
+    int rreg = 0, crv = kNeg, crm = kNeg, crp = kNeg;
+    for (int i = 0; i < A; ++i) {
+      if ((i & 63) == 0) {                   // 64 rows of residues (and carries) at a time
+        const int row = i + L;
+        rreg = row < A ? (int)a.rres[P.r + row] : 0;
+        if (t == 0) bad |= rreg >= alpha;
+        if (t > 0 && row < A) {
+          crv = cr[3 * row];
+          crm = cr[3 * row + 1];
+          crp = cr[3 * row + 2];
+        }
+      }
+      const int rc = min(readlane(rreg, i & 63), alpha - 1);
+      const int cv_in = t ? readlane(crv, i & 63) : kNeg;   // V(i, base-1)
+      const int cm_in = t ? readlane(crm, i & 63) : kNeg;   // M(i, base-1)
+      const int cp_in = t ? readlane(crp, i & 63) : kNeg;   // max_{y<base} M(i, y) + y ge
+      int Mv[C];
+      // no clamps below: every cell off row 0 and column 0 is reachable
+      // (gaps from the start), so unreachable values only arise next to
+      // the kNeg edges and never drift (the host bounds the rest)
+      const int d0 = dpp_wave_shr1(cv_prev, Vp[C - 1]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) Mv[c] = smat[qb[c] + rc] + (c ? Vp[c - 1] : d0);
+      if (i == 0 && jc0 == 0) Mv[0] = smat[qb[0] + rc];      // the start pair
+      int w[C], lp[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) w[c] = Mv[c] + wj[c];
+      lp[0] = kNeg;
+#pragma unroll
+      for (int c = 1; c < C; ++c) lp[c] = c == 1 ? w[0] : max(lp[c - 1], w[c - 1]);
+      const int agg = C == 1 ? w[0] : max(lp[C - 1], w[C - 1]);
+      const int exc = max(dpp_wave_shr1(kNeg, wave_max_scan(agg)), cp_in);
+      const int m_left = dpp_wave_shr1(cm_in, Mv[C - 1]);      // M(i, jc0 - 1)
+      uint32_t word = 0;
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int eg = max(exc, lp[c]) - ej[c];
+        const int mprev = c ? Mv[c - 1] : m_left;
+        const int g = max(Mv[c], eg);
+        const int fo = Gp[c] - go, fe = Fp[c] - ge;
+        const int f = max(fo, fe);
+        const int v = max(g, f);
+        const uint32_t nib = (uint32_t)(g >= f) | (uint32_t)(fo >= fe) << 1 |
+                             (uint32_t)(Mv[c] >= eg) << 2 | (uint32_t)(mprev - go == eg) << 3;
+        word |= nib << (4 * c);
+        Vp[c] = v;
+        Gp[c] = g;
+        Fp[c] = f;
+      }
+      bits[((size_t)t * A + i) * 64 + L] = (uint16_t)word;
+      if (t + 1 < T && L == 63) {
+        cw[3 * i] = Vp[C - 1];
+        cw[3 * i + 1] = Mv[C - 1];
+        cw[3 * i + 2] = max(exc, agg);
+      }
+      cv_prev = cv_in;
+      if (t == T - 1 && i == A - 1) {
+        const int jb = B - 1 - jc0;
+        int mend = Mv[0];
+#pragma unroll
+        for (int c = 1; c < C; ++c)
+          if (jb == c) mend = Mv[c];
+        ok = __ballot(jb >= 0 && jb < C && mend == P.score) != 0;
+      }
+    }
+    // carries and bits are read back by this same wavefront: a workgroup-
+    // scope fence (wait for its own stores) is enough; an agent-scope one
+    // would write back the L2 of the XCD on every tile
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  }
+  bad = __ballot(bad) != 0;
+
+  // ---- walk back from the end pair; runs written backward from the end of
+  // the pair's region (the last run of the path at out + cap - 1)
+  int nrun = 0;
+  bool fail = !ok || bad;
+  const int64_t end = P.out + P.cap;
+  auto emit = [&](uint32_t v) {
+    if (nrun < P.cap && L == 0) a.cigar[end - 1 - nrun] = v;
+    ++nrun;
+  };
+  // device-memory bits are read through an LDS window of kWalkRows rows of
+  // one tile (the walk only moves up and left): one coalesced copy per
+  // window instead of a dependent device-memory load per step
+  int w_tile = -1, w_lo = 0;
+  auto nib_at = [&](int i, int j) -> int {
+    const int t = j / TC, col = (j % TC) / C;
+    uint32_t wd;
+    if (LB) {
+      wd = bits[((size_t)t * A + i) * 64 + col];
+    } else {
+      if (t != w_tile || i < w_lo || i >= w_lo + kWalkRows) {
+        w_tile = t;
+        w_lo = max(0, i - kWalkRows + 1);
+        const int rows = min(kWalkRows, A - w_lo);
+        const uint4 *src = (const uint4 *)(bits + ((size_t)t * A + w_lo) * 64);
+        uint4 *dst = (uint4 *)lwin;
+        for (int k = L; k < rows * 8; k += 64) dst[k] = src[k];
+      }
+      wd = lwin[(i - w_lo) * 64 + col];
+    }
+    return (int)(wd >> (4 * (j % C))) & 15;
+  };
+  if (!fail) {
+    int ra = A - 1, qb_ = B - 1, mrun = 1, guard = A + B + 2;
+    while ((ra | qb_) != 0) {
+      if (ra == 0 || qb_ == 0 || --guard < 0) { fail = true; break; }
+      int i = ra - 1, j = qb_ - 1, nd = 0, ni = 0;
+      int nib = nib_at(i, j);
+      if (!(nib & 1)) {                      // a reference gap ends at (i, j)
+        for (;;) {
+          ++nd;
+          const bool open = nib & 2;
+          if (--i < 0) { fail = true; break; }
+          nib = nib_at(i, j);
+          if (open) break;
+        }
+        if (fail) break;
+      }
+      if (!(nib & 4)) {                      // a query gap ends at (i, j)
+        for (;;) {
+          ++ni;
+          const bool open = nib & 8;
+          if (--j < 0) { fail = true; break; }
+          nib = nib_at(i, j);
+          if (open) break;
+        }
+        if (fail) break;
+      }
+      if (nd | ni) {
+        emit((uint32_t)mrun << 4 | kCigarM);
+        if (ni) emit((uint32_t)ni << 4 | kCigarI);
+        if (nd) emit((uint32_t)nd << 4 | kCigarD);
+        mrun = 0;
+      }
+      ++mrun;
+      ra = i;
+      qb_ = j;
+    }
+    if (!fail) emit((uint32_t)mrun << 4 | kCigarM);
+  }
+  if (L == 0) a.n_runs[P.id] = bad ? kTraceBadResidue : fail ? kTraceInconsistent : nrun;
+}
+
+// LDS variant: C per pair from TracePair::pad (the fewest columns per lane
+// that cover a one-tile query, so short queries leave few lanes idle);
+// device-memory variant: 4.
 template <bool LB>
 __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   extern __shared__ int smem[];
@@ -78,180 +258,20 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   uint16_t *lbits = (uint16_t *)(smem + kMaxAlpha * kMaxAlpha);
   int *lcarry = (int *)(lbits + kTraceLdsRowTiles * 64);
   uint16_t *lwin = lbits;                                      // walk window (device-memory bits)
-  const int L = threadIdx.x;
-  const int alpha = a.alpha, go = a.go, ge = a.ge;
-  for (int k = L; k < alpha * alpha; k += 64) smat[k] = a.matrix[k];
+  for (int k = threadIdx.x; k < a.alpha * a.alpha; k += 64) smat[k] = a.matrix[k];
   __syncthreads();
-
   for (int p = blockIdx.x; p < a.n; p += gridDim.x) {
     const TracePair P = a.pairs[p];
-    const int A = P.A, B = P.B, T = (B + kTraceTileCols - 1) / kTraceTileCols;
-    uint16_t *bits = LB ? lbits : a.gbits + (size_t)blockIdx.x * a.slot_words;
-    int *carry = LB ? lcarry : a.gcarry + (size_t)blockIdx.x * 6 * a.carry_rows;
-    const int crow = LB ? kTraceLdsCarryRows : a.carry_rows;
-    bool bad = false, ok = false;
-
-    for (int t = 0; t < T; ++t) {
-      const int base = t * kTraceTileCols, jc0 = base + 4 * L;
-      const int *cr = carry + ((t + 1) & 1) * 3 * crow;   // written by tile t - 1
-      int *cw = carry + (t & 1) * 3 * crow;                // read by tile t + 1
-      int qb[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int code = jc0 + c < B ? (int)a.qres[P.q + jc0 + c] : 0;
-        bad |= code >= alpha;
-        qb[c] = min(code, alpha - 1) * alpha;
+    if (!LB) {
+      trace_one<LB, 4>(a, P, smat, lbits, lcarry, lwin);
+    } else {
+      switch (P.pad) {
+        case 1: trace_one<LB, 1>(a, P, smat, lbits, lcarry, lwin); break;
+        case 2: trace_one<LB, 2>(a, P, smat, lbits, lcarry, lwin); break;
+        case 3: trace_one<LB, 3>(a, P, smat, lbits, lcarry, lwin); break;
+        default: trace_one<LB, 4>(a, P, smat, lbits, lcarry, lwin); break;
       }
-      int Vp[4], Gp[4], Fp[4], wj[4], ej[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        Vp[c] = Gp[c] = Fp[c] = kNeg;
-        wj[c] = (jc0 + c) * ge;              // scan term offset of column j
-        ej[c] = go + (jc0 + c - 1) * ge;     // Eg(., j) = prefix max - go - (j - 1) ge
-      }
-      int cv_prev = kNeg;                      // V(i-1, base-1)
-      int rreg = 0, crv = kNeg, crm = kNeg, crp = kNeg;
-      for (int i = 0; i < A; ++i) {
-        if ((i & 63) == 0) {                   // 64 rows of residues (and carries) at a time
-          const int row = i + L;
-          rreg = row < A ? (int)a.rres[P.r + row] : 0;
-          if (t == 0) bad |= rreg >= alpha;
-          if (t > 0 && row < A) {
-            crv = cr[3 * row];
-            crm = cr[3 * row + 1];
-            crp = cr[3 * row + 2];
-          }
-        }
-        const int rc = min(readlane(rreg, i & 63), alpha - 1);
-        const int cv_in = t ? readlane(crv, i & 63) : kNeg;   // V(i, base-1)
-        const int cm_in = t ? readlane(crm, i & 63) : kNeg;   // M(i, base-1)
-        const int cp_in = t ? readlane(crp, i & 63) : kNeg;   // max_{y<base} M(i, y) + y ge
-        int Mv[4];
-        // no clamps below: every cell off row 0 and column 0 is reachable
-        // (gaps from the start), so unreachable values only arise next to
-        // the kNeg edges and never drift (the host bounds the rest)
-        Mv[0] = smat[qb[0] + rc] + dpp_wave_shr1(cv_prev, Vp[3]);
-        Mv[1] = smat[qb[1] + rc] + Vp[0];
-        Mv[2] = smat[qb[2] + rc] + Vp[1];
-        Mv[3] = smat[qb[3] + rc] + Vp[2];
-        if (i == 0 && jc0 == 0) Mv[0] = smat[qb[0] + rc];      // the start pair
-        int w[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) w[c] = Mv[c] + wj[c];
-        int lp[4];
-        lp[0] = kNeg;
-        lp[1] = w[0];
-        lp[2] = max(w[0], w[1]);
-        lp[3] = max(lp[2], w[2]);
-        const int agg = max(lp[3], w[3]);
-        const int exc = max(dpp_wave_shr1(kNeg, wave_max_scan(agg)), cp_in);
-        const int m_left = dpp_wave_shr1(cm_in, Mv[3]);          // M(i, jc0 - 1)
-        uint32_t word = 0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int eg = max(exc, lp[c]) - ej[c];
-          const int mprev = c ? Mv[c - 1] : m_left;
-          const int g = max(Mv[c], eg);
-          const int fo = Gp[c] - go, fe = Fp[c] - ge;
-          const int f = max(fo, fe);
-          const int v = max(g, f);
-          const uint32_t nib = (uint32_t)(g >= f) | (uint32_t)(fo >= fe) << 1 |
-                               (uint32_t)(Mv[c] >= eg) << 2 | (uint32_t)(mprev - go == eg) << 3;
-          word |= nib << (4 * c);
-          Vp[c] = v;
-          Gp[c] = g;
-          Fp[c] = f;
-        }
-        bits[((size_t)t * A + i) * 64 + L] = (uint16_t)word;
-        if (t + 1 < T && L == 63) {
-          cw[3 * i] = Vp[3];
-          cw[3 * i + 1] = Mv[3];
-          cw[3 * i + 2] = max(exc, agg);
-        }
-        cv_prev = cv_in;
-        if (t == T - 1 && i == A - 1) {
-          const int jb = B - 1 - jc0;
-          const int mend = jb == 0 ? Mv[0] : jb == 1 ? Mv[1] : jb == 2 ? Mv[2] : Mv[3];
-          ok = __ballot(jb >= 0 && jb < 4 && mend == P.score) != 0;
-        }
-      }
-      // carries and bits are read back by this same wavefront: a workgroup-
-      // scope fence (wait for its own stores) is enough; an agent-scope one
-      // would write back the L2 of the XCD on every tile
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     }
-    bad = __ballot(bad) != 0;
-
-    // ---- walk back from the end pair; runs written backward from the end of
-    // the pair's region (the last run of the path at out + cap - 1)
-    int nrun = 0;
-    bool fail = !ok || bad;
-    const int64_t end = P.out + P.cap;
-    auto emit = [&](uint32_t v) {
-      if (nrun < P.cap && L == 0) a.cigar[end - 1 - nrun] = v;
-      ++nrun;
-    };
-    // device-memory bits are read through an LDS window of kWalkRows rows of
-    // one tile (the walk only moves up and left): one coalesced copy per
-    // window instead of a dependent device-memory load per step
-    int w_tile = -1, w_lo = 0;
-    auto nib_at = [&](int i, int j) -> int {
-      const int t = j / kTraceTileCols, col = (j % kTraceTileCols) / 4;
-      uint32_t wd;
-      if (LB) {
-        wd = bits[((size_t)t * A + i) * 64 + col];
-      } else {
-        if (t != w_tile || i < w_lo || i >= w_lo + kWalkRows) {
-          w_tile = t;
-          w_lo = max(0, i - kWalkRows + 1);
-          const int rows = min(kWalkRows, A - w_lo);
-          const uint4 *src = (const uint4 *)(bits + ((size_t)t * A + w_lo) * 64);
-          uint4 *dst = (uint4 *)lwin;
-          for (int k = L; k < rows * 8; k += 64) dst[k] = src[k];
-        }
-        wd = lwin[(i - w_lo) * 64 + col];
-      }
-      return (int)(wd >> (4 * (j & 3))) & 15;
-    };
-    if (!fail) {
-      int ra = A - 1, qb_ = B - 1, mrun = 1, guard = A + B + 2;
-      while ((ra | qb_) != 0) {
-        if (ra == 0 || qb_ == 0 || --guard < 0) { fail = true; break; }
-        int i = ra - 1, j = qb_ - 1, nd = 0, ni = 0;
-        int nib = nib_at(i, j);
-        if (!(nib & 1)) {                      // a reference gap ends at (i, j)
-          for (;;) {
-            ++nd;
-            const bool open = nib & 2;
-            if (--i < 0) { fail = true; break; }
-            nib = nib_at(i, j);
-            if (open) break;
-          }
-          if (fail) break;
-        }
-        if (!(nib & 4)) {                      // a query gap ends at (i, j)
-          for (;;) {
-            ++ni;
-            const bool open = nib & 8;
-            if (--j < 0) { fail = true; break; }
-            nib = nib_at(i, j);
-            if (open) break;
-          }
-          if (fail) break;
-        }
-        if (nd | ni) {
-          emit((uint32_t)mrun << 4 | kCigarM);
-          if (ni) emit((uint32_t)ni << 4 | kCigarI);
-          if (nd) emit((uint32_t)nd << 4 | kCigarD);
-          mrun = 0;
-        }
-        ++mrun;
-        ra = i;
-        qb_ = j;
-      }
-      if (!fail) emit((uint32_t)mrun << 4 | kCigarM);
-    }
-    if (L == 0) a.n_runs[P.id] = bad ? kTraceBadResidue : fail ? kTraceInconsistent : nrun;
   }
 }
 
@@ -259,101 +279,114 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
 // free) score of each pair; one wavefront per pair, the query in tiles of 256
 // columns as in trace_kernel, V and the scan total of each tile's last column
 // carried per row in the wavefront's slot of gcarry.
+template <int MODE, int C>
+__device__ __forceinline__ void endtoend_one(const EndArgs &a, const TracePair &P,
+                                             const int *smat) {
+  constexpr int TC = 64 * C;
+  const int L = threadIdx.x;
+  const int alpha = a.alpha, go = a.go, ge = a.ge;
+  const int A = P.A, B = P.B, T = (B + TC - 1) / TC;
+  int *carry = a.gcarry + (size_t)blockIdx.x * 4 * a.carry_rows;
+  bool bad = false;
+  // semi-global: best V(a, B-1) over a = -1 .. A-1, the first one on ties
+  int best = -(go + (B - 1) * ge), best_row = -1, score = 0;
+  for (int t = 0; t < T; ++t) {
+    const int base = t * TC, jc0 = base + C * L;
+    const int *cr = carry + ((t + 1) & 1) * 2 * a.carry_rows;
+    int *cw = carry + (t & 1) * 2 * a.carry_rows;
+    int qb[C], Vp[C], Gp[C], Fp[C], wj[C], ej[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int code = jc0 + c < B ? (int)a.qres[P.q + jc0 + c] : 0;
+      bad |= code >= alpha;
+      qb[c] = min(code, alpha - 1) * alpha;
+      Vp[c] = Gp[c] = -(go + (jc0 + c) * ge);   // row -1: the first j + 1 query residues skipped
+      Fp[c] = kNeg;
+      wj[c] = (jc0 + c) * ge;
+      ej[c] = go + (jc0 + c - 1) * ge;
+    }
+    // V(-1, base - 1): the virtual pair, or the row -1 gap run
+    int cv_prev = base == 0 ? 0 : -(go + (base - 1) * ge);
+    int rreg = 0, crv = kNeg, crp = kNeg;
+    for (int i = 0; i < A; ++i) {
+      if ((i & 63) == 0) {
+        const int row = i + L;
+        rreg = row < A ? (int)a.rres[P.r + row] : 0;
+        if (t == 0) bad |= rreg >= alpha;
+        if (t > 0 && row < A) {
+          crv = cr[2 * row];
+          crp = cr[2 * row + 1];
+        }
+      }
+      const int rc = min(readlane(rreg, i & 63), alpha - 1);
+      // column -1: V(i, -1) and the scan term of M(i, -1)
+      const int cv_in = t ? readlane(crv, i & 63) : (MODE == 0 ? -(go + i * ge) : 0);
+      const int cp_in = t ? readlane(crp, i & 63) : (MODE == 0 ? kNeg : -ge);
+      int Mv[C];
+      const int d0 = dpp_wave_shr1(cv_prev, Vp[C - 1]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) Mv[c] = smat[qb[c] + rc] + (c ? Vp[c - 1] : d0);
+      int w[C], lp[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) w[c] = Mv[c] + wj[c];
+      lp[0] = kNeg;
+#pragma unroll
+      for (int c = 1; c < C; ++c) lp[c] = c == 1 ? w[0] : max(lp[c - 1], w[c - 1]);
+      const int agg = C == 1 ? w[0] : max(lp[C - 1], w[C - 1]);
+      const int exc = max(dpp_wave_shr1(kNeg, wave_max_scan(agg)), cp_in);
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        const int g = max(Mv[c], max(exc, lp[c]) - ej[c]);
+        const int f = max(Gp[c] - go, Fp[c] - ge);
+        Vp[c] = max(g, f);
+        Gp[c] = g;
+        Fp[c] = f;
+      }
+      if (t + 1 < T && L == 63) {
+        cw[2 * i] = Vp[C - 1];
+        cw[2 * i + 1] = max(exc, agg);
+      }
+      cv_prev = cv_in;
+      if (t == T - 1) {
+        const int jb = B - 1 - jc0;
+        int v = Vp[0];
+#pragma unroll
+        for (int c = 1; c < C; ++c)
+          if (jb == c) v = Vp[c];
+        if (MODE == 1 && v > best) {
+          best = v;
+          best_row = i;
+        }
+        score = v;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // carries before tile t + 1
+  }
+  bad = __ballot(bad) != 0;
+  const int jb = B - 1 - (T - 1) * TC - C * L;
+  if (jb >= 0 && jb < C) {
+    DevResult r;
+    r.score = MODE == 0 ? score : best;
+    r.qend = B - 1;
+    r.rend = MODE == 0 ? A - 1 : best_row;
+    r.flags = bad ? kFlagBadResidue : 0;
+    a.out[P.id] = r;
+  }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(64) void endtoend_kernel(EndArgs a) {
   extern __shared__ int smem[];
   int *smat = smem;
-  const int L = threadIdx.x;
-  const int alpha = a.alpha, go = a.go, ge = a.ge;
-  for (int k = L; k < alpha * alpha; k += 64) smat[k] = a.matrix[k];
+  for (int k = threadIdx.x; k < a.alpha * a.alpha; k += 64) smat[k] = a.matrix[k];
   __syncthreads();
   for (int p = blockIdx.x; p < a.n; p += gridDim.x) {
     const TracePair P = a.pairs[p];
-    const int A = P.A, B = P.B, T = (B + kTraceTileCols - 1) / kTraceTileCols;
-    int *carry = a.gcarry + (size_t)blockIdx.x * 4 * a.carry_rows;
-    bool bad = false;
-    // semi-global: best V(a, B-1) over a = -1 .. A-1, the first one on ties
-    int best = -(go + (B - 1) * ge), best_row = -1, score = 0;
-    for (int t = 0; t < T; ++t) {
-      const int base = t * kTraceTileCols, jc0 = base + 4 * L;
-      const int *cr = carry + ((t + 1) & 1) * 2 * a.carry_rows;
-      int *cw = carry + (t & 1) * 2 * a.carry_rows;
-      int qb[4], Vp[4], Gp[4], Fp[4], wj[4], ej[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int code = jc0 + c < B ? (int)a.qres[P.q + jc0 + c] : 0;
-        bad |= code >= alpha;
-        qb[c] = min(code, alpha - 1) * alpha;
-        Vp[c] = Gp[c] = -(go + (jc0 + c) * ge);   // row -1: the first j + 1 query residues skipped
-        Fp[c] = kNeg;
-        wj[c] = (jc0 + c) * ge;
-        ej[c] = go + (jc0 + c - 1) * ge;
-      }
-      // V(-1, base - 1): the virtual pair, or the row -1 gap run
-      int cv_prev = base == 0 ? 0 : -(go + (base - 1) * ge);
-      int rreg = 0, crv = kNeg, crp = kNeg;
-      for (int i = 0; i < A; ++i) {
-        if ((i & 63) == 0) {
-          const int row = i + L;
-          rreg = row < A ? (int)a.rres[P.r + row] : 0;
-          if (t == 0) bad |= rreg >= alpha;
-          if (t > 0 && row < A) {
-            crv = cr[2 * row];
-            crp = cr[2 * row + 1];
-          }
-        }
-        const int rc = min(readlane(rreg, i & 63), alpha - 1);
-        // column -1: V(i, -1) and the scan term of M(i, -1)
-        const int cv_in = t ? readlane(crv, i & 63) : (MODE == 0 ? -(go + i * ge) : 0);
-        const int cp_in = t ? readlane(crp, i & 63) : (MODE == 0 ? kNeg : -ge);
-        int Mv[4];
-        Mv[0] = smat[qb[0] + rc] + dpp_wave_shr1(cv_prev, Vp[3]);
-        Mv[1] = smat[qb[1] + rc] + Vp[0];
-        Mv[2] = smat[qb[2] + rc] + Vp[1];
-        Mv[3] = smat[qb[3] + rc] + Vp[2];
-        int w[4], lp[4];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) w[c] = Mv[c] + wj[c];
-        lp[0] = kNeg;
-        lp[1] = w[0];
-        lp[2] = max(w[0], w[1]);
-        lp[3] = max(lp[2], w[2]);
-        const int agg = max(lp[3], w[3]);
-        const int exc = max(dpp_wave_shr1(kNeg, wave_max_scan(agg)), cp_in);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int g = max(Mv[c], max(exc, lp[c]) - ej[c]);
-          const int f = max(Gp[c] - go, Fp[c] - ge);
-          Vp[c] = max(g, f);
-          Gp[c] = g;
-          Fp[c] = f;
-        }
-        if (t + 1 < T && L == 63) {
-          cw[2 * i] = Vp[3];
-          cw[2 * i + 1] = max(exc, agg);
-        }
-        cv_prev = cv_in;
-        if (t == T - 1) {
-          const int jb = B - 1 - jc0;
-          const int v = jb == 0 ? Vp[0] : jb == 1 ? Vp[1] : jb == 2 ? Vp[2] : Vp[3];
-          if (MODE == 1 && v > best) {
-            best = v;
-            best_row = i;
-          }
-          score = v;
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // carries before tile t + 1
-    }
-    bad = __ballot(bad) != 0;
-    const int jb = B - 1 - (T - 1) * kTraceTileCols - 4 * L;
-    if (jb >= 0 && jb < 4) {
-      DevResult r;
-      r.score = MODE == 0 ? score : best;
-      r.qend = B - 1;
-      r.rend = MODE == 0 ? A - 1 : best_row;
-      r.flags = bad ? kFlagBadResidue : 0;
-      a.out[P.id] = r;
+    switch (P.pad) {   // query columns per lane
+      case 1: endtoend_one<MODE, 1>(a, P, smat); break;
+      case 2: endtoend_one<MODE, 2>(a, P, smat); break;
+      case 3: endtoend_one<MODE, 3>(a, P, smat); break;
+      default: endtoend_one<MODE, 4>(a, P, smat); break;
     }
   }
 }

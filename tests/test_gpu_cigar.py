@@ -111,6 +111,17 @@ def test_paths_across_tiles_in_lds():
     _check_oracle(w, ends, qs, rs, runs, off, "tiles lds", range(w.n_pairs))
 
 
+def test_paths_every_column_count():
+    # 24-row rectangles whose query spans fall in each columns-per-lane class
+    # (1-64, 65-128, 129-192, 193-256 columns: 1, 2, 3, 4 columns per lane)
+    w = _gap_family(8, 964, (12, 12), [10, 40, 70, 100, 140, 150, 200, 230])
+    ends, qs, rs, runs, off = _paths(w)
+    _check_properties(w, ends, qs, rs, runs, off, "columns")
+    B = ends[:, 1] - qs + 1
+    assert {int((b + 63) // 64) for b in B} == {1, 2, 3, 4}
+    _check_oracle(w, ends, qs, rs, runs, off, "columns", range(w.n_pairs))
+
+
 def test_paths_in_device_memory():
     # 90 rows x about 290-370 columns: beyond LDS, decision bits in device memory
     w = _gap_family(4, 961, (45, 45), [200, 280])

@@ -54,6 +54,16 @@ def test_small_pairs_equal_the_oracle(mode, alpha, go, ge):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_every_column_count(mode):
+    # queries of 1-256 residues: 1, 2, 3 and 4 columns per lane, ragged ends
+    rng = np.random.default_rng(985 + mode)
+    w = W.random_pairs(300, 4, (1, 256), (1, 120), 986 + mode, matrix=W.random_matrix(rng, 4),
+                       gap_open=2, gap_extend=1)
+    assert {int((m + 63) // 64) for m in np.diff(w.query_off)} == {1, 2, 3, 4}
+    _check(w, mode, "columns")
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_queries_across_tiles(mode):
     # queries of 257-900 residues: two to four 256-column tiles with carries,
     # references from 1 to 400
