@@ -41,9 +41,10 @@ struct TraceArgs {
   int32_t *n_runs;         // device, indexed by TracePair::id
 };
 
-// LDS bytes of a workgroup; with lds_bits the decision bits and tile
-// carries live in LDS, else in gbits / gcarry (grid-stride over the pairs).
-size_t trace_lds_bytes(bool lds_bits);
+// LDS bytes of a workgroup (the matrix sized for the alphabet); with
+// lds_bits the decision bits and tile carries live in LDS, else in gbits /
+// gcarry (grid-stride over the pairs).
+size_t trace_lds_bytes(bool lds_bits, int alpha);
 hipError_t launch_trace(bool lds_bits, const TraceArgs &a, int grid, hipStream_t st);
 // End-to-end scores (sw_trace.hip): TracePair with A = n, B = m (both >= 1);
 // results to out[id] (flags kFlagBadResidue for a residue >= alphabet size).
@@ -58,7 +59,7 @@ struct EndArgs {
   int carry_rows;
   DevResult *out;
 };
-size_t endtoend_lds_bytes();
+size_t endtoend_lds_bytes(int alpha);
 hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st);
 
 // Runs of every pair (n_runs[id] of them, ending at out + cap) to

@@ -72,6 +72,9 @@ __device__ __forceinline__ int wave_max_scan(int x) {
 
 __device__ __forceinline__ int readlane(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
 
+// LDS words of the staged matrix: alpha^2, rounded up to 16 bytes
+__host__ __device__ constexpr int mat_words(int alpha) { return (alpha * alpha + 3) / 4 * 4; }
+
 // One pair at C query columns per lane (a tile of 64 C columns).
 template <bool LB, int C>
 __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P, const int *smat,
@@ -255,7 +258,8 @@ template <bool LB>
 __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   extern __shared__ int smem[];
   int *smat = smem;                                            // [query code][ref code]
-  uint16_t *lbits = (uint16_t *)(smem + kMaxAlpha * kMaxAlpha);
+  // the matrix takes alpha^2 words (16-byte aligned), the bits follow
+  uint16_t *lbits = (uint16_t *)(smem + mat_words(a.alpha));
   int *lcarry = (int *)(lbits + kTraceLdsRowTiles * 64);
   uint16_t *lwin = lbits;                                      // walk window (device-memory bits)
   for (int k = threadIdx.x; k < a.alpha * a.alpha; k += 64) smat[k] = a.matrix[k];
@@ -408,21 +412,23 @@ __global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, 
 }  // namespace
 }  // namespace dev
 
-size_t trace_lds_bytes(bool lds_bits) {
-  size_t b = (size_t)kMaxAlpha * kMaxAlpha * sizeof(int);
+size_t trace_lds_bytes(bool lds_bits, int alpha) {
+  size_t b = (size_t)dev::mat_words(alpha) * sizeof(int);
   if (lds_bits) b += (size_t)kTraceLdsRowTiles * 64 * sizeof(uint16_t) + 6 * kTraceLdsCarryRows * sizeof(int);
   else b += (size_t)dev::kWalkRows * 64 * sizeof(uint16_t);
   return b;
 }
 
-size_t endtoend_lds_bytes() { return (size_t)kMaxAlpha * kMaxAlpha * sizeof(int); }
+size_t endtoend_lds_bytes(int alpha) { return (size_t)dev::mat_words(alpha) * sizeof(int); }
 
 hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st) {
   if (a.n <= 0 || grid <= 0) return hipSuccess;
   if (mode == 0)
-    hipLaunchKernelGGL(dev::endtoend_kernel<0>, dim3(grid), dim3(64), endtoend_lds_bytes(), st, a);
+    hipLaunchKernelGGL(dev::endtoend_kernel<0>, dim3(grid), dim3(64), endtoend_lds_bytes(a.alpha),
+                       st, a);
   else
-    hipLaunchKernelGGL(dev::endtoend_kernel<1>, dim3(grid), dim3(64), endtoend_lds_bytes(), st, a);
+    hipLaunchKernelGGL(dev::endtoend_kernel<1>, dim3(grid), dim3(64), endtoend_lds_bytes(a.alpha),
+                       st, a);
   return hipGetLastError();
 }
 
@@ -438,9 +444,11 @@ hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs
 hipError_t launch_trace(bool lds_bits, const TraceArgs &a, int grid, hipStream_t st) {
   if (a.n <= 0 || grid <= 0) return hipSuccess;
   if (lds_bits)
-    hipLaunchKernelGGL(dev::trace_kernel<true>, dim3(grid), dim3(64), trace_lds_bytes(true), st, a);
+    hipLaunchKernelGGL(dev::trace_kernel<true>, dim3(grid), dim3(64), trace_lds_bytes(true, a.alpha),
+                       st, a);
   else
-    hipLaunchKernelGGL(dev::trace_kernel<false>, dim3(grid), dim3(64), trace_lds_bytes(false), st, a);
+    hipLaunchKernelGGL(dev::trace_kernel<false>, dim3(grid), dim3(64),
+                       trace_lds_bytes(false, a.alpha), st, a);
   return hipGetLastError();
 }
 
