@@ -42,6 +42,32 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(uint32_t *out, int trip
   out[blockIdx.x * blockDim.x + threadIdx.x] = x;
 }
 
+// The same for 32-bit integer maxima and adds (v_max_i32 / v_add_u32, the
+// instructions of the int32 path and end-to-end kernels): one op per lane
+// per instruction.
+__global__ __launch_bounds__(256) void valu_probe_i32_kernel(uint32_t *out, int trips) {
+  int acc[kAcc], add[kAcc];
+  const uint32_t seed = threadIdx.x * 2654435761u ^ blockIdx.x;
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) {
+    acc[k] = (int)(seed + 977u * k);
+    add[k] = (int)((seed >> 3) | 7u) + k;
+  }
+  for (int t = 0; t < trips; ++t) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+#pragma unroll
+      for (int k = 0; k < kAcc; ++k) {
+        acc[k] = max(acc[k] + add[k], add[k] - u);
+      }
+    }
+  }
+  uint32_t x = 0;
+#pragma unroll
+  for (int k = 0; k < kAcc; ++k) x ^= (uint32_t)acc[k];
+  out[blockIdx.x * blockDim.x + threadIdx.x] = x;
+}
+
 }  // namespace
 
 // Runs `grid` workgroups of 256 threads, `trips` loop trips each, and returns
@@ -67,6 +93,36 @@ extern "C" int swprobe_valu(int grid, int trips, double *ops_per_s) {
   if (e == hipSuccess) {
     const double instr = (double)grid * 256 * trips * kUnroll * kAcc * 2;
     *ops_per_s = ms > 0.f ? 2.0 * instr / (ms * 1e-3) : 0.0;
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (out) hipFree(out);
+  return (int)e;
+}
+
+// As swprobe_valu for the 32-bit kernel: *ops_per_s receives int32 operations
+// per second (an add and a maximum per step and lane; the subtraction of the
+// loop constant is hoisted by the compiler).  0 on success, else the HIP error.
+extern "C" int swprobe_valu_i32(int grid, int trips, double *ops_per_s) {
+  if (grid <= 0 || trips <= 0 || ops_per_s == nullptr) return (int)hipErrorInvalidValue;
+  uint32_t *out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc((void **)&out, (size_t)grid * 256 * sizeof(uint32_t));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  float ms = 0.f;
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(valu_probe_i32_kernel, dim3(grid), dim3(256), 0, nullptr, out, 1);
+    hipEventRecord(e0, nullptr);
+    hipLaunchKernelGGL(valu_probe_i32_kernel, dim3(grid), dim3(256), 0, nullptr, out, trips);
+    hipEventRecord(e1, nullptr);
+    e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  }
+  if (e == hipSuccess) {
+    const double ops = (double)grid * 256 * trips * kUnroll * kAcc * 2;
+    *ops_per_s = ms > 0.f ? ops / (ms * 1e-3) : 0.0;
   }
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);

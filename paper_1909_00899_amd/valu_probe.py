@@ -19,5 +19,17 @@ def measure(grid: int = 2048, trips: int = 20000) -> float:
     return out.value
 
 
+def measure_i32(grid: int = 2048, trips: int = 20000) -> float:
+    """32-bit integer operations per second (v_add_u32 and v_max_i32 streams)."""
+    lib = ctypes.CDLL(os.path.join(HERE, "libswprobe.so"))
+    lib.swprobe_valu_i32.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    out = ctypes.c_double(0.0)
+    rc = lib.swprobe_valu_i32(grid, trips, ctypes.byref(out))
+    if rc != 0:
+        raise RuntimeError("VALU probe failed with HIP error %d" % rc)
+    return out.value
+
+
 if __name__ == "__main__":
-    print("%.2f Tops/s" % (measure() / 1e12))
+    print("int16x2: %.2f Tops/s" % (measure() / 1e12))
+    print("int32:   %.2f Tops/s" % (measure_i32() / 1e12))

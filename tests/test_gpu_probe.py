@@ -11,3 +11,12 @@ def test_valu_probe_rate():
     derived = 256 * 4 * 16 * 2.4e9 * 2
     r = valu_probe.measure(grid=2048, trips=2000)
     assert 0.3 * derived < r < 1.1 * derived, r / derived
+
+
+def test_valu_probe_int32_rate():
+    # one 32-bit op per lane per instruction: of the order of 16 lanes per
+    # SIMD per cycle (some instructions may pair up, hence the slack)
+    from paper_1909_00899_amd import valu_probe
+    derived = 256 * 4 * 16 * 2.4e9
+    r = valu_probe.measure_i32(grid=2048, trips=2000)
+    assert 0.3 * derived < r < 2.2 * derived, r / derived
