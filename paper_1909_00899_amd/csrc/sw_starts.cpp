@@ -1,5 +1,7 @@
-// Start cells and paths of a batch's alignments (include/sw.h,
-// sw_align_batch_starts and sw_align_batch_cigar).
+// Start cells and paths of a batch's alignments, and end-to-end scores of a
+// batch (include/sw.h: sw_align_batch_starts, sw_align_batch_cigar,
+// sw_align_batch_global).  The three share the batch loading and validation
+// below and one set of work buffers, so their calls are serialised.
 //
 // The start of the reported alignment of a pair is the end cell of the same
 // local alignment problem on the reversed prefixes q[0..query_end] and
@@ -17,6 +19,10 @@
 //   lanes saturate, and batches that do not fit that kernel, take the next path;
 // * otherwise each reversed query prefix is a query of its own, through the
 //   batch path (device or host planner, int32 reruns).
+//
+// Paths and end-to-end scores run the kernels of sw_trace.hip; this file
+// builds their pair tables (validated on the host), sizes their scratch, and
+// packs the paths' runs for the caller.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
