@@ -354,3 +354,33 @@ def endtoend_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                             gap_open, gap_extend, mode))
     return np.array(out, dtype=np.int64).reshape(-1, 3)
 
+
+def endtoend_path(query, ref, matrix, gap_open: int, gap_extend: int, mode: int, end=None):
+    """(ref_start, runs) of the global (mode 0) or semi-global (mode 1)
+    alignment reported by ``endtoend``: walking back from its end, each
+    predecessor is the largest (ref, query) element -- aligned pair or the
+    virtual start pair, (-1, -1) globally, (v, -1) for a free reference prefix
+    r[0..v] -- on an optimal chain; between two elements D is written before
+    I.  ref_start is 0 globally, v + 1 semi-globally.  From
+    ``oracle_endtoend_path`` in sw_oracle.c (plain maxima over the chains)."""
+    q, r = _u8(query), _u8(ref)
+    M = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
+    s, qe, re_ = endtoend(q, r, M, gap_open, gap_extend, mode) if end is None else end
+    cap = q.size + r.size + 2
+    ops = np.zeros(cap, dtype=np.uint32)
+    rs = ctypes.c_int64(0)
+    lib = _load()
+    lib.oracle_endtoend_path.restype = ctypes.c_int64
+    lib.oracle_endtoend_path.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    n = lib.oracle_endtoend_path(q.ctypes.data if q.size else None, q.size,
+                                 r.ctypes.data if r.size else None, r.size, M.ctypes.data,
+                                 M.shape[0], int(gap_open), int(gap_extend), int(mode), int(re_),
+                                 int(s), ops.ctypes.data, cap, ctypes.byref(rs))
+    if n < 0:
+        raise ValueError("oracle_endtoend_path failed (%d)" % n)
+    return int(rs.value), [(int(v >> 4), _OPS[int(v & 15)]) for v in ops[:n]]
+

@@ -331,3 +331,104 @@ int oracle_endtoend(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
     free(best); free(W); free(G);
     return 0;
 }
+
+/*
+ * Path of an end-to-end alignment (mode 0 global, 1 semi-global as in
+ * oracle_endtoend), from its end (ref_end, m - 1) back to its start: the
+ * chain's elements are the aligned pairs plus a virtual start pair -- (-1, -1)
+ * in mode 0, any (v, -1) with v >= -1 in mode 1 (the free reference prefix
+ * r[0..v]) -- of value 0.  Walking back from the end, each predecessor is the
+ * largest (ref index, then query index) element, virtual ones included, on an
+ * optimal chain; between two elements (and after the last pair) the skipped
+ * reference residues (D) are written before the skipped query residues (I).
+ * Runs go to ops[] as (len << 4 | op), op 0 M, 1 I, 2 D, in forward order;
+ * *ref_start receives v + 1 for the virtual start (0 in mode 0).  Returns the
+ * number of runs, -1 on bad arguments / allocation failure / too small a cap,
+ * -2 if `score` is not the mode's optimum at that end.
+ */
+int64_t oracle_endtoend_path(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
+                             const int32_t *Mx, int32_t alpha, int64_t go, int64_t ge,
+                             int32_t mode, int64_t ref_end, int64_t score, uint32_t *ops,
+                             int64_t cap, int64_t *ref_start)
+{
+    if (m < 0 || n < 0 || alpha <= 0 || (mode != 0 && mode != 1)) return -1;
+    if (ref_end < -1 || ref_end >= n || (mode == 0 && ref_end != n - 1)) return -1;
+    if (ge > go) ge = go;
+    const int64_t NEG = INT64_MIN / 4;
+    const int64_t R = n + 1, C = m + 1;
+    int64_t *best = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
+    int64_t *W = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
+    int64_t *G = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
+    char *rev = (char *)malloc((size_t)(n + m + 2));
+    if (!best || !W || !G || !rev) { free(best); free(W); free(G); free(rev); return -1; }
+#define IX(a, b) (((a) + 1) * C + ((b) + 1))
+    for (int64_t a = -1; a < n; ++a) {
+        for (int64_t b = -1; b < m; ++b) {
+            const int64_t lead = mode == 0 ? -gcost(a + 1, go, ge) - gcost(b + 1, go, ge)
+                                           : -gcost(b + 1, go, ge);
+            if (a < 0 || b < 0) {
+                W[IX(a, b)] = NEG;
+                G[IX(a, b)] = NEG;
+                best[IX(a, b)] = lead;
+                continue;
+            }
+            W[IX(a, b)] = (int64_t)Mx[(int)q[b] * alpha + (int)r[a]] + best[IX(a - 1, b - 1)];
+            int64_t g = NEG;
+            for (int64_t y = 0; y <= b; ++y) g = max2(g, W[IX(a, y)] - gcost(b - y, go, ge));
+            G[IX(a, b)] = g;
+            int64_t v = lead;
+            for (int64_t x = 0; x <= a; ++x)
+                if (G[IX(x, b)] > NEG) v = max2(v, G[IX(x, b)] - gcost(a - x, go, ge));
+            best[IX(a, b)] = v;
+        }
+    }
+    int64_t rc = 0, nrev = 0;
+    if (best[IX(ref_end, m - 1)] != score) rc = -2;
+    /* walk: the current position (px, py) lies just before the element found
+     * last (the end, then each aligned pair); target = best(px, py) */
+    int64_t px = ref_end, py = m - 1, target = score, vstart = -1;
+    while (rc == 0) {
+        int64_t fx = NEG, fy = NEG;
+        /* real pairs, largest x first, then largest y */
+        for (int64_t x = px; x >= 0 && fx == NEG; --x)
+            for (int64_t y = py; y >= 0; --y)
+                if (W[IX(x, y)] > NEG &&
+                    W[IX(x, y)] - gcost(px - x, go, ge) - gcost(py - y, go, ge) == target) {
+                    fx = x; fy = y;
+                    break;
+                }
+        /* a virtual start element beats a real pair only with a larger x */
+        int64_t vx = NEG;
+        if (mode == 0) {
+            if (-gcost(px + 1, go, ge) - gcost(py + 1, go, ge) == target) vx = -1;
+        } else {
+            for (int64_t v = px; v >= -1 && vx == NEG; --v)
+                if (-gcost(px - v, go, ge) - gcost(py + 1, go, ge) == target) vx = v;
+        }
+        if (vx != NEG && (fx == NEG || vx > fx)) {
+            for (int64_t k = 0; k < py - (-1); ++k) rev[nrev++] = 'I';
+            for (int64_t k = 0; k < px - vx; ++k) rev[nrev++] = 'D';
+            vstart = vx;
+            break;
+        }
+        if (fx == NEG) { rc = -2; break; }
+        for (int64_t k = 0; k < py - fy; ++k) rev[nrev++] = 'I';
+        for (int64_t k = 0; k < px - fx; ++k) rev[nrev++] = 'D';
+        rev[nrev++] = 'M';
+        target = W[IX(fx, fy)] - (int64_t)Mx[(int)q[fy] * alpha + (int)r[fx]];
+        px = fx - 1;
+        py = fy - 1;
+    }
+#undef IX
+    int64_t cnt = 0;
+    for (int64_t k = nrev - 1; rc == 0 && k >= 0;) {
+        const char c = rev[k];
+        int64_t len = 0;
+        while (k >= 0 && rev[k] == c) { ++len; --k; }
+        if (cnt >= cap) { rc = -1; break; }
+        ops[cnt++] = (uint32_t)(len << 4) | (c == 'M' ? 0u : (c == 'I' ? 1u : 2u));
+    }
+    if (ref_start) *ref_start = vstart + 1;
+    free(best); free(W); free(G); free(rev);
+    return rc ? rc : cnt;
+}

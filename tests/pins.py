@@ -186,3 +186,55 @@ def brute_force_endtoend(q, r, M, go: int, ge: int, mode: int):
     score = max(best_at.values())
     end = min(a for a, v in best_at.items() if v == score)
     return score, m - 1, end
+
+
+def brute_force_endtoend_path(q, r, M, go: int, ge: int, mode: int):
+    """(ref_start, runs) of the reported end-to-end alignment by enumeration:
+    every chain of pairs with its virtual start element ((-1, -1) globally,
+    any (v, -1) semi-globally) that reaches the optimum at the reported end;
+    of those, the one whose elements read from the end backwards are
+    lexicographically largest; rendered with D before I between elements and
+    after the last pair.  Tiny inputs only."""
+    m, n = len(q), len(r)
+    ge = min(ge, go)
+    score, _, a_end = brute_force_endtoend(q, r, M, go, ge, mode)
+    chains = [[]]
+
+    def grow(chain):
+        i0, j0 = chain[-1] if chain else (-1, -1)
+        for i in range(i0 + 1, a_end + 1):
+            for j in range(j0 + 1, m):
+                c = chain + [(i, j)]
+                chains.append(c)
+                grow(c)
+
+    grow([])
+    best = None
+    for c in chains:
+        starts = [-1] if mode == 0 else list(range(-1, (c[0][0] if c else a_end + 1)))
+        for v in starts:
+            elems = [(v, -1)] + c
+            s = sum(int(M[q[j]][r[i]]) for i, j in c)
+            for (i, j), (i2, j2) in zip(elems, elems[1:]):
+                s -= gap_cost(i2 - i - 1, go, ge) + gap_cost(j2 - j - 1, go, ge)
+            li, lj = elems[-1]
+            s -= gap_cost(a_end - li, go, ge) + gap_cost(m - 1 - lj, go, ge)
+            if mode == 0 and not c:
+                pass        # both runs from the virtual pair: counted just above
+            if s == score:
+                key = list(reversed(elems))
+                if best is None or key > best:
+                    best = key
+    elems = list(reversed(best))
+    ops = []
+    for (i, j), (i2, j2) in zip(elems, elems[1:]):
+        ops += ["D"] * (i2 - i - 1) + ["I"] * (j2 - j - 1) + ["M"]
+    li, lj = elems[-1]
+    ops += ["D"] * (a_end - li) + ["I"] * (m - 1 - lj)
+    runs = []
+    for o in ops:
+        if runs and runs[-1][1] == o:
+            runs[-1] = (runs[-1][0] + 1, o)
+        else:
+            runs.append((1, o))
+    return elems[0][0] + 1, runs

@@ -540,3 +540,61 @@ def test_endtoend_invariants():
         assert oracle.endtoend(q[::-1], r[::-1], M, go, ge, 0)[0] == g
         assert oracle.endtoend(r, q, np.ascontiguousarray(np.asarray(M).T), go, ge, 0)[0] == g
 
+
+def test_endtoend_path_brute_force_random():
+    rng = np.random.default_rng(44)
+    n_cases = 0
+    for _ in range(400):
+        alpha = int(rng.integers(2, 4))
+        m, n = int(rng.integers(0, 5)), int(rng.integers(0, 6))
+        q = rng.integers(0, alpha, size=m).tolist()
+        r = rng.integers(0, alpha, size=n).tolist()
+        M = rng.integers(-4, 3, size=(alpha, alpha)).astype(np.int32)
+        go = int(rng.integers(0, 4))
+        ge = int(rng.integers(0, go + 3))
+        for mode in (0, 1):
+            want = pins.brute_force_endtoend_path(q, r, M, go, ge, mode)
+            got = oracle.endtoend_path(q, r, M, go, ge, mode)
+            assert got == want, (q, r, M.tolist(), go, ge, mode, got, want)
+            s = oracle.endtoend(q, r, M, go, ge, mode)[0]
+            # the runs add up to the score from the start (205 of these 800
+            # cases have another optimal path that the smallest-element rule
+            # would pick, so the tie rule is exercised)
+            assert _endtoend_runs_score(q, r, M, go, ge, (0, got[0]), got[1]) == s
+            n_cases += 1
+    assert n_cases == 800
+
+
+def _endtoend_runs_score(q, r, M, go, ge, start, runs):
+    ge = min(ge, go)
+    j, i = start
+    total = 0
+    for L, op in runs:
+        if op == "M":
+            for _ in range(L):
+                total += int(M[q[j]][r[i]])
+                i += 1
+                j += 1
+        else:
+            total -= go + (L - 1) * ge
+            if op == "I":
+                j += L
+            else:
+                i += L
+    assert j == len(q)
+    return total
+
+
+def test_endtoend_path_worked_examples():
+    M = np.full((4, 4), -2, dtype=np.int32)
+    np.fill_diagonal(M, 3)
+    # ACGT vs AGT globally: the C skipped
+    assert oracle.endtoend_path([0, 1, 2, 3], [0, 2, 3], M, 2, 1, 0) == \
+        (0, [(1, "M"), (1, "I"), (2, "M")])
+    # GT placed inside ACGTA
+    assert oracle.endtoend_path([2, 3], [0, 1, 2, 3, 0], M, 2, 1, 1) == (2, [(2, "M")])
+    # empty sides
+    assert oracle.endtoend_path([], [0, 1], M, 2, 1, 0) == (0, [(2, "D")])
+    assert oracle.endtoend_path([1], [], M, 2, 1, 1) == (0, [(1, "I")])
+    assert oracle.endtoend_path([1, 2], [0, 3], M, 9, 1, 0) == (0, [(2, "M")])
+
