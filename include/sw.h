@@ -244,6 +244,37 @@ enum { SW_MODE_GLOBAL = 0, SW_MODE_SEMIGLOBAL = 1 };
 int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, int32_t mode,
                           sw_result *out);
 
+/* ---------------------------------------------------------------------------
+ * sw_align_batch_global_cigar -- paths of the end-to-end alignments a
+ * sw_align_batch_global call found (same batch, scoring and mode; ends: its
+ * n_pairs results).
+ *
+ * Pair k's alignment runs from a virtual start pair -- (-1, -1) for
+ * SW_MODE_GLOBAL, (v, -1) for SW_MODE_SEMIGLOBAL, r[0..v] being the free
+ * reference prefix -- to its end cell; walking back from the end, each
+ * predecessor is the largest (ref index, then query index) element (aligned
+ * pair or virtual start) on an optimal chain, and between two elements, as
+ * after the last pair, the D run comes before the I run.  Runs as in
+ * sw_align_batch_cigar (packed: cigar[cigar_off[k] .. cigar_off[k+1]),
+ * cigar_off[0] = 0; SW_EINVAL with cigar_off filled and cigar untouched when
+ * the total exceeds cigar_cap).  Global paths consume both sequences whole;
+ * semi-global paths consume the whole query and r[ref_start[k] ..
+ * ref_end]: ref_start[k] = v + 1 (0 globally).  A pair needs at most
+ * (ref_end + 1) + m + 2 runs.
+ *
+ * Computed by the path kernel of sw_align_batch_cigar with the boundaries of
+ * sw_align_batch_global over r[0..ref_end] x q.  SW_EINVAL: a bad mode, NULL
+ * arrays, ids or offsets out of range, an end that is not (m - 1, n - 1)
+ * (global) or (m - 1, -1 .. n - 1) (semi-global), a score that is not the
+ * optimum there, a residue not below alphabet_size, or too small a
+ * cigar_cap; SW_EOVERFLOW and SW_ENOMEM as for sw_align_batch_cigar.  ends,
+ * ref_start, cigar and cigar_off are host arrays owned by the caller.
+ * Synchronous; serialised with the other calls of this group.
+ * ------------------------------------------------------------------------- */
+int sw_align_batch_global_cigar(const sw_batch *b, const sw_scoring *sc, int32_t mode,
+                                const sw_result *ends, int32_t *ref_start, uint32_t *cigar,
+                                int64_t cigar_cap, int64_t *cigar_off);
+
 /* Options and statistics for the extended batch call (tests, benchmarks,
  * the autotuner).  Zero-initialise and set what you need. */
 enum { SW_PAIRING_AUTO = 0, SW_PAIRING_ALIGNMENTS = 1, SW_PAIRING_ROWS = 2 };

@@ -29,7 +29,7 @@ EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align"
             "sw_align_batch", "sw_align_batch_ex", "sw_server_create", "sw_server_submit",
             "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay",
             "sw_autotune", "sw_tune_set", "sw_tune_get", "sw_align_batch_starts",
-            "sw_align_batch_cigar", "sw_align_batch_global"]
+            "sw_align_batch_cigar", "sw_align_batch_global", "sw_align_batch_global_cigar"]
 
 
 class NativeLibraryError(RuntimeError):
@@ -163,6 +163,9 @@ def load():
                                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     lib.sw_align_batch_global.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                           ctypes.c_int32, ctypes.c_void_p]
+    lib.sw_align_batch_global_cigar.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
+                                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     lib.sw_autotune.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), ctypes.c_int64,
                                 ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_int32)]
@@ -341,8 +344,8 @@ def sw_align_batch_cigar(query_res, query_off, ref_res, ref_off, pair_ref, matri
     ``cigar_cap`` overrides the run capacity passed (default: the bound the
     library documents, which always suffices)."""
     lib = load()
-    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, None
-                                  if pair_query is None else pair_query, SW_PREC_AUTO)
+    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
+                                  SW_PREC_AUTO)
     sc, M = make_scoring(matrix, gap_open, gap_extend)
     ends = np.ascontiguousarray(np.asarray(results, dtype=np.int32))
     qs = np.ascontiguousarray(np.asarray(query_start, dtype=np.int32))
@@ -382,6 +385,32 @@ def sw_align_batch_global(query_res, query_off, ref_res, ref_off, pair_ref, matr
     _check(lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), int(mode),
                                      out.ctypes.data))
     return out[:npairs]
+
+
+def sw_align_batch_global_cigar(query_res, query_off, ref_res, ref_off, pair_ref, matrix,
+                                gap_open: int, gap_extend: int, results,
+                                mode: int = SW_MODE_GLOBAL, pair_query=None, cigar_cap=None):
+    """Paths of the alignments ``sw_align_batch_global`` returned (``results``,
+    same batch, scoring and mode).  Returns (ref_start, runs, offsets): pair
+    k's runs are runs[offsets[k]:offsets[k + 1]] from its start (query 0,
+    reference ref_start[k]) to its end cell."""
+    lib = load()
+    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
+                                  SW_PREC_AUTO)
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    ends = np.ascontiguousarray(np.asarray(results, dtype=np.int32))
+    if ends.shape != (npairs, 4):
+        raise ValueError("results must be the (n_pairs, 4) array of sw_align_batch_global")
+    # capacity: the library's bound, (ref_end + 1) + m + 2 runs per pair
+    cap = int((ends[:, 2].astype(np.int64) + 1 + ends[:, 1].astype(np.int64) + 1 + 2).sum()) \
+        if cigar_cap is None else int(cigar_cap)
+    runs = np.empty(max(cap, 1), dtype=np.uint32)
+    off = np.empty(npairs + 1, dtype=np.int64)
+    rs = np.empty(max(npairs, 1), dtype=np.int32)
+    _check(lib.sw_align_batch_global_cigar(ctypes.byref(b), ctypes.byref(sc), int(mode),
+                                           ends.ctypes.data if npairs else None, rs.ctypes.data,
+                                           runs.ctypes.data, cap, off.ctypes.data))
+    return rs[:npairs], runs[:off[-1]], off
 
 
 def decode_cigar(runs, offsets, k: int) -> list:

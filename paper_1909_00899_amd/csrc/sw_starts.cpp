@@ -60,6 +60,7 @@ struct StartsWork {
   DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off;
   HostBuf tr_host, tr_hcounts;   // pinned: the pair table, the run counts
   DevBuf tr_res;                 // end-to-end results
+  DevBuf tr_rstart;              // end-to-end paths: reference starts
   HostBuf tr_hres;
   // device-memory rectangles: the largest group, the second, the rest each on
   // a stream of their own, so the long poles of the largest rectangles (one
@@ -372,10 +373,14 @@ int64_t run_bound(int64_t A, int64_t B) {
 
 }  // namespace
 
-extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
-                                    const sw_result *ends, const int32_t *query_start,
-                                    const int32_t *ref_start, uint32_t *cigar,
-                                    int64_t cigar_cap, int64_t *cigar_off) {
+// Paths of a batch: mode 0 the local alignments between start and end cells
+// (sw_align_batch_cigar), mode 1 / 2 whole global / semi-global alignments
+// from their end cells (sw_align_batch_global_cigar; ref_start_out receives
+// the semi-global reference starts).
+namespace {
+int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_result *ends,
+               const int32_t *query_start, const int32_t *ref_start, int32_t *ref_start_out,
+               uint32_t *cigar, int64_t cigar_cap, int64_t *cigar_off) {
   int rc = check_batch_args(b);
   if (rc) return rc;
   Scoring S;
@@ -384,7 +389,10 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
   if (!cigar_off) { set_error("cigar_off is NULL"); return SW_EINVAL; }
   cigar_off[0] = 0;
   if (np == 0) return SW_OK;
-  if (!ends || !query_start || !ref_start) { set_error("ends or starts are NULL"); return SW_EINVAL; }
+  if (!ends || (mode == 0 && (!query_start || !ref_start)) || (mode != 0 && !ref_start_out)) {
+    set_error("ends, starts or ref_start is NULL");
+    return SW_EINVAL;
+  }
   if (cigar_cap < 0 || (cigar_cap > 0 && !cigar)) { set_error("cigar is NULL or its capacity negative"); return SW_EINVAL; }
   if ((rc = ensure_init())) return rc;
   std::lock_guard<std::mutex> g(g_starts.mu);
@@ -403,17 +411,46 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
   int nl = 0;
   std::vector<swk::TracePair> glob;
   int64_t region = 0;
+  // end-to-end alignments with an empty side have their runs made here
+  std::vector<std::pair<int, std::vector<uint32_t>>> host_runs;
+  auto gap = [&](int64_t L) -> int64_t { return L <= 0 ? 0 : S.go + (L - 1) * (int64_t)S.ge; };
   for (int k = 0; k < np; ++k) {
     const sw_result &e = ends[k];
-    if (e.score <= 0) continue;
-    const int qs = query_start[k], rs = ref_start[k];
     const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
     const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
-    if (qs < 0 || qs > e.query_end || e.query_end >= m || rs < 0 || rs > e.ref_end ||
-        e.ref_end >= n) {
-      set_error("pair %d: start (%d, %d) and end (%d, %d) are not a rectangle of its %lld x %lld "
-                "sequences", k, qs, rs, e.query_end, e.ref_end, (long long)m, (long long)n);
-      return SW_EINVAL;
+    int qs = 0, rs = 0;
+    if (mode == 0) {
+      if (e.score <= 0) continue;
+      qs = query_start[k];
+      rs = ref_start[k];
+      if (qs < 0 || qs > e.query_end || e.query_end >= m || rs < 0 || rs > e.ref_end ||
+          e.ref_end >= n) {
+        set_error("pair %d: start (%d, %d) and end (%d, %d) are not a rectangle of its %lld x "
+                  "%lld sequences", k, qs, rs, e.query_end, e.ref_end, (long long)m, (long long)n);
+        return SW_EINVAL;
+      }
+    } else {
+      ref_start_out[k] = 0;
+      if (e.query_end != m - 1 || e.ref_end < -1 || e.ref_end >= n ||
+          (mode == 1 && e.ref_end != n - 1)) {
+        set_error("pair %d: end (%d, %d) is not the end cell of a %s alignment of its %lld x %lld "
+                  "sequences", k, e.query_end, e.ref_end, mode == 1 ? "global" : "semi-global",
+                  (long long)m, (long long)n);
+        return SW_EINVAL;
+      }
+      if (m == 0 || e.ref_end < 0) {        // nothing to pair: one or two gap runs
+        const int64_t rows = mode == 1 ? n : 0;
+        if (e.score != -gap(rows) - gap(m)) {
+          set_error("pair %d: score %d is not this alignment's", k, e.score);
+          return SW_EINVAL;
+        }
+        std::vector<uint32_t> v;
+        if (rows) v.push_back((uint32_t)rows << 4 | swk::kCigarD);
+        if (m) v.push_back((uint32_t)m << 4 | swk::kCigarI);
+        ref_start_out[k] = mode == 2 ? e.ref_end + 1 : 0;
+        host_runs.emplace_back(k, std::move(v));
+        continue;
+      }
     }
     const int64_t A = e.ref_end - rs + 1, Bq = e.query_end - qs + 1;
     // every reachable value stays above -2^28 and every row term below 2^30,
@@ -432,7 +469,7 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     tp.A = (int32_t)A;
     tp.B = (int32_t)Bq;
     tp.score = e.score;
-    tp.cap = (int32_t)run_bound(A, Bq);
+    tp.cap = (int32_t)(mode == 0 ? run_bound(A, Bq) : A + Bq + 2);
     tp.id = k;
     tp.pad = 0;
     region += tp.cap;
@@ -489,7 +526,8 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
         (rc = W.tr_mat.ensure((size_t)S.alpha * S.alpha * sizeof(int32_t))) ||
         (rc = W.tr_runs.ensure((size_t)std::max<int64_t>(region, 1) * sizeof(uint32_t))) ||
         (rc = W.tr_nruns.ensure((size_t)np * sizeof(int32_t))) ||
-        (rc = W.tr_off.ensure((size_t)(np + 1) * sizeof(int64_t))))
+        (rc = W.tr_off.ensure((size_t)(np + 1) * sizeof(int64_t))) ||
+        (rc = W.tr_rstart.ensure((size_t)np * sizeof(int32_t))))
       return rc;
     for (int k = 0; k < NS && k < (int)groups.size(); ++k) {
       if ((rc = W.tr_bits[k].ensure((size_t)std::max<int64_t>(bits_words[k], 1) * sizeof(uint16_t))) ||
@@ -513,6 +551,8 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     ta.ge = S.ge;
     ta.cigar = W.tr_runs.as<uint32_t>();
     ta.n_runs = W.tr_nruns.as<int32_t>();
+    ta.mode = mode;
+    ta.ref_start = W.tr_rstart.as<int32_t>();
     ta.pairs = dp;
     ta.n = nl;
     ta.slot_words = 0;
@@ -541,6 +581,12 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
     int32_t *dev_counts = W.tr_hcounts.as<int32_t>();
     HIPCHK(hipMemcpyAsync(dev_counts, W.tr_nruns.p, (size_t)np * sizeof(int32_t),
                           hipMemcpyDeviceToHost, W.st));
+    std::vector<int32_t> dev_rstart;
+    if (mode != 0) {
+      dev_rstart.resize(np);
+      HIPCHK(hipMemcpyAsync(dev_rstart.data(), W.tr_rstart.p, (size_t)np * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, W.st));
+    }
     HIPCHK(hipStreamSynchronize(W.st));
     for (int t = 0; t < nt; ++t) {
       const swk::TracePair &P = htab[t];
@@ -550,9 +596,13 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
         return SW_EINVAL;
       }
       if (c == swk::kTraceInconsistent) {
-        set_error("pair %d: no alignment of score %d runs from its start (%d, %d) to its end "
-                  "(%d, %d)", P.id, P.score, query_start[P.id], ref_start[P.id],
-                  ends[P.id].query_end, ends[P.id].ref_end);
+        if (mode == 0)
+          set_error("pair %d: no alignment of score %d runs from its start (%d, %d) to its end "
+                    "(%d, %d)", P.id, P.score, query_start[P.id], ref_start[P.id],
+                    ends[P.id].query_end, ends[P.id].ref_end);
+        else
+          set_error("pair %d: score %d is not the optimum at the end cell (%d, %d)", P.id,
+                    P.score, ends[P.id].query_end, ends[P.id].ref_end);
         return SW_EINVAL;
       }
       if (c < 1 || c > P.cap) {
@@ -560,8 +610,10 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
         return SW_EDEVICE;
       }
       counts[P.id] = c;
+      if (mode != 0) ref_start_out[P.id] = dev_rstart[P.id];
     }
   }
+  for (const auto &hr : host_runs) counts[hr.first] = (int32_t)hr.second.size();
   for (int k = 0; k < np; ++k) cigar_off[k + 1] = cigar_off[k] + counts[k];
   if (cigar_off[np] > cigar_cap) {
     set_error("the paths need %lld runs, cigar holds %lld", (long long)cigar_off[np],
@@ -579,7 +631,31 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
                           hipMemcpyDeviceToHost, W.st));
     HIPCHK(hipStreamSynchronize(W.st));
   }
+  for (const auto &hr : host_runs)
+    std::copy(hr.second.begin(), hr.second.end(), cigar + cigar_off[hr.first]);
   return SW_OK;
+}
+}  // namespace
+
+extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
+                                    const sw_result *ends, const int32_t *query_start,
+                                    const int32_t *ref_start, uint32_t *cigar,
+                                    int64_t cigar_cap, int64_t *cigar_off) {
+  return paths_impl(b, sc, 0, ends, query_start, ref_start, nullptr, cigar, cigar_cap,
+                    cigar_off);
+}
+
+extern "C" int sw_align_batch_global_cigar(const sw_batch *b, const sw_scoring *sc, int32_t mode,
+                                           const sw_result *ends, int32_t *ref_start,
+                                           uint32_t *cigar, int64_t cigar_cap,
+                                           int64_t *cigar_off) {
+  if (mode != SW_MODE_GLOBAL && mode != SW_MODE_SEMIGLOBAL) {
+    set_error("bad mode %d", mode);
+    if (cigar_off) cigar_off[0] = 0;
+    return SW_EINVAL;
+  }
+  return paths_impl(b, sc, mode == SW_MODE_GLOBAL ? 1 : 2, ends, nullptr, nullptr, ref_start,
+                    cigar, cigar_cap, cigar_off);
 }
 
 

@@ -39,6 +39,8 @@ struct TraceArgs {
   int carry_rows;
   uint32_t *cigar;         // device
   int32_t *n_runs;         // device, indexed by TracePair::id
+  int mode;                // 0 local rectangle, 1 global, 2 semi-global
+  int32_t *ref_start;      // modes 1, 2: device, indexed by TracePair::id
 };
 
 // LDS bytes of a workgroup (the matrix sized for the alphabet); with

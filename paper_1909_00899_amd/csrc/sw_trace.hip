@@ -75,8 +75,12 @@ __device__ __forceinline__ int readlane(int x, int l) { return __builtin_amdgcn_
 // LDS words of the staged matrix: alpha^2, rounded up to 16 bytes
 __host__ __device__ constexpr int mat_words(int alpha) { return (alpha * alpha + 3) / 4 * 4; }
 
-// One pair at C query columns per lane (a tile of 64 C columns).
-template <bool LB, int C>
+// One pair at C query columns per lane (a tile of 64 C columns).  MODE 0:
+// the rectangle between a local alignment's start and end pair, anchored at
+// the start pair; MODE 1 / 2: a whole global / semi-global alignment (the
+// boundaries of endtoend_kernel), walked back from its end cell to the
+// virtual start pair.
+template <bool LB, int C, int MODE>
 __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P, const int *smat,
                                           uint16_t *lbits, int *lcarry, uint16_t *lwin) {
   constexpr int TC = 64 * C;
@@ -102,11 +106,13 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     int Vp[C], Gp[C], Fp[C], wj[C], ej[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      Vp[c] = Gp[c] = Fp[c] = kNeg;
+      // row -1: nothing (MODE 0), or the gap run of the first j + 1 query residues
+      Vp[c] = Gp[c] = MODE == 0 ? kNeg : -(go + (jc0 + c) * ge);
+      Fp[c] = kNeg;
       wj[c] = (jc0 + c) * ge;              // scan term offset of column j
       ej[c] = go + (jc0 + c - 1) * ge;     // Eg(., j) = prefix max - go - (j - 1) ge
     }
-    int cv_prev = kNeg;                      // V(i-1, base-1)
+    int cv_prev = MODE == 0 ? kNeg : base == 0 ? 0 : -(go + (base - 1) * ge);   // V(i-1, base-1)
     int rreg = 0, crv = kNeg, crm = kNeg, crp = kNeg;
     for (int i = 0; i < A; ++i) {
       if ((i & 63) == 0) {                   // 64 rows of residues (and carries) at a time
@@ -120,9 +126,12 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
         }
       }
       const int rc = min(readlane(rreg, i & 63), alpha - 1);
-      const int cv_in = t ? readlane(crv, i & 63) : kNeg;   // V(i, base-1)
-      const int cm_in = t ? readlane(crm, i & 63) : kNeg;   // M(i, base-1)
-      const int cp_in = t ? readlane(crp, i & 63) : kNeg;   // max_{y<base} M(i, y) + y ge
+      // column -1 (tile 0): V(i, -1), M(i, -1) and its scan term: nothing in
+      // MODE 0; the reference gap run from the virtual start in MODE 1; a
+      // virtual start pair (free reference prefix) in MODE 2
+      const int cv_in = t ? readlane(crv, i & 63) : MODE == 0 ? kNeg : MODE == 1 ? -(go + i * ge) : 0;
+      const int cm_in = t ? readlane(crm, i & 63) : MODE == 2 ? 0 : kNeg;
+      const int cp_in = t ? readlane(crp, i & 63) : MODE == 2 ? -ge : kNeg;
       int Mv[C];
       // no clamps below: every cell off row 0 and column 0 is reachable
       // (gaps from the start), so unreachable values only arise next to
@@ -130,7 +139,7 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
       const int d0 = dpp_wave_shr1(cv_prev, Vp[C - 1]);
 #pragma unroll
       for (int c = 0; c < C; ++c) Mv[c] = smat[qb[c] + rc] + (c ? Vp[c - 1] : d0);
-      if (i == 0 && jc0 == 0) Mv[0] = smat[qb[0] + rc];      // the start pair
+      if (MODE == 0 && i == 0 && jc0 == 0) Mv[0] = smat[qb[0] + rc];   // the start pair
       int w[C], lp[C];
 #pragma unroll
       for (int c = 0; c < C; ++c) w[c] = Mv[c] + wj[c];
@@ -164,11 +173,12 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
       }
       cv_prev = cv_in;
       if (t == T - 1 && i == A - 1) {
+        // the end pair's M (MODE 0) or the end cell's V reaches the score
         const int jb = B - 1 - jc0;
-        int mend = Mv[0];
+        int mend = MODE == 0 ? Mv[0] : Vp[0];
 #pragma unroll
         for (int c = 1; c < C; ++c)
-          if (jb == c) mend = Mv[c];
+          if (jb == c) mend = MODE == 0 ? Mv[c] : Vp[c];
         ok = __ballot(jb >= 0 && jb < C && mend == P.score) != 0;
       }
     }
@@ -210,7 +220,67 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     }
     return (int)(wd >> (4 * (j % C))) & 15;
   };
-  if (!fail) {
+  int vstart = -1;                         // MODE 2: row of the virtual start pair
+  if (!fail && MODE != 0) {
+    // from the end cell (state V); pairs are counted into M runs, the gaps
+    // between two elements (the end, pairs, the virtual start) into one D
+    // and one I run; reaching row -1 or column -1 ends the walk
+    int i = A - 1, j = B - 1, mrun = 0, guard = A + B + 2;
+    for (;;) {
+      if (--guard < 0) { fail = true; break; }
+      int nd = 0, ni = 0;
+      bool start = false;
+      if (i < 0 || j < 0) {                  // on the boundary: to the virtual start
+        if (i >= 0 && MODE == 2) vstart = i;          // V(i, -1) = 0: a free prefix
+        else if (i >= 0) nd = i + 1;                  // MODE 1: the reference gap run
+        else ni = j + 1;                              // row -1: the query gap run
+        start = true;
+      } else {
+        int nib = nib_at(i, j);
+        if (!(nib & 1)) {                    // a reference gap ends at (i, j)
+          for (;;) {
+            ++nd;
+            const bool open = nib & 2;
+            if (--i < 0) {                   // G(-1, j): the query gap run of row -1
+              if (!open) fail = true;
+              ni = j + 1;
+              start = true;
+              break;
+            }
+            nib = nib_at(i, j);
+            if (open) break;
+          }
+        }
+        if (!fail && !start && !(nib & 4)) { // a query gap ends at (i, j)
+          for (;;) {
+            ++ni;
+            const bool open = nib & 8;
+            if (--j < 0) {                   // M(i, -1): a virtual start pair
+              if (!open || MODE != 2) fail = true;
+              vstart = i;
+              start = true;
+              break;
+            }
+            nib = nib_at(i, j);
+            if (open) break;
+          }
+        }
+      }
+      if (fail) break;
+      if (nd | ni) {
+        if (mrun) emit((uint32_t)mrun << 4 | kCigarM);
+        if (ni) emit((uint32_t)ni << 4 | kCigarI);
+        if (nd) emit((uint32_t)nd << 4 | kCigarD);
+        mrun = 0;
+      }
+      if (start) break;
+      ++mrun;                                // the pair (i, j)
+      --i;
+      --j;
+    }
+    if (!fail && mrun) emit((uint32_t)mrun << 4 | kCigarM);
+  }
+  if (!fail && MODE == 0) {
     int ra = A - 1, qb_ = B - 1, mrun = 1, guard = A + B + 2;
     while ((ra | qb_) != 0) {
       if (ra == 0 || qb_ == 0 || --guard < 0) { fail = true; break; }
@@ -248,7 +318,25 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     }
     if (!fail) emit((uint32_t)mrun << 4 | kCigarM);
   }
-  if (L == 0) a.n_runs[P.id] = bad ? kTraceBadResidue : fail ? kTraceInconsistent : nrun;
+  if (L == 0) {
+    a.n_runs[P.id] = bad ? kTraceBadResidue : fail ? kTraceInconsistent : nrun;
+    if (MODE != 0) a.ref_start[P.id] = MODE == 2 ? vstart + 1 : 0;
+  }
+}
+
+template <bool LB, int MODE>
+__device__ __forceinline__ void trace_mode(const TraceArgs &a, const TracePair &P, const int *smat,
+                                           uint16_t *lbits, int *lcarry, uint16_t *lwin) {
+  if (!LB) {
+    trace_one<LB, 4, MODE>(a, P, smat, lbits, lcarry, lwin);
+  } else {
+    switch (P.pad) {
+      case 1: trace_one<LB, 1, MODE>(a, P, smat, lbits, lcarry, lwin); break;
+      case 2: trace_one<LB, 2, MODE>(a, P, smat, lbits, lcarry, lwin); break;
+      case 3: trace_one<LB, 3, MODE>(a, P, smat, lbits, lcarry, lwin); break;
+      default: trace_one<LB, 4, MODE>(a, P, smat, lbits, lcarry, lwin); break;
+    }
+  }
 }
 
 // LDS variant: C per pair from TracePair::pad (the fewest columns per lane
@@ -266,16 +354,9 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   __syncthreads();
   for (int p = blockIdx.x; p < a.n; p += gridDim.x) {
     const TracePair P = a.pairs[p];
-    if (!LB) {
-      trace_one<LB, 4>(a, P, smat, lbits, lcarry, lwin);
-    } else {
-      switch (P.pad) {
-        case 1: trace_one<LB, 1>(a, P, smat, lbits, lcarry, lwin); break;
-        case 2: trace_one<LB, 2>(a, P, smat, lbits, lcarry, lwin); break;
-        case 3: trace_one<LB, 3>(a, P, smat, lbits, lcarry, lwin); break;
-        default: trace_one<LB, 4>(a, P, smat, lbits, lcarry, lwin); break;
-      }
-    }
+    if (a.mode == 0) trace_mode<LB, 0>(a, P, smat, lbits, lcarry, lwin);
+    else if (a.mode == 1) trace_mode<LB, 1>(a, P, smat, lbits, lcarry, lwin);
+    else trace_mode<LB, 2>(a, P, smat, lbits, lcarry, lwin);
   }
 }
 

@@ -200,3 +200,18 @@ def test_global_rejects_bad_arguments(lib):
     b.n_pairs = 1                                   # arrays missing
     assert lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), 1,
                                      out.ctypes.data) == api.SW_EINVAL
+
+
+def test_global_cigar_rejects_bad_arguments(lib):
+    M = np.eye(4, dtype=np.int32)
+    sc, keep = _sc(M)
+    b = api.Batch()
+    off = np.full(3, 7, dtype=np.int64)
+    assert lib.sw_align_batch_global_cigar(None, ctypes.byref(sc), 0, None, None, None, 0,
+                                           off.ctypes.data) == api.SW_EINVAL
+    b.n_pairs = 0
+    assert lib.sw_align_batch_global_cigar(ctypes.byref(b), ctypes.byref(sc), 1, None, None,
+                                           None, 0, off.ctypes.data) == api.SW_OK
+    assert off[0] == 0
+    assert lib.sw_align_batch_global_cigar(ctypes.byref(b), ctypes.byref(sc), 4, None, None,
+                                           None, 0, off.ctypes.data) == api.SW_EINVAL

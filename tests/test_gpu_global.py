@@ -116,3 +116,93 @@ def test_device_resident_inputs_and_errors():
     assert e.value.code == api.SW_EINVAL
     again = _run(w, api.SW_MODE_SEMIGLOBAL)
     assert (again == host).all()
+
+
+def _paths(w, mode, **kw):
+    res = _run(w, mode)
+    rs, runs, off = api.sw_align_batch_global_cigar(w.query_res, w.query_off, w.ref_res,
+                                                    w.ref_off, w.pair_ref, w.matrix, w.gap_open,
+                                                    w.gap_extend, res, mode=mode,
+                                                    pair_query=w.pair_query, **kw)
+    return res, rs, runs, off
+
+
+def _seqs(w, k):
+    qi = 0 if w.pair_query is None else int(w.pair_query[k])
+    ri = int(w.pair_ref[k])
+    return (w.query_res[w.query_off[qi]:w.query_off[qi + 1]],
+            w.ref_res[w.ref_off[ri]:w.ref_off[ri + 1]])
+
+
+def _check_paths(w, mode, label, pairs=None):
+    res, rs, runs, off = _paths(w, mode)
+    for k in (range(w.n_pairs) if pairs is None else pairs):
+        q, r = _seqs(w, k)
+        want = oracle.endtoend_path(q, r, w.matrix, w.gap_open, w.gap_extend, mode,
+                                    end=tuple(int(x) for x in res[k, :3]))
+        got = (int(rs[k]), api.decode_cigar(runs, off, k))
+        assert got == want, "%s mode %d pair %d: got %s want %s" % (label, mode, k, got, want)
+    return res, rs, runs, off
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("alpha,go,ge", [(2, 2, 1), (4, 3, 1), (20, 11, 1), (3, 1, 0), (4, 2, 5)])
+def test_paths_small_pairs_equal_the_oracle(mode, alpha, go, ge):
+    # empty sides included (their runs are made on the host)
+    rng = np.random.default_rng(1000 + alpha + go + 7 * mode)
+    M = W.protein_matrix() if alpha == 20 else W.random_matrix(rng, alpha)
+    w = W.random_pairs(300, alpha, (0, 40), (0, 50), 1001 + alpha + mode, matrix=M,
+                       gap_open=go, gap_extend=ge)
+    _check_paths(w, mode, "small")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_paths_across_tiles_and_in_device_memory(mode):
+    # queries of 257-700 residues (two or three tiles; rows x tiles beyond the
+    # LDS budget, so the decision bits live in device memory) and one-tile
+    # queries with up to 300 rows
+    rng = np.random.default_rng(1010 + mode)
+    M = W.random_matrix(rng, 4)
+    w = W.random_pairs(12, 4, (257, 700), (1, 90), 1011 + mode, matrix=M, gap_open=3,
+                       gap_extend=1)
+    _check_paths(w, mode, "tiles")
+    w = W.random_pairs(12, 4, (20, 100), (170, 300), 1012 + mode, matrix=M, gap_open=3,
+                       gap_extend=1)
+    _check_paths(w, mode, "rows")
+
+
+def test_paths_dna_reads_in_windows():
+    # semi-global: each read placed inside its window; the path consumes the
+    # read and r[ref_start .. ref_end]
+    w = W.dna_pairs(n_pairs=400, seed=27)
+    res, rs, runs, off = _check_paths(w, api.SW_MODE_SEMIGLOBAL, "dna", pairs=range(0, 400, 40))
+    for k in range(w.n_pairs):
+        got = api.decode_cigar(runs, off, k)
+        assert sum(n for n, o in got if o in "MI") == 150
+        assert sum(n for n, o in got if o in "MD") == res[k, 2] - rs[k] + 1
+    _check_paths(w, api.SW_MODE_GLOBAL, "dna", pairs=range(0, 400, 100))
+
+
+def test_paths_errors():
+    w = W.random_pairs(50, 4, (1, 40), (1, 40), 1020)
+    res = _run(w, api.SW_MODE_GLOBAL)
+    args = (w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref, w.matrix, w.gap_open,
+            w.gap_extend)
+    bad = res.copy()
+    bad[3, 0] += 1                                 # not the optimum
+    with pytest.raises(api.SwError) as e:
+        api.sw_align_batch_global_cigar(*args, bad, mode=api.SW_MODE_GLOBAL,
+                                        pair_query=w.pair_query)
+    assert e.value.code == api.SW_EINVAL
+    bad = res.copy()
+    bad[3, 2] -= 1                                 # a global end must be (m - 1, n - 1)
+    with pytest.raises(api.SwError) as e:
+        api.sw_align_batch_global_cigar(*args, bad, mode=api.SW_MODE_GLOBAL,
+                                        pair_query=w.pair_query)
+    assert e.value.code == api.SW_EINVAL
+    rs, runs, off = api.sw_align_batch_global_cigar(*args, res, mode=api.SW_MODE_GLOBAL,
+                                                    pair_query=w.pair_query)
+    with pytest.raises(api.SwError) as e:
+        api.sw_align_batch_global_cigar(*args, res, mode=api.SW_MODE_GLOBAL,
+                                        pair_query=w.pair_query, cigar_cap=int(off[-1]) - 1)
+    assert e.value.code == api.SW_EINVAL
