@@ -304,6 +304,21 @@ def _endtoend_leg(api, d, pq, w, reps):
         ms = (time.perf_counter() - t) / reps * 1e3
         res[name] = {"ms_per_call": round(ms, 3), "gcups": round(cells / ms / 1e6, 1),
                      "median_score": int(np.median(r[:, 0]))}
+        # their paths, from the end cells just found
+        api.sw_align_batch_global_cigar(*d, w.matrix, w.gap_open, w.gap_extend, r, mode=mode,
+                                        pair_query=pq)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            rs, runs, off = api.sw_align_batch_global_cigar(*d, w.matrix, w.gap_open,
+                                                            w.gap_extend, r, mode=mode,
+                                                            pair_query=pq)
+        pms = (time.perf_counter() - t) / reps * 1e3
+        rows = r[:, 2].astype(np.int64) + 1
+        pcells = int((rows * (r[:, 1].astype(np.int64) + 1)).sum())
+        res[name]["paths"] = {"ms_per_call": round(pms, 3), "cells": pcells,
+                              "gcups": round(pcells / pms / 1e6, 1),
+                              "median_runs": int(np.median(np.diff(off)))}
     return res
 
 

@@ -474,12 +474,12 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     tp.pad = 0;
     region += tp.cap;
     const int64_t tiles = (Bq + swk::kTraceTileCols - 1) / swk::kTraceTileCols;
-    // columns per lane: the fewest that hold a one-tile query (LDS path only)
+    // columns per lane: the fewest that hold a one-tile query (4 beyond), so
+    // a one-tile query's slot of 64-lane rows is the same at any count
     tp.pad = (int32_t)std::min<int64_t>(4, (Bq + 63) / 64);
     if (A * tiles <= swk::kTraceLdsRowTiles) {
       htab[nl++] = tp;
     } else {
-      tp.pad = 4;
       glob.push_back(tp);
     }
   }

@@ -20,8 +20,7 @@ constexpr int kTraceBadResidue = -3;     // a residue code >= alphabet size in t
 // rres[r .. r + A); its runs are written backward from cigar[out + cap - 1]
 // (first run of the path last); the count goes to n_runs[id], or
 // kTraceInconsistent / kTraceBadResidue.
-// pad: query columns per lane, 1-4 (a tile of 64 * pad columns; the LDS path
-// and end-to-end variants; the device-memory path variant uses 4).
+// pad: query columns per lane, 1-4 (a tile of 64 * pad columns).
 struct TracePair {
   int64_t q, r, out;
   int32_t A, B, score, cap, id, pad;

@@ -327,21 +327,16 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
 template <bool LB, int MODE>
 __device__ __forceinline__ void trace_mode(const TraceArgs &a, const TracePair &P, const int *smat,
                                            uint16_t *lbits, int *lcarry, uint16_t *lwin) {
-  if (!LB) {
-    trace_one<LB, 4, MODE>(a, P, smat, lbits, lcarry, lwin);
-  } else {
-    switch (P.pad) {
-      case 1: trace_one<LB, 1, MODE>(a, P, smat, lbits, lcarry, lwin); break;
-      case 2: trace_one<LB, 2, MODE>(a, P, smat, lbits, lcarry, lwin); break;
-      case 3: trace_one<LB, 3, MODE>(a, P, smat, lbits, lcarry, lwin); break;
-      default: trace_one<LB, 4, MODE>(a, P, smat, lbits, lcarry, lwin); break;
-    }
+  switch (P.pad) {
+    case 1: trace_one<LB, 1, MODE>(a, P, smat, lbits, lcarry, lwin); break;
+    case 2: trace_one<LB, 2, MODE>(a, P, smat, lbits, lcarry, lwin); break;
+    case 3: trace_one<LB, 3, MODE>(a, P, smat, lbits, lcarry, lwin); break;
+    default: trace_one<LB, 4, MODE>(a, P, smat, lbits, lcarry, lwin); break;
   }
 }
 
-// LDS variant: C per pair from TracePair::pad (the fewest columns per lane
-// that cover a one-tile query, so short queries leave few lanes idle);
-// device-memory variant: 4.
+// C per pair from TracePair::pad: the fewest columns per lane that cover a
+// one-tile query, so short queries leave few lanes idle.
 template <bool LB>
 __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   extern __shared__ int smem[];
