@@ -206,3 +206,22 @@ def test_paths_errors():
         api.sw_align_batch_global_cigar(*args, res, mode=api.SW_MODE_GLOBAL,
                                         pair_query=w.pair_query, cigar_cap=int(off[-1]) - 1)
     assert e.value.code == api.SW_EINVAL
+
+
+def test_paths_device_resident_inputs():
+    import torch
+    w = W.random_pairs(150, 4, (0, 120), (0, 200), 1030)
+    dev = torch.device("cuda")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    d = (t(w.query_res, torch.uint8), t(w.query_off, torch.int64), t(w.ref_res, torch.uint8),
+         t(w.ref_off, torch.int64), t(w.pair_ref, torch.int32))
+    pq = t(w.pair_query, torch.int32)
+    for mode in MODES:
+        res, rs, runs, off = _paths(w, mode)
+        res_d = api.sw_align_batch_global(*d, w.matrix, w.gap_open, w.gap_extend, mode=mode,
+                                          pair_query=pq)
+        assert (res_d == res).all()
+        rs_d, runs_d, off_d = api.sw_align_batch_global_cigar(*d, w.matrix, w.gap_open,
+                                                              w.gap_extend, res_d, mode=mode,
+                                                              pair_query=pq)
+        assert (rs_d == rs).all() and (off_d == off).all() and (runs_d == runs).all()
