@@ -469,7 +469,9 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     tp.A = (int32_t)A;
     tp.B = (int32_t)Bq;
     tp.score = e.score;
-    tp.cap = (int32_t)(mode == 0 ? run_bound(A, Bq) : A + Bq + 2);
+    // end-to-end: k <= min(A, B) pairs, k M runs and two gap runs in each of the
+    // k + 1 gaps (start, between pairs, end)
+    tp.cap = (int32_t)(mode == 0 ? run_bound(A, Bq) : std::min(A + Bq + 2, 3 * std::min(A, Bq) + 2));
     tp.id = k;
     tp.pad = 0;
     region += tp.cap;
