@@ -225,3 +225,21 @@ def test_paths_device_resident_inputs():
                                                               w.gap_extend, res_d, mode=mode,
                                                               pair_query=pq)
         assert (rs_d == rs).all() and (off_d == off).all() and (runs_d == runs).all()
+
+
+def test_largest_alphabet_and_overflow_refusal():
+    # 32 letters (the largest alphabet): the LDS matrix region at its size
+    rng = np.random.default_rng(1040)
+    M = rng.integers(-6, 7, size=(32, 32)).astype(np.int32)
+    np.fill_diagonal(M, 9)
+    w = W.random_pairs(120, 32, (1, 80), (1, 80), 1041, matrix=M, gap_open=5, gap_extend=2)
+    for mode in MODES:
+        _check(w, mode, "alpha 32")
+        _check_paths(w, mode, "alpha 32", pairs=range(0, 120, 10))
+    # scores that could leave the kernels' int32 range are refused, not wrapped
+    big = np.full((4, 4), -(1 << 27), dtype=np.int32)
+    np.fill_diagonal(big, 1 << 26)
+    wb = W.random_pairs(4, 4, (10, 20), (10, 20), 1042, matrix=big, gap_open=3, gap_extend=1)
+    with pytest.raises(api.SwError) as e:
+        _run(wb, api.SW_MODE_GLOBAL)
+    assert e.value.code == api.SW_EOVERFLOW
