@@ -283,6 +283,26 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
   if (!fail && MODE == 0) {
     int ra = A - 1, qb_ = B - 1, mrun = 1, guard = A + B + 2;
     while ((ra | qb_) != 0) {
+      if (LB && T == 1 && ra > 0 && qb_ > 0) {
+        // a run of plain diagonal steps (V = G = M before the pair): step
+        // the bit address along the diagonal instead of recomputing it
+        int i = ra - 1, j = qb_ - 1, col = j / C, c = j - col * C;
+        int addr = i * 64 + col;
+        while ((((int)bits[addr] >> (4 * c)) & 5) == 5) {
+          ++mrun;
+          ra = i;
+          qb_ = j;
+          if (i == 0 || j == 0) break;
+          --i;
+          --j;
+          addr -= 64;
+          if (--c < 0) {
+            c = C - 1;
+            --addr;
+          }
+        }
+        if ((ra | qb_) == 0) break;
+      }
       if (ra == 0 || qb_ == 0 || --guard < 0) { fail = true; break; }
       int i = ra - 1, j = qb_ - 1, nd = 0, ni = 0;
       int nib = nib_at(i, j);
