@@ -363,6 +363,7 @@ namespace {
 
 constexpr int64_t kTraceScratchBytes = 1ll << 30;    // device-memory decision bits per launch
 constexpr int kTraceMaxWaves = 4096;
+constexpr int kDualCols = 160;   // end-to-end queries up to this length run two per wavefront
 
 // Runs a path can have between start and end: every run but the first is
 // preceded by a change of operation, M runs alternate with one or two gap
@@ -684,7 +685,7 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
   if ((rc = W.tr_host.ensure((size_t)np * sizeof(swk::TracePair)))) return rc;
   swk::TracePair *htab = W.tr_host.as<swk::TracePair>();
   int n1 = 0;                        // one-tile pairs first, then the rest
-  std::vector<swk::TracePair> multi;
+  std::vector<swk::TracePair> single, multi;   // one-tile pairs with m > 160; longer ones
   int carry_rows = 0;
   for (int k = 0; k < np; ++k) {
     const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
@@ -714,17 +715,25 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
     tp.score = 0;
     tp.cap = 0;
     tp.id = k;
-    tp.pad = (int32_t)std::min<int64_t>(4, (m + 63) / 64);   // query columns per lane
-    if (m <= swk::kTraceTileCols) {
+    // query columns per lane: 32 lanes per pair up to 160 columns (two pairs
+    // per wavefront), 64 lanes per pair up to 256, 256-column tiles beyond
+    if (m <= kDualCols) {
+      tp.pad = (int32_t)((m + 31) / 32);
       htab[n1++] = tp;
+    } else if (m <= swk::kTraceTileCols) {
+      tp.pad = (int32_t)((m + 63) / 64);
+      single.push_back(tp);
     } else {
+      tp.pad = 4;
       multi.push_back(tp);
       carry_rows = std::max(carry_rows, (int)n);
     }
   }
-  const int nm = (int)multi.size(), nt = n1 + nm;
+  const int n_one = (int)single.size();
+  if (n_one) std::memcpy(htab + n1, single.data(), (size_t)n_one * sizeof(swk::TracePair));
+  const int nm = (int)multi.size(), nt = n1 + n_one + nm;
   if (nt == 0) return SW_OK;
-  if (nm) std::memcpy(htab + n1, multi.data(), (size_t)nm * sizeof(swk::TracePair));
+  if (nm) std::memcpy(htab + n1 + n_one, multi.data(), (size_t)nm * sizeof(swk::TracePair));
   const int64_t per_wave = 4ll * carry_rows * (int64_t)sizeof(int32_t);
   const int waves_m = nm == 0 ? 0 : (int)std::max<int64_t>(
       1, std::min<int64_t>({(int64_t)nm, kTraceScratchBytes / std::max<int64_t>(per_wave, 1),
@@ -751,8 +760,11 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
   ea.pairs = dp;
   ea.n = n1;
   ea.carry_rows = 0;
-  HIPCHK(swk::launch_endtoend(mode, ea, n1, W.st));   // a workgroup per one-tile pair
+  HIPCHK(swk::launch_endtoend2(mode, ea, W.st));   // a workgroup per two pairs
   ea.pairs = dp + n1;
+  ea.n = n_one;
+  HIPCHK(swk::launch_endtoend(mode, ea, n_one, W.st));   // a workgroup per pair
+  ea.pairs = dp + n1 + n_one;
   ea.n = nm;
   ea.carry_rows = carry_rows;
   HIPCHK(swk::launch_endtoend(mode, ea, waves_m, W.st));

@@ -62,6 +62,8 @@ struct EndArgs {
 };
 size_t endtoend_lds_bytes(int alpha);
 hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st);
+// Pairs with m <= 160, two per wavefront; pad = ceil(m / 32).
+hipError_t launch_endtoend2(int mode, const EndArgs &a, hipStream_t st);
 
 // Runs of every pair (n_runs[id] of them, ending at out + cap) to
 // dst[dst_off[id] ..]; every count must be <= its pair's cap.

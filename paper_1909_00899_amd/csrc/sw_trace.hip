@@ -474,6 +474,131 @@ __device__ __forceinline__ void endtoend_one(const EndArgs &a, const TracePair &
   }
 }
 
+// inclusive max over the lanes 0..l of each 32-lane half
+__device__ __forceinline__ int half_max_scan(int x) {
+  x = max(x, dpp_move<0x111, 0xf>(x));   // row_shr:1
+  x = max(x, dpp_move<0x112, 0xf>(x));   // row_shr:2
+  x = max(x, dpp_move<0x114, 0xf>(x));   // row_shr:4
+  x = max(x, dpp_move<0x118, 0xf>(x));   // row_shr:8
+  x = max(x, dpp_move<0x142, 0xa>(x));   // row_bcast:15 into rows 1 and 3
+  return x;
+}
+
+// Two one-tile pairs per wavefront, 32 lanes each (lanes 0-31 the first,
+// 32-63 the second), C query columns per lane: the row's scan and bookkeeping
+// serve both pairs, which halves their share per pair.  The wavefront runs
+// the longer pair's rows; the other half's extra rows change nothing it
+// reports.  Boundaries and results as in endtoend_one.
+template <int MODE, int C>
+__device__ __forceinline__ void endtoend_two(const EndArgs &a, const TracePair &P0,
+                                             const TracePair &P1, bool has1, const int *smat) {
+  const int L = threadIdx.x, l = L & 31;
+  const bool h = L >= 32;
+  const int alpha = a.alpha, go = a.go, ge = a.ge;
+  // this half's pair, field by field
+  const int A = h ? (has1 ? P1.A : 0) : P0.A;
+  const int B = h ? P1.B : P0.B;
+  const int64_t pq = h ? P1.q : P0.q;
+  const int64_t pr = h ? P1.r : P0.r;
+  const int pid = h ? P1.id : P0.id;
+  const int Amax = max(P0.A, has1 ? P1.A : 0);
+  const int jc0 = C * l;
+  bool bad = false;
+  int qb[C], Vp[C], Gp[C], Fp[C], wj[C], ej[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int code = jc0 + c < B ? (int)a.qres[pq + jc0 + c] : 0;
+    bad |= code >= alpha;
+    qb[c] = min(code, alpha - 1) * alpha;
+    Vp[c] = Gp[c] = -(go + (jc0 + c) * ge);
+    Fp[c] = kNeg;
+    wj[c] = (jc0 + c) * ge;
+    ej[c] = go + (jc0 + c - 1) * ge;
+  }
+  int best = -(go + (B - 1) * ge), best_row = -1, score = 0;
+  int cv_prev = 0, rreg = 0;
+  for (int i = 0; i < Amax; ++i) {
+    if ((i & 31) == 0) {                     // 32 rows of each pair's residues at a time
+      const int row = i + l;
+      rreg = row < A ? (int)a.rres[pr + row] : 0;
+      bad |= rreg >= alpha;
+    }
+    const int r0 = readlane(rreg, i & 31), r1 = readlane(rreg, 32 + (i & 31));
+    const int rc = min(h ? r1 : r0, alpha - 1);
+    const int cv_in = MODE == 0 ? -(go + i * ge) : 0;
+    const int cp_in = MODE == 0 ? kNeg : -ge;
+    const int dsh = dpp_wave_shr1(cv_prev, Vp[C - 1]);
+    const int d0 = l == 0 ? cv_prev : dsh;
+    int Mv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) Mv[c] = smat[qb[c] + rc] + (c ? Vp[c - 1] : d0);
+    int w[C], lp[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) w[c] = Mv[c] + wj[c];
+    lp[0] = kNeg;
+#pragma unroll
+    for (int c = 1; c < C; ++c) lp[c] = c == 1 ? w[0] : max(lp[c - 1], w[c - 1]);
+    const int agg = C == 1 ? w[0] : max(lp[C - 1], w[C - 1]);
+    const int sh = dpp_wave_shr1(kNeg, half_max_scan(agg));
+    const int exc = max(l == 0 ? kNeg : sh, cp_in);
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int g = max(Mv[c], max(exc, lp[c]) - ej[c]);
+      const int f = max(Gp[c] - go, Fp[c] - ge);
+      Vp[c] = max(g, f);
+      Gp[c] = g;
+      Fp[c] = f;
+    }
+    cv_prev = cv_in;
+    const int jb = B - 1 - jc0;
+    int v = Vp[0];
+#pragma unroll
+    for (int c = 1; c < C; ++c)
+      if (jb == c) v = Vp[c];
+    if (i < A) {
+      if (MODE == 1 && v > best) {
+        best = v;
+        best_row = i;
+      }
+      score = v;
+    }
+  }
+  const uint64_t bb = __ballot(bad);
+  const bool bad_h = h ? (bb >> 32) != 0 : (bb & 0xffffffffull) != 0;
+  const int jb = B - 1 - jc0;
+  if (jb >= 0 && jb < C && (!h || has1)) {
+    DevResult r;
+    r.score = MODE == 0 ? score : best;
+    r.qend = B - 1;
+    r.rend = MODE == 0 ? A - 1 : best_row;
+    r.flags = bad_h ? kFlagBadResidue : 0;
+    a.out[pid] = r;
+  }
+}
+
+// Couples of pairs with m <= 160 (pairs[2p], pairs[2p + 1]); TracePair::pad
+// holds ceil(m / 32) and a couple runs at the larger of its two (at most 5
+// columns per lane keeps the kernel's registers at several wavefronts per SIMD).
+template <int MODE>
+__global__ __launch_bounds__(64) void endtoend2_kernel(EndArgs a) {
+  extern __shared__ int smem[];
+  int *smat = smem;
+  for (int k = threadIdx.x; k < a.alpha * a.alpha; k += 64) smat[k] = a.matrix[k];
+  __syncthreads();
+  for (int p = blockIdx.x; 2 * p < a.n; p += gridDim.x) {
+    const TracePair P0 = a.pairs[2 * p];
+    const bool has1 = 2 * p + 1 < a.n;
+    const TracePair P1 = a.pairs[has1 ? 2 * p + 1 : 2 * p];
+    switch (max(P0.pad, P1.pad)) {
+      case 1: endtoend_two<MODE, 1>(a, P0, P1, has1, smat); break;
+      case 2: endtoend_two<MODE, 2>(a, P0, P1, has1, smat); break;
+      case 3: endtoend_two<MODE, 3>(a, P0, P1, has1, smat); break;
+      case 4: endtoend_two<MODE, 4>(a, P0, P1, has1, smat); break;
+      default: endtoend_two<MODE, 5>(a, P0, P1, has1, smat); break;
+    }
+  }
+}
+
 template <int MODE>
 __global__ __launch_bounds__(64) void endtoend_kernel(EndArgs a) {
   extern __shared__ int smem[];
@@ -516,6 +641,18 @@ size_t trace_lds_bytes(bool lds_bits, int alpha) {
 }
 
 size_t endtoend_lds_bytes(int alpha) { return (size_t)dev::mat_words(alpha) * sizeof(int); }
+
+hipError_t launch_endtoend2(int mode, const EndArgs &a, hipStream_t st) {
+  if (a.n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(((int64_t)a.n + 1) / 2, 1 << 30);
+  if (mode == 0)
+    hipLaunchKernelGGL(dev::endtoend2_kernel<0>, dim3(grid), dim3(64), endtoend_lds_bytes(a.alpha),
+                       st, a);
+  else
+    hipLaunchKernelGGL(dev::endtoend2_kernel<1>, dim3(grid), dim3(64), endtoend_lds_bytes(a.alpha),
+                       st, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st) {
   if (a.n <= 0 || grid <= 0) return hipSuccess;
