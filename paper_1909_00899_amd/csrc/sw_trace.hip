@@ -283,22 +283,29 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
   if (!fail && MODE == 0) {
     int ra = A - 1, qb_ = B - 1, mrun = 1, guard = A + B + 2;
     while ((ra | qb_) != 0) {
-      if (LB && T == 1 && ra > 0 && qb_ > 0) {
+      if (ra > 0 && qb_ > 0) {
         // a run of plain diagonal steps (V = G = M before the pair): step
-        // the bit address along the diagonal instead of recomputing it
-        int i = ra - 1, j = qb_ - 1, col = j / C, c = j - col * C;
-        int addr = i * 64 + col;
-        while ((((int)bits[addr] >> (4 * c)) & 5) == 5) {
-          ++mrun;
-          ra = i;
-          qb_ = j;
-          if (i == 0 || j == 0) break;
-          --i;
-          --j;
-          addr -= 64;
-          if (--c < 0) {
-            c = C - 1;
-            --addr;
+        // the bit address along the diagonal instead of recomputing it, up
+        // to a tile edge or (device-memory bits) the window's first row
+        int i = ra - 1, j = qb_ - 1;
+        const int t = j / TC;
+        int col = (j % TC) / C, c = j % C;
+        if (LB || (t == w_tile && i >= w_lo && i < w_lo + kWalkRows)) {
+          int addr = LB ? (t * A + i) * 64 + col : (i - w_lo) * 64 + col;
+          while ((((int)(LB ? bits[addr] : lwin[addr]) >> (4 * c)) & 5) == 5) {
+            ++mrun;
+            ra = i;
+            qb_ = j;
+            if (i == 0 || j == 0) break;
+            --i;
+            --j;
+            if (!LB && i < w_lo) break;
+            addr -= 64;
+            if (--c < 0) {
+              c = C - 1;
+              if (--col < 0) break;
+              --addr;
+            }
           }
         }
         if ((ra | qb_) == 0) break;
