@@ -10,7 +10,7 @@ same steps gives the per-launch kernel time for the roofline, and a leg with
 the host planner is timed beside it.  The autotuner picks the tile shapes
 before the timed region.  Prints ONE JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain] [--no-serve]
 """
 from __future__ import annotations
 
@@ -78,6 +78,31 @@ def _with_measured_peak(roof: dict) -> dict:
     return roof
 
 
+def copy_calibration():
+    """A plain device copy of 256 MiB, three launches: the known byte count
+    against which the HBM counters (FETCH_SIZE, WRITE_SIZE) are scaled."""
+    import torch
+    n = 256 * 1024 * 1024
+    src = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_per_launch": n, "launches": 3}))
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,16 +110,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--n-refs", type=int, default=100_000)
     ap.add_argument("--workload", default="protein_search",
-                    choices=["protein_search", "dna_pairs", "long_queries", "serving"])
+                    choices=["protein_search", "dna_pairs", "long_queries", "serving",
+                             "copy_calibration"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (no multi-GPU path); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "copy_calibration":
+        return copy_calibration()
     if args.workload == "long_queries":
         return bench_long_queries(args)
     if args.workload == "serving":
@@ -230,36 +259,72 @@ def main():
                               w, out.results, qs, rs, n_st)
 
     if not args.no_plain:
-        # plain kernel: one 256 x 1024 pair per launch (sw_align)
+        # plain kernel: one 256 x 1024 pair per launch (sw_align_ex: the plain
+        # call with the kernel's HIP-event time); the median over 1000 launches
         p = W.single_pair()
         q, r = p.pair(0)
-        for _ in range(3):
-            api.sw_align(q, r, p.matrix, p.gap_open, p.gap_extend)
-        n_pl = 200
-        t1 = time.perf_counter()
+        for _ in range(10):
+            api.sw_align_ex(q, r, p.matrix, p.gap_open, p.gap_extend)
+        n_pl = 1000
+        pk, pw = [], []
         for _ in range(n_pl):
-            pr = api.sw_align(q, r, p.matrix, p.gap_open, p.gap_extend)
-        pl_s = (time.perf_counter() - t1) / n_pl
-        plain_gcups = q.size * r.size / pl_s / 1e9
+            pres, pst = api.sw_align_ex(q, r, p.matrix, p.gap_open, p.gap_extend)
+            pk.append(pst["kernel_ms"])
+            pw.append(pst["total_ms"])
+        pk_ms = float(np.median(pk))
+        pw_ms = float(np.median(pw))
+        plain_kernel_gcups = q.size * r.size / (pk_ms / 1e3) / 1e9
+        kernel_gcups_batched = cells / (kms / 1e3) / 1e9
         rec["plain"] = {"workload": "single_pair 256x1024 int32, one launch per pair",
-                        "gcups": round(plain_gcups, 4), "us_per_pair": round(pl_s * 1e6, 2),
-                        "batched_over_plain": round(gcups / plain_gcups, 1)}
+                        "launches": n_pl,
+                        "kernel_us_median": round(pk_ms * 1e3, 2),
+                        "call_us_median": round(pw_ms * 1e3, 2),
+                        "kernel_gcups": round(plain_kernel_gcups, 3),
+                        "call_gcups": round(q.size * r.size / (pw_ms / 1e3) / 1e9, 3),
+                        "batched_over_plain": round(kernel_gcups_batched / plain_kernel_gcups, 1),
+                        "same_as_oracle": None}
+        if not args.no_cpu:
+            import oracle
+            rec["plain"]["same_as_oracle"] = bool(
+                tuple(pres[:3]) == oracle.align(q, r, p.matrix, p.gap_open, p.gap_extend))
+
+    if not args.no_serve:
+        # served latency: a compact open-loop sweep through the server (the
+        # full sweep is --workload serving), every result checked against the
+        # offline batch call on the same requests
+        rows = _serving_sweep(api, W, [10000, 50000, 200000], lambda rate: 4000)
+        rec["served"] = {"workload": "25k protein + 25k DNA resident refs, Poisson arrivals, "
+                                     "4000 requests per rate",
+                         "sweep": rows,
+                         "served_equals_offline": all(x["served_equals_offline"] for x in rows)}
 
     if not args.no_cpu:
         import oracle
         # the oracle on the same workload: a bounded sample of references
         n_s = min(w.n_pairs, 20_000)
         sub = w.subset(np.arange(n_s))
-        threads = os.cpu_count() or 1
+        threads = min(16, os.cpu_count() or 1)
         t2 = time.perf_counter()
         want = oracle.align_batch(sub.query_res, sub.query_off, sub.ref_res, sub.ref_off,
                                   sub.pair_ref, sub.matrix, sub.gap_open, sub.gap_extend,
                                   n_threads=threads)
         cs = time.perf_counter() - t2
+        # one thread on a smaller sample of the same references
+        n_1 = min(w.n_pairs, 2_000)
+        sub1 = w.subset(np.arange(n_1))
+        t3 = time.perf_counter()
+        oracle.align_batch(sub1.query_res, sub1.query_off, sub1.ref_res, sub1.ref_off,
+                           sub1.pair_ref, sub1.matrix, sub1.gap_open, sub1.gap_extend, n_threads=1)
+        c1 = time.perf_counter() - t3
         rec["cpu_baseline"] = {"value": round(sub.cells() / cs / 1e9, 3), "unit": "GCUPS",
                                "cores": threads, "kind": "oracle",
                                "sample": "first %d of the 100k references (%.2e cells), "
-                                         "scalar int64 C oracle, pthreads" % (n_s, sub.cells())}
+                                         "scalar int64 C oracle, pthreads" % (n_s, sub.cells()),
+                               "single_thread": {"value": round(sub1.cells() / c1 / 1e9, 4),
+                                                 "unit": "GCUPS",
+                                                 "sample": "first %d references (%.2e cells)"
+                                                           % (n_1, sub1.cells())},
+                               "cpu_model": _cpu_model()}
         rec["parity_sample"] = bool(np.array_equal(out.results[:n_s, :3], want))
     print(json.dumps(rec))
 
@@ -441,6 +506,7 @@ def bench_long_queries(args):
     64 queries x 10k references (1.3e13 cells).
     """
     import torch
+    import oracle
     from paper_1909_00899_amd import api, workloads as W
     api.load()
     api.sw_init(0)
@@ -468,6 +534,14 @@ def bench_long_queries(args):
                              "seglen": st["seglen_max"], "results": out.results}
             lz = res["lazyf"]
             passes = lz["lazyf_steps"] / max(1, lz["columns"]) / max(1, lz["seglen"])
+            # the oracle on a seeded sample of the class's pairs (both queries)
+            samp = np.random.default_rng(7).choice(sub.n_pairs, size=32, replace=False)
+            ws = sub.subset(np.sort(samp))
+            want = oracle.align_batch(ws.query_res, ws.query_off, ws.ref_res, ws.ref_off,
+                                      ws.pair_ref, ws.matrix, ws.gap_open, ws.gap_extend,
+                                      pair_query=ws.pair_query)
+            parity = bool(np.array_equal(res["scan"]["results"][np.sort(samp), :3], want) and
+                          np.array_equal(lz["results"][np.sort(samp), :3], want))
             rows["query_%s/ref_%s" % (qkind, rkind)] = {
                 "pairs": sub.n_pairs, "cells": sub.cells(),
                 "query_lens": [int(full.query_off[q + 1] - full.query_off[q]) for q in qsel],
@@ -475,7 +549,8 @@ def bench_long_queries(args):
                 "scan_kernel_gcups": res["scan"]["kernel_gcups"],
                 "lazyf_kernel_gcups": lz["kernel_gcups"],
                 "lazyf_passes_per_column": round(passes, 3),
-                "scan_equals_lazyf": bool(np.array_equal(res["scan"]["results"], lz["results"]))}
+                "scan_equals_lazyf": bool(np.array_equal(res["scan"]["results"], lz["results"])),
+                "parity_sample_32": parity}
     tot_scan = sum(r["cells"] for r in rows.values()) / sum(
         r["cells"] / r["scan_gcups"] for r in rows.values())
     print(json.dumps({"metric": METRIC, "value": round(tot_scan, 2), "unit": "GCUPS", "n_gpus": 1,
@@ -485,19 +560,41 @@ def bench_long_queries(args):
                       "by_class": rows}))
 
 
-def bench_serving(args):
-    """Continuous-batching server: Poisson arrivals at a swept rate, p50/p99."""
-    from paper_1909_00899_amd import api, workloads as W
-    api.load()
-    api.sw_init(0)
+def _offline_serving(api, db, scor, req):
+    """The requests as offline batches (one sw_align_batch per scoring family):
+    results in request order and the wall time of the two calls."""
+    res = np.zeros((req.ref_id.size, 4), dtype=np.int32)
+    fam = []
+    for dna in (False, True):
+        sel = np.nonzero(req.is_dna == dna)[0]
+        if sel.size == 0:
+            continue
+        qs = [req.query_res[req.query_off[k]:req.query_off[k + 1]] for k in sel]
+        qoff = np.zeros(sel.size + 1, dtype=np.int64)
+        np.cumsum([q.size for q in qs], out=qoff[1:])
+        r0 = 0 if not dna else db.n_protein
+        r1 = db.n_protein if not dna else db.n_protein + db.n_dna
+        rres = db.ref_res[db.ref_off[r0]:db.ref_off[r1]]
+        roff = db.ref_off[r0:r1 + 1] - db.ref_off[r0]
+        fam.append((sel, np.concatenate(qs), qoff, rres, roff,
+                    (req.ref_id[sel] - r0).astype(np.int32), np.arange(sel.size, dtype=np.int32),
+                    scor[1 if dna else 0]))
+    t0 = time.perf_counter()
+    for sel, qres, qoff, rres, roff, pr, pq, (M, go, ge) in fam:
+        res[sel] = api.sw_align_batch(qres, qoff, rres, roff, pr, M, go, ge, pair_query=pq).results
+    return res, time.perf_counter() - t0
+
+
+def _serving_sweep(api, W, rates, n_of_rate):
+    """Open-loop Poisson replay through the server at each rate; every served
+    result is compared with the offline batch call on the same requests."""
     db = W.serving_db()
     scor = [(W.protein_matrix(), 11, 1), (W.dna_matrix(), 6, 1)]
-    rates = [1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000]
-    out_rows = []
+    rows = []
     with api.Server(db.ref_res, db.ref_off, scor, hbm_budget_bytes=8 << 30, n_streams=4,
                     max_batch=4096) as srv:
         for rate in rates:
-            n = int(min(20000, max(2000, rate * 3)))
+            n = n_of_rate(rate)
             req = W.serving_requests(db, rate, n, seed=rate)
             sid = req.is_dna.astype(np.int32)
             t0 = time.perf_counter()
@@ -508,38 +605,32 @@ def bench_serving(args):
             ql = np.diff(req.query_off)
             rl = np.diff(db.ref_off)[req.ref_id]
             cells = float(np.sum(ql.astype(np.float64) * rl))
-            out_rows.append({"rate_per_s": rate, "requests": n,
-                             "p50_ms": round(float(np.percentile(lat[warm], 50)), 3),
-                             "p99_ms": round(float(np.percentile(lat[warm], 99)), 3),
-                             "served_gcups": round(cells / wall / 1e9, 2),
-                             "achieved_rate": round(n / wall, 1)})
-    # offline: the same requests of the last rate as two batches (one per scoring)
-    req = W.serving_requests(db, rates[-1], out_rows[-1]["requests"], seed=rates[-1])
-    fam = []
-    for dna in (False, True):
-        sel = np.nonzero(req.is_dna == dna)[0]
-        qs = [req.query_res[req.query_off[k]:req.query_off[k + 1]] for k in sel]
-        qoff = np.zeros(sel.size + 1, dtype=np.int64)
-        np.cumsum([q.size for q in qs], out=qoff[1:])
-        r0 = 0 if not dna else db.n_protein
-        r1 = db.n_protein if not dna else db.n_protein + db.n_dna
-        rres = db.ref_res[db.ref_off[r0]:db.ref_off[r1]]
-        roff = db.ref_off[r0:r1 + 1] - db.ref_off[r0]
-        fam.append((np.concatenate(qs), qoff, rres, roff, (req.ref_id[sel] - r0).astype(np.int32),
-                    np.arange(sel.size, dtype=np.int32), scor[1 if dna else 0]))
-    t0 = time.perf_counter()
-    for qres, qoff, rres, roff, pr, pq, (M, go, ge) in fam:
-        api.sw_align_batch(qres, qoff, rres, roff, pr, M, go, ge, pair_query=pq)
-    off_wall = time.perf_counter() - t0
-    ql = np.diff(req.query_off)
-    rl = np.diff(db.ref_off)[req.ref_id]
-    off_gcups = float(np.sum(ql.astype(np.float64) * rl)) / off_wall / 1e9
-    print(json.dumps({"metric": METRIC, "value": out_rows[-1]["p99_ms"], "unit": "ms p99",
+            off_res, off_wall = _offline_serving(api, db, scor, req)
+            rows.append({"rate_per_s": rate, "requests": n,
+                         "p50_ms": round(float(np.percentile(lat[warm], 50)), 3),
+                         "p99_ms": round(float(np.percentile(lat[warm], 99)), 3),
+                         "served_gcups": round(cells / wall / 1e9, 2),
+                         "offline_gcups": round(cells / off_wall / 1e9, 2),
+                         "achieved_rate": round(n / wall, 1),
+                         "served_equals_offline": bool(np.array_equal(res[:, :3],
+                                                                      off_res[:, :3]))})
+    return rows
+
+
+def bench_serving(args):
+    """Continuous-batching server: Poisson arrivals at a swept rate, p50/p99."""
+    from paper_1909_00899_amd import api, workloads as W
+    api.load()
+    api.sw_init(0)
+    rates = [1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000]
+    rows = _serving_sweep(api, W, rates, lambda rate: int(min(20000, max(2000, rate * 3))))
+    print(json.dumps({"metric": METRIC, "value": rows[-1]["p99_ms"], "unit": "ms p99",
                       "n_gpus": 1, "higher_is_better": False, "dtype": "i16x2",
                       "data": "synthetic",
                       "config": {"workload": "serving: 25k protein + 25k DNA resident refs, "
                                              "Poisson arrivals, one reference per request"},
-                      "sweep": out_rows, "offline_gcups": round(off_gcups, 2)}))
+                      "sweep": rows,
+                      "served_equals_offline": all(r["served_equals_offline"] for r in rows)}))
 
 
 if __name__ == "__main__":

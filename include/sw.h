@@ -365,6 +365,18 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
                       sw_result *out, sw_stats *stats);
 
 /* ---------------------------------------------------------------------------
+ * sw_align_ex -- sw_align with statistics (for measurement).
+ *
+ * Same operation, arguments, ownership and errors as sw_align (the plain form
+ * of Algorithm 6: one pair, one kernel launch).  If stats is not NULL it is
+ * zeroed and then receives kernel_ms (device time of the alignment kernel,
+ * from HIP events on the library's stream), total_ms (wall time of the call)
+ * and cells (query_len * ref_len); kernel_ms stays 0 for an empty side.
+ * ------------------------------------------------------------------------- */
+int sw_align_ex(const uint8_t *query, int32_t query_len, const uint8_t *ref, int32_t ref_len,
+                const sw_scoring *sc, sw_result *out, sw_stats *stats);
+
+/* ---------------------------------------------------------------------------
  * Autotuner.
  *
  * The planner picks, for each group of pairs, the lanes per alignment (16, 32

@@ -127,7 +127,7 @@ def align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix,
     n_pairs = pr.size
     out = np.zeros((n_pairs, 3), dtype=np.int64)
     if n_threads is None:
-        n_threads = os.cpu_count() or 1
+        n_threads = min(16, os.cpu_count() or 1)
     rc = _load().oracle_sw_batch(n_pairs, qres.ctypes.data, qoff.ctypes.data,
                                  rres.ctypes.data, roff.ctypes.data,
                                  None if pq is None else pq.ctypes.data, pr.ctypes.data,

@@ -29,7 +29,8 @@ EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align"
             "sw_align_batch", "sw_align_batch_ex", "sw_server_create", "sw_server_submit",
             "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay",
             "sw_autotune", "sw_tune_set", "sw_tune_get", "sw_align_batch_starts",
-            "sw_align_batch_cigar", "sw_align_batch_global", "sw_align_batch_global_cigar"]
+            "sw_align_batch_cigar", "sw_align_batch_global", "sw_align_batch_global_cigar",
+            "sw_align_ex"]
 
 
 class NativeLibraryError(RuntimeError):
@@ -152,6 +153,9 @@ def load():
     lib.sw_shutdown.argtypes = []
     lib.sw_align.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                              ctypes.POINTER(Scoring), ctypes.POINTER(Result)]
+    lib.sw_align_ex.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                ctypes.POINTER(Scoring), ctypes.POINTER(Result),
+                                ctypes.POINTER(Stats)]
     lib.sw_align_batch.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), ctypes.c_void_p]
     lib.sw_align_batch_ex.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                       ctypes.POINTER(Options), ctypes.c_void_p,
@@ -229,6 +233,20 @@ def sw_align(query, ref, matrix, gap_open: int, gap_extend: int):
                            r.ctypes.data if r.size else None, r.size,
                            ctypes.byref(sc), ctypes.byref(res)))
     return res.score, res.query_end, res.ref_end, res.flags
+
+
+def sw_align_ex(query, ref, matrix, gap_open: int, gap_extend: int):
+    """sw_align with statistics: ((score, query_end, ref_end, flags), stats dict
+    with kernel_ms from HIP events, total_ms and cells)."""
+    q = np.ascontiguousarray(np.asarray(query, dtype=np.uint8))
+    r = np.ascontiguousarray(np.asarray(ref, dtype=np.uint8))
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    res = Result()
+    st = Stats()
+    _check(load().sw_align_ex(q.ctypes.data if q.size else None, q.size,
+                              r.ctypes.data if r.size else None, r.size,
+                              ctypes.byref(sc), ctypes.byref(res), ctypes.byref(st)))
+    return (res.score, res.query_end, res.ref_end, res.flags), st.as_dict()
 
 
 def _is_torch_cuda(x) -> bool:

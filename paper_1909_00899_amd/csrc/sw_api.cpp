@@ -194,6 +194,13 @@ int sw_shutdown(void) {
 
 int sw_align(const uint8_t *query, int32_t query_len, const uint8_t *ref, int32_t ref_len,
              const sw_scoring *sc, sw_result *out) {
+  return sw_align_ex(query, query_len, ref, ref_len, sc, out, nullptr);
+}
+
+int sw_align_ex(const uint8_t *query, int32_t query_len, const uint8_t *ref, int32_t ref_len,
+                const sw_scoring *sc, sw_result *out, sw_stats *stats) {
+  const double t0 = now_ms();
+  if (stats) std::memset(stats, 0, sizeof(*stats));
   if (!out || query_len < 0 || ref_len < 0 || (query_len > 0 && !query) ||
       (ref_len > 0 && !ref)) {
     set_error("bad argument to sw_align");
@@ -231,8 +238,13 @@ int sw_align(const uint8_t *query, int32_t query_len, const uint8_t *ref, int32_
   ExecOptions opt;
   opt.force_kernel = 1;
   opt.force_lanes = 64;
-  return run_batch(in, S, SW_PREC_I32, opt, C.ws, 1, C.stream, C.ev0, C.ev1, C.num_cus, out,
-                   nullptr);
+  rc = run_batch(in, S, SW_PREC_I32, opt, C.ws, 1, C.stream, C.ev0, C.ev1, C.num_cus, out,
+                 stats);
+  if (stats) {
+    stats->cells = (int64_t)query_len * ref_len;
+    stats->total_ms = now_ms() - t0;
+  }
+  return rc;
 }
 
 int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options *opt,

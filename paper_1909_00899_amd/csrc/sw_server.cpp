@@ -57,6 +57,7 @@ struct sw_server {
   std::vector<Scoring> scorings;
   DevBuf db;                         // resident reference residues
   std::vector<int64_t> db_off;
+  std::vector<uint8_t> db_max_code;  // largest residue code of each reference (0 if empty)
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Request *> queue;
@@ -205,9 +206,19 @@ int sw_server_create(const sw_server_config *cfg, sw_server **out) {
     s->scorings.push_back(sc);
   }
   s->db_off.assign(cfg->db_off, cfg->db_off + cfg->n_db + 1);
+  if (s->db_off[0] != 0) { set_error("bad db offsets"); return SW_EINVAL; }
   for (int r = 0; r < cfg->n_db; ++r)
     if (s->db_off[r] < 0 || s->db_off[r + 1] < s->db_off[r]) { set_error("bad db offsets"); return SW_EINVAL; }
   const int64_t nbytes = s->db_off[cfg->n_db];
+  // A reference is only scored under schemes whose alphabet holds all of its
+  // residues (a larger code would index past the scheme's profile); submit
+  // checks this against the largest code recorded here.
+  s->db_max_code.assign(cfg->n_db, 0);
+  for (int r = 0; r < cfg->n_db; ++r) {
+    uint8_t mx = 0;
+    for (int64_t k = s->db_off[r]; k < s->db_off[r + 1]; ++k) mx = std::max(mx, cfg->db_res[k]);
+    s->db_max_code[r] = mx;
+  }
   if ((rc = s->db.ensure(std::max<int64_t>(nbytes, 1)))) return rc;
   if (hipSetDevice(s->device) != hipSuccess ||
       (nbytes && hipMemcpy(s->db.p, cfg->db_res, nbytes, hipMemcpyHostToDevice) != hipSuccess)) {
@@ -231,6 +242,11 @@ int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int3
   for (int k = 0; k < query_len; ++k)
     if (query[k] >= sc.alpha) { set_error("query residue %d out of range", k); return SW_EINVAL; }
   const int64_t n = s->db_off[ref_id + 1] - s->db_off[ref_id];
+  if (n > 0 && s->db_max_code[ref_id] >= sc.alpha) {
+    set_error("reference %d holds residue code %d, not below scoring %d's alphabet size %d",
+              ref_id, (int)s->db_max_code[ref_id], scoring_id, sc.alpha);
+    return SW_EINVAL;
+  }
   if (std::min<int64_t>(query_len, n) * (int64_t)sc.max_s >= 2147483647ll) {
     set_error("score may overflow int32");
     return SW_EOVERFLOW;

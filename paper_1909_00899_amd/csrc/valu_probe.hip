@@ -42,23 +42,29 @@ __global__ __launch_bounds__(256) void valu_probe_kernel(uint32_t *out, int trip
   out[blockIdx.x * blockDim.x + threadIdx.x] = x;
 }
 
-// The same for 32-bit integer maxima and adds (v_max_i32 / v_add_u32, the
-// instructions of the int32 path and end-to-end kernels): one op per lane
-// per instruction.
+// The same for 32-bit integer adds and maxima (v_add_u32 / v_max_i32, the
+// instructions of the int32 path and end-to-end kernels): one op per lane per
+// instruction.  Each step is written as the two instructions themselves, so
+// the count is exact: in plain C++ the chain max(acc + a, b) composes into one
+// add and one maximum over any number of unrolled steps (max-plus algebra with
+// loop-invariant operands), and the compiler folds it.
 __global__ __launch_bounds__(256) void valu_probe_i32_kernel(uint32_t *out, int trips) {
-  int acc[kAcc], add[kAcc];
+  int acc[kAcc], add[kAcc], lim[kAcc];
   const uint32_t seed = threadIdx.x * 2654435761u ^ blockIdx.x;
 #pragma unroll
   for (int k = 0; k < kAcc; ++k) {
     acc[k] = (int)(seed + 977u * k);
     add[k] = (int)((seed >> 3) | 7u) + k;
+    lim[k] = (int)(seed >> 7) - k;
   }
   for (int t = 0; t < trips; ++t) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
 #pragma unroll
       for (int k = 0; k < kAcc; ++k) {
-        acc[k] = max(acc[k] + add[k], add[k] - u);
+        asm volatile("v_add_u32 %0, %0, %1\n\tv_max_i32 %0, %0, %2"
+                     : "+v"(acc[k])
+                     : "v"(add[k]), "v"(lim[k]));
       }
     }
   }
@@ -101,8 +107,8 @@ extern "C" int swprobe_valu(int grid, int trips, double *ops_per_s) {
 }
 
 // As swprobe_valu for the 32-bit kernel: *ops_per_s receives int32 operations
-// per second (an add and a maximum per step and lane; the subtraction of the
-// loop constant is hoisted by the compiler).  0 on success, else the HIP error.
+// per second (one v_add_u32 and one v_max_i32 per step and lane, each one
+// operation per lane).  0 on success, else the HIP error.
 extern "C" int swprobe_valu_i32(int grid, int trips, double *ops_per_s) {
   if (grid <= 0 || trips <= 0 || ops_per_s == nullptr) return (int)hipErrorInvalidValue;
   uint32_t *out = nullptr;

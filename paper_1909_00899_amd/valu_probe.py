@@ -20,7 +20,8 @@ def measure(grid: int = 2048, trips: int = 20000) -> float:
 
 
 def measure_i32(grid: int = 2048, trips: int = 20000) -> float:
-    """32-bit integer operations per second (v_add_u32 and v_max_i32 streams)."""
+    """32-bit integer operations per second (v_add_u32 and v_max_i32 streams,
+    written as the instructions themselves so that their count is exact)."""
     lib = ctypes.CDLL(os.path.join(HERE, "libswprobe.so"))
     lib.swprobe_valu_i32.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     out = ctypes.c_double(0.0)

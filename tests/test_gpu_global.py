@@ -59,8 +59,38 @@ def test_every_column_count(mode):
     rng = np.random.default_rng(985 + mode)
     w = W.random_pairs(300, 4, (1, 256), (1, 120), 986 + mode, matrix=W.random_matrix(rng, 4),
                        gap_open=2, gap_extend=1)
-    assert {int((m + 63) // 64) for m in np.diff(w.query_off)} == {1, 2, 3, 4}
+    ms = np.diff(w.query_off)
+    # up to 160 residues two pairs share a wavefront, 32 lanes each (1-5
+    # columns per lane); 161-256 run on 64 lanes (3 or 4 columns per lane)
+    assert {int((m + 31) // 32) for m in ms if m <= 160} == {1, 2, 3, 4, 5}
+    assert {int((m + 63) // 64) for m in ms if 160 < m <= 256} == {3, 4}
     _check(w, mode, "columns")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_dual_pairs_odd_count_uneven_neighbours(mode):
+    # an odd number of short-query pairs (the last wavefront holds one pair)
+    # whose neighbours in the batch differ greatly in reference length and
+    # in columns per lane, so the two halves of a wavefront end far apart
+    rng = np.random.default_rng(1990 + mode)
+    M = W.random_matrix(rng, 4)
+    qs, rs = [], []
+    for k in range(41):
+        m = int(rng.integers(1, 161)) if k % 3 else int(rng.integers(129, 161))
+        n = int(rng.integers(1, 8)) if k % 2 else int(rng.integers(900, 1400))
+        qs.append(rng.integers(0, 4, size=m, dtype=np.uint8))
+        rs.append(rng.integers(0, 4, size=n, dtype=np.uint8))
+    qres = np.concatenate(qs)
+    rres = np.concatenate(rs)
+    qoff = np.zeros(42, dtype=np.int64)
+    roff = np.zeros(42, dtype=np.int64)
+    np.cumsum([q.size for q in qs], out=qoff[1:])
+    np.cumsum([r.size for r in rs], out=roff[1:])
+    idx = np.arange(41, dtype=np.int32)
+    w = W.Workload("dual_odd", qres, qoff, rres, roff, idx, idx.copy(), M, 3, 1, {})
+    assert w.n_pairs % 2 == 1 and (np.diff(qoff) <= 160).all()
+    assert {int((m + 31) // 32) for m in np.diff(qoff)} == {1, 2, 3, 4, 5}
+    _check(w, mode, "dual-odd")
 
 
 @pytest.mark.parametrize("mode", MODES)

@@ -30,7 +30,10 @@ def _oracle_requests(db, reqs):
 
 
 def test_replay_mixed_matches_oracle_and_batch(db):
-    reqs = W.serving_requests(db, rate_per_s=20000, n_requests=240, seed=41, dna_len=(100, 2000))
+    # the full DNA length range of the serving workload (100 - 10000 bp)
+    reqs = W.serving_requests(db, rate_per_s=20000, n_requests=240, seed=41, dna_len=(100, 10_000))
+    dlens = np.diff(reqs.query_off)[reqs.is_dna]
+    assert dlens.max() > 8000
     want = _oracle_requests(db, reqs)
     sid = reqs.is_dna.astype(np.int32)
     with api.Server(db.ref_res, db.ref_off, _scorings(), n_streams=4, max_batch=64) as srv:
@@ -81,3 +84,14 @@ def test_budget_admission_and_errors(db):
         with pytest.raises(api.SwError) as e:
             srv.submit([0, 25], 0, 0)           # residue outside the alphabet
         assert e.value.code == api.SW_EINVAL
+        # a protein reference (codes up to 19) under the 4-letter DNA scoring
+        assert db.ref_res[db.ref_off[0]:db.ref_off[1]].max() >= 4
+        with pytest.raises(api.SwError) as e:
+            srv.submit([0, 1, 2], 0, 1)
+        assert e.value.code == api.SW_EINVAL
+        # the same reference under its own scoring is accepted
+        t = srv.submit([0, 1, 2], 0, 0)
+        srv.drain()
+        q = np.array([0, 1, 2], dtype=np.uint8)
+        r = db.ref_res[db.ref_off[0]:db.ref_off[1]]
+        assert tuple(srv.poll(t)[:3]) == tuple(oracle.align(q, r, *_scorings()[0]))
