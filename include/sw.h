@@ -377,6 +377,45 @@ int sw_align_ex(const uint8_t *query, int32_t query_len, const uint8_t *ref, int
                 const sw_scoring *sc, sw_result *out, sw_stats *stats);
 
 /* ---------------------------------------------------------------------------
+ * sw_align_batch_noalloc -- sw_align_batch for callers that cannot allocate.
+ *
+ * For callers that must not allocate memory during the call: code under HIP
+ * stream capture, tight serving loops, hosts that forbid hipMalloc.  Computes
+ * exactly what sw_align_batch computes for the same batch and scoring (the
+ * same device planner and kernels), but allocates nothing: no device memory,
+ * no pinned host memory and no host heap.  Every buffer of the call lives in
+ * one fixed device array of the library (about 53 MiB per device, held from
+ * the library's initialisation of a device until the process ends), which
+ * bounds the batch to SW_NOALLOC_MAX_PAIRS pairs.
+ *
+ * Arguments as sw_align_batch, with these restrictions:
+ *   - b->device_resident must be 1 (every sequence, offset and pair array is
+ *     device memory on the library's device);
+ *   - out is DEVICE memory of n_pairs sw_result entries, owned by the caller;
+ *   - the batch must be one the device planner takes: one query (pair_query
+ *     NULL or n_queries 1) of at most 512 residues, or a query per pair whose
+ *     longest fits a compiled per-pair shape (SW_EINVAL otherwise);
+ *   - SW_PREC_AUTO: if any pair saturates its int16 lanes, the whole batch is
+ *     recomputed in int32 into the scratch array and the saturated pairs'
+ *     results are replaced on the device (flag SW_FLAG_SATURATED); a per-pair
+ *     batch whose int16 lanes could saturate while no int32 per-pair shape
+ *     holds its longest query is refused with SW_EINVAL before any launch.
+ * stats (may be NULL) receives kernel_ms, total_ms, cells, n_rerun and the
+ * layout counters as sw_align_batch_ex reports them.
+ *
+ * The array is shared by every call on a device and keeps the last call's
+ * contents; the calls serialise on the library's per-device lock, so calls
+ * from several threads do not overlap (calls that did overlap on one device
+ * would race on it).  Errors: as sw_align_batch, plus SW_EINVAL for host
+ * inputs, n_pairs > SW_NOALLOC_MAX_PAIRS or a batch outside the device
+ * planner; out holds {0, -1, -1, 0} for every pair after SW_EINVAL from a
+ * residue or pair check.  Synchronous.
+ * ------------------------------------------------------------------------- */
+#define SW_NOALLOC_MAX_PAIRS 1048576
+int sw_align_batch_noalloc(const sw_batch *b, const sw_scoring *sc, sw_result *out,
+                           sw_stats *stats);
+
+/* ---------------------------------------------------------------------------
  * Autotuner.
  *
  * The planner picks, for each group of pairs, the lanes per alignment (16, 32

@@ -30,7 +30,8 @@ EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align"
             "sw_server_poll", "sw_server_drain", "sw_server_destroy", "sw_server_replay",
             "sw_autotune", "sw_tune_set", "sw_tune_get", "sw_align_batch_starts",
             "sw_align_batch_cigar", "sw_align_batch_global", "sw_align_batch_global_cigar",
-            "sw_align_ex"]
+            "sw_align_ex", "sw_align_batch_noalloc"]
+SW_NOALLOC_MAX_PAIRS = 1048576
 
 
 class NativeLibraryError(RuntimeError):
@@ -160,6 +161,8 @@ def load():
     lib.sw_align_batch_ex.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                       ctypes.POINTER(Options), ctypes.c_void_p,
                                       ctypes.POINTER(Stats)]
+    lib.sw_align_batch_noalloc.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
+                                           ctypes.c_void_p, ctypes.POINTER(Stats)]
     lib.sw_align_batch_starts.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.sw_align_batch_cigar.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
@@ -325,6 +328,31 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
     _check(lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
                                  out.ctypes.data, ctypes.byref(st)))
     return BatchOutput(out[:npairs], st.as_dict())
+
+
+def sw_align_batch_noalloc(query_res, query_off, ref_res, ref_off, pair_ref, matrix,
+                           gap_open: int, gap_extend: int, out, pair_query=None,
+                           precision: int = SW_PREC_AUTO) -> dict:
+    """The batch call that allocates nothing (library scratch array only).
+
+    Inputs are torch CUDA tensors as for ``sw_align_batch``; ``out`` is a
+    C-contiguous (n_pairs, 4) int32 CUDA tensor that receives the results on
+    the device.  Returns the call's statistics.
+    """
+    lib = load()
+    if not (_is_torch_cuda(ref_res)):
+        raise TypeError("sw_align_batch_noalloc takes device-resident (torch CUDA) inputs")
+    b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
+                                  precision)
+    import torch
+    if not (_is_torch_cuda(out) and out.dtype == torch.int32 and out.is_contiguous() and
+            tuple(out.shape) == (npairs, 4)):
+        raise ValueError("out must be a contiguous (n_pairs, 4) int32 CUDA tensor")
+    sc, M = make_scoring(matrix, gap_open, gap_extend)
+    st = Stats()
+    _check(lib.sw_align_batch_noalloc(ctypes.byref(b), ctypes.byref(sc),
+                                      out.data_ptr() if npairs else None, ctypes.byref(st)))
+    return st.as_dict()
 
 
 def sw_align_batch_starts(query_res, query_off, ref_res, ref_off, pair_ref, matrix,

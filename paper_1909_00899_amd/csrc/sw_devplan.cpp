@@ -52,14 +52,6 @@ constexpr int kDevPlanMinPairs = 4096;   // smaller batches: the host planner
 constexpr size_t kPairDirectLds = 24 * 1024;
 constexpr int64_t kI32Limit = 2147483647ll;
 
-// Layout of the plan buffer, in int32 words.
-constexpr int kPlanStats = 0;                       // 8 x u64: stats words
-constexpr int kPlanMeta = 16;                       // kMetaWords
-constexpr int kPlanHist = kPlanMeta + kMetaWords;                // kPlanBlocks x kPlanBins
-constexpr int kPlanOff = kPlanHist + kPlanBlocks * kPlanBins;     // kPlanBlocks x kPlanBins
-constexpr int kPlanTotals = kPlanOff + kPlanBlocks * kPlanBins;   // kPlanBins
-constexpr int kPlanOrder = kPlanTotals + kPlanBins;               // n_pairs
-constexpr int kPlanCleared = kPlanMeta + kMetaWords;              // words cleared per call
 
 // The (rows per lane, lanes) shape for query length m: the caller's forced
 // shape, else the autotuner's entry, else the smallest compiled shape that
@@ -522,6 +514,253 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     stats->graph_hits = es.graph_hits;
     stats->planner_used = 2;
     stats->row_pairs = rows ? hm[kMetaValid] : 0;
+  }
+  return SW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The same device plan with every buffer in a caller-given scratch region and
+// the results written straight into a device array: no allocation of any kind
+// (no device, pinned or heap memory), for callers that cannot allocate.
+
+namespace {
+
+struct NoallocRegions {
+  int32_t *plan;
+  PairInfo *pairs;
+  DevResult *r32;
+  int32_t *matrix;
+};
+
+NoallocRegions noalloc_regions(unsigned char *scr, int max_pairs) {
+  auto up = noalloc_align256;
+  NoallocRegions R;
+  size_t o = 0;
+  R.plan = (int32_t *)(scr + o);
+  o += up(((size_t)kPlanOrder + max_pairs) * sizeof(int32_t));
+  R.pairs = (PairInfo *)(scr + o);
+  o += up((size_t)max_pairs * sizeof(PairInfo) + 4096);
+  R.r32 = (DevResult *)(scr + o);
+  o += up((size_t)max_pairs * sizeof(DevResult));
+  R.matrix = (int32_t *)(scr + o);
+  return R;
+}
+
+// What one pass reports back (read from the plan words after it).
+struct NoallocPass {
+  int32_t meta[kMetaWords];
+  unsigned long long stats[8];
+  float kernel_ms = 0;
+  int seg = 0, lanes = 0;
+  bool rows = false;
+};
+
+#define NA_HIP(expr)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) {                                                 \
+      set_error("no-allocation batch: %s failed: %s", #expr, hipGetErrorString(e_)); \
+      return SW_EDEVICE;                                                    \
+    }                                                                       \
+  } while (0)
+
+// Reads the stats and meta words of the plan into P (synchronous).
+int noalloc_read_plan(const int32_t *plan, NoallocPass &P, hipStream_t st) {
+  NA_HIP(hipMemcpyAsync(P.stats, plan + kPlanStats, sizeof(P.stats), hipMemcpyDeviceToHost, st));
+  NA_HIP(hipMemcpyAsync(P.meta, plan + kPlanMeta, sizeof(P.meta), hipMemcpyDeviceToHost, st));
+  NA_HIP(hipStreamSynchronize(st));
+  return SW_OK;
+}
+
+// One planned pass at precision `prec` whose results go to `res` (n_pairs
+// entries).  m > 0: one query of m residues at q_off0; m == 0: a query per
+// pair.  check_rerun: before the alignment launch, refuse a per-pair batch
+// whose int16 lanes could saturate while no int32 per-pair shape holds its
+// longest query (the rerun could not be run).
+int noalloc_pass(const sw_batch *b, const Scoring &S, Context &C, const NoallocRegions &R,
+                 Prec prec, int m, int64_t q_off0, int64_t qbytes, int64_t rbytes,
+                 bool check_rerun, DevResult *res, NoallocPass &P) {
+  const hipStream_t st = C.stream;
+  const int np = b->n_pairs;
+  const bool single = m > 0;
+  ExecOptions eo;   // the planner's defaults, as sw_align_batch without options
+  int seg = 0, lanes = 16, pes = 0;
+  bool rows = false;
+  if (single) {
+    if (prec == PREC_I16X2 && pick_rowpair_seg(m, S.alpha, 0, seg)) {
+      rows = true;
+    } else if (!pick_direct_shape(prec, S.alpha, m, eo, seg, lanes)) {
+      set_error("no-allocation batch: no compiled shape holds a query of %d residues", m);
+      return SW_EINVAL;
+    }
+  }
+  int32_t *plan = R.plan;
+  int32_t *meta = plan + kPlanMeta;
+  unsigned long long *d_stats = (unsigned long long *)(plan + kPlanStats);
+  const size_t mat_bytes = sizeof(int32_t) * S.M.size();
+  NA_HIP(hipMemcpyAsync(R.matrix, S.M.data(), mat_bytes, hipMemcpyHostToDevice, st));
+  NA_HIP(launch_fill_u32((uint32_t *)plan, kPlanCleared, 0u, st));
+  NA_HIP(launch_check_residues(b->query_res, qbytes, S.alpha, meta + kMetaErrResidue, st));
+  NA_HIP(launch_check_residues(b->ref_res, rbytes, S.alpha, meta + kMetaErrResidue, st));
+  NA_HIP(launch_plan_count(np, single ? nullptr : b->query_off, b->n_queries, qbytes, b->ref_off,
+                           b->pair_query, b->pair_ref, b->n_refs, rbytes, m, q_off0, R.pairs, res,
+                           plan + kPlanHist, meta, d_stats, st));
+  if (!single) {
+    int rc = noalloc_read_plan(plan, P, st);
+    if (rc) return rc;
+    if (P.meta[kMetaErrResidue] || P.meta[kMetaErrPair] || P.meta[kMetaMaxM] <= 0) return SW_OK;
+    const int max_m = P.meta[kMetaMaxM];
+    if ((int64_t)max_m * S.max_s >= kI32Limit) {
+      set_error("no-allocation batch: a query of %d residues may overflow int32", max_m);
+      return SW_EOVERFLOW;
+    }
+    if (!pick_pair_shape(prec, S, max_m, eo, seg, lanes, pes)) {
+      set_error("no-allocation batch: no per-pair shape holds queries of %d residues", max_m);
+      return SW_EINVAL;
+    }
+    int s32 = 0, l32 = 0, e32 = 0;
+    if (check_rerun && prec == PREC_I16X2 && (int64_t)max_m * S.max_s >= eo.int16_cap &&
+        !pick_pair_shape(PREC_I32, S, max_m, eo, s32, l32, e32)) {
+      set_error("no-allocation batch: int16 lanes could saturate on queries of %d residues and "
+                "no int32 per-pair shape holds them for the rerun", max_m);
+      return SW_EINVAL;
+    }
+  }
+  KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.pairs = R.pairs;
+  a.query_res = b->query_res;
+  a.shared_q_off = q_off0;
+  a.shared_m = m;
+  a.alpha = S.alpha;
+  a.matrix = R.matrix;
+  a.gap_open = S.go;
+  a.gap_extend = S.ge;
+  a.last_chunk = 1;
+  a.sat_cap = eo.int16_cap;
+  a.results = res;
+  a.stats = d_stats;
+  a.order = plan + kPlanOrder;
+  a.plan_meta = meta;
+  a.ref_res = b->ref_res;
+  NA_HIP(launch_plan_total(plan + kPlanHist, plan + kPlanOff, plan + kPlanTotals, st));
+  NA_HIP(launch_plan_scatter(np, R.pairs, plan + kPlanTotals, plan + kPlanOff, plan + kPlanOrder,
+                             meta, st));
+  NA_HIP(hipEventRecord(C.ev0, st));
+  if (single) {
+    const int slots = rows ? kWave / 16 : (kWave / lanes) * (prec == PREC_I16X2 ? 2 : 1);
+    const int ntasks_max = (np + slots - 1) / slots;
+    const int grid = rows ? std::max(1, std::min(ntasks_max, C.num_cus * 16))
+                          : std::max(1, std::min((ntasks_max + kWavesPerGroup - 1) / kWavesPerGroup,
+                                                 C.num_cus * 2));
+    NA_HIP(rows ? launch_shared_rowpair(seg, a, grid, st)
+                : launch_shared_direct(prec, seg, lanes, a, grid, st));
+  } else {
+    const int slots = (64 / lanes) * (prec == PREC_I16X2 ? 2 : 1);
+    const int ntasks_max = (np + slots - 1) / slots;
+    const int grid = std::max(1, std::min(ntasks_max, C.num_cus * 16));
+    NA_HIP(launch_pair_direct(prec, seg, lanes, pes, a, grid, st));
+  }
+  NA_HIP(hipEventRecord(C.ev1, st));
+  if (prec == PREC_I16X2) NA_HIP(launch_count_flag(np, res, kFlagNeedsI32, meta + kMetaNeedsI32, st));
+  int rc = noalloc_read_plan(plan, P, st);
+  if (rc) return rc;
+  NA_HIP(hipEventElapsedTime(&P.kernel_ms, C.ev0, C.ev1));
+  P.seg = seg;
+  P.lanes = rows ? 16 : lanes;
+  P.rows = rows;
+  return SW_OK;
+}
+
+}  // namespace
+
+int run_device_plan_noalloc(const sw_batch *b, const Scoring &S, Context &C, unsigned char *scr,
+                            int max_pairs, sw_result *out, sw_stats *stats, double t0) {
+  const hipStream_t st = C.stream;
+  const int np = b->n_pairs;
+  if (b->device_resident && b->stream) {
+    NA_HIP(hipEventRecord(C.evx, (hipStream_t)b->stream));
+    NA_HIP(hipStreamWaitEvent(st, C.evx, 0));
+  }
+  const bool single = b->pair_query == nullptr || b->n_queries == 1;
+  // query 0's offsets, the query set's end and the reference set's end
+  int64_t hv[4];
+  NA_HIP(hipMemcpyAsync(hv, b->query_off, 16, hipMemcpyDeviceToHost, st));
+  NA_HIP(hipMemcpyAsync(hv + 2, b->query_off + b->n_queries, 8, hipMemcpyDeviceToHost, st));
+  NA_HIP(hipMemcpyAsync(hv + 3, b->ref_off + b->n_refs, 8, hipMemcpyDeviceToHost, st));
+  NA_HIP(hipStreamSynchronize(st));
+  const int64_t q_off0 = hv[0], qbytes = hv[2], rbytes = hv[3];
+  if (q_off0 < 0 || hv[1] < q_off0 || hv[1] > qbytes || hv[1] - q_off0 > kI32Limit || rbytes < 0) {
+    set_error("no-allocation batch: query or reference offsets are not nondecreasing");
+    return SW_EINVAL;
+  }
+  const int m = single ? (int)(hv[1] - q_off0) : 0;
+  const NoallocRegions R = noalloc_regions(scr, max_pairs);
+  DevResult *res = (DevResult *)out;
+  if (single && m > 0 && (int64_t)m * S.max_s >= kI32Limit) {
+    set_error("no-allocation batch: the query may overflow int32");
+    return SW_EOVERFLOW;
+  }
+  if (single && m > 512) {
+    set_error("no-allocation batch: one query of %d residues (at most 512)", m);
+    return SW_EINVAL;
+  }
+  const Prec prec = (b->precision == SW_PREC_AUTO && S.fits_i16) ? PREC_I16X2 : PREC_I32;
+  NoallocPass P1;
+  int rc = SW_OK;
+  if (single && m == 0) {
+    // no alignment runs; the count pass validates ids and residues and sets
+    // every result to {0, -1, -1, 0}
+    NA_HIP(launch_fill_u32((uint32_t *)R.plan, kPlanCleared, 0u, st));
+    NA_HIP(launch_check_residues(b->query_res, qbytes, S.alpha, R.plan + kPlanMeta + kMetaErrResidue, st));
+    NA_HIP(launch_check_residues(b->ref_res, rbytes, S.alpha, R.plan + kPlanMeta + kMetaErrResidue, st));
+    NA_HIP(launch_plan_count(np, nullptr, b->n_queries, qbytes, b->ref_off, b->pair_query,
+                             b->pair_ref, b->n_refs, rbytes, 0, q_off0, R.pairs, res,
+                             R.plan + kPlanHist, R.plan + kPlanMeta,
+                             (unsigned long long *)(R.plan + kPlanStats), st));
+    if ((rc = noalloc_read_plan(R.plan, P1, st))) return rc;
+  } else if ((rc = noalloc_pass(b, S, C, R, prec, m, q_off0, qbytes, rbytes, true, res, P1))) {
+    return rc;
+  }
+  if (P1.meta[kMetaErrResidue] || P1.meta[kMetaErrPair]) {
+    NA_HIP(launch_init_results(np, res, st));
+    NA_HIP(hipStreamSynchronize(st));
+    set_error(P1.meta[kMetaErrResidue] ? "a residue code is >= alphabet_size"
+                                       : "a pair refers to a query or reference out of range, or "
+                                         "offsets that are not nondecreasing");
+    return SW_EINVAL;
+  }
+  // exact int32 rerun: the whole batch once more in int32 into the scratch
+  // results, merged on the device into the pairs whose int16 lanes saturated
+  int n_rerun_launches = 0;
+  float kms2 = 0;
+  if (prec == PREC_I16X2 && P1.meta[kMetaNeedsI32]) {
+    NoallocPass P2;
+    if ((rc = noalloc_pass(b, S, C, R, PREC_I32, m, q_off0, qbytes, rbytes, false, R.r32, P2)))
+      return rc;
+    NA_HIP(launch_merge_rerun(np, R.r32, res, st));
+    NA_HIP(hipStreamSynchronize(st));
+    n_rerun_launches = P2.seg > 0 ? 1 : 0;
+    kms2 = P2.kernel_ms;
+  }
+  if (stats) {
+    stats->kernel_ms = (double)P1.kernel_ms + kms2;
+    stats->total_ms = now_ms() - t0;
+    stats->cells = (int64_t)P1.stats[5];
+    stats->padded_cells = (int64_t)P1.stats[3];
+    stats->n_launches = (P1.seg > 0 ? 1 : 0) + n_rerun_launches;
+    stats->n_rerun = prec == PREC_I16X2 ? P1.meta[kMetaNeedsI32] : 0;
+    stats->columns = (int64_t)P1.stats[0];
+    stats->record_events = (int64_t)P1.stats[2];
+    stats->seglen_max = P1.seg;
+    stats->planner_used = 2;
+    const int valid = P1.meta[kMetaValid];
+    if (P1.rows)
+      stats->row_pairs = valid;
+    else if (P1.lanes == 8)
+      stats->lanes8 = valid;
+    else if (P1.seg > 0)
+      stats->lanes_used[P1.lanes == 16 ? 0 : (P1.lanes == 32 ? 1 : 2)] = valid;
   }
   return SW_OK;
 }

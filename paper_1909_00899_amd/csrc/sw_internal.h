@@ -89,12 +89,22 @@ enum : int {
   kMetaErrResidue = 2,  // set if a residue code is >= alpha
   kMetaErrPair = 3,     // set if a pair's query / reference id or offsets are invalid
   kMetaMaxM = 4,        // largest query length of the runnable pairs
+  kMetaNeedsI32 = 5,    // int16 results that ask for the int32 rerun
   kMetaWords = 16
 };
 // Length bins of the planner's counting sort: bin = ceil(n / kBlock), the
 // last bin also takes every longer reference.
 constexpr int kPlanBins = 4096;
 constexpr int kPlanBlocks = 32;   // workgroups of the planner's count and place passes
+
+// Layout of the device planner's plan buffer, in int32 words.
+constexpr int kPlanStats = 0;                                     // 8 x u64: stats words
+constexpr int kPlanMeta = 16;                                     // kMetaWords
+constexpr int kPlanHist = kPlanMeta + kMetaWords;                 // kPlanBlocks x kPlanBins
+constexpr int kPlanOff = kPlanHist + kPlanBlocks * kPlanBins;     // kPlanBlocks x kPlanBins
+constexpr int kPlanTotals = kPlanOff + kPlanBlocks * kPlanBins;   // kPlanBins
+constexpr int kPlanOrder = kPlanTotals + kPlanBins;               // n_pairs
+constexpr int kPlanCleared = kPlanMeta + kMetaWords;              // words cleared per call
 
 // Host-side launchers (defined in sw_kernels.hip).
 enum Prec { PREC_I16X2 = 0, PREC_I32 = 1 };
@@ -184,6 +194,12 @@ hipError_t launch_pair_rowpair(int seg, int lanes, bool chunked, const KArgs &a,
 
 // Sets every result to {0, -1, -1, 0}.
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);
+// *count += the entries of r[0..n) with a flag bit of `mask`.
+hipError_t launch_count_flag(int n, const DevResult *r, uint32_t mask, int32_t *count,
+                             hipStream_t st);
+// out[k] = r32[k] with flags kFlagSaturated for every k whose out[k] has
+// kFlagNeedsI32 (the int32 rerun's results merged on the device).
+hipError_t launch_merge_rerun(int n, const DevResult *r32, DevResult *out, hipStream_t st);
 
 // dst segment t = the dst_off[t+1] - dst_off[t] bytes of src from src_off[t]
 // on, reversed (offsets validated by the host; n segments).

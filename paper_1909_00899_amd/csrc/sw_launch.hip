@@ -274,6 +274,28 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(uint32_t *p, int64_t n, u
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) p[k] = v;
 }
+// *count += the results that carry a flag of `mask` (one atomic per
+// wavefront that saw one).
+__global__ __launch_bounds__(256) void count_flag_kernel(int n, const DevResult *r, uint32_t mask,
+                                                         int32_t *count) {
+  const int stride = gridDim.x * blockDim.x;
+  int c = 0;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+    c += (r[k].flags & mask) != 0 ? 1 : 0;
+  for (int d = 1; d < kWave; d <<= 1) c += __shfl_xor(c, d);
+  if (c != 0 && (threadIdx.x & 63) == 0) atomicAdd(count, c);
+}
+// out[k] = the int32 result r32[k] with SW_FLAG_SATURATED for every pair
+// whose int16 lanes asked for the rerun.
+__global__ __launch_bounds__(256) void merge_rerun_kernel(int n, const DevResult *r32,
+                                                          DevResult *out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n && (out[k].flags & kFlagNeedsI32)) {
+    DevResult v = r32[k];
+    v.flags = kFlagSaturated;
+    out[k] = v;
+  }
+}
 __global__ __launch_bounds__(256) void init_results_kernel(int n, DevResult *r) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) {
@@ -295,6 +317,21 @@ hipError_t launch_reverse_segments(int n, const uint8_t *src, const int64_t *src
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(dev::init_results_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_flag(int n, const DevResult *r, uint32_t mask, int32_t *count,
+                             hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = std::min((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(dev::count_flag_kernel, dim3(grid), dim3(256), 0, st, n, r, mask, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_merge_rerun(int n, const DevResult *r32, DevResult *out, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dev::merge_rerun_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, r32,
+                     out);
   return hipGetLastError();
 }
 

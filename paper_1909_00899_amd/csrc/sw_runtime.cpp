@@ -162,6 +162,8 @@ int Context::init(int dev) {
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
   HIPCHK(hipEventCreateWithFlags(&evx, hipEventDisableTiming));
+  const int rc = noalloc_setup(dev);
+  if (rc) return rc;
   inited = true;
   return SW_OK;
 }

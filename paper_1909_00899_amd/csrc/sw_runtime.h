@@ -35,9 +35,24 @@ struct HostBuf {
   template <class T> T *as() const { return (T *)p; }
 };
 
+// alpha*alpha matrix entries in fixed storage (preparing a scoring scheme
+// touches no heap, which the no-allocation batch call relies on).
+struct MatrixWords {
+  int v[swk::kMaxAlpha * swk::kMaxAlpha];
+  size_t n = 0;
+  void assign(const int *b, const int *e) {
+    n = (size_t)(e - b);
+    for (size_t k = 0; k < n; ++k) v[k] = b[k];
+  }
+  const int *data() const { return v; }
+  size_t size() const { return n; }
+  const int *begin() const { return v; }
+  const int *end() const { return v + n; }
+};
+
 struct Scoring {
   int alpha = 0;
-  std::vector<int> M;   // alpha*alpha, [query code][ref code]
+  MatrixWords M;        // alpha*alpha, [query code][ref code]
   int go = 0, ge = 0;   // ge already min(ge, go)
   int max_s = 0;        // max(0, max entry)
   bool fits_i16 = false;
@@ -231,6 +246,26 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
 // Rows per virtual lane of the device planner's row-pair layout for a query of
 // m residues (false if no compiled shape holds it in one chunk).
 bool rowpair_shape(int m, int alpha, int &seg);
+
+// The no-allocation batch call's scratch region for up to max_pairs pairs:
+// the plan words, PairInfo records, the int32 rerun's results and the
+// matrix, each 256-byte aligned.
+constexpr size_t noalloc_align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t noalloc_scratch_bytes(size_t max_pairs) {
+  return noalloc_align256(((size_t)swk::kPlanOrder + max_pairs) * sizeof(int32_t)) +
+         noalloc_align256(max_pairs * sizeof(swk::PairInfo) + 4096) +
+         noalloc_align256(max_pairs * sizeof(swk::DevResult)) +
+         noalloc_align256(sizeof(int32_t) * swk::kMaxAlpha * swk::kMaxAlpha);
+}
+// sw_align_batch's device plan with every buffer in `scr` (a region of
+// noalloc_scratch_bytes(max_pairs) bytes of device memory) and the results
+// written to the device array `out`: allocates nothing.  The caller holds
+// C.mu and has checked that b is device-resident with at most max_pairs pairs.
+int run_device_plan_noalloc(const sw_batch *b, const Scoring &S, Context &C, unsigned char *scr,
+                            int max_pairs, sw_result *out, sw_stats *stats, double t0);
+// Looks up the scratch array's device address on the current device (once
+// per device; the library's init calls it).  Defined beside the array.
+int noalloc_setup(int device);
 
 // Full batch semantics (int16 pass + int32 rerun) on prepared input.
 int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecOptions &opt,

@@ -215,3 +215,29 @@ def test_global_cigar_rejects_bad_arguments(lib):
     assert off[0] == 0
     assert lib.sw_align_batch_global_cigar(ctypes.byref(b), ctypes.byref(sc), 4, None, None,
                                            None, 0, off.ctypes.data) == api.SW_EINVAL
+
+
+def test_noalloc_rejects_bad_arguments(lib):
+    M = np.eye(4, dtype=np.int32)
+    sc, keep = _sc(M)
+    q = np.array([0, 1, 2], dtype=np.uint8)
+    off = np.array([0, 3], dtype=np.int64)
+    pr = np.zeros(1, dtype=np.int32)
+    out = np.zeros((1, 4), dtype=np.int32)
+    st = api.Stats()
+    b = api.Batch(1, q.ctypes.data, off.ctypes.data, 1, q.ctypes.data, off.ctypes.data, 1,
+                  None, pr.ctypes.data, api.SW_PREC_AUTO, 0, None)
+    # NULL batch or out; host-resident inputs; bad precision; too many pairs:
+    # all refused on the host, before any device is touched
+    assert lib.sw_align_batch_noalloc(None, ctypes.byref(sc), out.ctypes.data, None) == api.SW_EINVAL
+    assert lib.sw_align_batch_noalloc(ctypes.byref(b), ctypes.byref(sc), None, None) == api.SW_EINVAL
+    assert lib.sw_align_batch_noalloc(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data,
+                                      ctypes.byref(st)) == api.SW_EINVAL
+    b.device_resident = 1
+    b.precision = 7
+    assert lib.sw_align_batch_noalloc(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data, None) == api.SW_EINVAL
+    b.precision = api.SW_PREC_AUTO
+    b.n_pairs = api.SW_NOALLOC_MAX_PAIRS + 1
+    assert lib.sw_align_batch_noalloc(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data, None) == api.SW_EINVAL
+    b.n_pairs = 0
+    assert lib.sw_align_batch_noalloc(ctypes.byref(b), ctypes.byref(sc), out.ctypes.data, None) == api.SW_OK
