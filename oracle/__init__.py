@@ -28,8 +28,9 @@ adopted where the paper is silent are stated in each docstring:
 
 Start cells (``start_cell``, ``start_batch``): the end cell of the same
 recurrence on the reversed prefixes that end at the reported end cell.
-Paths (``path``) and end-to-end scores (``endtoend``: global and semi-global,
-not in the paper) are plain maxima over chains of aligned pairs.
+Paths (``path``) and end-to-end scores (``endtoend``: global, semi-global in
+either direction and overlap, not in the paper) are plain maxima over chains
+of aligned pairs.
 
 Parity status: pinned (brute-force enumeration of all local alignments on tiny
 inputs, a hand-computed worked example, closed-form special cases and
@@ -314,13 +315,17 @@ def path_score(query, ref, matrix, gap_open: int, gap_extend: int, start, runs) 
 
 
 def endtoend(query, ref, matrix, gap_open: int, gap_extend: int, mode: int) -> Tuple[int, int, int]:
-    """(score, query_end, ref_end) of the best global (mode 0) or semi-global
-    (mode 1: the query end to end, reference ends free) alignment, from
+    """(score, query_end, ref_end) of the best end-to-end alignment, from
     ``oracle_endtoend`` in sw_oracle.c (plain maxima over the chains of aligned
     pairs; gap runs priced with min(gap_extend, gap_open)).  Not in the paper,
-    whose problem is local alignment.  query_end is always m - 1; ref_end is
-    n - 1 in mode 0 and, in mode 1, the smallest reference prefix end holding
-    an optimal alignment (-1: the empty prefix)."""
+    whose problem is local alignment.  Modes: 0 global (both sequences end to
+    end; ends (m - 1, n - 1)); 1 semi-global (the query end to end, reference
+    ends free; query_end m - 1 and the smallest reference prefix end holding an
+    optimal alignment, -1 for the empty prefix); 2 the other semi-global (the
+    reference end to end, query ends free; ref_end n - 1 and the smallest
+    query prefix end); 3 overlap (the residues before the first pair of one
+    sequence free, likewise after the last pair; the end on the last query
+    row or the last reference column, the smallest (ref_end, query_end))."""
     q, r = _u8(query), _u8(ref)
     M = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
     lib = _load()
@@ -356,31 +361,35 @@ def endtoend_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
 
 
 def endtoend_path(query, ref, matrix, gap_open: int, gap_extend: int, mode: int, end=None):
-    """(ref_start, runs) of the global (mode 0) or semi-global (mode 1)
-    alignment reported by ``endtoend``: walking back from its end, each
-    predecessor is the largest (ref, query) element -- aligned pair or the
-    virtual start pair, (-1, -1) globally, (v, -1) for a free reference prefix
-    r[0..v] -- on an optimal chain; between two elements D is written before
-    I.  ref_start is 0 globally, v + 1 semi-globally.  From
-    ``oracle_endtoend_path`` in sw_oracle.c (plain maxima over the chains)."""
+    """(query_start, ref_start, runs) of the end-to-end alignment (modes as in
+    ``endtoend``) reported by ``endtoend`` (or ending at ``end`` = (score,
+    query_end, ref_end)): walking back from its end, each predecessor is the
+    largest (ref, query) element -- aligned pair or virtual start element:
+    (-1, -1) globally, (v, -1) for a free reference prefix r[0..v] in modes 1
+    and 3, (-1, w) for a free query prefix q[0..w] in modes 2 and 3 -- on an
+    optimal chain; between two elements D is written before I.  The starts are
+    the start element's coordinates plus one.  From ``oracle_endtoend_path`` in
+    sw_oracle.c (plain maxima over the chains)."""
     q, r = _u8(query), _u8(ref)
     M = np.ascontiguousarray(np.asarray(matrix, dtype=np.int32))
     s, qe, re_ = endtoend(q, r, M, gap_open, gap_extend, mode) if end is None else end
     cap = q.size + r.size + 2
     ops = np.zeros(cap, dtype=np.uint32)
-    rs = ctypes.c_int64(0)
+    qs, rs = ctypes.c_int64(0), ctypes.c_int64(0)
     lib = _load()
     lib.oracle_endtoend_path.restype = ctypes.c_int64
     lib.oracle_endtoend_path.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
-                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
-                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+                                         ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                         ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int64)]
     n = lib.oracle_endtoend_path(q.ctypes.data if q.size else None, q.size,
                                  r.ctypes.data if r.size else None, r.size, M.ctypes.data,
-                                 M.shape[0], int(gap_open), int(gap_extend), int(mode), int(re_),
-                                 int(s), ops.ctypes.data, cap, ctypes.byref(rs))
+                                 M.shape[0], int(gap_open), int(gap_extend), int(mode), int(qe),
+                                 int(re_), int(s), ops.ctypes.data, cap, ctypes.byref(qs),
+                                 ctypes.byref(rs))
     if n < 0:
         raise ValueError("oracle_endtoend_path failed (%d)" % n)
-    return int(rs.value), [(int(v >> 4), _OPS[int(v & 15)]) for v in ops[:n]]
-
+    return int(qs.value), int(rs.value), [(int(v >> 4), _OPS[int(v & 15)]) for v in ops[:n]]

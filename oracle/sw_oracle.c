@@ -257,37 +257,62 @@ int64_t oracle_path(const uint8_t *q, const uint8_t *r, const int32_t *Mx, int32
  * of L skipped residues costing go + (L - 1) * min(ge, go) (Gotoh's
  * recurrences reopen a gap rather than extend it at a higher cost).  Between
  * two pairs, before the first and after the last, the skipped reference
- * residues and the skipped query residues are one run each.
+ * residues and the skipped query residues are one run each.  Which of the
+ * runs before the first pair and after the last one are charged depends on
+ * the mode:
  *
  * mode 0, global: every residue of both sequences is aligned or skipped at a
  *   cost; the chain may be empty (both sequences skipped whole).
- * mode 1, semi-global (fitting): the query end to end as in mode 0, the
- *   reference residues before the first pair and after the last pair are
- *   skipped for free.  End: the smallest reference prefix end a (-1 for the
- *   empty prefix) such that the best such alignment of the query inside
- *   r[0..a] -- counting reference residues after its last pair up to a as a
- *   gap run -- reaches the score.
+ * mode 1, semi-global (the query fitted into the reference): the query end to
+ *   end as in mode 0, the reference residues before the first pair and after
+ *   the last pair skipped for free.
+ * mode 2, semi-global the other way (the reference fitted into the query):
+ *   the reference end to end, the query residues before the first and after
+ *   the last pair free.
+ * mode 3, overlap (free end gaps): before the first pair the skipped residues
+ *   of one of the two sequences are free, those of the other cost a run, and
+ *   likewise after the last pair -- a dovetail or containment of the two
+ *   sequences; the empty chain scores 0.
  *
- * Computed as plain maxima over the chains, no affine recurrence:
+ * The best alignment that ends at a cell (a, b) -- residues r[0..a] and
+ * q[0..b] consumed, those after the last pair up to (a, b) counted as runs --
+ * is computed as plain maxima over the chains, no affine recurrence:
  *   W(x, y) = S[q_y][r_x] + best(x - 1, y - 1)    (the best chain ending with pair (x, y))
  *   best(a, b) = max( lead(a, b),  max over x <= a, y <= b of W(x, y) - g(a - x) - g(b - y) )
  * with lead(a, b) the chain before any pair -- residues r[0..a] and q[0..b]
- * skipped: -g(a + 1) - g(b + 1) in mode 0, -g(b + 1) in mode 1 (g(0) = 0) --
- * and best(-1, -1) = 0, best(a, -1) = lead(a, -1), best(-1, b) = lead(-1, b).
- * The inner maximum is taken over y first, then x (one pass per row and one
- * per column), an exact regrouping of the same maximum.  Global score:
- * best(n - 1, m - 1).  Semi-global score: max over a in -1..n-1 of best(a, m - 1).
+ * skipped: -g(a + 1) - g(b + 1) in mode 0, -g(b + 1) in mode 1, -g(a + 1) in
+ * mode 2, -min(g(a + 1), g(b + 1)) in mode 3 (g(0) = 0) -- and best(a, -1) =
+ * lead(a, -1), best(-1, b) = lead(-1, b).  The inner maximum is taken over y
+ * first, then x (one pass per row and one per column), an exact regrouping
+ * of the same maximum.
+ *
+ * The alignment ends at a cell where the uncharged sequence ends are used up:
+ * mode 0 at (n - 1, m - 1); mode 1 at (a, m - 1), a in -1..n-1 (the
+ * reference after a is free); mode 2 at (n - 1, b), b in -1..m-1; mode 3 at
+ * either kind.  The score is the largest best() over the mode's end cells and
+ * the reported end the first of them in (ref_end, query_end) order that
+ * reaches it.
  */
 static int64_t gcost(int64_t L, int64_t go, int64_t ge) { return L <= 0 ? 0 : go + (L - 1) * ge; }
 
-int oracle_endtoend(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
-                    const int32_t *Mx, int32_t alpha, int64_t go, int64_t ge, int32_t mode,
-                    oracle_result *out)
+static int64_t lead_cost(int32_t mode, int64_t a, int64_t b, int64_t go, int64_t ge)
 {
-    if (m < 0 || n < 0 || alpha <= 0 || (mode != 0 && mode != 1)) return -1;
-    if (ge > go) ge = go;
+    const int64_t ga = gcost(a + 1, go, ge), gb = gcost(b + 1, go, ge);
+    switch (mode) {
+    case 0: return -ga - gb;
+    case 1: return -gb;
+    case 2: return -ga;
+    default: return ga < gb ? -ga : -gb;
+    }
+}
+
+/* best(a, b) over (a, b) in -1..n-1 x -1..m-1 (stored with a +1 offset) and
+ * W(x, y) of every pair; the caller frees both. */
+static int endtoend_tables(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
+                           const int32_t *Mx, int32_t alpha, int64_t go, int64_t ge, int32_t mode,
+                           int64_t **best_out, int64_t **W_out)
+{
     const int64_t NEG = INT64_MIN / 4;
-    /* best and W over (a, b) in -1..n-1 x -1..m-1, stored with a +1 offset */
     const int64_t R = n + 1, C = m + 1;
     int64_t *best = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
     int64_t *W = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
@@ -296,8 +321,7 @@ int oracle_endtoend(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
 #define IX(a, b) (((a) + 1) * C + ((b) + 1))
     for (int64_t a = -1; a < n; ++a) {
         for (int64_t b = -1; b < m; ++b) {
-            const int64_t lead = mode == 0 ? -gcost(a + 1, go, ge) - gcost(b + 1, go, ge)
-                                           : -gcost(b + 1, go, ge);
+            const int64_t lead = lead_cost(mode, a, b, go, ge);
             if (a < 0 || b < 0) {
                 W[IX(a, b)] = NEG;
                 G[IX(a, b)] = NEG;
@@ -315,78 +339,90 @@ int oracle_endtoend(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
             best[IX(a, b)] = v;
         }
     }
-    if (mode == 0) {
-        out->score = best[IX(n - 1, m - 1)];
-        out->query_end = m - 1;
-        out->ref_end = n - 1;
-    } else {
-        int64_t s = NEG, at = -1;
-        for (int64_t a = -1; a < n; ++a)
-            if (best[IX(a, m - 1)] > s) { s = best[IX(a, m - 1)]; at = a; }
-        out->score = s;
-        out->query_end = m - 1;
-        out->ref_end = at;
-    }
 #undef IX
-    free(best); free(W); free(G);
+    free(G);
+    *best_out = best;
+    *W_out = W;
+    return 0;
+}
+
+int oracle_endtoend(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
+                    const int32_t *Mx, int32_t alpha, int64_t go, int64_t ge, int32_t mode,
+                    oracle_result *out)
+{
+    if (m < 0 || n < 0 || alpha <= 0 || mode < 0 || mode > 3) return -1;
+    if (ge > go) ge = go;
+    const int64_t NEG = INT64_MIN / 4;
+    const int64_t C = m + 1;
+    int64_t *best = NULL, *W = NULL;
+    if (endtoend_tables(q, m, r, n, Mx, alpha, go, ge, mode, &best, &W)) return -1;
+#define IX(a, b) (((a) + 1) * C + ((b) + 1))
+    /* the mode's end cells in (ref_end, query_end) order; strict > keeps the first */
+    int64_t s = NEG, ea = -1, eb = -1;
+    if (mode == 0) {
+        s = best[IX(n - 1, m - 1)];
+        ea = n - 1;
+        eb = m - 1;
+    }
+    if (mode == 1 || mode == 3) {
+        const int64_t last = mode == 1 ? n - 1 : n - 2;   /* mode 3: (n - 1, .) below */
+        for (int64_t a = -1; a <= last; ++a)
+            if (best[IX(a, m - 1)] > s) { s = best[IX(a, m - 1)]; ea = a; eb = m - 1; }
+    }
+    if (mode == 2 || mode == 3) {
+        for (int64_t b = -1; b < m; ++b)
+            if (best[IX(n - 1, b)] > s) { s = best[IX(n - 1, b)]; ea = n - 1; eb = b; }
+    }
+    out->score = s;
+    out->query_end = eb;
+    out->ref_end = ea;
+#undef IX
+    free(best); free(W);
     return 0;
 }
 
 /*
- * Path of an end-to-end alignment (mode 0 global, 1 semi-global as in
- * oracle_endtoend), from its end (ref_end, m - 1) back to its start: the
- * chain's elements are the aligned pairs plus a virtual start pair -- (-1, -1)
- * in mode 0, any (v, -1) with v >= -1 in mode 1 (the free reference prefix
- * r[0..v]) -- of value 0.  Walking back from the end, each predecessor is the
- * largest (ref index, then query index) element, virtual ones included, on an
- * optimal chain; between two elements (and after the last pair) the skipped
- * reference residues (D) are written before the skipped query residues (I).
- * Runs go to ops[] as (len << 4 | op), op 0 M, 1 I, 2 D, in forward order;
- * *ref_start receives v + 1 for the virtual start (0 in mode 0).  Returns the
- * number of runs, -1 on bad arguments / allocation failure / too small a cap,
- * -2 if `score` is not the mode's optimum at that end.
+ * Path of an end-to-end alignment (modes as in oracle_endtoend), from its end
+ * cell (ref_end, query_end) back to its start: the chain's elements are the
+ * aligned pairs plus a virtual start element of value 0 -- (-1, -1) in mode 0;
+ * any (v, -1), v >= -1, in modes 1 and 3 (the free reference prefix r[0..v]);
+ * any (-1, w), w >= -1, in modes 2 and 3 (the free query prefix q[0..w]).
+ * Between two consecutive elements, and from the last one to the end cell,
+ * the skipped residues of each sequence are one run.  Walking back from the
+ * end, each predecessor is the largest (ref index, then query index) element,
+ * virtual ones included, on an optimal chain; between two elements (and
+ * after the last pair) the skipped reference residues (D) are written before
+ * the skipped query residues (I).  Runs go to ops[] as (len << 4 | op), op 0
+ * M, 1 I, 2 D, in forward order; *ref_start / *query_start receive the start
+ * element's coordinates plus one.  Returns the number of runs, -1 on bad
+ * arguments / allocation failure / too small a cap, -2 if `score` is not the
+ * mode's best at that end.
  */
 int64_t oracle_endtoend_path(const uint8_t *q, int64_t m, const uint8_t *r, int64_t n,
                              const int32_t *Mx, int32_t alpha, int64_t go, int64_t ge,
-                             int32_t mode, int64_t ref_end, int64_t score, uint32_t *ops,
-                             int64_t cap, int64_t *ref_start)
+                             int32_t mode, int64_t query_end, int64_t ref_end, int64_t score,
+                             uint32_t *ops, int64_t cap, int64_t *query_start, int64_t *ref_start)
 {
-    if (m < 0 || n < 0 || alpha <= 0 || (mode != 0 && mode != 1)) return -1;
-    if (ref_end < -1 || ref_end >= n || (mode == 0 && ref_end != n - 1)) return -1;
+    if (m < 0 || n < 0 || alpha <= 0 || mode < 0 || mode > 3) return -1;
+    if (ref_end < -1 || ref_end >= n || query_end < -1 || query_end >= m) return -1;
+    {
+        const int on_q = query_end == m - 1, on_r = ref_end == n - 1;
+        const int ok = mode == 0 ? (on_q && on_r) : mode == 1 ? on_q : mode == 2 ? on_r : (on_q || on_r);
+        if (!ok) return -1;
+    }
     if (ge > go) ge = go;
     const int64_t NEG = INT64_MIN / 4;
-    const int64_t R = n + 1, C = m + 1;
-    int64_t *best = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
-    int64_t *W = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
-    int64_t *G = (int64_t *)malloc((size_t)(R * C) * sizeof(int64_t));
+    const int64_t C = m + 1;
+    int64_t *best = NULL, *W = NULL;
+    if (endtoend_tables(q, m, r, n, Mx, alpha, go, ge, mode, &best, &W)) return -1;
     char *rev = (char *)malloc((size_t)(n + m + 2));
-    if (!best || !W || !G || !rev) { free(best); free(W); free(G); free(rev); return -1; }
+    if (!rev) { free(best); free(W); return -1; }
 #define IX(a, b) (((a) + 1) * C + ((b) + 1))
-    for (int64_t a = -1; a < n; ++a) {
-        for (int64_t b = -1; b < m; ++b) {
-            const int64_t lead = mode == 0 ? -gcost(a + 1, go, ge) - gcost(b + 1, go, ge)
-                                           : -gcost(b + 1, go, ge);
-            if (a < 0 || b < 0) {
-                W[IX(a, b)] = NEG;
-                G[IX(a, b)] = NEG;
-                best[IX(a, b)] = lead;
-                continue;
-            }
-            W[IX(a, b)] = (int64_t)Mx[(int)q[b] * alpha + (int)r[a]] + best[IX(a - 1, b - 1)];
-            int64_t g = NEG;
-            for (int64_t y = 0; y <= b; ++y) g = max2(g, W[IX(a, y)] - gcost(b - y, go, ge));
-            G[IX(a, b)] = g;
-            int64_t v = lead;
-            for (int64_t x = 0; x <= a; ++x)
-                if (G[IX(x, b)] > NEG) v = max2(v, G[IX(x, b)] - gcost(a - x, go, ge));
-            best[IX(a, b)] = v;
-        }
-    }
     int64_t rc = 0, nrev = 0;
-    if (best[IX(ref_end, m - 1)] != score) rc = -2;
+    if (best[IX(ref_end, query_end)] != score) rc = -2;
     /* walk: the current position (px, py) lies just before the element found
      * last (the end, then each aligned pair); target = best(px, py) */
-    int64_t px = ref_end, py = m - 1, target = score, vstart = -1;
+    int64_t px = ref_end, py = query_end, target = score, sx = -1, sy = -1;
     while (rc == 0) {
         int64_t fx = NEG, fy = NEG;
         /* real pairs, largest x first, then largest y */
@@ -397,18 +433,24 @@ int64_t oracle_endtoend_path(const uint8_t *q, int64_t m, const uint8_t *r, int6
                     fx = x; fy = y;
                     break;
                 }
-        /* a virtual start element beats a real pair only with a larger x */
-        int64_t vx = NEG;
-        if (mode == 0) {
-            if (-gcost(px + 1, go, ge) - gcost(py + 1, go, ge) == target) vx = -1;
-        } else {
+        /* the largest virtual start element on an optimal chain */
+        int64_t vx = NEG, vy = NEG;
+        if (mode == 1 || mode == 3)
             for (int64_t v = px; v >= -1 && vx == NEG; --v)
-                if (-gcost(px - v, go, ge) - gcost(py + 1, go, ge) == target) vx = v;
-        }
+                if (-gcost(px - v, go, ge) - gcost(py + 1, go, ge) == target) { vx = v; vy = -1; }
+        if ((mode == 2 || mode == 3) && (vx == NEG || vx < 0))
+            for (int64_t w = py; w >= -1; --w)
+                if (-gcost(px + 1, go, ge) - gcost(py - w, go, ge) == target) {
+                    if (vx == NEG || w > vy) { vx = -1; vy = w; }
+                    break;
+                }
+        if (mode == 0 && -gcost(px + 1, go, ge) - gcost(py + 1, go, ge) == target) { vx = -1; vy = -1; }
+        /* a virtual element (x = -1, or y = -1) beats a real pair only with a larger x */
         if (vx != NEG && (fx == NEG || vx > fx)) {
-            for (int64_t k = 0; k < py - (-1); ++k) rev[nrev++] = 'I';
+            for (int64_t k = 0; k < py - vy; ++k) rev[nrev++] = 'I';
             for (int64_t k = 0; k < px - vx; ++k) rev[nrev++] = 'D';
-            vstart = vx;
+            sx = vx;
+            sy = vy;
             break;
         }
         if (fx == NEG) { rc = -2; break; }
@@ -428,7 +470,8 @@ int64_t oracle_endtoend_path(const uint8_t *q, int64_t m, const uint8_t *r, int6
         if (cnt >= cap) { rc = -1; break; }
         ops[cnt++] = (uint32_t)(len << 4) | (c == 'M' ? 0u : (c == 'I' ? 1u : 2u));
     }
-    if (ref_start) *ref_start = vstart + 1;
-    free(best); free(W); free(G); free(rev);
+    if (ref_start) *ref_start = sx + 1;
+    if (query_start) *query_start = sy + 1;
+    free(best); free(W); free(rev);
     return rc ? rc : cnt;
 }

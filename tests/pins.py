@@ -143,16 +143,28 @@ def brute_force_path(q, r, M, go: int, ge: int):
     return runs
 
 
-def brute_force_endtoend(q, r, M, go: int, ge: int, mode: int):
-    """(score, query_end, ref_end) of the best global (mode 0) or semi-global
-    (mode 1: query end to end, reference ends free) alignment by enumerating
-    every chain of index pairs, the empty chain included, and pricing every
-    gap run from the definition (runs cost g(L) with the extension clamped to
-    the opening cost).  Mode 1's ref_end: the smallest prefix end a whose best
-    alignment -- the reference residues after the last pair up to a counted as
-    a gap run -- reaches the score.  Tiny inputs only."""
-    m, n = len(q), len(r)
-    ge = min(ge, go)
+def _endtoend_lead(mode: int, a: int, b: int, go: int, ge: int) -> int:
+    """Cost of skipping r[0..a] and q[0..b] before the first pair (the chain
+    so far empty): both charged (0), the query only (1), the reference only
+    (2), the cheaper of the two (3)."""
+    ga, gb = gap_cost(a + 1, go, ge), gap_cost(b + 1, go, ge)
+    return (ga + gb, gb, ga, min(ga, gb))[mode]
+
+
+def _endtoend_ends(mode: int, m: int, n: int):
+    """The mode's end cells (ref_end, query_end) in (ref_end, query_end) order:
+    where the ends that are charged are used up."""
+    cells = set()
+    if mode == 0:
+        cells.add((n - 1, m - 1))
+    if mode in (1, 3):
+        cells.update((a, m - 1) for a in range(-1, n))
+    if mode in (2, 3):
+        cells.update((n - 1, b) for b in range(-1, m))
+    return sorted(cells)
+
+
+def _chains(n: int, m: int):
     chains = [[]]
 
     def grow(chain):
@@ -164,63 +176,93 @@ def brute_force_endtoend(q, r, M, go: int, ge: int, mode: int):
                 grow(c)
 
     grow([])
+    return chains
+
+
+def brute_force_endtoend(q, r, M, go: int, ge: int, mode: int):
+    """(score, query_end, ref_end) of the best end-to-end alignment by
+    enumerating every chain of index pairs, the empty chain included, and
+    every end cell of the mode, pricing every gap run from the definition
+    (runs cost g(L) with the extension clamped to the opening cost).  Modes:
+    0 global, 1 semi-global (query end to end, reference ends free), 2 the
+    reverse (reference end to end, query ends free), 3 overlap.  The value of
+    a chain at an end cell (a, b) counts the runs before its first pair as the
+    mode charges them and the residues after its last pair up to (a, b) as a
+    run in each sequence; the reported end is the first end cell in
+    (ref_end, query_end) order that reaches the best value.  Tiny inputs
+    only."""
+    m, n = len(q), len(r)
+    ge = min(ge, go)
+    ends = _endtoend_ends(mode, m, n)
     best_at = {}
-    for c in chains:
+    for c in _chains(n, m):
         s = sum(int(M[q[j]][r[i]]) for i, j in c)
         for (i, j), (i2, j2) in zip(c, c[1:]):
             s -= gap_cost(i2 - i - 1, go, ge) + gap_cost(j2 - j - 1, go, ge)
-        fi, fj = c[0] if c else (n, m)         # first pair (or past the end)
-        li, lj = c[-1] if c else (-1, -1)      # last pair (or before the start)
-        if mode == 0:
+        for a, b in ends:
             if c:
-                s -= gap_cost(fi, go, ge) + gap_cost(fj, go, ge)
-                s -= gap_cost(n - 1 - li, go, ge) + gap_cost(m - 1 - lj, go, ge)
+                (fi, fj), (li, lj) = c[0], c[-1]
+                if a < li or b < lj:
+                    continue
+                v = s - _endtoend_lead(mode, fi - 1, fj - 1, go, ge) - \
+                    gap_cost(a - li, go, ge) - gap_cost(b - lj, go, ge)
             else:
-                s -= gap_cost(n, go, ge) + gap_cost(m, go, ge)
-            best_at[n - 1] = max(best_at.get(n - 1, s), s)
-        else:
-            s -= (gap_cost(fj, go, ge) + gap_cost(m - 1 - lj, go, ge)) if c else gap_cost(m, go, ge)
-            for a in range(li if c else -1, n):
-                v = s - (gap_cost(a - li, go, ge) if c else 0)
-                best_at[a] = max(best_at.get(a, v), v)
+                v = -_endtoend_lead(mode, a, b, go, ge)
+            best_at[(a, b)] = max(best_at.get((a, b), v), v)
     score = max(best_at.values())
-    end = min(a for a, v in best_at.items() if v == score)
-    return score, m - 1, end
+    a, b = min(e for e, v in best_at.items() if v == score)
+    return score, b, a
+
+
+def overlap_score_direct(q, r, M, go: int, ge: int) -> int:
+    """Overlap score straight from its definition, without end cells: the best
+    chain's substitution sum minus its inner runs, minus the cheaper of the
+    two runs before its first pair and the cheaper of the two after its last
+    pair (the empty chain: 0).  Tiny inputs only."""
+    m, n = len(q), len(r)
+    ge = min(ge, go)
+    best = 0
+    for c in _chains(n, m):
+        if not c:
+            continue
+        s = sum(int(M[q[j]][r[i]]) for i, j in c)
+        for (i, j), (i2, j2) in zip(c, c[1:]):
+            s -= gap_cost(i2 - i - 1, go, ge) + gap_cost(j2 - j - 1, go, ge)
+        (fi, fj), (li, lj) = c[0], c[-1]
+        s -= min(gap_cost(fi, go, ge), gap_cost(fj, go, ge))
+        s -= min(gap_cost(n - 1 - li, go, ge), gap_cost(m - 1 - lj, go, ge))
+        best = max(best, s)
+    return best
 
 
 def brute_force_endtoend_path(q, r, M, go: int, ge: int, mode: int):
-    """(ref_start, runs) of the reported end-to-end alignment by enumeration:
-    every chain of pairs with its virtual start element ((-1, -1) globally,
-    any (v, -1) semi-globally) that reaches the optimum at the reported end;
-    of those, the one whose elements read from the end backwards are
-    lexicographically largest; rendered with D before I between elements and
-    after the last pair.  Tiny inputs only."""
+    """(query_start, ref_start, runs) of the reported end-to-end alignment by
+    enumeration: every chain of pairs with a virtual start element of the
+    mode ((-1, -1) globally; any (v, -1), a free reference prefix, in modes 1
+    and 3; any (-1, w), a free query prefix, in modes 2 and 3) that reaches
+    the optimum at the reported end; of those, the one whose elements read
+    from the end backwards are lexicographically largest; rendered with D
+    before I between elements and after the last pair.  Tiny inputs only."""
     m, n = len(q), len(r)
     ge = min(ge, go)
-    score, _, a_end = brute_force_endtoend(q, r, M, go, ge, mode)
-    chains = [[]]
-
-    def grow(chain):
-        i0, j0 = chain[-1] if chain else (-1, -1)
-        for i in range(i0 + 1, a_end + 1):
-            for j in range(j0 + 1, m):
-                c = chain + [(i, j)]
-                chains.append(c)
-                grow(c)
-
-    grow([])
+    score, b_end, a_end = brute_force_endtoend(q, r, M, go, ge, mode)
     best = None
-    for c in chains:
-        starts = [-1] if mode == 0 else list(range(-1, (c[0][0] if c else a_end + 1)))
-        for v in starts:
-            elems = [(v, -1)] + c
+    for c in _chains(a_end + 1, b_end + 1):
+        x1, y1 = c[0] if c else (a_end + 1, b_end + 1)
+        starts = []
+        if mode == 0:
+            starts.append((-1, -1))
+        if mode in (1, 3):
+            starts += [(v, -1) for v in range(-1, x1)]
+        if mode in (2, 3):
+            starts += [(-1, w) for w in range(-1, y1)]
+        for st in set(starts):
+            elems = [st] + c
             s = sum(int(M[q[j]][r[i]]) for i, j in c)
             for (i, j), (i2, j2) in zip(elems, elems[1:]):
                 s -= gap_cost(i2 - i - 1, go, ge) + gap_cost(j2 - j - 1, go, ge)
             li, lj = elems[-1]
-            s -= gap_cost(a_end - li, go, ge) + gap_cost(m - 1 - lj, go, ge)
-            if mode == 0 and not c:
-                pass        # both runs from the virtual pair: counted just above
+            s -= gap_cost(a_end - li, go, ge) + gap_cost(b_end - lj, go, ge)
             if s == score:
                 key = list(reversed(elems))
                 if best is None or key > best:
@@ -230,11 +272,11 @@ def brute_force_endtoend_path(q, r, M, go: int, ge: int, mode: int):
     for (i, j), (i2, j2) in zip(elems, elems[1:]):
         ops += ["D"] * (i2 - i - 1) + ["I"] * (j2 - j - 1) + ["M"]
     li, lj = elems[-1]
-    ops += ["D"] * (a_end - li) + ["I"] * (m - 1 - lj)
+    ops += ["D"] * (a_end - li) + ["I"] * (b_end - lj)
     runs = []
     for o in ops:
         if runs and runs[-1][1] == o:
             runs[-1] = (runs[-1][0] + 1, o)
         else:
             runs.append((1, o))
-    return elems[0][0] + 1, runs
+    return elems[0][1] + 1, elems[0][0] + 1, runs

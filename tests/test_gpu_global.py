@@ -170,7 +170,7 @@ def _check_paths(w, mode, label, pairs=None):
         q, r = _seqs(w, k)
         want = oracle.endtoend_path(q, r, w.matrix, w.gap_open, w.gap_extend, mode,
                                     end=tuple(int(x) for x in res[k, :3]))
-        got = (int(rs[k]), api.decode_cigar(runs, off, k))
+        got = (0, int(rs[k]), api.decode_cigar(runs, off, k))   # query_start 0 in these modes
         assert got == want, "%s mode %d pair %d: got %s want %s" % (label, mode, k, got, want)
     return res, rs, runs, off
 

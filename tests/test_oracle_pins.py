@@ -482,19 +482,36 @@ def test_path_pins_tell_other_rules_apart():
 
 # ---------------------------------------------------------------- end to end
 
+MODES = (0, 1, 2, 3)    # global, semi-global (query fitted), semi-global (reference fitted), overlap
+
+
+def _tiny(rng):
+    alpha = int(rng.integers(2, 4))
+    m, n = int(rng.integers(0, 5)), int(rng.integers(0, 6))
+    q = rng.integers(0, alpha, size=m).tolist()
+    r = rng.integers(0, alpha, size=n).tolist()
+    M = rng.integers(-4, 3, size=(alpha, alpha)).astype(np.int32)
+    go = int(rng.integers(0, 4))
+    ge = int(rng.integers(0, go + 3))      # sometimes above the opening cost
+    return q, r, M, go, ge
+
+
 def test_endtoend_brute_force_random():
     rng = np.random.default_rng(41)
     for _ in range(500):
-        alpha = int(rng.integers(2, 4))
-        m, n = int(rng.integers(0, 5)), int(rng.integers(0, 6))
-        q = rng.integers(0, alpha, size=m).tolist()
-        r = rng.integers(0, alpha, size=n).tolist()
-        M = rng.integers(-4, 3, size=(alpha, alpha)).astype(np.int32)
-        go = int(rng.integers(0, 4))
-        ge = int(rng.integers(0, go + 3))      # sometimes above the opening cost
-        for mode in (0, 1):
+        q, r, M, go, ge = _tiny(rng)
+        for mode in MODES:
             want = pins.brute_force_endtoend(q, r, M, go, ge, mode)
             assert oracle.endtoend(q, r, M, go, ge, mode) == want, (q, r, M.tolist(), go, ge, mode)
+
+
+def test_overlap_score_from_its_definition():
+    # the overlap score without end cells: the cheaper run at each end of the
+    # chain, the empty chain 0
+    rng = np.random.default_rng(45)
+    for _ in range(400):
+        q, r, M, go, ge = _tiny(rng)
+        assert oracle.endtoend(q, r, M, go, ge, 3)[0] == pins.overlap_score_direct(q, r, M, go, ge)
 
 
 def test_endtoend_closed_forms():
@@ -505,67 +522,106 @@ def test_endtoend_closed_forms():
         m = int(rng.integers(1, 30))
         q = rng.integers(0, 4, size=m).tolist()
         go, ge = int(rng.integers(1, 8)), int(rng.integers(0, 3))
-        # a sequence against itself: every residue paired
-        assert oracle.endtoend(q, q, M, go, ge, 0) == (5 * m, m - 1, m - 1)
-        # against nothing: one gap run
-        assert oracle.endtoend(q, [], M, go, ge, 0)[0] == -(go + (m - 1) * min(ge, go))
-        assert oracle.endtoend([], q, M, go, ge, 0)[0] == -(go + (m - 1) * min(ge, go))
+        g1 = go + (m - 1) * min(ge, go)
+        # a sequence against itself: every residue paired, in every mode
+        for mode in MODES:
+            assert oracle.endtoend(q, q, M, go, ge, mode) == (5 * m, m - 1, m - 1)
+        # against nothing: one gap run where that side is charged
+        assert oracle.endtoend(q, [], M, go, ge, 0)[0] == -g1
+        assert oracle.endtoend([], q, M, go, ge, 0)[0] == -g1
         assert oracle.endtoend([], q, M, go, ge, 1) == (0, -1, -1)
+        assert oracle.endtoend(q, [], M, go, ge, 1) == (-g1, m - 1, -1)
+        assert oracle.endtoend(q, [], M, go, ge, 2) == (0, -1, -1)
+        assert oracle.endtoend([], q, M, go, ge, 2) == (-g1, -1, m - 1)
+        assert oracle.endtoend(q, [], M, go, ge, 3) == (0, -1, -1)
+        assert oracle.endtoend([], q, M, go, ge, 3) == (0, -1, -1)
         # a query inside a longer reference: free reference ends, the first
-        # occurrence's end
+        # occurrence's end; the reverse mode with the roles swapped
         pre = rng.integers(0, 4, size=int(rng.integers(0, 20))).tolist()
         post = rng.integers(0, 4, size=int(rng.integers(0, 20))).tolist()
         r = pre + q + post
-        s, qe, re_ = oracle.endtoend(q, r, M, go, ge, 1)
-        assert s == 5 * m and qe == m - 1
         first = min(k for k in range(m - 1, len(r)) if r[k - m + 1:k + 1] == q)
-        assert re_ == first
-    # free gaps and a +1 identity matrix: global = longest common subsequence
+        assert oracle.endtoend(q, r, M, go, ge, 1) == (5 * m, m - 1, first)
+        assert oracle.endtoend(r, q, M, go, ge, 2) == (5 * m, first, m - 1)
+        # containment is an overlap too
+        assert oracle.endtoend(q, r, M, go, ge, 3)[0] == 5 * m
+        # a dovetail: the query's suffix is the reference's prefix, the ends
+        # mismatching so badly that only the shared part pays
+        if len(pre) > 0 and len(post) > 0:
+            X = [(c + 1) % 4 for c in pre]
+            Z = [(c + 2) % 4 for c in post]
+            Mh = np.full((4, 4), -50, dtype=np.int32)
+            np.fill_diagonal(Mh, 5)
+            s, qe, re_ = oracle.endtoend(X + q, q + Z, Mh, 60, 60, 3)
+            assert s >= 5 * m
+            assert oracle.align(X + q, q + Z, Mh, 60, 60)[0] >= s
+    # free gaps and a +1 identity matrix: every mode = longest common subsequence
     I1 = np.eye(4, dtype=np.int32)
     for _ in range(100):
         q = rng.integers(0, 4, size=int(rng.integers(0, 15))).tolist()
         r = rng.integers(0, 4, size=int(rng.integers(0, 15))).tolist()
-        assert oracle.endtoend(q, r, I1, 0, 0, 0)[0] == pins.lcs(q, r)
-        assert oracle.endtoend(q, r, I1, 0, 0, 1)[0] == pins.lcs(q, r)
+        for mode in MODES:
+            assert oracle.endtoend(q, r, I1, 0, 0, mode)[0] == pins.lcs(q, r)
+
+
+def test_dovetail_worked_example():
+    # query ACGTT, reference GTTCA (A=0 C=1 G=2 T=3), +5 / -4, GapOpen 6,
+    # GapExtend 1 (worked by hand): the query's suffix GTT is the reference's
+    # prefix, 15 with both overhangs (the query's AC, the reference's CA)
+    # free.  No alignment scores more (15 is also the local optimum), and
+    # ending on the reference's last residue instead would pay for CA (8), so
+    # the end is the query's last residue against the reference's third
+    # (0-based query_end 4, ref_end 2) and the path starts at (2, 0).
+    M = np.full((4, 4), -4, dtype=np.int32)
+    np.fill_diagonal(M, 5)
+    q, r = [0, 1, 2, 3, 3], [2, 3, 3, 1, 0]
+    assert oracle.endtoend(q, r, M, 6, 1, 3) == (15, 4, 2)
+    assert oracle.endtoend_path(q, r, M, 6, 1, 3) == (2, 0, [(3, "M")])
+    assert oracle.align(q, r, M, 6, 1)[0] == 15
 
 
 def test_endtoend_invariants():
     rng = np.random.default_rng(43)
     for _ in range(300):
         q, r, M, go, ge = _case(rng, maxlen=12)
+        Mt = np.ascontiguousarray(np.asarray(M).T)
         g = oracle.endtoend(q, r, M, go, ge, 0)[0]
-        sg = oracle.endtoend(q, r, M, go, ge, 1)[0]
-        assert sg >= g                                       # fewer gaps are paid
-        assert oracle.align(q, r, M, go, ge)[0] >= sg        # a local alignment too
+        sg = oracle.endtoend(q, r, M, go, ge, 1)
+        sr = oracle.endtoend(q, r, M, go, ge, 2)
+        ov = oracle.endtoend(q, r, M, go, ge, 3)
+        assert sg[0] >= g and sr[0] >= g                     # fewer runs are paid
+        assert ov[0] >= max(sg[0], sr[0], 0)
+        assert oracle.align(q, r, M, go, ge)[0] >= ov[0]      # a local alignment too
         assert oracle.endtoend(q[::-1], r[::-1], M, go, ge, 0)[0] == g
-        assert oracle.endtoend(r, q, np.ascontiguousarray(np.asarray(M).T), go, ge, 0)[0] == g
+        assert oracle.endtoend(r, q, Mt, go, ge, 0)[0] == g
+        # swapping the sequences (and transposing the matrix) swaps the two
+        # semi-global modes; the overlap score is symmetric
+        t1 = oracle.endtoend(r, q, Mt, go, ge, 1)
+        assert (t1[0], t1[2], t1[1]) == sr
+        t2 = oracle.endtoend(r, q, Mt, go, ge, 2)
+        assert (t2[0], t2[2], t2[1]) == sg
+        assert oracle.endtoend(r, q, Mt, go, ge, 3)[0] == ov[0]
+        assert oracle.endtoend(q[::-1], r[::-1], M, go, ge, 3)[0] == ov[0]
 
 
 def test_endtoend_path_brute_force_random():
     rng = np.random.default_rng(44)
-    n_cases = 0
+    n_cases = n_query_start = 0
     for _ in range(400):
-        alpha = int(rng.integers(2, 4))
-        m, n = int(rng.integers(0, 5)), int(rng.integers(0, 6))
-        q = rng.integers(0, alpha, size=m).tolist()
-        r = rng.integers(0, alpha, size=n).tolist()
-        M = rng.integers(-4, 3, size=(alpha, alpha)).astype(np.int32)
-        go = int(rng.integers(0, 4))
-        ge = int(rng.integers(0, go + 3))
-        for mode in (0, 1):
+        q, r, M, go, ge = _tiny(rng)
+        for mode in MODES:
             want = pins.brute_force_endtoend_path(q, r, M, go, ge, mode)
             got = oracle.endtoend_path(q, r, M, go, ge, mode)
             assert got == want, (q, r, M.tolist(), go, ge, mode, got, want)
-            s = oracle.endtoend(q, r, M, go, ge, mode)[0]
-            # the runs add up to the score from the start (205 of these 800
-            # cases have another optimal path that the smallest-element rule
-            # would pick, so the tie rule is exercised)
-            assert _endtoend_runs_score(q, r, M, go, ge, (0, got[0]), got[1]) == s
+            s, qe, re_ = oracle.endtoend(q, r, M, go, ge, mode)
+            # the runs add up to the score from the start to the end
+            assert _endtoend_runs_score(q, r, M, go, ge, got[:2], got[2], (qe, re_)) == s
+            n_query_start += got[0] > 0
             n_cases += 1
-    assert n_cases == 800
+    assert n_cases == 1600 and n_query_start > 50
 
 
-def _endtoend_runs_score(q, r, M, go, ge, start, runs):
+def _endtoend_runs_score(q, r, M, go, ge, start, runs, end):
     ge = min(ge, go)
     j, i = start
     total = 0
@@ -581,7 +637,7 @@ def _endtoend_runs_score(q, r, M, go, ge, start, runs):
                 j += L
             else:
                 i += L
-    assert j == len(q)
+    assert (j - 1, i - 1) == tuple(end)
     return total
 
 
@@ -590,11 +646,16 @@ def test_endtoend_path_worked_examples():
     np.fill_diagonal(M, 3)
     # ACGT vs AGT globally: the C skipped
     assert oracle.endtoend_path([0, 1, 2, 3], [0, 2, 3], M, 2, 1, 0) == \
-        (0, [(1, "M"), (1, "I"), (2, "M")])
+        (0, 0, [(1, "M"), (1, "I"), (2, "M")])
     # GT placed inside ACGTA
-    assert oracle.endtoend_path([2, 3], [0, 1, 2, 3, 0], M, 2, 1, 1) == (2, [(2, "M")])
+    assert oracle.endtoend_path([2, 3], [0, 1, 2, 3, 0], M, 2, 1, 1) == (0, 2, [(2, "M")])
+    # ... and ACGTA's GT placed on the reference GT (the reference fitted)
+    assert oracle.endtoend_path([0, 1, 2, 3, 0], [2, 3], M, 2, 1, 2) == (2, 0, [(2, "M")])
     # empty sides
-    assert oracle.endtoend_path([], [0, 1], M, 2, 1, 0) == (0, [(2, "D")])
-    assert oracle.endtoend_path([1], [], M, 2, 1, 1) == (0, [(1, "I")])
-    assert oracle.endtoend_path([1, 2], [0, 3], M, 9, 1, 0) == (0, [(2, "M")])
-
+    assert oracle.endtoend_path([], [0, 1], M, 2, 1, 0) == (0, 0, [(2, "D")])
+    assert oracle.endtoend_path([1], [], M, 2, 1, 1) == (0, 0, [(1, "I")])
+    assert oracle.endtoend_path([], [1], M, 2, 1, 2) == (0, 0, [(1, "D")])
+    assert oracle.endtoend_path([1, 2], [0, 3], M, 9, 1, 0) == (0, 0, [(2, "M")])
+    # the empty overlap: nothing aligned, the query placed before the reference
+    assert oracle.endtoend([1, 1], [0, 0], M, 2, 1, 3) == (0, 1, -1)
+    assert oracle.endtoend_path([1, 1], [0, 0], M, 2, 1, 3) == (2, 0, [])
