@@ -354,12 +354,21 @@ def _paths_leg(api, d, pq, w, ends, qs, rs, reps):
 
 
 def _endtoend_leg(api, d, pq, w, reps):
-    """sw_align_batch_global in both modes on the same pairs (whole calls,
-    device-resident sequences): every cell of every pair is computed."""
+    """sw_align_batch_global in every mode on the same pairs (whole calls,
+    device-resident sequences): every cell of every pair is computed; the
+    reference-fitted mode with the roles swapped (each read, as the
+    reference, placed inside its window, as the query)."""
     import torch
     res = {}
     cells = w.cells()
-    for name, mode in (("global", api.SW_MODE_GLOBAL), ("semiglobal", api.SW_MODE_SEMIGLOBAL)):
+    legs = (("global", api.SW_MODE_GLOBAL, False), ("semiglobal", api.SW_MODE_SEMIGLOBAL, False),
+            ("overlap", api.SW_MODE_OVERLAP, False),
+            ("semiglobal_ref_swapped", api.SW_MODE_SEMIGLOBAL_REF, True))
+    d_fwd, pq_fwd = d, pq
+    for name, mode, swapped in legs:
+        # swapped: windows as queries, reads as references (same pairs)
+        d = [d_fwd[2], d_fwd[3], d_fwd[0], d_fwd[1], pq_fwd] if swapped else d_fwd
+        pq = d_fwd[4] if swapped else pq_fwd
         api.sw_align_batch_global(*d, w.matrix, w.gap_open, w.gap_extend, mode=mode, pair_query=pq)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -375,9 +384,9 @@ def _endtoend_leg(api, d, pq, w, reps):
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(reps):
-            rs, runs, off = api.sw_align_batch_global_cigar(*d, w.matrix, w.gap_open,
-                                                            w.gap_extend, r, mode=mode,
-                                                            pair_query=pq)
+            qs, rs, runs, off = api.sw_align_batch_global_cigar(*d, w.matrix, w.gap_open,
+                                                                w.gap_extend, r, mode=mode,
+                                                                pair_query=pq)
         pms = (time.perf_counter() - t) / reps * 1e3
         rows = r[:, 2].astype(np.int64) + 1
         pcells = int((rows * (r[:, 1].astype(np.int64) + 1)).sum())

@@ -228,11 +228,26 @@ int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc, const sw_resul
  *   reference prefix end a (-1: the empty prefix) such that the best
  *   alignment of the query inside r[0..a], with the reference residues after
  *   its last pair up to a counted as a gap run, reaches the score.
+ * mode SW_MODE_SEMIGLOBAL_REF: the same with the roles swapped: the
+ *   reference end to end, query residues before the first and after the last
+ *   pair free (a short reference placed inside a long query).  ref_end =
+ *   n - 1; query_end = the smallest query prefix end b (-1: the empty
+ *   prefix) whose best alignment, with the query residues after its last
+ *   pair up to b counted as a gap run, reaches the score.
+ * mode SW_MODE_OVERLAP: free end gaps: before the first pair the skipped
+ *   residues of one of the two sequences are free and the other's cost a
+ *   run, and likewise after the last pair (a dovetail of the two sequences,
+ *   or one contained in the other); the empty alignment scores 0.  The end
+ *   cell lies on the query's last residue (query_end = m - 1, any ref_end
+ *   from -1, the reference after it free) or on the reference's last residue
+ *   (ref_end = n - 1, any query_end from -1); of the end cells whose best
+ *   alignment reaches the score, the smallest ref_end, then the smallest
+ *   query_end.
  *
  * out[k] receives pair k's {score, query_end, ref_end, 0}; scores may be
- * negative.  An empty side gives the gap run of the other (or 0).  Computed
- * in int32 by one wavefront per pair (the query in 256-column tiles, a
- * max-plus scan over the lanes for the query gap); SW_EOVERFLOW for a pair
+ * negative.  An empty side gives the charged gap run of the other (or 0).
+ * Computed in int32 by one wavefront per pair (the query in 256-column tiles,
+ * a max-plus scan over the lanes for the query gap); SW_EOVERFLOW for a pair
  * whose scores could leave that range (about 2^27 / (gap_extend + 1) residues
  * in m + n).  SW_EINVAL for a bad mode, NULL arrays, ids or offsets out of
  * range, or a residue not below alphabet_size.  The batch's arrays follow
@@ -240,40 +255,45 @@ int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc, const sw_resul
  * out is a host array of n_pairs entries.  Synchronous; calls are serialised
  * with sw_align_batch_starts and sw_align_batch_cigar.
  * ------------------------------------------------------------------------- */
-enum { SW_MODE_GLOBAL = 0, SW_MODE_SEMIGLOBAL = 1 };
+enum { SW_MODE_GLOBAL = 0, SW_MODE_SEMIGLOBAL = 1, SW_MODE_SEMIGLOBAL_REF = 2,
+       SW_MODE_OVERLAP = 3 };
 int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, int32_t mode,
                           sw_result *out);
 
 /* ---------------------------------------------------------------------------
  * sw_align_batch_global_cigar -- paths of the end-to-end alignments a
  * sw_align_batch_global call found (same batch, scoring and mode; ends: its
- * n_pairs results).
+ * n_pairs results, or any end cell of the mode with the best score there).
  *
- * Pair k's alignment runs from a virtual start pair -- (-1, -1) for
- * SW_MODE_GLOBAL, (v, -1) for SW_MODE_SEMIGLOBAL, r[0..v] being the free
- * reference prefix -- to its end cell; walking back from the end, each
- * predecessor is the largest (ref index, then query index) element (aligned
- * pair or virtual start) on an optimal chain, and between two elements, as
- * after the last pair, the D run comes before the I run.  Runs as in
- * sw_align_batch_cigar (packed: cigar[cigar_off[k] .. cigar_off[k+1]),
- * cigar_off[0] = 0; SW_EINVAL with cigar_off filled and cigar untouched when
- * the total exceeds cigar_cap).  Global paths consume both sequences whole;
- * semi-global paths consume the whole query and r[ref_start[k] ..
- * ref_end]: ref_start[k] = v + 1 (0 globally).  A pair needs at most
- * (ref_end + 1) + m + 2 runs.
+ * Pair k's alignment runs from a virtual start element to its end cell: the
+ * element is (-1, -1) for SW_MODE_GLOBAL; (v, -1), v >= -1, r[0..v] being a
+ * free reference prefix, for SW_MODE_SEMIGLOBAL and SW_MODE_OVERLAP; (-1, w),
+ * q[0..w] being a free query prefix, for SW_MODE_SEMIGLOBAL_REF and
+ * SW_MODE_OVERLAP (element coordinates are (ref index, query index)).
+ * Walking back from the end, each predecessor is the largest (ref index,
+ * then query index) element (aligned pair or virtual start) on an optimal
+ * chain, and between two elements, as after the last pair, the D run comes
+ * before the I run.  Runs as in sw_align_batch_cigar (packed:
+ * cigar[cigar_off[k] .. cigar_off[k+1]), cigar_off[0] = 0; SW_EINVAL with
+ * cigar_off filled and cigar untouched when the total exceeds cigar_cap).
+ * The path consumes q[query_start[k] .. query_end] and r[ref_start[k] ..
+ * ref_end], the start element's coordinates plus one (0, 0 globally).  A
+ * pair needs at most (ref_end + 1) + (query_end + 1) + 2 runs.
  *
  * Computed by the path kernel of sw_align_batch_cigar with the boundaries of
- * sw_align_batch_global over r[0..ref_end] x q.  SW_EINVAL: a bad mode, NULL
- * arrays, ids or offsets out of range, an end that is not (m - 1, n - 1)
- * (global) or (m - 1, -1 .. n - 1) (semi-global), a score that is not the
- * optimum there, a residue not below alphabet_size, or too small a
- * cigar_cap; SW_EOVERFLOW and SW_ENOMEM as for sw_align_batch_cigar.  ends,
- * ref_start, cigar and cigar_off are host arrays owned by the caller.
- * Synchronous; serialised with the other calls of this group.
+ * sw_align_batch_global over r[0..ref_end] x q[0..query_end].  SW_EINVAL: a
+ * bad mode, NULL arrays, ids or offsets out of range, an end cell that is
+ * not one of the mode's ((m - 1, n - 1) global; query_end = m - 1
+ * semi-global; ref_end = n - 1 semi-global the other way; either overlap), a
+ * score that is not the optimum there, a residue not below alphabet_size, or
+ * too small a cigar_cap; SW_EOVERFLOW and SW_ENOMEM as for
+ * sw_align_batch_cigar.  ends, query_start, ref_start, cigar and cigar_off
+ * are host arrays owned by the caller.  Synchronous; serialised with the
+ * other calls of this group.
  * ------------------------------------------------------------------------- */
 int sw_align_batch_global_cigar(const sw_batch *b, const sw_scoring *sc, int32_t mode,
-                                const sw_result *ends, int32_t *ref_start, uint32_t *cigar,
-                                int64_t cigar_cap, int64_t *cigar_off);
+                                const sw_result *ends, int32_t *query_start, int32_t *ref_start,
+                                uint32_t *cigar, int64_t cigar_cap, int64_t *cigar_off);
 
 /* Options and statistics for the extended batch call (tests, benchmarks,
  * the autotuner).  Zero-initialise and set what you need. */

@@ -172,7 +172,8 @@ def load():
                                           ctypes.c_int32, ctypes.c_void_p]
     lib.sw_align_batch_global_cigar.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring),
                                                 ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
-                                                ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                ctypes.c_void_p]
     lib.sw_autotune.argtypes = [ctypes.POINTER(Batch), ctypes.POINTER(Scoring), ctypes.c_int64,
                                 ctypes.POINTER(TuneEntry), ctypes.c_int32,
                                 ctypes.POINTER(ctypes.c_int32)]
@@ -414,15 +415,17 @@ def sw_align_batch_cigar(query_res, query_off, ref_res, ref_off, pair_ref, matri
     return runs[:off[-1]], off
 
 
-SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL = 0, 1
+SW_MODE_GLOBAL, SW_MODE_SEMIGLOBAL, SW_MODE_SEMIGLOBAL_REF, SW_MODE_OVERLAP = 0, 1, 2, 3
 
 
 def sw_align_batch_global(query_res, query_off, ref_res, ref_off, pair_ref, matrix,
                           gap_open: int, gap_extend: int, mode: int = SW_MODE_GLOBAL,
                           pair_query=None) -> np.ndarray:
-    """End-to-end scores of every pair: global (``SW_MODE_GLOBAL``) or
-    semi-global with free reference ends (``SW_MODE_SEMIGLOBAL``).  Returns an
-    (n_pairs, 4) int32 array of {score, query_end, ref_end, flags}."""
+    """End-to-end scores of every pair: global (``SW_MODE_GLOBAL``),
+    semi-global with free reference ends (``SW_MODE_SEMIGLOBAL``) or free
+    query ends (``SW_MODE_SEMIGLOBAL_REF``), or overlap with free end gaps
+    (``SW_MODE_OVERLAP``).  Returns an (n_pairs, 4) int32 array of {score,
+    query_end, ref_end, flags}."""
     lib = load()
     b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
                                   SW_PREC_AUTO)
@@ -437,9 +440,9 @@ def sw_align_batch_global_cigar(query_res, query_off, ref_res, ref_off, pair_ref
                                 gap_open: int, gap_extend: int, results,
                                 mode: int = SW_MODE_GLOBAL, pair_query=None, cigar_cap=None):
     """Paths of the alignments ``sw_align_batch_global`` returned (``results``,
-    same batch, scoring and mode).  Returns (ref_start, runs, offsets): pair
-    k's runs are runs[offsets[k]:offsets[k + 1]] from its start (query 0,
-    reference ref_start[k]) to its end cell."""
+    same batch, scoring and mode).  Returns (query_start, ref_start, runs,
+    offsets): pair k's runs are runs[offsets[k]:offsets[k + 1]] from its start
+    (query_start[k], ref_start[k]) to its end cell."""
     lib = load()
     b, keep, npairs = _make_batch(query_res, query_off, ref_res, ref_off, pair_ref, pair_query,
                                   SW_PREC_AUTO)
@@ -452,11 +455,13 @@ def sw_align_batch_global_cigar(query_res, query_off, ref_res, ref_off, pair_ref
         if cigar_cap is None else int(cigar_cap)
     runs = np.empty(max(cap, 1), dtype=np.uint32)
     off = np.empty(npairs + 1, dtype=np.int64)
+    qs = np.empty(max(npairs, 1), dtype=np.int32)
     rs = np.empty(max(npairs, 1), dtype=np.int32)
     _check(lib.sw_align_batch_global_cigar(ctypes.byref(b), ctypes.byref(sc), int(mode),
-                                           ends.ctypes.data if npairs else None, rs.ctypes.data,
-                                           runs.ctypes.data, cap, off.ctypes.data))
-    return rs[:npairs], runs[:off[-1]], off
+                                           ends.ctypes.data if npairs else None, qs.ctypes.data,
+                                           rs.ctypes.data, runs.ctypes.data, cap,
+                                           off.ctypes.data))
+    return qs[:npairs], rs[:npairs], runs[:off[-1]], off
 
 
 def decode_cigar(runs, offsets, k: int) -> list:

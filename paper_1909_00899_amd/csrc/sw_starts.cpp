@@ -61,6 +61,7 @@ struct StartsWork {
   HostBuf tr_host, tr_hcounts;   // pinned: the pair table, the run counts
   DevBuf tr_res;                 // end-to-end results
   DevBuf tr_rstart;              // end-to-end paths: reference starts
+  DevBuf tr_qstart;              // end-to-end paths: query starts
   HostBuf tr_hres;
   // device-memory rectangles: the largest group, the second, the rest each on
   // a stream of their own, so the long poles of the largest rectangles (one
@@ -375,13 +376,14 @@ int64_t run_bound(int64_t A, int64_t B) {
 }  // namespace
 
 // Paths of a batch: mode 0 the local alignments between start and end cells
-// (sw_align_batch_cigar), mode 1 / 2 whole global / semi-global alignments
-// from their end cells (sw_align_batch_global_cigar; ref_start_out receives
-// the semi-global reference starts).
+// (sw_align_batch_cigar), modes 1-4 whole end-to-end alignments (the API's
+// mode + 1: global, semi-global query fitted, semi-global reference fitted,
+// overlap) from their end cells (sw_align_batch_global_cigar;
+// query_start_out / ref_start_out receive the start element + 1).
 namespace {
 int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_result *ends,
-               const int32_t *query_start, const int32_t *ref_start, int32_t *ref_start_out,
-               uint32_t *cigar, int64_t cigar_cap, int64_t *cigar_off) {
+               const int32_t *query_start, const int32_t *ref_start, int32_t *query_start_out,
+               int32_t *ref_start_out, uint32_t *cigar, int64_t cigar_cap, int64_t *cigar_off) {
   int rc = check_batch_args(b);
   if (rc) return rc;
   Scoring S;
@@ -390,10 +392,16 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
   if (!cigar_off) { set_error("cigar_off is NULL"); return SW_EINVAL; }
   cigar_off[0] = 0;
   if (np == 0) return SW_OK;
-  if (!ends || (mode == 0 && (!query_start || !ref_start)) || (mode != 0 && !ref_start_out)) {
-    set_error("ends, starts or ref_start is NULL");
+  if (!ends || (mode == 0 && (!query_start || !ref_start)) ||
+      (mode != 0 && (!ref_start_out || !query_start_out))) {
+    set_error("ends, starts or the start outputs are NULL");
     return SW_EINVAL;
   }
+  // end-to-end modes: which prefixes are free (virtual start elements (v, -1)
+  // and (-1, w)) and where an end cell may lie
+  const bool col_free = mode == 2 || mode == 4, row_free = mode == 3 || mode == 4;
+  static const char *const kModeName[] = {"local", "global", "semi-global (query fitted)",
+                                          "semi-global (reference fitted)", "overlap"};
   if (cigar_cap < 0 || (cigar_cap > 0 && !cigar)) { set_error("cigar is NULL or its capacity negative"); return SW_EINVAL; }
   if ((rc = ensure_init())) return rc;
   std::lock_guard<std::mutex> g(g_starts.mu);
@@ -432,23 +440,42 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
       }
     } else {
       ref_start_out[k] = 0;
-      if (e.query_end != m - 1 || e.ref_end < -1 || e.ref_end >= n ||
-          (mode == 1 && e.ref_end != n - 1)) {
+      query_start_out[k] = 0;
+      const bool in = e.ref_end >= -1 && e.ref_end < n && e.query_end >= -1 && e.query_end < m;
+      const bool on_q = e.query_end == m - 1, on_r = e.ref_end == n - 1;
+      const bool ok = mode == 1 ? on_q && on_r : mode == 2 ? on_q : mode == 3 ? on_r : on_q || on_r;
+      if (!in || !ok) {
         set_error("pair %d: end (%d, %d) is not the end cell of a %s alignment of its %lld x %lld "
-                  "sequences", k, e.query_end, e.ref_end, mode == 1 ? "global" : "semi-global",
-                  (long long)m, (long long)n);
+                  "sequences", k, e.query_end, e.ref_end, kModeName[mode], (long long)m,
+                  (long long)n);
         return SW_EINVAL;
       }
-      if (m == 0 || e.ref_end < 0) {        // nothing to pair: one or two gap runs
-        const int64_t rows = mode == 1 ? n : 0;
-        if (e.score != -gap(rows) - gap(m)) {
-          set_error("pair %d: score %d is not this alignment's", k, e.score);
+      if (e.query_end < 0 || e.ref_end < 0) {
+        // nothing to pair: runs from the best virtual start element -- the
+        // largest (ref, query) one -- to the end cell
+        const int64_t A0 = e.ref_end + 1, B0 = e.query_end + 1;
+        int64_t best = INT64_MIN, bx = 0, by = 0;
+        auto consider = [&](int64_t x, int64_t y) {   // element (x, y): its value at the end
+          const int64_t v = -gap(A0 - 1 - x) - gap(B0 - 1 - y);
+          if (v > best || (v == best && (x > bx || (x == bx && y > by)))) {
+            best = v;
+            bx = x;
+            by = y;
+          }
+        };
+        consider(-1, -1);
+        for (int64_t x = 0; col_free && x < A0; ++x) consider(x, -1);
+        for (int64_t y = 0; row_free && y < B0; ++y) consider(-1, y);
+        if (e.score != best) {
+          set_error("pair %d: score %d is not the optimum at the end cell (%d, %d)", k, e.score,
+                    e.query_end, e.ref_end);
           return SW_EINVAL;
         }
         std::vector<uint32_t> v;
-        if (rows) v.push_back((uint32_t)rows << 4 | swk::kCigarD);
-        if (m) v.push_back((uint32_t)m << 4 | swk::kCigarI);
-        ref_start_out[k] = mode == 2 ? e.ref_end + 1 : 0;
+        if (A0 - 1 - bx) v.push_back((uint32_t)(A0 - 1 - bx) << 4 | swk::kCigarD);
+        if (B0 - 1 - by) v.push_back((uint32_t)(B0 - 1 - by) << 4 | swk::kCigarI);
+        ref_start_out[k] = (int32_t)(bx + 1);
+        query_start_out[k] = (int32_t)(by + 1);
         host_runs.emplace_back(k, std::move(v));
         continue;
       }
@@ -530,7 +557,8 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
         (rc = W.tr_runs.ensure((size_t)std::max<int64_t>(region, 1) * sizeof(uint32_t))) ||
         (rc = W.tr_nruns.ensure((size_t)np * sizeof(int32_t))) ||
         (rc = W.tr_off.ensure((size_t)(np + 1) * sizeof(int64_t))) ||
-        (rc = W.tr_rstart.ensure((size_t)np * sizeof(int32_t))))
+        (rc = W.tr_rstart.ensure((size_t)np * sizeof(int32_t))) ||
+        (rc = W.tr_qstart.ensure((size_t)np * sizeof(int32_t))))
       return rc;
     for (int k = 0; k < NS && k < (int)groups.size(); ++k) {
       if ((rc = W.tr_bits[k].ensure((size_t)std::max<int64_t>(bits_words[k], 1) * sizeof(uint16_t))) ||
@@ -556,6 +584,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     ta.n_runs = W.tr_nruns.as<int32_t>();
     ta.mode = mode;
     ta.ref_start = W.tr_rstart.as<int32_t>();
+    ta.query_start = W.tr_qstart.as<int32_t>();
     ta.pairs = dp;
     ta.n = nl;
     ta.slot_words = 0;
@@ -584,10 +613,13 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     int32_t *dev_counts = W.tr_hcounts.as<int32_t>();
     HIPCHK(hipMemcpyAsync(dev_counts, W.tr_nruns.p, (size_t)np * sizeof(int32_t),
                           hipMemcpyDeviceToHost, W.st));
-    std::vector<int32_t> dev_rstart;
+    std::vector<int32_t> dev_rstart, dev_qstart;
     if (mode != 0) {
       dev_rstart.resize(np);
+      dev_qstart.resize(np);
       HIPCHK(hipMemcpyAsync(dev_rstart.data(), W.tr_rstart.p, (size_t)np * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, W.st));
+      HIPCHK(hipMemcpyAsync(dev_qstart.data(), W.tr_qstart.p, (size_t)np * sizeof(int32_t),
                             hipMemcpyDeviceToHost, W.st));
     }
     HIPCHK(hipStreamSynchronize(W.st));
@@ -613,7 +645,10 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
         return SW_EDEVICE;
       }
       counts[P.id] = c;
-      if (mode != 0) ref_start_out[P.id] = dev_rstart[P.id];
+      if (mode != 0) {
+        ref_start_out[P.id] = dev_rstart[P.id];
+        query_start_out[P.id] = dev_qstart[P.id];
+      }
     }
   }
   for (const auto &hr : host_runs) counts[hr.first] = (int32_t)hr.second.size();
@@ -644,21 +679,21 @@ extern "C" int sw_align_batch_cigar(const sw_batch *b, const sw_scoring *sc,
                                     const sw_result *ends, const int32_t *query_start,
                                     const int32_t *ref_start, uint32_t *cigar,
                                     int64_t cigar_cap, int64_t *cigar_off) {
-  return paths_impl(b, sc, 0, ends, query_start, ref_start, nullptr, cigar, cigar_cap,
+  return paths_impl(b, sc, 0, ends, query_start, ref_start, nullptr, nullptr, cigar, cigar_cap,
                     cigar_off);
 }
 
 extern "C" int sw_align_batch_global_cigar(const sw_batch *b, const sw_scoring *sc, int32_t mode,
-                                           const sw_result *ends, int32_t *ref_start,
-                                           uint32_t *cigar, int64_t cigar_cap,
-                                           int64_t *cigar_off) {
-  if (mode != SW_MODE_GLOBAL && mode != SW_MODE_SEMIGLOBAL) {
+                                           const sw_result *ends, int32_t *query_start,
+                                           int32_t *ref_start, uint32_t *cigar,
+                                           int64_t cigar_cap, int64_t *cigar_off) {
+  if (mode < SW_MODE_GLOBAL || mode > SW_MODE_OVERLAP) {
     set_error("bad mode %d", mode);
     if (cigar_off) cigar_off[0] = 0;
     return SW_EINVAL;
   }
-  return paths_impl(b, sc, mode == SW_MODE_GLOBAL ? 1 : 2, ends, nullptr, nullptr, ref_start,
-                    cigar, cigar_cap, cigar_off);
+  return paths_impl(b, sc, mode + 1, ends, nullptr, nullptr, query_start, ref_start, cigar,
+                    cigar_cap, cigar_off);
 }
 
 
@@ -668,7 +703,7 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
                                      sw_result *out) {
   int rc = check_batch_args(b);
   if (rc) return rc;
-  if (mode != SW_MODE_GLOBAL && mode != SW_MODE_SEMIGLOBAL) { set_error("bad mode %d", mode); return SW_EINVAL; }
+  if (mode < SW_MODE_GLOBAL || mode > SW_MODE_OVERLAP) { set_error("bad mode %d", mode); return SW_EINVAL; }
   Scoring S;
   if ((rc = prepare_scoring(sc, S))) return rc;
   const int np = b->n_pairs;
@@ -691,10 +726,14 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
     const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
     const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
     if (m == 0 || n == 0) {          // a side with nothing to align: one gap run (or none)
-      const int64_t s = mode == SW_MODE_GLOBAL ? -gap(m) - gap(n) : -gap(m);
+      // the charged sides' runs; ends where the charged sides are used up,
+      // the smallest (ref_end, query_end) among the free choices
+      const bool qc = mode == SW_MODE_GLOBAL || mode == SW_MODE_SEMIGLOBAL;
+      const bool rc_ = mode == SW_MODE_GLOBAL || mode == SW_MODE_SEMIGLOBAL_REF;
+      const int64_t s = -(qc ? gap(m) : 0) - (rc_ ? gap(n) : 0);
       out[k].score = (int32_t)s;
-      out[k].query_end = (int32_t)(m - 1);
-      out[k].ref_end = mode == SW_MODE_GLOBAL ? (int32_t)(n - 1) : -1;
+      out[k].query_end = qc ? (int32_t)(m - 1) : -1;
+      out[k].ref_end = rc_ ? (int32_t)(n - 1) : -1;
       out[k].flags = 0;
       if (s < INT32_MIN) { set_error("pair %d: score below the int32 range", k); return SW_EOVERFLOW; }
       continue;

@@ -38,8 +38,11 @@ struct TraceArgs {
   int carry_rows;
   uint32_t *cigar;         // device
   int32_t *n_runs;         // device, indexed by TracePair::id
-  int mode;                // 0 local rectangle, 1 global, 2 semi-global
-  int32_t *ref_start;      // modes 1, 2: device, indexed by TracePair::id
+  int mode;                // 0 local rectangle; 1-4 the end-to-end mode + 1 (global,
+                           // semi-global query fitted, semi-global reference fitted,
+                           // overlap)
+  int32_t *ref_start;      // modes 1-4: the start element's coordinates + 1, device,
+  int32_t *query_start;    // indexed by TracePair::id
 };
 
 // LDS bytes of a workgroup (the matrix sized for the alphabet); with

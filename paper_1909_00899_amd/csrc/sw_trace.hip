@@ -77,12 +77,16 @@ __host__ __device__ constexpr int mat_words(int alpha) { return (alpha * alpha +
 
 // One pair at C query columns per lane (a tile of 64 C columns).  MODE 0:
 // the rectangle between a local alignment's start and end pair, anchored at
-// the start pair; MODE 1 / 2: a whole global / semi-global alignment (the
-// boundaries of endtoend_kernel), walked back from its end cell to the
-// virtual start pair.
+// the start pair; MODE 1-4: a whole end-to-end alignment in the API's mode
+// MODE - 1 (global, semi-global either way, overlap: the boundaries of
+// endtoend_kernel) over r[0..ref_end] x q[0..query_end], walked back from
+// its end cell to a virtual start element.
 template <bool LB, int C, int MODE>
 __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P, const int *smat,
                                           uint16_t *lbits, int *lcarry, uint16_t *lwin) {
+  // row -1 free: virtual pairs (-1, j) (query prefix free); column -1 free:
+  // virtual pairs (i, -1) (reference prefix free)
+  constexpr bool kRowFree = MODE == 3 || MODE == 4, kColFree = MODE == 2 || MODE == 4;
   constexpr int TC = 64 * C;
   const int L = threadIdx.x;
   const int alpha = a.alpha, go = a.go, ge = a.ge;
@@ -106,13 +110,15 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     int Vp[C], Gp[C], Fp[C], wj[C], ej[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      // row -1: nothing (MODE 0), or the gap run of the first j + 1 query residues
-      Vp[c] = Gp[c] = MODE == 0 ? kNeg : -(go + (jc0 + c) * ge);
+      // row -1: nothing (MODE 0), the gap run of the first j + 1 query
+      // residues, or a free query prefix (a virtual pair at (-1, j))
+      Vp[c] = Gp[c] = MODE == 0 ? kNeg : kRowFree ? 0 : -(go + (jc0 + c) * ge);
       Fp[c] = kNeg;
       wj[c] = (jc0 + c) * ge;              // scan term offset of column j
       ej[c] = go + (jc0 + c - 1) * ge;     // Eg(., j) = prefix max - go - (j - 1) ge
     }
-    int cv_prev = MODE == 0 ? kNeg : base == 0 ? 0 : -(go + (base - 1) * ge);   // V(i-1, base-1)
+    // V(-1, base - 1)
+    int cv_prev = MODE == 0 ? kNeg : base == 0 || kRowFree ? 0 : -(go + (base - 1) * ge);
     int rreg = 0, crv = kNeg, crm = kNeg, crp = kNeg;
     for (int i = 0; i < A; ++i) {
       if ((i & 63) == 0) {                   // 64 rows of residues (and carries) at a time
@@ -127,11 +133,11 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
       }
       const int rc = min(readlane(rreg, i & 63), alpha - 1);
       // column -1 (tile 0): V(i, -1), M(i, -1) and its scan term: nothing in
-      // MODE 0; the reference gap run from the virtual start in MODE 1; a
-      // virtual start pair (free reference prefix) in MODE 2
-      const int cv_in = t ? readlane(crv, i & 63) : MODE == 0 ? kNeg : MODE == 1 ? -(go + i * ge) : 0;
-      const int cm_in = t ? readlane(crm, i & 63) : MODE == 2 ? 0 : kNeg;
-      const int cp_in = t ? readlane(crp, i & 63) : MODE == 2 ? -ge : kNeg;
+      // MODE 0; the reference gap run from the virtual start (-1, -1); or a
+      // virtual start pair at (i, -1) (free reference prefix)
+      const int cv_in = t ? readlane(crv, i & 63) : MODE == 0 ? kNeg : kColFree ? 0 : -(go + i * ge);
+      const int cm_in = t ? readlane(crm, i & 63) : kColFree ? 0 : kNeg;
+      const int cp_in = t ? readlane(crp, i & 63) : kColFree ? -ge : kNeg;
       int Mv[C];
       // no clamps below: every cell off row 0 and column 0 is reachable
       // (gaps from the start), so unreachable values only arise next to
@@ -220,7 +226,8 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     }
     return (int)(wd >> (4 * (j % C))) & 15;
   };
-  int vstart = -1;                         // MODE 2: row of the virtual start pair
+  // the virtual start element: (vstart, -1) or (-1, qvstart)
+  int vstart = -1, qvstart = -1;
   if (!fail && MODE != 0) {
     // from the end cell (state V); pairs are counted into M runs, the gaps
     // between two elements (the end, pairs, the virtual start) into one D
@@ -231,8 +238,9 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
       int nd = 0, ni = 0;
       bool start = false;
       if (i < 0 || j < 0) {                  // on the boundary: to the virtual start
-        if (i >= 0 && MODE == 2) vstart = i;          // V(i, -1) = 0: a free prefix
-        else if (i >= 0) nd = i + 1;                  // MODE 1: the reference gap run
+        if (i >= 0 && kColFree) vstart = i;           // V(i, -1) = 0: a free reference prefix
+        else if (i >= 0) nd = i + 1;                  // the reference gap run from (-1, -1)
+        else if (kRowFree) qvstart = j;               // V(-1, j) = 0: a free query prefix
         else ni = j + 1;                              // row -1: the query gap run
         start = true;
       } else {
@@ -241,9 +249,10 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
           for (;;) {
             ++nd;
             const bool open = nib & 2;
-            if (--i < 0) {                   // G(-1, j): the query gap run of row -1
+            if (--i < 0) {                   // G(-1, j): row -1 (a run, or a virtual pair)
               if (!open) fail = true;
-              ni = j + 1;
+              if (kRowFree) qvstart = j;
+              else ni = j + 1;
               start = true;
               break;
             }
@@ -256,7 +265,7 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
             ++ni;
             const bool open = nib & 8;
             if (--j < 0) {                   // M(i, -1): a virtual start pair
-              if (!open || MODE != 2) fail = true;
+              if (!open || !kColFree) fail = true;
               vstart = i;
               start = true;
               break;
@@ -347,7 +356,10 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
   }
   if (L == 0) {
     a.n_runs[P.id] = bad ? kTraceBadResidue : fail ? kTraceInconsistent : nrun;
-    if (MODE != 0) a.ref_start[P.id] = MODE == 2 ? vstart + 1 : 0;
+    if (MODE != 0) {
+      a.ref_start[P.id] = vstart + 1;
+      a.query_start[P.id] = qvstart + 1;
+    }
   }
 }
 
@@ -376,27 +388,60 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   __syncthreads();
   for (int p = blockIdx.x; p < a.n; p += gridDim.x) {
     const TracePair P = a.pairs[p];
-    if (a.mode == 0) trace_mode<LB, 0>(a, P, smat, lbits, lcarry, lwin);
-    else if (a.mode == 1) trace_mode<LB, 1>(a, P, smat, lbits, lcarry, lwin);
-    else trace_mode<LB, 2>(a, P, smat, lbits, lcarry, lwin);
+    switch (a.mode) {
+      case 0: trace_mode<LB, 0>(a, P, smat, lbits, lcarry, lwin); break;
+      case 1: trace_mode<LB, 1>(a, P, smat, lbits, lcarry, lwin); break;
+      case 2: trace_mode<LB, 2>(a, P, smat, lbits, lcarry, lwin); break;
+      case 3: trace_mode<LB, 3>(a, P, smat, lbits, lcarry, lwin); break;
+      default: trace_mode<LB, 4>(a, P, smat, lbits, lcarry, lwin); break;
+    }
   }
 }
 
-// Global (MODE 0) or semi-global (MODE 1: query end to end, reference ends
-// free) score of each pair; one wavefront per pair, the query in tiles of 256
-// columns as in trace_kernel, V and the scan total of each tile's last column
-// carried per row in the wavefront's slot of gcarry.
+// End-to-end modes (the API's): 0 global, 1 semi-global with the query end
+// to end (column -1 free: a virtual pair at every (i, -1)), 2 semi-global
+// with the reference end to end (row -1 free: a virtual pair at every
+// (-1, j), entering the column gap), 3 overlap (both free).
+template <int MODE> struct EndMode {
+  static constexpr bool kRowFree = MODE == 2 || MODE == 3;   // query prefix free
+  static constexpr bool kColFree = MODE == 1 || MODE == 3;   // reference prefix free
+  static constexpr bool kEndCol = MODE == 1 || MODE == 3;    // ends on the query's last column
+  static constexpr bool kEndRow = MODE == 2 || MODE == 3;    // ends on the reference's last row
+};
+
+// (v, col) of the larger value, the smaller column on ties: the end cells of
+// the last row in (ref_end, query_end) order.  Lanes xor-paired within `width`.
+template <int WIDTH>
+__device__ __forceinline__ void argmax_first(int &v, int &col) {
+#pragma unroll
+  for (int d = 1; d < WIDTH; d <<= 1) {
+    const int ov = __shfl_xor(v, d), oc = __shfl_xor(col, d);
+    if (ov > v || (ov == v && oc < col)) {
+      v = ov;
+      col = oc;
+    }
+  }
+}
+
+// End-to-end score of each pair (modes of EndMode); one wavefront per pair,
+// the query in tiles of 256 columns as in trace_kernel, V and the scan total
+// of each tile's last column carried per row in the wavefront's slot of
+// gcarry.
 template <int MODE, int C>
 __device__ __forceinline__ void endtoend_one(const EndArgs &a, const TracePair &P,
                                              const int *smat) {
+  using EM = EndMode<MODE>;
   constexpr int TC = 64 * C;
   const int L = threadIdx.x;
   const int alpha = a.alpha, go = a.go, ge = a.ge;
   const int A = P.A, B = P.B, T = (B + TC - 1) / TC;
   int *carry = a.gcarry + (size_t)blockIdx.x * 4 * a.carry_rows;
   bool bad = false;
-  // semi-global: best V(a, B-1) over a = -1 .. A-1, the first one on ties
-  int best = -(go + (B - 1) * ge), best_row = -1, score = 0;
+  // end cells on the last column: the best V(a, B-1) over a = -1 .. A-1
+  // (overlap: .. A-2, the last row's cells follow), the first one on ties
+  int best = EM::kRowFree ? 0 : -(go + (B - 1) * ge), best_row = -1, score = 0;
+  // end cells on the last row: V(A-1, b) over b = -1 .. B-1 (this lane's columns)
+  int rbest = EM::kColFree ? 0 : -(go + (A - 1) * ge), rcol = -1;
   for (int t = 0; t < T; ++t) {
     const int base = t * TC, jc0 = base + C * L;
     const int *cr = carry + ((t + 1) & 1) * 2 * a.carry_rows;
@@ -407,13 +452,14 @@ __device__ __forceinline__ void endtoend_one(const EndArgs &a, const TracePair &
       const int code = jc0 + c < B ? (int)a.qres[P.q + jc0 + c] : 0;
       bad |= code >= alpha;
       qb[c] = min(code, alpha - 1) * alpha;
-      Vp[c] = Gp[c] = -(go + (jc0 + c) * ge);   // row -1: the first j + 1 query residues skipped
+      // row -1: the first j + 1 query residues skipped, or a free prefix
+      Vp[c] = Gp[c] = EM::kRowFree ? 0 : -(go + (jc0 + c) * ge);
       Fp[c] = kNeg;
       wj[c] = (jc0 + c) * ge;
       ej[c] = go + (jc0 + c - 1) * ge;
     }
     // V(-1, base - 1): the virtual pair, or the row -1 gap run
-    int cv_prev = base == 0 ? 0 : -(go + (base - 1) * ge);
+    int cv_prev = base == 0 || EM::kRowFree ? 0 : -(go + (base - 1) * ge);
     int rreg = 0, crv = kNeg, crp = kNeg;
     for (int i = 0; i < A; ++i) {
       if ((i & 63) == 0) {
@@ -427,8 +473,8 @@ __device__ __forceinline__ void endtoend_one(const EndArgs &a, const TracePair &
       }
       const int rc = min(readlane(rreg, i & 63), alpha - 1);
       // column -1: V(i, -1) and the scan term of M(i, -1)
-      const int cv_in = t ? readlane(crv, i & 63) : (MODE == 0 ? -(go + i * ge) : 0);
-      const int cp_in = t ? readlane(crp, i & 63) : (MODE == 0 ? kNeg : -ge);
+      const int cv_in = t ? readlane(crv, i & 63) : (EM::kColFree ? 0 : -(go + i * ge));
+      const int cp_in = t ? readlane(crp, i & 63) : (EM::kColFree ? -ge : kNeg);
       int Mv[C];
       const int d0 = dpp_wave_shr1(cv_prev, Vp[C - 1]);
 #pragma unroll
@@ -460,22 +506,33 @@ __device__ __forceinline__ void endtoend_one(const EndArgs &a, const TracePair &
 #pragma unroll
         for (int c = 1; c < C; ++c)
           if (jb == c) v = Vp[c];
-        if (MODE == 1 && v > best) {
+        if (EM::kEndCol && (MODE == 1 || i < A - 1) && v > best) {
           best = v;
           best_row = i;
         }
         score = v;
       }
+      if (EM::kEndRow && i == A - 1) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+          if (jc0 + c < B && Vp[c] > rbest) {
+            rbest = Vp[c];
+            rcol = jc0 + c;
+          }
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");   // carries before tile t + 1
   }
   bad = __ballot(bad) != 0;
+  if (EM::kEndRow) argmax_first<64>(rbest, rcol);
   const int jb = B - 1 - (T - 1) * TC - C * L;
   if (jb >= 0 && jb < C) {
     DevResult r;
-    r.score = MODE == 0 ? score : best;
-    r.qend = B - 1;
-    r.rend = MODE == 0 ? A - 1 : best_row;
+    r.score = MODE == 0 ? score : MODE == 1 ? best : MODE == 2 ? rbest : max(best, rbest);
+    // overlap: a last-column end precedes every last-row end in (ref, query) order
+    const bool on_col = MODE == 0 || MODE == 1 || (MODE == 3 && best >= rbest);
+    r.qend = on_col ? B - 1 : rcol;
+    r.rend = MODE == 0 ? A - 1 : on_col ? best_row : A - 1;
     r.flags = bad ? kFlagBadResidue : 0;
     a.out[P.id] = r;
   }
@@ -499,6 +556,7 @@ __device__ __forceinline__ int half_max_scan(int x) {
 template <int MODE, int C>
 __device__ __forceinline__ void endtoend_two(const EndArgs &a, const TracePair &P0,
                                              const TracePair &P1, bool has1, const int *smat) {
+  using EM = EndMode<MODE>;
   const int L = threadIdx.x, l = L & 31;
   const bool h = L >= 32;
   const int alpha = a.alpha, go = a.go, ge = a.ge;
@@ -517,12 +575,13 @@ __device__ __forceinline__ void endtoend_two(const EndArgs &a, const TracePair &
     const int code = jc0 + c < B ? (int)a.qres[pq + jc0 + c] : 0;
     bad |= code >= alpha;
     qb[c] = min(code, alpha - 1) * alpha;
-    Vp[c] = Gp[c] = -(go + (jc0 + c) * ge);
+    Vp[c] = Gp[c] = EM::kRowFree ? 0 : -(go + (jc0 + c) * ge);
     Fp[c] = kNeg;
     wj[c] = (jc0 + c) * ge;
     ej[c] = go + (jc0 + c - 1) * ge;
   }
-  int best = -(go + (B - 1) * ge), best_row = -1, score = 0;
+  int best = EM::kRowFree ? 0 : -(go + (B - 1) * ge), best_row = -1, score = 0;
+  int rbest = EM::kColFree ? 0 : -(go + (A - 1) * ge), rcol = -1;
   int cv_prev = 0, rreg = 0;
   for (int i = 0; i < Amax; ++i) {
     if ((i & 31) == 0) {                     // 32 rows of each pair's residues at a time
@@ -532,8 +591,8 @@ __device__ __forceinline__ void endtoend_two(const EndArgs &a, const TracePair &
     }
     const int r0 = readlane(rreg, i & 31), r1 = readlane(rreg, 32 + (i & 31));
     const int rc = min(h ? r1 : r0, alpha - 1);
-    const int cv_in = MODE == 0 ? -(go + i * ge) : 0;
-    const int cp_in = MODE == 0 ? kNeg : -ge;
+    const int cv_in = EM::kColFree ? 0 : -(go + i * ge);
+    const int cp_in = EM::kColFree ? -ge : kNeg;
     const int dsh = dpp_wave_shr1(cv_prev, Vp[C - 1]);
     const int d0 = l == 0 ? cv_prev : dsh;
     int Mv[C];
@@ -563,21 +622,31 @@ __device__ __forceinline__ void endtoend_two(const EndArgs &a, const TracePair &
     for (int c = 1; c < C; ++c)
       if (jb == c) v = Vp[c];
     if (i < A) {
-      if (MODE == 1 && v > best) {
+      if (EM::kEndCol && (MODE == 1 || i < A - 1) && v > best) {
         best = v;
         best_row = i;
       }
       score = v;
     }
+    if (EM::kEndRow && i == A - 1) {
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        if (jc0 + c < B && Vp[c] > rbest) {
+          rbest = Vp[c];
+          rcol = jc0 + c;
+        }
+    }
   }
   const uint64_t bb = __ballot(bad);
   const bool bad_h = h ? (bb >> 32) != 0 : (bb & 0xffffffffull) != 0;
+  if (EM::kEndRow) argmax_first<32>(rbest, rcol);   // within each 32-lane half
   const int jb = B - 1 - jc0;
   if (jb >= 0 && jb < C && (!h || has1)) {
     DevResult r;
-    r.score = MODE == 0 ? score : best;
-    r.qend = B - 1;
-    r.rend = MODE == 0 ? A - 1 : best_row;
+    r.score = MODE == 0 ? score : MODE == 1 ? best : MODE == 2 ? rbest : max(best, rbest);
+    const bool on_col = MODE == 0 || MODE == 1 || (MODE == 3 && best >= rbest);
+    r.qend = on_col ? B - 1 : rcol;
+    r.rend = MODE == 0 ? A - 1 : on_col ? best_row : A - 1;
     r.flags = bad_h ? kFlagBadResidue : 0;
     a.out[pid] = r;
   }
@@ -652,23 +721,27 @@ size_t endtoend_lds_bytes(int alpha) { return (size_t)dev::mat_words(alpha) * si
 hipError_t launch_endtoend2(int mode, const EndArgs &a, hipStream_t st) {
   if (a.n <= 0) return hipSuccess;
   const int grid = (int)std::min<int64_t>(((int64_t)a.n + 1) / 2, 1 << 30);
-  if (mode == 0)
-    hipLaunchKernelGGL(dev::endtoend2_kernel<0>, dim3(grid), dim3(64), endtoend_lds_bytes(a.alpha),
-                       st, a);
-  else
-    hipLaunchKernelGGL(dev::endtoend2_kernel<1>, dim3(grid), dim3(64), endtoend_lds_bytes(a.alpha),
-                       st, a);
+  const size_t lds = endtoend_lds_bytes(a.alpha);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(dev::endtoend2_kernel<0>, dim3(grid), dim3(64), lds, st, a); break;
+    case 1: hipLaunchKernelGGL(dev::endtoend2_kernel<1>, dim3(grid), dim3(64), lds, st, a); break;
+    case 2: hipLaunchKernelGGL(dev::endtoend2_kernel<2>, dim3(grid), dim3(64), lds, st, a); break;
+    case 3: hipLaunchKernelGGL(dev::endtoend2_kernel<3>, dim3(grid), dim3(64), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st) {
   if (a.n <= 0 || grid <= 0) return hipSuccess;
-  if (mode == 0)
-    hipLaunchKernelGGL(dev::endtoend_kernel<0>, dim3(grid), dim3(64), endtoend_lds_bytes(a.alpha),
-                       st, a);
-  else
-    hipLaunchKernelGGL(dev::endtoend_kernel<1>, dim3(grid), dim3(64), endtoend_lds_bytes(a.alpha),
-                       st, a);
+  const size_t lds = endtoend_lds_bytes(a.alpha);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(dev::endtoend_kernel<0>, dim3(grid), dim3(64), lds, st, a); break;
+    case 1: hipLaunchKernelGGL(dev::endtoend_kernel<1>, dim3(grid), dim3(64), lds, st, a); break;
+    case 2: hipLaunchKernelGGL(dev::endtoend_kernel<2>, dim3(grid), dim3(64), lds, st, a); break;
+    case 3: hipLaunchKernelGGL(dev::endtoend_kernel<3>, dim3(grid), dim3(64), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -195,7 +195,7 @@ def test_global_rejects_bad_arguments(lib):
     assert lib.sw_align_batch_global(None, ctypes.byref(sc), 0, out.ctypes.data) == api.SW_EINVAL
     b.n_pairs = 0
     assert lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), 0, None) == api.SW_OK
-    assert lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), 2,
+    assert lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), 4,
                                      out.ctypes.data) == api.SW_EINVAL        # no such mode
     b.n_pairs = 1                                   # arrays missing
     assert lib.sw_align_batch_global(ctypes.byref(b), ctypes.byref(sc), 1,
@@ -207,14 +207,16 @@ def test_global_cigar_rejects_bad_arguments(lib):
     sc, keep = _sc(M)
     b = api.Batch()
     off = np.full(3, 7, dtype=np.int64)
-    assert lib.sw_align_batch_global_cigar(None, ctypes.byref(sc), 0, None, None, None, 0,
-                                           off.ctypes.data) == api.SW_EINVAL
+    assert lib.sw_align_batch_global_cigar(None, ctypes.byref(sc), 0, None, None, None, None,
+                                           0, off.ctypes.data) == api.SW_EINVAL
     b.n_pairs = 0
-    assert lib.sw_align_batch_global_cigar(ctypes.byref(b), ctypes.byref(sc), 1, None, None,
-                                           None, 0, off.ctypes.data) == api.SW_OK
-    assert off[0] == 0
+    for mode in (0, 1, 2, 3):
+        off[0] = 7
+        assert lib.sw_align_batch_global_cigar(ctypes.byref(b), ctypes.byref(sc), mode, None,
+                                               None, None, None, 0, off.ctypes.data) == api.SW_OK
+        assert off[0] == 0
     assert lib.sw_align_batch_global_cigar(ctypes.byref(b), ctypes.byref(sc), 4, None, None,
-                                           None, 0, off.ctypes.data) == api.SW_EINVAL
+                                           None, None, 0, off.ctypes.data) == api.SW_EINVAL
 
 
 def test_noalloc_rejects_bad_arguments(lib):

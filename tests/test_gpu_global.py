@@ -1,6 +1,8 @@
-"""End-to-end scores (sw_align_batch_global): global and semi-global (query
-end to end, reference ends free) results equal the CPU oracle's exactly --
-score, query_end and the smallest optimal reference end -- through the C ABI."""
+"""End-to-end scores (sw_align_batch_global) and paths
+(sw_align_batch_global_cigar) in every mode -- global, semi-global with the
+query fitted (reference ends free) or the reference fitted (query ends free),
+overlap (free end gaps) -- equal the CPU oracle's exactly through the C ABI:
+score, end cell (the mode's tie rule), start element and runs."""
 import numpy as np
 import pytest
 
@@ -8,7 +10,8 @@ import oracle
 from paper_1909_00899_amd import api, workloads as W
 
 pytestmark = pytest.mark.gpu
-MODES = [api.SW_MODE_GLOBAL, api.SW_MODE_SEMIGLOBAL]
+MODES = [api.SW_MODE_GLOBAL, api.SW_MODE_SEMIGLOBAL, api.SW_MODE_SEMIGLOBAL_REF,
+         api.SW_MODE_OVERLAP]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -150,11 +153,11 @@ def test_device_resident_inputs_and_errors():
 
 def _paths(w, mode, **kw):
     res = _run(w, mode)
-    rs, runs, off = api.sw_align_batch_global_cigar(w.query_res, w.query_off, w.ref_res,
-                                                    w.ref_off, w.pair_ref, w.matrix, w.gap_open,
-                                                    w.gap_extend, res, mode=mode,
-                                                    pair_query=w.pair_query, **kw)
-    return res, rs, runs, off
+    qs, rs, runs, off = api.sw_align_batch_global_cigar(w.query_res, w.query_off, w.ref_res,
+                                                        w.ref_off, w.pair_ref, w.matrix,
+                                                        w.gap_open, w.gap_extend, res, mode=mode,
+                                                        pair_query=w.pair_query, **kw)
+    return res, qs, rs, runs, off
 
 
 def _seqs(w, k):
@@ -165,14 +168,14 @@ def _seqs(w, k):
 
 
 def _check_paths(w, mode, label, pairs=None):
-    res, rs, runs, off = _paths(w, mode)
+    res, qs, rs, runs, off = _paths(w, mode)
     for k in (range(w.n_pairs) if pairs is None else pairs):
         q, r = _seqs(w, k)
         want = oracle.endtoend_path(q, r, w.matrix, w.gap_open, w.gap_extend, mode,
                                     end=tuple(int(x) for x in res[k, :3]))
-        got = (0, int(rs[k]), api.decode_cigar(runs, off, k))   # query_start 0 in these modes
+        got = (int(qs[k]), int(rs[k]), api.decode_cigar(runs, off, k))
         assert got == want, "%s mode %d pair %d: got %s want %s" % (label, mode, k, got, want)
-    return res, rs, runs, off
+    return res, qs, rs, runs, off
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -205,12 +208,21 @@ def test_paths_dna_reads_in_windows():
     # semi-global: each read placed inside its window; the path consumes the
     # read and r[ref_start .. ref_end]
     w = W.dna_pairs(n_pairs=400, seed=27)
-    res, rs, runs, off = _check_paths(w, api.SW_MODE_SEMIGLOBAL, "dna", pairs=range(0, 400, 40))
+    res, qs, rs, runs, off = _check_paths(w, api.SW_MODE_SEMIGLOBAL, "dna",
+                                          pairs=range(0, 400, 40))
     for k in range(w.n_pairs):
         got = api.decode_cigar(runs, off, k)
-        assert sum(n for n, o in got if o in "MI") == 150
+        assert qs[k] == 0 and sum(n for n, o in got if o in "MI") == 150
         assert sum(n for n, o in got if o in "MD") == res[k, 2] - rs[k] + 1
     _check_paths(w, api.SW_MODE_GLOBAL, "dna", pairs=range(0, 400, 100))
+    _check_paths(w, api.SW_MODE_OVERLAP, "dna", pairs=range(0, 400, 100))
+    # the roles swapped: each read is the reference, fitted into its window
+    sw = W.Workload("dna_swapped", w.ref_res, w.ref_off, w.query_res, w.query_off,
+                    w.pair_ref.copy(), w.pair_query.copy(), w.matrix, w.gap_open, w.gap_extend)
+    res2, qs2, rs2, runs2, off2 = _check_paths(sw, api.SW_MODE_SEMIGLOBAL_REF, "dna swapped",
+                                               pairs=range(0, 400, 40))
+    assert (res2[:, 0] == res[:, 0]).all() and (res2[:, 1] == res[:, 2]).all()
+    assert (qs2 == rs).all() and (rs2 == 0).all()
 
 
 def test_paths_errors():
@@ -230,8 +242,8 @@ def test_paths_errors():
         api.sw_align_batch_global_cigar(*args, bad, mode=api.SW_MODE_GLOBAL,
                                         pair_query=w.pair_query)
     assert e.value.code == api.SW_EINVAL
-    rs, runs, off = api.sw_align_batch_global_cigar(*args, res, mode=api.SW_MODE_GLOBAL,
-                                                    pair_query=w.pair_query)
+    qs, rs, runs, off = api.sw_align_batch_global_cigar(*args, res, mode=api.SW_MODE_GLOBAL,
+                                                        pair_query=w.pair_query)
     with pytest.raises(api.SwError) as e:
         api.sw_align_batch_global_cigar(*args, res, mode=api.SW_MODE_GLOBAL,
                                         pair_query=w.pair_query, cigar_cap=int(off[-1]) - 1)
@@ -247,14 +259,15 @@ def test_paths_device_resident_inputs():
          t(w.ref_off, torch.int64), t(w.pair_ref, torch.int32))
     pq = t(w.pair_query, torch.int32)
     for mode in MODES:
-        res, rs, runs, off = _paths(w, mode)
+        res, qs, rs, runs, off = _paths(w, mode)
         res_d = api.sw_align_batch_global(*d, w.matrix, w.gap_open, w.gap_extend, mode=mode,
                                           pair_query=pq)
         assert (res_d == res).all()
-        rs_d, runs_d, off_d = api.sw_align_batch_global_cigar(*d, w.matrix, w.gap_open,
-                                                              w.gap_extend, res_d, mode=mode,
-                                                              pair_query=pq)
-        assert (rs_d == rs).all() and (off_d == off).all() and (runs_d == runs).all()
+        qs_d, rs_d, runs_d, off_d = api.sw_align_batch_global_cigar(*d, w.matrix, w.gap_open,
+                                                                    w.gap_extend, res_d,
+                                                                    mode=mode, pair_query=pq)
+        assert (qs_d == qs).all() and (rs_d == rs).all()
+        assert (off_d == off).all() and (runs_d == runs).all()
 
 
 def test_largest_alphabet_and_overflow_refusal():
@@ -273,3 +286,58 @@ def test_largest_alphabet_and_overflow_refusal():
     with pytest.raises(api.SwError) as e:
         _run(wb, api.SW_MODE_GLOBAL)
     assert e.value.code == api.SW_EOVERFLOW
+
+
+def test_overlap_dovetails_and_reference_fitted_reads():
+    # reads that hang off either end of their window: the overlap places the
+    # shared part, paying nothing for the overhangs; the same pairs fitted the
+    # other way round (the window inside the read) and globally for contrast
+    rng = np.random.default_rng(1050)
+    qs, rs = [], []
+    for k in range(300):
+        L = int(rng.integers(40, 120))
+        core = rng.integers(0, 4, size=L, dtype=np.uint8)
+        hang_q = rng.integers(0, 4, size=int(rng.integers(0, 60)), dtype=np.uint8)
+        hang_r = rng.integers(0, 4, size=int(rng.integers(0, 60)), dtype=np.uint8)
+        if k % 3 == 0:       # the read's suffix is the window's prefix
+            q, r = np.concatenate([hang_q, core]), np.concatenate([core, hang_r])
+        elif k % 3 == 1:     # the read's prefix is the window's suffix
+            q, r = np.concatenate([core, hang_q]), np.concatenate([hang_r, core])
+        else:                # the window inside the read
+            q, r = np.concatenate([hang_q, core, hang_r]), core.copy()
+        qs.append(q)
+        rs.append(r)
+    qoff = np.zeros(301, dtype=np.int64)
+    roff = np.zeros(301, dtype=np.int64)
+    np.cumsum([q.size for q in qs], out=qoff[1:])
+    np.cumsum([r.size for r in rs], out=roff[1:])
+    idx = np.arange(300, dtype=np.int32)
+    w = W.Workload("dovetails", np.concatenate(qs), qoff, np.concatenate(rs), roff, idx,
+                   idx.copy(), W.dna_matrix(), 6, 1, {})
+    ov = _check(w, api.SW_MODE_OVERLAP, "dovetail")
+    assert (ov[:, 0] >= 40).all()                  # at least the shared part, overhangs free
+    sr = _check(w, api.SW_MODE_SEMIGLOBAL_REF, "window in read")
+    assert (sr[2::3, 0] == np.array([r.size for r in rs[2::3]])).all()   # exact match of the window
+    _check(w, api.SW_MODE_GLOBAL, "global")
+    assert (ov[:, 0] >= sr[:, 0]).all()
+    _check_paths(w, api.SW_MODE_OVERLAP, "dovetail paths", pairs=range(0, 300, 7))
+    _check_paths(w, api.SW_MODE_SEMIGLOBAL_REF, "window paths", pairs=range(0, 300, 7))
+
+
+def test_overlap_and_reference_fitted_end_errors():
+    w = W.random_pairs(30, 4, (5, 40), (5, 40), 1060)
+    args = (w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref, w.matrix, w.gap_open,
+            w.gap_extend)
+    for mode in (api.SW_MODE_SEMIGLOBAL_REF, api.SW_MODE_OVERLAP):
+        res = _run(w, mode)
+        bad = res.copy()
+        bad[4, 1] = np.diff(w.query_off)[4] - 2
+        bad[4, 2] = np.diff(w.ref_off)[4] - 2      # on neither sequence's last residue
+        with pytest.raises(api.SwError) as e:
+            api.sw_align_batch_global_cigar(*args, bad, mode=mode, pair_query=w.pair_query)
+        assert e.value.code == api.SW_EINVAL
+        bad = res.copy()
+        bad[6, 0] += 1                             # not the optimum there
+        with pytest.raises(api.SwError) as e:
+            api.sw_align_batch_global_cigar(*args, bad, mode=mode, pair_query=w.pair_query)
+        assert e.value.code == api.SW_EINVAL
