@@ -530,11 +530,16 @@ def bench_long_queries(args):
             sub = full.subset(np.array(idx))
             d, pq = _device_batch(sub)
             res = {}
-            for alg, name in ((api.SW_ALG_SCAN, "scan"), (api.SW_ALG_LAZYF, "lazyf")):
+            # the scan with two int32 chains per sub-group (the default), with
+            # one chain, and the lazy-F comparator
+            for alg, name, chains in ((api.SW_ALG_SCAN, "scan", api.SW_CHAINS_TWO),
+                                      (api.SW_ALG_SCAN, "scan_one_chain", api.SW_CHAINS_ONE),
+                                      (api.SW_ALG_LAZYF, "lazyf", api.SW_CHAINS_AUTO)):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 out = api.sw_align_batch(*d, sub.matrix, sub.gap_open, sub.gap_extend,
-                                         pair_query=pq, precision=api.SW_PREC_I32, algorithm=alg)
+                                         pair_query=pq, precision=api.SW_PREC_I32, algorithm=alg,
+                                         int32_chains=chains)
                 wall = time.perf_counter() - t0
                 st = out.stats
                 res[name] = {"gcups": round(sub.cells() / wall / 1e9, 1),
@@ -556,6 +561,14 @@ def bench_long_queries(args):
                 "query_lens": [int(full.query_off[q + 1] - full.query_off[q]) for q in qsel],
                 "scan_gcups": res["scan"]["gcups"], "lazyf_gcups": lz["gcups"],
                 "scan_kernel_gcups": res["scan"]["kernel_gcups"],
+                "scan_kernel_frac_i32": round(res["scan"]["kernel_gcups"] * OPS_PER_CELL /
+                                              (PEAK_I32_TOPS * 1e3), 4),
+                "scan_one_chain_gcups": res["scan_one_chain"]["gcups"],
+                "scan_one_chain_kernel_gcups": res["scan_one_chain"]["kernel_gcups"],
+                "scan_one_chain_kernel_frac_i32": round(
+                    res["scan_one_chain"]["kernel_gcups"] * OPS_PER_CELL / (PEAK_I32_TOPS * 1e3), 4),
+                "two_chains_equal_one": bool(np.array_equal(res["scan"]["results"],
+                                                            res["scan_one_chain"]["results"])),
                 "lazyf_kernel_gcups": lz["kernel_gcups"],
                 "lazyf_passes_per_column": round(passes, 3),
                 "scan_equals_lazyf": bool(np.array_equal(res["scan"]["results"], lz["results"])),

@@ -353,8 +353,17 @@ typedef struct {
                                     launches, where AUTO lets the cost model
                                     choose (row pairs need int16 lanes and an
                                     alphabet of at most 24 letters)             */
-    int32_t reserved[7];
+    int32_t int32_chains;        /* int32 lanes of the shared-query kernel (one
+                                    query against many references, scan
+                                    algorithm): alignments per sub-group.
+                                    SW_CHAINS_AUTO = the library's default (one);
+                                    SW_CHAINS_ONE = one; SW_CHAINS_TWO = two
+                                    independent column chains, each with its
+                                    own state, interleaved in one instruction
+                                    stream (results are the same either way)   */
+    int32_t reserved[6];
 } sw_options;
+enum { SW_CHAINS_AUTO = 0, SW_CHAINS_ONE = 1, SW_CHAINS_TWO = 2 };
 
 typedef struct {
     double kernel_ms;            /* device time of the alignment kernels (hipEvents) */

@@ -265,7 +265,8 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
     if (opt->force_seglen < 0 || opt->int16_cap < 0 || opt->int16_cap > 32767 ||
         opt->mixed_layout < 0 || opt->mixed_layout > 2 || opt->use_graph < 0 || opt->use_graph > 1 ||
         opt->force_kernel < 0 || opt->force_kernel > 2 || opt->planner < 0 || opt->planner > 2 ||
-        opt->lane_pairing < 0 || opt->lane_pairing > 2) {
+        opt->lane_pairing < 0 || opt->lane_pairing > 2 || opt->int32_chains < 0 ||
+        opt->int32_chains > 2) {
       set_error("bad option value");
       return SW_EINVAL;
     }
@@ -276,6 +277,7 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
     eo.mixed_layout = opt->mixed_layout;
     eo.use_graph = opt->use_graph;
     eo.lane_pairing = opt->lane_pairing;
+    eo.int32_chains = opt->int32_chains;
     if (opt->int16_cap) eo.int16_cap = opt->int16_cap;
   }
   if (stats) std::memset(stats, 0, sizeof(*stats));

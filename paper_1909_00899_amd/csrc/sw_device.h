@@ -827,6 +827,277 @@ void shared_kernel(KArgs a, uint32_t mode_mask) {
   }
 }
 
+// ================================================================ two chains per sub-group (int32)
+
+// int32 lanes carry one alignment each, so a sub-group's column step is one
+// dependent chain (profile reads, the inner loop's F and Hin carries, the
+// scan's DPP steps).  Two alignments per sub-group -- the task's even and odd
+// slot, each with its own state, residue and chunk boundaries -- give every
+// step an independent twin the compiler interleaves with it, and share the
+// per-column work that does not depend on the alignment (residue words, loop
+// control, the record test): the explicit interleave of two Smith-Waterman
+// executions that the paper's closing remarks propose, where int16 lanes get
+// it from their two halves.
+
+// Record of both chains under one branch: a lane whose maximum improves in a
+// chain copies that chain's H (as record()).
+template <int SEG>
+__device__ __forceinline__ void record_dual(State<SEG> &s0, State<SEG> &s1, uint32_t c0,
+                                            uint32_t c1, int i) {
+  using O = OpsI32;
+  const uint32_t n0 = O::vmax(s0.G, c0), n1 = O::vmax(s1.G, c1);
+  if (__any(n0 != s0.G || n1 != s1.G)) {
+    ++s0.events;
+    const uint32_t m0 = n0 != s0.G ? 0xffffffffu : 0u;
+    const uint32_t m1 = n1 != s1.G ? 0xffffffffu : 0u;
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      s0.snap[j] = (s0.H[j] & m0) | (s0.snap[j] & ~m0);
+      s1.snap[j] = (s1.H[j] & m1) | (s1.snap[j] & ~m1);
+    }
+    if (m0) s0.rc[0] = i;
+    if (m1) s1.rc[0] = i;
+    s0.S = (n0 & m0) | (s0.S & ~m0);
+    s1.S = (n1 & m1) | (s1.S & ~m1);
+    s0.G = n0;
+    s1.G = n1;
+  }
+}
+
+// One column step (Algorithm 6, as column()) of two independent alignments of
+// the sub-group: chain 0 against the residue at profile base b0, chain 1 at b1.
+template <int SEG, int PMAX, bool CHUNKED, class Prof>
+__device__ __forceinline__ void column_dual(State<SEG> &s0, State<SEG> &s1, const LaneCtx &L,
+                                            const Params &pr, const Prof &pf, uint32_t b0,
+                                            uint32_t b1, uint32_t hin0, uint32_t fin0,
+                                            uint32_t hin1, uint32_t fin1, uint32_t &ho0,
+                                            uint32_t &fo0, uint32_t &ho1, uint32_t &fo1, int i) {
+  using O = OpsI32;
+  uint32_t Fj0 = s0.Fscan, Fj1 = s1.Fscan;
+  const uint32_t hl0 = O::vmax(s0.H[SEG - 1], O::usub(Fj0, pr.wlast));
+  const uint32_t hl1 = O::vmax(s1.H[SEG - 1], O::usub(Fj1, pr.wlast));
+  ho0 = hl0;
+  ho1 = hl1;
+  uint32_t Hin0 = shift1<PMAX, CHUNKED>(hl0, L, hin0);
+  uint32_t Hin1 = shift1<PMAX, CHUNKED>(hl1, L, hin1);
+  uint32_t F0 = 0, F1 = 0, c0 = 0, c1 = 0;
+#pragma unroll
+  for (int j = 0; j < SEG; ++j) {
+    const uint32_t p0 = pf.load(b0, b0, j), p1 = pf.load(b1, b1, j);
+    const uint32_t hd0 = O::hadd(Hin0, p0), hd1 = O::hadd(Hin1, p1);
+    c0 = j == 0 ? hd0 : O::vmax(c0, hd0);
+    c1 = j == 0 ? hd1 : O::vmax(c1, hd1);
+    const uint32_t h0 = O::vmax(O::vmax(hd0, s0.E[j]), F0);
+    const uint32_t h1 = O::vmax(O::vmax(hd1, s1.E[j]), F1);
+    const uint32_t o0 = s0.H[j], o1 = s1.H[j];
+    s0.H[j] = h0;
+    s1.H[j] = h1;
+    const uint32_t t0 = O::usub(h0, pr.go), t1 = O::usub(h1, pr.go);
+    s0.E[j] = O::vmax(O::usub(s0.E[j], pr.ge), t0);
+    s1.E[j] = O::vmax(O::usub(s1.E[j], pr.ge), t1);
+    F0 = O::vmax(O::usub(F0, pr.ge), t0);
+    F1 = O::vmax(O::usub(F1, pr.ge), t1);
+    if (j + 1 < SEG) {
+      Hin0 = O::vmax(o0, Fj0);
+      Hin1 = O::vmax(o1, Fj1);
+      Fj0 = O::usub(Fj0, pr.ge);
+      Fj1 = O::usub(Fj1, pr.ge);
+    }
+  }
+  // the two max-plus scans, step by step side by side
+  uint32_t G0 = F0, G1 = F1;
+  if constexpr (CHUNKED) {
+    G0 = O::vmax(G0, O::usub(fin0, L.wcarry));
+    G1 = O::vmax(G1, O::usub(fin1, L.wcarry));
+  }
+  G0 = O::vmax(G0, O::usub(dpp<kRowShr1>(G0), pr.w1));
+  G1 = O::vmax(G1, O::usub(dpp<kRowShr1>(G1), pr.w1));
+  G0 = O::vmax(G0, O::usub(dpp<kRowShr2>(G0), pr.w2));
+  G1 = O::vmax(G1, O::usub(dpp<kRowShr2>(G1), pr.w2));
+  G0 = O::vmax(G0, O::usub(dpp<kRowShr4>(G0), pr.w4));
+  G1 = O::vmax(G1, O::usub(dpp<kRowShr4>(G1), pr.w4));
+  G0 = O::vmax(G0, O::usub(dpp<kRowShr8>(G0), pr.w8));
+  G1 = O::vmax(G1, O::usub(dpp<kRowShr8>(G1), pr.w8));
+  if constexpr (PMAX >= 32) {
+    G0 = O::vmax(G0, O::usub(dpp<kRowBcast15, 0xa, false>(G0), L.w16));
+    G1 = O::vmax(G1, O::usub(dpp<kRowBcast15, 0xa, false>(G1), L.w16));
+  }
+  if constexpr (PMAX >= 64) {
+    G0 = O::vmax(G0, O::usub(dpp<kRowBcast31, 0xc, false>(G0), L.w32));
+    G1 = O::vmax(G1, O::usub(dpp<kRowBcast31, 0xc, false>(G1), L.w32));
+  }
+  fo0 = G0;
+  fo1 = G1;
+  s0.Fscan = shift1<PMAX, CHUNKED>(G0, L, fin0);
+  s1.Fscan = shift1<PMAX, CHUNKED>(G1, L, fin1);
+  record_dual<SEG>(s0, s1, c0, c1, i);
+}
+
+// run_columns() for two chains: chain h reads residue word half h (the
+// task's slot 2*sg + h) and, when chunked, its own boundary arrays.
+template <int SEG, int PMAX, bool CHUNKED, class ProfMap, class Src>
+__device__ __forceinline__ void run_columns_dual(State<SEG> &s0, State<SEG> &s1, const LaneCtx &L,
+                                                 const Params &pr, const ProfMap &pm,
+                                                 const Src &src, int ncols,
+                                                 const uint32_t *const hb_in[2],
+                                                 const uint32_t *const fb_in[2],
+                                                 uint32_t *const hb_out[2],
+                                                 uint32_t *const fb_out[2]) {
+  using O = OpsI32;
+  const int nblk = ncols / kBlock;
+  uint32_t ev_shared = s0.events;
+  uint2 rc = src.get(0);
+  uint2 rn = src.get(1);
+  for (int b = 0; b < nblk; ++b) {
+    const uint2 r = rc;
+    rc = rn;
+    rn = src.get(b + 2);
+    uint4 h0 = make_uint4(0, 0, 0, 0), f0 = h0, h1 = h0, f1 = h0;
+    if constexpr (CHUNKED) {
+      h0 = ((const uint4 *)hb_in[0])[b];
+      f0 = ((const uint4 *)fb_in[0])[b];
+      h1 = ((const uint4 *)hb_in[1])[b];
+      f1 = ((const uint4 *)fb_in[1])[b];
+    }
+    const uint32_t hi0[kBlock] = {h0.x, h0.y, h0.z, h0.w}, fi0[kBlock] = {f0.x, f0.y, f0.z, f0.w};
+    const uint32_t hi1[kBlock] = {h1.x, h1.y, h1.z, h1.w}, fi1[kBlock] = {f1.x, f1.y, f1.z, f1.w};
+    uint32_t ho0[kBlock], fo0[kBlock], ho1[kBlock], fo1[kBlock];
+#pragma unroll
+    for (int k = 0; k < kBlock; ++k) {
+      const uint32_t c0 = (r.x >> (8 * k)) & 0xffu;
+      const uint32_t c1 = (r.y >> (8 * k)) & 0xffu;
+      column_dual<SEG, PMAX, CHUNKED>(s0, s1, L, pr, pm.prof, pm.base_lo(c0), pm.base_hi(c1),
+                                      hi0[k], fi0[k], hi1[k], fi1[k], ho0[k], fo0[k], ho1[k],
+                                      fo1[k], b * kBlock + k);
+    }
+    if (hb_out[0] != nullptr && L.last) {
+      ((uint4 *)hb_out[0])[b] = make_uint4(ho0[0], ho0[1], ho0[2], ho0[3]);
+      ((uint4 *)fb_out[0])[b] = make_uint4(fo0[0], fo0[1], fo0[2], fo0[3]);
+      ((uint4 *)hb_out[1])[b] = make_uint4(ho1[0], ho1[1], ho1[2], ho1[3]);
+      ((uint4 *)fb_out[1])[b] = make_uint4(fo1[0], fo1[1], fo1[2], fo1[3]);
+    }
+    if (s0.events != ev_shared) {
+      share_threshold<O, SEG, PMAX>(s0, L);
+      share_threshold<O, SEG, PMAX>(s1, L);
+      ev_shared = s0.events;
+    }
+  }
+}
+
+// Previous query chunks' merged result of one slot (int32: one half).
+__device__ __forceinline__ void prev_load_slot(Prev &p, int pid, const PairInfo *pairs,
+                                               const DevResult *results) {
+  prev_reset(p);
+  if (pid >= 0) {
+    const DevResult r = results[pairs[pid].out];
+    if (r.score > 0) { p.s[0] = r.score; p.c[0] = r.rend; p.r[0] = r.qend; }
+    p.f[0] = r.flags;
+  }
+}
+
+// One task of the shared-query kernel with two int32 chains per sub-group.
+// Chunk boundaries: [8 slots][ncols] H words, then [8 slots][ncols] F words.
+template <int SEG, int P, bool CHUNKED>
+__device__ __forceinline__ void shared_task_dual(const KArgs &a, const Task &t, const Task *tp,
+                                                 uint32_t prof_off, unsigned long long &cols,
+                                                 unsigned long long &events) {
+  using O = OpsI32;
+  const LaneCtx L = make_lane<O>(t.layout, SEG, (uint32_t)a.gap_extend);
+  const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
+  SharedMap<O, SEG, P> pm;
+  pm.lane_base = prof_off + L.l * O::kES;
+  const int pid0 = tp->pair[2 * L.sg], pid1 = tp->pair[2 * L.sg + 1];
+  Prev prev0, prev1;
+  prev_reset(prev0);
+  prev_reset(prev1);
+  if (CHUNKED && a.chunk > 0) {
+    prev_load_slot(prev0, pid0, a.pairs, a.results);
+    prev_load_slot(prev1, pid1, a.pairs, a.results);
+  }
+  State<SEG> s0, s1;
+  state_reset(s0, prev_g0<O>(prev0));
+  state_reset(s1, prev_g0<O>(prev1));
+  const uint32_t *hb_in[2] = {nullptr, nullptr}, *fb_in[2] = {nullptr, nullptr};
+  uint32_t *hb_out[2] = {nullptr, nullptr}, *fb_out[2] = {nullptr, nullptr};
+  if constexpr (CHUNKED) {
+    const int64_t fofs = 8ll * t.ncols;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t base = t.bnd_off + (int64_t)(2 * L.sg + h) * t.ncols;
+      hb_in[h] = a.bnd_in + base;
+      fb_in[h] = a.bnd_in + base + fofs;
+      if (!a.last_chunk) {
+        hb_out[h] = a.bnd_out + base;
+        fb_out[h] = a.bnd_out + base + fofs;
+      }
+    }
+  }
+  const StreamSrc src{(const uint2 *)(a.streams + t.stream_off) + L.sg};
+  run_columns_dual<SEG, P, CHUNKED>(s0, s1, L, pr, pm, src, t.ncols, hb_in, fb_in, hb_out,
+                                    fb_out);
+  cols += (unsigned long long)t.ncols;
+  events += s0.events;
+  const int p0[2] = {pid0, -1}, p1[2] = {pid1, -1};
+  finish<O, SEG>(s0, L, p0, a.pairs, a.results, a.chunk * P * SEG, prev0, a.sat_cap);
+  finish<O, SEG>(s1, L, p1, a.pairs, a.results, a.chunk * P * SEG, prev1, a.sat_cap);
+}
+
+// shared_kernel for int32 with two chains per sub-group (scan algorithm).
+// Two chains need twice the state registers: up to 16 rows per lane that is
+// more than 128 VGPRs, so the kernel is built for two wavefronts per SIMD (each
+// with the work of two).
+template <int S16, int S32, int S64, bool CHUNKED>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2)))
+void shared_dual_kernel(KArgs a, uint32_t mode_mask) {
+  using O = OpsI32;
+  stage_matrix(a);
+  __syncthreads();
+  uint32_t off0 = 0, off1 = 0, off2 = 0;
+  uint32_t cur = matrix_lds_bytes(a.alpha);
+  const int nrow = a.alpha + 1;
+  if constexpr (S16 > 0) {
+    if (mode_mask & 1u) {
+      off0 = cur;
+      build_shared_profile<O, S16, 16>(a, cur);
+      cur += nrow * shared_cstride(S16, 16, O::kES);
+    }
+  }
+  if constexpr (S32 > 0) {
+    if (mode_mask & 2u) {
+      off1 = cur;
+      build_shared_profile<O, S32, 32>(a, cur);
+      cur += nrow * shared_cstride(S32, 32, O::kES);
+    }
+  }
+  if constexpr (S64 > 0) {
+    if (mode_mask & 4u) {
+      off2 = cur;
+      build_shared_profile<O, S64, 64>(a, cur);
+      cur += nrow * shared_cstride(S64, 64, O::kES);
+    }
+  }
+  __syncthreads();
+  unsigned long long cols = 0, events = 0;
+  for (;;) {
+    const int ti = pop_task(a.task_counter);
+    if (ti >= a.ntasks) break;
+    const Task t = a.tasks[ti];
+    if constexpr (S16 > 0) {
+      if (t.mode == 0) { shared_task_dual<S16, 16, CHUNKED>(a, t, a.tasks + ti, off0, cols, events); continue; }
+    }
+    if constexpr (S32 > 0) {
+      if (t.mode == 1) { shared_task_dual<S32, 32, CHUNKED>(a, t, a.tasks + ti, off1, cols, events); continue; }
+    }
+    if constexpr (S64 > 0) {
+      if (t.mode == 2) { shared_task_dual<S64, 64, CHUNKED>(a, t, a.tasks + ti, off2, cols, events); continue; }
+    }
+  }
+  if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
+    if (cols) atomicAdd(&a.stats[0], cols);
+    if (events) atomicAdd(&a.stats[2], events);
+  }
+}
+
 // ================================================================ device-planned shared-query kernel
 
 // One query (one chunk), one sub-group width.  Task t is entries

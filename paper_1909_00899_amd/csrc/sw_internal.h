@@ -117,7 +117,10 @@ struct SharedMenu { int seg16, seg32, seg64; };
 int shared_menu_count();
 SharedMenu shared_menu(int idx);
 size_t shared_lds_bytes(Prec prec, int menu, int alpha);
-hipError_t launch_shared(Prec prec, Alg alg, int menu, bool chunked, const KArgs &a,
+// dual: int32 lanes (scan algorithm) with two alignments per sub-group,
+// the task's even and odd slots, each with its own chunk boundaries
+// ([8 slots][ncols] H words, then F words).
+hipError_t launch_shared(Prec prec, Alg alg, int menu, bool chunked, bool dual, const KArgs &a,
                          int grid, hipStream_t st);
 
 // Per-pair kernel: each slot-half has its own query; profiles live in each

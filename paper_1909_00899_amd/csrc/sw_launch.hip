@@ -10,6 +10,8 @@ hipError_t launch_shared_i16(Alg alg, int menu, bool chunked, const KArgs &a, in
                              hipStream_t st, uint32_t mask, size_t lds);
 hipError_t launch_shared_i32(Alg alg, int menu, bool chunked, const KArgs &a, int grid,
                              hipStream_t st, uint32_t mask, size_t lds);
+hipError_t launch_shared_dual_i32(int menu, bool chunked, const KArgs &a, int grid,
+                                  hipStream_t st, uint32_t mask, size_t lds);
 hipError_t launch_pair_i16(int seg, int pmax, bool chunked, const KArgs &a, int grid,
                            hipStream_t st, size_t lds);
 hipError_t launch_pair_i32(int seg, int pmax, bool chunked, const KArgs &a, int grid,
@@ -490,11 +492,13 @@ size_t shared_lds_bytes(Prec prec, int menu, int alpha) {
   return b;
 }
 
-hipError_t launch_shared(Prec prec, Alg alg, int menu, bool chunked, const KArgs &a, int grid,
-                         hipStream_t st) {
+hipError_t launch_shared(Prec prec, Alg alg, int menu, bool chunked, bool dual, const KArgs &a,
+                         int grid, hipStream_t st) {
   if (menu < 0 || menu >= kNumSharedMenus) return hipErrorInvalidValue;
   const size_t lds = shared_lds_bytes(prec, menu, a.alpha);
-  if (prec == PREC_I16X2) return launch_shared_i16(alg, menu, chunked, a, grid, st, 7u, lds);
+  if (prec == PREC_I16X2) return dual ? hipErrorInvalidValue : launch_shared_i16(alg, menu, chunked, a, grid, st, 7u, lds);
+  if (dual) return alg == ALG_SCAN ? launch_shared_dual_i32(menu, chunked, a, grid, st, 7u, lds)
+                                   : hipErrorInvalidValue;
   return launch_shared_i32(alg, menu, chunked, a, grid, st, 7u, lds);
 }
 

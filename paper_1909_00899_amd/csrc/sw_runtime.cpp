@@ -239,8 +239,14 @@ int LengthIndex::slot(int m) {
 namespace {
 
 constexpr int64_t kI32Limit = 2147483647ll;
+// int32 shared-query launches run one chain per sub-group unless the options
+// ask for two: two chains need twice the state registers (about 200 VGPRs at
+// 16 rows per lane, two wavefronts per SIMD instead of four), and on the
+// long-query workload they ran at 0.48 of the int32 VALU bound against 0.72
+// for one chain -- the wavefronts in flight already provide the independent
+// instruction streams the interleave would add.
+constexpr bool kDualInt32Default = false;
 
-int slots_per_wave(Prec prec, int P) { return (prec == PREC_I16X2 ? 2 : 1) * (kWave / P); }
 
 // Approximate VALU instructions per column step of one wavefront.
 double step_cost(Prec prec, int P, int seg) {
@@ -276,6 +282,7 @@ void sort_by_n_desc(const PlanItem *items, size_t cnt, std::vector<int> &order,
 
 struct LaunchDesc {
   bool shared;
+  bool dual;         // shared, int32: two alignments per sub-group
   bool rp;           // per-pair: row pairs (pair_rowpair_kernel)
   int task_begin, task_end;
   int menu;          // shared
@@ -293,9 +300,12 @@ struct LaunchDesc {
 // stays short next to the average load of a wavefront (long references get
 // more lanes so they finish in time); consecutive pairs of one mode share a
 // task.  Tasks are emitted longest-first (by estimated cost) across modes.
-static void plan_shared(const PlanItem *items, size_t cnt, Prec prec, int menu, int num_waves,
-                        int force_lanes, HostScratch &hs, std::vector<Task> &tasks,
+static void plan_shared(const PlanItem *items, size_t cnt, Prec prec, bool dual, int menu,
+                        int num_waves, int force_lanes, HostScratch &hs, std::vector<Task> &tasks,
                         int mode_counts[3]) {
+  // alignments per sub-group: two int16 halves, or two int32 chains (dual)
+  const int halves = prec == PREC_I16X2 || dual ? 2 : 1;
+  auto spw_of = [&](int P) { return halves * (kWave / P); };
   const SharedMenu mm = shared_menu(menu);
   const int segs[3] = {mm.seg16, mm.seg32, mm.seg64};
   const int Ps[3] = {16, 32, 64};
@@ -306,7 +316,7 @@ static void plan_shared(const PlanItem *items, size_t cnt, Prec prec, int menu, 
     if (segs[k]) { narrow = k; break; }
   double total = 0;
   for (size_t k = 0; k < cnt; ++k) total += (double)items[k].n;
-  total *= step_cost(prec, Ps[narrow], segs[narrow]) / slots_per_wave(prec, Ps[narrow]);
+  total *= step_cost(prec, Ps[narrow], segs[narrow]) / spw_of(Ps[narrow]);
   const double per_wave = total / std::max(1, num_waves);
   // mode boundaries in the sorted order: [0, b2) mode 2, [b2, b1) mode 1, rest mode 0
   auto mode_of = [&](int n) {
@@ -325,13 +335,12 @@ static void plan_shared(const PlanItem *items, size_t cnt, Prec prec, int menu, 
     }
     begin[3] = pos;
   }
-  const int halves = prec == PREC_I16X2 ? 2 : 1;
   std::vector<Task> bym[3];
   for (int md = 2; md >= 0; --md) {
     const int from = begin[md];
     const int to = (md == 0) ? begin[3] : begin[md - 1];
     if (to <= from) continue;
-    const int spw = slots_per_wave(prec, Ps[md]);
+    const int spw = spw_of(Ps[md]);
     mode_counts[md] += to - from;
     bym[md].reserve((to - from + spw - 1) / spw);
     for (int a = from; a < to; a += spw) {
@@ -1039,18 +1048,23 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
     const int nch = (m + rows - 1) / rows;
     LaunchDesc L{};
     L.shared = true;
+    // int32 scan launches: two chains per sub-group where the options ask
+    // for them (SW_CHAINS_TWO) or leave the choice (the default below)
+    L.dual = prec == PREC_I32 && !lazy &&
+             (opt.int32_chains == SW_CHAINS_TWO ||
+              (opt.int32_chains == SW_CHAINS_AUTO && kDualInt32Default));
     L.menu = menu;
     L.nchunks = nch;
     L.query = q;
     L.task_begin = (int)tasks.size();
     int mc[3] = {0, 0, 0};
-    plan_shared(group, gcnt, prec, menu, waves_total, fl, hs, tasks, mc);
+    plan_shared(group, gcnt, prec, L.dual, menu, waves_total, fl, hs, tasks, mc);
     L.task_end = (int)tasks.size();
     for (int k = 0; k < 3; ++k) stats.lanes_used[k] += mc[k];
     const int segs[3] = {mm.seg16, mm.seg32, mm.seg64};
     for (int t = L.task_begin; t < L.task_end; ++t) {
       tasks[t].nchunks = nch;
-      if (nch > 1) { tasks[t].bnd_off = bnd_elems; bnd_elems += 8ll * tasks[t].ncols; }
+      if (nch > 1) { tasks[t].bnd_off = bnd_elems; bnd_elems += (L.dual ? 16ll : 8ll) * tasks[t].ncols; }
       stats.seglen_max = std::max(stats.seglen_max, segs[tasks[t].mode]);
       const int P = 16 << tasks[t].mode;
       int used = 0;
@@ -1091,7 +1105,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
                 layout_valid(tk.layout, L.shared ? 64 : L.pmax) &&
                 tk.stream_off + (int64_t)tk.ncols / kBlock * kStreamBlockBytes <= stream_bytes;
       if (chunked) ok = ok && tk.bnd_off >= 0 && tk.bnd_off % 4 == 0 &&
-                        tk.bnd_off + 8ll * tk.ncols <= bnd_elems;
+                        tk.bnd_off + (L.dual ? 16ll : 8ll) * tk.ncols <= bnd_elems;
       if (L.shared) ok = ok && tk.mode >= 0 && tk.mode < 3 && tk.layout == layout_for(16 << tk.mode);
       int widths[4];
       const int ngroups = layout_groups(tk.layout, widths);
@@ -1107,7 +1121,7 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
           if (ok && !L.shared)
             ok = tk.nchunks >= 1 && (chunked || tk.nchunks == 1) &&
                  (int64_t)mlen[pid] <= (int64_t)tk.nchunks * widths[s2 / 2] * L.seg * (L.rp ? 2 : 1);
-          if (prec == PREC_I32 || L.rp) ok = ok && (s2 & 1) == 0;
+          if ((prec == PREC_I32 && !L.dual) || L.rp) ok = ok && (s2 & 1) == 0;
           if (L.rp) ok = ok && widths[s2 / 2] == L.pmax && prec == PREC_I16X2;
         }
       }
@@ -1248,12 +1262,12 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
         a.bnd_in = (c & 1) ? bndB : bndA;
         a.bnd_out = (c & 1) ? bndA : bndB;
         const int menu = L.menu, grid = L.grid;
-        const bool chunked = L.nchunks > 1;
-        const uint64_t v[6] = {5, (uint64_t)prec, (uint64_t)alg, (uint64_t)menu, (uint64_t)chunked,
-                               (uint64_t)grid};
+        const bool chunked = L.nchunks > 1, dual = L.dual;
+        const uint64_t v[7] = {5, (uint64_t)prec, (uint64_t)alg, (uint64_t)menu, (uint64_t)chunked,
+                               (uint64_t)grid, (uint64_t)dual};
         note(v, sizeof(v));
         note(&a, sizeof(a));
-        ops.push_back([=]() { return launch_shared(prec, alg, menu, chunked, a, grid, st); });
+        ops.push_back([=]() { return launch_shared(prec, alg, menu, chunked, dual, a, grid, st); });
         stats.launches++;
       }
     } else {

@@ -87,6 +87,7 @@ struct ExecOptions {
   int force_lanes = 0, force_seglen = 0, force_kernel = 0, mixed_layout = 0, use_graph = 0;
   int int16_cap = 32767;
   int lane_pairing = 0;     // SW_PAIRING_*
+  int int32_chains = 0;     // SW_CHAINS_*
 };
 
 struct ExecStats {

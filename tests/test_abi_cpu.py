@@ -105,6 +105,10 @@ def test_batch_rejects_bad_options(lib):
     b.precision = 0
     assert lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
                                  out.ctypes.data, None) == api.SW_EINVAL
+    opt = api.Options()
+    opt.int32_chains = 3
+    assert lib.sw_align_batch_ex(ctypes.byref(b), ctypes.byref(sc), ctypes.byref(opt),
+                                 out.ctypes.data, None) == api.SW_EINVAL
 
 
 def _entry(**kw):
