@@ -532,14 +532,17 @@ def bench_long_queries(args):
             res = {}
             # the scan with two int32 chains per sub-group (the default), with
             # one chain, and the lazy-F comparator
-            for alg, name, chains in ((api.SW_ALG_SCAN, "scan", api.SW_CHAINS_TWO),
-                                      (api.SW_ALG_SCAN, "scan_one_chain", api.SW_CHAINS_ONE),
-                                      (api.SW_ALG_LAZYF, "lazyf", api.SW_CHAINS_AUTO)):
+            # and the scan with the references striped and the queries streamed
+            for alg, name, chains, stripe in (
+                    (api.SW_ALG_SCAN, "scan", api.SW_CHAINS_TWO, api.SW_STRIPE_QUERY),
+                    (api.SW_ALG_SCAN, "scan_one_chain", api.SW_CHAINS_ONE, api.SW_STRIPE_QUERY),
+                    (api.SW_ALG_SCAN, "scan_swapped", api.SW_CHAINS_AUTO, api.SW_STRIPE_SHORTER),
+                    (api.SW_ALG_LAZYF, "lazyf", api.SW_CHAINS_AUTO, api.SW_STRIPE_QUERY)):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 out = api.sw_align_batch(*d, sub.matrix, sub.gap_open, sub.gap_extend,
                                          pair_query=pq, precision=api.SW_PREC_I32, algorithm=alg,
-                                         int32_chains=chains)
+                                         int32_chains=chains, striping=stripe)
                 wall = time.perf_counter() - t0
                 st = out.stats
                 res[name] = {"gcups": round(sub.cells() / wall / 1e9, 1),
@@ -569,6 +572,12 @@ def bench_long_queries(args):
                     res["scan_one_chain"]["kernel_gcups"] * OPS_PER_CELL / (PEAK_I32_TOPS * 1e3), 4),
                 "two_chains_equal_one": bool(np.array_equal(res["scan"]["results"],
                                                             res["scan_one_chain"]["results"])),
+                "scan_swapped_gcups": res["scan_swapped"]["gcups"],
+                "scan_swapped_kernel_gcups": res["scan_swapped"]["kernel_gcups"],
+                "scan_swapped_kernel_frac_i32": round(
+                    res["scan_swapped"]["kernel_gcups"] * OPS_PER_CELL / (PEAK_I32_TOPS * 1e3), 4),
+                "swapped_equal_query_striped": bool(np.array_equal(
+                    res["scan_swapped"]["results"], res["scan_one_chain"]["results"])),
                 "lazyf_kernel_gcups": lz["kernel_gcups"],
                 "lazyf_passes_per_column": round(passes, 3),
                 "scan_equals_lazyf": bool(np.array_equal(res["scan"]["results"], lz["results"])),

@@ -361,9 +361,26 @@ typedef struct {
                                     independent column chains, each with its
                                     own state, interleaved in one instruction
                                     stream (results are the same either way)   */
-    int32_t reserved[6];
+    int32_t striping;            /* which sequence the lanes stripe (host planner):
+                                    SW_STRIPE_AUTO = the query (the paper's
+                                    layout); SW_STRIPE_QUERY = the query;
+                                    SW_STRIPE_SHORTER = for each pair whose
+                                    reference is shorter than its query and at
+                                    most 2048 residues, the reference, striped
+                                    over one 64-lane wavefront (up to 32 rows per
+                                    lane) with the query streamed one residue
+                                    per column in int32 -- no query chunks at
+                                    any query length; the scores are read from
+                                    the substitution matrix in LDS, and the end
+                                    cell keeps the (ref_end, query_end) order.
+                                    Other pairs, the lazy-F algorithm and
+                                    batches forced onto the device planner
+                                    (planner 2) stripe the query.  Results are
+                                    the same either way.                       */
+    int32_t reserved[5];
 } sw_options;
 enum { SW_CHAINS_AUTO = 0, SW_CHAINS_ONE = 1, SW_CHAINS_TWO = 2 };
+enum { SW_STRIPE_AUTO = 0, SW_STRIPE_QUERY = 1, SW_STRIPE_SHORTER = 2 };
 
 typedef struct {
     double kernel_ms;            /* device time of the alignment kernels (hipEvents) */

@@ -24,6 +24,7 @@ SW_PREC_AUTO, SW_PREC_I32 = 0, 1
 SW_ALG_SCAN, SW_ALG_LAZYF = 0, 1
 SW_PAIRING_AUTO, SW_PAIRING_ALIGNMENTS, SW_PAIRING_ROWS = 0, 1, 2
 SW_CHAINS_AUTO, SW_CHAINS_ONE, SW_CHAINS_TWO = 0, 1, 2
+SW_STRIPE_AUTO, SW_STRIPE_QUERY, SW_STRIPE_SHORTER = 0, 1, 2
 SW_FLAG_SATURATED = 1
 
 EXPORTED = ["sw_strerror", "sw_last_error", "sw_init", "sw_shutdown", "sw_align",
@@ -72,7 +73,7 @@ class Options(ctypes.Structure):
                 ("mixed_layout", ctypes.c_int32), ("int16_cap", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("planner", ctypes.c_int32),
                 ("lane_pairing", ctypes.c_int32), ("int32_chains", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("striping", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -305,7 +306,8 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                    algorithm: int = SW_ALG_SCAN, force_lanes: int = 0, force_seglen: int = 0,
                    force_kernel: int = 0, mixed_layout: int = 0, int16_cap: int = 0,
                    use_graph: int = 0, planner: int = 0,
-                   lane_pairing: int = 0, int32_chains: int = 0, out=None) -> BatchOutput:
+                   lane_pairing: int = 0, int32_chains: int = 0, striping: int = 0,
+                   out=None) -> BatchOutput:
     """Many pairs in one persistent launch (plus an int32 rerun if needed).
 
     Sequences are CSR.  Either all six arrays are numpy (host) or all are torch
@@ -319,7 +321,7 @@ def sw_align_batch(query_res, query_off, ref_res, ref_off, pair_ref, matrix, gap
                                   precision)
     sc, M = make_scoring(matrix, gap_open, gap_extend)
     opt = Options(algorithm, force_lanes, force_seglen, force_kernel, mixed_layout, int16_cap,
-                  use_graph, planner, lane_pairing, int32_chains)
+                  use_graph, planner, lane_pairing, int32_chains, striping)
     # the library writes every entry (sw_result layout: four int32; flags are
     # small bit sets), so the array is returned as it is, without a copy
     if out is None:

@@ -266,7 +266,7 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
         opt->mixed_layout < 0 || opt->mixed_layout > 2 || opt->use_graph < 0 || opt->use_graph > 1 ||
         opt->force_kernel < 0 || opt->force_kernel > 2 || opt->planner < 0 || opt->planner > 2 ||
         opt->lane_pairing < 0 || opt->lane_pairing > 2 || opt->int32_chains < 0 ||
-        opt->int32_chains > 2) {
+        opt->int32_chains > 2 || opt->striping < 0 || opt->striping > 2) {
       set_error("bad option value");
       return SW_EINVAL;
     }
@@ -278,6 +278,7 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
     eo.use_graph = opt->use_graph;
     eo.lane_pairing = opt->lane_pairing;
     eo.int32_chains = opt->int32_chains;
+    eo.striping = opt->striping;
     if (opt->int16_cap) eo.int16_cap = opt->int16_cap;
   }
   if (stats) std::memset(stats, 0, sizeof(*stats));
@@ -290,7 +291,11 @@ int sw_align_batch_ex(const sw_batch *b, const sw_scoring *sc, const sw_options 
   Context &C = g_ctx;
   HIPCHK(hipSetDevice(C.device));
   bool handled = false;
-  rc = run_device_plan(b, S, eo, opt ? opt->planner : 0, C, out, stats, t0, handled);
+  // swapped striping is planned on the host: unless the caller forces the
+  // device planner, it takes the batch
+  int planner = opt ? opt->planner : 0;
+  if (eo.striping == SW_STRIPE_SHORTER && planner == 0) planner = 1;
+  rc = run_device_plan(b, S, eo, planner, C, out, stats, t0, handled);
   if (handled) return rc;
   if (rc) return rc;
   if (eo.force_lanes == 8) {

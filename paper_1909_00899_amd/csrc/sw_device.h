@@ -413,6 +413,21 @@ __device__ __forceinline__ void share_threshold(State<SEG> &st, const LaneCtx &L
   st.G = L.glast == 15 ? t15 : (L.glast == 31 ? t31 : (L.glast == 47 ? t47 : t63));
 }
 
+// Record rule of the swapped layout (the reference striped over the lanes,
+// the query streamed as columns): the end cell is still the smallest
+// (ref_end, query_end) among the cells holding the maximum, which here is the
+// smallest (row, column) instead of (column, row).  A lane records when its
+// column maximum rises above its threshold as record() does, and also when
+// it ties the threshold with a row smaller than the recorded one.  For the
+// cell X that matters (the smallest row, then column, holding the overall
+// maximum S): no cell of a smaller row holds S, so no H of such a row reaches
+// S either (E and F come from cells of smaller or equal rows minus a gap
+// cost), so in X's column the first row of X's lane whose H reaches S is X's
+// row, and every earlier record of S in that lane lies in a larger row: the
+// lane ends with X recorded.  Records of other lanes score below S or lie in
+// larger rows.
+template <class P> struct SwapRecord { static constexpr bool value = false; };
+
 // ---------------------------------------------------------------- one column
 
 template <class O, int SEG, int PMAX, bool CHUNKED, bool LAZY, class Prof>
@@ -460,7 +475,8 @@ __device__ __forceinline__ void column(State<SEG> &st, const LaneCtx &L, const P
     if constexpr (PMAX >= 64) G = O::vmax(G, O::usub(dpp<kRowBcast31, 0xc, false>(G), L.w32));
     fb_out = G;
     st.Fscan = shift1<PMAX, CHUNKED>(G, L, fb_in);
-    record<O, SEG>(st, cmax, i);
+    if constexpr (SwapRecord<Prof>::value) pf.record(st, cmax, i);
+    else record<O, SEG>(st, cmax, i);
   } else {
     // Algorithm 1: H[] already holds corrected values.
     hb_out = st.H[SEG - 1];
@@ -1622,6 +1638,162 @@ void shared_rowpair_kernel(KArgs a) {
     if (cols) atomicAdd(&a.stats[0], cols);
     if (events) atomicAdd(&a.stats[2], events);
     if (padded) atomicAdd(&a.stats[3], padded);
+  }
+}
+
+// ================================================================ swapped striping
+
+// The paper stripes the query over the lanes and streams the reference.  For
+// a long query against short references the roles can swap: the reference
+// is striped (lane l holds reference rows l*SEG + j) and the query streamed
+// one residue per column, so a query of any length needs no chunks and its
+// residues are the same for every lane (one word per four columns).  A
+// per-reference profile would take (alpha+1) x rows bytes of LDS per
+// alignment (40 KB for 2000 protein rows); instead every cell reads the
+// substitution matrix itself, staged in LDS as [query code][ref code] with a
+// sentinel row and column of -2^30: lane-constant byte offsets of its rows'
+// reference codes plus the column's row offset (one address add per cell).
+// One 64-lane alignment per wavefront, int32 lanes, the swapped record rule.
+template <int SEG>
+struct SwapProf {
+  uint32_t roff[SEG];   // bytes: reference code of row l*SEG + j, times 4
+  uint32_t snap;        // LDS bytes of this lane's end-cell copy (row j at + 256*j)
+  __device__ __forceinline__ uint32_t load(uint32_t lo, uint32_t, int j) const {
+    return *(const uint32_t *)(smem + lo + roff[j]);
+  }
+  __device__ __forceinline__ uint32_t snap_at(int j) const {
+    return *(const uint32_t *)(smem + snap + 256 * j);
+  }
+  // The swapped record rule, with the copy of H in LDS (a wavefront's SEG x
+  // 64 words) instead of SEG registers: a lane records when its column
+  // maximum rises above its threshold, or ties it (above 0) in a row smaller
+  // than the recorded one (rows of a record of a smaller value never block).
+  __device__ __forceinline__ void record(State<SEG> &st, uint32_t cmax, int i) const {
+    const int g = (int)st.G, cm = (int)cmax;
+    const bool up = cm > g, tie = cm == g && g > 0;
+    if (__any(up || tie)) {
+      ++st.events;
+      bool take = up;
+      if (tie) {
+        int rn = SEG, ro = SEG;
+        const bool held = (int)st.S == g;
+#pragma unroll
+        for (int j = SEG - 1; j >= 0; --j) {
+          if ((int)st.H[j] >= g) rn = j;
+          if (held && (int)snap_at(j) >= g) ro = j;
+        }
+        take = rn < ro;
+      }
+      if (take) {
+#pragma unroll
+        for (int j = 0; j < SEG; ++j) *(uint32_t *)(smem + snap + 256 * j) = st.H[j];
+        st.rc[0] = i;
+        st.S = cmax;
+      }
+      st.G = (uint32_t)max(g, cm);
+    }
+  }
+};
+template <int SEG> struct SwapRecord<SwapProf<SEG>> { static constexpr bool value = true; };
+
+template <int SEG>
+struct SwapMap {
+  SwapProf<SEG> prof;
+  uint32_t row_bytes;   // (alpha + 1) * 4
+  uint32_t alpha;       // codes above the alphabet read the sentinel row (the
+                        // host reports them after the launch)
+  __device__ __forceinline__ uint32_t base_lo(uint32_t c) const { return min(c, alpha) * row_bytes; }
+  __device__ __forceinline__ uint32_t base_hi(uint32_t c) const { return base_lo(c); }
+};
+
+// LDS bytes of the padded matrix (16-byte aligned): the end-cell copy follows.
+__host__ __device__ constexpr uint32_t swap_snap_offset(int alpha) {
+  return (uint32_t)(((alpha + 1) * (alpha + 1) * 4 + 15) / 16 * 16);
+}
+
+// S[q][r] for q, r < alpha, -2^30 where either is the sentinel code alpha.
+__device__ __forceinline__ void stage_matrix_padded(const KArgs &a) {
+  int32_t *M = (int32_t *)smem;
+  const int w = a.alpha + 1;
+  for (int k = threadIdx.x; k < w * w; k += blockDim.x) {
+    const int q = k / w, r = k % w;
+    M[k] = (q < a.alpha && r < a.alpha) ? a.matrix[q * a.alpha + r] : -(1 << 30);
+  }
+}
+
+__device__ __forceinline__ bool better_swap(int s, int r, int c, int s2, int r2, int c2) {
+  return s > s2 || (s == s2 && (r < r2 || (r == r2 && c < c2)));
+}
+
+// Task t: pair tasks[t].pair[0], its query streamed over tasks[t].ncols
+// columns (the query length rounded up to a block), its reference of at most
+// 64*SEG rows striped.
+template <int SEG>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3)))
+void swap_kernel(KArgs a) {
+  using O = OpsI32;
+  stage_matrix_padded(a);
+  __syncthreads();
+  // LDS: the padded matrix, then the end-cell copy [SEG][64 lanes]
+  const uint32_t snap0 = swap_snap_offset(a.alpha) + (uint32_t)(threadIdx.x & 63) * 4u;
+  const LaneCtx L = make_lane<O>(0x1, SEG, (uint32_t)a.gap_extend);
+  const Params pr = make_params<O, SEG>((uint32_t)a.gap_open, (uint32_t)a.gap_extend);
+  const uint32_t sentw = (uint32_t)a.alpha * 0x01010101u;
+  uint32_t lazy_steps = 0;
+  unsigned long long cols = 0, events = 0;
+  for (;;) {
+    const int ti = pop_task(a.task_counter);
+    if (ti >= a.ntasks) break;
+    const Task t = a.tasks[ti];
+    const int pid = t.pair[0];
+    const PairInfo p = a.pairs[pid];
+    SwapMap<SEG> pm;
+    pm.row_bytes = (uint32_t)(a.alpha + 1) * 4u;
+    pm.alpha = (uint32_t)a.alpha;
+    pm.prof.snap = snap0;
+#pragma unroll
+    for (int j = 0; j < SEG; ++j) {
+      const int row = L.l * SEG + j;
+      const int code = row < p.n ? min((int)a.ref_res[p.r_off + row], a.alpha) : a.alpha;
+      pm.prof.roff[j] = (uint32_t)code * 4u;
+    }
+    State<SEG> st;
+    state_reset(st, 0u);
+    const uint8_t *qp = a.query_res + p.q_off;
+    const DirectSrc src{qp, qp, p.m, p.m, sentw};
+    run_columns<O, SEG, 64, false, false>(st, L, pr, pm, src, t.ncols, nullptr, nullptr, nullptr,
+                                          nullptr, lazy_steps);
+    cols += (unsigned long long)t.ncols;
+    events += st.events;
+    // smallest (score desc, row asc, column asc) over the wavefront
+    int s = st.rc[0] != 0x7fffffff ? (int)st.S : 0;
+    int r = 0x7fffffff, c = 0x7fffffff;
+    if (s > 0) {
+      int jj = SEG - 1;
+#pragma unroll
+      for (int j = SEG - 1; j >= 0; --j)
+        if ((int)pm.prof.snap_at(j) >= s) jj = j;
+      r = L.l * SEG + jj;
+      c = st.rc[0];
+    } else {
+      s = 0;
+    }
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int s2 = __shfl_xor(s, d), r2 = __shfl_xor(r, d), c2 = __shfl_xor(c, d);
+      if (better_swap(s2, r2, c2, s, r, c)) { s = s2; r = r2; c = c2; }
+    }
+    if (L.lane == 0) {
+      DevResult res;
+      res.score = s;
+      res.qend = s > 0 ? c : -1;
+      res.rend = s > 0 ? r : -1;
+      res.flags = 0;
+      a.results[p.out] = res;
+    }
+  }
+  if ((threadIdx.x & 63) == 0 && a.stats != nullptr) {
+    if (cols) atomicAdd(&a.stats[0], cols);
+    if (events) atomicAdd(&a.stats[2], events);
   }
 }
 

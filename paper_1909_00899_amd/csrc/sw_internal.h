@@ -195,6 +195,15 @@ size_t pair_rowpair_lds_bytes(int alpha);
 hipError_t launch_pair_rowpair(int seg, int lanes, bool chunked, const KArgs &a, int grid,
                                hipStream_t st);
 
+// Swapped striping (int32): task t = pair tasks[t].pair[0] with its query
+// streamed over tasks[t].ncols columns and its reference (at most 64*seg
+// rows) striped over one wavefront; results to results[pairs[pid].out].
+constexpr int kSwapSegs[] = {4, 8, 12, 16, 20, 24, 28, 32};
+constexpr int kSwapMaxRows = 64 * 32;
+bool swap_has(int seg);
+size_t swap_lds_bytes(int alpha, int seg);
+hipError_t launch_swap(int seg, const KArgs &a, int grid, hipStream_t st);
+
 // Sets every result to {0, -1, -1, 0}.
 hipError_t launch_init_results(int n, DevResult *r, hipStream_t st);
 // *count += the entries of r[0..n) with a flag bit of `mask`.

@@ -1366,14 +1366,160 @@ int execute(const ExecInput &in, const Scoring &sc, Prec prec, const ExecOptions
   return SW_OK;
 }
 
+// Pairs in the swapped layout (reference striped over one wavefront, query
+// streamed; int32): grouped by rows per lane (the fewest that hold the
+// reference), each group one persistent launch, the groups spread over the
+// main stream and the side streams.  Results go to ws.results (n_results
+// entries, all initialised first when init_all).  Synchronous.
+static int run_swapped(const ExecInput &in, const std::vector<PlanItem> &items, const Scoring &sc,
+                       Workspace &ws, int n_results, bool init_all, hipStream_t st,
+                       hipEvent_t e0, hipEvent_t e1, int num_cus, ExecStats &es) {
+  int rc;
+  constexpr int kNumSeg = (int)(sizeof(kSwapSegs) / sizeof(kSwapSegs[0]));
+  std::vector<std::vector<const PlanItem *>> by(kNumSeg);
+  for (const auto &it : items) {
+    int g = 0;
+    while (g < kNumSeg && 64 * kSwapSegs[g] < it.n) ++g;
+    if (g == kNumSeg) { set_error("internal planner error: swapped pair beyond %d rows", kSwapMaxRows); return SW_EINVAL; }
+    by[g].push_back(&it);
+  }
+  std::vector<Task> tasks;
+  tasks.reserve(items.size());
+  struct Group { int seg, begin, end; double work; };
+  std::vector<Group> groups;
+  for (int g = 0; g < kNumSeg; ++g) {
+    if (by[g].empty()) continue;
+    // longest queries first inside a group (one wavefront per pair)
+    std::stable_sort(by[g].begin(), by[g].end(),
+                     [](const PlanItem *x, const PlanItem *y) { return x->m > y->m; });
+    Group G{kSwapSegs[g], (int)tasks.size(), 0, 0.0};
+    for (const PlanItem *it : by[g]) {
+      Task t;
+      std::memset(&t, 0, sizeof(t));
+      t.layout = 1;
+      t.mode = 0;
+      t.nchunks = 1;
+      t.bnd_off = -1;
+      for (int k = 0; k < kSlots; ++k) t.pair[k] = -1;
+      t.pair[0] = it->pair;
+      t.ncols = round_up(std::max(it->m, 1), kBlock);
+      G.work += (double)t.ncols * kSwapSegs[g];
+      tasks.push_back(t);
+    }
+    G.end = (int)tasks.size();
+    groups.push_back(G);
+  }
+  if (tasks.empty()) return SW_OK;
+  const PairInfo *d_pairs = in.d_pairs;
+  const size_t task_bytes = tasks.size() * sizeof(Task);
+  const size_t misc_bytes = 64 + 4 * groups.size();
+  if ((rc = ws.results.ensure((size_t)std::max(1, n_results) * sizeof(DevResult))) ||
+      (rc = ws.matrix.ensure(sizeof(int32_t) * sc.M.size())) ||
+      (rc = ws.tasks.ensure(task_bytes)) || (rc = ws.misc.ensure(misc_bytes)) ||
+      (rc = ws.staging.ensure(task_bytes + sizeof(int32_t) * sc.M.size() + 64)))
+    return rc;
+  if (!d_pairs) {
+    if ((rc = ws.pairs.ensure(std::max<size_t>(1, in.pairs.size()) * sizeof(PairInfo)))) return rc;
+    HIPCHK(hipMemcpyAsync(ws.pairs.p, in.pairs.data(), in.pairs.size() * sizeof(PairInfo),
+                          hipMemcpyHostToDevice, st));
+    d_pairs = ws.pairs.as<PairInfo>();
+  }
+  char *stg = ws.staging.as<char>();
+  std::memcpy(stg, tasks.data(), task_bytes);
+  std::memcpy(stg + task_bytes, sc.M.data(), sizeof(int32_t) * sc.M.size());
+  HIPCHK(hipMemcpyAsync(ws.tasks.p, stg, task_bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ws.matrix.p, stg + task_bytes, sizeof(int32_t) * sc.M.size(),
+                        hipMemcpyHostToDevice, st));
+  uint32_t *misc = ws.misc.as<uint32_t>();
+  unsigned long long *d_stats = (unsigned long long *)misc;   // 3 x u64, then counters
+  HIPCHK(launch_fill_u32(misc, (int64_t)(misc_bytes / 4), 0u, st));
+  if (init_all) HIPCHK(launch_init_results(n_results, ws.results.as<DevResult>(), st));
+  // the largest groups first, round robin over the streams
+  std::vector<int> order(groups.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return groups[x].work > groups[y].work; });
+  const int nside = std::min<int>(kSideStreams, (int)groups.size() - 1);
+  if (nside > 0 && (rc = ws.ensure_side_streams())) return rc;
+  HIPCHK(hipEventRecord(e0, st));
+  if (nside > 0) {
+    HIPCHK(hipEventRecord(ws.fork, st));
+    for (int k = 0; k < nside; ++k) HIPCHK(hipStreamWaitEvent(ws.side[k], ws.fork, 0));
+  }
+  for (size_t oi = 0; oi < order.size(); ++oi) {
+    const Group &G = groups[order[oi]];
+    const int lane = nside > 0 ? (int)(oi % (nside + 1)) : 0;
+    hipStream_t ls = lane == 0 ? st : ws.side[lane - 1];
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.tasks = ws.tasks.as<Task>() + G.begin;
+    a.ntasks = G.end - G.begin;
+    a.task_counter = (int32_t *)(misc + 16) + order[oi];
+    a.pairs = d_pairs;
+    a.query_res = in.d_qres;
+    a.ref_res = in.d_rres;
+    a.alpha = sc.alpha;
+    a.matrix = ws.matrix.as<int32_t>();
+    a.gap_open = sc.go;
+    a.gap_extend = sc.ge;
+    a.results = ws.results.as<DevResult>();
+    a.stats = d_stats;
+    a.sat_cap = 32767;
+    const int grid = std::max(1, std::min(a.ntasks, num_cus * 24));
+    HIPCHK(launch_swap(G.seg, a, grid, ls));
+    es.launches++;
+    es.seglen_max = std::max(es.seglen_max, G.seg);
+  }
+  for (int k = 0; k < nside; ++k) {
+    HIPCHK(hipEventRecord(ws.join[k], ws.side[k]));
+    HIPCHK(hipStreamWaitEvent(st, ws.join[k], 0));
+  }
+  HIPCHK(hipEventRecord(e1, st));
+  unsigned long long hs[3];
+  HIPCHK(hipMemcpyAsync(hs, d_stats, sizeof(hs), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  float ms = 0;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  es.kernel_ms += ms;
+  for (int k = 0; k < 3; ++k) es.dev_stats[k] += hs[k];
+  for (const Group &G : groups)
+    for (int t = G.begin; t < G.end; ++t) es.padded_cells += (int64_t)tasks[t].ncols * 64 * G.seg;
+  return SW_OK;
+}
+
 int run_batch(const ExecInput &in, const Scoring &sc, int precision, const ExecOptions &opt,
               Workspace &ws, int n_pairs, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
               int num_cus, sw_result *out, sw_stats *stats) {
   Prec prec = (precision == SW_PREC_AUTO && sc.fits_i16 && opt.algorithm == SW_ALG_SCAN)
                   ? PREC_I16X2 : PREC_I32;
   ExecStats es;
-  int rc = execute(in, sc, prec, opt, ws, n_pairs, st, e0, e1, num_cus, es, true);
+  // swapped striping: pairs whose reference fits one wavefront's rows and is
+  // shorter than the query run with the reference striped (scan only)
+  std::vector<PlanItem> swapped;
+  ExecInput rest_in;
+  const ExecInput *main_in = &in;
+  if (opt.striping == SW_STRIPE_SHORTER && opt.algorithm == SW_ALG_SCAN) {
+    rest_in.d_qres = in.d_qres;
+    rest_in.d_rres = in.d_rres;
+    rest_in.d_pairs = in.d_pairs;
+    rest_in.pairs = in.pairs;
+    rest_in.n_pairs = in.n_pairs;
+    rest_in.n_queries = in.n_queries;
+    rest_in.q_off_of_query = in.q_off_of_query;
+    rest_in.m_of_query = in.m_of_query;
+    for (const auto &it : in.items) {
+      if (it.n <= kSwapMaxRows && it.n < it.m) swapped.push_back(it);
+      else rest_in.items.push_back(it);
+    }
+    main_in = &rest_in;
+  }
+  int rc = execute(*main_in, sc, prec, opt, ws, n_pairs, st, e0, e1, num_cus, es, true);
   if (rc) return rc;
+  if (!swapped.empty()) {
+    rc = run_swapped(in, swapped, sc, ws, n_pairs, main_in->items.empty(), st, e0, e1, num_cus,
+                     es);
+    if (rc) return rc;
+  }
   const double t_res0 = now_ms();
   int rerun = 0;
   static_assert(sizeof(DevResult) == sizeof(sw_result), "result layout");

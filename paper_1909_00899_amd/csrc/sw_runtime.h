@@ -88,6 +88,7 @@ struct ExecOptions {
   int int16_cap = 32767;
   int lane_pairing = 0;     // SW_PAIRING_*
   int int32_chains = 0;     // SW_CHAINS_*
+  int striping = 0;         // SW_STRIPE_*
 };
 
 struct ExecStats {
