@@ -428,7 +428,8 @@ int sw_align_ex(const uint8_t *query, int32_t query_len, const uint8_t *ref, int
  * For callers that must not allocate memory during the call: code under HIP
  * stream capture, tight serving loops, hosts that forbid hipMalloc.  Computes
  * exactly what sw_align_batch computes for the same batch and scoring (the
- * same device planner and kernels), but allocates nothing: no device memory,
+ * same device planner and kernels, in the planner's fixed shapes: the
+ * autotuner's table is not consulted), but allocates nothing: no device memory,
  * no pinned host memory and no host heap.  Every buffer of the call lives in
  * one fixed device array of the library (about 53 MiB per device, held from
  * the library's initialisation of a device until the process ends), which
@@ -476,7 +477,9 @@ int sw_align_batch_noalloc(const sw_batch *b, const sw_scoring *sc, sw_result *o
  * again (a cache across processes).
  * ------------------------------------------------------------------------- */
 enum { SW_TUNE_SHARED = 0,       /* one query against many references            */
-       SW_TUNE_PAIR = 1 };       /* a query per pair (per-pair kernel)            */
+       SW_TUNE_PAIR = 1,         /* a query per pair (per-pair kernel)            */
+       SW_TUNE_DEVICE_SHARED = 2,/* device-planned batch with one query           */
+       SW_TUNE_DEVICE_PAIR = 3 };/* device-planned batch with a query per pair    */
 
 typedef struct {
     int32_t kind;                /* SW_TUNE_*                                      */
@@ -489,12 +492,26 @@ typedef struct {
                                     rows per lane of the 64-lane mode)            */
     int32_t mixed;               /* SW_TUNE_PAIR: 1 = mixed layouts at this seglen
                                     for every per-pair query in [m_lo, m_hi]      */
+    int32_t pairing;             /* SW_TUNE_DEVICE_SHARED: SW_PAIRING_ROWS (row
+                                    pairs, lanes 16) or SW_PAIRING_ALIGNMENTS
+                                    (two alignments per lane, lanes 16 or 32);
+                                    other kinds: 0                                */
+    int32_t lds_records;         /* SW_TUNE_DEVICE_SHARED with row pairs: 1 = the
+                                    end-cell records in LDS, 0 = in registers     */
     double gcups;                /* measured kernel GCUPS of the winner            */
     double model_gcups;          /* measured GCUPS of the cost model's own choice  */
 } sw_tune_entry;
 
 /* Tunes the shapes for the pairs of `b` (same arguments as sw_align_batch) and
- * installs the winners.  sample_cells > 0 caps the cells timed per group (a
+ * installs the winners.  For the host planner: the shared-query menu and lane
+ * mode of the largest query groups, the per-pair shapes per query-length
+ * bucket, the mixed layout.  For a batch the device planner takes (one query
+ * of at most 512 residues, or a query per pair, at least 4096 pairs): every
+ * compiled device-planned shape that holds the query -- row pairs at each
+ * rows-per-lane with the end-cell records in LDS or in registers, two
+ * alignments per lane at each (rows, lanes) -- or, for a query per pair, the
+ * 8- and 16-lane shapes that hold the longest query, each timed on the whole
+ * batch (SW_TUNE_DEVICE_* entries for that query length).  sample_cells > 0 caps the cells timed per group (a
  * seeded subset of the group's pairs; 0 = 5e10).  Writes up to `cap` entries to
  * `out` (may be NULL) and their number to *n_out (may be NULL).  Results of
  * later calls are unchanged by tuning: only their speed. */

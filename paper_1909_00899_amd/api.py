@@ -100,17 +100,18 @@ class Stats(ctypes.Structure):
                 "lanes8": self.lanes8}
 
 
-SW_TUNE_SHARED, SW_TUNE_PAIR = 0, 1
+SW_TUNE_SHARED, SW_TUNE_PAIR, SW_TUNE_DEVICE_SHARED, SW_TUNE_DEVICE_PAIR = 0, 1, 2, 3
 
 
 class TuneEntry(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("alphabet_size", ctypes.c_int32), ("m_lo", ctypes.c_int32),
                 ("m_hi", ctypes.c_int32), ("lanes", ctypes.c_int32), ("seglen", ctypes.c_int32),
-                ("mixed", ctypes.c_int32), ("gcups", ctypes.c_double),
+                ("mixed", ctypes.c_int32), ("pairing", ctypes.c_int32),
+                ("lds_records", ctypes.c_int32), ("gcups", ctypes.c_double),
                 ("model_gcups", ctypes.c_double)]
     KEYS = ("kind", "precision", "alphabet_size", "m_lo", "m_hi", "lanes", "seglen", "mixed",
-            "gcups", "model_gcups")
+            "pairing", "lds_records", "gcups", "model_gcups")
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k in self.KEYS}

@@ -294,13 +294,15 @@ struct ProfLds {
 template <class O, int JSTRIDE>
 struct ProfLds8 {
   __device__ __forceinline__ uint32_t load(uint32_t lo, uint32_t hi, int j) const {
-    const int a = *(const signed char *)(smem + lo + j * JSTRIDE);
     if constexpr (O::kHalves == 2) {
-      const int b = *(const signed char *)(smem + hi + j * JSTRIDE);
-      // low 16 bits of each sign-extended byte: one byte permute
-      return __builtin_amdgcn_perm((uint32_t)b, (uint32_t)a, 0x05040100u);
+      // each byte sign-extended straight into its 16-bit half (the LDS
+      // pipe's d16 loads), no merging instruction on the VALU
+      s16x2 v;
+      v.x = (short)*(const signed char *)(smem + lo + j * JSTRIDE);
+      v.y = (short)*(const signed char *)(smem + hi + j * JSTRIDE);
+      return bc<uint32_t>(v);
     } else {
-      return (uint32_t)a;
+      return (uint32_t)(int)*(const signed char *)(smem + lo + j * JSTRIDE);
     }
   }
 };

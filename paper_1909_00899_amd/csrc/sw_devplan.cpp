@@ -119,6 +119,17 @@ bool pick_pair_shape(Prec prec, const Scoring &S, int max_m, const ExecOptions &
            pair_direct_lds_bytes(prec, s, S.alpha, es) <= kPairDirectLds;
   };
   int s16 = 0, s8 = 0;
+  // the autotuner's measured shape for this longest query, when it applies
+  sw_tune_entry td;
+  if (!eo.force_lanes && !eo.force_seglen && eo.use_tuning &&
+      tune_lookup(SW_TUNE_DEVICE_PAIR, prec, S.alpha, max_m, td)) {
+    if ((td.lanes == 16 || (td.lanes == 8 && prec == PREC_I16X2 && es == 1)) &&
+        fits(td.seglen, td.lanes)) {
+      seg = td.seglen;
+      lanes = td.lanes;
+      return true;
+    }
+  }
   if (eo.force_lanes != 8) {
     if (eo.force_seglen) {
       if (fits(eo.force_seglen, 16)) s16 = eo.force_seglen;
@@ -146,6 +157,9 @@ bool pick_pair_shape(Prec prec, const Scoring &S, int max_m, const ExecOptions &
 }  // namespace
 
 bool rowpair_shape(int m, int alpha, int &seg) { return pick_rowpair_seg(m, alpha, 0, seg); }
+bool rowpair_shape_forced(int m, int alpha, int force_seg, int &seg) {
+  return pick_rowpair_seg(m, alpha, force_seg, seg);
+}
 
 int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, int planner,
                     Context &C, sw_result *out, sw_stats *stats, double t0, bool &handled,
@@ -207,6 +221,7 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
   const Prec prec = (b->precision == SW_PREC_AUTO && S.fits_i16) ? PREC_I16X2 : PREC_I32;
   int seg = 0, lanes = 16, pes = 0;   // pes: per-pair profile entry bytes
   bool rows = false;   // row pairs: both halves of a lane hold rows of one alignment
+  int lrec = eo.lds_records;          // row pairs: end-cell records in LDS
   if (first_row) {
     // start-cell pass: masked row pairs only
     if (!single) return refuse("masked rows need one query");
@@ -215,11 +230,25 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
     rows = true;
     handled = true;
   } else if (single) {
+    // the autotuner's measured shape for this query length, when no option
+    // forces one
+    sw_tune_entry td;
+    const bool tuned = eo.use_tuning && !eo.force_lanes && !eo.force_seglen &&
+                       eo.lane_pairing == SW_PAIRING_AUTO &&
+                       tune_lookup(SW_TUNE_DEVICE_SHARED, prec, S.alpha, m, td);
     if (eo.lane_pairing == SW_PAIRING_ROWS) {
       if (prec != PREC_I16X2) return refuse("row pairs need int16 lanes");
       if (eo.force_lanes && eo.force_lanes != 16) return refuse("row pairs use 16 lanes");
       rows = pick_rowpair_seg(m, S.alpha, eo.force_seglen, seg);
       if (!rows) return refuse("no compiled row-pair shape holds the query");
+    } else if (tuned && td.pairing == SW_PAIRING_ROWS && prec == PREC_I16X2 &&
+               pick_rowpair_seg(m, S.alpha, td.seglen, seg)) {
+      rows = true;
+      lrec = td.lds_records;
+    } else if (tuned && td.pairing == SW_PAIRING_ALIGNMENTS &&
+               shared_direct_has(prec, td.seglen, td.lanes) && td.seglen * td.lanes >= m) {
+      seg = td.seglen;
+      lanes = td.lanes;
     } else if (eo.lane_pairing == SW_PAIRING_AUTO && prec == PREC_I16X2 && !eo.force_lanes &&
                !eo.force_seglen && pick_rowpair_seg(m, S.alpha, 0, seg)) {
       rows = true;   // the default for int16 lanes: one profile word per row pair
@@ -383,12 +412,12 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
       hipError_t e = prep();
       if (e == hipSuccess) e = place();
       if (e == hipSuccess)
-        e = rows ? launch_shared_rowpair(seg, a, grid, st)
+        e = rows ? launch_shared_rowpair(seg, a, grid, st, lrec)
                  : launch_shared_direct(prec, seg, lanes, a, grid, st);
       return e;
     };
     if ((rc = run({0xD1D1, (uint64_t)seg, (uint64_t)lanes, (uint64_t)rows, (uint64_t)grid,
-                   (uint64_t)(uintptr_t)first_row}, all,
+                   (uint64_t)(uintptr_t)first_row, (uint64_t)(int64_t)lrec}, all,
                   true)))
       return rc;
   } else {
@@ -583,7 +612,8 @@ int noalloc_pass(const sw_batch *b, const Scoring &S, Context &C, const NoallocR
   const hipStream_t st = C.stream;
   const int np = b->n_pairs;
   const bool single = m > 0;
-  ExecOptions eo;   // the planner's defaults, as sw_align_batch without options
+  ExecOptions eo;   // the planner's fixed rule (the tuning table is not consulted)
+  eo.use_tuning = false;
   int seg = 0, lanes = 16, pes = 0;
   bool rows = false;
   if (single) {

@@ -174,7 +174,10 @@ hipError_t launch_shared_direct(Prec prec, int seg, int lanes, const KArgs &a, i
 // `seg` rows (32*seg query rows).  grid: wavefronts wanted.
 bool shared_rowpair_has(int seg);
 size_t shared_rowpair_lds_bytes(int seg, int alpha);
-hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st);
+// lrec: end-cell records in LDS (1, when they fit, else in registers), in
+// registers (0), or in LDS when they fit (-1).
+hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st, int lrec = -1);
+bool shared_rowpair_lds_records_fit(int seg, int alpha);
 
 // Device-planned per-pair kernel: four 16-lane sub-groups per wavefront,
 // `seg` rows per lane (16*seg query rows at most), profiles per task.

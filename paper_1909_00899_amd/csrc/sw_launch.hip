@@ -455,12 +455,16 @@ static size_t rowpair_lds_records_bytes(int seg, int alpha) {
          (size_t)dev::rowpair_waves_per_group(true) * (seg + dev::kRecRows) * 256;
 }
 
-hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st) {
+bool shared_rowpair_lds_records_fit(int seg, int alpha) {
+  return rowpair_lds_records_bytes(seg, alpha) <= 160 * 1024;
+}
+
+hipError_t launch_shared_rowpair(int seg, const KArgs &a, int grid, hipStream_t st, int lrec) {
   if (!shared_rowpair_has(seg) || a.order == nullptr || a.plan_meta == nullptr ||
       a.ref_res == nullptr)
     return hipErrorInvalidValue;
   const size_t with = rowpair_lds_records_bytes(seg, a.alpha);
-  if (with <= 160 * 1024) return launch_rowpair_i16(seg, true, a, grid, st, with);
+  if (lrec != 0 && with <= 160 * 1024) return launch_rowpair_i16(seg, true, a, grid, st, with);
   return launch_rowpair_i16(seg, false, a, grid, st, shared_rowpair_lds_bytes(seg, a.alpha));
 }
 

@@ -89,6 +89,7 @@ struct ExecOptions {
   int lane_pairing = 0;     // SW_PAIRING_*
   int int32_chains = 0;     // SW_CHAINS_*
   int striping = 0;         // SW_STRIPE_*
+  int lds_records = -1;     // device-planned row pairs: -1 as LDS allows, 0 registers, 1 LDS
 };
 
 struct ExecStats {
@@ -248,6 +249,9 @@ int run_device_plan(const sw_batch *b, const Scoring &S, const ExecOptions &eo, 
 // Rows per virtual lane of the device planner's row-pair layout for a query of
 // m residues (false if no compiled shape holds it in one chunk).
 bool rowpair_shape(int m, int alpha, int &seg);
+// The row-pair rows per lane force_seg if it holds a query of m residues
+// within the planner's LDS budget.
+bool rowpair_shape_forced(int m, int alpha, int force_seg, int &seg);
 
 // The no-allocation batch call's scratch region for up to max_pairs pairs:
 // the plan words, PairInfo records, the int32 rerun's results and the

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "sw.h"
+#include "sw_menus.h"
 #include "sw_runtime.h"
 
 using namespace swrt;
@@ -51,11 +52,29 @@ void tune_merge(const std::vector<sw_tune_entry> &add) {
 }  // namespace
 
 int tune_validate(const sw_tune_entry &e) {
-  if (e.kind != SW_TUNE_SHARED && e.kind != SW_TUNE_PAIR) return SW_EINVAL;
+  if (e.kind < SW_TUNE_SHARED || e.kind > SW_TUNE_DEVICE_PAIR) return SW_EINVAL;
   if (e.precision != SW_PREC_AUTO && e.precision != SW_PREC_I32) return SW_EINVAL;
   if (e.alphabet_size < 1 || e.alphabet_size > kMaxAlpha) return SW_EINVAL;
   if (e.m_lo < 1 || e.m_hi < e.m_lo) return SW_EINVAL;
   if (e.mixed != 0 && e.mixed != 1) return SW_EINVAL;
+  if (e.kind == SW_TUNE_DEVICE_SHARED) {
+    if (e.mixed) return SW_EINVAL;
+    if (e.pairing == SW_PAIRING_ROWS)
+      return e.precision == SW_PREC_AUTO && e.lanes == 16 && shared_rowpair_has(e.seglen) &&
+                     (e.lds_records == 0 || e.lds_records == 1)
+                 ? SW_OK : SW_EINVAL;
+    if (e.pairing == SW_PAIRING_ALIGNMENTS && e.lds_records == 0)
+      return shared_direct_has(e.precision == SW_PREC_AUTO ? PREC_I16X2 : PREC_I32, e.seglen,
+                               e.lanes) ? SW_OK : SW_EINVAL;
+    return SW_EINVAL;
+  }
+  if (e.kind == SW_TUNE_DEVICE_PAIR) {
+    if (e.mixed || e.pairing || e.lds_records) return SW_EINVAL;
+    if (e.lanes == 8 && e.precision != SW_PREC_AUTO) return SW_EINVAL;
+    return (e.lanes == 8 || e.lanes == 16) && pair_direct_has(e.seglen, e.lanes) ? SW_OK
+                                                                                  : SW_EINVAL;
+  }
+  if (e.pairing || e.lds_records) return SW_EINVAL;
   if (e.kind == SW_TUNE_SHARED) {
     if (e.mixed) return SW_EINVAL;
     if (e.lanes != 0 && e.lanes != 16 && e.lanes != 32 && e.lanes != 64) return SW_EINVAL;
@@ -350,6 +369,96 @@ int sw_autotune(const sw_batch *b, const sw_scoring *sc, int64_t sample_cells,
       std::vector<sw_tune_entry> mx{entry(SW_TUNE_PAIR, m_min, m_max, 64, best_s, 1, c, best, tuned_ms)};
       tune_merge(mx);
       found.push_back(mx[0]);
+    }
+  }
+  // ---- device-planned batches: every compiled shape that holds the query,
+  // timed on the whole batch (the device planner reads it in place)
+  {
+    std::vector<sw_result> dres(np);
+    auto dtime = [&](const ExecOptions &o, double &ms, bool &handled) -> int {
+      ms = 1e300;
+      handled = false;
+      for (int rep = 0; rep < 2; ++rep) {
+        sw_stats st;
+        std::memset(&st, 0, sizeof(st));
+        bool h = false;
+        const int r = run_device_plan(b, S, o, 0, C, dres.data(), &st, now_ms(), h);
+        if (r) return r;
+        if (!h) return SW_OK;
+        handled = true;
+        ms = std::min(ms, st.kernel_ms);
+      }
+      return SW_OK;
+    };
+    ExecOptions fixed;
+    fixed.use_tuning = false;
+    double model_ms;
+    bool handled;
+    if ((rc = dtime(fixed, model_ms, handled))) return rc;
+    const bool single = b->pair_query == nullptr || b->n_queries == 1;
+    if (handled && single) {
+      const int m = in.m_of_query[0];
+      double best = 1e300;
+      int best_seg = 0, best_lanes = 0, best_pair = 0, best_lrec = 0;
+      if (prec == PREC_I16X2) {
+        for (int s2 : {4, 8, 12, 16}) {
+          int seg = 0;
+          if (!rowpair_shape_forced(m, S.alpha, s2, seg)) continue;
+          for (int lr : {1, 0}) {
+            if (lr && !shared_rowpair_lds_records_fit(seg, S.alpha)) continue;
+            ExecOptions o = fixed;
+            o.lane_pairing = SW_PAIRING_ROWS;
+            o.force_seglen = seg;
+            o.lds_records = lr;
+            double ms;
+            bool h;
+            if ((rc = dtime(o, ms, h))) return rc;
+            if (h && ms < best) { best = ms; best_seg = seg; best_lanes = 16; best_pair = SW_PAIRING_ROWS; best_lrec = lr; }
+          }
+        }
+      }
+      for (int k = 0; k < kNumDirectShapes; ++k) {
+        const DirectShape d = kDirectShapes[k];
+        if (d.seg * d.lanes < m) continue;
+        ExecOptions o = fixed;
+        o.lane_pairing = SW_PAIRING_ALIGNMENTS;
+        o.force_lanes = d.lanes;
+        o.force_seglen = d.seg;
+        double ms;
+        bool h;
+        if ((rc = dtime(o, ms, h))) return rc;
+        if (h && ms < best) { best = ms; best_seg = d.seg; best_lanes = d.lanes; best_pair = SW_PAIRING_ALIGNMENTS; best_lrec = 0; }
+      }
+      if (best_seg) {
+        sw_tune_entry e = entry(SW_TUNE_DEVICE_SHARED, m, m, best_lanes, best_seg, 0, cells, best,
+                                model_ms);
+        e.pairing = best_pair;
+        e.lds_records = best_lrec;
+        found.push_back(e);
+      }
+    } else if (handled) {
+      int max_m = 0;
+      for (const auto &it : all) max_m = std::max(max_m, it.m);
+      double best = 1e300;
+      int best_seg = 0, best_lanes = 0;
+      for (int L : {8, 16}) {
+        if (L == 8 && !(prec == PREC_I16X2 && S.fits_i8)) continue;
+        const int *segs = L == 8 ? kPair8Segs : kPairSegs;
+        const int nseg = L == 8 ? kNumPair8Segs : kNumPairSegs;
+        for (int k = 0; k < nseg; ++k) {
+          if (L * segs[k] < max_m) continue;
+          ExecOptions o = fixed;
+          o.force_lanes = L;
+          o.force_seglen = segs[k];
+          double ms;
+          bool h;
+          if ((rc = dtime(o, ms, h))) return rc;
+          if (h && ms < best) { best = ms; best_seg = segs[k]; best_lanes = L; }
+        }
+      }
+      if (best_seg)
+        found.push_back(entry(SW_TUNE_DEVICE_PAIR, max_m, max_m, best_lanes, best_seg, 0, cells,
+                              best, model_ms));
     }
   }
   tune_merge(found);

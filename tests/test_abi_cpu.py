@@ -113,7 +113,8 @@ def test_batch_rejects_bad_options(lib):
 
 def _entry(**kw):
     d = dict(kind=api.SW_TUNE_PAIR, precision=api.SW_PREC_AUTO, alphabet_size=4, m_lo=129,
-             m_hi=160, lanes=16, seglen=10, mixed=0, gcups=1.0, model_gcups=1.0)
+             m_hi=160, lanes=16, seglen=10, mixed=0, pairing=0, lds_records=0, gcups=1.0,
+             model_gcups=1.0)
     d.update(kw)
     return d
 
@@ -126,7 +127,12 @@ def test_tuning_table_round_trip_and_validation(lib, tmp_path):
                                  lanes=0, seglen=8),
                 _entry(kind=api.SW_TUNE_SHARED, alphabet_size=20, m_lo=1, m_hi=64, lanes=16,
                        seglen=4),
-                _entry(mixed=1, m_lo=1, m_hi=1000, lanes=64, seglen=16)]
+                _entry(mixed=1, m_lo=1, m_hi=1000, lanes=64, seglen=16),
+                _entry(kind=api.SW_TUNE_DEVICE_SHARED, alphabet_size=20, m_lo=512, m_hi=512,
+                       lanes=16, seglen=16, pairing=api.SW_PAIRING_ROWS, lds_records=1),
+                _entry(kind=api.SW_TUNE_DEVICE_SHARED, alphabet_size=20, m_lo=300, m_hi=300,
+                       lanes=32, seglen=12, pairing=api.SW_PAIRING_ALIGNMENTS),
+                _entry(kind=api.SW_TUNE_DEVICE_PAIR, m_lo=150, m_hi=150, lanes=8, seglen=19)]
         api.tune_set(good)
         assert api.tune_get() == good
         path = str(tmp_path / "tune.json")
@@ -138,7 +144,16 @@ def test_tuning_table_round_trip_and_validation(lib, tmp_path):
                _entry(m_lo=10, m_hi=9), _entry(lanes=8), _entry(seglen=7), _entry(mixed=2),
                _entry(kind=api.SW_TUNE_SHARED, lanes=0, seglen=5),
                _entry(kind=api.SW_TUNE_SHARED, lanes=16, seglen=2),
-               _entry(kind=api.SW_TUNE_SHARED, mixed=1, lanes=0, seglen=8)]
+               _entry(kind=api.SW_TUNE_SHARED, mixed=1, lanes=0, seglen=8),
+               _entry(kind=api.SW_TUNE_DEVICE_SHARED, lanes=32, seglen=16,
+                      pairing=api.SW_PAIRING_ROWS),
+               _entry(kind=api.SW_TUNE_DEVICE_SHARED, lanes=16, seglen=16,
+                      pairing=api.SW_PAIRING_ROWS, lds_records=2),
+               _entry(kind=api.SW_TUNE_DEVICE_SHARED, lanes=16, seglen=16),
+               _entry(kind=api.SW_TUNE_DEVICE_PAIR, lanes=8, seglen=19,
+                      precision=api.SW_PREC_I32),
+               _entry(kind=api.SW_TUNE_DEVICE_PAIR, lanes=32, seglen=8),
+               _entry(pairing=api.SW_PAIRING_ROWS)]
         for e in bad:
             with pytest.raises(api.SwError) as ex:
                 api.tune_set([e])
