@@ -226,6 +226,27 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     }
     return (int)(wd >> (4 * (j % C))) & 15;
   };
+  // Runs of plain diagonal steps (a pair whose predecessor is the pair just
+  // up-left: V = G = M, bits 0 and 2 of the nibble) are found 64 cells at a
+  // time: lane k reads the nibble of (i - k, j - k), and the run is the
+  // number of consecutive plain cells from lane 0 on (one LDS read per lane
+  // instead of a dependent read per step).  A cell outside the rectangle,
+  // or (device-memory bits) outside the window the caller loaded for (i, j),
+  // ends the run; the step-by-step walk continues from there.
+  auto diag_run = [&](int i, int j) -> int {
+    const int ii = i - L, jj = j - L;
+    bool in = ii >= 0 && jj >= 0;
+    if (!LB) in = in && jj / TC == w_tile && ii >= w_lo;
+    int nib = 0;
+    if (in) {
+      const int t = jj / TC, col = (jj % TC) / C;
+      const uint32_t wd = LB ? (uint32_t)bits[((size_t)t * A + ii) * 64 + col]
+                             : (uint32_t)lwin[(ii - w_lo) * 64 + col];
+      nib = (int)(wd >> (4 * (jj % C))) & 15;
+    }
+    const uint64_t plain = __ballot(in && (nib & 5) == 5);
+    return plain == ~0ull ? 64 : __builtin_ctzll(~plain);
+  };
   // the virtual start element: (vstart, -1) or (-1, qvstart)
   int vstart = -1, qvstart = -1;
   if (!fail && MODE != 0) {
@@ -235,6 +256,14 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     int i = A - 1, j = B - 1, mrun = 0, guard = A + B + 2;
     for (;;) {
       if (--guard < 0) { fail = true; break; }
+      while (i >= 0 && j >= 0) {            // pairs of a diagonal run
+        if (!LB) (void)nib_at(i, j);         // the window holds (i, j)
+        const int n = diag_run(i, j);
+        mrun += n;
+        i -= n;
+        j -= n;
+        if (n < 64) break;
+      }
       int nd = 0, ni = 0;
       bool start = false;
       if (i < 0 || j < 0) {                  // on the boundary: to the virtual start
@@ -292,33 +321,15 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
   if (!fail && MODE == 0) {
     int ra = A - 1, qb_ = B - 1, mrun = 1, guard = A + B + 2;
     while ((ra | qb_) != 0) {
-      if (ra > 0 && qb_ > 0) {
-        // a run of plain diagonal steps (V = G = M before the pair): step
-        // the bit address along the diagonal instead of recomputing it, up
-        // to a tile edge or (device-memory bits) the window's first row
-        int i = ra - 1, j = qb_ - 1;
-        const int t = j / TC;
-        int col = (j % TC) / C, c = j % C;
-        if (LB || (t == w_tile && i >= w_lo && i < w_lo + kWalkRows)) {
-          int addr = LB ? (t * A + i) * 64 + col : (i - w_lo) * 64 + col;
-          while ((((int)(LB ? bits[addr] : lwin[addr]) >> (4 * c)) & 5) == 5) {
-            ++mrun;
-            ra = i;
-            qb_ = j;
-            if (i == 0 || j == 0) break;
-            --i;
-            --j;
-            if (!LB && i < w_lo) break;
-            addr -= 64;
-            if (--c < 0) {
-              c = C - 1;
-              if (--col < 0) break;
-              --addr;
-            }
-          }
-        }
-        if ((ra | qb_) == 0) break;
+      while (ra > 0 && qb_ > 0) {           // predecessors along a diagonal run
+        if (!LB) (void)nib_at(ra - 1, qb_ - 1);   // the window holds (ra-1, qb_-1)
+        const int n = diag_run(ra - 1, qb_ - 1);
+        mrun += n;
+        ra -= n;
+        qb_ -= n;
+        if (n < 64) break;
       }
+      if ((ra | qb_) == 0) break;
       if (ra == 0 || qb_ == 0 || --guard < 0) { fail = true; break; }
       int i = ra - 1, j = qb_ - 1, nd = 0, ni = 0;
       int nib = nib_at(i, j);
