@@ -575,7 +575,10 @@ int sw_server_destroy(sw_server *s);
  * another collects completions, then waits for all of them.  Queries are CSR
  * (host).  out[k] gets the result; times_ns[3k..3k+2] = {submit, admit, done}
  * relative to the call's start.  A submit that returns SW_EBUSY is retried
- * until accepted (its submit time is the first attempt). */
+ * until accepted (its submit time is the first attempt).  The collector takes
+ * finished requests as the workers report them (no polling of outstanding
+ * tickets); one replay at a time per server: a second concurrent call returns
+ * SW_EBUSY without submitting anything. */
 int sw_server_replay(sw_server *s, int32_t n_requests, const uint8_t *query_res,
                      const int64_t *query_off, const int32_t *ref_id,
                      const int32_t *scoring_id, const int64_t *arrival_ns,

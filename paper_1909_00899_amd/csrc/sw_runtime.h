@@ -21,6 +21,7 @@ extern thread_local std::string g_last_error;
 struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
+  int grow_pct = 25;          // slack added on growth, percent of the request
   int ensure(size_t bytes);
   void release();
   template <class T> T *as() const { return (T *)p; }
@@ -30,6 +31,7 @@ struct DevBuf {
 struct HostBuf {
   void *p = nullptr;
   size_t cap = 0;
+  int grow_pct = 25;          // slack added on growth, percent of the request
   int ensure(size_t bytes);
   void release();
   template <class T> T *as() const { return (T *)p; }
@@ -175,6 +177,14 @@ struct Workspace {
   hipEvent_t fork = nullptr, join[kSideStreams] = {};
   bool side_ready = false;
   int ensure_side_streams();
+  // Sets the growth slack of every buffer (a long-lived caller whose batches
+  // grow, such as a server worker, reallocates less often with more slack;
+  // each reallocation frees the old buffer, which waits for the device).
+  void set_growth(int pct) {
+    for (DevBuf *b : {&tasks, &pairs, &streams, &results, &bnd, &misc, &matrix, &offs, &plan})
+      b->grow_pct = pct;
+    staging.grow_pct = pct;
+  }
   void release() {
     graphs.clear();
     if (side_ready) {

@@ -66,6 +66,10 @@ struct sw_server {
   int outstanding = 0;               // accepted and not yet finished
   int running = 0;                   // batches on the device
   bool stop = false;
+  // While a replay runs, workers append the tickets of each finished batch
+  // here, so that its collector takes only finished requests (one lock per
+  // batch) instead of polling every outstanding ticket in turn.
+  std::vector<uint64_t> *done_sink = nullptr;
   std::vector<std::thread> workers;
 
   size_t request_bytes(int m, int n) const {
@@ -87,6 +91,11 @@ void sw_server::worker_main() {
   Workspace ws;
   DevBuf qbuf;
   HostBuf qstage;
+  // batches grow with the load: double on growth, so that a worker
+  // reallocates (and waits for the device) a few times at most
+  ws.set_growth(100);
+  qbuf.grow_pct = 100;
+  qstage.grow_pct = 100;
   std::vector<Request *> batch;
   std::vector<sw_result> out;
   for (;;) {
@@ -168,6 +177,8 @@ void sw_server::worker_main() {
         r->t_done = t;
         r->done = true;
       }
+      if (done_sink)
+        for (Request *r : batch) done_sink->push_back(r->ticket);
       in_flight -= bytes;
       --running;
       outstanding -= (int)batch.size();
@@ -239,8 +250,14 @@ int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int3
     return SW_EINVAL;
   }
   const Scoring &sc = s->scorings[scoring_id];
-  for (int k = 0; k < query_len; ++k)
-    if (query[k] >= sc.alpha) { set_error("query residue %d out of range", k); return SW_EINVAL; }
+  uint8_t qmax = 0;
+  for (int k = 0; k < query_len; ++k) qmax = std::max(qmax, query[k]);
+  if (query_len > 0 && qmax >= sc.alpha) {
+    int k = 0;
+    while (query[k] < sc.alpha) ++k;
+    set_error("query residue %d out of range", k);
+    return SW_EINVAL;
+  }
   const int64_t n = s->db_off[ref_id + 1] - s->db_off[ref_id];
   if (n > 0 && s->db_max_code[ref_id] >= sc.alpha) {
     set_error("reference %d holds residue code %d, not below scoring %d's alphabet size %d",
@@ -316,6 +333,18 @@ int sw_server_replay(sw_server *s, int32_t n, const uint8_t *qres, const int64_t
     set_error("bad replay arguments");
     return SW_EINVAL;
   }
+  // The collector below takes the tickets of finished batches from the
+  // server (one lock per wake-up) instead of polling every outstanding
+  // ticket in turn; one replay at a time can collect them.
+  std::vector<uint64_t> sink, work;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->done_sink) {
+      set_error("another replay is running on this server");
+      return SW_EBUSY;
+    }
+    s->done_sink = &sink;
+  }
   std::vector<uint64_t> tickets(n, 0);
   std::vector<int64_t> first_try(n, 0);
   std::atomic<int> submitted{0};
@@ -339,30 +368,52 @@ int sw_server_replay(sw_server *s, int32_t n, const uint8_t *qres, const int64_t
       submitted.store(k + 1, std::memory_order_release);
     }
   });
-  std::vector<char> got(n, 0);
-  int remaining = n;
-  int cursor = 0;
+  // Collector: matches finished tickets to request indices as the producer
+  // publishes its tickets, and fetches each result with one poll.
+  std::unordered_map<uint64_t, int> index;
+  index.reserve((size_t)n);
+  int remaining = n, indexed = 0;
   while (remaining > 0) {
     const int upto = submitted.load(std::memory_order_acquire);
-    bool any = false;
-    for (int k = cursor; k < upto; ++k) {
-      if (got[k]) continue;
-      if (tickets[k] == 0) { got[k] = 1; --remaining; out[k] = sw_result{0, -1, -1, 0}; any = true; continue; }
+    for (; indexed < upto; ++indexed) {
+      if (tickets[indexed] == 0) {       // rejected at submit
+        out[indexed] = sw_result{0, -1, -1, 0};
+        times_ns[3 * indexed + 0] = times_ns[3 * indexed + 1] = times_ns[3 * indexed + 2] =
+            first_try[indexed] - t0;
+        --remaining;
+      } else {
+        index.emplace(tickets[indexed], indexed);
+      }
+    }
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (sink.empty())
+        s->cv_done.wait_for(lk, std::chrono::microseconds(work.empty() ? 500 : 20),
+                            [&] { return !sink.empty(); });
+      work.insert(work.end(), sink.begin(), sink.end());
+      sink.clear();
+    }
+    size_t keep = 0;
+    for (const uint64_t tk : work) {
+      auto it = index.find(tk);
+      if (it == index.end()) { work[keep++] = tk; continue; }   // submit not yet returned
+      const int k = it->second;
+      index.erase(it);
       int64_t ts[3];
-      const int rc = sw_server_poll(s, tickets[k], &out[k], ts);
-      if (rc == SW_PENDING) continue;
+      const int rc = sw_server_poll(s, tk, &out[k], ts);
       if (rc != SW_OK) err = rc;
       times_ns[3 * k + 0] = first_try[k] - t0;
       times_ns[3 * k + 1] = ts[1] - t0;
       times_ns[3 * k + 2] = ts[2] - t0;
-      got[k] = 1;
       --remaining;
-      any = true;
     }
-    while (cursor < upto && got[cursor]) ++cursor;
-    if (!any) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    work.resize(keep);
   }
   producer.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->done_sink = nullptr;
+  }
   return err.load();
 }
 

@@ -63,6 +63,10 @@ struct StartsWork {
   DevBuf tr_rstart;              // end-to-end paths: reference starts
   DevBuf tr_qstart;              // end-to-end paths: query starts
   HostBuf tr_hres;
+  // host scratch of the path tables: LDS rectangles of the two less common
+  // kernel variants, device-memory rectangles and their size classes
+  std::vector<swk::TracePair> tr_lds_v32, tr_lds_v8, tr_glob;
+  std::vector<uint8_t> tr_gcls;
   // device-memory rectangles: the largest group, the second, the rest each on
   // a stream of their own, so the long poles of the largest rectangles (one
   // wavefront each) overlap instead of adding up
@@ -373,6 +377,29 @@ int64_t run_bound(int64_t A, int64_t B) {
   return std::min(A + B - 1, 3 * std::min(A, B) - 2);
 }
 
+// 2-byte units of a rectangle's decision words: rows x tiles x 64 lanes x
+// the word width of its variant
+int64_t trace_slot_words(const swk::TracePair &P) {
+  int64_t tiles;
+  switch (swk::trace_cols(P.pad)) {   // constant divisors (the tables hold millions)
+    case 1: tiles = (P.B + 63) / 64; break;
+    case 2: tiles = (P.B + 127) / 128; break;
+    case 3: tiles = (P.B + 191) / 192; break;
+    case 8: tiles = (P.B + 511) / 512; break;
+    default: tiles = (P.B + 255) / 256; break;
+  }
+  return (int64_t)P.A * tiles * 64 * (swk::trace_word_bytes(P.pad) / 2);
+}
+
+// Size class of a device-memory rectangle: its variant and the power of two
+// below its slot, largest first.  Every member of a class needs more than
+// half the largest member's slot, so one class is one launch group.
+constexpr int kSlotBuckets = 40;   // slots below 2^40 words
+int trace_size_class(int64_t slot, int variant) {
+  const int b = std::min(kSlotBuckets - 1, 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(slot, 1)));
+  return (kSlotBuckets - 1 - b) * 3 + variant;
+}
+
 }  // namespace
 
 // Paths of a batch: mode 0 the local alignments between start and end cells
@@ -418,7 +445,12 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     return rc;
   swk::TracePair *htab = W.tr_host.as<swk::TracePair>();
   int nl = 0;
-  std::vector<swk::TracePair> glob;
+  std::vector<swk::TracePair> &glob = W.tr_glob, &lds32 = W.tr_lds_v32, &lds8 = W.tr_lds_v8;
+  std::vector<uint8_t> &gcls = W.tr_gcls;
+  glob.clear();
+  lds32.clear();
+  lds8.clear();
+  gcls.clear();
   int64_t region = 0;
   // end-to-end alignments with an empty side have their runs made here
   std::vector<std::pair<int, std::vector<uint32_t>>> host_runs;
@@ -503,53 +535,76 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     tp.id = k;
     tp.pad = 0;
     region += tp.cap;
-    const int64_t tiles = (Bq + swk::kTraceTileCols - 1) / swk::kTraceTileCols;
     // columns per lane: the fewest that hold a one-tile query (4 beyond), so
     // a one-tile query's slot of 64-lane rows is the same at any count
     tp.pad = (int32_t)std::min<int64_t>(4, (Bq + 63) / 64);
-    if (A * tiles <= swk::kTraceLdsRowTiles) {
-      htab[nl++] = tp;
+    // 16-bit values (4 or 8 columns per lane) when the rectangle's range
+    // provably fits: every reachable value -- a pair and two gap runs from
+    // the start or a boundary, plus a gap opening, or a scan term with its
+    // tile offset -- stays above every value derived from an unreachable
+    // edge (-32768 plus a score, a tile's scan offsets and an opening), and
+    // the largest chain score with its tile offset stays below 32767
+    if (Bq > 64) {
+      const int64_t tc = Bq <= 256 ? 256 : 512;
+      const int64_t span = 5 * (maxabs + S.go) + (A + Bq + 3 + tc) * (int64_t)S.ge + 256;
+      const int64_t top = std::min(A, Bq) * (int64_t)S.max_s + tc * S.ge + maxabs + 256;
+      if (span < 32768 && top < 32767) tp.pad = swk::kTracePad16 | (int32_t)(tc / 64);
+    }
+    const int64_t slot = trace_slot_words(tp);
+    const int variant = swk::trace_variant(tp.pad);
+    if (slot <= (int64_t)swk::kTraceLdsRowTiles * 64) {
+      // LDS rectangles in runs of one kernel variant (one launch each): the
+      // 16-bit four-column one straight into the table, the others after it
+      if (variant == swk::kTraceV16x4) htab[nl++] = tp;
+      else (variant == swk::kTraceV32 ? lds32 : lds8).push_back(tp);
     } else {
+      if (slot * 2 > (2ll << 30)) {
+        set_error("pair %d: a %lld x %lld rectangle needs more than 2 GiB of path scratch", k,
+                  (long long)A, (long long)Bq);
+        return SW_ENOMEM;
+      }
       glob.push_back(tp);
+      gcls.push_back((uint8_t)trace_size_class(slot, variant));
     }
   }
-  // device-memory rectangles: largest first, in groups of similar size
-  std::sort(glob.begin(), glob.end(), [](const swk::TracePair &x, const swk::TracePair &y) {
-    const int64_t nx = (int64_t)x.A * ((x.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols);
-    const int64_t ny = (int64_t)y.A * ((y.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols);
-    return nx > ny;
-  });
-  struct Group { int first, count, waves; int64_t slot_words; int carry_rows; };
+  for (const auto *v : {&lds32, &lds8}) {
+    if (!v->empty()) std::memcpy(htab + nl, v->data(), v->size() * sizeof(swk::TracePair));
+    nl += (int)v->size();
+  }
+  // device-memory rectangles by size class (two passes, no sort), largest
+  // class first; one launch group per class
+  constexpr int NCLS = kSlotBuckets * 3;
+  int64_t ccount[NCLS] = {}, cslot[NCLS] = {}, cstart[NCLS + 1] = {};
+  int crows[NCLS] = {};
+  const int ng = (int)glob.size(), nt = nl + ng;
+  for (int t = 0; t < ng; ++t) {
+    const int c = gcls[t];
+    ++ccount[c];
+    cslot[c] = std::max(cslot[c], trace_slot_words(glob[t]));
+    crows[c] = std::max(crows[c], glob[t].A);
+  }
+  for (int c = 0; c < NCLS; ++c) cstart[c + 1] = cstart[c] + ccount[c];
+  {
+    int64_t fill[NCLS];
+    std::memcpy(fill, cstart, sizeof(fill));
+    for (int t = 0; t < ng; ++t) htab[nl + fill[gcls[t]]++] = glob[t];
+  }
+  struct Group { int first, count, waves; int64_t slot_words; int carry_rows; int variant; };
   std::vector<Group> groups;
   constexpr int NS = StartsWork::kTraceStreams;
   int64_t bits_words[NS] = {}, carry_ints[NS] = {};
-  for (int t = 0; t < (int)glob.size();) {
-    const swk::TracePair &P0 = glob[t];
-    const int64_t slot = (int64_t)P0.A * ((P0.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols) * 64;
-    if (slot * 2 > (2ll << 30)) {
-      set_error("pair %d: a %d x %d rectangle needs more than 2 GiB of path scratch", P0.id,
-                P0.A, P0.B);
-      return SW_ENOMEM;
-    }
-    int u = t, carry_rows = 1;
-    while (u < (int)glob.size()) {   // members need at least half the first one's slot
-      const swk::TracePair &P = glob[u];
-      const int64_t need = (int64_t)P.A * ((P.B + swk::kTraceTileCols - 1) / swk::kTraceTileCols) * 64;
-      if (2 * need < slot) break;
-      carry_rows = std::max(carry_rows, P.A);
-      ++u;
-    }
+  for (int c = 0; c < NCLS; ++c) {
+    if (!ccount[c]) continue;
+    const int64_t slot = cslot[c];
+    const int carry_rows = std::max(1, crows[c]);
     const int64_t per_wave = slot * 2 + 6ll * carry_rows * 4;
     const int waves = (int)std::max<int64_t>(
-        1, std::min<int64_t>({(int64_t)(u - t), kTraceScratchBytes / per_wave, kTraceMaxWaves}));
+        1, std::min<int64_t>({ccount[c], kTraceScratchBytes / per_wave, kTraceMaxWaves}));
     const int sk = std::min((int)groups.size(), NS - 1);
-    groups.push_back({t, u - t, waves, slot, carry_rows});
+    groups.push_back({(int)cstart[c], (int)ccount[c], waves, slot, carry_rows, c % 3});
     bits_words[sk] = std::max<int64_t>(bits_words[sk], slot * waves);
     carry_ints[sk] = std::max<int64_t>(carry_ints[sk], 6ll * carry_rows * waves);
-    t = u;
   }
-  const int ng = (int)glob.size(), nt = nl + ng;
-  if (ng) std::memcpy(htab + nl, glob.data(), (size_t)ng * sizeof(swk::TracePair));
   std::vector<int32_t> counts(np, 0);
   if (nt > 0) {
     if ((rc = W.tr_pairs.ensure((size_t)nt * sizeof(swk::TracePair))) ||
@@ -594,7 +649,15 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     const int used = std::min((int)groups.size(), NS);
     if (used) HIPCHK(hipEventRecord(W.tr_ready, W.st));
     for (int k = 0; k < used; ++k) HIPCHK(hipStreamWaitEvent(W.tr_st[k], W.tr_ready, 0));
-    HIPCHK(swk::launch_trace(true, ta, nl, W.st));
+    for (int lo = 0; lo < nl;) {                   // one LDS launch per variant
+      const int v = swk::trace_variant(htab[lo].pad);
+      int hi = lo;
+      while (hi < nl && swk::trace_variant(htab[hi].pad) == v) ++hi;
+      ta.pairs = dp + lo;
+      ta.n = hi - lo;
+      HIPCHK(swk::launch_trace(true, v, ta, hi - lo, W.st));
+      lo = hi;
+    }
     for (int g = 0; g < (int)groups.size(); ++g) {
       const Group &gr = groups[g];
       const int k = std::min(g, NS - 1);
@@ -604,7 +667,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
       ta.carry_rows = gr.carry_rows;
       ta.gbits = W.tr_bits[k].as<uint16_t>();
       ta.gcarry = W.tr_carry[k].as<int32_t>();
-      HIPCHK(swk::launch_trace(false, ta, gr.waves, W.tr_st[k]));
+      HIPCHK(swk::launch_trace(false, gr.variant, ta, gr.waves, W.tr_st[k]));
     }
     for (int k = 0; k < used; ++k) {
       HIPCHK(hipEventRecord(W.tr_done[k], W.tr_st[k]));

@@ -10,7 +10,7 @@
 namespace swk {
 
 constexpr int kTraceTileCols = 256;      // query columns per tile at 4 columns per lane
-constexpr int kTraceLdsRowTiles = 160;   // rows x tiles whose decision bits fit in LDS
+constexpr int kTraceLdsRowTiles = 160;   // rows x tiles of 2-byte decision words that fit in LDS
 constexpr int kTraceLdsCarryRows = 80;   // a rectangle of two or more tiles in LDS has <= 80 rows
 constexpr int kCigarM = 0, kCigarI = 1, kCigarD = 2;
 constexpr int kTraceInconsistent = -2;   // no alignment of the given score from start to end
@@ -20,7 +20,20 @@ constexpr int kTraceBadResidue = -3;     // a residue code >= alphabet size in t
 // rres[r .. r + A); its runs are written backward from cigar[out + cap - 1]
 // (first run of the path last); the count goes to n_runs[id], or
 // kTraceInconsistent / kTraceBadResidue.
-// pad: query columns per lane, 1-4 (a tile of 64 * pad columns).
+// pad: query columns per lane in the low bits, 1-4 (a tile of 64 * pad
+// columns), 32-bit values; with kTracePad16 set, 4 or 8 columns per lane
+// whose values fit 16 bits (two adjacent columns per register; the host
+// checks the rectangle's value range).
+constexpr int kTracePad16 = 16;
+__host__ __device__ constexpr int trace_cols(int pad) { return pad & (kTracePad16 - 1); }
+__host__ __device__ constexpr int trace_tile_cols(int pad) { return 64 * trace_cols(pad); }
+// bytes of one lane's decision word per row (4 bits per column)
+__host__ __device__ constexpr int trace_word_bytes(int pad) { return trace_cols(pad) > 4 ? 4 : 2; }
+// kernel variants: every pair of one launch has the same one
+constexpr int kTraceV32 = 0, kTraceV16x4 = 1, kTraceV16x8 = 2;
+__host__ __device__ constexpr int trace_variant(int pad) {
+  return (pad & kTracePad16) ? (trace_cols(pad) == 8 ? kTraceV16x8 : kTraceV16x4) : kTraceV32;
+}
 struct TracePair {
   int64_t q, r, out;
   int32_t A, B, score, cap, id, pad;
@@ -32,7 +45,7 @@ struct TraceArgs {
   const uint8_t *qres, *rres;
   const int32_t *matrix;   // alpha x alpha, [query code][ref code], device
   int alpha, go, ge;       // ge <= go
-  uint16_t *gbits;         // device-memory variant: slot_words per workgroup
+  uint16_t *gbits;         // device-memory variant: slot_words 2-byte units per workgroup
   int64_t slot_words;
   int32_t *gcarry;         // device-memory variant: 6 * carry_rows per workgroup
   int carry_rows;
@@ -49,7 +62,8 @@ struct TraceArgs {
 // lds_bits the decision bits and tile carries live in LDS, else in gbits /
 // gcarry (grid-stride over the pairs).
 size_t trace_lds_bytes(bool lds_bits, int alpha);
-hipError_t launch_trace(bool lds_bits, const TraceArgs &a, int grid, hipStream_t st);
+// every pair of a.pairs[0 .. a.n) must have trace_variant(pad) == variant
+hipError_t launch_trace(bool lds_bits, int variant, const TraceArgs &a, int grid, hipStream_t st);
 // End-to-end scores (sw_trace.hip): TracePair with A = n, B = m (both >= 1);
 // results to out[id] (flags kFlagBadResidue for a residue >= alphabet size).
 constexpr int kFlagBadResidue = 1 << 20;

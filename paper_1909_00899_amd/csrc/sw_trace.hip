@@ -38,6 +38,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "sw_internal.h"
 #include "sw_trace.h"
@@ -47,7 +48,6 @@ namespace dev {
 namespace {
 
 constexpr int kNeg = -(1 << 30);     // unreachable edge; every reachable value stays above -2^28
-constexpr int kWalkRows = 64;        // rows of one tile in the walk window (8 KiB)
 
 __device__ __forceinline__ int dpp_wave_shr1(int old, int x) {
   return __builtin_amdgcn_update_dpp(old, x, 0x138, 0xf, 0xf, false);
@@ -74,6 +74,232 @@ __device__ __forceinline__ int readlane(int x, int l) { return __builtin_amdgcn_
 
 // LDS words of the staged matrix: alpha^2, rounded up to 16 bytes
 __host__ __device__ constexpr int mat_words(int alpha) { return (alpha * alpha + 3) / 4 * 4; }
+// the same matrix as 16-bit entries, after it (alpha^2 shorts, 16-byte rounded)
+__host__ __device__ constexpr int mat16_words(int alpha) { return (alpha * alpha + 7) / 8 * 4; }
+constexpr int kWalkWindowBytes = 8192;  // LDS window of the walk over device-memory bits
+
+// ---------------------------------------------------------------- 16-bit fill
+//
+// Rectangles whose values provably fit 16 bits (the host checks the range)
+// keep two adjacent columns per 32-bit register, the even column in the low
+// half, and run the row step on packed saturating 16-bit operations: half the
+// VALU instructions of the 32-bit step per cell.  The lane scan stays a
+// fused 32-bit DPP scan of one value per lane.  A decision bit is the sign of
+// a packed difference (x - y < 0 exactly when x >= y fails; saturation keeps
+// the sign); one v_perm_b32 with sign-replicating selectors gathers the four
+// signs of two registers into four bytes, and one and-or places them, so a
+// row's decision word costs two instructions per decision and register pair.
+constexpr int kNeg16 = -32768;          // unreachable; reachable values stay far above
+
+typedef short tr16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t padd(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_add_sat(__builtin_bit_cast(tr16x2, a),
+                                                                    __builtin_bit_cast(tr16x2, b)));
+}
+__device__ __forceinline__ uint32_t psub(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_sub_sat(__builtin_bit_cast(tr16x2, a),
+                                                                    __builtin_bit_cast(tr16x2, b)));
+}
+__device__ __forceinline__ uint32_t pmax(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(tr16x2, a),
+                                                                __builtin_bit_cast(tr16x2, b)));
+}
+__device__ __forceinline__ uint32_t ppack(int lo, int hi) {
+  return ((uint32_t)lo & 0xffffu) | ((uint32_t)hi << 16);
+}
+__device__ __forceinline__ uint32_t psplat(int v) { return ((uint32_t)v & 0xffffu) * 0x10001u; }
+__device__ __forceinline__ int plo(uint32_t x) { return (int)(short)(x & 0xffffu); }
+__device__ __forceinline__ int phi(uint32_t x) { return (int)x >> 16; }
+// (x.hi, x.hi)
+__device__ __forceinline__ uint32_t phi2(uint32_t x) { return __builtin_amdgcn_perm(x, x, 0x03020302u); }
+// (lo.hi, hi.lo): for each of hi's two columns, the column before it
+__device__ __forceinline__ uint32_t pshift(uint32_t hi, uint32_t lo) {
+  return __builtin_amdgcn_alignbit(hi, lo, 16);
+}
+// bytes 0-3 = 0xff where the sign bit of (x.lo, x.hi, y.lo, y.hi) is set
+__device__ __forceinline__ uint32_t psigns(uint32_t x, uint32_t y) {
+  return __builtin_amdgcn_perm(x, y, 0x09080B0Au);
+}
+__device__ __forceinline__ uint32_t dpp_shr1_u(uint32_t old, uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)x, 0x138, 0xf, 0xf, false);
+}
+
+// Nibble of column c (of the lane's C) in its decision word: 4c for 32-bit
+// values; with 16-bit values the order the byte gather leaves.
+template <int C, bool W16>
+__device__ __forceinline__ int nib_shift(int c) {
+  if constexpr (!W16) return 4 * c;
+  else if constexpr (C == 4) return 8 * (c & 1) + 4 * (c >> 1);
+  else return 8 * (c & 3) + 4 * (c >> 2);
+}
+
+// Fills the decision words of rectangle P at C = 4 or 8 columns per lane in
+// 16-bit values (the recurrences of the 32-bit fill in trace_one, in the same
+// notation).  The Eg scan runs per tile in the tile's frame: the term of
+// column j is M(a, j) + (j - base) ge, so every term stays in 16 bits;
+// a tile passes V, M and the scan total (already in the next tile's frame)
+// of its last column per row.
+template <int C, int MODE, bool FIRST, bool NEXT, class Word>
+__device__ __forceinline__ void fill16_tile(const TraceArgs &a, const TracePair &P,
+                                            const short *smat16, Word *bits, const int *cr, int *cw,
+                                            int t, bool &bad, bool &ok) {
+  constexpr bool kRowFree = MODE == 3 || MODE == 4, kColFree = MODE == 2 || MODE == 4;
+  constexpr int NP = C / 2, TC = 64 * C;
+  const int L = threadIdx.x;
+  const int alpha = a.alpha, go = a.go, ge = a.ge;
+  const int A = P.A, B = P.B;
+  const bool last_tile = !NEXT;
+  const int base = t * TC, jr0 = C * L, jc0 = base + jr0;
+  const uint32_t go2 = psplat(go), ge2 = psplat(ge), negw = 0x80008000u;
+  int qoff[C];   // [query code][.] row of the 16-bit matrix for each column
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    const int code = jc0 + c < B ? (int)a.qres[P.q + jc0 + c] : 0;
+    bad |= code >= alpha;
+    qoff[c] = min(code, alpha - 1) * alpha;
+  }
+  uint32_t Vp[NP], Gp[NP], Fp[NP], wj[NP], ej[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int j0 = jc0 + 2 * p;
+    // row -1: nothing (MODE 0), the query gap run, or a free query prefix
+    const int v0 = MODE == 0 ? kNeg16 : kRowFree ? 0 : -(go + j0 * ge);
+    const int v1 = MODE == 0 ? kNeg16 : kRowFree ? 0 : -(go + (j0 + 1) * ge);
+    Vp[p] = Gp[p] = ppack(v0, v1);
+    Fp[p] = psplat(kNeg16);
+    wj[p] = ppack((jr0 + 2 * p) * ge, (jr0 + 2 * p + 1) * ge);
+    ej[p] = ppack(go + (jr0 + 2 * p - 1) * ge, go + (jr0 + 2 * p) * ge);
+  }
+  // V(-1, base - 1); in MODE 0 the first tile's V(-1, -1) = 0 makes the
+  // start pair's M its own score
+  int cv_prev = MODE == 0 ? (FIRST ? 0 : kNeg16) : (FIRST || kRowFree) ? 0 : -(go + (base - 1) * ge);
+  Word *brow = bits + (size_t)t * A * 64 + L;
+  for (int blk = 0; blk < A; blk += 64) {
+    const int row = blk + L;
+    int rreg = row < A ? (int)a.rres[P.r + row] : 0;
+    if (FIRST) bad |= rreg >= alpha;
+    rreg = min(rreg, alpha - 1);
+    // column -1 of the tile for the block's rows: the previous tile's carry,
+    // or the boundary (nothing in MODE 0, the reference gap run from the
+    // virtual start, or a free reference prefix)
+    int crv, crm, crp;
+    if (FIRST) {
+      crv = MODE == 0 ? kNeg16 : kColFree ? 0 : -(go + row * ge);
+      crm = kColFree ? 0 : kNeg16;
+      crp = kColFree ? -ge : kNeg16;
+    } else {
+      crv = row < A ? cr[3 * row] : kNeg16;
+      crm = row < A ? cr[3 * row + 1] : kNeg16;
+      crp = row < A ? cr[3 * row + 2] : kNeg16;
+    }
+    const int nr = min(64, A - blk);
+    for (int ii = 0; ii < nr; ++ii) {
+      const int i = blk + ii;
+      const int rc = readlane(rreg, ii);
+      const int cv_in = readlane(crv, ii), cm_in = readlane(crm, ii);
+      const int cp_in = readlane(crp, ii);
+      uint32_t s2[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+        s2[p] = ppack(smat16[qoff[2 * p] + rc], smat16[qoff[2 * p + 1] + rc]);
+      // the diagonal: V(i-1, j-1), the left lane's last column (or the
+      // carry) for the lane's first one
+      const uint32_t vleft = dpp_shr1_u((uint32_t)cv_prev << 16, Vp[NP - 1]);
+      uint32_t Mv[NP], w[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        Mv[p] = padd(s2[p], pshift(Vp[p], p ? Vp[p - 1] : vleft));
+        w[p] = padd(Mv[p], wj[p]);
+      }
+      // exclusive prefix maxima of the scan terms inside the lane
+      uint32_t I[NP], lp[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const uint32_t r = pmax(w[p], pshift(w[p], negw));
+        I[p] = p ? pmax(r, phi2(I[p - 1])) : r;
+        lp[p] = pshift(I[p], p ? I[p - 1] : negw);
+      }
+      const int agg = phi(I[NP - 1]);
+      const int exc = max(dpp_wave_shr1(kNeg16, wave_max_scan(agg)), cp_in);
+      const uint32_t exc2 = psplat(exc);
+      // the scan term of the column before the lane's first: the left lane's
+      // last, or M(i, base - 1) - ge from the carry
+      const int wl_in = max(cm_in - ge, kNeg16);
+      const uint32_t wleft = dpp_shr1_u((uint32_t)wl_in << 16, w[NP - 1]);
+      uint32_t D0[NP], D1[NP], D2[NP], D3[NP];
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const uint32_t mx = pmax(exc2, lp[p]);
+        const uint32_t eg = psub(mx, ej[p]);
+        const uint32_t g = pmax(Mv[p], eg);
+        const uint32_t fo = psub(Gp[p], go2), fe = psub(Fp[p], ge2);
+        const uint32_t f = pmax(fo, fe);
+        const uint32_t wprev = pshift(w[p], p ? w[p - 1] : wleft);
+        // sign set = the decision fails: V = G?, Fv opened?, G = M?, Eg
+        // opened (the previous column's term is the prefix maximum)?
+        D0[p] = psub(g, f);
+        D1[p] = psub(fo, fe);
+        D2[p] = psub(Mv[p], eg);
+        D3[p] = psub(wprev, mx);
+        Vp[p] = pmax(g, f);
+        Gp[p] = g;
+        Fp[p] = f;
+      }
+      uint32_t word;
+      if constexpr (NP == 2) {
+        uint32_t acc = psigns(D0[0], D0[1]) & 0x10100101u;
+        acc |= psigns(D1[0], D1[1]) & 0x20200202u;
+        acc |= psigns(D2[0], D2[1]) & 0x40400404u;
+        acc |= psigns(D3[0], D3[1]) & 0x80800808u;
+        word = ~(acc | (acc >> 16)) & 0xffffu;
+      } else {
+        uint32_t acc = (psigns(D0[0], D0[1]) & 0x01010101u) | (psigns(D0[2], D0[3]) & 0x10101010u);
+        acc |= (psigns(D1[0], D1[1]) & 0x02020202u) | (psigns(D1[2], D1[3]) & 0x20202020u);
+        acc |= (psigns(D2[0], D2[1]) & 0x04040404u) | (psigns(D2[2], D2[3]) & 0x40404040u);
+        acc |= (psigns(D3[0], D3[1]) & 0x08080808u) | (psigns(D3[2], D3[3]) & 0x80808080u);
+        word = ~acc;
+      }
+      brow[(size_t)i * 64] = (Word)word;
+      if (NEXT && L == 63) {
+        cw[3 * i] = phi(Vp[NP - 1]);
+        cw[3 * i + 1] = phi(Mv[NP - 1]);
+        cw[3 * i + 2] = max(max(exc, agg) - TC * ge, kNeg16);
+      }
+      cv_prev = cv_in;
+      if (last_tile && i == A - 1) {
+        // the end pair's M (MODE 0) or the end cell's V reaches the score
+        const int jb = B - 1 - jc0;
+        int mend = 0;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const uint32_t x = MODE == 0 ? Mv[c / 2] : Vp[c / 2];
+          if (jb == c) mend = (c & 1) ? phi(x) : plo(x);
+        }
+        ok = __ballot(jb >= 0 && jb < C && mend == P.score) != 0;
+      }
+    }
+  }
+}
+
+template <bool LB, int C, int MODE, class Word>
+__device__ __forceinline__ void fill16(const TraceArgs &a, const TracePair &P, const short *smat16,
+                                       Word *bits, int *carry, int crow, bool &bad, bool &ok) {
+  const int T = (P.B + 64 * C - 1) / (64 * C);
+  for (int t = 0; t < T; ++t) {
+    const int *cr = carry + ((t + 1) & 1) * 3 * crow;   // written by tile t - 1
+    int *cw = carry + (t & 1) * 3 * crow;                // read by tile t + 1
+    const bool next = t + 1 < T;
+    if (t == 0) {
+      if (next) fill16_tile<C, MODE, true, true>(a, P, smat16, bits, cr, cw, t, bad, ok);
+      else fill16_tile<C, MODE, true, false>(a, P, smat16, bits, cr, cw, t, bad, ok);
+    } else {
+      if (next) fill16_tile<C, MODE, false, true>(a, P, smat16, bits, cr, cw, t, bad, ok);
+      else fill16_tile<C, MODE, false, false>(a, P, smat16, bits, cr, cw, t, bad, ok);
+    }
+    // carries and bits are read back by this same wavefront (see trace_one)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  }
+}
 
 // One pair at C query columns per lane (a tile of 64 C columns).  MODE 0:
 // the rectangle between a local alignment's start and end pair, anchored at
@@ -81,22 +307,28 @@ __host__ __device__ constexpr int mat_words(int alpha) { return (alpha * alpha +
 // MODE - 1 (global, semi-global either way, overlap: the boundaries of
 // endtoend_kernel) over r[0..ref_end] x q[0..query_end], walked back from
 // its end cell to a virtual start element.
-template <bool LB, int C, int MODE>
+template <bool LB, int C, int MODE, bool W16>
 __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P, const int *smat,
-                                          uint16_t *lbits, int *lcarry, uint16_t *lwin) {
+                                          const short *smat16, uint16_t *lbits, int *lcarry,
+                                          uint16_t *lwin16) {
   // row -1 free: virtual pairs (-1, j) (query prefix free); column -1 free:
   // virtual pairs (i, -1) (reference prefix free)
   constexpr bool kRowFree = MODE == 3 || MODE == 4, kColFree = MODE == 2 || MODE == 4;
   constexpr int TC = 64 * C;
+  // one lane's decision word per row: 4 bits per column
+  using Word = typename std::conditional<(C > 4), uint32_t, uint16_t>::type;
+  constexpr int kWinRows = kWalkWindowBytes / (64 * (int)sizeof(Word));
   const int L = threadIdx.x;
   const int alpha = a.alpha, go = a.go, ge = a.ge;
   const int A = P.A, B = P.B, T = (B + TC - 1) / TC;
-  uint16_t *bits = LB ? lbits : a.gbits + (size_t)blockIdx.x * a.slot_words;
+  Word *bits = (Word *)(LB ? lbits : a.gbits + (size_t)blockIdx.x * a.slot_words);
+  Word *lwin = (Word *)lwin16;
   int *carry = LB ? lcarry : a.gcarry + (size_t)blockIdx.x * 6 * a.carry_rows;
   const int crow = LB ? kTraceLdsCarryRows : a.carry_rows;
   bool bad = false, ok = false;
 
-  for (int t = 0; t < T; ++t) {
+  if constexpr (W16) fill16<LB, C, MODE, Word>(a, P, smat16, bits, carry, crow, bad, ok);
+  else for (int t = 0; t < T; ++t) {
     const int base = t * TC, jc0 = base + C * L;
     const int *cr = carry + ((t + 1) & 1) * 3 * crow;   // written by tile t - 1
     int *cw = carry + (t & 1) * 3 * crow;                // read by tile t + 1
@@ -171,7 +403,7 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
         Gp[c] = g;
         Fp[c] = f;
       }
-      bits[((size_t)t * A + i) * 64 + L] = (uint16_t)word;
+      bits[((size_t)t * A + i) * 64 + L] = (Word)word;
       if (t + 1 < T && L == 63) {
         cw[3 * i] = Vp[C - 1];
         cw[3 * i + 1] = Mv[C - 1];
@@ -204,7 +436,7 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     if (nrun < P.cap && L == 0) a.cigar[end - 1 - nrun] = v;
     ++nrun;
   };
-  // device-memory bits are read through an LDS window of kWalkRows rows of
+  // device-memory bits are read through an LDS window of kWinRows rows of
   // one tile (the walk only moves up and left): one coalesced copy per
   // window instead of a dependent device-memory load per step
   int w_tile = -1, w_lo = 0;
@@ -214,17 +446,17 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     if (LB) {
       wd = bits[((size_t)t * A + i) * 64 + col];
     } else {
-      if (t != w_tile || i < w_lo || i >= w_lo + kWalkRows) {
+      if (t != w_tile || i < w_lo || i >= w_lo + kWinRows) {
         w_tile = t;
-        w_lo = max(0, i - kWalkRows + 1);
-        const int rows = min(kWalkRows, A - w_lo);
+        w_lo = max(0, i - kWinRows + 1);
+        const int rows = min(kWinRows, A - w_lo);
         const uint4 *src = (const uint4 *)(bits + ((size_t)t * A + w_lo) * 64);
         uint4 *dst = (uint4 *)lwin;
-        for (int k = L; k < rows * 8; k += 64) dst[k] = src[k];
+        for (int k = L; k < rows * 4 * (int)sizeof(Word); k += 64) dst[k] = src[k];
       }
       wd = lwin[(i - w_lo) * 64 + col];
     }
-    return (int)(wd >> (4 * (j % C))) & 15;
+    return (int)(wd >> nib_shift<C, W16>(j % C)) & 15;
   };
   // Runs of plain diagonal steps (a pair whose predecessor is the pair just
   // up-left: V = G = M, bits 0 and 2 of the nibble) are found 64 cells at a
@@ -242,7 +474,7 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
       const int t = jj / TC, col = (jj % TC) / C;
       const uint32_t wd = LB ? (uint32_t)bits[((size_t)t * A + ii) * 64 + col]
                              : (uint32_t)lwin[(ii - w_lo) * 64 + col];
-      nib = (int)(wd >> (4 * (jj % C))) & 15;
+      nib = (int)(wd >> nib_shift<C, W16>(jj % C)) & 15;
     }
     const uint64_t plain = __ballot(in && (nib & 5) == 5);
     return plain == ~0ull ? 64 : __builtin_ctzll(~plain);
@@ -374,37 +606,51 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
   }
 }
 
-template <bool LB, int MODE>
+// V: the variant of every pair of the launch (kTraceV32: C from
+// TracePair::pad, the fewest columns per lane that cover a one-tile query, so
+// short queries leave few lanes idle; kTraceV16x4 / kTraceV16x8: 16-bit
+// values at 4 / 8 columns per lane).  One kernel per variant, so that each
+// keeps its own register budget and occupancy.
+template <bool LB, int MODE, int V>
 __device__ __forceinline__ void trace_mode(const TraceArgs &a, const TracePair &P, const int *smat,
-                                           uint16_t *lbits, int *lcarry, uint16_t *lwin) {
-  switch (P.pad) {
-    case 1: trace_one<LB, 1, MODE>(a, P, smat, lbits, lcarry, lwin); break;
-    case 2: trace_one<LB, 2, MODE>(a, P, smat, lbits, lcarry, lwin); break;
-    case 3: trace_one<LB, 3, MODE>(a, P, smat, lbits, lcarry, lwin); break;
-    default: trace_one<LB, 4, MODE>(a, P, smat, lbits, lcarry, lwin); break;
+                                           const short *smat16, uint16_t *lbits, int *lcarry,
+                                           uint16_t *lwin) {
+  if constexpr (V == kTraceV16x4) {
+    trace_one<LB, 4, MODE, true>(a, P, smat, smat16, lbits, lcarry, lwin);
+  } else if constexpr (V == kTraceV16x8) {
+    trace_one<LB, 8, MODE, true>(a, P, smat, smat16, lbits, lcarry, lwin);
+  } else {
+    switch (P.pad) {
+      case 1: trace_one<LB, 1, MODE, false>(a, P, smat, smat16, lbits, lcarry, lwin); break;
+      case 2: trace_one<LB, 2, MODE, false>(a, P, smat, smat16, lbits, lcarry, lwin); break;
+      case 3: trace_one<LB, 3, MODE, false>(a, P, smat, smat16, lbits, lcarry, lwin); break;
+      default: trace_one<LB, 4, MODE, false>(a, P, smat, smat16, lbits, lcarry, lwin); break;
+    }
   }
 }
 
-// C per pair from TracePair::pad: the fewest columns per lane that cover a
-// one-tile query, so short queries leave few lanes idle.
-template <bool LB>
+template <bool LB, int V>
 __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   extern __shared__ int smem[];
   int *smat = smem;                                            // [query code][ref code]
-  // the matrix takes alpha^2 words (16-byte aligned), the bits follow
-  uint16_t *lbits = (uint16_t *)(smem + mat_words(a.alpha));
+  short *smat16 = (short *)(smem + mat_words(a.alpha));        // the same, 16-bit entries
+  // the matrices take alpha^2 words and shorts (16-byte aligned), the bits follow
+  uint16_t *lbits = (uint16_t *)(smem + mat_words(a.alpha) + mat16_words(a.alpha));
   int *lcarry = (int *)(lbits + kTraceLdsRowTiles * 64);
   uint16_t *lwin = lbits;                                      // walk window (device-memory bits)
-  for (int k = threadIdx.x; k < a.alpha * a.alpha; k += 64) smat[k] = a.matrix[k];
+  for (int k = threadIdx.x; k < a.alpha * a.alpha; k += 64) {
+    smat[k] = a.matrix[k];
+    smat16[k] = (short)a.matrix[k];
+  }
   __syncthreads();
   for (int p = blockIdx.x; p < a.n; p += gridDim.x) {
     const TracePair P = a.pairs[p];
     switch (a.mode) {
-      case 0: trace_mode<LB, 0>(a, P, smat, lbits, lcarry, lwin); break;
-      case 1: trace_mode<LB, 1>(a, P, smat, lbits, lcarry, lwin); break;
-      case 2: trace_mode<LB, 2>(a, P, smat, lbits, lcarry, lwin); break;
-      case 3: trace_mode<LB, 3>(a, P, smat, lbits, lcarry, lwin); break;
-      default: trace_mode<LB, 4>(a, P, smat, lbits, lcarry, lwin); break;
+      case 0: trace_mode<LB, 0, V>(a, P, smat, smat16, lbits, lcarry, lwin); break;
+      case 1: trace_mode<LB, 1, V>(a, P, smat, smat16, lbits, lcarry, lwin); break;
+      case 2: trace_mode<LB, 2, V>(a, P, smat, smat16, lbits, lcarry, lwin); break;
+      case 3: trace_mode<LB, 3, V>(a, P, smat, smat16, lbits, lcarry, lwin); break;
+      default: trace_mode<LB, 4, V>(a, P, smat, smat16, lbits, lcarry, lwin); break;
     }
   }
 }
@@ -721,9 +967,9 @@ __global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, 
 }  // namespace dev
 
 size_t trace_lds_bytes(bool lds_bits, int alpha) {
-  size_t b = (size_t)dev::mat_words(alpha) * sizeof(int);
+  size_t b = (size_t)(dev::mat_words(alpha) + dev::mat16_words(alpha)) * sizeof(int);
   if (lds_bits) b += (size_t)kTraceLdsRowTiles * 64 * sizeof(uint16_t) + 6 * kTraceLdsCarryRows * sizeof(int);
-  else b += (size_t)dev::kWalkRows * 64 * sizeof(uint16_t);
+  else b += (size_t)dev::kWalkWindowBytes;
   return b;
 }
 
@@ -765,14 +1011,22 @@ hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs
   return hipGetLastError();
 }
 
-hipError_t launch_trace(bool lds_bits, const TraceArgs &a, int grid, hipStream_t st) {
+template <bool LB>
+static void launch_trace_v(int variant, const TraceArgs &a, int grid, hipStream_t st) {
+  const size_t lds = trace_lds_bytes(LB, a.alpha);
+  switch (variant) {
+    case kTraceV16x4: hipLaunchKernelGGL((dev::trace_kernel<LB, kTraceV16x4>), dim3(grid), dim3(64), lds, st, a); break;
+    case kTraceV16x8: hipLaunchKernelGGL((dev::trace_kernel<LB, kTraceV16x8>), dim3(grid), dim3(64), lds, st, a); break;
+    default: hipLaunchKernelGGL((dev::trace_kernel<LB, kTraceV32>), dim3(grid), dim3(64), lds, st, a); break;
+  }
+}
+
+hipError_t launch_trace(bool lds_bits, int variant, const TraceArgs &a, int grid, hipStream_t st) {
   if (a.n <= 0 || grid <= 0) return hipSuccess;
-  if (lds_bits)
-    hipLaunchKernelGGL(dev::trace_kernel<true>, dim3(grid), dim3(64), trace_lds_bytes(true, a.alpha),
-                       st, a);
-  else
-    hipLaunchKernelGGL(dev::trace_kernel<false>, dim3(grid), dim3(64),
-                       trace_lds_bytes(false, a.alpha), st, a);
+  if (variant != kTraceV32 && variant != kTraceV16x4 && variant != kTraceV16x8)
+    return hipErrorInvalidValue;
+  if (lds_bits) launch_trace_v<true>(variant, a, grid, st);
+  else launch_trace_v<false>(variant, a, grid, st);
   return hipGetLastError();
 }
 

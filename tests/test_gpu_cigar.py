@@ -1,7 +1,15 @@
 """Alignment paths (sw_align_batch_cigar): every path equals the CPU oracle's
 (canonical predecessor rule, reference gap before query gap) where the oracle
 finishes quickly, and at every size the runs cover exactly the rectangle
-between start and end cell and add up to the score; through the C ABI."""
+between start and end cell and add up to the score; through the C ABI.
+
+The path kernel fills rectangles in 16-bit values when their value range
+fits and in 32-bit values otherwise.  Scaling the matrix and both gap
+penalties by 1000 keeps every optimal path and every tie (all scores scale
+alike) but leaves the 16-bit range, so the shape tests run each rectangle
+class through both fills."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -23,6 +31,26 @@ def _seqs(w, k):
     ri = int(w.pair_ref[k])
     return (w.query_res[w.query_off[qi]:w.query_off[qi + 1]],
             w.ref_res[w.ref_off[ri]:w.ref_off[ri + 1]])
+
+
+def _scaled(w, k):
+    """The same pairs with the matrix and both penalties times k."""
+    if k == 1:
+        return w
+    return dataclasses.replace(w, matrix=(w.matrix * k).astype(np.int32),
+                               gap_open=w.gap_open * k, gap_extend=w.gap_extend * k)
+
+
+def _fits16(w, ends, qs, rs, k):
+    """The host's 16-bit rule for pair k's rectangle (4 or 8 columns per lane)."""
+    A = int(ends[k, 2] - rs[k] + 1)
+    B = int(ends[k, 1] - qs[k] + 1)
+    ge = min(w.gap_extend, w.gap_open)
+    maxabs = int(np.abs(w.matrix).max())
+    tc = 256 if B <= 256 else 512
+    span = 5 * (maxabs + w.gap_open) + (A + B + 3 + tc) * ge + 256
+    top = min(A, B) * int(max(w.matrix.max(), 0)) + tc * ge + maxabs + 256
+    return B > 64 and span < 32768 and top < 32767
 
 
 def _paths(w):
@@ -103,31 +131,64 @@ def _gap_family(n_pairs, seed, core, junk, alpha=4, go=2, ge=0):
 
 
 def test_paths_across_tiles_in_lds():
-    # 48 rows x about 300-550 columns: two or three tiles, decision bits in LDS
-    w = _gap_family(6, 960, (24, 24), [250, 330, 500])
+    # 48 rows x about 300-550 columns in 32-bit values: two or three tiles of
+    # 256 columns, decision bits in LDS
+    w = _scaled(_gap_family(6, 960, (24, 24), [250, 330, 500]), 1000)
     ends, qs, rs, runs, off = _paths(w)
     _check_properties(w, ends, qs, rs, runs, off, "tiles lds")
     assert (ends[:, 1] - qs + 1 > 256).all()
+    assert not any(_fits16(w, ends, qs, rs, k) for k in range(w.n_pairs))
     _check_oracle(w, ends, qs, rs, runs, off, "tiles lds", range(w.n_pairs))
 
 
-def test_paths_every_column_count():
-    # 24-row rectangles whose query spans fall in each columns-per-lane class
-    # (1-64, 65-128, 129-192, 193-256 columns: 1, 2, 3, 4 columns per lane)
-    w = _gap_family(8, 964, (12, 12), [10, 40, 70, 100, 140, 150, 200, 230])
+def test_paths_16bit_across_tiles_in_lds():
+    # 24 rows x about 540-930 columns in 16-bit values: two tiles of 512
+    # columns (8 per lane, 4-byte decision words), decision bits in LDS
+    w = _gap_family(6, 965, (12, 12), [520, 600, 750, 900])
     ends, qs, rs, runs, off = _paths(w)
-    _check_properties(w, ends, qs, rs, runs, off, "columns")
+    _check_properties(w, ends, qs, rs, runs, off, "16-bit tiles lds")
     B = ends[:, 1] - qs + 1
-    assert {int((b + 63) // 64) for b in B} == {1, 2, 3, 4}
-    _check_oracle(w, ends, qs, rs, runs, off, "columns", range(w.n_pairs))
+    assert ((B > 512) & (B <= 1024)).all() and (ends[:, 2] - rs + 1 <= 40).all()
+    assert all(_fits16(w, ends, qs, rs, k) for k in range(w.n_pairs))
+    _check_oracle(w, ends, qs, rs, runs, off, "16-bit tiles lds", range(w.n_pairs))
 
 
-def test_paths_in_device_memory():
-    # 90 rows x about 290-370 columns: beyond LDS, decision bits in device memory
-    w = _gap_family(4, 961, (45, 45), [200, 280])
+@pytest.mark.parametrize("scale", [1, 1000])
+def test_paths_every_column_count(scale):
+    # 24-row rectangles whose query spans fall in each columns-per-lane class:
+    # in 32-bit values (scale 1000) 1-64, 65-128, 129-192, 193-256 columns
+    # (1, 2, 3, 4 columns per lane); in 16-bit values (scale 1) 1-64 columns
+    # stay 32-bit, 65-256 take 4 columns per lane, 257-512 take 8
+    junk = [10, 40, 70, 100, 140, 150, 200, 230] + ([300, 420] if scale == 1 else [])
+    w = _scaled(_gap_family(len(junk), 964, (12, 12), junk), scale)
+    ends, qs, rs, runs, off = _paths(w)
+    _check_properties(w, ends, qs, rs, runs, off, "columns x%d" % scale)
+    B = ends[:, 1] - qs + 1
+    if scale == 1:
+        assert {int(b <= 64) + 4 * int(64 < b <= 256) + 8 * int(b > 256) for b in B} == {1, 4, 8}
+        assert all(_fits16(w, ends, qs, rs, k) == (B[k] > 64) for k in range(w.n_pairs))
+    else:
+        assert {int((b + 63) // 64) for b in B} == {1, 2, 3, 4}
+        assert not any(_fits16(w, ends, qs, rs, k) for k in range(w.n_pairs))
+    _check_oracle(w, ends, qs, rs, runs, off, "columns x%d" % scale, range(w.n_pairs))
+
+
+@pytest.mark.parametrize("scale,junk", [(1, [200, 280]), (1000, [200, 280]), (1, [600, 800])])
+def test_paths_in_device_memory(scale, junk):
+    # 90 rows x about 290-370 columns (one 512-column tile in 16-bit values,
+    # two 256-column tiles in 32-bit ones) or about 690-890 (two 512-column
+    # tiles): beyond LDS, decision bits in device memory
+    w = _scaled(_gap_family(4, 961, (45, 45), junk), scale)
     ends, qs, rs, runs, off = _paths(w)
     _check_properties(w, ends, qs, rs, runs, off, "device memory")
-    assert ((ends[:, 2] - rs + 1) * ((ends[:, 1] - qs + 256) // 256) > 160).all()
+    A = ends[:, 2] - rs + 1
+    B = ends[:, 1] - qs + 1
+    if scale == 1:
+        assert all(_fits16(w, ends, qs, rs, k) for k in range(w.n_pairs))
+        assert (A * ((B + 511) // 512) * 2 > 160).all()
+    else:
+        assert not any(_fits16(w, ends, qs, rs, k) for k in range(w.n_pairs))
+        assert (A * ((B + 255) // 256) > 160).all()
     _check_oracle(w, ends, qs, rs, runs, off, "device memory", range(w.n_pairs))
 
 

@@ -190,18 +190,22 @@ def test_paths_small_pairs_equal_the_oracle(mode, alpha, go, ge):
 
 
 @pytest.mark.parametrize("mode", MODES)
-def test_paths_across_tiles_and_in_device_memory(mode):
-    # queries of 257-700 residues (two or three tiles; rows x tiles beyond the
-    # LDS budget, so the decision bits live in device memory) and one-tile
-    # queries with up to 300 rows
+@pytest.mark.parametrize("scale", [1, 1000])
+def test_paths_across_tiles_and_in_device_memory(mode, scale):
+    # queries of 257-700 residues (one or two 512-column tiles in 16-bit
+    # values, two or three 256-column tiles in 32-bit values; rows x tiles
+    # beyond the LDS budget, so the decision bits live in device memory) and
+    # queries of 20-100 residues with up to 300 rows.  Scale 1000 multiplies
+    # the matrix and both penalties: the same optimal paths and ties, values
+    # beyond the 16-bit range, so the 32-bit fill runs
     rng = np.random.default_rng(1010 + mode)
-    M = W.random_matrix(rng, 4)
-    w = W.random_pairs(12, 4, (257, 700), (1, 90), 1011 + mode, matrix=M, gap_open=3,
-                       gap_extend=1)
-    _check_paths(w, mode, "tiles")
-    w = W.random_pairs(12, 4, (20, 100), (170, 300), 1012 + mode, matrix=M, gap_open=3,
-                       gap_extend=1)
-    _check_paths(w, mode, "rows")
+    M = W.random_matrix(rng, 4) * scale
+    w = W.random_pairs(12, 4, (257, 700), (1, 90), 1011 + mode, matrix=M, gap_open=3 * scale,
+                       gap_extend=scale)
+    _check_paths(w, mode, "tiles x%d" % scale)
+    w = W.random_pairs(12, 4, (20, 100), (170, 300), 1012 + mode, matrix=M, gap_open=3 * scale,
+                       gap_extend=scale)
+    _check_paths(w, mode, "rows x%d" % scale)
 
 
 def test_paths_dna_reads_in_windows():
