@@ -404,12 +404,18 @@ def sw_align_batch_cigar(query_res, query_off, ref_res, ref_off, pair_ref, matri
     rs = np.ascontiguousarray(np.asarray(ref_start, dtype=np.int32))
     if ends.shape != (npairs, 4) or qs.shape != (npairs,) or rs.shape != (npairs,):
         raise ValueError("results must be (n_pairs, 4), query_start and ref_start (n_pairs,)")
-    # capacity: the library's bound on the runs of each rectangle
-    live = ends[:, 0] > 0
-    A = (ends[:, 2] - rs).astype(np.int64) + 1
-    B = (ends[:, 1] - qs).astype(np.int64) + 1
-    bound = np.where(live, np.minimum(A + B - 1, 3 * np.minimum(A, B) - 2), 0)
-    cap = int(np.clip(bound, 0, None).sum()) if cigar_cap is None else int(cigar_cap)
+    # capacity: A + B - 1 runs per A x B rectangle (at least the library's
+    # bound, min(A + B - 1, 3 min(A, B) - 2)), in a few in-place passes
+    if cigar_cap is None:
+        live = ends[:, 0] > 0
+        span = ends[:, 1].astype(np.int64)
+        span += ends[:, 2]
+        span -= qs
+        span -= rs
+        span += 1
+        cap = int(span[live].clip(0, None).sum())
+    else:
+        cap = int(cigar_cap)
     runs = np.empty(max(cap, 1), dtype=np.uint32)
     off = np.empty(npairs + 1, dtype=np.int64)
     _check(lib.sw_align_batch_cigar(ctypes.byref(b), ctypes.byref(sc),
@@ -455,9 +461,13 @@ def sw_align_batch_global_cigar(query_res, query_off, ref_res, ref_off, pair_ref
     ends = np.ascontiguousarray(np.asarray(results, dtype=np.int32))
     if ends.shape != (npairs, 4):
         raise ValueError("results must be the (n_pairs, 4) array of sw_align_batch_global")
-    # capacity: the library's bound, (ref_end + 1) + m + 2 runs per pair
-    cap = int((ends[:, 2].astype(np.int64) + 1 + ends[:, 1].astype(np.int64) + 1 + 2).sum()) \
-        if cigar_cap is None else int(cigar_cap)
+    # capacity: the library's bound, (ref_end + 1) + (query_end + 1) + 2 runs per pair
+    if cigar_cap is None:
+        span = ends[:, 2].astype(np.int64)
+        span += ends[:, 1]
+        cap = int(span.sum()) + 4 * npairs
+    else:
+        cap = int(cigar_cap)
     runs = np.empty(max(cap, 1), dtype=np.uint32)
     off = np.empty(npairs + 1, dtype=np.int64)
     qs = np.empty(max(npairs, 1), dtype=np.int32)

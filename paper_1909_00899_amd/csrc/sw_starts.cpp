@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -59,14 +60,15 @@ struct StartsWork {
   // paths
   DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off;
   HostBuf tr_host, tr_hcounts;   // pinned: the pair table, the run counts
+  HostBuf ld_stage;              // pinned: a device-resident batch's offsets and indices
   DevBuf tr_res;                 // end-to-end results
   DevBuf tr_rstart;              // end-to-end paths: reference starts
   DevBuf tr_qstart;              // end-to-end paths: query starts
   HostBuf tr_hres;
-  // host scratch of the path tables: LDS rectangles of the two less common
-  // kernel variants, device-memory rectangles and their size classes
-  std::vector<swk::TracePair> tr_lds_v32, tr_lds_v8, tr_glob;
-  std::vector<uint8_t> tr_gcls;
+  // host scratch of the path tables: each pair's rectangle and class (the
+  // tables are built by host threads in two passes)
+  std::vector<swk::TracePair> tr_rect;
+  std::vector<uint8_t> tr_cls;
   // device-memory rectangles: the largest group, the second, the rest each on
   // a stream of their own, so the long poles of the largest rectangles (one
   // wavefront each) overlap instead of adding up
@@ -77,22 +79,17 @@ struct StartsWork {
 };
 StartsWork g_starts;
 
-template <class T>
-int read_back(std::vector<T> &dst, const T *src, size_t n, bool device) {
-  dst.resize(n);
-  if (n == 0) return SW_OK;
-  if (device) HIPCHK(hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
-  else std::memcpy(dst.data(), src, n * sizeof(T));
-  return SW_OK;
-}
 
 // What every path needs: the batch's offsets and ids on the host, its residues
 // on the device.
 struct Batch {
   const sw_batch *b;
   const sw_result *ends;
-  std::vector<int64_t> qoff, roff;
-  std::vector<int32_t> pq, pr;
+  // offsets and pair indices on the host: the caller's arrays, or (device-
+  // resident batches) a pinned copy; pq is all zeros without pair_query
+  const int64_t *qoff = nullptr, *roff = nullptr;
+  const int32_t *pq = nullptr, *pr = nullptr;
+  std::vector<int32_t> pq_zero;
   const uint8_t *d_q = nullptr, *d_r = nullptr;
 };
 
@@ -265,30 +262,66 @@ int load_batch(const sw_batch *b, StartsWork &W, Batch &B) {
     (void)hipEventDestroy(ev);
     HIPCHK(e);
   }
-  int rc;
   B.b = b;
-  if ((rc = read_back(B.qoff, b->query_off, (size_t)b->n_queries + 1, dev)) ||
-      (rc = read_back(B.roff, b->ref_off, (size_t)b->n_refs + 1, dev)) ||
-      (rc = read_back(B.pr, b->pair_ref, (size_t)np, dev)))
-    return rc;
-  if (b->pair_query) {
-    if ((rc = read_back(B.pq, b->pair_query, (size_t)np, dev))) return rc;
+  const int64_t nq = b->n_queries, nr = b->n_refs;
+  if (dev) {
+    // one pinned staging area, four asynchronous copies, one wait
+    const size_t bytes = (size_t)(nq + 1 + nr + 1) * 8 + (size_t)np * 8;
+    int rc = W.ld_stage.ensure(std::max<size_t>(bytes, 8));
+    if (rc) return rc;
+    unsigned char *h = W.ld_stage.as<unsigned char>();
+    int64_t *hq = (int64_t *)h, *hr = hq + nq + 1;
+    int32_t *hpr = (int32_t *)(hr + nr + 1), *hpq = hpr + np;
+    HIPCHK(hipMemcpyAsync(hq, b->query_off, (size_t)(nq + 1) * 8, hipMemcpyDeviceToHost, W.st));
+    HIPCHK(hipMemcpyAsync(hr, b->ref_off, (size_t)(nr + 1) * 8, hipMemcpyDeviceToHost, W.st));
+    if (np) HIPCHK(hipMemcpyAsync(hpr, b->pair_ref, (size_t)np * 4, hipMemcpyDeviceToHost, W.st));
+    if (np && b->pair_query)
+      HIPCHK(hipMemcpyAsync(hpq, b->pair_query, (size_t)np * 4, hipMemcpyDeviceToHost, W.st));
+    HIPCHK(hipStreamSynchronize(W.st));
+    B.qoff = hq;
+    B.roff = hr;
+    B.pr = hpr;
+    B.pq = b->pair_query ? hpq : nullptr;
   } else {
-    B.pq.assign(np, 0);
+    B.qoff = b->query_off;
+    B.roff = b->ref_off;
+    B.pr = b->pair_ref;
+    B.pq = b->pair_query;
   }
-  for (int k = 0; k < b->n_queries; ++k)
-    if (B.qoff[k] < 0 || B.qoff[k + 1] < B.qoff[k]) { set_error("query offsets not nondecreasing"); return SW_EINVAL; }
-  for (int k = 0; k < b->n_refs; ++k)
-    if (B.roff[k] < 0 || B.roff[k + 1] < B.roff[k]) { set_error("reference offsets not nondecreasing"); return SW_EINVAL; }
-  for (int k = 0; k < np; ++k)
-    if (B.pq[k] < 0 || B.pq[k] >= b->n_queries || B.pr[k] < 0 || B.pr[k] >= b->n_refs) {
-      set_error("pair %d refers to a query or reference out of range", k);
-      return SW_EINVAL;
-    }
+  if (!B.pq) {
+    B.pq_zero.assign(np, 0);
+    B.pq = B.pq_zero.data();
+  }
+  // validation on host threads; each check reports the first failing entry
+  const int T = std::max<int64_t>({nq, nr, (int64_t)np}) >= 65536 ? host_threads() : 1;
+  auto first_bad = [&](int64_t n, auto bad) -> int64_t {
+    std::vector<int64_t> at(T, INT64_MAX);
+    parallel_ranges((size_t)n, T, [&](int t, size_t lo, size_t hi) {
+      for (size_t k = lo; k < hi; ++k)
+        if (bad((int64_t)k)) { at[t] = (int64_t)k; return; }
+    });
+    return *std::min_element(at.begin(), at.end());
+  };
+  if (first_bad(nq, [&](int64_t k) { return B.qoff[k] < 0 || B.qoff[k + 1] < B.qoff[k]; }) != INT64_MAX) {
+    set_error("query offsets not nondecreasing");
+    return SW_EINVAL;
+  }
+  if (first_bad(nr, [&](int64_t k) { return B.roff[k] < 0 || B.roff[k + 1] < B.roff[k]; }) != INT64_MAX) {
+    set_error("reference offsets not nondecreasing");
+    return SW_EINVAL;
+  }
+  const int64_t kp = first_bad(np, [&](int64_t k) {
+    return B.pq[k] < 0 || B.pq[k] >= nq || B.pr[k] < 0 || B.pr[k] >= nr;
+  });
+  if (kp != INT64_MAX) {
+    set_error("pair %d refers to a query or reference out of range", (int)kp);
+    return SW_EINVAL;
+  }
   B.d_q = b->query_res;
   B.d_r = b->ref_res;
   if (!dev) {
     const size_t qb = (size_t)B.qoff[b->n_queries], rb = (size_t)B.roff[b->n_refs];
+    int rc;
     if ((rc = W.src_q.ensure(qb + 1)) || (rc = W.src_r.ensure(rb + 1))) return rc;
     if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, qb, hipMemcpyHostToDevice, W.st));
     if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, rb, hipMemcpyHostToDevice, W.st));
@@ -438,48 +471,52 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
   if ((rc = load_batch(b, W, B))) return rc;
   int64_t maxabs = 0;
   for (int v : S.M) maxabs = std::max<int64_t>(maxabs, v < 0 ? -(int64_t)v : v);
-  // ---- one rectangle per pair with a positive score; LDS-sized ones first,
-  // built straight into pinned memory (one fast upload)
+  // the table lives in pinned memory (one fast upload)
   if ((rc = W.tr_host.ensure((size_t)np * sizeof(swk::TracePair))) ||
       (rc = W.tr_hcounts.ensure((size_t)np * sizeof(int32_t))))
     return rc;
   swk::TracePair *htab = W.tr_host.as<swk::TracePair>();
-  int nl = 0;
-  std::vector<swk::TracePair> &glob = W.tr_glob, &lds32 = W.tr_lds_v32, &lds8 = W.tr_lds_v8;
-  std::vector<uint8_t> &gcls = W.tr_gcls;
-  glob.clear();
-  lds32.clear();
-  lds8.clear();
-  gcls.clear();
   int64_t region = 0;
-  // end-to-end alignments with an empty side have their runs made here
-  std::vector<std::pair<int, std::vector<uint32_t>>> host_runs;
+  // ---- one rectangle per pair with a positive score, built by host threads:
+  // pass 1 classifies every pair (its rectangle, kernel variant and size
+  // class, or an error, or runs made here), pass 2 lays the classes out
+  // (LDS rectangles by variant, then device-memory ones by size class,
+  // largest first; within a class in pair order) and assigns run regions in
+  // pair order, pass 3 writes the table straight into pinned memory
   auto gap = [&](int64_t L) -> int64_t { return L <= 0 ? 0 : S.go + (L - 1) * (int64_t)S.ge; };
-  for (int k = 0; k < np; ++k) {
+  // end-to-end alignments with an empty side: at most a D and an I run
+  struct HostRun { int k; int n; uint32_t run[2]; };
+  constexpr int NCLS = 3 + kSlotBuckets * 3;     // LDS variants, then size classes
+  constexpr uint8_t kSkip = 0xff, kHost = 0xfe;
+  // classifies pair k: kSkip (no path), kHost (runs in *hr), a class with the
+  // rectangle in *tp, or an error (returns its code; with report, sets the message)
+  auto classify = [&](int k, bool report, swk::TracePair *tp, HostRun *hr,
+                      uint8_t *cls) -> int {
     const sw_result &e = ends[k];
     const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
     const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
     int qs = 0, rs = 0;
+    *cls = kSkip;
     if (mode == 0) {
-      if (e.score <= 0) continue;
+      if (e.score <= 0) return SW_OK;
       qs = query_start[k];
       rs = ref_start[k];
       if (qs < 0 || qs > e.query_end || e.query_end >= m || rs < 0 || rs > e.ref_end ||
           e.ref_end >= n) {
-        set_error("pair %d: start (%d, %d) and end (%d, %d) are not a rectangle of its %lld x "
-                  "%lld sequences", k, qs, rs, e.query_end, e.ref_end, (long long)m, (long long)n);
+        if (report)
+          set_error("pair %d: start (%d, %d) and end (%d, %d) are not a rectangle of its %lld x "
+                    "%lld sequences", k, qs, rs, e.query_end, e.ref_end, (long long)m, (long long)n);
         return SW_EINVAL;
       }
     } else {
-      ref_start_out[k] = 0;
-      query_start_out[k] = 0;
       const bool in = e.ref_end >= -1 && e.ref_end < n && e.query_end >= -1 && e.query_end < m;
       const bool on_q = e.query_end == m - 1, on_r = e.ref_end == n - 1;
       const bool ok = mode == 1 ? on_q && on_r : mode == 2 ? on_q : mode == 3 ? on_r : on_q || on_r;
       if (!in || !ok) {
-        set_error("pair %d: end (%d, %d) is not the end cell of a %s alignment of its %lld x %lld "
-                  "sequences", k, e.query_end, e.ref_end, kModeName[mode], (long long)m,
-                  (long long)n);
+        if (report)
+          set_error("pair %d: end (%d, %d) is not the end cell of a %s alignment of its %lld x "
+                    "%lld sequences", k, e.query_end, e.ref_end, kModeName[mode], (long long)m,
+                    (long long)n);
         return SW_EINVAL;
       }
       if (e.query_end < 0 || e.ref_end < 0) {
@@ -499,17 +536,19 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
         for (int64_t x = 0; col_free && x < A0; ++x) consider(x, -1);
         for (int64_t y = 0; row_free && y < B0; ++y) consider(-1, y);
         if (e.score != best) {
-          set_error("pair %d: score %d is not the optimum at the end cell (%d, %d)", k, e.score,
-                    e.query_end, e.ref_end);
+          if (report)
+            set_error("pair %d: score %d is not the optimum at the end cell (%d, %d)", k, e.score,
+                      e.query_end, e.ref_end);
           return SW_EINVAL;
         }
-        std::vector<uint32_t> v;
-        if (A0 - 1 - bx) v.push_back((uint32_t)(A0 - 1 - bx) << 4 | swk::kCigarD);
-        if (B0 - 1 - by) v.push_back((uint32_t)(B0 - 1 - by) << 4 | swk::kCigarI);
+        hr->k = k;
+        hr->n = 0;
+        if (A0 - 1 - bx) hr->run[hr->n++] = (uint32_t)(A0 - 1 - bx) << 4 | swk::kCigarD;
+        if (B0 - 1 - by) hr->run[hr->n++] = (uint32_t)(B0 - 1 - by) << 4 | swk::kCigarI;
         ref_start_out[k] = (int32_t)(bx + 1);
         query_start_out[k] = (int32_t)(by + 1);
-        host_runs.emplace_back(k, std::move(v));
-        continue;
+        *cls = kHost;
+        return SW_OK;
       }
     }
     const int64_t A = e.ref_end - rs + 1, Bq = e.query_end - qs + 1;
@@ -518,26 +557,24 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     const int64_t lo = 2 * (maxabs + S.go) + (A + Bq + 2 * swk::kTraceTileCols) * (S.ge + 1);
     const int64_t hi = std::min(A, Bq) * (int64_t)S.max_s + (Bq + swk::kTraceTileCols) * S.ge;
     if (lo >= (1ll << 27) || hi >= (1ll << 30)) {
-      set_error("pair %d: a %lld x %lld rectangle leaves the int32 range of the path kernel", k,
-                (long long)A, (long long)Bq);
+      if (report)
+        set_error("pair %d: a %lld x %lld rectangle leaves the int32 range of the path kernel", k,
+                  (long long)A, (long long)Bq);
       return SW_EOVERFLOW;
     }
-    swk::TracePair tp;
-    tp.q = B.qoff[B.pq[k]] + qs;
-    tp.r = B.roff[B.pr[k]] + rs;
-    tp.out = region;
-    tp.A = (int32_t)A;
-    tp.B = (int32_t)Bq;
-    tp.score = e.score;
+    tp->q = B.qoff[B.pq[k]] + qs;
+    tp->r = B.roff[B.pr[k]] + rs;
+    tp->out = 0;
+    tp->A = (int32_t)A;
+    tp->B = (int32_t)Bq;
+    tp->score = e.score;
     // end-to-end: k <= min(A, B) pairs, k M runs and two gap runs in each of the
     // k + 1 gaps (start, between pairs, end)
-    tp.cap = (int32_t)(mode == 0 ? run_bound(A, Bq) : std::min(A + Bq + 2, 3 * std::min(A, Bq) + 2));
-    tp.id = k;
-    tp.pad = 0;
-    region += tp.cap;
+    tp->cap = (int32_t)(mode == 0 ? run_bound(A, Bq) : std::min(A + Bq + 2, 3 * std::min(A, Bq) + 2));
+    tp->id = k;
     // columns per lane: the fewest that hold a one-tile query (4 beyond), so
     // a one-tile query's slot of 64-lane rows is the same at any count
-    tp.pad = (int32_t)std::min<int64_t>(4, (Bq + 63) / 64);
+    tp->pad = (int32_t)std::min<int64_t>(4, (Bq + 63) / 64);
     // 16-bit values (4 or 8 columns per lane) when the rectangle's range
     // provably fits: every reachable value -- a pair and two gap runs from
     // the start or a boundary, plus a gap opening, or a scan term with its
@@ -548,63 +585,133 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
       const int64_t tc = Bq <= 256 ? 256 : 512;
       const int64_t span = 5 * (maxabs + S.go) + (A + Bq + 3 + tc) * (int64_t)S.ge + 256;
       const int64_t top = std::min(A, Bq) * (int64_t)S.max_s + tc * S.ge + maxabs + 256;
-      if (span < 32768 && top < 32767) tp.pad = swk::kTracePad16 | (int32_t)(tc / 64);
+      if (span < 32768 && top < 32767) tp->pad = swk::kTracePad16 | (int32_t)(tc / 64);
     }
-    const int64_t slot = trace_slot_words(tp);
-    const int variant = swk::trace_variant(tp.pad);
+    const int64_t slot = trace_slot_words(*tp);
+    const int variant = swk::trace_variant(tp->pad);
     if (slot <= (int64_t)swk::kTraceLdsRowTiles * 64) {
-      // LDS rectangles in runs of one kernel variant (one launch each): the
-      // 16-bit four-column one straight into the table, the others after it
-      if (variant == swk::kTraceV16x4) htab[nl++] = tp;
-      else (variant == swk::kTraceV32 ? lds32 : lds8).push_back(tp);
+      // LDS rectangles in runs of one kernel variant (one launch each), the
+      // common 16-bit four-column one first
+      *cls = (uint8_t)(variant == swk::kTraceV16x4 ? 0 : variant == swk::kTraceV32 ? 1 : 2);
     } else {
       if (slot * 2 > (2ll << 30)) {
-        set_error("pair %d: a %lld x %lld rectangle needs more than 2 GiB of path scratch", k,
-                  (long long)A, (long long)Bq);
+        if (report)
+          set_error("pair %d: a %lld x %lld rectangle needs more than 2 GiB of path scratch", k,
+                    (long long)A, (long long)Bq);
         return SW_ENOMEM;
       }
-      glob.push_back(tp);
-      gcls.push_back((uint8_t)trace_size_class(slot, variant));
+      *cls = (uint8_t)(3 + trace_size_class(slot, variant));
+    }
+    return SW_OK;
+  };
+
+  if (W.tr_rect.size() < (size_t)np) W.tr_rect.resize(np);
+  if (W.tr_cls.size() < (size_t)np) W.tr_cls.resize(np);
+  swk::TracePair *rect = W.tr_rect.data();
+  uint8_t *cls = W.tr_cls.data();
+  const int T = np >= 65536 ? host_threads() : 1;
+  struct Part {
+    int64_t count[NCLS] = {}, caps = 0, cslot[NCLS] = {};
+    int crows[NCLS] = {};
+    int first_err = INT32_MAX;
+    std::vector<HostRun> host;
+  };
+  std::vector<Part> part(T);
+  parallel_ranges((size_t)np, T, [&](int t, size_t lo, size_t hi) {
+    Part &P = part[t];
+    for (size_t k = lo; k < hi; ++k) {
+      if (mode != 0) {
+        ref_start_out[k] = 0;
+        query_start_out[k] = 0;
+      }
+      HostRun hr;
+      if (classify((int)k, false, &rect[k], &hr, &cls[k]) != SW_OK) {
+        P.first_err = (int)k;
+        return;
+      }
+      const uint8_t c = cls[k];
+      if (c == kHost) {
+        P.host.push_back(hr);
+      } else if (c != kSkip) {
+        ++P.count[c];
+        P.caps += rect[k].cap;
+        P.cslot[c] = std::max(P.cslot[c], trace_slot_words(rect[k]));
+        P.crows[c] = std::max(P.crows[c], rect[k].A);
+      }
+    }
+  });
+  {
+    int first = INT32_MAX;
+    for (const Part &P : part) first = std::min(first, P.first_err);
+    if (first != INT32_MAX) {   // the first failing pair, as a serial pass finds it
+      swk::TracePair tp;
+      HostRun hr;
+      uint8_t c;
+      return classify(first, true, &tp, &hr, &c);
     }
   }
-  for (const auto *v : {&lds32, &lds8}) {
-    if (!v->empty()) std::memcpy(htab + nl, v->data(), v->size() * sizeof(swk::TracePair));
-    nl += (int)v->size();
-  }
-  // device-memory rectangles by size class (two passes, no sort), largest
-  // class first; one launch group per class
-  constexpr int NCLS = kSlotBuckets * 3;
-  int64_t ccount[NCLS] = {}, cslot[NCLS] = {}, cstart[NCLS + 1] = {};
+  // class layout, and each thread's first slot in every class and region
+  int64_t cstart[NCLS + 1] = {}, cslot[NCLS] = {};
   int crows[NCLS] = {};
-  const int ng = (int)glob.size(), nt = nl + ng;
-  for (int t = 0; t < ng; ++t) {
-    const int c = gcls[t];
-    ++ccount[c];
-    cslot[c] = std::max(cslot[c], trace_slot_words(glob[t]));
-    crows[c] = std::max(crows[c], glob[t].A);
+  for (int c = 0; c < NCLS; ++c) {
+    int64_t cnt = 0;
+    for (const Part &P : part) {
+      cnt += P.count[c];
+      cslot[c] = std::max(cslot[c], P.cslot[c]);
+      crows[c] = std::max(crows[c], P.crows[c]);
+    }
+    cstart[c + 1] = cstart[c] + cnt;
   }
-  for (int c = 0; c < NCLS; ++c) cstart[c + 1] = cstart[c] + ccount[c];
+  const int nl = (int)cstart[3], nt = (int)cstart[NCLS], ng = nt - nl;
+  std::vector<std::array<int64_t, NCLS>> tpos(T);
+  std::vector<int64_t> treg(T);
   {
-    int64_t fill[NCLS];
-    std::memcpy(fill, cstart, sizeof(fill));
-    for (int t = 0; t < ng; ++t) htab[nl + fill[gcls[t]]++] = glob[t];
+    int64_t run[NCLS];
+    std::memcpy(run, cstart, sizeof(run));
+    int64_t reg = 0;
+    for (int t = 0; t < T; ++t) {
+      for (int c = 0; c < NCLS; ++c) {
+        tpos[t][c] = run[c];
+        run[c] += part[t].count[c];
+      }
+      treg[t] = reg;
+      reg += part[t].caps;
+    }
+    region = reg;
   }
+  parallel_ranges((size_t)np, T, [&](int t, size_t lo, size_t hi) {
+    int64_t reg = treg[t];
+    std::array<int64_t, NCLS> &pos = tpos[t];
+    for (size_t k = lo; k < hi; ++k) {
+      const uint8_t c = cls[k];
+      if (c >= NCLS) continue;
+      swk::TracePair tp = rect[k];
+      tp.out = reg;
+      reg += tp.cap;
+      htab[pos[c]++] = tp;
+    }
+  });
+  std::vector<HostRun> host_runs;
+  for (Part &P : part) host_runs.insert(host_runs.end(), P.host.begin(), P.host.end());
+  // one launch group per device-memory size class
   struct Group { int first, count, waves; int64_t slot_words; int carry_rows; int variant; };
   std::vector<Group> groups;
   constexpr int NS = StartsWork::kTraceStreams;
   int64_t bits_words[NS] = {}, carry_ints[NS] = {};
-  for (int c = 0; c < NCLS; ++c) {
-    if (!ccount[c]) continue;
+  for (int c = 3; c < NCLS; ++c) {
+    const int64_t cnt = cstart[c + 1] - cstart[c];
+    if (!cnt) continue;
     const int64_t slot = cslot[c];
     const int carry_rows = std::max(1, crows[c]);
     const int64_t per_wave = slot * 2 + 6ll * carry_rows * 4;
     const int waves = (int)std::max<int64_t>(
-        1, std::min<int64_t>({ccount[c], kTraceScratchBytes / per_wave, kTraceMaxWaves}));
+        1, std::min<int64_t>({cnt, kTraceScratchBytes / per_wave, kTraceMaxWaves}));
     const int sk = std::min((int)groups.size(), NS - 1);
-    groups.push_back({(int)cstart[c], (int)ccount[c], waves, slot, carry_rows, c % 3});
+    groups.push_back({(int)(cstart[c] - nl), (int)cnt, waves, slot, carry_rows, (c - 3) % 3});
     bits_words[sk] = std::max<int64_t>(bits_words[sk], slot * waves);
     carry_ints[sk] = std::max<int64_t>(carry_ints[sk], 6ll * carry_rows * waves);
   }
+  (void)ng;
   std::vector<int32_t> counts(np, 0);
   if (nt > 0) {
     if ((rc = W.tr_pairs.ensure((size_t)nt * sizeof(swk::TracePair))) ||
@@ -686,14 +793,18 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
                             hipMemcpyDeviceToHost, W.st));
     }
     HIPCHK(hipStreamSynchronize(W.st));
-    for (int t = 0; t < nt; ++t) {
+    // run counts by pair; the first entry of the table (LDS rectangles, then
+    // device-memory ones) with an error is reported
+    auto check = [&](int t, bool report) -> int {
       const swk::TracePair &P = htab[t];
       const int c = dev_counts[P.id];
       if (c == swk::kTraceBadResidue) {
-        set_error("pair %d: a residue code inside its alignment is not below alphabet_size", P.id);
+        if (report)
+          set_error("pair %d: a residue code inside its alignment is not below alphabet_size", P.id);
         return SW_EINVAL;
       }
       if (c == swk::kTraceInconsistent) {
+        if (!report) return SW_EINVAL;
         if (mode == 0)
           set_error("pair %d: no alignment of score %d runs from its start (%d, %d) to its end "
                     "(%d, %d)", P.id, P.score, query_start[P.id], ref_start[P.id],
@@ -704,7 +815,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
         return SW_EINVAL;
       }
       if (c < 1 || c > P.cap) {
-        set_error("pair %d: internal path error (%d runs, bound %d)", P.id, c, P.cap);
+        if (report) set_error("pair %d: internal path error (%d runs, bound %d)", P.id, c, P.cap);
         return SW_EDEVICE;
       }
       counts[P.id] = c;
@@ -712,10 +823,32 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
         ref_start_out[P.id] = dev_rstart[P.id];
         query_start_out[P.id] = dev_qstart[P.id];
       }
-    }
+      return SW_OK;
+    };
+    const int TT = nt >= 65536 ? host_threads() : 1;
+    std::vector<int> bad(TT, INT32_MAX);
+    parallel_ranges((size_t)nt, TT, [&](int th, size_t lo, size_t hi) {
+      for (size_t t = lo; t < hi; ++t)
+        if (check((int)t, false) != SW_OK) { bad[th] = (int)t; return; }
+    });
+    const int first = *std::min_element(bad.begin(), bad.end());
+    if (first != INT32_MAX) return check(first, true);
   }
-  for (const auto &hr : host_runs) counts[hr.first] = (int32_t)hr.second.size();
-  for (int k = 0; k < np; ++k) cigar_off[k + 1] = cigar_off[k] + counts[k];
+  for (const HostRun &hr : host_runs) counts[hr.k] = hr.n;
+  {  // cigar_off: an exclusive prefix sum of the counts, two passes on host threads
+    const int TP = np >= 65536 ? host_threads() : 1;
+    std::vector<int64_t> base(TP + 1, 0);
+    parallel_ranges((size_t)np, TP, [&](int t, size_t lo, size_t hi) {
+      int64_t sum = 0;
+      for (size_t k = lo; k < hi; ++k) sum += counts[k];
+      base[t + 1] = sum;
+    });
+    for (int t = 0; t < TP; ++t) base[t + 1] += base[t];
+    parallel_ranges((size_t)np, TP, [&](int t, size_t lo, size_t hi) {
+      int64_t run = base[t];
+      for (size_t k = lo; k < hi; ++k) cigar_off[k + 1] = run += counts[k];
+    });
+  }
   if (cigar_off[np] > cigar_cap) {
     set_error("the paths need %lld runs, cigar holds %lld", (long long)cigar_off[np],
               (long long)cigar_cap);
@@ -732,8 +865,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
                           hipMemcpyDeviceToHost, W.st));
     HIPCHK(hipStreamSynchronize(W.st));
   }
-  for (const auto &hr : host_runs)
-    std::copy(hr.second.begin(), hr.second.end(), cigar + cigar_off[hr.first]);
+  for (const HostRun &hr : host_runs) std::copy(hr.run, hr.run + hr.n, cigar + cigar_off[hr.k]);
   return SW_OK;
 }
 }  // namespace
