@@ -65,7 +65,12 @@ double now_ms() {
 
 int DevBuf::ensure(size_t bytes) {
   if (bytes <= cap) return SW_OK;
-  if (p) { (void)hipFree(p); p = nullptr; cap = 0; }
+  if (p) {
+    if (retired) retired->push_back(p);
+    else (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
   size_t want = std::max<size_t>(bytes + bytes / 100 * (size_t)grow_pct, 4096);
   hipError_t e = hipMalloc(&p, want);
   if (e != hipSuccess) {
@@ -84,7 +89,12 @@ void DevBuf::release() {
 
 int HostBuf::ensure(size_t bytes) {
   if (bytes <= cap) return SW_OK;
-  if (p) { (void)hipHostFree(p); p = nullptr; cap = 0; }
+  if (p) {
+    if (retired) retired->push_back(p);
+    else (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
   size_t want = std::max<size_t>(bytes + bytes / 100 * (size_t)grow_pct, 4096);
   hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
   if (e != hipSuccess) {

@@ -22,6 +22,9 @@ struct DevBuf {
   void *p = nullptr;
   size_t cap = 0;
   int grow_pct = 25;          // slack added on growth, percent of the request
+  // when set, an outgrown buffer is kept here instead of freed (a free waits
+  // for the whole device; the owner frees the list when it is done)
+  std::vector<void *> *retired = nullptr;
   int ensure(size_t bytes);
   void release();
   template <class T> T *as() const { return (T *)p; }
@@ -32,6 +35,7 @@ struct HostBuf {
   void *p = nullptr;
   size_t cap = 0;
   int grow_pct = 25;          // slack added on growth, percent of the request
+  std::vector<void *> *retired = nullptr;   // as DevBuf::retired (pinned host memory)
   int ensure(size_t bytes);
   void release();
   template <class T> T *as() const { return (T *)p; }
@@ -180,10 +184,14 @@ struct Workspace {
   // Sets the growth slack of every buffer (a long-lived caller whose batches
   // grow, such as a server worker, reallocates less often with more slack;
   // each reallocation frees the old buffer, which waits for the device).
-  void set_growth(int pct) {
-    for (DevBuf *b : {&tasks, &pairs, &streams, &results, &bnd, &misc, &matrix, &offs, &plan})
+  void set_growth(int pct, std::vector<void *> *dev_retired = nullptr,
+                  std::vector<void *> *host_retired = nullptr) {
+    for (DevBuf *b : {&tasks, &pairs, &streams, &results, &bnd, &misc, &matrix, &offs, &plan}) {
       b->grow_pct = pct;
+      b->retired = dev_retired;
+    }
     staging.grow_pct = pct;
+    staging.retired = host_retired;
   }
   void release() {
     graphs.clear();

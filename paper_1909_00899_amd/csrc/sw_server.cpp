@@ -3,7 +3,7 @@
 // Requests (one query against one resident database reference) enter a FIFO
 // queue.  n_streams worker threads each own a HIP stream and a device
 // workspace; an idle worker takes, under the server lock, the longest FIFO
-// prefix of requests that share the head's scoring scheme and fit the
+// prefix of requests that share the head's scoring scheme and size class and fit the
 // remaining memory budget (at most max_batch), marks them admitted, releases
 // the lock and runs them as one batch (the batch planner re-buckets them by
 // length into per-pair kernel launches).  Requests that arrive meanwhile wait
@@ -31,6 +31,13 @@ using swk::PairInfo;
 
 namespace {
 
+// A request is long when its query needs chunks in the per-pair kernels or
+// its matrix is large: such pairs bound a batch's time (one wavefront runs
+// one alignment's column chain), so they are batched apart from short ones.
+constexpr int kLongQuery = 1024;
+constexpr int64_t kLongCells = 1 << 20;
+bool is_long(int64_t m, int64_t n) { return m > kLongQuery || m * n > kLongCells; }
+
 int64_t mono_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(
              std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -40,6 +47,7 @@ struct Request {
   uint64_t ticket;
   std::vector<uint8_t> query;
   int32_t ref_id, scoring_id;
+  int32_t klass;             // batch class: scoring and size (see kLongCells)
   size_t bytes;
   int64_t t_submit = 0, t_admit = 0, t_done = 0;
   sw_result res{0, -1, -1, 0};
@@ -91,11 +99,16 @@ void sw_server::worker_main() {
   Workspace ws;
   DevBuf qbuf;
   HostBuf qstage;
-  // batches grow with the load: double on growth, so that a worker
-  // reallocates (and waits for the device) a few times at most
-  ws.set_growth(100);
+  // batches grow with the load: buffers double on growth, and an outgrown
+  // one is kept until the worker exits (freeing it would wait for the whole
+  // device, stalling every other worker's batch); at most the final size
+  // again is held that way
+  std::vector<void *> dev_old, host_old;
+  ws.set_growth(100, &dev_old, &host_old);
   qbuf.grow_pct = 100;
+  qbuf.retired = &dev_old;
   qstage.grow_pct = 100;
+  qstage.retired = &host_old;
   std::vector<Request *> batch;
   std::vector<sw_result> out;
   for (;;) {
@@ -105,11 +118,13 @@ void sw_server::worker_main() {
       std::unique_lock<std::mutex> lk(mu);
       cv_work.wait(lk, [&] { return stop || !queue.empty(); });
       if (stop && queue.empty()) break;
-      // admission: FIFO prefix with the head's scoring, within the budget
-      const int sid = queue.front()->scoring_id;
+      // admission: the head's class (scoring and size) in FIFO order, within
+      // the budget; a batch lasts as long as its longest pair, so short
+      // requests do not wait behind long ones of the same scoring
+      const int klass = queue.front()->klass;
       for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
         Request *r = *it;
-        if (r->scoring_id != sid) { ++it; continue; }
+        if (r->klass != klass) { ++it; continue; }
         if (in_flight + bytes + r->bytes > budget && !(batch.empty() && in_flight == 0)) break;
         bytes += r->bytes;
         batch.push_back(r);
@@ -189,6 +204,8 @@ void sw_server::worker_main() {
   ws.release();
   qbuf.release();
   qstage.release();
+  for (void *p : dev_old) (void)hipFree(p);
+  for (void *p : host_old) (void)hipHostFree(p);
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   hipStreamDestroy(st);
@@ -272,6 +289,7 @@ int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int3
   r->query.assign(query, query + query_len);
   r->ref_id = ref_id;
   r->scoring_id = scoring_id;
+  r->klass = 2 * scoring_id + (is_long(query_len, n) ? 1 : 0);
   r->bytes = s->request_bytes(query_len, (int)n);
   if (r->bytes > s->budget) { set_error("request needs %zu bytes, budget %zu", r->bytes, s->budget); return SW_ENOMEM; }
   r->t_submit = mono_ns();
