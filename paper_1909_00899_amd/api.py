@@ -404,18 +404,12 @@ def sw_align_batch_cigar(query_res, query_off, ref_res, ref_off, pair_ref, matri
     rs = np.ascontiguousarray(np.asarray(ref_start, dtype=np.int32))
     if ends.shape != (npairs, 4) or qs.shape != (npairs,) or rs.shape != (npairs,):
         raise ValueError("results must be (n_pairs, 4), query_start and ref_start (n_pairs,)")
-    # capacity: A + B - 1 runs per A x B rectangle (at least the library's
-    # bound, min(A + B - 1, 3 min(A, B) - 2)), in a few in-place passes
-    if cigar_cap is None:
-        live = ends[:, 0] > 0
-        span = ends[:, 1].astype(np.int64)
-        span += ends[:, 2]
-        span -= qs
-        span -= rs
-        span += 1
-        cap = int(span[live].clip(0, None).sum())
-    else:
-        cap = int(cigar_cap)
+    # capacity: (query_end + 1) + (ref_end + 1) per pair, one pass (at least
+    # A + B - 1 >= the library's bound min(A + B - 1, 3 min(A, B) - 2) for
+    # every A x B rectangle; the array is allocated lazily, so only the runs
+    # written are touched)
+    cap = int(ends[:, 1:3].sum(dtype=np.int64)) + 2 * npairs if cigar_cap is None \
+        else int(cigar_cap)
     runs = np.empty(max(cap, 1), dtype=np.uint32)
     off = np.empty(npairs + 1, dtype=np.int64)
     _check(lib.sw_align_batch_cigar(ctypes.byref(b), ctypes.byref(sc),

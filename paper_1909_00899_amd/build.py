@@ -24,7 +24,7 @@ ARCH = "gfx950"
 SOURCES = ["sw_shared_i16.hip", "sw_shared_i32.hip", "sw_pair_i16.hip", "sw_pair8_i16.hip",
            "sw_pair_i32.hip",
            "sw_launch.hip", "sw_runtime.cpp", "sw_devplan.cpp", "sw_starts.cpp", "sw_trace.hip", "sw_api.cpp", "sw_server.cpp", "sw_tune.cpp",
-           "sw_noalloc.hip", "sw_swap.hip"]
+           "sw_noalloc.hip", "sw_swap.hip", "sw_trplan.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          # packed FP32 VALU forms are kept out of every code object

@@ -65,10 +65,12 @@ struct StartsWork {
   DevBuf tr_rstart;              // end-to-end paths: reference starts
   DevBuf tr_qstart;              // end-to-end paths: query starts
   HostBuf tr_hres;
-  // host scratch of the path tables: each pair's rectangle and class (the
-  // tables are built by host threads in two passes)
-  std::vector<swk::TracePair> tr_rect;
-  std::vector<uint8_t> tr_cls;
+  // path tables built on the device: the caller's inputs (results, start
+  // cells; a host batch's offsets and indices), per-pair scratch, the
+  // planner's workgroup arrays, its summaries (pinned)
+  DevBuf tr_ends, tr_qs, tr_rs, tr_qoff, tr_roff, tr_pq, tr_pr;
+  DevBuf tr_rect, tr_cls, tr_hruns, tr_blk, tr_blkcaps, tr_clsmax, tr_err, tr_sum, tr_bsum;
+  HostBuf tr_hsum;
   // device-memory rectangles: the largest group, the second, the rest each on
   // a stream of their own, so the long poles of the largest rectangles (one
   // wavefront each) overlap instead of adding up
@@ -403,36 +405,6 @@ constexpr int64_t kTraceScratchBytes = 1ll << 30;    // device-memory decision b
 constexpr int kTraceMaxWaves = 4096;
 constexpr int kDualCols = 160;   // end-to-end queries up to this length run two per wavefront
 
-// Runs a path can have between start and end: every run but the first is
-// preceded by a change of operation, M runs alternate with one or two gap
-// runs, and a rectangle of A x B cells holds at most min(A, B) pairs.
-int64_t run_bound(int64_t A, int64_t B) {
-  return std::min(A + B - 1, 3 * std::min(A, B) - 2);
-}
-
-// 2-byte units of a rectangle's decision words: rows x tiles x 64 lanes x
-// the word width of its variant
-int64_t trace_slot_words(const swk::TracePair &P) {
-  int64_t tiles;
-  switch (swk::trace_cols(P.pad)) {   // constant divisors (the tables hold millions)
-    case 1: tiles = (P.B + 63) / 64; break;
-    case 2: tiles = (P.B + 127) / 128; break;
-    case 3: tiles = (P.B + 191) / 192; break;
-    case 8: tiles = (P.B + 511) / 512; break;
-    default: tiles = (P.B + 255) / 256; break;
-  }
-  return (int64_t)P.A * tiles * 64 * (swk::trace_word_bytes(P.pad) / 2);
-}
-
-// Size class of a device-memory rectangle: its variant and the power of two
-// below its slot, largest first.  Every member of a class needs more than
-// half the largest member's slot, so one class is one launch group.
-constexpr int kSlotBuckets = 40;   // slots below 2^40 words
-int trace_size_class(int64_t slot, int variant) {
-  const int b = std::min(kSlotBuckets - 1, 63 - __builtin_clzll((unsigned long long)std::max<int64_t>(slot, 1)));
-  return (kSlotBuckets - 1 - b) * 3 + variant;
-}
-
 }  // namespace
 
 // Paths of a batch: mode 0 the local alignments between start and end cells
@@ -441,6 +413,90 @@ int trace_size_class(int64_t slot, int variant) {
 // overlap) from their end cells (sw_align_batch_global_cigar;
 // query_start_out / ref_start_out receive the start element + 1).
 namespace {
+// Lengths of pair k's sequences (for messages): from the host arrays, or read
+// from a device-resident batch.
+void pair_lengths(const sw_batch *b, int k, int64_t &m, int64_t &n) {
+  m = n = -1;
+  int32_t q = 0, r = 0;
+  int64_t qo[2] = {0, 0}, ro[2] = {0, 0};
+  if (b->device_resident) {
+    if (b->pair_query && hipMemcpy(&q, b->pair_query + k, 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+    if (hipMemcpy(&r, b->pair_ref + k, 4, hipMemcpyDeviceToHost) != hipSuccess) return;
+    if (q < 0 || q >= b->n_queries || r < 0 || r >= b->n_refs) return;
+    if (hipMemcpy(qo, b->query_off + q, 16, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(ro, b->ref_off + r, 16, hipMemcpyDeviceToHost) != hipSuccess)
+      return;
+  } else {
+    q = b->pair_query ? b->pair_query[k] : 0;
+    r = b->pair_ref[k];
+    if (q < 0 || q >= b->n_queries || r < 0 || r >= b->n_refs) return;
+    qo[0] = b->query_off[q];
+    qo[1] = b->query_off[q + 1];
+    ro[0] = b->ref_off[r];
+    ro[1] = b->ref_off[r + 1];
+  }
+  m = qo[1] - qo[0];
+  n = ro[1] - ro[0];
+}
+
+const char *const kModeName[] = {"local", "global", "semi-global (query fitted)",
+                                 "semi-global (reference fitted)", "overlap"};
+
+// The message and status of the planner's error word for pair k.
+int path_error(const sw_batch *b, int mode, const sw_result *ends, const int32_t *query_start,
+               const int32_t *ref_start, int k, int code) {
+  const sw_result &e = ends[k];
+  int64_t m, n;
+  pair_lengths(b, k, m, n);
+  const int qs = mode == 0 ? query_start[k] : 0, rs = mode == 0 ? ref_start[k] : 0;
+  switch (code) {
+    case swk::kTrErrPair:
+      set_error("pair %d refers to a query or reference out of range", k);
+      return SW_EINVAL;
+    case swk::kTrErrQoff:
+      set_error("query offsets not nondecreasing");
+      return SW_EINVAL;
+    case swk::kTrErrRoff:
+      set_error("reference offsets not nondecreasing");
+      return SW_EINVAL;
+    case swk::kTrErrRect:
+      set_error("pair %d: start (%d, %d) and end (%d, %d) are not a rectangle of its %lld x "
+                "%lld sequences", k, qs, rs, e.query_end, e.ref_end, (long long)m, (long long)n);
+      return SW_EINVAL;
+    case swk::kTrErrEnd:
+      set_error("pair %d: end (%d, %d) is not the end cell of a %s alignment of its %lld x %lld "
+                "sequences", k, e.query_end, e.ref_end, kModeName[mode], (long long)m,
+                (long long)n);
+      return SW_EINVAL;
+    case swk::kTrErrOptimum:
+      set_error("pair %d: score %d is not the optimum at the end cell (%d, %d)", k, e.score,
+                e.query_end, e.ref_end);
+      return SW_EINVAL;
+    case swk::kTrErrRange:
+      set_error("pair %d: a %lld x %lld rectangle leaves the int32 range of the path kernel", k,
+                (long long)(e.ref_end - rs + 1), (long long)(e.query_end - qs + 1));
+      return SW_EOVERFLOW;
+    case swk::kTrErrScratch:
+      set_error("pair %d: a %lld x %lld rectangle needs more than 2 GiB of path scratch", k,
+                (long long)(e.ref_end - rs + 1), (long long)(e.query_end - qs + 1));
+      return SW_ENOMEM;
+    case swk::kTrErrResidue:
+      set_error("pair %d: a residue code inside its alignment is not below alphabet_size", k);
+      return SW_EINVAL;
+    case swk::kTrErrInconsistent:
+      if (mode == 0)
+        set_error("pair %d: no alignment of score %d runs from its start (%d, %d) to its end "
+                  "(%d, %d)", k, e.score, qs, rs, e.query_end, e.ref_end);
+      else
+        set_error("pair %d: score %d is not the optimum at the end cell (%d, %d)", k, e.score,
+                  e.query_end, e.ref_end);
+      return SW_EINVAL;
+    default:
+      set_error("pair %d: internal path error (run count outside its bound)", k);
+      return SW_EDEVICE;
+  }
+}
+
 int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_result *ends,
                const int32_t *query_start, const int32_t *ref_start, int32_t *query_start_out,
                int32_t *ref_start_out, uint32_t *cigar, int64_t cigar_cap, int64_t *cigar_off) {
@@ -457,415 +513,229 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     set_error("ends, starts or the start outputs are NULL");
     return SW_EINVAL;
   }
-  // end-to-end modes: which prefixes are free (virtual start elements (v, -1)
-  // and (-1, w)) and where an end cell may lie
-  const bool col_free = mode == 2 || mode == 4, row_free = mode == 3 || mode == 4;
-  static const char *const kModeName[] = {"local", "global", "semi-global (query fitted)",
-                                          "semi-global (reference fitted)", "overlap"};
   if (cigar_cap < 0 || (cigar_cap > 0 && !cigar)) { set_error("cigar is NULL or its capacity negative"); return SW_EINVAL; }
   if ((rc = ensure_init())) return rc;
   std::lock_guard<std::mutex> g(g_starts.mu);
   StartsWork &W = g_starts;
-  Batch B;
-  B.ends = ends;
-  if ((rc = load_batch(b, W, B))) return rc;
+  HIPCHK(hipSetDevice(g_ctx.device));
+  if (!W.st) HIPCHK(hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking));
+  const bool dev = b->device_resident != 0;
+  if (dev && b->stream) {
+    // the caller's stream produced the inputs
+    hipEvent_t ev;
+    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, (hipStream_t)b->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(W.st, ev, 0);
+    (void)hipEventDestroy(ev);
+    HIPCHK(e);
+  }
+  const int64_t nq = b->n_queries, nr = b->n_refs;
+  // ---- inputs on the device: the batch (a host batch's offsets, indices and
+  // residues uploaded), the results and start cells
+  const int64_t *d_qoff = b->query_off, *d_roff = b->ref_off;
+  const int32_t *d_pq = b->pair_query, *d_pr = b->pair_ref;
+  const uint8_t *d_q = b->query_res, *d_r = b->ref_res;
+  if (!dev) {
+    const int64_t qb = b->query_off[nq], rb = b->ref_off[nr];
+    if (qb < 0 || rb < 0) {
+      set_error(qb < 0 ? "query offsets not nondecreasing" : "reference offsets not nondecreasing");
+      return SW_EINVAL;
+    }
+    if ((rc = W.tr_qoff.ensure((size_t)(nq + 1) * 8)) || (rc = W.tr_roff.ensure((size_t)(nr + 1) * 8)) ||
+        (rc = W.tr_pr.ensure((size_t)np * 4)) || (rc = W.tr_pq.ensure((size_t)np * 4)) ||
+        (rc = W.src_q.ensure((size_t)qb + 1)) || (rc = W.src_r.ensure((size_t)rb + 1)))
+      return rc;
+    HIPCHK(hipMemcpyAsync(W.tr_qoff.p, b->query_off, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, W.st));
+    HIPCHK(hipMemcpyAsync(W.tr_roff.p, b->ref_off, (size_t)(nr + 1) * 8, hipMemcpyHostToDevice, W.st));
+    HIPCHK(hipMemcpyAsync(W.tr_pr.p, b->pair_ref, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
+    if (b->pair_query)
+      HIPCHK(hipMemcpyAsync(W.tr_pq.p, b->pair_query, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
+    if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, (size_t)qb, hipMemcpyHostToDevice, W.st));
+    if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, (size_t)rb, hipMemcpyHostToDevice, W.st));
+    d_qoff = W.tr_qoff.as<int64_t>();
+    d_roff = W.tr_roff.as<int64_t>();
+    d_pr = W.tr_pr.as<int32_t>();
+    d_pq = b->pair_query ? W.tr_pq.as<int32_t>() : nullptr;
+    d_q = W.src_q.as<uint8_t>();
+    d_r = W.src_r.as<uint8_t>();
+  }
+  constexpr int NC = swk::kTrClasses;
+  if ((rc = W.tr_ends.ensure((size_t)np * sizeof(sw_result))) ||
+      (rc = W.tr_qs.ensure((size_t)np * 4)) || (rc = W.tr_rs.ensure((size_t)np * 4)) ||
+      (rc = W.tr_rect.ensure((size_t)np * sizeof(swk::TracePair))) ||
+      (rc = W.tr_cls.ensure((size_t)np)) || (rc = W.tr_hruns.ensure((size_t)np * 8)) ||
+      (rc = W.tr_nruns.ensure((size_t)np * 4)) || (rc = W.tr_rstart.ensure((size_t)np * 4)) ||
+      (rc = W.tr_qstart.ensure((size_t)np * 4)) ||
+      (rc = W.tr_blk.ensure((size_t)swk::kTrBlocks * NC * 4)) ||
+      (rc = W.tr_blkcaps.ensure((size_t)swk::kTrBlocks * 8)) ||
+      (rc = W.tr_clsmax.ensure((size_t)NC * 16)) || (rc = W.tr_err.ensure(16)) ||
+      (rc = W.tr_sum.ensure((size_t)(NC + 2) * 8)) ||
+      (rc = W.tr_pairs.ensure((size_t)np * sizeof(swk::TracePair))) ||
+      (rc = W.tr_mat.ensure((size_t)S.alpha * S.alpha * sizeof(int32_t))) ||
+      (rc = W.tr_off.ensure((size_t)(np + 1) * sizeof(int64_t))) ||
+      (rc = W.tr_bsum.ensure((size_t)(np / 4096 + 2) * 8)) ||
+      (rc = W.tr_hsum.ensure((size_t)(3 * NC + 8) * 8)))
+    return rc;
+  HIPCHK(hipMemcpyAsync(W.tr_ends.p, ends, (size_t)np * sizeof(sw_result), hipMemcpyHostToDevice, W.st));
+  if (mode == 0) {
+    HIPCHK(hipMemcpyAsync(W.tr_qs.p, query_start, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
+    HIPCHK(hipMemcpyAsync(W.tr_rs.p, ref_start, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
+  }
+  HIPCHK(hipMemcpyAsync(W.tr_mat.p, S.M.data(), (size_t)S.alpha * S.alpha * sizeof(int32_t),
+                        hipMemcpyHostToDevice, W.st));
+  HIPCHK(hipMemsetAsync(W.tr_clsmax.p, 0, (size_t)NC * 16, W.st));
+  HIPCHK(hipMemsetAsync(W.tr_err.p, 0xff, 8, W.st));
   int64_t maxabs = 0;
   for (int v : S.M) maxabs = std::max<int64_t>(maxabs, v < 0 ? -(int64_t)v : v);
-  // the table lives in pinned memory (one fast upload)
-  if ((rc = W.tr_host.ensure((size_t)np * sizeof(swk::TracePair))) ||
-      (rc = W.tr_hcounts.ensure((size_t)np * sizeof(int32_t))))
-    return rc;
-  swk::TracePair *htab = W.tr_host.as<swk::TracePair>();
-  int64_t region = 0;
-  // ---- one rectangle per pair with a positive score, built by host threads:
-  // pass 1 classifies every pair (its rectangle, kernel variant and size
-  // class, or an error, or runs made here), pass 2 lays the classes out
-  // (LDS rectangles by variant, then device-memory ones by size class,
-  // largest first; within a class in pair order) and assigns run regions in
-  // pair order, pass 3 writes the table straight into pinned memory
-  auto gap = [&](int64_t L) -> int64_t { return L <= 0 ? 0 : S.go + (L - 1) * (int64_t)S.ge; };
-  // end-to-end alignments with an empty side: at most a D and an I run
-  struct HostRun { int k; int n; uint32_t run[2]; };
-  constexpr int NCLS = 3 + kSlotBuckets * 3;     // LDS variants, then size classes
-  constexpr uint8_t kSkip = 0xff, kHost = 0xfe;
-  // classifies pair k: kSkip (no path), kHost (runs in *hr), a class with the
-  // rectangle in *tp, or an error (returns its code; with report, sets the message)
-  auto classify = [&](int k, bool report, swk::TracePair *tp, HostRun *hr,
-                      uint8_t *cls) -> int {
-    const sw_result &e = ends[k];
-    const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
-    const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
-    int qs = 0, rs = 0;
-    *cls = kSkip;
-    if (mode == 0) {
-      if (e.score <= 0) return SW_OK;
-      qs = query_start[k];
-      rs = ref_start[k];
-      if (qs < 0 || qs > e.query_end || e.query_end >= m || rs < 0 || rs > e.ref_end ||
-          e.ref_end >= n) {
-        if (report)
-          set_error("pair %d: start (%d, %d) and end (%d, %d) are not a rectangle of its %lld x "
-                    "%lld sequences", k, qs, rs, e.query_end, e.ref_end, (long long)m, (long long)n);
-        return SW_EINVAL;
-      }
-    } else {
-      const bool in = e.ref_end >= -1 && e.ref_end < n && e.query_end >= -1 && e.query_end < m;
-      const bool on_q = e.query_end == m - 1, on_r = e.ref_end == n - 1;
-      const bool ok = mode == 1 ? on_q && on_r : mode == 2 ? on_q : mode == 3 ? on_r : on_q || on_r;
-      if (!in || !ok) {
-        if (report)
-          set_error("pair %d: end (%d, %d) is not the end cell of a %s alignment of its %lld x "
-                    "%lld sequences", k, e.query_end, e.ref_end, kModeName[mode], (long long)m,
-                    (long long)n);
-        return SW_EINVAL;
-      }
-      if (e.query_end < 0 || e.ref_end < 0) {
-        // nothing to pair: runs from the best virtual start element -- the
-        // largest (ref, query) one -- to the end cell
-        const int64_t A0 = e.ref_end + 1, B0 = e.query_end + 1;
-        int64_t best = INT64_MIN, bx = 0, by = 0;
-        auto consider = [&](int64_t x, int64_t y) {   // element (x, y): its value at the end
-          const int64_t v = -gap(A0 - 1 - x) - gap(B0 - 1 - y);
-          if (v > best || (v == best && (x > bx || (x == bx && y > by)))) {
-            best = v;
-            bx = x;
-            by = y;
-          }
-        };
-        consider(-1, -1);
-        for (int64_t x = 0; col_free && x < A0; ++x) consider(x, -1);
-        for (int64_t y = 0; row_free && y < B0; ++y) consider(-1, y);
-        if (e.score != best) {
-          if (report)
-            set_error("pair %d: score %d is not the optimum at the end cell (%d, %d)", k, e.score,
-                      e.query_end, e.ref_end);
-          return SW_EINVAL;
-        }
-        hr->k = k;
-        hr->n = 0;
-        if (A0 - 1 - bx) hr->run[hr->n++] = (uint32_t)(A0 - 1 - bx) << 4 | swk::kCigarD;
-        if (B0 - 1 - by) hr->run[hr->n++] = (uint32_t)(B0 - 1 - by) << 4 | swk::kCigarI;
-        ref_start_out[k] = (int32_t)(bx + 1);
-        query_start_out[k] = (int32_t)(by + 1);
-        *cls = kHost;
-        return SW_OK;
-      }
-    }
-    const int64_t A = e.ref_end - rs + 1, Bq = e.query_end - qs + 1;
-    // every reachable value stays above -2^28 and every row term below 2^30,
-    // so unreachable values (near -2^30) never meet reachable ones
-    const int64_t lo = 2 * (maxabs + S.go) + (A + Bq + 2 * swk::kTraceTileCols) * (S.ge + 1);
-    const int64_t hi = std::min(A, Bq) * (int64_t)S.max_s + (Bq + swk::kTraceTileCols) * S.ge;
-    if (lo >= (1ll << 27) || hi >= (1ll << 30)) {
-      if (report)
-        set_error("pair %d: a %lld x %lld rectangle leaves the int32 range of the path kernel", k,
-                  (long long)A, (long long)Bq);
-      return SW_EOVERFLOW;
-    }
-    tp->q = B.qoff[B.pq[k]] + qs;
-    tp->r = B.roff[B.pr[k]] + rs;
-    tp->out = 0;
-    tp->A = (int32_t)A;
-    tp->B = (int32_t)Bq;
-    tp->score = e.score;
-    // end-to-end: k <= min(A, B) pairs, k M runs and two gap runs in each of the
-    // k + 1 gaps (start, between pairs, end)
-    tp->cap = (int32_t)(mode == 0 ? run_bound(A, Bq) : std::min(A + Bq + 2, 3 * std::min(A, Bq) + 2));
-    tp->id = k;
-    // columns per lane: the fewest that hold a one-tile query (4 beyond), so
-    // a one-tile query's slot of 64-lane rows is the same at any count
-    tp->pad = (int32_t)std::min<int64_t>(4, (Bq + 63) / 64);
-    // 16-bit values (4 or 8 columns per lane) when the rectangle's range
-    // provably fits: every reachable value -- a pair and two gap runs from
-    // the start or a boundary, plus a gap opening, or a scan term with its
-    // tile offset -- stays above every value derived from an unreachable
-    // edge (-32768 plus a score, a tile's scan offsets and an opening), and
-    // the largest chain score with its tile offset stays below 32767
-    if (Bq > 64) {
-      const int64_t tc = Bq <= 256 ? 256 : 512;
-      const int64_t span = 5 * (maxabs + S.go) + (A + Bq + 3 + tc) * (int64_t)S.ge + 256;
-      const int64_t top = std::min(A, Bq) * (int64_t)S.max_s + tc * S.ge + maxabs + 256;
-      if (span < 32768 && top < 32767) tp->pad = swk::kTracePad16 | (int32_t)(tc / 64);
-    }
-    const int64_t slot = trace_slot_words(*tp);
-    const int variant = swk::trace_variant(tp->pad);
-    if (slot <= (int64_t)swk::kTraceLdsRowTiles * 64) {
-      // LDS rectangles in runs of one kernel variant (one launch each), the
-      // common 16-bit four-column one first
-      *cls = (uint8_t)(variant == swk::kTraceV16x4 ? 0 : variant == swk::kTraceV32 ? 1 : 2);
-    } else {
-      if (slot * 2 > (2ll << 30)) {
-        if (report)
-          set_error("pair %d: a %lld x %lld rectangle needs more than 2 GiB of path scratch", k,
-                    (long long)A, (long long)Bq);
-        return SW_ENOMEM;
-      }
-      *cls = (uint8_t)(3 + trace_size_class(slot, variant));
-    }
-    return SW_OK;
-  };
-
-  if (W.tr_rect.size() < (size_t)np) W.tr_rect.resize(np);
-  if (W.tr_cls.size() < (size_t)np) W.tr_cls.resize(np);
-  swk::TracePair *rect = W.tr_rect.data();
-  uint8_t *cls = W.tr_cls.data();
-  const int T = np >= 65536 ? host_threads() : 1;
-  struct Part {
-    int64_t count[NCLS] = {}, caps = 0, cslot[NCLS] = {};
-    int crows[NCLS] = {};
-    int first_err = INT32_MAX;
-    std::vector<HostRun> host;
-  };
-  std::vector<Part> part(T);
-  parallel_ranges((size_t)np, T, [&](int t, size_t lo, size_t hi) {
-    Part &P = part[t];
-    for (size_t k = lo; k < hi; ++k) {
-      if (mode != 0) {
-        ref_start_out[k] = 0;
-        query_start_out[k] = 0;
-      }
-      HostRun hr;
-      if (classify((int)k, false, &rect[k], &hr, &cls[k]) != SW_OK) {
-        P.first_err = (int)k;
-        return;
-      }
-      const uint8_t c = cls[k];
-      if (c == kHost) {
-        P.host.push_back(hr);
-      } else if (c != kSkip) {
-        ++P.count[c];
-        P.caps += rect[k].cap;
-        P.cslot[c] = std::max(P.cslot[c], trace_slot_words(rect[k]));
-        P.crows[c] = std::max(P.crows[c], rect[k].A);
-      }
-    }
-  });
-  {
-    int first = INT32_MAX;
-    for (const Part &P : part) first = std::min(first, P.first_err);
-    if (first != INT32_MAX) {   // the first failing pair, as a serial pass finds it
-      swk::TracePair tp;
-      HostRun hr;
-      uint8_t c;
-      return classify(first, true, &tp, &hr, &c);
-    }
-  }
-  // class layout, and each thread's first slot in every class and region
-  int64_t cstart[NCLS + 1] = {}, cslot[NCLS] = {};
-  int crows[NCLS] = {};
-  for (int c = 0; c < NCLS; ++c) {
-    int64_t cnt = 0;
-    for (const Part &P : part) {
-      cnt += P.count[c];
-      cslot[c] = std::max(cslot[c], P.cslot[c]);
-      crows[c] = std::max(crows[c], P.crows[c]);
-    }
-    cstart[c + 1] = cstart[c] + cnt;
-  }
-  const int nl = (int)cstart[3], nt = (int)cstart[NCLS], ng = nt - nl;
-  std::vector<std::array<int64_t, NCLS>> tpos(T);
-  std::vector<int64_t> treg(T);
-  {
-    int64_t run[NCLS];
-    std::memcpy(run, cstart, sizeof(run));
-    int64_t reg = 0;
-    for (int t = 0; t < T; ++t) {
-      for (int c = 0; c < NCLS; ++c) {
-        tpos[t][c] = run[c];
-        run[c] += part[t].count[c];
-      }
-      treg[t] = reg;
-      reg += part[t].caps;
-    }
-    region = reg;
-  }
-  parallel_ranges((size_t)np, T, [&](int t, size_t lo, size_t hi) {
-    int64_t reg = treg[t];
-    std::array<int64_t, NCLS> &pos = tpos[t];
-    for (size_t k = lo; k < hi; ++k) {
-      const uint8_t c = cls[k];
-      if (c >= NCLS) continue;
-      swk::TracePair tp = rect[k];
-      tp.out = reg;
-      reg += tp.cap;
-      htab[pos[c]++] = tp;
-    }
-  });
-  std::vector<HostRun> host_runs;
-  for (Part &P : part) host_runs.insert(host_runs.end(), P.host.begin(), P.host.end());
-  // one launch group per device-memory size class
+  // ---- the table: classify, totals, summary to the host
+  swk::TrPlanArgs pa;
+  pa.np = np;
+  pa.nq = (int)nq;
+  pa.nr = (int)nr;
+  pa.mode = mode;
+  pa.alpha = S.alpha;
+  pa.go = S.go;
+  pa.ge = S.ge;
+  pa.max_s = S.max_s;
+  pa.maxabs = (int)std::min<int64_t>(maxabs, INT32_MAX);
+  pa.qoff = d_qoff;
+  pa.roff = d_roff;
+  pa.pq = d_pq;
+  pa.pr = d_pr;
+  pa.ends = W.tr_ends.as<swk::DevResult>();
+  pa.qs = W.tr_qs.as<int32_t>();
+  pa.rs = W.tr_rs.as<int32_t>();
+  pa.rect = W.tr_rect.as<swk::TracePair>();
+  pa.cls = W.tr_cls.as<uint8_t>();
+  pa.hruns = W.tr_hruns.as<uint32_t>();
+  pa.n_runs = W.tr_nruns.as<int32_t>();
+  pa.ref_start = W.tr_rstart.as<int32_t>();
+  pa.query_start = W.tr_qstart.as<int32_t>();
+  pa.blk_count = W.tr_blk.as<int32_t>();
+  pa.blk_caps = W.tr_blkcaps.as<int64_t>();
+  pa.cls_max = W.tr_clsmax.as<unsigned long long>();
+  pa.err = W.tr_err.as<unsigned long long>();
+  pa.summary = W.tr_sum.as<int64_t>();
+  pa.table = W.tr_pairs.as<swk::TracePair>();
+  pa.runs = nullptr;
+  HIPCHK(swk::launch_trplan_classify(pa, W.st));
+  HIPCHK(swk::launch_trplan_totals(pa, W.st));
+  int64_t *hs = W.tr_hsum.as<int64_t>();          // [NC + 2] summary, [2 NC] maxima, error word
+  HIPCHK(hipMemcpyAsync(hs, W.tr_sum.p, (size_t)(NC + 2) * 8, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemcpyAsync(hs + NC + 2, W.tr_clsmax.p, (size_t)NC * 16, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemcpyAsync(hs + 3 * NC + 2, W.tr_err.p, 8, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipStreamSynchronize(W.st));
+  const uint64_t err1 = (uint64_t)hs[3 * NC + 2];
+  if (err1 != ~0ull)
+    return path_error(b, mode, ends, query_start, ref_start, (int)(err1 >> 8), (int)(err1 & 0xff));
+  int64_t cstart[NC + 1];
+  for (int c = 0; c <= NC; ++c) cstart[c] = hs[c];
+  const int64_t region = hs[NC + 1];
+  const uint64_t *cmax = (const uint64_t *)(hs + NC + 2);
+  const int nt = (int)cstart[NC];
+  if ((rc = W.tr_runs.ensure((size_t)std::max<int64_t>(region, 1) * sizeof(uint32_t)))) return rc;
+  pa.runs = W.tr_runs.as<uint32_t>();
+  HIPCHK(swk::launch_trplan_scatter(pa, W.st));
+  // ---- launches: LDS classes (one per variant), device-memory classes
   struct Group { int first, count, waves; int64_t slot_words; int carry_rows; int variant; };
   std::vector<Group> groups;
   constexpr int NS = StartsWork::kTraceStreams;
   int64_t bits_words[NS] = {}, carry_ints[NS] = {};
-  for (int c = 3; c < NCLS; ++c) {
+  for (int c = 3; c < swk::kTrHostClass; ++c) {
     const int64_t cnt = cstart[c + 1] - cstart[c];
     if (!cnt) continue;
-    const int64_t slot = cslot[c];
-    const int carry_rows = std::max(1, crows[c]);
+    const int64_t slot = (int64_t)cmax[2 * c];
+    const int carry_rows = std::max<int>(1, (int)cmax[2 * c + 1]);
     const int64_t per_wave = slot * 2 + 6ll * carry_rows * 4;
     const int waves = (int)std::max<int64_t>(
         1, std::min<int64_t>({cnt, kTraceScratchBytes / per_wave, kTraceMaxWaves}));
     const int sk = std::min((int)groups.size(), NS - 1);
-    groups.push_back({(int)(cstart[c] - nl), (int)cnt, waves, slot, carry_rows, (c - 3) % 3});
+    groups.push_back({(int)cstart[c], (int)cnt, waves, slot, carry_rows, (c - 3) % 3});
     bits_words[sk] = std::max<int64_t>(bits_words[sk], slot * waves);
     carry_ints[sk] = std::max<int64_t>(carry_ints[sk], 6ll * carry_rows * waves);
   }
-  (void)ng;
-  std::vector<int32_t> counts(np, 0);
-  if (nt > 0) {
-    if ((rc = W.tr_pairs.ensure((size_t)nt * sizeof(swk::TracePair))) ||
-        (rc = W.tr_mat.ensure((size_t)S.alpha * S.alpha * sizeof(int32_t))) ||
-        (rc = W.tr_runs.ensure((size_t)std::max<int64_t>(region, 1) * sizeof(uint32_t))) ||
-        (rc = W.tr_nruns.ensure((size_t)np * sizeof(int32_t))) ||
-        (rc = W.tr_off.ensure((size_t)(np + 1) * sizeof(int64_t))) ||
-        (rc = W.tr_rstart.ensure((size_t)np * sizeof(int32_t))) ||
-        (rc = W.tr_qstart.ensure((size_t)np * sizeof(int32_t))))
+  for (int k = 0; k < NS && k < (int)groups.size(); ++k) {
+    if ((rc = W.tr_bits[k].ensure((size_t)std::max<int64_t>(bits_words[k], 1) * sizeof(uint16_t))) ||
+        (rc = W.tr_carry[k].ensure((size_t)std::max<int64_t>(carry_ints[k], 1) * sizeof(int32_t))))
       return rc;
-    for (int k = 0; k < NS && k < (int)groups.size(); ++k) {
-      if ((rc = W.tr_bits[k].ensure((size_t)std::max<int64_t>(bits_words[k], 1) * sizeof(uint16_t))) ||
-          (rc = W.tr_carry[k].ensure((size_t)std::max<int64_t>(carry_ints[k], 1) * sizeof(int32_t))))
-        return rc;
-      if (!W.tr_st[k]) HIPCHK(hipStreamCreateWithFlags(&W.tr_st[k], hipStreamNonBlocking));
-      if (!W.tr_done[k]) HIPCHK(hipEventCreateWithFlags(&W.tr_done[k], hipEventDisableTiming));
-    }
-    if (!W.tr_ready) HIPCHK(hipEventCreateWithFlags(&W.tr_ready, hipEventDisableTiming));
-    swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
-    HIPCHK(hipMemcpyAsync(dp, htab, (size_t)nt * sizeof(swk::TracePair), hipMemcpyHostToDevice,
-                          W.st));
-    HIPCHK(hipMemcpyAsync(W.tr_mat.p, S.M.data(), (size_t)S.alpha * S.alpha * sizeof(int32_t),
-                          hipMemcpyHostToDevice, W.st));
-    swk::TraceArgs ta;
-    ta.qres = B.d_q;
-    ta.rres = B.d_r;
-    ta.matrix = W.tr_mat.as<int32_t>();
-    ta.alpha = S.alpha;
-    ta.go = S.go;
-    ta.ge = S.ge;
-    ta.cigar = W.tr_runs.as<uint32_t>();
-    ta.n_runs = W.tr_nruns.as<int32_t>();
-    ta.mode = mode;
-    ta.ref_start = W.tr_rstart.as<int32_t>();
-    ta.query_start = W.tr_qstart.as<int32_t>();
-    ta.pairs = dp;
-    ta.n = nl;
-    ta.slot_words = 0;
-    ta.carry_rows = 0;
-    ta.gbits = nullptr;
-    ta.gcarry = nullptr;
-    const int used = std::min((int)groups.size(), NS);
-    if (used) HIPCHK(hipEventRecord(W.tr_ready, W.st));
-    for (int k = 0; k < used; ++k) HIPCHK(hipStreamWaitEvent(W.tr_st[k], W.tr_ready, 0));
-    for (int lo = 0; lo < nl;) {                   // one LDS launch per variant
-      const int v = swk::trace_variant(htab[lo].pad);
-      int hi = lo;
-      while (hi < nl && swk::trace_variant(htab[hi].pad) == v) ++hi;
-      ta.pairs = dp + lo;
-      ta.n = hi - lo;
-      HIPCHK(swk::launch_trace(true, v, ta, hi - lo, W.st));
-      lo = hi;
-    }
-    for (int g = 0; g < (int)groups.size(); ++g) {
-      const Group &gr = groups[g];
-      const int k = std::min(g, NS - 1);
-      ta.pairs = dp + nl + gr.first;
-      ta.n = gr.count;
-      ta.slot_words = gr.slot_words;
-      ta.carry_rows = gr.carry_rows;
-      ta.gbits = W.tr_bits[k].as<uint16_t>();
-      ta.gcarry = W.tr_carry[k].as<int32_t>();
-      HIPCHK(swk::launch_trace(false, gr.variant, ta, gr.waves, W.tr_st[k]));
-    }
-    for (int k = 0; k < used; ++k) {
-      HIPCHK(hipEventRecord(W.tr_done[k], W.tr_st[k]));
-      HIPCHK(hipStreamWaitEvent(W.st, W.tr_done[k], 0));
-    }
-    int32_t *dev_counts = W.tr_hcounts.as<int32_t>();
-    HIPCHK(hipMemcpyAsync(dev_counts, W.tr_nruns.p, (size_t)np * sizeof(int32_t),
-                          hipMemcpyDeviceToHost, W.st));
-    std::vector<int32_t> dev_rstart, dev_qstart;
-    if (mode != 0) {
-      dev_rstart.resize(np);
-      dev_qstart.resize(np);
-      HIPCHK(hipMemcpyAsync(dev_rstart.data(), W.tr_rstart.p, (size_t)np * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, W.st));
-      HIPCHK(hipMemcpyAsync(dev_qstart.data(), W.tr_qstart.p, (size_t)np * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, W.st));
-    }
-    HIPCHK(hipStreamSynchronize(W.st));
-    // run counts by pair; the first entry of the table (LDS rectangles, then
-    // device-memory ones) with an error is reported
-    auto check = [&](int t, bool report) -> int {
-      const swk::TracePair &P = htab[t];
-      const int c = dev_counts[P.id];
-      if (c == swk::kTraceBadResidue) {
-        if (report)
-          set_error("pair %d: a residue code inside its alignment is not below alphabet_size", P.id);
-        return SW_EINVAL;
-      }
-      if (c == swk::kTraceInconsistent) {
-        if (!report) return SW_EINVAL;
-        if (mode == 0)
-          set_error("pair %d: no alignment of score %d runs from its start (%d, %d) to its end "
-                    "(%d, %d)", P.id, P.score, query_start[P.id], ref_start[P.id],
-                    ends[P.id].query_end, ends[P.id].ref_end);
-        else
-          set_error("pair %d: score %d is not the optimum at the end cell (%d, %d)", P.id,
-                    P.score, ends[P.id].query_end, ends[P.id].ref_end);
-        return SW_EINVAL;
-      }
-      if (c < 1 || c > P.cap) {
-        if (report) set_error("pair %d: internal path error (%d runs, bound %d)", P.id, c, P.cap);
-        return SW_EDEVICE;
-      }
-      counts[P.id] = c;
-      if (mode != 0) {
-        ref_start_out[P.id] = dev_rstart[P.id];
-        query_start_out[P.id] = dev_qstart[P.id];
-      }
-      return SW_OK;
-    };
-    const int TT = nt >= 65536 ? host_threads() : 1;
-    std::vector<int> bad(TT, INT32_MAX);
-    parallel_ranges((size_t)nt, TT, [&](int th, size_t lo, size_t hi) {
-      for (size_t t = lo; t < hi; ++t)
-        if (check((int)t, false) != SW_OK) { bad[th] = (int)t; return; }
-    });
-    const int first = *std::min_element(bad.begin(), bad.end());
-    if (first != INT32_MAX) return check(first, true);
+    if (!W.tr_st[k]) HIPCHK(hipStreamCreateWithFlags(&W.tr_st[k], hipStreamNonBlocking));
+    if (!W.tr_done[k]) HIPCHK(hipEventCreateWithFlags(&W.tr_done[k], hipEventDisableTiming));
   }
-  for (const HostRun &hr : host_runs) counts[hr.k] = hr.n;
-  {  // cigar_off: an exclusive prefix sum of the counts, two passes on host threads
-    const int TP = np >= 65536 ? host_threads() : 1;
-    std::vector<int64_t> base(TP + 1, 0);
-    parallel_ranges((size_t)np, TP, [&](int t, size_t lo, size_t hi) {
-      int64_t sum = 0;
-      for (size_t k = lo; k < hi; ++k) sum += counts[k];
-      base[t + 1] = sum;
-    });
-    for (int t = 0; t < TP; ++t) base[t + 1] += base[t];
-    parallel_ranges((size_t)np, TP, [&](int t, size_t lo, size_t hi) {
-      int64_t run = base[t];
-      for (size_t k = lo; k < hi; ++k) cigar_off[k + 1] = run += counts[k];
-    });
+  if (!W.tr_ready) HIPCHK(hipEventCreateWithFlags(&W.tr_ready, hipEventDisableTiming));
+  swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
+  swk::TraceArgs ta;
+  ta.qres = d_q;
+  ta.rres = d_r;
+  ta.matrix = W.tr_mat.as<int32_t>();
+  ta.alpha = S.alpha;
+  ta.go = S.go;
+  ta.ge = S.ge;
+  ta.cigar = W.tr_runs.as<uint32_t>();
+  ta.n_runs = W.tr_nruns.as<int32_t>();
+  ta.mode = mode;
+  ta.ref_start = W.tr_rstart.as<int32_t>();
+  ta.query_start = W.tr_qstart.as<int32_t>();
+  ta.slot_words = 0;
+  ta.carry_rows = 0;
+  ta.gbits = nullptr;
+  ta.gcarry = nullptr;
+  const int used = std::min((int)groups.size(), NS);
+  if (used) HIPCHK(hipEventRecord(W.tr_ready, W.st));
+  for (int k = 0; k < used; ++k) HIPCHK(hipStreamWaitEvent(W.tr_st[k], W.tr_ready, 0));
+  static const int kLdsVariant[3] = {swk::kTraceV16x4, swk::kTraceV32, swk::kTraceV16x8};
+  for (int c = 0; c < 3; ++c) {
+    const int cnt = (int)(cstart[c + 1] - cstart[c]);
+    if (!cnt) continue;
+    ta.pairs = dp + cstart[c];
+    ta.n = cnt;
+    HIPCHK(swk::launch_trace(true, kLdsVariant[c], ta, cnt, W.st));
   }
-  if (cigar_off[np] > cigar_cap) {
-    set_error("the paths need %lld runs, cigar holds %lld", (long long)cigar_off[np],
-              (long long)cigar_cap);
+  for (int g = 0; g < (int)groups.size(); ++g) {
+    const Group &gr = groups[g];
+    const int k = std::min(g, NS - 1);
+    ta.pairs = dp + gr.first;
+    ta.n = gr.count;
+    ta.slot_words = gr.slot_words;
+    ta.carry_rows = gr.carry_rows;
+    ta.gbits = W.tr_bits[k].as<uint16_t>();
+    ta.gcarry = W.tr_carry[k].as<int32_t>();
+    HIPCHK(swk::launch_trace(false, gr.variant, ta, gr.waves, W.tr_st[k]));
+  }
+  for (int k = 0; k < used; ++k) {
+    HIPCHK(hipEventRecord(W.tr_done[k], W.tr_st[k]));
+    HIPCHK(hipStreamWaitEvent(W.st, W.tr_done[k], 0));
+  }
+  // ---- run counts checked, offsets by a device prefix sum
+  HIPCHK(swk::launch_trplan_check(dp, nt, W.tr_nruns.as<int32_t>(), W.tr_err.as<unsigned long long>(),
+                                  W.st));
+  HIPCHK(swk::launch_count_scan(W.tr_nruns.as<int32_t>(), np, W.tr_off.as<int64_t>(),
+                                W.tr_bsum.as<int64_t>(), W.st));
+  HIPCHK(hipMemcpyAsync(hs, W.tr_err.p, 8, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemcpyAsync(cigar_off, W.tr_off.p, (size_t)(np + 1) * sizeof(int64_t),
+                        hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipStreamSynchronize(W.st));
+  const uint64_t err2 = (uint64_t)hs[0];
+  if (err2 != ~0ull) {
+    cigar_off[0] = 0;
+    return path_error(b, mode, ends, query_start, ref_start, (int)(err2 >> 8), (int)(err2 & 0xff));
+  }
+  const int64_t total = cigar_off[np];
+  if (total > cigar_cap) {
+    set_error("the paths need %lld runs, cigar holds %lld", (long long)total, (long long)cigar_cap);
     return SW_EINVAL;
   }
-  if (nt > 0 && cigar_off[np] > 0) {
-    if ((rc = W.tr_packed.ensure((size_t)cigar_off[np] * sizeof(uint32_t)))) return rc;
-    HIPCHK(hipMemcpyAsync(W.tr_off.p, cigar_off, (size_t)(np + 1) * sizeof(int64_t),
-                          hipMemcpyHostToDevice, W.st));
-    HIPCHK(swk::launch_pack_runs(W.tr_pairs.as<swk::TracePair>(), nt, W.tr_nruns.as<int32_t>(),
-                                 W.tr_off.as<int64_t>(), W.tr_runs.as<uint32_t>(),
-                                 W.tr_packed.as<uint32_t>(), W.st));
-    HIPCHK(hipMemcpyAsync(cigar, W.tr_packed.p, (size_t)cigar_off[np] * sizeof(uint32_t),
+  if (total > 0) {
+    if ((rc = W.tr_packed.ensure((size_t)total * sizeof(uint32_t)))) return rc;
+    HIPCHK(swk::launch_pack_runs(dp, nt, W.tr_nruns.as<int32_t>(), W.tr_off.as<int64_t>(),
+                                 W.tr_runs.as<uint32_t>(), W.tr_packed.as<uint32_t>(), W.st));
+    HIPCHK(hipMemcpyAsync(cigar, W.tr_packed.p, (size_t)total * sizeof(uint32_t),
                           hipMemcpyDeviceToHost, W.st));
-    HIPCHK(hipStreamSynchronize(W.st));
   }
-  for (const HostRun &hr : host_runs) std::copy(hr.run, hr.run + hr.n, cigar + cigar_off[hr.k]);
+  if (mode != 0) {
+    HIPCHK(hipMemcpyAsync(ref_start_out, W.tr_rstart.p, (size_t)np * 4, hipMemcpyDeviceToHost, W.st));
+    HIPCHK(hipMemcpyAsync(query_start_out, W.tr_qstart.p, (size_t)np * 4, hipMemcpyDeviceToHost, W.st));
+  }
+  HIPCHK(hipStreamSynchronize(W.st));
   return SW_OK;
 }
 }  // namespace

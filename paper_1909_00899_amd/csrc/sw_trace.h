@@ -39,6 +39,94 @@ struct TracePair {
   int32_t A, B, score, cap, id, pad;
 };
 
+// Runs a local path can have between start and end: every run but the first
+// is preceded by a change of operation, M runs alternate with one or two gap
+// runs, and a rectangle of A x B cells holds at most min(A, B) pairs.
+__host__ __device__ inline int64_t trace_run_bound(int64_t A, int64_t B) {
+  return A + B - 1 < 3 * (A < B ? A : B) - 2 ? A + B - 1 : 3 * (A < B ? A : B) - 2;
+}
+// 2-byte units of a rectangle's decision words: rows x tiles x 64 lanes x
+// the word width of its variant (constant divisors)
+__host__ __device__ inline int64_t trace_slot_words(const TracePair &P) {
+  int64_t tiles;
+  switch (trace_cols(P.pad)) {
+    case 1: tiles = (P.B + 63) / 64; break;
+    case 2: tiles = (P.B + 127) / 128; break;
+    case 3: tiles = (P.B + 191) / 192; break;
+    case 8: tiles = (P.B + 511) / 512; break;
+    default: tiles = (P.B + 255) / 256; break;
+  }
+  return (int64_t)P.A * tiles * 64 * (trace_word_bytes(P.pad) / 2);
+}
+
+// ---- path tables on the device (sw_trplan.hip)
+//
+// Every pair is classified once: no path (a local alignment of score <= 0),
+// runs made by the planner itself (an end-to-end alignment with an empty
+// side: at most a D and an I run from the best virtual start element), or a
+// rectangle of one of the classes below; a pair that breaks the API's rules
+// sets an error word (the smallest pair index wins).  Classes: the three LDS
+// variants (16-bit x4, 32-bit, 16-bit x8: one launch each), then device-
+// memory rectangles by variant and power of two below their slot, largest
+// first (any member needs more than half its class's largest slot: one
+// launch group per class), then the planner-made runs.
+constexpr int kTrBuckets = 40;                         // slots below 2^40 words
+constexpr int kTrClasses = 3 + 3 * kTrBuckets + 1;
+constexpr int kTrHostClass = kTrClasses - 1;
+constexpr int kTrBlocks = 256;                         // classify / scatter workgroups
+__host__ __device__ inline int trace_size_class(int64_t slot, int variant) {
+  int b = 0;
+  for (int64_t s = slot; s > 1 && b + 1 < kTrBuckets; s >>= 1) ++b;
+  return 3 + (kTrBuckets - 1 - b) * 3 + variant;
+}
+// error codes of the planner's error word (pair index << 8 | code)
+enum : int {
+  kTrErrRect = 1,        // mode 0: start and end are not a rectangle of the pair
+  kTrErrEnd = 2,         // modes 1-4: not an end cell of that mode
+  kTrErrOptimum = 3,     // modes 1-4, empty side: the score is not the optimum
+  kTrErrRange = 4,       // the rectangle leaves the 32-bit range of the path kernel
+  kTrErrScratch = 5,     // more than 2 GiB of decision bits
+  kTrErrPair = 6,        // pair index out of range
+  kTrErrQoff = 7,        // the pair's query offsets decrease or are negative
+  kTrErrRoff = 8,        // the pair's reference offsets decrease or are negative
+  kTrErrResidue = 9,     // after the path kernels: a residue code >= alphabet size
+  kTrErrInconsistent = 10,
+  kTrErrCount = 11,      // a run count outside 1..cap
+};
+struct TrPlanArgs {
+  int np, nq, nr, mode, alpha, go, ge, max_s, maxabs;
+  const int64_t *qoff, *roff;        // device
+  const int32_t *pq, *pr;            // device; pq may be null (query 0)
+  const DevResult *ends;             // device copy of the caller's results
+  const int32_t *qs, *rs;            // device copies of the start cells (mode 0)
+  TracePair *rect;                   // per pair: its rectangle (scratch)
+  uint8_t *cls;                      // per pair: its class, or 0xff (no path)
+  uint32_t *hruns;                   // per pair: planner-made runs (2 words)
+  int32_t *n_runs;                   // per pair: run count (0 without a path)
+  int32_t *ref_start, *query_start;  // modes 1-4: start element + 1 per pair
+  int32_t *blk_count;                // [kTrBlocks][kTrClasses]
+  int64_t *blk_caps;                 // [kTrBlocks] run capacity per workgroup
+  unsigned long long *cls_max;       // [kTrClasses][2]: largest slot, most rows
+  unsigned long long *err;           // error word (initialised to ~0)
+  int64_t *summary;                  // [kTrClasses + 2]: class starts, entries, region total
+  TracePair *table;                  // the entries by class, with run regions
+  uint32_t *runs;                    // run regions (planner-made runs written here)
+};
+// classify + workgroup histograms; totals (class starts, workgroup cursors,
+// region bases); scatter.  The host reads the summary between totals and
+// scatter (it sizes the run regions and the launches).
+hipError_t launch_trplan_classify(const TrPlanArgs &a, hipStream_t st);
+hipError_t launch_trplan_totals(const TrPlanArgs &a, hipStream_t st);
+hipError_t launch_trplan_scatter(const TrPlanArgs &a, hipStream_t st);
+// after the path kernels: every rectangle's run count checked (error word),
+// and off[0..np] = the exclusive prefix sum of the per-pair counts
+// (negative ones as 0); off[np] is the total; bsum: (np + 4095) / 4096 + 1
+// scratch entries
+hipError_t launch_trplan_check(const TracePair *table, int nt, const int32_t *n_runs,
+                               unsigned long long *err, hipStream_t st);
+hipError_t launch_count_scan(const int32_t *counts, int np, int64_t *off, int64_t *bsum,
+                             hipStream_t st);
+
 struct TraceArgs {
   const TracePair *pairs;
   int n;
