@@ -295,8 +295,9 @@ template <class O, int JSTRIDE>
 struct ProfLds8 {
   __device__ __forceinline__ uint32_t load(uint32_t lo, uint32_t hi, int j) const {
     if constexpr (O::kHalves == 2) {
-      // each byte sign-extended straight into its 16-bit half (the LDS
-      // pipe's d16 loads), no merging instruction on the VALU
+      // two byte loads merged by one permute: the d16 loads that would write
+      // each byte into its half directly zero the register's other half on
+      // this chip (SRAM ECC), so they cannot build the pair
       s16x2 v;
       v.x = (short)*(const signed char *)(smem + lo + j * JSTRIDE);
       v.y = (short)*(const signed char *)(smem + hi + j * JSTRIDE);

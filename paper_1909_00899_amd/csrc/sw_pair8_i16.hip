@@ -10,7 +10,7 @@ using O = dev::OpsI16;
 template <int SEG>
 hipError_t launch_d8(const KArgs &a, int grid, hipStream_t st, size_t lds) {
   auto k = dev::pair_direct_kernel<O, SEG, 8, 1>;
-  hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, dim3(grid), dim3(kWave), lds, st, a);
   return hipGetLastError();
 }
