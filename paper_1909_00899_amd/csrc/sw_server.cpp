@@ -72,6 +72,8 @@ struct sw_server {
   std::unordered_map<uint64_t, std::unique_ptr<Request>> table;
   uint64_t next_ticket = 1;
   int outstanding = 0;               // accepted and not yet finished
+  int idle_workers = 0;              // workers waiting for requests (a submit wakes
+                                     // one only then: a wake-up is a system call)
   int running = 0;                   // batches on the device
   bool stop = false;
   // While a replay runs, workers append the tickets of each finished batch
@@ -116,7 +118,11 @@ void sw_server::worker_main() {
     size_t bytes = 0;
     {
       std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+      if (!stop && queue.empty()) {
+        ++idle_workers;
+        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        --idle_workers;
+      }
       if (stop && queue.empty()) break;
       // admission: the head's class (scoring and size) in FIFO order, within
       // the budget; a batch lasts as long as its longest pair, so short
@@ -293,6 +299,7 @@ int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int3
   r->bytes = s->request_bytes(query_len, (int)n);
   if (r->bytes > s->budget) { set_error("request needs %zu bytes, budget %zu", r->bytes, s->budget); return SW_ENOMEM; }
   r->t_submit = mono_ns();
+  bool wake = false;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) { set_error("server stopping"); return SW_EINVAL; }
@@ -302,8 +309,9 @@ int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int3
     s->queue.push_back(r.get());
     s->outstanding++;
     s->table.emplace(r->ticket, std::move(r));
+    wake = s->idle_workers > 0;
   }
-  s->cv_work.notify_one();
+  if (wake) s->cv_work.notify_one();
   return SW_OK;
 }
 
