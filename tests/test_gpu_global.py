@@ -181,7 +181,7 @@ def _check_paths(w, mode, label, pairs=None):
 @pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("alpha,go,ge", [(2, 2, 1), (4, 3, 1), (20, 11, 1), (3, 1, 0), (4, 2, 5)])
 def test_paths_small_pairs_equal_the_oracle(mode, alpha, go, ge):
-    # empty sides included (their runs are made on the host)
+    # empty sides included (their runs are made by the path planner, no kernel)
     rng = np.random.default_rng(1000 + alpha + go + 7 * mode)
     M = W.protein_matrix() if alpha == 20 else W.random_matrix(rng, alpha)
     w = W.random_pairs(300, alpha, (0, 40), (0, 50), 1001 + alpha + mode, matrix=M,
