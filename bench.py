@@ -294,10 +294,13 @@ def main():
         # offline batch call on the same requests
         # (20000 requests per rate: at 200k req/s a shorter run is mostly the
         # tail of its last batches, not the sustained rate; 1M req/s saturates
-        # the server, so its achieved rate is the capacity)
-        rows = _serving_sweep(api, W, [10000, 50000, 200000, 1000000], lambda rate: 20000)
+        # the server, so its achieved rate is the capacity, taken over 60000
+        # requests so that the first, small batches and the last batches'
+        # long pairs weigh little against the sustained part)
+        rows = _serving_sweep(api, W, [10000, 50000, 200000, SATURATING_RATE],
+                              lambda rate: SATURATED_REQUESTS if rate >= SATURATING_RATE else 20000)
         rec["served"] = {"workload": "25k protein + 25k DNA resident refs, Poisson arrivals, "
-                                     "20000 requests per rate",
+                                     "20000 requests per rate, 60000 at the saturating rate",
                          "sweep": rows,
                          "served_equals_offline": all(x["served_equals_offline"] for x in rows)}
 
@@ -619,6 +622,11 @@ def _offline_serving(api, db, scor, req):
     return res, time.perf_counter() - t0
 
 
+# An offered rate above the server's capacity, and the requests replayed at it.
+SATURATING_RATE = 1_000_000
+SATURATED_REQUESTS = 60_000
+
+
 def _serving_sweep(api, W, rates, n_of_rate):
     """Open-loop Poisson replay through the server at each rate; every served
     result is compared with the offline batch call on the same requests."""
@@ -656,8 +664,10 @@ def bench_serving(args):
     from paper_1909_00899_amd import api, workloads as W
     api.load()
     api.sw_init(0)
-    rates = [1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000, 1000000]
-    rows = _serving_sweep(api, W, rates, lambda rate: int(min(20000, max(2000, rate * 3))))
+    rates = [1000, 2000, 5000, 10000, 20000, 50000, 100000, 200000, SATURATING_RATE]
+    rows = _serving_sweep(api, W, rates,
+                          lambda rate: SATURATED_REQUESTS if rate >= SATURATING_RATE
+                          else int(min(20000, max(2000, rate * 3))))
     print(json.dumps({"metric": METRIC, "value": rows[-1]["p99_ms"], "unit": "ms p99",
                       "n_gpus": 1, "higher_is_better": False, "dtype": "i16x2",
                       "data": "synthetic",
