@@ -37,8 +37,9 @@ __device__ int classify(const TrPlanArgs &a, int k, TracePair &tp) {
   const int q = a.pq ? a.pq[k] : 0, r = a.pr[k];
   if (q < 0 || q >= a.nq || r < 0 || r >= a.nr) return -kTrErrPair;
   const int64_t q0 = a.qoff[q], q1 = a.qoff[q + 1], r0 = a.roff[r], r1 = a.roff[r + 1];
-  if (q0 < 0 || q1 < q0) return -kTrErrQoff;
-  if (r0 < 0 || r1 < r0) return -kTrErrRoff;
+  // within the residue arrays too (they hold qoff[nq] and roff[nr] bytes)
+  if (q0 < 0 || q1 < q0 || q1 > a.qoff[a.nq]) return -kTrErrQoff;
+  if (r0 < 0 || r1 < r0 || r1 > a.roff[a.nr]) return -kTrErrRoff;
   const int64_t m = q1 - q0, n = r1 - r0;
   int qs = 0, rs = 0;
   if (a.mode == 0) {

@@ -266,6 +266,23 @@ def test_paths_device_resident_inputs_and_errors():
         api.sw_align_batch_cigar(w.query_res, w.query_off, ref, w.ref_off, w.pair_ref, w.matrix,
                                  w.gap_open, w.gap_extend, ends, qs, rs, pair_query=w.pair_query)
     assert e.value.code == api.SW_EINVAL
+    # offsets that decrease: a query running past the residue total
+    qoff = w.query_off.copy()
+    q = int(w.pair_query[k])
+    qoff[-1] = qoff[q + 1] - 1
+    with pytest.raises(api.SwError) as e:
+        api.sw_align_batch_cigar(w.query_res[:qoff[-1]], qoff, w.ref_res, w.ref_off, w.pair_ref,
+                                 w.matrix, w.gap_open, w.gap_extend, ends, qs, rs,
+                                 pair_query=w.pair_query)
+    assert e.value.code == api.SW_EINVAL and "query offsets" in str(e.value)
+    roff = w.ref_off.copy()
+    r = int(w.pair_ref[k])
+    roff[-1] = roff[r + 1] - 1
+    with pytest.raises(api.SwError) as e:
+        api.sw_align_batch_cigar(w.query_res, w.query_off, w.ref_res[:roff[-1]], roff, w.pair_ref,
+                                 w.matrix, w.gap_open, w.gap_extend, ends, qs, rs,
+                                 pair_query=w.pair_query)
+    assert e.value.code == api.SW_EINVAL and "reference offsets" in str(e.value)
     # the library still works afterwards
     runs3, off3 = api.sw_align_batch_cigar(*args, ends, qs, rs, pair_query=w.pair_query)
     assert (off3 == off).all() and (runs3 == runs).all()
