@@ -573,7 +573,8 @@ int sw_server_destroy(sw_server *s);
 /* Open-loop replay for measurement: submits request k at arrival_ns[k]
  * (nanoseconds after the call starts; nondecreasing) from one thread while
  * another collects completions, then waits for all of them.  Queries are CSR
- * (host).  out[k] gets the result; times_ns[3k..3k+2] = {submit, admit, done}
+ * (host), read in place (not copied per request: the buffer must stay
+ * unchanged until the call returns).  out[k] gets the result; times_ns[3k..3k+2] = {submit, admit, done}
  * relative to the call's start.  A submit that returns SW_EBUSY is retried
  * until accepted (its submit time is the first attempt).  The collector takes
  * finished requests as the workers report them (no polling of outstanding

@@ -1,11 +1,11 @@
 // Continuous-batching request server (include/sw.h, "Serving").
 //
-// Requests (one query against one resident database reference) enter a FIFO
-// queue.  n_streams worker threads each own a HIP stream and a device
-// workspace; an idle worker takes, under the server lock, the longest FIFO
-// prefix of requests that share the head's scoring scheme and size class and fit the
-// remaining memory budget (at most max_batch), marks them admitted, releases
-// the lock and runs them as one batch (the batch planner re-buckets them by
+// Requests (one query against one resident database reference) enter the
+// FIFO of their class (scoring scheme and size).  n_streams worker threads
+// each own a HIP stream and a device workspace; an idle worker takes, under
+// the server lock, the longest prefix of the FIFO that holds the oldest
+// waiting request that fits the remaining memory budget (at most max_batch),
+// marks them admitted, releases the lock and runs them as one batch (the batch planner re-buckets them by
 // length into per-pair kernel launches).  Requests that arrive meanwhile wait
 // for the next idle worker, so their kernels overlap with the batches already
 // on the device.  Each result is the batch path's result for that pair.
@@ -45,7 +45,9 @@ int64_t mono_ns() {
 
 struct Request {
   uint64_t ticket;
-  std::vector<uint8_t> query;
+  const uint8_t *query = nullptr;   // the residues: `own`, or the replay caller's buffer
+  int32_t qlen = 0;
+  std::vector<uint8_t> own;
   int32_t ref_id, scoring_id;
   int32_t klass;             // batch class: scoring and size (see kLongCells)
   size_t bytes;
@@ -68,7 +70,13 @@ struct sw_server {
   std::vector<uint8_t> db_max_code;  // largest residue code of each reference (0 if empty)
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<Request *> queue;
+  // One FIFO per batch class (two per scoring: short and long requests): a
+  // worker takes the class of the oldest waiting request and pops from the
+  // front of that FIFO only, so admission costs the batch, not the depth of
+  // the backlog (a scan of one shared queue, erasing from its middle, held
+  // the lock for milliseconds once it was deep and stalled every submit)
+  std::vector<std::deque<Request *>> queues;
+  int64_t queued = 0;
   std::unordered_map<uint64_t, std::unique_ptr<Request>> table;
   uint64_t next_ticket = 1;
   int outstanding = 0;               // accepted and not yet finished
@@ -118,27 +126,33 @@ void sw_server::worker_main() {
     size_t bytes = 0;
     {
       std::unique_lock<std::mutex> lk(mu);
-      if (!stop && queue.empty()) {
+      if (!stop && queued == 0) {
         ++idle_workers;
-        cv_work.wait(lk, [&] { return stop || !queue.empty(); });
+        cv_work.wait(lk, [&] { return stop || queued > 0; });
         --idle_workers;
       }
-      if (stop && queue.empty()) break;
-      // admission: the head's class (scoring and size) in FIFO order, within
-      // the budget; a batch lasts as long as its longest pair, so short
-      // requests do not wait behind long ones of the same scoring
-      const int klass = queue.front()->klass;
-      for (auto it = queue.begin(); it != queue.end() && (int)batch.size() < max_batch;) {
-        Request *r = *it;
-        if (r->klass != klass) { ++it; continue; }
+      if (stop && queued == 0) break;
+      // admission: the class (scoring and size) of the oldest waiting
+      // request, in FIFO order, within the budget; a batch lasts as long as
+      // its longest pair, so short requests do not wait behind long ones of
+      // the same scoring
+      int klass = -1;
+      for (int c = 0; c < (int)queues.size(); ++c)
+        if (!queues[c].empty() &&
+            (klass < 0 || queues[c].front()->ticket < queues[klass].front()->ticket))
+          klass = c;
+      std::deque<Request *> &q = queues[klass];
+      while (!q.empty() && (int)batch.size() < max_batch) {
+        Request *r = q.front();
         if (in_flight + bytes + r->bytes > budget && !(batch.empty() && in_flight == 0)) break;
         bytes += r->bytes;
         batch.push_back(r);
-        it = queue.erase(it);
+        q.pop_front();
       }
+      queued -= (int64_t)batch.size();
       if (batch.empty()) {
         // the head does not fit next to what is running: wait for a finish
-        cv_done.wait(lk, [&] { return stop || in_flight == 0 || queue.empty(); });
+        cv_done.wait(lk, [&] { return stop || in_flight == 0 || queued == 0; });
         continue;
       }
       in_flight += bytes;
@@ -149,7 +163,7 @@ void sw_server::worker_main() {
     // ---- run the batch (outside the lock)
     const Scoring &sc = scorings[batch[0]->scoring_id];
     int64_t qtotal = 0;
-    for (Request *r : batch) qtotal += (int64_t)r->query.size();
+    for (Request *r : batch) qtotal += (int64_t)r->qlen;
     int rc = qstage.ensure(std::max<int64_t>(qtotal, 1));
     if (!rc) rc = qbuf.ensure(std::max<int64_t>(qtotal, 1));
     ExecInput in;
@@ -162,18 +176,18 @@ void sw_server::worker_main() {
       in.m_of_query.resize(batch.size());
       for (size_t k = 0; k < batch.size(); ++k) {
         Request *r = batch[k];
-        std::memcpy(h + off, r->query.data(), r->query.size());
+        if (r->qlen) std::memcpy(h + off, r->query, (size_t)r->qlen);
         PairInfo &p = in.pairs[k];
         std::memset(&p, 0, sizeof(p));
         p.q_off = off;
         p.r_off = db_off[r->ref_id];
-        p.m = (int)r->query.size();
+        p.m = (int)r->qlen;
         p.n = (int)(db_off[r->ref_id + 1] - db_off[r->ref_id]);
         p.out = (int)k;
         in.q_off_of_query[k] = off;
         in.m_of_query[k] = p.m;
         if (p.m > 0 && p.n > 0) in.items.push_back(PlanItem{(int)k, (int)k, p.m, p.n});
-        off += (int64_t)r->query.size();
+        off += (int64_t)r->qlen;
       }
       if (qtotal && hipMemcpyAsync(qbuf.p, h, qtotal, hipMemcpyHostToDevice, st) != hipSuccess) {
         set_error("server: query upload failed");
@@ -259,13 +273,20 @@ int sw_server_create(const sw_server_config *cfg, sw_server **out) {
     set_error("server: database upload failed");
     return SW_EDEVICE;
   }
+  s->queues.resize(2 * s->scorings.size());
   for (int k = 0; k < nst; ++k) s->workers.emplace_back(&sw_server::worker_main, s.get());
   *out = s.release();
   return SW_OK;
 }
 
-int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int32_t ref_id,
-                     int32_t scoring_id, uint64_t *ticket) {
+}  // extern "C"
+
+namespace {
+
+// sw_server_submit; with copy == false the request reads the caller's
+// residues in place (the replay, whose buffer outlives all its requests).
+int submit_impl(sw_server *s, const uint8_t *query, int32_t query_len, int32_t ref_id,
+                int32_t scoring_id, uint64_t *ticket, bool copy) {
   if (!s || !ticket || query_len < 0 || (query_len > 0 && !query)) { set_error("bad submit"); return SW_EINVAL; }
   if (ref_id < 0 || ref_id + 1 >= (int64_t)s->db_off.size() || scoring_id < 0 ||
       scoring_id >= (int)s->scorings.size()) {
@@ -292,7 +313,13 @@ int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int3
     return SW_EOVERFLOW;
   }
   std::unique_ptr<Request> r(new Request());
-  r->query.assign(query, query + query_len);
+  if (copy) {
+    r->own.assign(query, query + query_len);
+    r->query = r->own.data();
+  } else {
+    r->query = query;
+  }
+  r->qlen = query_len;
   r->ref_id = ref_id;
   r->scoring_id = scoring_id;
   r->klass = 2 * scoring_id + (is_long(query_len, n) ? 1 : 0);
@@ -306,13 +333,23 @@ int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int3
     if ((int)s->table.size() >= s->max_queued) return SW_EBUSY;
     r->ticket = s->next_ticket++;
     *ticket = r->ticket;
-    s->queue.push_back(r.get());
+    s->queues[r->klass].push_back(r.get());
+    s->queued++;
     s->outstanding++;
     s->table.emplace(r->ticket, std::move(r));
     wake = s->idle_workers > 0;
   }
   if (wake) s->cv_work.notify_one();
   return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_server_submit(sw_server *s, const uint8_t *query, int32_t query_len, int32_t ref_id,
+                     int32_t scoring_id, uint64_t *ticket) {
+  return submit_impl(s, query, query_len, ref_id, scoring_id, ticket, true);
 }
 
 int sw_server_poll(sw_server *s, uint64_t ticket, sw_result *out, int64_t *ts) {
@@ -341,7 +378,8 @@ int sw_server_destroy(sw_server *s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
-    s->queue.clear();
+    for (auto &q : s->queues) q.clear();
+    s->queued = 0;
   }
   s->cv_work.notify_all();
   s->cv_done.notify_all();
@@ -370,6 +408,7 @@ int sw_server_replay(sw_server *s, int32_t n, const uint8_t *qres, const int64_t
       return SW_EBUSY;
     }
     s->done_sink = &sink;
+    s->table.reserve(s->table.size() + (size_t)n);
   }
   std::vector<uint64_t> tickets(n, 0);
   std::vector<int64_t> first_try(n, 0);
@@ -386,8 +425,8 @@ int sw_server_replay(sw_server *s, int32_t n, const uint8_t *qres, const int64_t
       first_try[k] = mono_ns();
       int rc;
       uint64_t tk = 0;
-      while ((rc = sw_server_submit(s, qres + qoff[k], (int32_t)(qoff[k + 1] - qoff[k]), ref_id[k],
-                                    scoring_id[k], &tk)) == SW_EBUSY)
+      while ((rc = submit_impl(s, qres + qoff[k], (int32_t)(qoff[k + 1] - qoff[k]), ref_id[k],
+                               scoring_id[k], &tk, false)) == SW_EBUSY)
         std::this_thread::sleep_for(std::chrono::microseconds(20));
       if (rc != SW_OK) { err = rc; tickets[k] = 0; }
       else tickets[k] = tk;
@@ -398,6 +437,8 @@ int sw_server_replay(sw_server *s, int32_t n, const uint8_t *qres, const int64_t
   // publishes its tickets, and fetches each result with one poll.
   std::unordered_map<uint64_t, int> index;
   index.reserve((size_t)n);
+  std::vector<std::pair<uint64_t, int>> matched;
+  std::vector<std::unique_ptr<Request>> freed;
   int remaining = n, indexed = 0;
   while (remaining > 0) {
     const int upto = submitted.load(std::memory_order_acquire);
@@ -420,20 +461,40 @@ int sw_server_replay(sw_server *s, int32_t n, const uint8_t *qres, const int64_t
       sink.clear();
     }
     size_t keep = 0;
+    matched.clear();
     for (const uint64_t tk : work) {
       auto it = index.find(tk);
       if (it == index.end()) { work[keep++] = tk; continue; }   // submit not yet returned
-      const int k = it->second;
+      matched.emplace_back(tk, it->second);
       index.erase(it);
-      int64_t ts[3];
-      const int rc = sw_server_poll(s, tk, &out[k], ts);
-      if (rc != SW_OK) err = rc;
-      times_ns[3 * k + 0] = first_try[k] - t0;
-      times_ns[3 * k + 1] = ts[1] - t0;
-      times_ns[3 * k + 2] = ts[2] - t0;
-      --remaining;
     }
     work.resize(keep);
+    if (matched.empty()) continue;
+    {
+      // the finished requests of these batches, taken under one lock (their
+      // records are freed after it is released)
+      std::lock_guard<std::mutex> lk(s->mu);
+      for (const auto &tk_k : matched) {
+        auto it = s->table.find(tk_k.first);
+        const int k = tk_k.second;
+        times_ns[3 * k + 0] = first_try[k] - t0;
+        if (it == s->table.end()) {
+          err = SW_ENOENT;
+          out[k] = sw_result{0, -1, -1, 0};
+          times_ns[3 * k + 1] = times_ns[3 * k + 2] = times_ns[3 * k + 0];
+          continue;
+        }
+        const Request *r = it->second.get();
+        if (r->status != SW_OK) err = r->status;
+        out[k] = r->res;
+        times_ns[3 * k + 1] = r->t_admit - t0;
+        times_ns[3 * k + 2] = r->t_done - t0;
+        freed.push_back(std::move(it->second));
+        s->table.erase(it);
+      }
+    }
+    freed.clear();
+    remaining -= (int)matched.size();
   }
   producer.join();
   {
