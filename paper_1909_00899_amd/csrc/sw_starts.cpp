@@ -59,12 +59,10 @@ struct StartsWork {
   DevBuf tab;            // offsets (int64), pair ids and first rows (int32)
   // paths
   DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off;
-  HostBuf tr_host, tr_hcounts;   // pinned: the pair table, the run counts
   HostBuf ld_stage;              // pinned: a device-resident batch's offsets and indices
   DevBuf tr_res;                 // end-to-end results
   DevBuf tr_rstart;              // end-to-end paths: reference starts
   DevBuf tr_qstart;              // end-to-end paths: query starts
-  HostBuf tr_hres;
   // path tables built on the device: the caller's inputs (results, start
   // cells; a host batch's offsets and indices), per-pair scratch, the
   // planner's workgroup arrays, its summaries (pinned)
@@ -403,7 +401,6 @@ namespace {
 
 constexpr int64_t kTraceScratchBytes = 1ll << 30;    // device-memory decision bits per launch
 constexpr int kTraceMaxWaves = 4096;
-constexpr int kDualCols = 160;   // end-to-end queries up to this length run two per wavefront
 
 }  // namespace
 
@@ -497,6 +494,62 @@ int path_error(const sw_batch *b, int mode, const sw_result *ends, const int32_t
   }
 }
 
+// The batch on W.st's device: a host batch's offsets, pair indices and
+// residues uploaded on W.st, a device batch's own arrays (W.st first waits
+// for the stream that produced them).  Offsets are checked by the device
+// planners, pair by pair.
+struct DevInputs {
+  const int64_t *qoff, *roff;
+  const int32_t *pq, *pr;   // pq null: query 0 for every pair
+  const uint8_t *q, *r;
+};
+
+int device_inputs(const sw_batch *b, StartsWork &W, DevInputs &d) {
+  int rc;
+  const int np = b->n_pairs;
+  const int64_t nq = b->n_queries, nr = b->n_refs;
+  d.qoff = b->query_off;
+  d.roff = b->ref_off;
+  d.pq = b->pair_query;
+  d.pr = b->pair_ref;
+  d.q = b->query_res;
+  d.r = b->ref_res;
+  if (b->device_resident) {
+    if (b->stream) {
+      hipEvent_t ev;
+      HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      hipError_t e = hipEventRecord(ev, (hipStream_t)b->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(W.st, ev, 0);
+      (void)hipEventDestroy(ev);
+      HIPCHK(e);
+    }
+    return SW_OK;
+  }
+  const int64_t qb = b->query_off[nq], rb = b->ref_off[nr];
+  if (qb < 0 || rb < 0) {
+    set_error(qb < 0 ? "query offsets not nondecreasing" : "reference offsets not nondecreasing");
+    return SW_EINVAL;
+  }
+  if ((rc = W.tr_qoff.ensure((size_t)(nq + 1) * 8)) || (rc = W.tr_roff.ensure((size_t)(nr + 1) * 8)) ||
+      (rc = W.tr_pr.ensure((size_t)np * 4)) || (rc = W.tr_pq.ensure((size_t)np * 4)) ||
+      (rc = W.src_q.ensure((size_t)qb + 1)) || (rc = W.src_r.ensure((size_t)rb + 1)))
+    return rc;
+  HIPCHK(hipMemcpyAsync(W.tr_qoff.p, b->query_off, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, W.st));
+  HIPCHK(hipMemcpyAsync(W.tr_roff.p, b->ref_off, (size_t)(nr + 1) * 8, hipMemcpyHostToDevice, W.st));
+  HIPCHK(hipMemcpyAsync(W.tr_pr.p, b->pair_ref, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
+  if (b->pair_query)
+    HIPCHK(hipMemcpyAsync(W.tr_pq.p, b->pair_query, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
+  if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, (size_t)qb, hipMemcpyHostToDevice, W.st));
+  if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, (size_t)rb, hipMemcpyHostToDevice, W.st));
+  d.qoff = W.tr_qoff.as<int64_t>();
+  d.roff = W.tr_roff.as<int64_t>();
+  d.pr = W.tr_pr.as<int32_t>();
+  d.pq = b->pair_query ? W.tr_pq.as<int32_t>() : nullptr;
+  d.q = W.src_q.as<uint8_t>();
+  d.r = W.src_r.as<uint8_t>();
+  return SW_OK;
+}
+
 int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_result *ends,
                const int32_t *query_start, const int32_t *ref_start, int32_t *query_start_out,
                int32_t *ref_start_out, uint32_t *cigar, int64_t cigar_cap, int64_t *cigar_off) {
@@ -519,46 +572,12 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
   StartsWork &W = g_starts;
   HIPCHK(hipSetDevice(g_ctx.device));
   if (!W.st) HIPCHK(hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking));
-  const bool dev = b->device_resident != 0;
-  if (dev && b->stream) {
-    // the caller's stream produced the inputs
-    hipEvent_t ev;
-    HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
-    hipError_t e = hipEventRecord(ev, (hipStream_t)b->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(W.st, ev, 0);
-    (void)hipEventDestroy(ev);
-    HIPCHK(e);
-  }
+  DevInputs din;
+  if ((rc = device_inputs(b, W, din))) return rc;
   const int64_t nq = b->n_queries, nr = b->n_refs;
-  // ---- inputs on the device: the batch (a host batch's offsets, indices and
-  // residues uploaded), the results and start cells
-  const int64_t *d_qoff = b->query_off, *d_roff = b->ref_off;
-  const int32_t *d_pq = b->pair_query, *d_pr = b->pair_ref;
-  const uint8_t *d_q = b->query_res, *d_r = b->ref_res;
-  if (!dev) {
-    const int64_t qb = b->query_off[nq], rb = b->ref_off[nr];
-    if (qb < 0 || rb < 0) {
-      set_error(qb < 0 ? "query offsets not nondecreasing" : "reference offsets not nondecreasing");
-      return SW_EINVAL;
-    }
-    if ((rc = W.tr_qoff.ensure((size_t)(nq + 1) * 8)) || (rc = W.tr_roff.ensure((size_t)(nr + 1) * 8)) ||
-        (rc = W.tr_pr.ensure((size_t)np * 4)) || (rc = W.tr_pq.ensure((size_t)np * 4)) ||
-        (rc = W.src_q.ensure((size_t)qb + 1)) || (rc = W.src_r.ensure((size_t)rb + 1)))
-      return rc;
-    HIPCHK(hipMemcpyAsync(W.tr_qoff.p, b->query_off, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, W.st));
-    HIPCHK(hipMemcpyAsync(W.tr_roff.p, b->ref_off, (size_t)(nr + 1) * 8, hipMemcpyHostToDevice, W.st));
-    HIPCHK(hipMemcpyAsync(W.tr_pr.p, b->pair_ref, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
-    if (b->pair_query)
-      HIPCHK(hipMemcpyAsync(W.tr_pq.p, b->pair_query, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
-    if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, (size_t)qb, hipMemcpyHostToDevice, W.st));
-    if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, (size_t)rb, hipMemcpyHostToDevice, W.st));
-    d_qoff = W.tr_qoff.as<int64_t>();
-    d_roff = W.tr_roff.as<int64_t>();
-    d_pr = W.tr_pr.as<int32_t>();
-    d_pq = b->pair_query ? W.tr_pq.as<int32_t>() : nullptr;
-    d_q = W.src_q.as<uint8_t>();
-    d_r = W.src_r.as<uint8_t>();
-  }
+  const int64_t *d_qoff = din.qoff, *d_roff = din.roff;
+  const int32_t *d_pq = din.pq, *d_pr = din.pr;
+  const uint8_t *d_q = din.q, *d_r = din.r;
   constexpr int NC = swk::kTrClasses;
   if ((rc = W.tr_ends.ensure((size_t)np * sizeof(sw_result))) ||
       (rc = W.tr_qs.ensure((size_t)np * 4)) || (rc = W.tr_rs.ensure((size_t)np * 4)) ||
@@ -764,6 +783,40 @@ extern "C" int sw_align_batch_global_cigar(const sw_batch *b, const sw_scoring *
 
 // ------------------------------------------------------------------ end-to-end scores
 
+namespace {
+
+// The message and status of the end-to-end planner's error word for pair k.
+int endtoend_error(const sw_batch *b, int k, int code) {
+  int64_t m, n;
+  pair_lengths(b, k, m, n);
+  switch (code) {
+    case swk::kTrErrPair:
+      set_error("pair %d refers to a query or reference out of range", k);
+      return SW_EINVAL;
+    case swk::kTrErrQoff:
+      set_error("query offsets not nondecreasing");
+      return SW_EINVAL;
+    case swk::kTrErrRoff:
+      set_error("reference offsets not nondecreasing");
+      return SW_EINVAL;
+    case swk::kTrErrRange:
+      set_error("pair %d: %lld x %lld leaves the int32 range of the end-to-end kernel", k,
+                (long long)m, (long long)n);
+      return SW_EOVERFLOW;
+    case swk::kE2eErrScore:
+      set_error("pair %d: score below the int32 range", k);
+      return SW_EOVERFLOW;
+    case swk::kTrErrResidue:
+      set_error("pair %d: a residue code is not below alphabet_size", k);
+      return SW_EINVAL;
+    default:
+      set_error("pair %d: internal end-to-end error %d", k, code);
+      return SW_EDEVICE;
+  }
+}
+
+}  // namespace
+
 extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, int32_t mode,
                                      sw_result *out) {
   int rc = check_batch_args(b);
@@ -777,116 +830,97 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
   if ((rc = ensure_init())) return rc;
   std::lock_guard<std::mutex> g(g_starts.mu);
   StartsWork &W = g_starts;
-  Batch B;
-  if ((rc = load_batch(b, W, B))) return rc;
+  HIPCHK(hipSetDevice(g_ctx.device));
+  if (!W.st) HIPCHK(hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking));
+  DevInputs din;
+  if ((rc = device_inputs(b, W, din))) return rc;
   int64_t maxabs = 0;
   for (int v : S.M) maxabs = std::max<int64_t>(maxabs, v < 0 ? -(int64_t)v : v);
-  auto gap = [&](int64_t L) -> int64_t { return L <= 0 ? 0 : S.go + (L - 1) * (int64_t)S.ge; };
-  if ((rc = W.tr_host.ensure((size_t)np * sizeof(swk::TracePair)))) return rc;
-  swk::TracePair *htab = W.tr_host.as<swk::TracePair>();
-  int n1 = 0;                        // one-tile pairs first, then the rest
-  std::vector<swk::TracePair> single, multi;   // one-tile pairs with m > 160; longer ones
-  int carry_rows = 0;
-  for (int k = 0; k < np; ++k) {
-    const int64_t m = B.qoff[B.pq[k] + 1] - B.qoff[B.pq[k]];
-    const int64_t n = B.roff[B.pr[k] + 1] - B.roff[B.pr[k]];
-    if (m == 0 || n == 0) {          // a side with nothing to align: one gap run (or none)
-      // the charged sides' runs; ends where the charged sides are used up,
-      // the smallest (ref_end, query_end) among the free choices
-      const bool qc = mode == SW_MODE_GLOBAL || mode == SW_MODE_SEMIGLOBAL;
-      const bool rc_ = mode == SW_MODE_GLOBAL || mode == SW_MODE_SEMIGLOBAL_REF;
-      const int64_t s = -(qc ? gap(m) : 0) - (rc_ ? gap(n) : 0);
-      out[k].score = (int32_t)s;
-      out[k].query_end = qc ? (int32_t)(m - 1) : -1;
-      out[k].ref_end = rc_ ? (int32_t)(n - 1) : -1;
-      out[k].flags = 0;
-      if (s < INT32_MIN) { set_error("pair %d: score below the int32 range", k); return SW_EOVERFLOW; }
-      continue;
-    }
-    const int64_t lo = 2 * (maxabs + S.go) + (m + n + 2 * swk::kTraceTileCols) * (S.ge + 1);
-    const int64_t hi = std::min(m, n) * (int64_t)S.max_s + (m + swk::kTraceTileCols) * S.ge;
-    if (lo >= (1ll << 27) || hi >= (1ll << 30)) {
-      set_error("pair %d: %lld x %lld leaves the int32 range of the end-to-end kernel", k,
-                (long long)m, (long long)n);
-      return SW_EOVERFLOW;
-    }
-    swk::TracePair tp;
-    tp.q = B.qoff[B.pq[k]];
-    tp.r = B.roff[B.pr[k]];
-    tp.out = 0;
-    tp.A = (int32_t)n;
-    tp.B = (int32_t)m;
-    tp.score = 0;
-    tp.cap = 0;
-    tp.id = k;
-    // query columns per lane: 32 lanes per pair up to 160 columns (two pairs
-    // per wavefront), 64 lanes per pair up to 256, 256-column tiles beyond
-    if (m <= kDualCols) {
-      tp.pad = (int32_t)((m + 31) / 32);
-      htab[n1++] = tp;
-    } else if (m <= swk::kTraceTileCols) {
-      tp.pad = (int32_t)((m + 63) / 64);
-      single.push_back(tp);
-    } else {
-      tp.pad = 4;
-      multi.push_back(tp);
-      carry_rows = std::max(carry_rows, (int)n);
-    }
-  }
-  const int n_one = (int)single.size();
-  if (n_one) std::memcpy(htab + n1, single.data(), (size_t)n_one * sizeof(swk::TracePair));
-  const int nm = (int)multi.size(), nt = n1 + n_one + nm;
-  if (nt == 0) return SW_OK;
-  if (nm) std::memcpy(htab + n1 + n_one, multi.data(), (size_t)nm * sizeof(swk::TracePair));
-  const int64_t per_wave = 4ll * carry_rows * (int64_t)sizeof(int32_t);
-  const int waves_m = nm == 0 ? 0 : (int)std::max<int64_t>(
-      1, std::min<int64_t>({(int64_t)nm, kTraceScratchBytes / std::max<int64_t>(per_wave, 1),
-                            kTraceMaxWaves}));
-  if ((rc = W.tr_pairs.ensure((size_t)nt * sizeof(swk::TracePair))) ||
+  constexpr int NC = swk::kE2eClasses;
+  if ((rc = W.tr_res.ensure((size_t)np * sizeof(swk::DevResult))) ||
+      (rc = W.tr_cls.ensure((size_t)np)) ||
+      (rc = W.tr_blk.ensure((size_t)swk::kTrBlocks * NC * 4)) ||
+      (rc = W.tr_clsmax.ensure(16)) || (rc = W.tr_err.ensure(16)) ||
+      (rc = W.tr_sum.ensure((size_t)(NC + 1) * 8)) ||
+      (rc = W.tr_pairs.ensure((size_t)np * sizeof(swk::TracePair))) ||
       (rc = W.tr_mat.ensure((size_t)S.alpha * S.alpha * sizeof(int32_t))) ||
-      (rc = W.tr_carry[0].ensure((size_t)std::max<int64_t>(per_wave * waves_m, 4))) ||
-      (rc = W.tr_res.ensure((size_t)np * sizeof(swk::DevResult))) ||
-      (rc = W.tr_hres.ensure((size_t)np * sizeof(swk::DevResult))))
+      (rc = W.tr_hsum.ensure((size_t)(NC + 4) * 8)))
     return rc;
-  swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
-  HIPCHK(hipMemcpyAsync(dp, htab, (size_t)nt * sizeof(swk::TracePair), hipMemcpyHostToDevice, W.st));
   HIPCHK(hipMemcpyAsync(W.tr_mat.p, S.M.data(), (size_t)S.alpha * S.alpha * sizeof(int32_t),
                         hipMemcpyHostToDevice, W.st));
-  swk::EndArgs ea;
-  ea.qres = B.d_q;
-  ea.rres = B.d_r;
-  ea.matrix = W.tr_mat.as<int32_t>();
-  ea.alpha = S.alpha;
-  ea.go = S.go;
-  ea.ge = S.ge;
-  ea.gcarry = W.tr_carry[0].as<int32_t>();
-  ea.out = W.tr_res.as<swk::DevResult>();
-  ea.pairs = dp;
-  ea.n = n1;
-  ea.carry_rows = 0;
-  HIPCHK(swk::launch_endtoend2(mode, ea, W.st));   // a workgroup per two pairs
-  ea.pairs = dp + n1;
-  ea.n = n_one;
-  HIPCHK(swk::launch_endtoend(mode, ea, n_one, W.st));   // a workgroup per pair
-  ea.pairs = dp + n1 + n_one;
-  ea.n = nm;
-  ea.carry_rows = carry_rows;
-  HIPCHK(swk::launch_endtoend(mode, ea, waves_m, W.st));
-  swk::DevResult *hres = W.tr_hres.as<swk::DevResult>();
-  HIPCHK(hipMemcpyAsync(hres, W.tr_res.p, (size_t)np * sizeof(swk::DevResult),
-                        hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemsetAsync(W.tr_clsmax.p, 0, 8, W.st));
+  HIPCHK(hipMemsetAsync(W.tr_err.p, 0xff, 8, W.st));
+  // ---- the table: classify (empty sides' results written there), totals,
+  // summary to the host
+  swk::E2ePlanArgs pa;
+  pa.np = np;
+  pa.nq = b->n_queries;
+  pa.nr = b->n_refs;
+  pa.mode = mode;
+  pa.go = S.go;
+  pa.ge = S.ge;
+  pa.max_s = S.max_s;
+  pa.maxabs = (int)std::min<int64_t>(maxabs, INT32_MAX);
+  pa.qoff = din.qoff;
+  pa.roff = din.roff;
+  pa.pq = din.pq;
+  pa.pr = din.pr;
+  pa.out = W.tr_res.as<swk::DevResult>();
+  pa.cls = W.tr_cls.as<uint8_t>();
+  pa.blk_count = W.tr_blk.as<int32_t>();
+  pa.rows_max = W.tr_clsmax.as<unsigned long long>();
+  pa.err = W.tr_err.as<unsigned long long>();
+  pa.summary = W.tr_sum.as<int64_t>();
+  pa.table = W.tr_pairs.as<swk::TracePair>();
+  HIPCHK(swk::launch_e2eplan_classify(pa, W.st));
+  HIPCHK(swk::launch_e2eplan_totals(pa, W.st));
+  int64_t *hs = W.tr_hsum.as<int64_t>();   // [NC + 1] summary, rows, error word
+  HIPCHK(hipMemcpyAsync(hs, W.tr_sum.p, (size_t)(NC + 1) * 8, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemcpyAsync(hs + NC + 1, W.tr_clsmax.p, 8, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemcpyAsync(hs + NC + 2, W.tr_err.p, 8, hipMemcpyDeviceToHost, W.st));
   HIPCHK(hipStreamSynchronize(W.st));
-  for (int t = 0; t < nt; ++t) {
-    const int k = htab[t].id;
-    const swk::DevResult &r = hres[k];
-    if (r.flags & swk::kFlagBadResidue) {
-      set_error("pair %d: a residue code is not below alphabet_size", k);
-      return SW_EINVAL;
-    }
-    out[k].score = r.score;
-    out[k].query_end = r.qend;
-    out[k].ref_end = r.rend;
-    out[k].flags = 0;
+  const uint64_t err1 = (uint64_t)hs[NC + 2];
+  if (err1 != ~0ull) return endtoend_error(b, (int)(err1 >> 8), (int)(err1 & 0xff));
+  const int n1 = (int)(hs[1] - hs[0]), n_one = (int)(hs[2] - hs[1]), nm = (int)(hs[3] - hs[2]);
+  const int carry_rows = (int)hs[NC + 1];
+  if (n1 + n_one + nm > 0) {
+    HIPCHK(swk::launch_e2eplan_scatter(pa, W.st));
+    const int64_t per_wave = 4ll * carry_rows * (int64_t)sizeof(int32_t);
+    const int waves_m = nm == 0 ? 0 : (int)std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)nm, kTraceScratchBytes / std::max<int64_t>(per_wave, 1),
+                              kTraceMaxWaves}));
+    if ((rc = W.tr_carry[0].ensure((size_t)std::max<int64_t>(per_wave * waves_m, 4)))) return rc;
+    swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
+    swk::EndArgs ea;
+    ea.qres = din.q;
+    ea.rres = din.r;
+    ea.matrix = W.tr_mat.as<int32_t>();
+    ea.alpha = S.alpha;
+    ea.go = S.go;
+    ea.ge = S.ge;
+    ea.gcarry = W.tr_carry[0].as<int32_t>();
+    ea.out = W.tr_res.as<swk::DevResult>();
+    ea.pairs = dp;
+    ea.n = n1;
+    ea.carry_rows = 0;
+    HIPCHK(swk::launch_endtoend2(mode, ea, W.st));   // a workgroup per two pairs
+    ea.pairs = dp + n1;
+    ea.n = n_one;
+    HIPCHK(swk::launch_endtoend(mode, ea, n_one, W.st));   // a workgroup per pair
+    ea.pairs = dp + n1 + n_one;
+    ea.n = nm;
+    ea.carry_rows = carry_rows;
+    HIPCHK(swk::launch_endtoend(mode, ea, waves_m, W.st));
+    HIPCHK(swk::launch_e2e_check(W.tr_res.as<swk::DevResult>(), np, W.tr_err.as<unsigned long long>(),
+                                 W.st));
   }
+  // every pair's result (a device result has the API's layout; on success
+  // its flags are 0)
+  static_assert(sizeof(swk::DevResult) == sizeof(sw_result), "result layouts differ");
+  HIPCHK(hipMemcpyAsync(hs, W.tr_err.p, 8, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemcpyAsync(out, W.tr_res.p, (size_t)np * sizeof(sw_result), hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipStreamSynchronize(W.st));
+  const uint64_t err2 = (uint64_t)hs[0];
+  if (err2 != ~0ull) return endtoend_error(b, (int)(err2 >> 8), (int)(err2 & 0xff));
   return SW_OK;
 }

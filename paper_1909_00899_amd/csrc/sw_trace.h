@@ -127,6 +127,34 @@ hipError_t launch_trplan_check(const TracePair *table, int nt, const int32_t *n_
 hipError_t launch_count_scan(const int32_t *counts, int np, int64_t *off, int64_t *bsum,
                              hipStream_t st);
 
+// End-to-end score tables on the device (sw_align_batch_global): each pair
+// checked and put in a class -- couples of queries up to kE2eDualCols
+// residues, one-tile queries, longer ones -- or, with an empty side, its
+// result written at once; workgroup histograms, class starts, the table.
+constexpr int kE2eClasses = 3;
+constexpr int kE2eDualCols = 160;
+enum : int { kE2eErrScore = 12 };   // an empty side's score below the int32 range
+struct E2ePlanArgs {
+  int np, nq, nr, mode, go, ge, max_s, maxabs;   // mode: the API's (0-3)
+  const int64_t *qoff, *roff;                    // device
+  const int32_t *pq, *pr;                        // device; pq may be null (query 0)
+  DevResult *out;                                // per pair; empty sides written here
+  uint8_t *cls;                                  // per pair: its class or 0xff
+  int32_t *blk_count;                            // [kTrBlocks][kE2eClasses]
+  unsigned long long *rows_max;                  // most rows of a longer-query pair
+  unsigned long long *err;                       // error word (initialised to ~0)
+  int64_t *summary;                              // [kE2eClasses + 1]: class starts, entries
+  TracePair *table;
+};
+// classify + histograms; totals; scatter (the host reads the summary and the
+// error word between totals and scatter)
+hipError_t launch_e2eplan_classify(const E2ePlanArgs &a, hipStream_t st);
+hipError_t launch_e2eplan_totals(const E2ePlanArgs &a, hipStream_t st);
+hipError_t launch_e2eplan_scatter(const E2ePlanArgs &a, hipStream_t st);
+// after the kernels: the first pair whose result has kFlagBadResidue
+hipError_t launch_e2e_check(const DevResult *res, int np, unsigned long long *err,
+                            hipStream_t st);
+
 struct TraceArgs {
   const TracePair *pairs;
   int n;

@@ -1,5 +1,6 @@
 // Path tables on the device (include/sw.h, sw_align_batch_cigar and
-// sw_align_batch_global_cigar): each pair's rectangle, its kernel variant and
+// sw_align_batch_global_cigar), and the end-to-end score tables
+// (sw_align_batch_global) at the end: each pair's rectangle, its kernel variant and
 // size class, the planner-made runs of end-to-end alignments with an empty
 // side, the table ordered by class with a run region per entry, and after the
 // path kernels the run-count check and the prefix sum of the counts.  The
@@ -23,8 +24,11 @@ __device__ __forceinline__ void set_err(unsigned long long *err, int k, int code
   atomicMin(err, ((unsigned long long)(unsigned)k << 8) | (unsigned)code);
 }
 
+__device__ __forceinline__ int64_t gap_cost(int go, int ge, int64_t L) {
+  return L <= 0 ? 0 : go + (L - 1) * (int64_t)ge;
+}
 __device__ __forceinline__ int64_t gap_cost(const TrPlanArgs &a, int64_t L) {
-  return L <= 0 ? 0 : a.go + (L - 1) * (int64_t)a.ge;
+  return gap_cost(a.go, a.ge, L);
 }
 
 // Pair k's class (or kSkip) and rectangle, or a negative error code.  The
@@ -336,8 +340,165 @@ __global__ __launch_bounds__(kThreads) void scan_write_kernel(const int32_t *cou
   if (blockIdx.x == 0 && threadIdx.x == 0) off[0] = 0;
 }
 
+// ---------------------------------------------------------------- end-to-end score tables
+
+constexpr int kE2eMulti = 2;
+
+// Pair k's class (0 couples, 1 one tile, 2 longer; kSkip with an empty side,
+// whose result is written here) and table entry, or a negative error code.
+// The rules are the API's (include/sw.h, sw_align_batch_global).
+__device__ int e2e_classify(const E2ePlanArgs &a, int k, TracePair &tp) {
+  const int q = a.pq ? a.pq[k] : 0, r = a.pr[k];
+  if (q < 0 || q >= a.nq || r < 0 || r >= a.nr) return -kTrErrPair;
+  const int64_t q0 = a.qoff[q], q1 = a.qoff[q + 1], r0 = a.roff[r], r1 = a.roff[r + 1];
+  if (q0 < 0 || q1 < q0 || q1 > a.qoff[a.nq]) return -kTrErrQoff;
+  if (r0 < 0 || r1 < r0 || r1 > a.roff[a.nr]) return -kTrErrRoff;
+  const int64_t m = q1 - q0, n = r1 - r0;
+  if (m == 0 || n == 0) {
+    // one gap run per charged side (or none); the ends where the charged
+    // sides are used up
+    const bool qc = a.mode == 0 || a.mode == 1, rc = a.mode == 0 || a.mode == 2;
+    const int64_t s = -(qc ? gap_cost(a.go, a.ge, m) : 0) - (rc ? gap_cost(a.go, a.ge, n) : 0);
+    if (s < INT32_MIN) return -kE2eErrScore;
+    DevResult res;
+    res.score = (int32_t)s;
+    res.qend = qc ? (int32_t)(m - 1) : -1;
+    res.rend = rc ? (int32_t)(n - 1) : -1;
+    res.flags = 0;
+    a.out[k] = res;
+    return kSkip;
+  }
+  // the 32-bit range of the end-to-end kernels (their unreachable values
+  // near -2^30 stay below every reachable one)
+  const int64_t lo = 2 * ((int64_t)a.maxabs + a.go) + (m + n + 2 * kTraceTileCols) * (a.ge + 1);
+  const int64_t hi = (m < n ? m : n) * (int64_t)a.max_s + (m + kTraceTileCols) * a.ge;
+  if (lo >= (1ll << 27) || hi >= (1ll << 30)) return -kTrErrRange;
+  tp.q = q0;
+  tp.r = r0;
+  tp.out = 0;
+  tp.A = (int32_t)n;
+  tp.B = (int32_t)m;
+  tp.score = 0;
+  tp.cap = 0;
+  tp.id = k;
+  // query columns per lane: 32 lanes per pair up to kE2eDualCols columns
+  // (two pairs per wavefront), 64 lanes up to one tile, tiles beyond
+  if (m <= kE2eDualCols) {
+    tp.pad = (int32_t)((m + 31) / 32);
+    return 0;
+  }
+  if (m <= kTraceTileCols) {
+    tp.pad = (int32_t)((m + 63) / 64);
+    return 1;
+  }
+  tp.pad = 4;
+  return kE2eMulti;
+}
+
+__global__ __launch_bounds__(kThreads) void e2eplan_classify_kernel(E2ePlanArgs a) {
+  __shared__ int cnt[kE2eClasses];
+  __shared__ unsigned long long rows;
+  if (threadIdx.x < kE2eClasses) cnt[threadIdx.x] = 0;
+  if (threadIdx.x == 0) rows = 0;
+  __syncthreads();
+  int lo, hi;
+  block_range(a.np, blockIdx.x, gridDim.x, lo, hi);
+  for (int k = lo + threadIdx.x; k < hi; k += kThreads) {
+    TracePair tp;
+    const int c = e2e_classify(a, k, tp);
+    if (c < 0) {
+      set_err(a.err, k, -c);
+      a.cls[k] = kSkip;
+      continue;
+    }
+    a.cls[k] = (uint8_t)c;
+    if (c == kSkip) continue;
+    atomicAdd(&cnt[c], 1);
+    if (c == kE2eMulti) atomicMax(&rows, (unsigned long long)tp.A);
+  }
+  __syncthreads();
+  if (threadIdx.x < kE2eClasses)
+    a.blk_count[(size_t)blockIdx.x * kE2eClasses + threadIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x == 0 && rows) atomicMax(a.rows_max, rows);
+}
+
+// One workgroup: per class the workgroups' first table positions, and the
+// class starts.
+__global__ __launch_bounds__(kThreads) void e2eplan_totals_kernel(E2ePlanArgs a) {
+  __shared__ int64_t total[kE2eClasses];
+  const int c = threadIdx.x;
+  if (c < kE2eClasses) {
+    int64_t run = 0;
+    for (int b = 0; b < kTrBlocks; ++b) {
+      const int v = a.blk_count[(size_t)b * kE2eClasses + c];
+      a.blk_count[(size_t)b * kE2eClasses + c] = (int)run;
+      run += v;
+    }
+    total[c] = run;
+  }
+  __syncthreads();
+  if (c == 0) {
+    int64_t s = 0;
+    for (int k = 0; k < kE2eClasses; ++k) {
+      a.summary[k] = s;
+      s += total[k];
+    }
+    a.summary[kE2eClasses] = s;
+  }
+  __syncthreads();
+  if (c < kE2eClasses)
+    for (int b = 0; b < kTrBlocks; ++b) a.blk_count[(size_t)b * kE2eClasses + c] += (int)a.summary[c];
+}
+
+// Each workgroup places its pairs (the classify ranges) with LDS cursors;
+// order inside a class is free.
+__global__ __launch_bounds__(kThreads) void e2eplan_scatter_kernel(E2ePlanArgs a) {
+  __shared__ int cur[kE2eClasses];
+  if (threadIdx.x < kE2eClasses)
+    cur[threadIdx.x] = a.blk_count[(size_t)blockIdx.x * kE2eClasses + threadIdx.x];
+  __syncthreads();
+  int lo, hi;
+  block_range(a.np, blockIdx.x, gridDim.x, lo, hi);
+  for (int k = lo + threadIdx.x; k < hi; k += kThreads) {
+    const int c = a.cls[k];
+    if (c == kSkip) continue;
+    TracePair tp;
+    (void)e2e_classify(a, k, tp);   // a non-empty pair: only the entry is rebuilt
+    a.table[atomicAdd(&cur[c], 1)] = tp;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void e2e_check_kernel(const DevResult *res, int np,
+                                                             unsigned long long *err) {
+  for (int k = blockIdx.x * kThreads + threadIdx.x; k < np; k += gridDim.x * kThreads)
+    if (res[k].flags & kFlagBadResidue) set_err(err, k, kTrErrResidue);
+}
+
 }  // namespace
 }  // namespace dev
+
+hipError_t launch_e2eplan_classify(const E2ePlanArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(dev::e2eplan_classify_kernel, dim3(kTrBlocks), dim3(dev::kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_e2eplan_totals(const E2ePlanArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(dev::e2eplan_totals_kernel, dim3(1), dim3(dev::kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_e2eplan_scatter(const E2ePlanArgs &a, hipStream_t st) {
+  hipLaunchKernelGGL(dev::e2eplan_scatter_kernel, dim3(kTrBlocks), dim3(dev::kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_e2e_check(const DevResult *res, int np, unsigned long long *err,
+                            hipStream_t st) {
+  if (np <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(((int64_t)np + dev::kThreads - 1) / dev::kThreads, 4096);
+  hipLaunchKernelGGL(dev::e2e_check_kernel, dim3(grid), dim3(dev::kThreads), 0, st, res, np, err);
+  return hipGetLastError();
+}
 
 hipError_t launch_trplan_classify(const TrPlanArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(dev::trplan_classify_kernel, dim3(kTrBlocks), dim3(dev::kThreads), 0, st, a);
