@@ -881,9 +881,10 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
   HIPCHK(hipStreamSynchronize(W.st));
   const uint64_t err1 = (uint64_t)hs[NC + 2];
   if (err1 != ~0ull) return endtoend_error(b, (int)(err1 >> 8), (int)(err1 & 0xff));
-  const int n1 = (int)(hs[1] - hs[0]), n_one = (int)(hs[2] - hs[1]), nm = (int)(hs[3] - hs[2]);
+  const int n1 = (int)(hs[1] - hs[0]), n_one = (int)(hs[2] - hs[1]), nw = (int)(hs[3] - hs[2]);
+  const int nm = (int)(hs[4] - hs[3]);
   const int carry_rows = (int)hs[NC + 1];
-  if (n1 + n_one + nm > 0) {
+  if (n1 + n_one + nw + nm > 0) {
     HIPCHK(swk::launch_e2eplan_scatter(pa, W.st));
     const int64_t per_wave = 4ll * carry_rows * (int64_t)sizeof(int32_t);
     const int waves_m = nm == 0 ? 0 : (int)std::max<int64_t>(
@@ -906,11 +907,14 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
     HIPCHK(swk::launch_endtoend2(mode, ea, W.st));   // a workgroup per two pairs
     ea.pairs = dp + n1;
     ea.n = n_one;
-    HIPCHK(swk::launch_endtoend(mode, ea, n_one, W.st));   // a workgroup per pair
+    HIPCHK(swk::launch_endtoend(mode, ea, n_one, W.st));        // a workgroup per pair
     ea.pairs = dp + n1 + n_one;
+    ea.n = nw;
+    HIPCHK(swk::launch_endtoend_wide(mode, ea, nw, W.st));      // a workgroup per pair
+    ea.pairs = dp + n1 + n_one + nw;
     ea.n = nm;
     ea.carry_rows = carry_rows;
-    HIPCHK(swk::launch_endtoend(mode, ea, waves_m, W.st));
+    HIPCHK(swk::launch_endtoend_wide(mode, ea, waves_m, W.st)); // carries between tiles
     HIPCHK(swk::launch_e2e_check(W.tr_res.as<swk::DevResult>(), np, W.tr_err.as<unsigned long long>(),
                                  W.st));
   }

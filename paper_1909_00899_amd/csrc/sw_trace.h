@@ -129,10 +129,12 @@ hipError_t launch_count_scan(const int32_t *counts, int np, int64_t *off, int64_
 
 // End-to-end score tables on the device (sw_align_batch_global): each pair
 // checked and put in a class -- couples of queries up to kE2eDualCols
-// residues, one-tile queries, longer ones -- or, with an empty side, its
+// residues, queries of one 256-column tile, of one kE2eWideCols tile, longer
+// ones in tiles of kE2eWideCols -- or, with an empty side, its
 // result written at once; workgroup histograms, class starts, the table.
-constexpr int kE2eClasses = 3;
+constexpr int kE2eClasses = 4;        // couples, one 256 tile, one 512 tile, 512 tiles
 constexpr int kE2eDualCols = 160;
+constexpr int kE2eWideCols = 512;
 enum : int { kE2eErrScore = 12 };   // an empty side's score below the int32 range
 struct E2ePlanArgs {
   int np, nq, nr, mode, go, ge, max_s, maxabs;   // mode: the API's (0-3)
@@ -197,6 +199,8 @@ size_t endtoend_lds_bytes(int alpha);
 hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st);
 // Pairs with m <= 160, two per wavefront; pad = ceil(m / 32).
 hipError_t launch_endtoend2(int mode, const EndArgs &a, hipStream_t st);
+// Pairs with m > 256: pad = 5-8 query columns per lane (tiles of 64 pad).
+hipError_t launch_endtoend_wide(int mode, const EndArgs &a, int grid, hipStream_t st);
 
 // Runs of every pair (n_runs[id] of them, ending at out + cap) to
 // dst[dst_off[id] ..]; every count must be <= its pair's cap.

@@ -949,6 +949,26 @@ __global__ __launch_bounds__(64) void endtoend_kernel(EndArgs a) {
   }
 }
 
+// endtoend_kernel for queries beyond 256 residues: 5-8 columns per lane, one
+// tile up to 512 residues, tiles of 512 beyond (a kernel of its own, so that
+// the wider lanes' registers do not lower the narrow kernel's occupancy).
+template <int MODE>
+__global__ __launch_bounds__(64) void endtoend_wide_kernel(EndArgs a) {
+  extern __shared__ int smem[];
+  int *smat = smem;
+  for (int k = threadIdx.x; k < a.alpha * a.alpha; k += 64) smat[k] = a.matrix[k];
+  __syncthreads();
+  for (int p = blockIdx.x; p < a.n; p += gridDim.x) {
+    const TracePair P = a.pairs[p];
+    switch (P.pad) {   // query columns per lane
+      case 5: endtoend_one<MODE, 5>(a, P, smat); break;
+      case 6: endtoend_one<MODE, 6>(a, P, smat); break;
+      case 7: endtoend_one<MODE, 7>(a, P, smat); break;
+      default: endtoend_one<MODE, 8>(a, P, smat); break;
+    }
+  }
+}
+
 // Pair t's runs (the last n_runs[id] entries of its region) to
 // cigar_dst[dst_off[id] ..]; a workgroup per pair, grid-stride.
 __global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, int n,
@@ -997,6 +1017,19 @@ hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st)
     case 1: hipLaunchKernelGGL(dev::endtoend_kernel<1>, dim3(grid), dim3(64), lds, st, a); break;
     case 2: hipLaunchKernelGGL(dev::endtoend_kernel<2>, dim3(grid), dim3(64), lds, st, a); break;
     case 3: hipLaunchKernelGGL(dev::endtoend_kernel<3>, dim3(grid), dim3(64), lds, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_endtoend_wide(int mode, const EndArgs &a, int grid, hipStream_t st) {
+  if (a.n <= 0 || grid <= 0) return hipSuccess;
+  const size_t lds = endtoend_lds_bytes(a.alpha);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(dev::endtoend_wide_kernel<0>, dim3(grid), dim3(64), lds, st, a); break;
+    case 1: hipLaunchKernelGGL(dev::endtoend_wide_kernel<1>, dim3(grid), dim3(64), lds, st, a); break;
+    case 2: hipLaunchKernelGGL(dev::endtoend_wide_kernel<2>, dim3(grid), dim3(64), lds, st, a); break;
+    case 3: hipLaunchKernelGGL(dev::endtoend_wide_kernel<3>, dim3(grid), dim3(64), lds, st, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

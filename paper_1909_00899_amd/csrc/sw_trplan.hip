@@ -342,9 +342,10 @@ __global__ __launch_bounds__(kThreads) void scan_write_kernel(const int32_t *cou
 
 // ---------------------------------------------------------------- end-to-end score tables
 
-constexpr int kE2eMulti = 2;
+constexpr int kE2eMulti = 3;
 
-// Pair k's class (0 couples, 1 one tile, 2 longer; kSkip with an empty side,
+// Pair k's class (0 couples, 1 one 256 tile, 2 one 512 tile, 3 longer; kSkip
+// with an empty side,
 // whose result is written here) and table entry, or a negative error code.
 // The rules are the API's (include/sw.h, sw_align_batch_global).
 __device__ int e2e_classify(const E2ePlanArgs &a, int k, TracePair &tp) {
@@ -369,9 +370,10 @@ __device__ int e2e_classify(const E2ePlanArgs &a, int k, TracePair &tp) {
     return kSkip;
   }
   // the 32-bit range of the end-to-end kernels (their unreachable values
-  // near -2^30 stay below every reachable one)
-  const int64_t lo = 2 * ((int64_t)a.maxabs + a.go) + (m + n + 2 * kTraceTileCols) * (a.ge + 1);
-  const int64_t hi = (m < n ? m : n) * (int64_t)a.max_s + (m + kTraceTileCols) * a.ge;
+  // near -2^30 stay below every reachable one; a tile's padding columns
+  // carry scan terms too)
+  const int64_t lo = 2 * ((int64_t)a.maxabs + a.go) + (m + n + 2 * kE2eWideCols) * (a.ge + 1);
+  const int64_t hi = (m < n ? m : n) * (int64_t)a.max_s + (m + kE2eWideCols) * a.ge;
   if (lo >= (1ll << 27) || hi >= (1ll << 30)) return -kTrErrRange;
   tp.q = q0;
   tp.r = r0;
@@ -382,16 +384,17 @@ __device__ int e2e_classify(const E2ePlanArgs &a, int k, TracePair &tp) {
   tp.cap = 0;
   tp.id = k;
   // query columns per lane: 32 lanes per pair up to kE2eDualCols columns
-  // (two pairs per wavefront), 64 lanes up to one tile, tiles beyond
+  // (two pairs per wavefront), 64 lanes up to one tile of 256 or of
+  // kE2eWideCols, tiles of kE2eWideCols beyond
   if (m <= kE2eDualCols) {
     tp.pad = (int32_t)((m + 31) / 32);
     return 0;
   }
-  if (m <= kTraceTileCols) {
+  if (m <= kE2eWideCols) {
     tp.pad = (int32_t)((m + 63) / 64);
-    return 1;
+    return m <= kTraceTileCols ? 1 : 2;
   }
-  tp.pad = 4;
+  tp.pad = kE2eWideCols / 64;
   return kE2eMulti;
 }
 
