@@ -95,3 +95,41 @@ def test_budget_admission_and_errors(db):
         q = np.array([0, 1, 2], dtype=np.uint8)
         r = db.ref_res[db.ref_off[0]:db.ref_off[1]]
         assert tuple(srv.poll(t)[:3]) == tuple(oracle.align(q, r, *_scorings()[0]))
+
+
+def test_replay_backlog_fifo_per_class_and_exact(db):
+    # every request offered at once with small batches: a deep backlog in
+    # every class.  Each class (scoring, and whether the request is long: a
+    # query over 1024 residues or over 2^20 cells) is admitted in arrival
+    # order, and every result equals the offline batch call's; a sample is
+    # checked against the oracle as well
+    reqs = W.serving_requests(db, rate_per_s=1e9, n_requests=1500, seed=43, dna_len=(100, 3000))
+    sid = reqs.is_dna.astype(np.int32)
+    with api.Server(db.ref_res, db.ref_off, _scorings(), n_streams=4, max_batch=48) as srv:
+        out, ts = srv.replay(reqs.query_res, reqs.query_off, reqs.ref_id, sid, reqs.arrival_s)
+    m = np.diff(reqs.query_off)
+    n = np.diff(db.ref_off)[reqs.ref_id]
+    cls = 2 * sid + ((m > 1024) | (m * n > (1 << 20)))
+    assert len(np.unique(cls)) == 4
+    for c in np.unique(cls):
+        assert (np.diff(ts[cls == c, 1]) >= 0).all()
+    for dna in (False, True):
+        # one family's queries and references (the batch call checks every
+        # residue it is given)
+        sel = np.nonzero(reqs.is_dna == dna)[0]
+        qs = [reqs.query_res[reqs.query_off[k]:reqs.query_off[k + 1]] for k in sel]
+        qoff = np.zeros(sel.size + 1, dtype=np.int64)
+        np.cumsum([q.size for q in qs], out=qoff[1:])
+        r0, r1 = (db.n_protein, db.n_protein + db.n_dna) if dna else (0, db.n_protein)
+        rres = db.ref_res[db.ref_off[r0]:db.ref_off[r1]]
+        roff = db.ref_off[r0:r1 + 1] - db.ref_off[r0]
+        M, go, ge = _scorings()[1 if dna else 0]
+        got = api.sw_align_batch(np.concatenate(qs), qoff, rres, roff,
+                                 (reqs.ref_id[sel] - r0).astype(np.int32), M, go, ge,
+                                 pair_query=np.arange(sel.size, dtype=np.int32))
+        assert (out[sel, :3] == got.results[:, :3]).all()
+    for k in range(0, 1500, 75):
+        q = reqs.query_res[reqs.query_off[k]:reqs.query_off[k + 1]]
+        r = db.ref_res[db.ref_off[reqs.ref_id[k]]:db.ref_off[reqs.ref_id[k] + 1]]
+        M, go, ge = _scorings()[1 if reqs.is_dna[k] else 0]
+        assert tuple(out[k, :3]) == tuple(oracle.align(q, r, M, go, ge))
