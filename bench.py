@@ -636,7 +636,7 @@ def _serving_sweep(api, W, rates, n_of_rate):
     scor = [(W.protein_matrix(), 11, 1), (W.dna_matrix(), 6, 1)]
     rows = []
     with api.Server(db.ref_res, db.ref_off, scor, hbm_budget_bytes=8 << 30, n_streams=4,
-                    max_batch=4096) as srv:
+                    max_batch=16384) as srv:
         for rate in rates:
             n = n_of_rate(rate)
             req = W.serving_requests(db, rate, n, seed=rate)

@@ -545,8 +545,8 @@ typedef struct {
     int32_t n_db;
     const sw_scoring *scorings;     /* n_scorings schemes (copied)                 */
     int32_t n_scorings;
-    int32_t max_batch;              /* requests per launch (0 = library default)   */
-    int32_t n_streams;              /* concurrent launches (0 = library default)   */
+    int32_t max_batch;              /* requests per batch (0 = 16384)              */
+    int32_t n_streams;              /* worker threads and streams (0 = 4)          */
     int32_t reserved[6];
 } sw_server_config;
 

@@ -246,7 +246,7 @@ int sw_server_create(const sw_server_config *cfg, sw_server **out) {
   s->num_cus = g_ctx.num_cus;
   s->budget = cfg->hbm_budget_bytes ? cfg->hbm_budget_bytes : ((size_t)1 << 32);
   s->max_queued = cfg->max_queued ? cfg->max_queued : 1 << 20;
-  s->max_batch = cfg->max_batch ? cfg->max_batch : 4096;
+  s->max_batch = cfg->max_batch ? cfg->max_batch : 16384;
   const int nst = cfg->n_streams ? cfg->n_streams : 4;
   for (int k = 0; k < cfg->n_scorings; ++k) {
     Scoring sc;
