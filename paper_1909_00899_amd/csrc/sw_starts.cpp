@@ -60,6 +60,15 @@ struct StartsWork {
   // paths
   DevBuf tr_pairs, tr_mat, tr_runs, tr_packed, tr_nruns, tr_off;
   HostBuf ld_stage;              // pinned: a device-resident batch's offsets and indices
+  // pinned staging of the caller's pageable arrays (see stage_up / stage_down)
+  struct Pending {
+    void *dst;
+    const void *src;
+    size_t bytes;
+  };
+  HostBuf up_stage, dn_stage;
+  size_t up_used = 0, dn_used = 0;
+  std::vector<Pending> dn_pending;
   DevBuf tr_res;                 // end-to-end results
   DevBuf tr_rstart;              // end-to-end paths: reference starts
   DevBuf tr_qstart;              // end-to-end paths: query starts
@@ -78,6 +87,83 @@ struct StartsWork {
   DevBuf tr_bits[kTraceStreams], tr_carry[kTraceStreams];
 };
 StartsWork g_starts;
+
+// Transfers between the caller's pageable host arrays and the device go
+// through pinned staging memory: the host side copies on several threads and
+// the DMA runs at the bus rate (the runtime's path for pageable memory stages
+// chunk by chunk with one thread copying in between: about 7.5 GB/s).  The
+// regions a call stages do not overlap; a staging buffer grows only after the
+// stream has drained.  Transfers below kStageMin go directly.
+constexpr size_t kStageMin = 1 << 20;
+
+size_t stage_round(size_t bytes) { return (bytes + 255) & ~(size_t)255; }
+
+void host_copy(void *dst, const void *src, size_t bytes) {
+  constexpr size_t kPerThread = 4u << 20;
+  const int T = (int)std::min<size_t>((size_t)host_threads(), (bytes + kPerThread - 1) / kPerThread);
+  if (T <= 1) {
+    std::memcpy(dst, src, bytes);
+    return;
+  }
+  parallel_ranges(bytes, T, [&](int, size_t lo, size_t hi) {
+    std::memcpy((char *)dst + lo, (const char *)src + lo, hi - lo);
+  });
+}
+
+// A call's staging starts empty (earlier calls' copies have finished).
+int stage_begin(StartsWork &W) {
+  HIPCHK(hipStreamSynchronize(W.st));
+  W.up_used = W.dn_used = 0;
+  W.dn_pending.clear();
+  return SW_OK;
+}
+
+int stage_up(StartsWork &W, void *dst, const void *src, size_t bytes) {
+  if (bytes < kStageMin) {
+    if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, W.st));
+    return SW_OK;
+  }
+  if (W.up_used + stage_round(bytes) > W.up_stage.cap) {
+    const size_t need = W.up_used + stage_round(bytes);
+    HIPCHK(hipStreamSynchronize(W.st));   // the regions staged so far are consumed
+    const int rc = W.up_stage.ensure(need);
+    if (rc) return rc;
+    W.up_used = 0;
+  }
+  char *p = W.up_stage.as<char>() + W.up_used;
+  host_copy(p, src, bytes);
+  HIPCHK(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, W.st));
+  W.up_used += stage_round(bytes);
+  return SW_OK;
+}
+
+// The staged downloads to their destinations, once the stream has drained.
+void stage_complete(StartsWork &W) {
+  for (const auto &x : W.dn_pending) host_copy(x.dst, x.src, x.bytes);
+  W.dn_pending.clear();
+  W.dn_used = 0;
+}
+
+// Queues a download; dst holds the data after the stream is synchronised and
+// stage_complete has run.
+int stage_down(StartsWork &W, void *dst, const void *src, size_t bytes) {
+  if (bytes < kStageMin) {
+    if (bytes) HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, W.st));
+    return SW_OK;
+  }
+  if (W.dn_used + stage_round(bytes) > W.dn_stage.cap) {
+    const size_t need = W.dn_used + stage_round(bytes);
+    HIPCHK(hipStreamSynchronize(W.st));
+    stage_complete(W);                    // the pending ones leave the old buffer first
+    const int rc = W.dn_stage.ensure(need);
+    if (rc) return rc;
+  }
+  char *p = W.dn_stage.as<char>() + W.dn_used;
+  HIPCHK(hipMemcpyAsync(p, src, bytes, hipMemcpyDeviceToHost, W.st));
+  W.dn_pending.push_back({dst, p, bytes});
+  W.dn_used += stage_round(bytes);
+  return SW_OK;
+}
 
 
 // What every path needs: the batch's offsets and ids on the host, its residues
@@ -251,6 +337,10 @@ int load_batch(const sw_batch *b, StartsWork &W, Batch &B) {
   const int np = b->n_pairs;
   HIPCHK(hipSetDevice(g_ctx.device));
   if (!W.st) HIPCHK(hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking));
+  {
+    const int rc0 = stage_begin(W);
+    if (rc0) return rc0;
+  }
   const bool dev = b->device_resident != 0;
   if (dev && b->stream) {
     // the caller's stream produced the inputs
@@ -323,8 +413,8 @@ int load_batch(const sw_batch *b, StartsWork &W, Batch &B) {
     const size_t qb = (size_t)B.qoff[b->n_queries], rb = (size_t)B.roff[b->n_refs];
     int rc;
     if ((rc = W.src_q.ensure(qb + 1)) || (rc = W.src_r.ensure(rb + 1))) return rc;
-    if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, qb, hipMemcpyHostToDevice, W.st));
-    if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, rb, hipMemcpyHostToDevice, W.st));
+    if ((rc = stage_up(W, W.src_q.p, b->query_res, qb)) || (rc = stage_up(W, W.src_r.p, b->ref_res, rb)))
+      return rc;
     B.d_q = W.src_q.as<uint8_t>();
     B.d_r = W.src_r.as<uint8_t>();
   }
@@ -534,13 +624,13 @@ int device_inputs(const sw_batch *b, StartsWork &W, DevInputs &d) {
       (rc = W.tr_pr.ensure((size_t)np * 4)) || (rc = W.tr_pq.ensure((size_t)np * 4)) ||
       (rc = W.src_q.ensure((size_t)qb + 1)) || (rc = W.src_r.ensure((size_t)rb + 1)))
     return rc;
-  HIPCHK(hipMemcpyAsync(W.tr_qoff.p, b->query_off, (size_t)(nq + 1) * 8, hipMemcpyHostToDevice, W.st));
-  HIPCHK(hipMemcpyAsync(W.tr_roff.p, b->ref_off, (size_t)(nr + 1) * 8, hipMemcpyHostToDevice, W.st));
-  HIPCHK(hipMemcpyAsync(W.tr_pr.p, b->pair_ref, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
-  if (b->pair_query)
-    HIPCHK(hipMemcpyAsync(W.tr_pq.p, b->pair_query, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
-  if (qb) HIPCHK(hipMemcpyAsync(W.src_q.p, b->query_res, (size_t)qb, hipMemcpyHostToDevice, W.st));
-  if (rb) HIPCHK(hipMemcpyAsync(W.src_r.p, b->ref_res, (size_t)rb, hipMemcpyHostToDevice, W.st));
+  if ((rc = stage_up(W, W.tr_qoff.p, b->query_off, (size_t)(nq + 1) * 8)) ||
+      (rc = stage_up(W, W.tr_roff.p, b->ref_off, (size_t)(nr + 1) * 8)) ||
+      (rc = stage_up(W, W.tr_pr.p, b->pair_ref, (size_t)np * 4)) ||
+      (b->pair_query && (rc = stage_up(W, W.tr_pq.p, b->pair_query, (size_t)np * 4))) ||
+      (rc = stage_up(W, W.src_q.p, b->query_res, (size_t)qb)) ||
+      (rc = stage_up(W, W.src_r.p, b->ref_res, (size_t)rb)))
+    return rc;
   d.qoff = W.tr_qoff.as<int64_t>();
   d.roff = W.tr_roff.as<int64_t>();
   d.pr = W.tr_pr.as<int32_t>();
@@ -572,6 +662,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
   StartsWork &W = g_starts;
   HIPCHK(hipSetDevice(g_ctx.device));
   if (!W.st) HIPCHK(hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking));
+  if ((rc = stage_begin(W))) return rc;
   DevInputs din;
   if ((rc = device_inputs(b, W, din))) return rc;
   const int64_t nq = b->n_queries, nr = b->n_refs;
@@ -595,11 +686,10 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
       (rc = W.tr_bsum.ensure((size_t)(np / 4096 + 2) * 8)) ||
       (rc = W.tr_hsum.ensure((size_t)(3 * NC + 8) * 8)))
     return rc;
-  HIPCHK(hipMemcpyAsync(W.tr_ends.p, ends, (size_t)np * sizeof(sw_result), hipMemcpyHostToDevice, W.st));
-  if (mode == 0) {
-    HIPCHK(hipMemcpyAsync(W.tr_qs.p, query_start, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
-    HIPCHK(hipMemcpyAsync(W.tr_rs.p, ref_start, (size_t)np * 4, hipMemcpyHostToDevice, W.st));
-  }
+  if ((rc = stage_up(W, W.tr_ends.p, ends, (size_t)np * sizeof(sw_result)))) return rc;
+  if (mode == 0 && ((rc = stage_up(W, W.tr_qs.p, query_start, (size_t)np * 4)) ||
+                    (rc = stage_up(W, W.tr_rs.p, ref_start, (size_t)np * 4))))
+    return rc;
   HIPCHK(hipMemcpyAsync(W.tr_mat.p, S.M.data(), (size_t)S.alpha * S.alpha * sizeof(int32_t),
                         hipMemcpyHostToDevice, W.st));
   HIPCHK(hipMemsetAsync(W.tr_clsmax.p, 0, (size_t)NC * 16, W.st));
@@ -730,9 +820,9 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
   HIPCHK(swk::launch_count_scan(W.tr_nruns.as<int32_t>(), np, W.tr_off.as<int64_t>(),
                                 W.tr_bsum.as<int64_t>(), W.st));
   HIPCHK(hipMemcpyAsync(hs, W.tr_err.p, 8, hipMemcpyDeviceToHost, W.st));
-  HIPCHK(hipMemcpyAsync(cigar_off, W.tr_off.p, (size_t)(np + 1) * sizeof(int64_t),
-                        hipMemcpyDeviceToHost, W.st));
+  if ((rc = stage_down(W, cigar_off, W.tr_off.p, (size_t)(np + 1) * sizeof(int64_t)))) return rc;
   HIPCHK(hipStreamSynchronize(W.st));
+  stage_complete(W);
   const uint64_t err2 = (uint64_t)hs[0];
   if (err2 != ~0ull) {
     cigar_off[0] = 0;
@@ -747,14 +837,13 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     if ((rc = W.tr_packed.ensure((size_t)total * sizeof(uint32_t)))) return rc;
     HIPCHK(swk::launch_pack_runs(dp, nt, W.tr_nruns.as<int32_t>(), W.tr_off.as<int64_t>(),
                                  W.tr_runs.as<uint32_t>(), W.tr_packed.as<uint32_t>(), W.st));
-    HIPCHK(hipMemcpyAsync(cigar, W.tr_packed.p, (size_t)total * sizeof(uint32_t),
-                          hipMemcpyDeviceToHost, W.st));
+    if ((rc = stage_down(W, cigar, W.tr_packed.p, (size_t)total * sizeof(uint32_t)))) return rc;
   }
-  if (mode != 0) {
-    HIPCHK(hipMemcpyAsync(ref_start_out, W.tr_rstart.p, (size_t)np * 4, hipMemcpyDeviceToHost, W.st));
-    HIPCHK(hipMemcpyAsync(query_start_out, W.tr_qstart.p, (size_t)np * 4, hipMemcpyDeviceToHost, W.st));
-  }
+  if (mode != 0 && ((rc = stage_down(W, ref_start_out, W.tr_rstart.p, (size_t)np * 4)) ||
+                    (rc = stage_down(W, query_start_out, W.tr_qstart.p, (size_t)np * 4))))
+    return rc;
   HIPCHK(hipStreamSynchronize(W.st));
+  stage_complete(W);
   return SW_OK;
 }
 }  // namespace
@@ -832,6 +921,7 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
   StartsWork &W = g_starts;
   HIPCHK(hipSetDevice(g_ctx.device));
   if (!W.st) HIPCHK(hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking));
+  if ((rc = stage_begin(W))) return rc;
   DevInputs din;
   if ((rc = device_inputs(b, W, din))) return rc;
   int64_t maxabs = 0;
@@ -922,8 +1012,9 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
   // its flags are 0)
   static_assert(sizeof(swk::DevResult) == sizeof(sw_result), "result layouts differ");
   HIPCHK(hipMemcpyAsync(hs, W.tr_err.p, 8, hipMemcpyDeviceToHost, W.st));
-  HIPCHK(hipMemcpyAsync(out, W.tr_res.p, (size_t)np * sizeof(sw_result), hipMemcpyDeviceToHost, W.st));
+  if ((rc = stage_down(W, out, W.tr_res.p, (size_t)np * sizeof(sw_result)))) return rc;
   HIPCHK(hipStreamSynchronize(W.st));
+  stage_complete(W);
   const uint64_t err2 = (uint64_t)hs[0];
   if (err2 != ~0ull) return endtoend_error(b, (int)(err2 >> 8), (int)(err2 & 0xff));
   return SW_OK;
