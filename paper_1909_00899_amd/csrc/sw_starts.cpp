@@ -67,6 +67,7 @@ struct StartsWork {
     size_t bytes;
   };
   HostBuf up_stage, dn_stage;
+  DevBuf sp_src, sp_dst;         // start cells: reversed prefixes' sources and offsets
   size_t up_used = 0, dn_used = 0;
   std::vector<Pending> dn_pending;
   DevBuf tr_res;                 // end-to-end results
@@ -434,6 +435,11 @@ int check_batch_args(const sw_batch *b) {
 
 }  // namespace
 
+namespace {
+int starts_device(const sw_batch *b, const sw_scoring *sc, StartsWork &W, const sw_result *ends,
+                  int32_t *query_start, int32_t *ref_start, bool &handled);
+}  // namespace
+
 extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
                                      const sw_result *ends, int32_t *query_start,
                                      int32_t *ref_start) {
@@ -447,6 +453,13 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
   if ((rc = ensure_init())) return rc;
   std::lock_guard<std::mutex> g(g_starts.mu);
   StartsWork &W = g_starts;
+  if (b->pair_query && b->n_queries > 1) {
+    // one query per pair: the tables on the device (unless every aligned
+    // pair turns out to share one query: the one-query launch below)
+    bool handled = false;
+    rc = starts_device(b, sc, W, ends, query_start, ref_start, handled);
+    if (handled) return rc;
+  }
   Batch B;
   B.ends = ends;
   if ((rc = load_batch(b, W, B))) return rc;
@@ -870,6 +883,127 @@ extern "C" int sw_align_batch_global_cigar(const sw_batch *b, const sw_scoring *
 }
 
 
+// ------------------------------------------------------------------ start cells, tables on the device
+
+namespace {
+
+// Start cells of a batch with one query per pair: the reversed prefixes'
+// tables built on the device (startplan_kernel, two prefix sums), the
+// prefixes reversed there, one batch call over them (pairs without an
+// alignment become empty pairs).  handled = false leaves the batch to the
+// host-table path (every aligned pair has the same query).
+int starts_device(const sw_batch *b, const sw_scoring *sc, StartsWork &W, const sw_result *ends,
+                  int32_t *query_start, int32_t *ref_start, bool &handled) {
+  handled = true;
+  int rc;
+  const int np = b->n_pairs;
+  HIPCHK(hipSetDevice(g_ctx.device));
+  if (!W.st) HIPCHK(hipStreamCreateWithFlags(&W.st, hipStreamNonBlocking));
+  if ((rc = stage_begin(W))) return rc;
+  DevInputs din;
+  if ((rc = device_inputs(b, W, din))) return rc;
+  if ((rc = W.tr_ends.ensure((size_t)np * sizeof(sw_result))) ||
+      (rc = W.tr_qs.ensure((size_t)np * 4)) || (rc = W.tr_rs.ensure((size_t)np * 4)) ||
+      (rc = W.tr_nruns.ensure((size_t)np * 4)) ||
+      (rc = W.sp_src.ensure((size_t)(np + 1) * 16)) || (rc = W.sp_dst.ensure((size_t)(np + 1) * 16)) ||
+      (rc = W.tr_bsum.ensure((size_t)(np / 4096 + 2) * 8)) || (rc = W.tr_err.ensure(16)) ||
+      (rc = W.tr_hsum.ensure(64)))
+    return rc;
+  if ((rc = stage_up(W, W.tr_ends.p, ends, (size_t)np * sizeof(sw_result)))) return rc;
+  static const int32_t kRangeInit[2] = {INT32_MAX, -1};
+  HIPCHK(hipMemsetAsync(W.tr_err.p, 0xff, 8, W.st));
+  HIPCHK(hipMemcpyAsync((char *)W.tr_err.p + 8, kRangeInit, 8, hipMemcpyHostToDevice, W.st));
+  int64_t *qsrc = W.sp_src.as<int64_t>(), *rsrc = qsrc + (np + 1);
+  int64_t *qdst = W.sp_dst.as<int64_t>(), *rdst = qdst + (np + 1);
+  swk::StartPlanArgs pa;
+  pa.np = np;
+  pa.nq = b->n_queries;
+  pa.nr = b->n_refs;
+  pa.ends = W.tr_ends.as<swk::DevResult>();
+  pa.qoff = din.qoff;
+  pa.roff = din.roff;
+  pa.pq = din.pq;
+  pa.pr = din.pr;
+  pa.qcnt = W.tr_qs.as<int32_t>();
+  pa.rcnt = W.tr_rs.as<int32_t>();
+  pa.ids = W.tr_nruns.as<int32_t>();
+  pa.qsrc = qsrc;
+  pa.rsrc = rsrc;
+  pa.err = W.tr_err.as<unsigned long long>();
+  pa.qrange = (int32_t *)((char *)W.tr_err.p + 8);
+  HIPCHK(swk::launch_startplan(pa, W.st));
+  HIPCHK(swk::launch_count_scan(pa.qcnt, np, qdst, W.tr_bsum.as<int64_t>(), W.st));
+  HIPCHK(swk::launch_count_scan(pa.rcnt, np, rdst, W.tr_bsum.as<int64_t>(), W.st));
+  int64_t *hs = W.tr_hsum.as<int64_t>();   // error word, query range, the two totals
+  HIPCHK(hipMemcpyAsync(hs, W.tr_err.p, 16, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemcpyAsync(hs + 2, qdst + np, 8, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipMemcpyAsync(hs + 3, rdst + np, 8, hipMemcpyDeviceToHost, W.st));
+  HIPCHK(hipStreamSynchronize(W.st));
+  const uint64_t err = (uint64_t)hs[0];
+  if (err != ~0ull) {
+    const int k = (int)(err >> 8), code = (int)(err & 0xff);
+    int64_t m, n;
+    pair_lengths(b, k, m, n);
+    if (code == swk::kSpErrEnd)
+      set_error("pair %d: end cell (%d, %d) outside its %lld x %lld sequences", k, ends[k].query_end,
+                ends[k].ref_end, (long long)m, (long long)n);
+    else if (code == swk::kTrErrPair)
+      set_error("pair %d refers to a query or reference out of range", k);
+    else
+      set_error(code == swk::kTrErrQoff ? "query offsets not nondecreasing"
+                                        : "reference offsets not nondecreasing");
+    return SW_EINVAL;
+  }
+  const int32_t *qr = (const int32_t *)(hs + 1);
+  if (qr[1] >= 0 && qr[0] == qr[1]) {   // one query for every aligned pair
+    handled = false;
+    return SW_OK;
+  }
+  if (qr[1] < 0) {                        // no alignment at all
+    for (int k = 0; k < np; ++k) query_start[k] = ref_start[k] = -1;
+    return SW_OK;
+  }
+  const int64_t qtot = hs[2], rtot = hs[3];
+  if ((rc = W.rev_q.ensure((size_t)qtot + 1)) || (rc = W.rev_r.ensure((size_t)rtot + 1))) return rc;
+  HIPCHK(swk::launch_reverse_segments(np, din.q, qsrc, qdst, W.rev_q.as<uint8_t>(), W.st));
+  HIPCHK(swk::launch_reverse_segments(np, din.r, rsrc, rdst, W.rev_r.as<uint8_t>(), W.st));
+  sw_batch nb;
+  std::memset(&nb, 0, sizeof(nb));
+  nb.n_pairs = np;
+  nb.query_res = W.rev_q.as<uint8_t>();
+  nb.query_off = qdst;
+  nb.n_queries = np;
+  nb.ref_res = W.rev_r.as<uint8_t>();
+  nb.ref_off = rdst;
+  nb.n_refs = np;
+  nb.pair_query = pa.ids;
+  nb.pair_ref = pa.ids;
+  nb.precision = b->precision;
+  nb.device_resident = 1;
+  nb.stream = W.st;
+  std::vector<sw_result> rev(np);
+  if ((rc = sw_align_batch(&nb, sc, rev.data()))) return rc;
+  for (int k = 0; k < np; ++k) {
+    const sw_result &e = ends[k];
+    if (e.score <= 0) {
+      query_start[k] = ref_start[k] = -1;
+      continue;
+    }
+    if (rev[k].score != e.score) {
+      for (int u = 0; u < np; ++u) query_start[u] = ref_start[u] = -1;
+      set_error("pair %d: score %d is not this pair's optimum at its end cell (%d found)", k,
+                e.score, rev[k].score);
+      return SW_EINVAL;
+    }
+    query_start[k] = e.query_end - rev[k].query_end;
+    ref_start[k] = e.ref_end - rev[k].ref_end;
+  }
+  return SW_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ end-to-end scores
 // ------------------------------------------------------------------ end-to-end scores
 
 namespace {

@@ -127,6 +127,24 @@ hipError_t launch_trplan_check(const TracePair *table, int nt, const int32_t *n_
 hipError_t launch_count_scan(const int32_t *counts, int np, int64_t *off, int64_t *bsum,
                              hipStream_t st);
 
+// Start-cell tables on the device for one query per pair
+// (sw_align_batch_starts): per pair k the lengths of the reversed prefixes it
+// aligns (0 without an alignment) and their sources, the identity index, the
+// first error (indices, offsets, an end cell outside the pair) and the
+// smallest and largest query id of a pair with an alignment.
+enum : int { kSpErrEnd = 13 };
+struct StartPlanArgs {
+  int np, nq, nr;
+  const DevResult *ends;                 // device copy of the caller's results
+  const int64_t *qoff, *roff;
+  const int32_t *pq, *pr;
+  int32_t *qcnt, *rcnt, *ids;            // [np]
+  int64_t *qsrc, *rsrc;                  // [np + 1]
+  unsigned long long *err;               // error word (initialised to ~0)
+  int32_t *qrange;                       // {min, max} (initialised to {INT_MAX, -1})
+};
+hipError_t launch_startplan(const StartPlanArgs &a, hipStream_t st);
+
 // End-to-end score tables on the device (sw_align_batch_global): each pair
 // checked and put in a class -- couples of queries up to kE2eDualCols
 // residues, queries of one 256-column tile, of one kE2eWideCols tile, longer

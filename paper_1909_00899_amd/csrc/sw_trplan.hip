@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 
 #include "sw_internal.h"
 #include "sw_trace.h"
@@ -340,6 +341,58 @@ __global__ __launch_bounds__(kThreads) void scan_write_kernel(const int32_t *cou
   if (blockIdx.x == 0 && threadIdx.x == 0) off[0] = 0;
 }
 
+// ---------------------------------------------------------------- start-cell tables
+
+__global__ __launch_bounds__(kThreads) void startplan_kernel(StartPlanArgs a) {
+  const int stride = gridDim.x * kThreads;
+  int qmin = INT_MAX, qmax = -1;
+  for (int k = blockIdx.x * kThreads + threadIdx.x; k < a.np; k += stride) {
+    const DevResult e = a.ends[k];
+    int qc = 0, rc = 0;
+    int64_t qs = 0, rs = 0;
+    a.ids[k] = k;
+    if (e.score > 0) {
+      const int q = a.pq[k], r = a.pr[k];
+      if (q < 0 || q >= a.nq || r < 0 || r >= a.nr) {
+        set_err(a.err, k, kTrErrPair);
+      } else {
+        const int64_t q0 = a.qoff[q], q1 = a.qoff[q + 1], r0 = a.roff[r], r1 = a.roff[r + 1];
+        if (q0 < 0 || q1 < q0 || q1 > a.qoff[a.nq]) {
+          set_err(a.err, k, kTrErrQoff);
+        } else if (r0 < 0 || r1 < r0 || r1 > a.roff[a.nr]) {
+          set_err(a.err, k, kTrErrRoff);
+        } else if (e.qend < 0 || e.qend >= q1 - q0 || e.rend < 0 || e.rend >= r1 - r0) {
+          set_err(a.err, k, kSpErrEnd);
+        } else {
+          qc = e.qend + 1;
+          rc = e.rend + 1;
+          qs = q0;
+          rs = r0;
+          qmin = min(qmin, q);
+          qmax = max(qmax, q);
+        }
+      }
+    }
+    a.qcnt[k] = qc;
+    a.rcnt[k] = rc;
+    a.qsrc[k] = qs;
+    a.rsrc[k] = rs;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.qsrc[a.np] = 0;
+    a.rsrc[a.np] = 0;
+  }
+  // one atomic pair per wavefront
+  for (int d = 1; d < 64; d <<= 1) {
+    qmin = min(qmin, __shfl_xor(qmin, d));
+    qmax = max(qmax, __shfl_xor(qmax, d));
+  }
+  if ((threadIdx.x & 63) == 0 && qmax >= 0) {
+    atomicMin(&a.qrange[0], qmin);
+    atomicMax(&a.qrange[1], qmax);
+  }
+}
+
 // ---------------------------------------------------------------- end-to-end score tables
 
 constexpr int kE2eMulti = 3;
@@ -479,6 +532,13 @@ __global__ __launch_bounds__(kThreads) void e2e_check_kernel(const DevResult *re
 
 }  // namespace
 }  // namespace dev
+
+hipError_t launch_startplan(const StartPlanArgs &a, hipStream_t st) {
+  if (a.np <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(((int64_t)a.np + dev::kThreads - 1) / dev::kThreads, 2048);
+  hipLaunchKernelGGL(dev::startplan_kernel, dim3(grid), dim3(dev::kThreads), 0, st, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_e2eplan_classify(const E2ePlanArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(dev::e2eplan_classify_kernel, dim3(kTrBlocks), dim3(dev::kThreads), 0, st, a);

@@ -162,3 +162,34 @@ def test_starts_one_query_saturated_pairs_take_int32():
                    np.arange(len(refs), dtype=np.int32), M, 11, 1)
     ends, starts = _check(w, "one query, saturated")
     assert (ends[:, 3] == api.SW_FLAG_SATURATED).sum() > 10
+
+
+def test_starts_one_aligned_query_among_several_and_offsets():
+    # pair_query names three queries, but only query 1 aligns anywhere (the
+    # other two are empty): the device tables see one query and hand the
+    # batch to the one-query launch; then a query whose offsets run past the
+    # residue total is refused
+    rng = np.random.default_rng(905)
+    M = W.random_matrix(rng, 4)
+    q = rng.integers(0, 4, size=180).astype(np.uint8)
+    qoff = np.array([0, 0, 180, 180], dtype=np.int64)
+    lens = rng.integers(50, 400, size=40)
+    roff = np.zeros(41, dtype=np.int64)
+    np.cumsum(lens, out=roff[1:])
+    rres = rng.integers(0, 4, size=int(roff[-1])).astype(np.uint8)
+    pr = np.arange(40, dtype=np.int32)
+    pq = np.array([1 if k % 3 else (0 if k % 2 else 2) for k in range(40)], dtype=np.int32)
+    w = W.Workload("one_aligned", q, qoff, rres, roff, pq, pr, M, 3, 1, {})
+    ends, starts = _check(w, "one aligned query")
+    assert (ends[pq != 1, 0] == 0).all() and (ends[pq == 1, 0] > 0).all()
+    # several aligned queries, one of whose offsets runs past the residues
+    w2 = W.random_pairs(200, 4, (20, 120), (20, 200), 906)
+    ends2, _ = _check(w2, "several queries")
+    k = int(np.argmax(ends2[:, 0]))
+    qo = w2.query_off.copy()
+    qo[-1] = qo[w2.pair_query[k] + 1] - 1
+    with pytest.raises(api.SwError) as e:
+        api.sw_align_batch_starts(w2.query_res[:qo[-1]], qo, w2.ref_res, w2.ref_off, w2.pair_ref,
+                                  w2.matrix, w2.gap_open, w2.gap_extend, ends2,
+                                  pair_query=w2.pair_query)
+    assert e.value.code == api.SW_EINVAL
