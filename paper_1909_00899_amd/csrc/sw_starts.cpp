@@ -436,8 +436,8 @@ int check_batch_args(const sw_batch *b) {
 }  // namespace
 
 namespace {
-int starts_device(const sw_batch *b, const sw_scoring *sc, StartsWork &W, const sw_result *ends,
-                  int32_t *query_start, int32_t *ref_start, bool &handled);
+int starts_device(const sw_batch *b, const sw_scoring *sc, const Scoring &S, StartsWork &W,
+                  const sw_result *ends, int32_t *query_start, int32_t *ref_start, bool &handled);
 }  // namespace
 
 extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
@@ -457,7 +457,7 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
     // one query per pair: the tables on the device (unless every aligned
     // pair turns out to share one query: the one-query launch below)
     bool handled = false;
-    rc = starts_device(b, sc, W, ends, query_start, ref_start, handled);
+    rc = starts_device(b, sc, S, W, ends, query_start, ref_start, handled);
     if (handled) return rc;
   }
   Batch B;
@@ -888,12 +888,13 @@ extern "C" int sw_align_batch_global_cigar(const sw_batch *b, const sw_scoring *
 namespace {
 
 // Start cells of a batch with one query per pair: the reversed prefixes'
-// tables built on the device (startplan_kernel, two prefix sums), the
+// tables built on the device (startplan_kernel, two prefix sums; each prefix
+// cut to the span an alignment of the pair's score can have), the
 // prefixes reversed there, one batch call over them (pairs without an
 // alignment become empty pairs).  handled = false leaves the batch to the
 // host-table path (every aligned pair has the same query).
-int starts_device(const sw_batch *b, const sw_scoring *sc, StartsWork &W, const sw_result *ends,
-                  int32_t *query_start, int32_t *ref_start, bool &handled) {
+int starts_device(const sw_batch *b, const sw_scoring *sc, const Scoring &S, StartsWork &W,
+                  const sw_result *ends, int32_t *query_start, int32_t *ref_start, bool &handled) {
   handled = true;
   int rc;
   const int np = b->n_pairs;
@@ -919,6 +920,9 @@ int starts_device(const sw_batch *b, const sw_scoring *sc, StartsWork &W, const 
   pa.np = np;
   pa.nq = b->n_queries;
   pa.nr = b->n_refs;
+  pa.go = S.go;
+  pa.ge = S.ge;
+  pa.max_s = S.max_s;
   pa.ends = W.tr_ends.as<swk::DevResult>();
   pa.qoff = din.qoff;
   pa.roff = din.roff;

@@ -131,10 +131,15 @@ hipError_t launch_count_scan(const int32_t *counts, int np, int64_t *off, int64_
 // (sw_align_batch_starts): per pair k the lengths of the reversed prefixes it
 // aligns (0 without an alignment) and their sources, the identity index, the
 // first error (indices, offsets, an end cell outside the pair) and the
-// smallest and largest query id of a pair with an alignment.
+// smallest and largest query id of a pair with an alignment.  A prefix is cut
+// to the span an alignment of the pair's score can have: every alignment of
+// that score inside the prefixes ends at the end cell (the first maximum), so
+// reversed it starts at the origin, and with P pairs it spans at most
+// P + 1 + (P max_s - go - score) / ge residues of either sequence.
 enum : int { kSpErrEnd = 13 };
 struct StartPlanArgs {
   int np, nq, nr;
+  int go, ge, max_s;                     // ge = min(gap_extend, gap_open); max_s >= 0
   const DevResult *ends;                 // device copy of the caller's results
   const int64_t *qoff, *roff;
   const int32_t *pq, *pr;

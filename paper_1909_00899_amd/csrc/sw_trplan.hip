@@ -364,10 +364,20 @@ __global__ __launch_bounds__(kThreads) void startplan_kernel(StartPlanArgs a) {
         } else if (e.qend < 0 || e.qend >= q1 - q0 || e.rend < 0 || e.rend >= r1 - r0) {
           set_err(a.err, k, kSpErrEnd);
         } else {
-          qc = e.qend + 1;
-          rc = e.rend + 1;
-          qs = q0;
-          rs = r0;
+          // the spans an alignment of this score can have (P <= the other
+          // prefix's length pairs; rounding toward zero only widens them)
+          const int64_t Lq = e.qend + 1, Lr = e.rend + 1;
+          int64_t Qb = Lq, Rb = Lr;
+          if (a.ge > 0) {
+            const int64_t sr = Lq + 1 + (Lq * a.max_s - a.go - e.score) / a.ge;
+            const int64_t sq = Lr + 1 + (Lr * a.max_s - a.go - e.score) / a.ge;
+            Rb = min(Lr, max(Lq, sr));
+            Qb = min(Lq, max(Lr, sq));
+          }
+          qc = (int)Qb;
+          rc = (int)Rb;
+          qs = q0 + (Lq - Qb);   // the prefixes' last Qb and Rb residues
+          rs = r0 + (Lr - Rb);
           qmin = min(qmin, q);
           qmax = max(qmax, q);
         }

@@ -193,3 +193,37 @@ def test_starts_one_aligned_query_among_several_and_offsets():
                                   w2.matrix, w2.gap_open, w2.gap_extend, ends2,
                                   pair_query=w2.pair_query)
     assert e.value.code == api.SW_EINVAL
+
+
+@pytest.mark.parametrize("alpha,go,ge", [(4, 6, 1), (2, 2, 3), (4, 1, 1)])
+def test_starts_short_queries_long_references(alpha, go, ge):
+    # 20-80 residue queries against 500-2000 residue references, each query
+    # planted (mutated) near a random place and a second copy elsewhere: the
+    # reversed reference prefixes run far past the alignments, so the cut to
+    # the span an alignment of the score can have decides most of the work;
+    # two letters make many optimal alignments, so the tie rule is exercised
+    rng = np.random.default_rng(907 + alpha + 10 * go + 100 * ge)
+    M = W.random_matrix(rng, alpha)
+    np.fill_diagonal(M, np.abs(np.diag(M)) + 1)
+    qs, rs = [], []
+    for k in range(300):
+        m = int(rng.integers(20, 81))
+        n = int(rng.integers(500, 2001))
+        q = rng.integers(0, alpha, size=m).astype(np.uint8)
+        r = rng.integers(0, alpha, size=n).astype(np.uint8)
+        for _ in range(2):
+            at = int(rng.integers(0, n - m))
+            cp = q.copy()
+            flip = rng.random(m) < 0.05
+            cp[flip] = rng.integers(0, alpha, size=int(flip.sum()))
+            r[at:at + m] = cp
+        qs.append(q)
+        rs.append(r)
+    qoff = np.zeros(301, dtype=np.int64)
+    roff = np.zeros(301, dtype=np.int64)
+    np.cumsum([x.size for x in qs], out=qoff[1:])
+    np.cumsum([x.size for x in rs], out=roff[1:])
+    idx = np.arange(300, dtype=np.int32)
+    w = W.Workload("short_vs_long", np.concatenate(qs), qoff, np.concatenate(rs), roff, idx,
+                   idx.copy(), M, go, ge, {})
+    _check(w, "short vs long alpha=%d go=%d ge=%d" % (alpha, go, ge))
