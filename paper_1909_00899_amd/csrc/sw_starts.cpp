@@ -798,6 +798,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
   ta.ref_start = W.tr_rstart.as<int32_t>();
   ta.query_start = W.tr_qstart.as<int32_t>();
   ta.slot_words = 0;
+  ta.lds_words = 0;
   ta.carry_rows = 0;
   ta.gbits = nullptr;
   ta.gcarry = nullptr;
@@ -810,6 +811,8 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     if (!cnt) continue;
     ta.pairs = dp + cstart[c];
     ta.n = cnt;
+    // LDS for the class's largest rectangle only (more workgroups per CU)
+    ta.lds_words = (int)std::max<uint64_t>(8, (cmax[2 * c] + 7) / 8 * 8);
     HIPCHK(swk::launch_trace(true, kLdsVariant[c], ta, cnt, W.st));
   }
   for (int g = 0; g < (int)groups.size(); ++g) {

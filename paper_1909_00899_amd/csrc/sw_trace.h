@@ -45,8 +45,17 @@ struct TracePair {
 __host__ __device__ inline int64_t trace_run_bound(int64_t A, int64_t B) {
   return A + B - 1 < 3 * (A < B ? A : B) - 2 ? A + B - 1 : 3 * (A < B ? A : B) - 2;
 }
-// 2-byte units of a rectangle's decision words: rows x tiles x 64 lanes x
-// the word width of its variant (constant divisors)
+// Lanes per row of a rectangle's decision words: a one-tile rectangle keeps
+// only the lanes that hold its columns (rounded up to 8, so a row is a whole
+// number of 16-byte units), a longer one all 64.
+__host__ __device__ inline int trace_lane_stride(int B, int C) {
+  if (B > 64 * C) return 64;
+  const int nl = (B > 0 ? B + C - 1 : C) / C;
+  const int r = (nl + 7) / 8 * 8;
+  return r < 64 ? r : 64;
+}
+// 2-byte units of a rectangle's decision words: rows x tiles x its lane
+// stride x the word width of its variant (constant divisors)
 __host__ __device__ inline int64_t trace_slot_words(const TracePair &P) {
   int64_t tiles;
   switch (trace_cols(P.pad)) {
@@ -56,7 +65,8 @@ __host__ __device__ inline int64_t trace_slot_words(const TracePair &P) {
     case 8: tiles = (P.B + 511) / 512; break;
     default: tiles = (P.B + 255) / 256; break;
   }
-  return (int64_t)P.A * tiles * 64 * (trace_word_bytes(P.pad) / 2);
+  return (int64_t)P.A * tiles * trace_lane_stride(P.B, trace_cols(P.pad)) *
+         (trace_word_bytes(P.pad) / 2);
 }
 
 // ---- path tables on the device (sw_trplan.hip)
@@ -188,6 +198,8 @@ struct TraceArgs {
   int alpha, go, ge;       // ge <= go
   uint16_t *gbits;         // device-memory variant: slot_words 2-byte units per workgroup
   int64_t slot_words;
+  int lds_words;           // LDS variant: 2-byte units of LDS for decision words, a
+                           // multiple of 8 and >= every pair's trace_slot_words
   int32_t *gcarry;         // device-memory variant: 6 * carry_rows per workgroup
   int carry_rows;
   uint32_t *cigar;         // device
@@ -202,7 +214,7 @@ struct TraceArgs {
 // LDS bytes of a workgroup (the matrix sized for the alphabet); with
 // lds_bits the decision bits and tile carries live in LDS, else in gbits /
 // gcarry (grid-stride over the pairs).
-size_t trace_lds_bytes(bool lds_bits, int alpha);
+size_t trace_lds_bytes(bool lds_bits, int alpha, int lds_words);
 // every pair of a.pairs[0 .. a.n) must have trace_variant(pad) == variant
 hipError_t launch_trace(bool lds_bits, int variant, const TraceArgs &a, int grid, hipStream_t st);
 // End-to-end scores (sw_trace.hip): TracePair with A = n, B = m (both >= 1);

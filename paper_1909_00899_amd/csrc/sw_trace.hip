@@ -141,8 +141,8 @@ __device__ __forceinline__ int nib_shift(int c) {
 // of its last column per row.
 template <int C, int MODE, bool FIRST, bool NEXT, class Word>
 __device__ __forceinline__ void fill16_tile(const TraceArgs &a, const TracePair &P,
-                                            const short *smat16, Word *bits, const int *cr, int *cw,
-                                            int t, bool &bad, bool &ok) {
+                                            const short *smat16, Word *bits, int LS, const int *cr,
+                                            int *cw, int t, bool &bad, bool &ok) {
   constexpr bool kRowFree = MODE == 3 || MODE == 4, kColFree = MODE == 2 || MODE == 4;
   constexpr int NP = C / 2, TC = 64 * C;
   const int L = threadIdx.x;
@@ -173,7 +173,7 @@ __device__ __forceinline__ void fill16_tile(const TraceArgs &a, const TracePair 
   // V(-1, base - 1); in MODE 0 the first tile's V(-1, -1) = 0 makes the
   // start pair's M its own score
   int cv_prev = MODE == 0 ? (FIRST ? 0 : kNeg16) : (FIRST || kRowFree) ? 0 : -(go + (base - 1) * ge);
-  Word *brow = bits + (size_t)t * A * 64 + L;
+  Word *brow = bits + (size_t)t * A * LS + L;   // lanes past LS hold no column
   for (int blk = 0; blk < A; blk += 64) {
     const int row = blk + L;
     int rreg = row < A ? (int)a.rres[P.r + row] : 0;
@@ -259,7 +259,7 @@ __device__ __forceinline__ void fill16_tile(const TraceArgs &a, const TracePair 
         acc |= (psigns(D3[0], D3[1]) & 0x08080808u) | (psigns(D3[2], D3[3]) & 0x80808080u);
         word = ~acc;
       }
-      brow[(size_t)i * 64] = (Word)word;
+      if (L < LS) brow[(size_t)i * LS] = (Word)word;
       if (NEXT && L == 63) {
         cw[3 * i] = phi(Vp[NP - 1]);
         cw[3 * i + 1] = phi(Mv[NP - 1]);
@@ -283,18 +283,19 @@ __device__ __forceinline__ void fill16_tile(const TraceArgs &a, const TracePair 
 
 template <bool LB, int C, int MODE, class Word>
 __device__ __forceinline__ void fill16(const TraceArgs &a, const TracePair &P, const short *smat16,
-                                       Word *bits, int *carry, int crow, bool &bad, bool &ok) {
+                                       Word *bits, int LS, int *carry, int crow, bool &bad,
+                                       bool &ok) {
   const int T = (P.B + 64 * C - 1) / (64 * C);
   for (int t = 0; t < T; ++t) {
     const int *cr = carry + ((t + 1) & 1) * 3 * crow;   // written by tile t - 1
     int *cw = carry + (t & 1) * 3 * crow;                // read by tile t + 1
     const bool next = t + 1 < T;
     if (t == 0) {
-      if (next) fill16_tile<C, MODE, true, true>(a, P, smat16, bits, cr, cw, t, bad, ok);
-      else fill16_tile<C, MODE, true, false>(a, P, smat16, bits, cr, cw, t, bad, ok);
+      if (next) fill16_tile<C, MODE, true, true>(a, P, smat16, bits, LS, cr, cw, t, bad, ok);
+      else fill16_tile<C, MODE, true, false>(a, P, smat16, bits, LS, cr, cw, t, bad, ok);
     } else {
-      if (next) fill16_tile<C, MODE, false, true>(a, P, smat16, bits, cr, cw, t, bad, ok);
-      else fill16_tile<C, MODE, false, false>(a, P, smat16, bits, cr, cw, t, bad, ok);
+      if (next) fill16_tile<C, MODE, false, true>(a, P, smat16, bits, LS, cr, cw, t, bad, ok);
+      else fill16_tile<C, MODE, false, false>(a, P, smat16, bits, LS, cr, cw, t, bad, ok);
     }
     // carries and bits are read back by this same wavefront (see trace_one)
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -321,13 +322,14 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
   const int L = threadIdx.x;
   const int alpha = a.alpha, go = a.go, ge = a.ge;
   const int A = P.A, B = P.B, T = (B + TC - 1) / TC;
+  const int LS = trace_lane_stride(B, C);   // lanes per row of decision words
   Word *bits = (Word *)(LB ? lbits : a.gbits + (size_t)blockIdx.x * a.slot_words);
   Word *lwin = (Word *)lwin16;
   int *carry = LB ? lcarry : a.gcarry + (size_t)blockIdx.x * 6 * a.carry_rows;
   const int crow = LB ? kTraceLdsCarryRows : a.carry_rows;
   bool bad = false, ok = false;
 
-  if constexpr (W16) fill16<LB, C, MODE, Word>(a, P, smat16, bits, carry, crow, bad, ok);
+  if constexpr (W16) fill16<LB, C, MODE, Word>(a, P, smat16, bits, LS, carry, crow, bad, ok);
   else for (int t = 0; t < T; ++t) {
     const int base = t * TC, jc0 = base + C * L;
     const int *cr = carry + ((t + 1) & 1) * 3 * crow;   // written by tile t - 1
@@ -403,7 +405,7 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
         Gp[c] = g;
         Fp[c] = f;
       }
-      bits[((size_t)t * A + i) * 64 + L] = (Word)word;
+      if (L < LS) bits[((size_t)t * A + i) * LS + L] = (Word)word;
       if (t + 1 < T && L == 63) {
         cw[3 * i] = Vp[C - 1];
         cw[3 * i + 1] = Mv[C - 1];
@@ -444,17 +446,19 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     const int t = j / TC, col = (j % TC) / C;
     uint32_t wd;
     if (LB) {
-      wd = bits[((size_t)t * A + i) * 64 + col];
+      wd = bits[((size_t)t * A + i) * LS + col];
     } else {
       if (t != w_tile || i < w_lo || i >= w_lo + kWinRows) {
         w_tile = t;
         w_lo = max(0, i - kWinRows + 1);
         const int rows = min(kWinRows, A - w_lo);
-        const uint4 *src = (const uint4 *)(bits + ((size_t)t * A + w_lo) * 64);
+        // rows of LS words: LS * sizeof(Word) / 16 units of 16 bytes each
+        const uint4 *src = (const uint4 *)(bits + ((size_t)t * A + w_lo) * LS);
         uint4 *dst = (uint4 *)lwin;
-        for (int k = L; k < rows * 4 * (int)sizeof(Word); k += 64) dst[k] = src[k];
+        const int units = rows * LS * (int)sizeof(Word) / 16;
+        for (int k = L; k < units; k += 64) dst[k] = src[k];
       }
-      wd = lwin[(i - w_lo) * 64 + col];
+      wd = lwin[(i - w_lo) * LS + col];
     }
     return (int)(wd >> nib_shift<C, W16>(j % C)) & 15;
   };
@@ -472,8 +476,8 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
     int nib = 0;
     if (in) {
       const int t = jj / TC, col = (jj % TC) / C;
-      const uint32_t wd = LB ? (uint32_t)bits[((size_t)t * A + ii) * 64 + col]
-                             : (uint32_t)lwin[(ii - w_lo) * 64 + col];
+      const uint32_t wd = LB ? (uint32_t)bits[((size_t)t * A + ii) * LS + col]
+                             : (uint32_t)lwin[(ii - w_lo) * LS + col];
       nib = (int)(wd >> nib_shift<C, W16>(jj % C)) & 15;
     }
     const uint64_t plain = __ballot(in && (nib & 5) == 5);
@@ -636,7 +640,7 @@ __global__ __launch_bounds__(64) void trace_kernel(TraceArgs a) {
   short *smat16 = (short *)(smem + mat_words(a.alpha));        // the same, 16-bit entries
   // the matrices take alpha^2 words and shorts (16-byte aligned), the bits follow
   uint16_t *lbits = (uint16_t *)(smem + mat_words(a.alpha) + mat16_words(a.alpha));
-  int *lcarry = (int *)(lbits + kTraceLdsRowTiles * 64);
+  int *lcarry = (int *)(lbits + a.lds_words);                  // LDS variant: after the bits
   uint16_t *lwin = lbits;                                      // walk window (device-memory bits)
   for (int k = threadIdx.x; k < a.alpha * a.alpha; k += 64) {
     smat[k] = a.matrix[k];
@@ -986,9 +990,9 @@ __global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, 
 }  // namespace
 }  // namespace dev
 
-size_t trace_lds_bytes(bool lds_bits, int alpha) {
+size_t trace_lds_bytes(bool lds_bits, int alpha, int lds_words) {
   size_t b = (size_t)(dev::mat_words(alpha) + dev::mat16_words(alpha)) * sizeof(int);
-  if (lds_bits) b += (size_t)kTraceLdsRowTiles * 64 * sizeof(uint16_t) + 6 * kTraceLdsCarryRows * sizeof(int);
+  if (lds_bits) b += (size_t)lds_words * sizeof(uint16_t) + 6 * kTraceLdsCarryRows * sizeof(int);
   else b += (size_t)dev::kWalkWindowBytes;
   return b;
 }
@@ -1046,7 +1050,7 @@ hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs
 
 template <bool LB>
 static void launch_trace_v(int variant, const TraceArgs &a, int grid, hipStream_t st) {
-  const size_t lds = trace_lds_bytes(LB, a.alpha);
+  const size_t lds = trace_lds_bytes(LB, a.alpha, a.lds_words);
   switch (variant) {
     case kTraceV16x4: hipLaunchKernelGGL((dev::trace_kernel<LB, kTraceV16x4>), dim3(grid), dim3(64), lds, st, a); break;
     case kTraceV16x8: hipLaunchKernelGGL((dev::trace_kernel<LB, kTraceV16x8>), dim3(grid), dim3(64), lds, st, a); break;
@@ -1057,6 +1061,8 @@ static void launch_trace_v(int variant, const TraceArgs &a, int grid, hipStream_
 hipError_t launch_trace(bool lds_bits, int variant, const TraceArgs &a, int grid, hipStream_t st) {
   if (a.n <= 0 || grid <= 0) return hipSuccess;
   if (variant != kTraceV32 && variant != kTraceV16x4 && variant != kTraceV16x8)
+    return hipErrorInvalidValue;
+  if (lds_bits && (a.lds_words < 8 || a.lds_words % 8 || a.lds_words > kTraceLdsRowTiles * 64))
     return hipErrorInvalidValue;
   if (lds_bits) launch_trace_v<true>(variant, a, grid, st);
   else launch_trace_v<false>(variant, a, grid, st);
