@@ -813,6 +813,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     ta.n = cnt;
     // LDS for the class's largest rectangle only (more workgroups per CU)
     ta.lds_words = (int)std::max<uint64_t>(8, (cmax[2 * c] + 7) / 8 * 8);
+    ta.carry_rows = (int)cmax[2 * c + 1];   // rows of its rectangles of two or more tiles
     HIPCHK(swk::launch_trace(true, kLdsVariant[c], ta, cnt, W.st));
   }
   for (int g = 0; g < (int)groups.size(); ++g) {

@@ -201,7 +201,8 @@ struct TraceArgs {
   int lds_words;           // LDS variant: 2-byte units of LDS for decision words, a
                            // multiple of 8 and >= every pair's trace_slot_words
   int32_t *gcarry;         // device-memory variant: 6 * carry_rows per workgroup
-  int carry_rows;
+  int carry_rows;          // rows of carries (LDS variant: in LDS, 0 when every
+                           // rectangle of the launch is one tile)
   uint32_t *cigar;         // device
   int32_t *n_runs;         // device, indexed by TracePair::id
   int mode;                // 0 local rectangle; 1-4 the end-to-end mode + 1 (global,
@@ -214,7 +215,7 @@ struct TraceArgs {
 // LDS bytes of a workgroup (the matrix sized for the alphabet); with
 // lds_bits the decision bits and tile carries live in LDS, else in gbits /
 // gcarry (grid-stride over the pairs).
-size_t trace_lds_bytes(bool lds_bits, int alpha, int lds_words);
+size_t trace_lds_bytes(bool lds_bits, int alpha, int lds_words, int carry_rows);
 // every pair of a.pairs[0 .. a.n) must have trace_variant(pad) == variant
 hipError_t launch_trace(bool lds_bits, int variant, const TraceArgs &a, int grid, hipStream_t st);
 // End-to-end scores (sw_trace.hip): TracePair with A = n, B = m (both >= 1);

@@ -326,7 +326,7 @@ __device__ __forceinline__ void trace_one(const TraceArgs &a, const TracePair &P
   Word *bits = (Word *)(LB ? lbits : a.gbits + (size_t)blockIdx.x * a.slot_words);
   Word *lwin = (Word *)lwin16;
   int *carry = LB ? lcarry : a.gcarry + (size_t)blockIdx.x * 6 * a.carry_rows;
-  const int crow = LB ? kTraceLdsCarryRows : a.carry_rows;
+  const int crow = a.carry_rows;   // LDS: <= kTraceLdsCarryRows, 0 if every rectangle is one tile
   bool bad = false, ok = false;
 
   if constexpr (W16) fill16<LB, C, MODE, Word>(a, P, smat16, bits, LS, carry, crow, bad, ok);
@@ -990,9 +990,9 @@ __global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, 
 }  // namespace
 }  // namespace dev
 
-size_t trace_lds_bytes(bool lds_bits, int alpha, int lds_words) {
+size_t trace_lds_bytes(bool lds_bits, int alpha, int lds_words, int carry_rows) {
   size_t b = (size_t)(dev::mat_words(alpha) + dev::mat16_words(alpha)) * sizeof(int);
-  if (lds_bits) b += (size_t)lds_words * sizeof(uint16_t) + 6 * kTraceLdsCarryRows * sizeof(int);
+  if (lds_bits) b += (size_t)lds_words * sizeof(uint16_t) + 6 * (size_t)carry_rows * sizeof(int);
   else b += (size_t)dev::kWalkWindowBytes;
   return b;
 }
@@ -1050,7 +1050,7 @@ hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs
 
 template <bool LB>
 static void launch_trace_v(int variant, const TraceArgs &a, int grid, hipStream_t st) {
-  const size_t lds = trace_lds_bytes(LB, a.alpha, a.lds_words);
+  const size_t lds = trace_lds_bytes(LB, a.alpha, a.lds_words, a.carry_rows);
   switch (variant) {
     case kTraceV16x4: hipLaunchKernelGGL((dev::trace_kernel<LB, kTraceV16x4>), dim3(grid), dim3(64), lds, st, a); break;
     case kTraceV16x8: hipLaunchKernelGGL((dev::trace_kernel<LB, kTraceV16x8>), dim3(grid), dim3(64), lds, st, a); break;
@@ -1062,7 +1062,8 @@ hipError_t launch_trace(bool lds_bits, int variant, const TraceArgs &a, int grid
   if (a.n <= 0 || grid <= 0) return hipSuccess;
   if (variant != kTraceV32 && variant != kTraceV16x4 && variant != kTraceV16x8)
     return hipErrorInvalidValue;
-  if (lds_bits && (a.lds_words < 8 || a.lds_words % 8 || a.lds_words > kTraceLdsRowTiles * 64))
+  if (lds_bits && (a.lds_words < 8 || a.lds_words % 8 || a.lds_words > kTraceLdsRowTiles * 64 ||
+                   a.carry_rows < 0 || a.carry_rows > kTraceLdsCarryRows))
     return hipErrorInvalidValue;
   if (lds_bits) launch_trace_v<true>(variant, a, grid, st);
   else launch_trace_v<false>(variant, a, grid, st);

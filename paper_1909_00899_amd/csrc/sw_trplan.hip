@@ -177,7 +177,10 @@ __global__ __launch_bounds__(kThreads) void trplan_classify_kernel(TrPlanArgs a)
     mycaps += (unsigned long long)tp.cap;
     if (c != kTrHostClass) {
       atomicMax(&mx[2 * c], (unsigned long long)trace_slot_words(tp));
-      atomicMax(&mx[2 * c + 1], (unsigned long long)tp.A);
+      // rows that need carries: an LDS class's rectangles of two or more
+      // tiles only (a device-memory class sizes its slots by every row)
+      const bool one_tile = tp.B <= trace_tile_cols(tp.pad);
+      atomicMax(&mx[2 * c + 1], (unsigned long long)(c < 3 && one_tile ? 0 : tp.A));
     }
   }
   atomicAdd(&caps, mycaps);
