@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <array>
 #include <cstring>
 #include <mutex>
@@ -68,6 +69,7 @@ struct StartsWork {
   };
   HostBuf up_stage, dn_stage;
   DevBuf sp_src, sp_dst;         // start cells: reversed prefixes' sources and offsets
+  HostBuf rev_res;               // pinned: the reversed prefixes' results
   size_t up_used = 0, dn_used = 0;
   std::vector<Pending> dn_pending;
   DevBuf tr_res;                 // end-to-end results
@@ -989,22 +991,34 @@ int starts_device(const sw_batch *b, const sw_scoring *sc, const Scoring &S, Sta
   nb.precision = b->precision;
   nb.device_resident = 1;
   nb.stream = W.st;
-  std::vector<sw_result> rev(np);
-  if ((rc = sw_align_batch(&nb, sc, rev.data()))) return rc;
-  for (int k = 0; k < np; ++k) {
-    const sw_result &e = ends[k];
-    if (e.score <= 0) {
-      query_start[k] = ref_start[k] = -1;
-      continue;
+  // the reversed results in pinned memory (copied back at the bus rate), then
+  // the starts on host threads
+  if ((rc = W.rev_res.ensure((size_t)np * sizeof(sw_result)))) return rc;
+  const sw_result *rev = W.rev_res.as<sw_result>();
+  if ((rc = sw_align_batch(&nb, sc, W.rev_res.as<sw_result>()))) return rc;
+  const int T = np >= 65536 ? host_threads() : 1;
+  std::vector<int> wrong(T, INT_MAX);
+  parallel_ranges((size_t)np, T, [&](int t, size_t lo, size_t hi) {
+    for (size_t kk = lo; kk < hi; ++kk) {
+      const int k = (int)kk;
+      const sw_result &e = ends[k];
+      if (e.score <= 0) {
+        query_start[k] = ref_start[k] = -1;
+      } else if (rev[k].score != e.score) {
+        wrong[t] = k;
+        return;
+      } else {
+        query_start[k] = e.query_end - rev[k].query_end;
+        ref_start[k] = e.ref_end - rev[k].ref_end;
+      }
     }
-    if (rev[k].score != e.score) {
-      for (int u = 0; u < np; ++u) query_start[u] = ref_start[u] = -1;
-      set_error("pair %d: score %d is not this pair's optimum at its end cell (%d found)", k,
-                e.score, rev[k].score);
-      return SW_EINVAL;
-    }
-    query_start[k] = e.query_end - rev[k].query_end;
-    ref_start[k] = e.ref_end - rev[k].ref_end;
+  });
+  const int kw = *std::min_element(wrong.begin(), wrong.end());
+  if (kw != INT_MAX) {
+    for (int u = 0; u < np; ++u) query_start[u] = ref_start[u] = -1;
+    set_error("pair %d: score %d is not this pair's optimum at its end cell (%d found)", kw,
+              ends[kw].score, rev[kw].score);
+    return SW_EINVAL;
   }
   return SW_OK;
 }
