@@ -235,7 +235,8 @@ size_t endtoend_lds_bytes(int alpha);
 hipError_t launch_endtoend(int mode, const EndArgs &a, int grid, hipStream_t st);
 // Pairs with m <= 160, two per wavefront; pad = ceil(m / 32).
 hipError_t launch_endtoend2(int mode, const EndArgs &a, hipStream_t st);
-// Pairs with m > 256: pad = 5-8 query columns per lane (tiles of 64 pad).
+// Pairs with m > 256: pad = 5-8 query columns per lane (tiles of 64 pad
+// columns: one up to 512 residues, beyond that ceil(m / 512) tiles).
 hipError_t launch_endtoend_wide(int mode, const EndArgs &a, int grid, hipStream_t st);
 
 // Runs of every pair (n_runs[id] of them, ending at out + cap) to

@@ -460,7 +460,11 @@ __device__ int e2e_classify(const E2ePlanArgs &a, int k, TracePair &tp) {
     tp.pad = (int32_t)((m + 63) / 64);
     return m <= kTraceTileCols ? 1 : 2;
   }
-  tp.pad = kE2eWideCols / 64;
+  // as many tiles as kE2eWideCols-column tiles would need, each as narrow as
+  // covers the query (5-8 columns per lane: 640 columns for 600 residues
+  // instead of 1024)
+  const int64_t tiles = (m + kE2eWideCols - 1) / kE2eWideCols;
+  tp.pad = (int32_t)((m + 64 * tiles - 1) / (64 * tiles));
   return kE2eMulti;
 }
 

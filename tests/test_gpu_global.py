@@ -99,14 +99,17 @@ def test_dual_pairs_odd_count_uneven_neighbours(mode):
 @pytest.mark.parametrize("mode", MODES)
 def test_queries_across_tiles(mode):
     # queries of 257-1600 residues: up to 512 one tile at 5-8 columns per
-    # lane, beyond that two to four 512-column tiles with carries; references
-    # from 1 to 400
+    # lane, beyond that two to four tiles with carries, as many as 512-column
+    # tiles would need, each of the fewest columns per lane (5-8) that cover
+    # the query; references from 1 to 400
     rng = np.random.default_rng(980 + mode)
     w = W.random_pairs(120, 4, (257, 1600), (1, 400), 981 + mode, matrix=W.random_matrix(rng, 4),
                        gap_open=3, gap_extend=1)
     ms = np.diff(w.query_off)
     assert {int((m + 63) // 64) for m in ms if m <= 512} == {5, 6, 7, 8}
-    assert {int((m + 511) // 512) for m in ms if m > 512} == {2, 3, 4}
+    tiles = {int(m): int((m + 511) // 512) for m in ms if m > 512}
+    assert set(tiles.values()) == {2, 3, 4}
+    assert {(m + 64 * t - 1) // (64 * t) for m, t in tiles.items()} == {5, 6, 7, 8}
     _check(w, mode, "tiles")
 
 
