@@ -113,6 +113,37 @@ def test_queries_across_tiles(mode):
     _check(w, mode, "tiles")
 
 
+@pytest.mark.parametrize("mode", MODES)
+def test_queries_at_tile_edges(mode):
+    # query lengths on both sides of every width edge of the long-query
+    # kernel: 5-8 columns per lane in one tile up to 512 residues, then t
+    # tiles (t = ceil(m / 512)) of the fewest columns per lane (5-8) that
+    # cover the query; references from 1 to 300, some of one residue
+    rng = np.random.default_rng(1995 + mode)
+    M = W.random_matrix(rng, 4)
+    lens = []
+    for t in (1, 2, 3, 4):
+        for c in (5, 6, 7, 8):
+            lens += [64 * c * t, 64 * c * t + 1]
+    lens = sorted(set(m for m in lens if m > 256 and m <= 2049) | {257, 2049})
+    qs, rs = [], []
+    for m in lens:
+        for n in (1, int(rng.integers(2, 60)), int(rng.integers(60, 301))):
+            qs.append(rng.integers(0, 4, size=m, dtype=np.uint8))
+            rs.append(rng.integers(0, 4, size=n, dtype=np.uint8))
+    qres, qoff = np.concatenate(qs), np.zeros(len(qs) + 1, dtype=np.int64)
+    rres, roff = np.concatenate(rs), np.zeros(len(rs) + 1, dtype=np.int64)
+    np.cumsum([q.size for q in qs], out=qoff[1:])
+    np.cumsum([r.size for r in rs], out=roff[1:])
+    idx = np.arange(len(qs), dtype=np.int32)
+    w = W.Workload("tile_edges", qres, qoff, rres, roff, idx, idx.copy(), M, 3, 1, {})
+    ms = np.diff(qoff)
+    tiles = {int(m): max(1, int((m + 511) // 512)) for m in ms}
+    assert set(tiles.values()) == {1, 2, 3, 4, 5}
+    assert {(m + 64 * t - 1) // (64 * t) for m, t in tiles.items()} == {5, 6, 7, 8}
+    _check(w, mode, "tile edges")
+
+
 def test_dna_pairs_subset():
     # reads inside their windows: semi-global places each read, global also
     # pays for the window's overhang; every pair scores at least as well
