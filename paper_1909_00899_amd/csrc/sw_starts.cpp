@@ -73,6 +73,7 @@ struct StartsWork {
   size_t up_used = 0, dn_used = 0;
   std::vector<Pending> dn_pending;
   DevBuf tr_res;                 // end-to-end results
+  DevBuf e2e_sorted, e2e_hist;   // end-to-end: the two-pairs-per-wavefront entries reordered
   DevBuf tr_rstart;              // end-to-end paths: reference starts
   DevBuf tr_qstart;              // end-to-end paths: query starts
   // path tables built on the device: the caller's inputs (results, start
@@ -1150,6 +1151,16 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
     ea.pairs = dp;
     ea.n = n1;
     ea.carry_rows = 0;
+    if (n1 > 2) {
+      // couples of equal columns per lane and similar row counts
+      if ((rc = W.e2e_sorted.ensure((size_t)n1 * sizeof(swk::TracePair))) ||
+          (rc = W.e2e_hist.ensure((size_t)swk::kE2eSortBins * sizeof(int32_t))))
+        return rc;
+      HIPCHK(hipMemsetAsync(W.e2e_hist.p, 0, (size_t)swk::kE2eSortBins * sizeof(int32_t), W.st));
+      HIPCHK(swk::launch_e2e_sort(dp, n1, W.e2e_hist.as<int32_t>(),
+                                  W.e2e_sorted.as<swk::TracePair>(), W.st));
+      ea.pairs = W.e2e_sorted.as<swk::TracePair>();
+    }
     HIPCHK(swk::launch_endtoend2(mode, ea, W.st));   // a workgroup per two pairs
     ea.pairs = dp + n1;
     ea.n = n_one;

@@ -186,6 +186,16 @@ struct E2ePlanArgs {
 hipError_t launch_e2eplan_classify(const E2ePlanArgs &a, hipStream_t st);
 hipError_t launch_e2eplan_totals(const E2ePlanArgs &a, hipStream_t st);
 hipError_t launch_e2eplan_scatter(const E2ePlanArgs &a, hipStream_t st);
+// The two-pairs-per-wavefront class reordered so that a wavefront's two
+// pairs have the same columns per lane and similar row counts (a couple runs
+// its longer pair's rows at its wider pair's columns), most columns and rows
+// first: a counting sort of in[0 .. n) into out over (pad, rows) buckets,
+// rows from kE2eSortRows - 1 on sharing one; hist holds kE2eSortBins
+// counters that the caller zeroes; the order inside a bucket is free.
+constexpr int kE2eSortRows = 1024;
+constexpr int kE2eSortBins = 5 * kE2eSortRows;   // pad 1-5
+hipError_t launch_e2e_sort(const TracePair *in, int n, int32_t *hist, TracePair *out,
+                           hipStream_t st);
 // after the kernels: the first pair whose result has kFlagBadResidue
 hipError_t launch_e2e_check(const DevResult *res, int np, unsigned long long *err,
                             hipStream_t st);

@@ -954,8 +954,9 @@ __global__ __launch_bounds__(64) void endtoend_kernel(EndArgs a) {
 }
 
 // endtoend_kernel for queries beyond 256 residues: 5-8 columns per lane, one
-// tile up to 512 residues, tiles of 512 beyond (a kernel of its own, so that
-// the wider lanes' registers do not lower the narrow kernel's occupancy).
+// tile up to 512 residues, beyond that as many tiles as 512-column ones would
+// need (a kernel of its own, so that the wider lanes' registers do not lower
+// the narrow kernel's occupancy).
 template <int MODE>
 __global__ __launch_bounds__(64) void endtoend_wide_kernel(EndArgs a) {
   extern __shared__ int smem[];

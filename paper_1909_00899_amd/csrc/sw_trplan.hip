@@ -541,6 +541,76 @@ __global__ __launch_bounds__(kThreads) void e2eplan_scatter_kernel(E2ePlanArgs a
   }
 }
 
+// Bucket of a two-pairs-per-wavefront entry: more columns per lane first,
+// then more rows.
+__device__ __forceinline__ int e2e_sort_key(const TracePair &tp) {
+  const int pc = tp.pad < 1 ? 1 : tp.pad > 5 ? 5 : tp.pad;
+  const int rows = tp.A < 0 ? 0 : tp.A < kE2eSortRows - 1 ? tp.A : kE2eSortRows - 1;
+  return (5 - pc) * kE2eSortRows + (kE2eSortRows - 1 - rows);
+}
+
+// Bucket sizes: a workgroup histogram in LDS, added into hist.
+__global__ __launch_bounds__(kThreads) void e2esort_count_kernel(const TracePair *in, int n,
+                                                                 int32_t *hist) {
+  __shared__ int cnt[kE2eSortBins];
+  for (int b = threadIdx.x; b < kE2eSortBins; b += kThreads) cnt[b] = 0;
+  __syncthreads();
+  int lo, hi;
+  block_range(n, blockIdx.x, gridDim.x, lo, hi);
+  for (int k = lo + threadIdx.x; k < hi; k += kThreads) atomicAdd(&cnt[e2e_sort_key(in[k])], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kE2eSortBins; b += kThreads)
+    if (cnt[b]) atomicAdd(&hist[b], cnt[b]);
+}
+
+// One workgroup: the bucket sizes turned into bucket starts, in place.
+__global__ __launch_bounds__(kThreads) void e2esort_scan_kernel(int32_t *hist) {
+  static_assert(kE2eSortBins % kThreads == 0, "buckets per thread");
+  constexpr int kPer = kE2eSortBins / kThreads;
+  __shared__ int part[kThreads];
+  const int b0 = threadIdx.x * kPer;
+  int s = 0;
+  for (int j = 0; j < kPer; ++j) s += hist[b0 + j];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int t = 0; t < kThreads; ++t) {
+      const int v = part[t];
+      part[t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int run = part[threadIdx.x];
+  for (int j = 0; j < kPer; ++j) {
+    const int v = hist[b0 + j];
+    hist[b0 + j] = run;
+    run += v;
+  }
+}
+
+// Each workgroup reserves its share of every bucket with one atomic and
+// places its entries there with LDS cursors.
+__global__ __launch_bounds__(kThreads) void e2esort_scatter_kernel(const TracePair *in, int n,
+                                                                   int32_t *start,
+                                                                   TracePair *out) {
+  __shared__ int cur[kE2eSortBins];
+  for (int b = threadIdx.x; b < kE2eSortBins; b += kThreads) cur[b] = 0;
+  __syncthreads();
+  int lo, hi;
+  block_range(n, blockIdx.x, gridDim.x, lo, hi);
+  for (int k = lo + threadIdx.x; k < hi; k += kThreads) atomicAdd(&cur[e2e_sort_key(in[k])], 1);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kE2eSortBins; b += kThreads)
+    if (cur[b]) cur[b] = atomicAdd(&start[b], cur[b]);
+  __syncthreads();
+  for (int k = lo + threadIdx.x; k < hi; k += kThreads) {
+    const TracePair tp = in[k];
+    out[atomicAdd(&cur[e2e_sort_key(tp)], 1)] = tp;
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void e2e_check_kernel(const DevResult *res, int np,
                                                              unsigned long long *err) {
   for (int k = blockIdx.x * kThreads + threadIdx.x; k < np; k += gridDim.x * kThreads)
@@ -569,6 +639,18 @@ hipError_t launch_e2eplan_totals(const E2ePlanArgs &a, hipStream_t st) {
 
 hipError_t launch_e2eplan_scatter(const E2ePlanArgs &a, hipStream_t st) {
   hipLaunchKernelGGL(dev::e2eplan_scatter_kernel, dim3(kTrBlocks), dim3(dev::kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_e2e_sort(const TracePair *in, int n, int32_t *hist, TracePair *out,
+                           hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(kTrBlocks, ((int64_t)n + 2047) / 2048);
+  hipLaunchKernelGGL(dev::e2esort_count_kernel, dim3(grid), dim3(dev::kThreads), 0, st, in, n,
+                     hist);
+  hipLaunchKernelGGL(dev::e2esort_scan_kernel, dim3(1), dim3(dev::kThreads), 0, st, hist);
+  hipLaunchKernelGGL(dev::e2esort_scatter_kernel, dim3(grid), dim3(dev::kThreads), 0, st, in, n,
+                     hist, out);
   return hipGetLastError();
 }
 

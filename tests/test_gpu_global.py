@@ -96,6 +96,38 @@ def test_dual_pairs_odd_count_uneven_neighbours(mode):
     _check(w, mode, "dual-odd")
 
 
+def _pairs_of(qlens, rlens, seed, alpha=4, go=3, ge=1):
+    rng = np.random.default_rng(seed)
+    M = W.random_matrix(rng, alpha)
+    qs = [rng.integers(0, alpha, size=int(m), dtype=np.uint8) for m in qlens]
+    rs = [rng.integers(0, alpha, size=int(n), dtype=np.uint8) for n in rlens]
+    qres, qoff = np.concatenate(qs), np.zeros(len(qs) + 1, dtype=np.int64)
+    rres, roff = np.concatenate(rs), np.zeros(len(rs) + 1, dtype=np.int64)
+    np.cumsum([q.size for q in qs], out=qoff[1:])
+    np.cumsum([r.size for r in rs], out=roff[1:])
+    idx = np.arange(len(qs), dtype=np.int32)
+    return W.Workload("pairs_of", qres, qoff, rres, roff, idx, idx.copy(), M, go, ge, {})
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_dual_couples_after_the_reorder(mode):
+    # queries up to 160 residues are reordered by columns per lane and rows
+    # (more first) before they are coupled two per wavefront: two pairs stay
+    # in place (a 1-row pair beside a 1400-row one, 1 and 5 columns per
+    # lane); three of different widths leave an uneven couple (5 columns x
+    # 1400 rows with 3 x 700) and a lone pair; rows from 1023 on share one
+    # bucket, so a crowd of them couples in any order
+    w = _pairs_of([20, 150], [1, 1400], 1996 + mode)
+    _check(w, mode, "two")
+    w = _pairs_of([150, 10, 70], [1400, 3, 700], 1997 + mode)
+    _check(w, mode, "three")
+    rng = np.random.default_rng(1998 + mode)
+    n = 37
+    w = _pairs_of(rng.integers(1, 161, size=n), rng.integers(1000, 1600, size=n), 1999 + mode)
+    assert (np.diff(w.ref_off) >= 1023).sum() > n // 2
+    _check(w, mode, "clamped bucket")
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_queries_across_tiles(mode):
     # queries of 257-1600 residues: up to 512 one tile at 5-8 columns per
