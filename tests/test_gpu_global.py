@@ -129,6 +129,17 @@ def test_dual_couples_after_the_reorder(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_dual_reorder_across_workgroups(mode):
+    # 6000 queries up to 160 residues: the reorder's histogram and scatter
+    # run in three workgroups that reserve their shares of each bucket
+    rng = np.random.default_rng(2003 + mode)
+    w = W.random_pairs(6000, 4, (1, 160), (1, 30), 2004 + mode, matrix=W.random_matrix(rng, 4),
+                       gap_open=3, gap_extend=1)
+    assert (np.diff(w.query_off) <= 160).all()
+    _check(w, mode, "reorder x3")
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_queries_across_tiles(mode):
     # queries of 257-1600 residues: up to 512 one tile at 5-8 columns per
     # lane, beyond that two to four tiles with carries, as many as 512-column
