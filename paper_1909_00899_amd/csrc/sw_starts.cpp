@@ -507,6 +507,16 @@ namespace {
 
 constexpr int64_t kTraceScratchBytes = 1ll << 30;    // device-memory decision bits per launch
 constexpr int kTraceMaxWaves = 4096;
+// The end-to-end kernel for queries of several tiles keeps only a per-row
+// carry per wavefront (no decision bits), so its launch takes up to twice as
+// many wavefronts (about five fit per SIMD at its register count).
+constexpr int kEndMaxWaves = 8192;
+
+int launch_waves(int64_t count, int64_t per_wave, int max_waves) {
+  per_wave = std::max<int64_t>(per_wave, 1);
+  return (int)std::max<int64_t>(
+      1, std::min<int64_t>({count, kTraceScratchBytes / per_wave, (int64_t)max_waves}));
+}
 
 }  // namespace
 
@@ -772,8 +782,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     const int64_t slot = (int64_t)cmax[2 * c];
     const int carry_rows = std::max<int>(1, (int)cmax[2 * c + 1]);
     const int64_t per_wave = slot * 2 + 6ll * carry_rows * 4;
-    const int waves = (int)std::max<int64_t>(
-        1, std::min<int64_t>({cnt, kTraceScratchBytes / per_wave, kTraceMaxWaves}));
+    const int waves = launch_waves(cnt, per_wave, kTraceMaxWaves);
     const int sk = std::min((int)groups.size(), NS - 1);
     groups.push_back({(int)cstart[c], (int)cnt, waves, slot, carry_rows, (c - 3) % 3});
     bits_words[sk] = std::max<int64_t>(bits_words[sk], slot * waves);
@@ -1134,9 +1143,7 @@ extern "C" int sw_align_batch_global(const sw_batch *b, const sw_scoring *sc, in
   if (n1 + n_one + nw + nm > 0) {
     HIPCHK(swk::launch_e2eplan_scatter(pa, W.st));
     const int64_t per_wave = 4ll * carry_rows * (int64_t)sizeof(int32_t);
-    const int waves_m = nm == 0 ? 0 : (int)std::max<int64_t>(
-        1, std::min<int64_t>({(int64_t)nm, kTraceScratchBytes / std::max<int64_t>(per_wave, 1),
-                              kTraceMaxWaves}));
+    const int waves_m = nm == 0 ? 0 : launch_waves(nm, per_wave, kEndMaxWaves);
     if ((rc = W.tr_carry[0].ensure((size_t)std::max<int64_t>(per_wave * waves_m, 4)))) return rc;
     swk::TracePair *dp = W.tr_pairs.as<swk::TracePair>();
     swk::EndArgs ea;
