@@ -506,10 +506,17 @@ extern "C" int sw_align_batch_starts(const sw_batch *b, const sw_scoring *sc,
 namespace {
 
 constexpr int64_t kTraceScratchBytes = 1ll << 30;    // device-memory decision bits per launch
-constexpr int kTraceMaxWaves = 4096;
+// Wavefronts of a device-memory path launch, by measurement on 1M DNA pairs
+// and the 100k protein search: 8192 (local, semi-global, overlap paths: 3-5
+// ms faster than 4096 per DNA call, 2048 far slower); global paths, whose
+// rectangles are whole pairs, ran fastest at 4096 (79 ms; 2048: 94, 6144:
+// 93, 8192: 86.5).
+constexpr int kTraceMaxWaves = 8192;
+constexpr int kTraceGlobalWaves = 4096;
 // The end-to-end kernel for queries of several tiles keeps only a per-row
 // carry per wavefront (no decision bits), so its launch takes up to twice as
-// many wavefronts (about five fit per SIMD at its register count).
+// many wavefronts as the 4096 it had (about five fit per SIMD at its register
+// count).
 constexpr int kEndMaxWaves = 8192;
 
 int launch_waves(int64_t count, int64_t per_wave, int max_waves) {
@@ -782,7 +789,7 @@ int paths_impl(const sw_batch *b, const sw_scoring *sc, int mode, const sw_resul
     const int64_t slot = (int64_t)cmax[2 * c];
     const int carry_rows = std::max<int>(1, (int)cmax[2 * c + 1]);
     const int64_t per_wave = slot * 2 + 6ll * carry_rows * 4;
-    const int waves = launch_waves(cnt, per_wave, kTraceMaxWaves);
+    const int waves = launch_waves(cnt, per_wave, mode == 1 ? kTraceGlobalWaves : kTraceMaxWaves);
     const int sk = std::min((int)groups.size(), NS - 1);
     groups.push_back({(int)cstart[c], (int)cnt, waves, slot, carry_rows, (c - 3) % 3});
     bits_words[sk] = std::max<int64_t>(bits_words[sk], slot * waves);
