@@ -509,8 +509,8 @@ constexpr int64_t kTraceScratchBytes = 1ll << 30;    // device-memory decision b
 // Wavefronts of a device-memory path launch, by measurement on 1M DNA pairs
 // and the 100k protein search: 8192 (local, semi-global, overlap paths: 3-5
 // ms faster than 4096 per DNA call, 2048 far slower); global paths, whose
-// rectangles are whole pairs, ran fastest at 4096 (79 ms; 2048: 94, 6144:
-// 93, 8192: 86.5).
+// rectangles are whole pairs, ran fastest at 4096 (79 ms; 2048: 94, 5120:
+// 98.5, 6144: 93, 8192: 86.5).
 constexpr int kTraceMaxWaves = 8192;
 constexpr int kTraceGlobalWaves = 4096;
 // The end-to-end kernel for queries of several tiles keeps only a per-row
