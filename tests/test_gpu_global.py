@@ -140,6 +140,27 @@ def test_dual_reorder_across_workgroups(mode):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_many_tiled_queries_share_wavefronts(mode):
+    # 20000 queries of 513-700 residues (two tiles each): one launch of the
+    # most wavefronts it takes, each running two or three pairs in turn with
+    # its carry slot; a sample against the oracle, every pair against the
+    # same pairs run 1000 at a time (as many wavefronts as pairs)
+    rng = np.random.default_rng(2010 + mode)
+    w = W.random_pairs(20000, 4, (513, 700), (60, 160), 2011 + mode,
+                       matrix=W.random_matrix(rng, 4), gap_open=3, gap_extend=1)
+    got = _run(w, mode)
+    assert (got[:, 3] == 0).all()
+    sample = sorted(rng.choice(w.n_pairs, size=150, replace=False).tolist())
+    want = oracle.endtoend_batch(w.query_res, w.query_off, w.ref_res, w.ref_off, w.pair_ref,
+                                 w.matrix, w.gap_open, w.gap_extend, mode,
+                                 pair_query=w.pair_query, pairs=sample)
+    np.testing.assert_array_equal(got[sample, :3].astype(np.int64), want)
+    for lo in range(0, w.n_pairs, 1000):
+        part = _run(w.subset(np.arange(lo, lo + 1000)), mode)
+        np.testing.assert_array_equal(part, got[lo:lo + 1000])
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_queries_across_tiles(mode):
     # queries of 257-1600 residues: up to 512 one tile at 5-8 columns per
     # lane, beyond that two to four tiles with carries, as many as 512-column
