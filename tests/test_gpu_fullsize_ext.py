@@ -3,7 +3,9 @@ the configuration bench.py times (device-resident sequences): every path of
 the 100k protein-search and 1M DNA-pair alignments covers exactly the
 rectangle between its start and end cell, has the canonical shape and adds
 up to the score (checked for all pairs, vectorised); sampled pairs equal the
-CPU oracle's paths, start cells and global / semi-global results."""
+CPU oracle's paths, start cells, global / semi-global results and semi-global
+paths, and the reference-fitted results with the roles swapped (which equal
+the semi-global scores for every pair: the DNA scoring is symmetric)."""
 import numpy as np
 import pytest
 
@@ -134,3 +136,23 @@ def test_dna_pairs_paths_and_endtoend_full_size():
         for got, mode in ((glob, 0), (semi, 1)):
             want = oracle.endtoend(q, r, w.matrix, w.gap_open, w.gap_extend, mode)
             assert tuple(int(x) for x in got[k, :3]) == want, (k, mode)
+    # the semi-global paths of every pair (device-memory path launches of the
+    # most wavefronts they take), sampled against the oracle
+    qs, rs, runs, off = api.sw_align_batch_global_cigar(
+        *args, w.matrix, w.gap_open, w.gap_extend, semi, mode=api.SW_MODE_SEMIGLOBAL, pair_query=pq)
+    for k in range(0, 1_000_000, 20_000):
+        q, r = _seqs(w, k)
+        want = oracle.endtoend_path(q, r, w.matrix, w.gap_open, w.gap_extend, 1,
+                                    end=tuple(int(x) for x in semi[k, :3]))
+        assert (int(qs[k]), int(rs[k]), api.decode_cigar(runs, off, k)) == want, k
+    # the roles swapped (windows of 300-600 as queries, reads as references;
+    # the windows over 512 residues in two tiles, up to 8192 wavefronts)
+    swapped = (args[2], args[3], args[0], args[1], pq)
+    sref = api.sw_align_batch_global(*swapped, w.matrix, w.gap_open, w.gap_extend,
+                                     mode=api.SW_MODE_SEMIGLOBAL_REF, pair_query=args[4])
+    assert (sref[:, 0] == semi[:, 0]).all()
+    for k in range(0, 1_000_000, 20_000):
+        q, r = _seqs(w, k)
+        want = oracle.endtoend(r, q, w.matrix, w.gap_open, w.gap_extend,
+                               api.SW_MODE_SEMIGLOBAL_REF)
+        assert tuple(int(x) for x in sref[k, :3]) == want, k
