@@ -260,15 +260,24 @@ __global__ __launch_bounds__(1024) void plan_scatter_kernel(int n_pairs, const P
 }
 
 // Segment t of dst (bytes [dst_off[t], dst_off[t+1])) = the same number of
-// bytes of src from src_off[t] on, in reverse order; a workgroup per segment
-// (grid-stride over the segments).
+// bytes of src from src_off[t] on, in reverse order; a wavefront per segment
+// (grid-stride over the segments), four bytes per lane per step, so a short
+// segment (a 150-residue read) is one step and a long one moves 256 bytes a
+// step.
 __global__ __launch_bounds__(256) void reverse_segments_kernel(int n, const uint8_t *src,
                                                                const int64_t *src_off,
                                                                const int64_t *dst_off,
                                                                uint8_t *dst) {
-  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int per_block = blockDim.x / kWave;
+  const int stride = gridDim.x * per_block;
+  for (int t = blockIdx.x * per_block + threadIdx.x / kWave; t < n; t += stride) {
     const int64_t d0 = dst_off[t], len = dst_off[t + 1] - d0, s_last = src_off[t] + len - 1;
-    for (int64_t x = threadIdx.x; x < len; x += blockDim.x) dst[d0 + x] = src[s_last - x];
+    for (int64_t x = 4 * lane; x < len; x += 4 * kWave) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (x + b < len) dst[d0 + x + b] = src[s_last - x - b];
+    }
   }
 }
 
@@ -311,8 +320,8 @@ __global__ __launch_bounds__(256) void init_results_kernel(int n, DevResult *r) 
 hipError_t launch_reverse_segments(int n, const uint8_t *src, const int64_t *src_off,
                                    const int64_t *dst_off, uint8_t *dst, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::reverse_segments_kernel, dim3(std::min(n, 65535)), dim3(256), 0, st, n,
-                     src, src_off, dst_off, dst);
+  hipLaunchKernelGGL(dev::reverse_segments_kernel, dim3(std::min((n + 3) / 4, 65535)), dim3(256), 0,
+                     st, n, src, src_off, dst_off, dst);
   return hipGetLastError();
 }
 
