@@ -975,16 +975,20 @@ __global__ __launch_bounds__(64) void endtoend_wide_kernel(EndArgs a) {
 }
 
 // Pair t's runs (the last n_runs[id] entries of its region) to
-// cigar_dst[dst_off[id] ..]; a workgroup per pair, grid-stride.
+// cigar_dst[dst_off[id] ..]; a wavefront per pair (most paths have a few
+// runs), four per workgroup, grid-stride.
 __global__ __launch_bounds__(256) void pack_runs_kernel(const TracePair *pairs, int n,
                                                         const int32_t *n_runs,
                                                         const int64_t *dst_off,
                                                         const uint32_t *src, uint32_t *dst) {
-  for (int t = blockIdx.x; t < n; t += gridDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int per_block = blockDim.x / 64;
+  const int stride = gridDim.x * per_block;
+  for (int t = blockIdx.x * per_block + threadIdx.x / 64; t < n; t += stride) {
     const TracePair P = pairs[t];
     const int cnt = min(n_runs[P.id], P.cap);   // the host checked every count already
     const int64_t s0 = P.out + P.cap - cnt, d0 = dst_off[P.id];
-    for (int k = threadIdx.x; k < cnt; k += blockDim.x) dst[d0 + k] = src[s0 + k];
+    for (int k = lane; k < cnt; k += 64) dst[d0 + k] = src[s0 + k];
   }
 }
 
@@ -1044,8 +1048,8 @@ hipError_t launch_pack_runs(const TracePair *pairs, int n, const int32_t *n_runs
                             const int64_t *dst_off, const uint32_t *src, uint32_t *dst,
                             hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(dev::pack_runs_kernel, dim3(std::min(n, 65535)), dim3(256), 0, st, pairs, n,
-                     n_runs, dst_off, src, dst);
+  hipLaunchKernelGGL(dev::pack_runs_kernel, dim3(std::min((n + 3) / 4, 65535)), dim3(256), 0, st,
+                     pairs, n, n_runs, dst_off, src, dst);
   return hipGetLastError();
 }
 
