@@ -56,13 +56,28 @@ __global__ __launch_bounds__(256) void build_streams_kernel(const Task *tasks, c
   }
 }
 
-// Sets *flag to 1 if any of the n residues is >= alpha.
+// Sets *flag to 1 if any of the n residues is >= alpha.  Sixteen bytes per
+// load between the first and the last 16-byte boundary of the array; the
+// bytes before and after (fewer than 16 each) one per thread of the first
+// workgroup.
 __global__ __launch_bounds__(256) void check_residues_kernel(const uint8_t *p, int64_t n, int alpha,
                                                              int *flag) {
-  int bad = 0;
+  const int64_t head = min(n, (int64_t)((16 - ((uintptr_t)p & 15)) & 15));
+  const int64_t body = (n - head) / 16, tail0 = head + body * 16;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
-    bad |= p[k] >= alpha;
+  const uint4 *v = (const uint4 *)(p + head);
+  int bad = 0;
+  for (int64_t k = tid; k < body; k += stride) {
+    const uint4 x = v[k];
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int b = 0; b < 32; b += 8) bad |= (int)((w[j] >> b) & 0xffu) >= alpha;
+  }
+  if (tid < head) bad |= p[tid] >= alpha;
+  if (tid < n - tail0) bad |= p[tail0 + tid] >= alpha;
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 // PairInfo of every pair from CSR offsets already on the device.
@@ -365,7 +380,9 @@ hipError_t launch_build_pairs(int n_pairs, const int64_t *qoff, const int64_t *r
 hipError_t launch_check_residues(const uint8_t *p, int64_t n, int alpha, int *flag,
                                  hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  int grid = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  // one 16-byte load per thread per step; at least one workgroup for the
+  // unaligned head and tail
+  int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n / 16 + 255) / 256, 4096));
   hipLaunchKernelGGL(dev::check_residues_kernel, dim3(grid), dim3(256), 0, st, p, n, alpha, flag);
   return hipGetLastError();
 }

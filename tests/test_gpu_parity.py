@@ -226,6 +226,47 @@ def test_batch_invalid_residue_rejected():
     assert e.value.code == api.SW_EINVAL
 
 
+@pytest.mark.parametrize("shift", [0, 3, 16])
+def test_invalid_residue_found_anywhere_in_device_arrays(shift):
+    # the residue check reads 16 bytes at a time between the first and last
+    # 16-byte boundaries of an array and single bytes outside them: a bad code
+    # in the first, last or a middle byte of a reference set that starts off
+    # a boundary (and in a query set of 1-40 bytes) is rejected; none is
+    # reported without one
+    import torch
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(120 + shift)
+    M = np.eye(4, dtype=np.int32)
+    n = 5003
+    base = rng.integers(0, 4, size=n + shift, dtype=np.uint8)
+    q = torch.from_numpy(rng.integers(0, 4, size=40, dtype=np.uint8)).to(dev)
+    qoff = torch.tensor([0, 40], dtype=torch.int64, device=dev)
+    roff = torch.tensor([0, n], dtype=torch.int64, device=dev)
+    pr = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def run(refs, query=q, query_off=qoff):
+        r = torch.from_numpy(refs).to(dev)[shift:]
+        return api.sw_align_batch(query, query_off, r, roff, pr, M, 2, 1)
+
+    got = run(base).results
+    assert tuple(int(x) for x in got[0, :3]) == \
+        oracle.align(q.cpu().numpy(), base[shift:], M, 2, 1)
+    for pos in (0, 1, 12, 13, 15, 16, 17, n // 2, n - 17, n - 16, n - 15, n - 2, n - 1):
+        bad = base.copy()
+        bad[shift + pos] = 4 + pos % 200
+        with pytest.raises(api.SwError) as e:
+            run(bad)
+        assert e.value.code == api.SW_EINVAL, pos
+    for m in (1, 15, 16, 17, 40):
+        for pos in (0, m - 1):
+            qs = rng.integers(0, 4, size=m + shift, dtype=np.uint8)
+            qs[shift + pos] = 255
+            qd = torch.from_numpy(qs).to(dev)[shift:]
+            with pytest.raises(api.SwError) as e:
+                run(base, qd, torch.tensor([0, m], dtype=torch.int64, device=dev))
+            assert e.value.code == api.SW_EINVAL, (m, pos)
+
+
 def test_device_resident_inputs_match_host():
     import torch
     w = _random_batch(13, 200, 20, (1, 300), (1, 300))
